@@ -1,0 +1,175 @@
+"""Benchmark of the line radiative-transfer ray march on one MI355X.
+
+A step is one full-size forward render: 512 x 512 pixels x 64 channels x 512
+samples per ray through a 256 x 128 (r, z/r) disk (seeded parametric disk
+with three density gaps), inputs resident in HBM.  Prints one JSON line with
+ray-samples/s, the roofline of the dominant kernel (the forward march), the
+forward+adjoint rate on the 256 x 256 x 48 x 256 case, and the FP64 oracle
+timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# MI355X unit counts and clock: 256 CUs x 4 SIMDs x 16 lanes at 2.4 GHz issue
+# 3.93e13 single-rate FP32 lane-instructions per second; a transcendental
+# (exp2, log2, rcp, rsq, sqrt) takes 4 issue slots.
+LANE_SLOTS_PER_S = 256 * 4 * 16 * 2.4e9
+TRANS_SLOTS = 4
+# Algorithmic work of one ray-sample in the channel loop: d = a - v b (FMA),
+# d^2, g = 2^-d^2, x = K g, att = 2^-x, 1 - att, Tr (1 - att), I += . S (FMA),
+# Tr *= att  ->  11 FLOP (FMA = 2, transcendental = 1) in 7 VALU + 2 TRANS.
+LOOP_FLOP, LOOP_VALU, LOOP_TRANS = 11, 7, 2
+# Channel-independent shading of one pixel-sample, shared by the channels of
+# a lane: position, grid fetch and bilinear interpolation, density, CO mask,
+# partition function, populations, source function, width, projected velocity.
+SHADE_FLOP, SHADE_VALU, SHADE_TRANS = 150, 100, 14
+
+
+def algorithmic(nch: int, cb: int):
+    """(FLOP per ray-sample, issue slots per ray-sample) of the dense march."""
+    flop = LOOP_FLOP + SHADE_FLOP / cb
+    slots = LOOP_VALU + TRANS_SLOTS * LOOP_TRANS + (SHADE_VALU + TRANS_SLOTS * SHADE_TRANS) / cb
+    return flop, slots
+
+
+def cpu_baseline(prob, seconds=12.0):
+    """FP64 oracle on seeded pixels of the same workload, all host cores."""
+    import numpy as np
+    import oracle
+    ncores = os.cpu_count() or 1
+    nx, ny = prob.camera.nx, prob.camera.ny
+    rng = np.random.Generator(np.random.PCG64(99))
+    per_pix = prob.nch * prob.nsamp
+    n = 256
+    t_used = 0.0
+    done = 0
+    while t_used < seconds:
+        px = rng.integers(0, nx, n)
+        py = rng.integers(0, ny, n)
+        t0 = time.perf_counter()
+        oracle.render_pixels(prob, px, py, nthreads=ncores)
+        dt = time.perf_counter() - t0
+        t_used += dt
+        done += n
+        n = int(min(max(n * 2, 64), max(64, n * (seconds - t_used) / max(dt, 1e-3))))
+        if n < 64:
+            break
+    return dict(value=done * per_pix / t_used, unit="ray-samples/s", cores=ncores, kind="oracle",
+                sample=f"{done} seeded random pixels of the 512x512x64ch x512-sample disk "
+                       f"({done * per_pix:.3g} ray-samples, {t_used:.1f} s, FP64 scalar C, OpenMP)")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--seed", type=int, default=2000)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU: the renderer is a single-GPU build (rays are independent, "
+              "so more GPUs would each render their own pixel tiles); run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import synth
+    import paper_2509_03623_amd as rt
+    from paper_2509_03623_amd import _lib as L
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    prob = synth.config2(args.seed)
+    sc = rt.scene_from_problem(prob, device=dev)
+    cube = torch.empty(sc.nch, sc.ny, sc.nx, device=dev)
+    for _ in range(args.warmup):
+        rt.render(sc, out=cube)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.steps):
+        rt.render(sc, out=cube)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kern_ms = e0.elapsed_time(e1) / args.steps
+    ms_per_step = wall * 1e3 / args.steps
+    rs = sc.ray_samples
+    value = rs / (wall / args.steps)
+    cb = rt.get_option(L.RT_OPT_CHANNEL_BLOCK) or (32 if sc.nch >= 32 else (16 if sc.nch >= 16 else 8))
+    flop, slots = algorithmic(sc.nch, cb)
+    achieved = flop * rs / (kern_ms * 1e-3) / 1e12
+    peak = flop / slots * LANE_SLOTS_PER_S / 1e12
+    out = {
+        "metric": "ray-samples/s fwd & fwd+adjoint at 512^2x64ch; p50/p99 served latency",
+        "value": value,
+        "unit": "ray-samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "forward render 512x512 px x 64 ch x 512 samples/ray, 256x128 (r,z/r) grid, "
+                               f"seeded disk {args.seed} (3 gaps, incl {prob.camera.incl_deg:.1f} deg)",
+                   "global_batch": 1, "ray_samples": rs, "parallelism": "single GPU"},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": None,
+                     "kernel": "march_fwd", "kernel_ms": kern_ms,
+                     "flop_per_ray_sample": flop, "issue_slots_per_ray_sample": slots},
+    }
+    if not args.no_adjoint:
+        try:
+            out["fwd_adjoint"] = bench_adjoint(rt, synth, dev, args)
+        except rt.RtError as e:
+            out["fwd_adjoint"] = {"error": str(e)}
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+def bench_adjoint(rt, synth, dev, args):
+    """Forward + adjoint on the 256 x 256 x 48 x 256 case (L2 loss)."""
+    import torch
+    prob = synth.config3()
+    sc = rt.scene_from_problem(prob, device=dev)
+    tgt = rt.render(sc.replace(z_up_au=sc.z_up_au * 1.05))
+    steps = max(3, args.steps // 2)
+
+    def step():
+        cube = rt.render(sc)
+        dl = 2.0 * (cube - tgt)
+        return rt.render_adjoint(sc, dl, want=("ln_nh2", "temp_k", "z_lo_au", "z_up_au"))
+
+    for _ in range(max(1, args.warmup // 2)):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    return {"ray_samples_per_s": sc.ray_samples / dt, "ms_per_step": dt * 1e3,
+            "workload": "forward + adjoint 256x256 px x 48 ch x 256 samples, L2 loss"}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,216 @@
+/*
+ * rtcube.h -- C ABI of the MI355X line radiative-transfer renderer.
+ *
+ * The library renders spectral data cubes of LTE molecular line emission from
+ * an azimuthally and mirror-symmetric protoplanetary disk, and differentiates
+ * them.  Physics (Methods, "Line Radiative Transfer"): the formal solution of
+ * Eq. rt-int with the optical depth of Eq. optical_depth, LTE emissivity j and
+ * extinction beta from Boltzmann level populations, a Gaussian Doppler profile
+ * shifted by the projected velocity and broadened by thermal + turbulent
+ * motions.  Disk model (Methods, "Parametric Disk Modeling"): H2 density,
+ * temperature and azimuthal velocity on an (r, z/r) grid, with the CO layer
+ * between a freeze-out and a photodissociation surface (Eq. co_layer).
+ *
+ * Discretisation (identical in every entry point):
+ *   - grid nodes r_i = r_min (r_max/r_min)^(i/(nr-1)), (z/r)_j = zr_max j/(nz-1);
+ *     fields are bilinear in (ln r, z/r) index space, clamped to the edge, and
+ *     the density fades linearly to zero one cell beyond the last node;
+ *   - CO abundance x_co times a logistic mask sigma((z_up-|z|)/w) sigma((|z|-z_lo)/w),
+ *     w = mask_width * r * d(z/r), with z_lo / z_up linear in the radial index;
+ *   - orthographic camera: pixel centres ((p+1/2-nx/2) d, (q+1/2-ny/2) d),
+ *     d = fov/nx, rotated by the position angle; ray direction
+ *     (0, sin i, -cos i); gas rotates counter-clockwise about +z;
+ *   - each ray's chord through the cylinder r <= r_max e^dln, |z| <= (zr_max +
+ *     d(z/r)) r_max e^dln is cut into nsamp equal segments; each segment holds
+ *     the fields of its midpoint and contributes S (1 - e^-dtau) attenuated by
+ *     everything in front of it (no background);
+ *   - channels are velocities v_c [km/s] (radio convention); the profile of a
+ *     channel depends on (v_los - v_c) / alpha only.
+ *
+ * Conventions for every entry point:
+ *   - Array pointers are DEVICE pointers into caller-owned HIP memory unless
+ *     marked [host].  Layouts: fields [nr][nz] (z/r index fastest), surfaces
+ *     [nr], cubes [nch][ny][nx] (x fastest), all float32.
+ *   - Arguments are validated on the host only; device data is never read
+ *     for validation, so NaNs in inputs propagate to outputs.
+ *   - Work is enqueued on the given HIP stream (a hipStream_t passed as
+ *     void*, NULL = the null stream) and the call returns without waiting;
+ *     buffers must stay valid until that stream work has completed.
+ *   - Outputs are written only when the call returns RT_OK; gradients are
+ *     overwritten, not accumulated.
+ *   - On any non-OK status rt_last_error() returns a message (thread-local).
+ */
+#ifndef RTCUBE_H
+#define RTCUBE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RT_ABI_VERSION 1
+#define RT_MAX_CHANNELS 4096     /* per call; larger cubes are several calls */
+
+typedef enum {
+    RT_OK = 0,
+    RT_PENDING = 1,       /* server ticket not finished yet */
+    RT_EINVAL = -1,       /* invalid argument (see rt_last_error) */
+    RT_ENOMEM = -2,       /* device allocation failed */
+    RT_EDEVICE = -3,      /* a HIP call or kernel launch failed */
+    RT_EAGAIN = -4,       /* server pending queue full: retry later */
+    RT_ECANCELED = -5,    /* request cancelled before it ran */
+    RT_ETOOBIG = -6,      /* request footprint exceeds the server's HBM budget */
+    RT_ENOTFOUND = -7     /* unknown server ticket */
+} rt_status;
+
+/* (r, z/r) node grid: nr, nz >= 2; 0 < r_min_au < r_max_au; zr_max > 0. */
+typedef struct {
+    int32_t nr, nz;
+    double r_min_au, r_max_au, zr_max;
+} rt_grid;
+
+/* Disk fields.  ln_nh2: natural log of n_H2 [cm^-3]; temp_k: gas temperature
+ * [K] (must be > 0); vphi_kms: azimuthal velocity [km/s]; z_lo_au / z_up_au:
+ * lower (freeze-out) and upper (photodissociation) CO surface heights per
+ * radial node [au].  x_co: CO abundance inside the layer; mask_width: mask
+ * width in units of r d(z/r) (> 0); v_turb: turbulent Mach number. */
+typedef struct {
+    const float *ln_nh2, *temp_k, *vphi_kms;   /* [nr][nz] */
+    const float *z_lo_au, *z_up_au;            /* [nr] */
+    double x_co, mask_width, v_turb;
+} rt_fields;
+
+/* One line transition in LTE.  lev_e_k / lev_g: [host] energies [K] and
+ * degeneracies of the levels summed in the partition function (copied during
+ * the call; the partition function is tabulated for 0.1 K <= T <= 1e4 K and
+ * clamped outside).  m_mol_amu: mean molecular mass of the gas [amu]. */
+typedef struct {
+    double nu0_hz, a_ul, g_u, g_l, e_u_k, e_l_k, m_co_amu, m_mol_amu;
+    int32_t nlev;
+    const double *lev_e_k, *lev_g;
+} rt_line;
+
+/* Orthographic camera: nx x ny pixels over fov_au along x (square pixels);
+ * inclination 0..90 deg; position angle rotates the image plane. */
+typedef struct {
+    int32_t nx, ny;
+    double fov_au, incl_deg, pa_deg, dist_pc;
+} rt_camera;
+
+/* Spectral axis: nch channel velocities [km/s] ([host], copied during the
+ * call) and the systemic velocity added to every line-of-sight velocity. */
+typedef struct {
+    int32_t nch;
+    const double *v_kms;
+    double v_sys_kms;
+} rt_spectral;
+
+/* Neural CO layer (optional): 16 Fourier frequencies 2^(3k/15) on the two
+ * normalised grid coordinates, 4 SiLU hidden layers of width 128, 3 outputs
+ * giving z_up = zr_max r sigma(o0), z_lo = zr_max r sigma(o1) and
+ * T <- T exp(0.5 tanh(o2)).  weights: float32, per layer W [out][in] then
+ * b [out].  precision: RT_MLP_BF16 (BF16 matrix cores, FP32 accumulation) or
+ * RT_MLP_FP32. */
+enum { RT_MLP_FP32 = 0, RT_MLP_BF16 = 1 };
+#define RT_MLP_PARAMS 58243
+typedef struct {
+    const float *weights;
+    int32_t precision;
+} rt_mlp;
+
+typedef struct {
+    rt_grid grid;
+    rt_fields f;
+    rt_line line;
+    rt_camera cam;
+    rt_spectral spec;
+    int32_t nsamp;             /* samples per ray, >= 1 */
+    double intensity_scale;    /* output = scale * I_nu [erg s^-1 cm^-2 Hz^-1 sr^-1] */
+    const rt_mlp *mlp;         /* NULL: surfaces and temperature from the grid */
+} rt_problem;
+
+/* Gradient outputs, each NULL when not requested. */
+typedef struct {
+    float *d_ln_nh2, *d_temp_k, *d_vphi_kms;   /* [nr][nz] */
+    float *d_z_lo_au, *d_z_up_au;              /* [nr] */
+    float *d_mlp;                              /* [RT_MLP_PARAMS] */
+} rt_grads;
+
+/* Render the cube [nch][ny][nx] of problem p. */
+rt_status rt_render_cube(const rt_problem *p, float *cube, void *stream);
+
+/* Vector-Jacobian product of rt_render_cube: given dL/dcube [nch][ny][nx],
+ * write the requested gradients of L w.r.t. the fields, surfaces and network
+ * weights.  cube_opt (may be NULL) receives the forward cube.  The reverse
+ * sweep recomputes each segment of samples from optical-depth checkpoints
+ * instead of storing every sample.  Gradients use float atomics, so their
+ * last bits may vary from run to run. */
+rt_status rt_render_cube_adjoint(const rt_problem *p, const float *dl_dcube, const rt_grads *g,
+                                 float *cube_opt, void *stream);
+
+/* ---------------------------------------------------------------- server */
+/* Continuous-batching render server on one GPU.  Requests are admitted while
+ * their HBM footprint fits the budget and a slot is free; admitted requests
+ * are cut into tile work items that persistent launches pull from a device
+ * queue, so work of different requests overlaps on the device.  A request's
+ * forward cube is bitwise the one rt_render_cube gives. */
+typedef struct rt_server rt_server;
+
+typedef struct {
+    uint64_t hbm_budget_bytes;   /* admission budget for request footprints */
+    int32_t max_slots;           /* requests admitted at once (1..1024) */
+    int32_t max_pending;         /* queued, not yet admitted (>= 1) */
+    int32_t device;              /* HIP device ordinal */
+    int32_t streams;             /* launches in flight at once (1..8) */
+} rt_server_cfg;
+
+enum { RT_REQ_FWD = 0, RT_REQ_FWD_ADJ = 1 };
+enum { RT_TICKET_QUEUED = 0, RT_TICKET_RUNNING = 1, RT_TICKET_DONE = 2, RT_TICKET_CANCELED = 3,
+       RT_TICKET_FAILED = 4 };
+
+/* kind RT_REQ_FWD renders into cube; RT_REQ_FWD_ADJ also takes target
+ * [nch][ny][nx] and writes the gradients of L = sum (cube - target)^2 into
+ * grads (L itself is reported by rt_poll). */
+typedef struct {
+    rt_problem problem;          /* host copy is taken at submit time */
+    int32_t kind;
+    float *cube;                 /* device, [nch][ny][nx] */
+    const float *target;         /* device, RT_REQ_FWD_ADJ only */
+    rt_grads grads;              /* device, RT_REQ_FWD_ADJ only */
+} rt_request;
+
+typedef struct {
+    int32_t state;               /* RT_TICKET_* */
+    int32_t status;              /* rt_status of the request */
+    uint64_t t_submit_ns, t_admit_ns, t_done_ns;   /* steady-clock stamps */
+    double loss;                 /* RT_REQ_FWD_ADJ: L once done */
+    uint64_t ray_samples;
+} rt_ticket_info;
+
+rt_status rt_server_create(const rt_server_cfg *cfg, rt_server **out);
+rt_status rt_submit(rt_server *sv, const rt_request *rq, uint64_t *ticket);
+rt_status rt_poll(rt_server *sv, uint64_t ticket, rt_ticket_info *info);
+rt_status rt_wait(rt_server *sv, uint64_t ticket, rt_ticket_info *info, uint64_t timeout_ns);
+rt_status rt_cancel(rt_server *sv, uint64_t ticket);
+rt_status rt_server_destroy(rt_server *sv);   /* drains admitted work, cancels the rest */
+
+/* ---------------------------------------------------------------- misc */
+const char *rt_last_error(void);
+int32_t rt_abi_version(void);
+
+/* The cgs constants the library uses, in the order h, k_B, c, amu, au, pi
+ * ([host] out[n]); returns how many exist. */
+int32_t rt_constants(double *out, int32_t n);
+
+/* Tuning knobs (process-wide).  RT_OPT_CHANNEL_BLOCK: channels per lane
+ * (8, 16, 32 or 64; 0 = automatic).  RT_OPT_THIN_EXPM1: 1 (default) evaluates
+ * 1 - e^-dtau with a series for small dtau, 0 uses 1 - e^-dtau directly. */
+enum { RT_OPT_CHANNEL_BLOCK = 1, RT_OPT_THIN_EXPM1 = 2, RT_OPT_CKPT_SEGMENT = 3 };
+rt_status rt_set_option(int32_t key, int64_t value);
+int64_t rt_get_option(int32_t key);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RTCUBE_H */

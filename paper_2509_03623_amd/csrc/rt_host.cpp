@@ -1,0 +1,289 @@
+// rt_host.cpp -- C ABI of the renderer: argument validation, the
+// channel-independent constants of the line (in double, once per call), the
+// partition-function table, and kernel launches.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/rtcube.h"
+#include "rt_host.h"
+#include "rt_kernels.h"
+#include "rt_launch.h"
+
+namespace rt {
+
+// cgs constants (CODATA 2018), typed here on their own
+constexpr double kH = 6.62607015e-27;
+constexpr double kKB = 1.380649e-16;
+constexpr double kC = 2.99792458e10;
+constexpr double kAMU = 1.66053906660e-24;
+constexpr double kAU = 1.495978707e13;
+constexpr double kPI = 3.14159265358979323846;
+
+static thread_local std::string g_err;
+
+rt_status fail(rt_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+rt_status fail_hip(hipError_t e, const char *what) {
+    return fail(e == hipErrorOutOfMemory ? RT_ENOMEM : RT_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+// ---------------------------------------------------------------- options
+static int64_t g_opt_cb = 0;
+static int64_t g_opt_thin = 1;
+static int64_t g_opt_ckpt = 0;
+
+int channel_block_for(int nch) {
+    if (g_opt_cb) return (int)g_opt_cb;
+    if (nch >= 32) return 32;
+    if (nch >= 16) return 16;
+    return 8;
+}
+bool thin_series() { return g_opt_thin != 0; }
+int ckpt_segment_option() { return (int)g_opt_ckpt; }
+
+// ---------------------------------------------------------------- validation
+static bool finite(double x) { return std::isfinite(x); }
+
+rt_status validate(const rt_problem *p) {
+    if (!p) return fail(RT_EINVAL, "problem is NULL");
+    const rt_grid &g = p->grid;
+    if (g.nr < 2 || g.nz < 2) return fail(RT_EINVAL, "grid needs nr >= 2 and nz >= 2 (got %d, %d)", g.nr, g.nz);
+    if ((int64_t)g.nr * g.nz > (int64_t)1 << 30) return fail(RT_EINVAL, "grid too large");
+    if (!(finite(g.r_min_au) && finite(g.r_max_au) && g.r_min_au > 0 && g.r_max_au > g.r_min_au))
+        return fail(RT_EINVAL, "need 0 < r_min_au < r_max_au");
+    if (!(finite(g.zr_max) && g.zr_max > 0)) return fail(RT_EINVAL, "need zr_max > 0");
+    const rt_fields &f = p->f;
+    if (!f.ln_nh2 || !f.temp_k || !f.vphi_kms || !f.z_lo_au || !f.z_up_au)
+        return fail(RT_EINVAL, "a field pointer is NULL");
+    if (!(finite(f.x_co) && f.x_co >= 0)) return fail(RT_EINVAL, "need x_co >= 0");
+    if (!(finite(f.mask_width) && f.mask_width > 0)) return fail(RT_EINVAL, "need mask_width > 0");
+    if (!(finite(f.v_turb) && f.v_turb >= 0)) return fail(RT_EINVAL, "need v_turb >= 0");
+    const rt_line &l = p->line;
+    if (!(finite(l.nu0_hz) && l.nu0_hz > 0 && finite(l.a_ul) && l.a_ul >= 0 && l.g_u > 0 && l.g_l > 0 &&
+          finite(l.g_u) && finite(l.g_l) && finite(l.e_u_k) && finite(l.e_l_k) && l.e_l_k >= 0 &&
+          l.m_co_amu > 0 && l.m_mol_amu > 0 && finite(l.m_co_amu) && finite(l.m_mol_amu)))
+        return fail(RT_EINVAL, "invalid line data");
+    if (l.nlev < 1 || !l.lev_e_k || !l.lev_g) return fail(RT_EINVAL, "level table missing");
+    for (int i = 0; i < l.nlev; ++i)
+        if (!(finite(l.lev_e_k[i]) && l.lev_e_k[i] >= 0 && finite(l.lev_g[i]) && l.lev_g[i] >= 0))
+            return fail(RT_EINVAL, "invalid level %d", i);
+    const rt_camera &c = p->cam;
+    if (c.nx < 1 || c.ny < 1) return fail(RT_EINVAL, "need nx, ny >= 1");
+    if ((int64_t)c.nx * c.ny > (int64_t)1 << 30) return fail(RT_EINVAL, "image too large");
+    if (!(finite(c.fov_au) && c.fov_au > 0)) return fail(RT_EINVAL, "need fov_au > 0");
+    if (!(finite(c.incl_deg) && c.incl_deg >= 0 && c.incl_deg <= 90))
+        return fail(RT_EINVAL, "inclination must be within [0, 90] deg");
+    if (!finite(c.pa_deg)) return fail(RT_EINVAL, "position angle not finite");
+    const rt_spectral &s = p->spec;
+    if (s.nch < 1 || s.nch > RT_MAX_CHANNELS) return fail(RT_EINVAL, "need 1 <= nch <= %d", RT_MAX_CHANNELS);
+    if (!s.v_kms) return fail(RT_EINVAL, "channel velocities missing");
+    for (int i = 0; i < s.nch; ++i)
+        if (!finite(s.v_kms[i])) return fail(RT_EINVAL, "channel %d velocity not finite", i);
+    if (!finite(s.v_sys_kms)) return fail(RT_EINVAL, "v_sys not finite");
+    if (p->nsamp < 1 || p->nsamp > (1 << 20)) return fail(RT_EINVAL, "need 1 <= nsamp <= 2^20");
+    if (!finite(p->intensity_scale)) return fail(RT_EINVAL, "intensity_scale not finite");
+    if (p->mlp) {
+        if (!p->mlp->weights) return fail(RT_EINVAL, "mlp weights missing");
+        if (p->mlp->precision != RT_MLP_FP32 && p->mlp->precision != RT_MLP_BF16)
+            return fail(RT_EINVAL, "unknown mlp precision %d", p->mlp->precision);
+    }
+    return RT_OK;
+}
+
+// ---------------------------------------------------------------- Z(T) table
+struct ZKey {
+    int dev;
+    uint64_t hash;
+    bool operator<(const ZKey &o) const { return dev != o.dev ? dev < o.dev : hash < o.hash; }
+};
+static std::mutex g_ztab_mu;
+static std::map<ZKey, float4 *> g_ztab;
+
+static uint64_t fnv(uint64_t h, const void *p, size_t n) {
+    const unsigned char *b = (const unsigned char *)p;
+    for (size_t i = 0; i < n; ++i) { h ^= b[i]; h *= 1099511628211ull; }
+    return h;
+}
+
+constexpr double kZT0 = 0.1, kZT1 = 1.0e4;
+
+rt_status partition_table(const rt_line &l, const float4 **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail_hip(e, "hipGetDevice");
+    uint64_t h = 1469598103934665603ull;
+    h = fnv(h, &l.nlev, sizeof l.nlev);
+    h = fnv(h, l.lev_e_k, sizeof(double) * l.nlev);
+    h = fnv(h, l.lev_g, sizeof(double) * l.nlev);
+    std::lock_guard<std::mutex> lk(g_ztab_mu);
+    auto it = g_ztab.find({dev, h});
+    if (it != g_ztab.end()) { *out = it->second; return RT_OK; }
+    const int N = kZTableNodes;
+    const double l0 = std::log2(kZT0), l1 = std::log2(kZT1), step = (l1 - l0) / (N - 1);
+    std::vector<double> z(N), dz(N);
+    for (int i = 0; i < N; ++i) {
+        const double T = std::exp2(l0 + i * step);
+        double s = 0.0, d = 0.0;
+        for (int j = 0; j < l.nlev; ++j) {
+            const double w = l.lev_g[j] * std::exp(-l.lev_e_k[j] / T);
+            s += w;
+            d += w * l.lev_e_k[j] / T;
+        }
+        z[i] = s;
+        dz[i] = d * std::log(2.0) * step;   // dZ/d(table index)
+    }
+    std::vector<float4> tab(N - 1);
+    for (int i = 0; i < N - 1; ++i)
+        tab[i] = make_float4((float)z[i], (float)dz[i], (float)z[i + 1], (float)dz[i + 1]);
+    float4 *d = nullptr;
+    e = hipMalloc(&d, sizeof(float4) * (N - 1));
+    if (e != hipSuccess) return fail_hip(e, "hipMalloc(partition table)");
+    e = hipMemcpy(d, tab.data(), sizeof(float4) * (N - 1), hipMemcpyHostToDevice);
+    if (e != hipSuccess) { (void)hipFree(d); return fail_hip(e, "hipMemcpy(partition table)"); }
+    g_ztab[{dev, h}] = d;
+    *out = d;
+    return RT_OK;
+}
+
+// ---------------------------------------------------------------- set-up
+rt_status build_launch(const rt_problem *p, Geometry *g, Shade *s) {
+    const rt_grid &gr = p->grid;
+    const double dln = std::log(gr.r_max_au / gr.r_min_au) / (gr.nr - 1);
+    const double dzr = gr.zr_max / (gr.nz - 1);
+    const double ang = p->cam.incl_deg * kPI / 180.0, pa = p->cam.pa_deg * kPI / 180.0;
+    std::memset(g, 0, sizeof *g);
+    g->d_pix = p->cam.fov_au / p->cam.nx;
+    g->cpa = std::cos(pa);
+    g->spa = std::sin(pa);
+    g->si = std::sin(ang);
+    g->ci = std::cos(ang);
+    if (p->cam.incl_deg == 0.0) { g->si = 0.0; g->ci = 1.0; }
+    if (p->cam.incl_deg == 90.0) { g->si = 1.0; g->ci = 0.0; }
+    g->rc = gr.r_max_au * std::exp(dln);
+    g->zc = (gr.zr_max + dzr) * g->rc;
+    g->nx = p->cam.nx;
+    g->ny = p->cam.ny;
+    g->nsamp = p->nsamp;
+
+    std::memset(s, 0, sizeof *s);
+    const rt_line &l = p->line;
+    const float4 *tab = nullptr;
+    rt_status st = partition_table(l, &tab);
+    if (st != RT_OK) return st;
+    s->ln_n = p->f.ln_nh2;
+    s->temp = p->f.temp_k;
+    s->vphi = p->f.vphi_kms;
+    s->zlo = p->f.z_lo_au;
+    s->zup = p->f.z_up_au;
+    s->ztab = tab;
+    s->nr = gr.nr;
+    s->nz = gr.nz;
+    s->u_scale = (float)(std::log(2.0) / dln);
+    s->log2_rmin = (float)std::log2(gr.r_min_au);
+    s->inv_dzr = (float)(1.0 / dzr);
+    s->fnr = (float)gr.nr;
+    s->fnz = (float)gr.nz;
+    const double log2e = 1.0 / std::log(2.0);
+    s->inv_w = (float)(log2e / (p->f.mask_width * dzr));
+    const double l0 = std::log2(kZT0), l1 = std::log2(kZT1);
+    s->zt_l2t0 = (float)l0;
+    s->zt_scale = (float)((kZTableNodes - 1) / (l1 - l0));
+    s->el_log2e = (float)(l.e_l_k * log2e);
+    const double nu = l.nu0_hz;
+    s->theta = (float)(kH * nu / kKB);
+    s->c_s = (float)(p->intensity_scale * 2.0 * kH * nu * nu * nu / (kC * kC));
+    const double bul = l.a_ul * kC * kC / (2.0 * kH * nu * nu * nu);
+    const double blu = l.g_u / l.g_l * bul;
+    s->c_k = (float)(p->f.x_co * (kH * nu / (4.0 * kPI)) * blu * l.g_l * (kC / nu) * kAU /
+                     (std::sqrt(kPI) * 1e5) * log2e);
+    s->c_alpha = (float)((2.0 * kKB / (l.m_co_amu * kAMU) +
+                          p->f.v_turb * p->f.v_turb * 2.0 * kKB / (l.m_mol_amu * kAMU)) / 1e10);
+    s->sqrt_log2e = (float)std::sqrt(log2e);
+    s->vrot = (float)g->si;
+    s->vsys = (float)p->spec.v_sys_kms;
+    s->thin_thr = (float)(0.125 * log2e);
+    return RT_OK;
+}
+
+} // namespace rt
+
+using namespace rt;
+
+extern "C" {
+
+const char *rt_last_error(void) { return g_err.c_str(); }
+int32_t rt_abi_version(void) { return RT_ABI_VERSION; }
+
+int32_t rt_constants(double *out, int32_t n) {
+    const double v[6] = {kH, kKB, kC, kAMU, kAU, kPI};
+    for (int i = 0; i < n && i < 6; ++i) out[i] = v[i];
+    return 6;
+}
+
+rt_status rt_set_option(int32_t key, int64_t value) {
+    switch (key) {
+    case RT_OPT_CHANNEL_BLOCK:
+        if (value != 0 && value != 8 && value != 16 && value != 32 && value != 64)
+            return fail(RT_EINVAL, "channel block must be 0, 8, 16, 32 or 64");
+        g_opt_cb = value;
+        return RT_OK;
+    case RT_OPT_THIN_EXPM1:
+        g_opt_thin = value ? 1 : 0;
+        return RT_OK;
+    case RT_OPT_CKPT_SEGMENT:
+        if (value < 0 || value > 64) return fail(RT_EINVAL, "checkpoint segment must be 0..64");
+        g_opt_ckpt = value;
+        return RT_OK;
+    default:
+        return fail(RT_EINVAL, "unknown option %d", key);
+    }
+}
+
+int64_t rt_get_option(int32_t key) {
+    switch (key) {
+    case RT_OPT_CHANNEL_BLOCK: return g_opt_cb;
+    case RT_OPT_THIN_EXPM1: return g_opt_thin;
+    case RT_OPT_CKPT_SEGMENT: return g_opt_ckpt;
+    default: return -1;
+    }
+}
+
+rt_status rt_render_cube(const rt_problem *p, float *cube, void *stream) {
+    rt_status st = validate(p);
+    if (st != RT_OK) return st;
+    if (!cube) return fail(RT_EINVAL, "cube is NULL");
+    if (p->mlp) return render_cube_mlp(p, cube, (hipStream_t)stream);
+    Geometry g;
+    Shade s;
+    st = build_launch(p, &g, &s);
+    if (st != RT_OK) return st;
+    const int cb = channel_block_for(p->spec.nch);
+    const size_t plane = (size_t)p->cam.nx * p->cam.ny;
+    for (int c0 = 0; c0 < p->spec.nch; c0 += kLaunchChannels) {
+        Channels ch;
+        std::memset(&ch, 0, sizeof ch);
+        ch.n = std::min(kLaunchChannels, p->spec.nch - c0);
+        for (int c = 0; c < ch.n; ++c) ch.v[c] = (float)p->spec.v_kms[c0 + c];
+        hipError_t e = launch_forward(g, s, ch, cube + (size_t)c0 * plane, cb, thin_series(), (hipStream_t)stream);
+        if (e != hipSuccess) return fail_hip(e, "forward launch");
+    }
+    return RT_OK;
+}
+
+} // extern "C"

@@ -1,0 +1,20 @@
+// rt_host.h -- internal host helpers shared by the library's translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "../../include/rtcube.h"
+#include "rt_kernels.h"
+
+namespace rt {
+
+rt_status fail(rt_status st, const char *fmt, ...);
+rt_status fail_hip(hipError_t e, const char *what);
+rt_status validate(const rt_problem *p);
+rt_status build_launch(const rt_problem *p, Geometry *g, Shade *s);
+int channel_block_for(int nch);
+bool thin_series();
+int ckpt_segment_option();
+
+rt_status render_cube_mlp(const rt_problem *p, float *cube, hipStream_t st);
+
+} // namespace rt

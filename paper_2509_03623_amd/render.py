@@ -1,0 +1,217 @@
+"""Torch-facing calls of the renderer (device memory and streams only).
+
+``Scene`` holds a problem with its fields resident on the GPU; ``render``
+and ``render_adjoint`` marshal it into the C structs of include/rtcube.h and
+call the library on torch's current stream.  ``Render`` is the
+torch.autograd.Function whose backward is the library's adjoint.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass, field, replace
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+_f = C.POINTER(C.c_float)
+
+
+@dataclass
+class Scene:
+    nr: int
+    nz: int
+    r_min_au: float
+    r_max_au: float
+    zr_max: float
+    ln_nh2: torch.Tensor      # [nr, nz] float32, device
+    temp_k: torch.Tensor
+    vphi_kms: torch.Tensor
+    z_lo_au: torch.Tensor     # [nr]
+    z_up_au: torch.Tensor
+    x_co: float
+    mask_width: float
+    v_turb: float
+    nu0_hz: float
+    a_ul: float
+    g_u: float
+    g_l: float
+    e_u_k: float
+    e_l_k: float
+    m_co_amu: float
+    m_mol_amu: float
+    lev_e_k: np.ndarray
+    lev_g: np.ndarray
+    nx: int
+    ny: int
+    fov_au: float
+    incl_deg: float
+    pa_deg: float
+    dist_pc: float
+    v_kms: np.ndarray
+    v_sys_kms: float
+    nsamp: int
+    intensity_scale: float = 1.0
+    mlp_w: Optional[torch.Tensor] = None
+    mlp_precision: int = L.RT_MLP_BF16
+    keep: list = field(default_factory=list, repr=False)
+
+    @property
+    def nch(self) -> int:
+        return int(len(self.v_kms))
+
+    @property
+    def ray_samples(self) -> int:
+        return self.nx * self.ny * self.nch * self.nsamp
+
+    def replace(self, **kw) -> "Scene":
+        return replace(self, **kw)
+
+
+def scene_from_problem(prob, device="cuda", mlp_precision=L.RT_MLP_BF16) -> Scene:
+    """Copy a problem description (attributes as in synth.Problem) to the GPU."""
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a, np.float32), device=device)
+    g, cam, line = prob.grid, prob.camera, prob.line
+    mlp = getattr(prob, "mlp_w", None)
+    return Scene(nr=g.nr, nz=g.nz, r_min_au=g.r_min_au, r_max_au=g.r_max_au, zr_max=g.zr_max,
+                 ln_nh2=t(prob.ln_nh2), temp_k=t(prob.temp_k), vphi_kms=t(prob.vphi_kms),
+                 z_lo_au=t(prob.z_lo_au), z_up_au=t(prob.z_up_au), x_co=prob.x_co,
+                 mask_width=prob.mask_width, v_turb=prob.v_turb, nu0_hz=line.nu0_hz, a_ul=line.a_ul,
+                 g_u=line.g_u, g_l=line.g_l, e_u_k=line.e_u_k, e_l_k=line.e_l_k,
+                 m_co_amu=line.m_co_amu, m_mol_amu=line.m_mol_amu,
+                 lev_e_k=np.ascontiguousarray(line.lev_e_k, np.float64),
+                 lev_g=np.ascontiguousarray(line.lev_g, np.float64), nx=cam.nx, ny=cam.ny,
+                 fov_au=cam.fov_au, incl_deg=cam.incl_deg, pa_deg=cam.pa_deg, dist_pc=cam.dist_pc,
+                 v_kms=np.ascontiguousarray(prob.v_kms, np.float64), v_sys_kms=prob.v_sys_kms,
+                 nsamp=prob.nsamp, intensity_scale=prob.intensity_scale,
+                 mlp_w=None if mlp is None else t(mlp), mlp_precision=mlp_precision)
+
+
+def _fptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return _f()
+    if t.dtype != torch.float32 or not t.is_contiguous() or t.device.type != "cuda":
+        raise ValueError("expected a contiguous float32 CUDA tensor")
+    return C.cast(C.c_void_p(t.data_ptr()), _f)
+
+
+def problem_struct(sc: Scene, fields: Optional[dict] = None):
+    """rt_problem for the scene (fields may override the scene's tensors).
+    Returns (struct, keepalive)."""
+    fl = dict(ln_nh2=sc.ln_nh2, temp_k=sc.temp_k, vphi_kms=sc.vphi_kms, z_lo_au=sc.z_lo_au,
+              z_up_au=sc.z_up_au, mlp_w=sc.mlp_w)
+    if fields:
+        fl.update(fields)
+    for k, n in (("ln_nh2", sc.nr * sc.nz), ("temp_k", sc.nr * sc.nz), ("vphi_kms", sc.nr * sc.nz),
+                 ("z_lo_au", sc.nr), ("z_up_au", sc.nr)):
+        if fl[k].numel() != n:
+            raise ValueError(f"{k} has {fl[k].numel()} elements, expected {n}")
+    lev_e = np.ascontiguousarray(sc.lev_e_k, np.float64)
+    lev_g = np.ascontiguousarray(sc.lev_g, np.float64)
+    vk = np.ascontiguousarray(sc.v_kms, np.float64)
+    p = L.rt_problem()
+    p.grid = L.rt_grid(sc.nr, sc.nz, sc.r_min_au, sc.r_max_au, sc.zr_max)
+    p.f = L.rt_fields(_fptr(fl["ln_nh2"]), _fptr(fl["temp_k"]), _fptr(fl["vphi_kms"]), _fptr(fl["z_lo_au"]),
+                      _fptr(fl["z_up_au"]), sc.x_co, sc.mask_width, sc.v_turb)
+    p.line = L.rt_line(sc.nu0_hz, sc.a_ul, sc.g_u, sc.g_l, sc.e_u_k, sc.e_l_k, sc.m_co_amu, sc.m_mol_amu,
+                       len(lev_e), lev_e.ctypes.data_as(C.POINTER(C.c_double)),
+                       lev_g.ctypes.data_as(C.POINTER(C.c_double)))
+    p.cam = L.rt_camera(sc.nx, sc.ny, sc.fov_au, sc.incl_deg, sc.pa_deg, sc.dist_pc)
+    p.spec = L.rt_spectral(len(vk), vk.ctypes.data_as(C.POINTER(C.c_double)), sc.v_sys_kms)
+    p.nsamp = sc.nsamp
+    p.intensity_scale = sc.intensity_scale
+    keep = [lev_e, lev_g, vk, fl]
+    if fl["mlp_w"] is not None:
+        if fl["mlp_w"].numel() != L.RT_MLP_PARAMS:
+            raise ValueError("mlp_w has the wrong number of parameters")
+        m = L.rt_mlp(_fptr(fl["mlp_w"]), sc.mlp_precision)
+        keep.append(m)
+        p.mlp = C.pointer(m)
+    return p, keep
+
+
+def _stream(stream=None) -> int:
+    s = torch.cuda.current_stream() if stream is None else stream
+    return int(s.cuda_stream)
+
+
+def render(sc: Scene, out: Optional[torch.Tensor] = None, stream=None, fields=None) -> torch.Tensor:
+    """Cube [nch, ny, nx] (float32, on the scene's device)."""
+    dev = sc.ln_nh2.device
+    if out is None:
+        out = torch.empty(sc.nch, sc.ny, sc.nx, dtype=torch.float32, device=dev)
+    if out.shape != (sc.nch, sc.ny, sc.nx):
+        raise ValueError("output has the wrong shape")
+    p, keep = problem_struct(sc, fields)
+    L.check(L.lib().rt_render_cube(C.byref(p), _fptr(out), C.c_void_p(_stream(stream))))
+    del keep
+    return out
+
+
+GRAD_KEYS = ("ln_nh2", "temp_k", "vphi_kms", "z_lo_au", "z_up_au", "mlp_w")
+
+
+def render_adjoint(sc: Scene, dl_dcube: torch.Tensor, want=GRAD_KEYS, cube_out: Optional[torch.Tensor] = None,
+                   stream=None, fields=None) -> dict:
+    """Gradients of L w.r.t. the requested inputs given dL/dcube."""
+    dev = sc.ln_nh2.device
+    dl = dl_dcube.contiguous().to(torch.float32)
+    if dl.shape != (sc.nch, sc.ny, sc.nx):
+        raise ValueError("dL/dcube has the wrong shape")
+    shapes = dict(ln_nh2=(sc.nr, sc.nz), temp_k=(sc.nr, sc.nz), vphi_kms=(sc.nr, sc.nz), z_lo_au=(sc.nr,),
+                  z_up_au=(sc.nr,), mlp_w=(L.RT_MLP_PARAMS,))
+    out = {}
+    for k in want:
+        if k == "mlp_w" and sc.mlp_w is None:
+            continue
+        out[k] = torch.empty(shapes[k], dtype=torch.float32, device=dev)
+    g = L.rt_grads(_fptr(out.get("ln_nh2")), _fptr(out.get("temp_k")), _fptr(out.get("vphi_kms")),
+                   _fptr(out.get("z_lo_au")), _fptr(out.get("z_up_au")), _fptr(out.get("mlp_w")))
+    p, keep = problem_struct(sc, fields)
+    L.check(L.lib().rt_render_cube_adjoint(C.byref(p), _fptr(dl), C.byref(g), _fptr(cube_out),
+                                           C.c_void_p(_stream(stream))))
+    del keep
+    return out
+
+
+class Render(torch.autograd.Function):
+    """cube = Render.apply(scene, ln_nh2, temp_k, vphi_kms, z_lo_au, z_up_au, mlp_w)."""
+
+    @staticmethod
+    def forward(ctx, sc, ln_nh2, temp_k, vphi_kms, z_lo_au, z_up_au, mlp_w=None):
+        fields = dict(ln_nh2=ln_nh2.detach().contiguous(), temp_k=temp_k.detach().contiguous(),
+                      vphi_kms=vphi_kms.detach().contiguous(), z_lo_au=z_lo_au.detach().contiguous(),
+                      z_up_au=z_up_au.detach().contiguous(),
+                      mlp_w=None if mlp_w is None else mlp_w.detach().contiguous())
+        ctx.sc = sc
+        ctx.fields = fields
+        return render(sc, fields=fields)
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        want = [k for k, need in zip(GRAD_KEYS, ctx.needs_input_grad[1:]) if need]
+        g = render_adjoint(ctx.sc, grad_out, want=want, fields=ctx.fields)
+        return (None,) + tuple(g.get(k) for k in GRAD_KEYS)
+
+
+def render_differentiable(sc: Scene, ln_nh2=None, temp_k=None, vphi_kms=None, z_lo_au=None, z_up_au=None,
+                          mlp_w=None) -> torch.Tensor:
+    a = lambda x, d: d if x is None else x
+    return Render.apply(sc, a(ln_nh2, sc.ln_nh2), a(temp_k, sc.temp_k), a(vphi_kms, sc.vphi_kms),
+                        a(z_lo_au, sc.z_lo_au), a(z_up_au, sc.z_up_au), a(mlp_w, sc.mlp_w))
+
+
+def set_option(key: int, value: int) -> None:
+    L.check(L.lib().rt_set_option(key, value))
+
+
+def get_option(key: int) -> int:
+    return int(L.lib().rt_get_option(key))
+
+
+def constants() -> dict:
+    out = (C.c_double * 6)()
+    L.lib().rt_constants(out, 6)
+    return dict(zip(["h", "k_B", "c", "amu", "au", "pi"], list(out)))

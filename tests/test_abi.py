@@ -1,0 +1,99 @@
+"""Host-side checks of the C ABI (no GPU work): the library loads, exports
+every symbol include/rtcube.h declares, rejects invalid problems on the host,
+and types the same physical constants as the oracle."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+import paper_2509_03623_amd as rt
+from paper_2509_03623_amd import _lib as L
+
+HEADER = os.path.join(os.path.dirname(__file__), "..", "include", "rtcube.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(rt_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = L.lib()
+    names = declared_functions()
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(L.EXPORTS) == names
+
+
+def test_abi_version():
+    assert L.lib().rt_abi_version() == 1
+
+
+def test_constants_match_oracle_digit_for_digit():
+    assert rt.constants() == oracle.constants()
+
+
+def _struct_for(prob):
+    """rt_problem with host-only fake device pointers (validation never
+    dereferences them)."""
+    fake = C.cast(C.c_void_p(0x1000), C.POINTER(C.c_float))
+    g, cam, line = prob.grid, prob.camera, prob.line
+    lev_e = np.ascontiguousarray(line.lev_e_k)
+    lev_g = np.ascontiguousarray(line.lev_g)
+    vk = np.ascontiguousarray(prob.v_kms)
+    p = L.rt_problem()
+    p.grid = L.rt_grid(g.nr, g.nz, g.r_min_au, g.r_max_au, g.zr_max)
+    p.f = L.rt_fields(fake, fake, fake, fake, fake, prob.x_co, prob.mask_width, prob.v_turb)
+    p.line = L.rt_line(line.nu0_hz, line.a_ul, line.g_u, line.g_l, line.e_u_k, line.e_l_k, line.m_co_amu,
+                       line.m_mol_amu, len(lev_e), lev_e.ctypes.data_as(C.POINTER(C.c_double)),
+                       lev_g.ctypes.data_as(C.POINTER(C.c_double)))
+    p.cam = L.rt_camera(cam.nx, cam.ny, cam.fov_au, cam.incl_deg, cam.pa_deg, cam.dist_pc)
+    p.spec = L.rt_spectral(len(vk), vk.ctypes.data_as(C.POINTER(C.c_double)), prob.v_sys_kms)
+    p.nsamp = prob.nsamp
+    p.intensity_scale = 1.0
+    return p, (lev_e, lev_g, vk), fake
+
+
+@pytest.mark.parametrize("mutate,msg", [
+    (lambda p: setattr(p.grid, "nr", 1), "nr >= 2"),
+    (lambda p: setattr(p.grid, "r_min_au", -1.0), "r_min"),
+    (lambda p: setattr(p.grid, "zr_max", 0.0), "zr_max"),
+    (lambda p: setattr(p.f, "ln_nh2", C.POINTER(C.c_float)()), "NULL"),
+    (lambda p: setattr(p.f, "mask_width", 0.0), "mask_width"),
+    (lambda p: setattr(p.cam, "nx", 0), "nx"),
+    (lambda p: setattr(p.cam, "incl_deg", 95.0), "inclination"),
+    (lambda p: setattr(p.cam, "fov_au", float("nan")), "fov"),
+    (lambda p: setattr(p.spec, "nch", 0), "nch"),
+    (lambda p: setattr(p, "nsamp", 0), "nsamp"),
+    (lambda p: setattr(p.line, "nlev", 0), "level"),
+])
+def test_validation_rejects_on_host(mutate, msg):
+    prob = synth.small_problem()
+    p, keep, fake = _struct_for(prob)
+    mutate(p)
+    st = L.lib().rt_render_cube(C.byref(p), fake, None)
+    assert st == L.RT_EINVAL
+    assert msg in L.lib().rt_last_error().decode()
+
+
+def test_null_outputs_rejected():
+    prob = synth.small_problem()
+    p, keep, fake = _struct_for(prob)
+    assert L.lib().rt_render_cube(C.byref(p), C.POINTER(C.c_float)(), None) == L.RT_EINVAL
+    assert L.lib().rt_render_cube(None, fake, None) == L.RT_EINVAL
+
+
+def test_options_roundtrip():
+    lib = L.lib()
+    old = lib.rt_get_option(L.RT_OPT_CHANNEL_BLOCK)
+    assert lib.rt_set_option(L.RT_OPT_CHANNEL_BLOCK, 16) == 0
+    assert lib.rt_get_option(L.RT_OPT_CHANNEL_BLOCK) == 16
+    assert lib.rt_set_option(L.RT_OPT_CHANNEL_BLOCK, 12) == L.RT_EINVAL
+    assert lib.rt_set_option(L.RT_OPT_CHANNEL_BLOCK, old) == 0
+    assert lib.rt_set_option(999, 1) == L.RT_EINVAL

@@ -1,0 +1,140 @@
+"""GPU forward march vs the FP64 oracle, element by element.
+
+Bar: max |I_gpu - I_64| <= 1e-5 max |I_64| over each cube (FP32 arithmetic on
+the GPU against FP64 on the CPU)."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+def _rt():
+    import paper_2509_03623_amd as rt
+    return rt
+
+
+def gpu_cube(prob, **opts):
+    rt = _rt()
+    from paper_2509_03623_amd import _lib as L
+    old = {}
+    for k, v in opts.items():
+        key = {"cb": L.RT_OPT_CHANNEL_BLOCK, "thin": L.RT_OPT_THIN_EXPM1}[k]
+        old[key] = rt.get_option(key)
+        rt.set_option(key, v)
+    try:
+        print(f"[gpu] render {prob.meta.get('config')} {prob.camera.nx}x{prob.camera.ny}x{prob.nch} "
+              f"ns={prob.nsamp} opts={opts}", flush=True)
+        sc = rt.scene_from_problem(prob)
+        cube = rt.render(sc)
+        torch.cuda.synchronize()
+        return cube.cpu().numpy().astype(np.float64)
+    finally:
+        for key, v in old.items():
+            rt.set_option(key, v)
+
+
+def rel_err(a, ref):
+    return float(np.abs(a - ref).max() / max(np.abs(ref).max(), 1e-300))
+
+
+def test_config1_full_cube():
+    prob = synth.config1()
+    ref = oracle.render(prob)
+    got = gpu_cube(prob)
+    err = rel_err(got, ref)
+    print("config1 max|dI|/peak =", err)
+    assert ref.max() > 0
+    assert err <= TOL
+
+
+@pytest.mark.parametrize("cb", [8, 16, 32, 64])
+@pytest.mark.parametrize("thin", [1, 0])
+def test_channel_blocks_and_ragged_tiles(cb, thin):
+    # 37 x 23 pixels: ragged 16 x 16 tiles; 13 channels: ragged channel blocks
+    prob = synth.small_problem(nx=37, ny=23, nch=13, nsamp=96, nr=64, nz=32, seed=11, dv=0.2)
+    ref = oracle.render(prob)
+    got = gpu_cube(prob, cb=cb, thin=thin)
+    assert rel_err(got, ref) <= TOL
+
+
+def test_mirror_symmetry_on_gpu():
+    prob = synth.config1(nx=48, ny=40, nch=12, nsamp=128, incl=55.0)
+    got = gpu_cube(prob)
+    mir = got[::-1, :, ::-1]
+    assert np.abs(got - mir).max() <= 1e-6 * np.abs(got).max()
+
+
+def test_isothermal_slab_on_gpu():
+    prob = synth.slab_problem(temp=40.0, ln_n=math.log(1e6))
+    ref = oracle.render(prob)
+    got = gpu_cube(prob)
+    assert rel_err(got, ref) <= TOL
+
+
+@pytest.mark.parametrize("case", ["nsamp1", "one_pixel", "one_channel", "face_on", "edge_on", "pa",
+                                  "many_channels", "vsys", "empty_corners"])
+def test_edge_cases(case):
+    base = dict(nx=20, ny=18, nch=7, nsamp=64, nr=32, nz=16, seed=9)
+    prob = {
+        "nsamp1": lambda: synth.small_problem(**{**base, "nsamp": 1}),
+        "one_pixel": lambda: synth.small_problem(**{**base, "nx": 1, "ny": 1}),
+        "one_channel": lambda: synth.small_problem(**{**base, "nch": 1}),
+        "face_on": lambda: synth.small_problem(**{**base, "incl": 0.0}),
+        "edge_on": lambda: synth.small_problem(**{**base, "incl": 90.0}),
+        "pa": lambda: synth.small_problem(**{**base, "pa": 37.0}),
+        "many_channels": lambda: synth.small_problem(**{**base, "nx": 9, "ny": 7, "nch": 300, "dv": 0.02}),
+        "vsys": lambda: synth.small_problem(**{**base, "v_sys": 5.76}),
+        "empty_corners": lambda: synth.small_problem(**{**base, "fov": 3000.0}),
+    }[case]()
+    ref = oracle.render(prob)
+    got = gpu_cube(prob)
+    if ref.max() == 0:
+        assert np.all(got == 0)
+    else:
+        assert rel_err(got, ref) <= TOL
+    if case == "empty_corners":
+        assert got[:, 0, 0].max() == 0.0
+
+
+def test_zero_density_gives_zero():
+    prob = synth.small_problem()
+    prob = prob.replace(ln_nh2=np.full_like(prob.ln_nh2, -1000.0))
+    got = gpu_cube(prob)
+    assert np.all(got == 0.0)
+
+
+def test_deterministic():
+    prob = synth.config1(nx=32, ny=32)
+    a = gpu_cube(prob)
+    b = gpu_cube(prob)
+    assert np.array_equal(a, b)
+
+
+def test_full_size_sampled_pixels():
+    """512 x 512 x 64 x 512 on a 256 x 128 grid, in the benchmark's launch
+    configuration; the oracle evaluates 160 seeded pixels one by one."""
+    prob = synth.config2(2000)
+    got = gpu_cube(prob)
+    rng = np.random.Generator(np.random.PCG64(12))
+    nx, ny = prob.camera.nx, prob.camera.ny
+    # pixels spread over the whole image plus the brightest rows
+    px = rng.integers(0, nx, 120)
+    py = rng.integers(0, ny, 120)
+    peak_q, peak_p = np.unravel_index(np.argmax(got.max(axis=0)), (ny, nx))
+    px = np.concatenate([px, peak_p + rng.integers(-20, 21, 40)]).clip(0, nx - 1)
+    py = np.concatenate([py, peak_q + rng.integers(-20, 21, 40)]).clip(0, ny - 1)
+    ref = oracle.render_pixels(prob, px, py)            # [n][nch]
+    sub = got[:, py, px].T
+    scale = max(ref.max(), 1e-300)
+    err = float(np.abs(sub - ref).max() / scale)
+    print("config2 sampled max|dI|/peak(sample) =", err)
+    assert ref.max() > 0
+    assert err <= TOL
