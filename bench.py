@@ -19,10 +19,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# MI355X unit counts and clock: 256 CUs x 4 SIMDs x 16 lanes at 2.4 GHz issue
-# 3.93e13 single-rate FP32 lane-instructions per second; a transcendental
-# (exp2, log2, rcp, rsq, sqrt) takes 4 issue slots.
-LANE_SLOTS_PER_S = 256 * 4 * 16 * 2.4e9
+# MI355X unit counts and clock: 256 CUs, each issuing 128 FP32 VALU lanes per
+# clock (4 SIMDs x 32 lanes: the published 157.3 TFLOP/s FP32 vector rate is
+# 256 x 128 x 2 FLOP x 2.4 GHz, reached by unpacked v_fma_f32), i.e. 7.86e13
+# lane-instructions per second; a transcendental (exp2, log2, rcp, rsq,
+# sqrt) runs at a quarter of that rate, i.e. takes 4 issue slots.
+LANE_SLOTS_PER_S = 256 * 128 * 2.4e9
 TRANS_SLOTS = 4
 # Algorithmic work of one ray-sample in the channel loop: d = a - v b (FMA),
 # d^2, g = 2^-d^2, x = K g, att = 2^-x, 1 - att, Tr (1 - att), I += . S (FMA),
@@ -39,6 +41,20 @@ def algorithmic(nch: int, cb: int):
     flop = LOOP_FLOP + SHADE_FLOP / cb
     slots = LOOP_VALU + TRANS_SLOTS * LOOP_TRANS + (SHADE_VALU + TRANS_SLOTS * SHADE_TRANS) / cb
     return flop, slots
+
+
+def auto_shape(nch: int, npix: int, nsamp: int):
+    """The library's automatic (channel block, ray split) of the forward
+    march (same rule as its host code)."""
+    cb = next((c for c in (8, 16, 24, 32, 48, 64) if c >= nch), 64)
+    waves = lambda c, ns: ((npix * ns + 63) // 64) * ((nch + c - 1) // c)
+    if cb == 64 and waves(64, 1) < 4096:
+        cb = 32
+    max_split = 1 if cb >= 64 else (4 if cb >= 48 else 8)
+    ns = 1
+    while ns < max_split and waves(cb, ns) < 4096 and nsamp >= 32 * ns:
+        ns *= 2
+    return cb, ns
 
 
 def cpu_baseline(prob, seconds=12.0):
@@ -111,7 +127,7 @@ def main():
     ms_per_step = wall * 1e3 / args.steps
     rs = sc.ray_samples
     value = rs / (wall / args.steps)
-    cb = rt.get_option(L.RT_OPT_CHANNEL_BLOCK) or (32 if sc.nch >= 32 else (16 if sc.nch >= 16 else 8))
+    cb = rt.get_option(L.RT_OPT_CHANNEL_BLOCK) or auto_shape(sc.nch, sc.nx * sc.ny, sc.nsamp)[0]
     flop, slots = algorithmic(sc.nch, cb)
     achieved = flop * rs / (kern_ms * 1e-3) / 1e12
     peak = flop / slots * LANE_SLOTS_PER_S / 1e12

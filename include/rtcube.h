@@ -203,10 +203,14 @@ int32_t rt_abi_version(void);
  * ([host] out[n]); returns how many exist. */
 int32_t rt_constants(double *out, int32_t n);
 
-/* Tuning knobs (process-wide).  RT_OPT_CHANNEL_BLOCK: channels per lane
- * (8, 16, 32 or 64; 0 = automatic).  RT_OPT_THIN_EXPM1: 1 (default) evaluates
- * 1 - e^-dtau with a series for small dtau, 0 uses 1 - e^-dtau directly. */
-enum { RT_OPT_CHANNEL_BLOCK = 1, RT_OPT_THIN_EXPM1 = 2, RT_OPT_CKPT_SEGMENT = 3 };
+/* Tuning knobs (process-wide).  RT_OPT_CHANNEL_BLOCK: channels per lane of
+ * the forward march (8, 16, 24, 32, 48 or 64; 0 = automatic).
+ * RT_OPT_THIN_EXPM1: 1 evaluates 1 - e^-dtau of the forward march with a
+ * series for small dtau, 0 (default) uses 1 - e^-dtau directly.
+ * RT_OPT_CKPT_SEGMENT: samples per checkpoint segment of the adjoint (4, 8 or
+ * 16; 0 = automatic).  RT_OPT_RAY_SPLIT: lanes sharing one ray in the forward
+ * march, each taking a consecutive sub-chord (1, 2, 4 or 8; 0 = automatic). */
+enum { RT_OPT_CHANNEL_BLOCK = 1, RT_OPT_THIN_EXPM1 = 2, RT_OPT_CKPT_SEGMENT = 3, RT_OPT_RAY_SPLIT = 4 };
 rt_status rt_set_option(int32_t key, int64_t value);
 int64_t rt_get_option(int32_t key);
 

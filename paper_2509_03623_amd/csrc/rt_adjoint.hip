@@ -1,0 +1,275 @@
+// rt_adjoint.hip -- reverse-mode derivative of the ray march.
+//
+// Pass A (adj_tape): one lane per pixel walks its ray and writes the
+//   channel-independent sample quantities (S, K, a, b) of every sample to a
+//   sample-major tape, plus the ray's set-up.
+// Pass B (adj_march<CB, KSEG>): one lane per pixel x channel block.  A
+//   forward sweep stores the transmission of each channel at the start of
+//   every KSEG-sample segment (the checkpoints); the reverse sweep visits the
+//   segments back to front, recomputes the segment's transmissions in
+//   registers from its checkpoint, and walks it backwards with the
+//   intensity-from-behind recurrence
+//       J_{k-1} = S_k (1 - a_k) + a_k J_k,
+//   giving dI/dS_k = Tr_k (1 - a_k) and dI/ddtau_k = Tr_{k+1} (S_k - J_k)
+//   without the cancellation of I minus a prefix sum.  Channel sums of the
+//   per-sample cotangents (S, K, a, b) are written per channel block.
+// Pass C (adj_chain): one lane per pixel-sample recomputes the shading with
+//   its local derivatives, chains the cotangents to the interpolated fields
+//   and scatters them to the grid nodes (float atomics; the surface vectors
+//   are accumulated in LDS first).
+#include "rt_adjoint.h"
+
+namespace rt {
+
+__global__ __launch_bounds__(256) void adj_tape(Geometry g, Shade s, float4 *__restrict__ tape,
+                                                float4 *__restrict__ rays) {
+    __shared__ float4 ztab[kZTableNodes - 1];
+    stage_ztab(s, ztab);
+    const int npix = g.nx * g.ny;
+    const int pix = blockIdx.x * 256 + threadIdx.x;
+    if (pix >= npix) return;
+    const RaySetup r = ray_setup(g, pix % g.nx, pix / g.nx);
+    rays[pix] = make_float4(r.px, r.pmy, r.pmz, r.live ? r.ds : 0.0f);
+    const float half = 0.5f * (float)g.nsamp;
+    for (int k = 0; k < g.nsamp; ++k) {
+        float4 o = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if (r.live) {
+            const float t = ((float)k + 0.5f - half) * r.ds;
+            const SampleQ q = shade_sample(s, ztab, r.px, fmaf(t, r.wy, r.pmy), fmaf(t, r.wz, r.pmz), r.ds);
+            o = make_float4(q.S, q.K, q.a, q.b);
+        }
+        tape[(size_t)k * npix + pix] = o;
+    }
+}
+
+template <int CB, int KSEG>
+__global__ __launch_bounds__(256) void adj_march(int nsamp, int npix, Channels ch, const float4 *__restrict__ tape,
+                                                 const float *__restrict__ dl_dcube, float *__restrict__ ckpt,
+                                                 float4 *__restrict__ cot, float *__restrict__ cube_out) {
+    const int pix = blockIdx.x * 256 + threadIdx.x;
+    if (pix >= npix) return;
+    const int blk = blockIdx.y, nblk = gridDim.y;
+    const int c0 = blk * CB;
+    const int nseg = (nsamp + KSEG - 1) / KSEG;
+    float w[CB], Tr[CB], I[CB];
+#pragma unroll
+    for (int c = 0; c < CB; ++c) {
+        w[c] = (c0 + c < ch.n) ? dl_dcube[(size_t)(c0 + c) * npix + pix] : 0.0f;
+        Tr[c] = 1.0f;
+        I[c] = 0.0f;
+    }
+    // forward sweep with checkpoints
+    for (int seg = 0; seg < nseg; ++seg) {
+#pragma unroll
+        for (int c = 0; c < CB; ++c) ckpt[((size_t)seg * nblk * CB + c0 + c) * npix + pix] = Tr[c];
+#pragma unroll
+        for (int kk = 0; kk < KSEG; ++kk) {
+            const int k = seg * KSEG + kk;
+            if (k < nsamp) {
+                const float4 q = tape[(size_t)k * npix + pix];
+#pragma unroll
+                for (int c = 0; c < CB; ++c) {
+                    const float d = fmaf(-ch.v[c0 + c], q.w, q.z);
+                    const float att = fexp2(-(q.y * fexp2(-(d * d))));
+                    I[c] = fmaf(Tr[c] * (1.0f - att), q.x, I[c]);
+                    Tr[c] *= att;
+                }
+            }
+        }
+    }
+    if (cube_out) {
+#pragma unroll
+        for (int c = 0; c < CB; ++c)
+            if (c0 + c < ch.n) cube_out[(size_t)(c0 + c) * npix + pix] = I[c];
+    }
+    // reverse sweep, one segment at a time
+    float J[CB];
+#pragma unroll
+    for (int c = 0; c < CB; ++c) J[c] = 0.0f;
+    for (int seg = nseg - 1; seg >= 0; --seg) {
+        float4 Q[KSEG];
+        float TrK[KSEG][CB];
+#pragma unroll
+        for (int c = 0; c < CB; ++c) Tr[c] = ckpt[((size_t)seg * nblk * CB + c0 + c) * npix + pix];
+#pragma unroll
+        for (int kk = 0; kk < KSEG; ++kk) {
+            const int k = seg * KSEG + kk;
+            Q[kk] = k < nsamp ? tape[(size_t)k * npix + pix] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+#pragma unroll
+            for (int c = 0; c < CB; ++c) {
+                TrK[kk][c] = Tr[c];
+                const float d = fmaf(-ch.v[c0 + c], Q[kk].w, Q[kk].z);
+                Tr[c] *= fexp2(-(Q[kk].y * fexp2(-(d * d))));
+            }
+        }
+#pragma unroll
+        for (int kk = KSEG - 1; kk >= 0; --kk) {
+            const int k = seg * KSEG + kk;
+            if (k >= nsamp) continue;
+            const float S = Q[kk].x, K = Q[kk].y, a = Q[kk].z, b = Q[kk].w;
+            float cS = 0.0f, cK = 0.0f, ca = 0.0f, cb = 0.0f;
+#pragma unroll
+            for (int c = 0; c < CB; ++c) {
+                const float vc = ch.v[c0 + c];
+                const float d = fmaf(-vc, b, a);
+                const float gk = fexp2(-(d * d));
+                const float att = fexp2(-(K * gk));
+                const float om = 1.0f - att;
+                const float t0 = TrK[kk][c];
+                const float t1 = t0 * att;
+                cS = fmaf(w[c] * t0, om, cS);
+                // dL/d(dtau) with dtau = ln2 K g, g = 2^-d^2
+                const float gg = w[c] * t1 * (S - J[c]) * kLn2 * gk;
+                J[c] = fmaf(att, J[c], S * om);
+                cK += gg;
+                const float gd = gg * K * (-2.0f * kLn2) * d;
+                ca += gd;
+                cb = fmaf(-vc, gd, cb);
+            }
+            cot[((size_t)blk * nsamp + k) * npix + pix] = make_float4(cS, cK, ca, cb);
+        }
+    }
+}
+
+__device__ __forceinline__ void scatter4(double *dst, int n00, int n10, float gv, float w00, float w01, float w10,
+                                         float w11) {
+    if (!dst || gv == 0.0f) return;
+    atomicAdd(dst + n00, (double)(gv * w00));
+    atomicAdd(dst + n00 + 1, (double)(gv * w01));
+    atomicAdd(dst + n10, (double)(gv * w10));
+    atomicAdd(dst + n10 + 1, (double)(gv * w11));
+}
+
+__global__ __launch_bounds__(256) void adj_chain(Geometry g, Shade s, const float4 *__restrict__ rays,
+                                                 const float4 *__restrict__ cot, int nblk, GradAcc go,
+                                                 int lds_surfaces) {
+    extern __shared__ double lds[];  // [2][nr] surface gradients when lds_surfaces
+    __shared__ float4 ztab[kZTableNodes - 1];
+    stage_ztab(s, ztab);
+    const int npix = g.nx * g.ny;
+    const int nr = s.nr;
+    if (lds_surfaces) {
+        for (int i = threadIdx.x; i < 2 * nr; i += 256) lds[i] = 0.0;
+        __syncthreads();
+    }
+    const size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x;
+    const size_t total = (size_t)g.nsamp * npix;
+    if (idx < total) {
+        const int k = (int)(idx / npix);
+        const int pix = (int)(idx - (size_t)k * npix);
+        const float4 r = rays[pix];
+        float4 c = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        for (int b = 0; b < nblk; ++b) {
+            const float4 t = cot[((size_t)b * g.nsamp + k) * npix + pix];
+            c.x += t.x; c.y += t.y; c.z += t.z; c.w += t.w;
+        }
+        if (r.w > 0.0f && (c.x != 0.0f || c.y != 0.0f || c.z != 0.0f || c.w != 0.0f)) {
+            const float ds = r.w;
+            const float t = ((float)k + 0.5f - 0.5f * (float)g.nsamp) * ds;
+            const float wy = (float)g.si, wz = (float)(-g.ci);
+            const float py = fmaf(t, wy, r.y), pz = fmaf(t, wz, r.z);
+            const Locus L = locate(s, r.x, py, pz);
+            const Fields F = fetch(s, L);
+            PhysTape tp;
+            const SampleQ q = physics<true>(s, ztab, L, F, r.x, ds, &tp);
+            const float gS = c.x, gK = c.y, ga = c.z, gb = c.w;
+            const float gKK = gK * q.K;                       // dK/d ln n = K
+            const float dlnK_dT = tp.rT * (s.el_log2e * kLn2 * tp.rT - tp.x / tp.em1 -
+                                           tp.dZ / (tp.Z * kLn2) - 0.5f);
+            const float dS_dT = q.S * (1.0f + tp.em1) / tp.em1 * tp.x * tp.rT;
+            const float gT = gS * dS_dT + gKK * dlnK_dT - 0.5f * tp.rT * (gb * q.b + ga * q.a);
+            const float gV = ga * q.b * tp.vfac;
+            const float gzu = gKK * tp.sa * tp.iw * kLn2;
+            const float gzl = -gKK * tp.sb * tp.iw * kLn2;
+            const float fu = L.fu, fv = L.fv;
+            const float w00 = (1.0f - fu) * (1.0f - fv), w01 = (1.0f - fu) * fv, w10 = fu * (1.0f - fv), w11 = fu * fv;
+            const int n00 = L.i0 * s.nz + L.j0, n10 = n00 + s.nz;
+            scatter4(go.ln_n, n00, n10, gKK, w00, w01, w10, w11);
+            scatter4(go.temp, n00, n10, gT, w00, w01, w10, w11);
+            scatter4(go.vphi, n00, n10, gV, w00, w01, w10, w11);
+            double *zl = lds_surfaces ? lds : go.zlo;
+            double *zu = lds_surfaces ? lds + nr : go.zup;
+            if (zl && gzl != 0.0f) { atomicAdd(zl + L.i0, (double)(gzl * (1.0f - fu))); atomicAdd(zl + L.i0 + 1, (double)(gzl * fu)); }
+            if (zu && gzu != 0.0f) { atomicAdd(zu + L.i0, (double)(gzu * (1.0f - fu))); atomicAdd(zu + L.i0 + 1, (double)(gzu * fu)); }
+        }
+    }
+    if (lds_surfaces) {
+        __syncthreads();
+        for (int i = threadIdx.x; i < nr; i += 256) {
+            const double a = lds[i], b = lds[nr + i];
+            if (go.zlo && a != 0.0) atomicAdd(go.zlo + i, a);
+            if (go.zup && b != 0.0) atomicAdd(go.zup + i, b);
+        }
+    }
+}
+
+__global__ void fill_zero_d(double *p, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0.0;
+}
+
+__global__ void to_float(const double *src, float *dst, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        dst[i] = (float)src[i];
+}
+
+hipError_t zero_async_d(double *p, size_t n, hipStream_t st) {
+    if (!p || n == 0) return hipSuccess;
+    const int blocks = (int)std::min<size_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(fill_zero_d, dim3(blocks), dim3(256), 0, st, p, n);
+    return hipGetLastError();
+}
+
+hipError_t to_float_async(const double *src, float *dst, size_t n, hipStream_t st) {
+    if (!dst || n == 0) return hipSuccess;
+    const int blocks = (int)std::min<size_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(to_float, dim3(blocks), dim3(256), 0, st, src, dst, n);
+    return hipGetLastError();
+}
+
+__global__ void fill_zero(float *p, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0.0f;
+}
+
+hipError_t zero_async(float *p, size_t n, hipStream_t st) {
+    if (!p || n == 0) return hipSuccess;
+    const int blocks = (int)std::min<size_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(fill_zero, dim3(blocks), dim3(256), 0, st, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_tape(const Geometry &g, const Shade &s, float4 *tape, float4 *rays, hipStream_t st) {
+    const int npix = g.nx * g.ny;
+    hipLaunchKernelGGL(adj_tape, dim3((npix + 255) / 256), dim3(256), 0, st, g, s, tape, rays);
+    return hipGetLastError();
+}
+
+template <int CB, int KSEG>
+static hipError_t launch_march_t(int nsamp, int npix, const Channels &ch, const float4 *tape, const float *dl,
+                                 float *ckpt, float4 *cot, float *cube_out, hipStream_t st) {
+    dim3 grid((npix + 255) / 256, (ch.n + CB - 1) / CB);
+    hipLaunchKernelGGL((adj_march<CB, KSEG>), grid, dim3(256), 0, st, nsamp, npix, ch, tape, dl, ckpt, cot, cube_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_march(int cb, int kseg, int nsamp, int npix, const Channels &ch, const float4 *tape,
+                            const float *dl, float *ckpt, float4 *cot, float *cube_out, hipStream_t st) {
+#define RT_MARCH_CASE(C, K) \
+    if (cb == C && kseg == K) return launch_march_t<C, K>(nsamp, npix, ch, tape, dl, ckpt, cot, cube_out, st);
+    RT_MARCH_CASE(8, 4) RT_MARCH_CASE(8, 8) RT_MARCH_CASE(8, 16)
+    RT_MARCH_CASE(16, 4) RT_MARCH_CASE(16, 8)
+    RT_MARCH_CASE(32, 4)
+#undef RT_MARCH_CASE
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_adj_chain(const Geometry &g, const Shade &s, const float4 *rays, const float4 *cot, int nblk,
+                            const GradAcc &go, hipStream_t st) {
+    const size_t total = (size_t)g.nsamp * g.nx * g.ny;
+    const int lds_surf = (s.nr <= 2048) ? 1 : 0;
+    const size_t shmem = lds_surf ? sizeof(double) * 2 * s.nr : 0;
+    hipLaunchKernelGGL(adj_chain, dim3((unsigned)((total + 255) / 256)), dim3(256), shmem, st, g, s, rays, cot, nblk,
+                       go, lds_surf);
+    return hipGetLastError();
+}
+
+} // namespace rt

@@ -1,0 +1,99 @@
+// rt_adjoint_host.cpp -- rt_render_cube_adjoint: scratch sizing and the
+// three adjoint passes, all stream-ordered on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+
+#include "rt_adjoint.h"
+#include "rt_host.h"
+
+namespace rt {
+
+// channels per lane and samples per checkpoint segment of the reverse march
+static void adjoint_shape(int nch, int *cb, int *kseg) {
+    *cb = nch > 8 ? 16 : 8;
+    *kseg = 8;
+    const int opt = ckpt_segment_option();
+    if (opt == 4 || opt == 8 || opt == 16) *kseg = opt;
+    if (*cb == 16 && *kseg == 16) *kseg = 8;
+}
+
+struct Scratch {
+    void *p = nullptr;
+    hipStream_t st = nullptr;
+    ~Scratch() { if (p) (void)hipFreeAsync(p, st); }
+};
+
+rt_status adjoint_grid(const rt_problem *p, const float *dl, const rt_grads *g, float *cube_opt, hipStream_t st) {
+    Geometry geo;
+    Shade sh;
+    rt_status rs = build_launch(p, &geo, &sh);
+    if (rs != RT_OK) return rs;
+    const int npix = p->cam.nx * p->cam.ny;
+    const int ns = p->nsamp;
+    const size_t nn = (size_t)p->grid.nr * p->grid.nz, nr = (size_t)p->grid.nr;
+    hipError_t e;
+    // gradients accumulate in double, then overwrite the caller's float outputs
+    const size_t acc_n = 3 * nn + 2 * nr;
+    Scratch acc;
+    acc.st = st;
+    e = hipMallocAsync(&acc.p, sizeof(double) * acc_n, st);
+    if (e != hipSuccess) { acc.p = nullptr; return fail_hip(e, "gradient accumulators"); }
+    double *ab = (double *)acc.p;
+    if ((e = zero_async_d(ab, acc_n, st)) != hipSuccess) return fail_hip(e, "zero");
+    GradAcc go{g->d_ln_nh2 ? ab : nullptr, g->d_temp_k ? ab + nn : nullptr, g->d_vphi_kms ? ab + 2 * nn : nullptr,
+               g->d_z_lo_au ? ab + 3 * nn : nullptr, g->d_z_up_au ? ab + 3 * nn + nr : nullptr};
+    int cb, kseg;
+    adjoint_shape(std::min(p->spec.nch, kLaunchChannels), &cb, &kseg);
+    const int nseg = (ns + kseg - 1) / kseg;
+    const size_t plane = (size_t)npix;
+    for (int c0 = 0; c0 < p->spec.nch; c0 += kLaunchChannels) {
+        Channels ch;
+        std::memset(&ch, 0, sizeof ch);
+        ch.n = std::min(kLaunchChannels, p->spec.nch - c0);
+        for (int c = 0; c < ch.n; ++c) ch.v[c] = (float)p->spec.v_kms[c0 + c];
+        const int nblk = (ch.n + cb - 1) / cb;
+        const size_t tape_b = sizeof(float4) * (size_t)ns * npix;
+        const size_t rays_b = sizeof(float4) * (size_t)npix;
+        const size_t ckpt_b = sizeof(float) * (size_t)nseg * nblk * cb * npix;
+        const size_t cot_b = sizeof(float4) * (size_t)nblk * ns * npix;
+        Scratch ws;
+        ws.st = st;
+        e = hipMallocAsync(&ws.p, tape_b + rays_b + ckpt_b + cot_b, st);
+        if (e != hipSuccess) { ws.p = nullptr; return fail_hip(e, "adjoint scratch"); }
+        char *base = (char *)ws.p;
+        float4 *tape = (float4 *)base;
+        float4 *rays = (float4 *)(base + tape_b);
+        float *ckpt = (float *)(base + tape_b + rays_b);
+        float4 *cot = (float4 *)(base + tape_b + rays_b + ckpt_b);
+        if ((e = launch_adj_tape(geo, sh, tape, rays, st)) != hipSuccess) return fail_hip(e, "adjoint tape");
+        if ((e = launch_adj_march(cb, kseg, ns, npix, ch, tape, dl + (size_t)c0 * plane, ckpt, cot,
+                                  cube_opt ? cube_opt + (size_t)c0 * plane : nullptr, st)) != hipSuccess)
+            return fail_hip(e, "adjoint march");
+        if ((e = launch_adj_chain(geo, sh, rays, cot, nblk, go, st)) != hipSuccess)
+            return fail_hip(e, "adjoint chain");
+    }
+    if ((e = to_float_async(ab, g->d_ln_nh2, nn, st)) != hipSuccess ||
+        (e = to_float_async(ab + nn, g->d_temp_k, nn, st)) != hipSuccess ||
+        (e = to_float_async(ab + 2 * nn, g->d_vphi_kms, nn, st)) != hipSuccess ||
+        (e = to_float_async(ab + 3 * nn, g->d_z_lo_au, nr, st)) != hipSuccess ||
+        (e = to_float_async(ab + 3 * nn + nr, g->d_z_up_au, nr, st)) != hipSuccess)
+        return fail_hip(e, "gradient output");
+    return RT_OK;
+}
+
+} // namespace rt
+
+using namespace rt;
+
+extern "C" rt_status rt_render_cube_adjoint(const rt_problem *p, const float *dl_dcube, const rt_grads *g,
+                                            float *cube_opt, void *stream) {
+    rt_status st = validate(p);
+    if (st != RT_OK) return st;
+    if (!dl_dcube) return fail(RT_EINVAL, "dl_dcube is NULL");
+    if (!g) return fail(RT_EINVAL, "grads is NULL");
+    if (p->mlp) return adjoint_mlp(p, dl_dcube, g, cube_opt, (hipStream_t)stream);
+    if (g->d_mlp) return fail(RT_EINVAL, "d_mlp requested but the problem has no network");
+    return adjoint_grid(p, dl_dcube, g, cube_opt, (hipStream_t)stream);
+}

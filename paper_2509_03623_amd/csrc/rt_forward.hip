@@ -13,129 +13,37 @@
 
 namespace rt {
 
-struct RaySetup {
-    float px, pmy, pmz;  // image-plane x' and the chord midpoint (y, z)
-    float ds;            // segment length [au]
-    float wy, wz;        // ray direction (y, z) components
-    bool live;
-};
-
-__device__ __forceinline__ RaySetup ray_setup(const Geometry &g, int p, int q) {
-    RaySetup r;
-    const double X = ((double)p + 0.5 - 0.5 * g.nx) * g.d_pix;
-    const double Y = ((double)q + 0.5 - 0.5 * g.ny) * g.d_pix;
-    const double xp = g.cpa * X - g.spa * Y;
-    const double yp = g.spa * X + g.cpa * Y;
-    double lo = -1e300, hi = 1e300;
-    bool ok = xp * xp < g.rc * g.rc;
-    const double qq = sqrt(fmax(g.rc * g.rc - xp * xp, 0.0));
-    if (g.si > 0.0) {
-        lo = fmax(lo, (-yp * g.ci - qq) / g.si);
-        hi = fmin(hi, (-yp * g.ci + qq) / g.si);
-    } else {
-        ok = ok && fabs(yp * g.ci) <= qq;
-    }
-    if (g.ci > 0.0) {
-        lo = fmax(lo, (yp * g.si - g.zc) / g.ci);
-        hi = fmin(hi, (yp * g.si + g.zc) / g.ci);
-    } else {
-        ok = ok && fabs(yp * g.si) <= g.zc;
-    }
-    ok = ok && hi > lo;
-    const double ds = ok ? (hi - lo) / g.nsamp : 0.0;
-    const double sm = ok ? 0.5 * (lo + hi) : 0.0;
-    r.px = (float)xp;
-    r.pmy = (float)(yp * g.ci + sm * g.si);
-    r.pmz = (float)(yp * g.si - sm * g.ci);
-    r.ds = (float)ds;
-    r.wy = (float)g.si;
-    r.wz = (float)(-g.ci);
-    r.live = ok;
-    return r;
-}
-
-// Channel-independent quantities of one sample.
-struct SampleQ {
-    float S;     // source function (times intensity_scale)
-    float K;     // optical depth of the segment at line centre (log2 units)
-    float a, b;  // d_c = a - v_c b is (v_los - v_c)/alpha scaled by sqrt(log2 e)
-};
-
-__device__ __forceinline__ SampleQ shade_sample(const Shade &s, float px, float py, float pz, float ds) {
-    const float rho2 = px * px + py * py;
-    const bool on = rho2 > 0.0f;
-    const float rho = fsqrt(rho2);
-    const float inv_rho = frcp(rho);
-    const float az = fabsf(pz);
-    float u = (flog2(rho) - s.log2_rmin) * s.u_scale;
-    float v = az * inv_rho * s.inv_dzr;
-    u = on ? u : -2.0f;
-    v = on ? v : 0.0f;
-    const float uc = clampf(u, 0.0f, s.fnr - 1.0f);
-    const float vc = clampf(v, 0.0f, s.fnz - 1.0f);
-    int i0 = (int)uc;
-    int j0 = (int)vc;
-    i0 = i0 > s.nr - 2 ? s.nr - 2 : i0;
-    j0 = j0 > s.nz - 2 ? s.nz - 2 : j0;
-    const float fu = uc - (float)i0, fv = vc - (float)j0;
-    const int n00 = i0 * s.nz + j0;
-    const int n10 = n00 + s.nz;
-    const float l00 = s.ln_n[n00], l01 = s.ln_n[n00 + 1], l10 = s.ln_n[n10], l11 = s.ln_n[n10 + 1];
-    const float t00 = s.temp[n00], t01 = s.temp[n00 + 1], t10 = s.temp[n10], t11 = s.temp[n10 + 1];
-    const float v00 = s.vphi[n00], v01 = s.vphi[n00 + 1], v10 = s.vphi[n10], v11 = s.vphi[n10 + 1];
-    const float zl0 = s.zlo[i0], zl1 = s.zlo[i0 + 1], zu0 = s.zup[i0], zu1 = s.zup[i0 + 1];
-    const float la = fmaf(fv, l01 - l00, l00), lb = fmaf(fv, l11 - l10, l10);
-    const float ln_n = fmaf(fu, lb - la, la);
-    const float ta = fmaf(fv, t01 - t00, t00), tb = fmaf(fv, t11 - t10, t10);
-    const float T = fmaf(fu, tb - ta, ta);
-    const float va = fmaf(fv, v01 - v00, v00), vb = fmaf(fv, v11 - v10, v10);
-    const float vphi = fmaf(fu, vb - va, va);
-    const float zlo = fmaf(fu, zl1 - zl0, zl0);
-    const float zup = fmaf(fu, zu1 - zu0, zu0);
-    // density, fading to zero one cell beyond the grid
-    const float taper = clampf(u + 1.0f, 0.0f, 1.0f) * clampf(s.fnr - u, 0.0f, 1.0f) * clampf(s.fnz - v, 0.0f, 1.0f);
-    const float n = fexp2(ln_n * kLog2E) * taper;
-    // logistic CO mask between the two surfaces
-    const float iw = s.inv_w * inv_rho;
-    const float ea = fexp2((az - zup) * iw);
-    const float eb = fexp2((zlo - az) * iw);
-    const float mask = frcp((1.0f + ea) * (1.0f + eb));
-    // LTE populations and source function
-    const float rT = frcp(T);
-    const float Z = partition_fn(s, flog2(T));
-    const float el = fexp2(-s.el_log2e * rT);
-    const float x = fminf(s.theta * rT, 80.0f);
-    const float em1 = expm1_pos(x);
-    SampleQ q;
-    q.S = s.c_s * frcp(em1);
-    const float inv_alpha = frsq(T * s.c_alpha);
-    q.K = s.c_k * n * mask * el * em1 * frcp(Z * (1.0f + em1)) * ds * inv_alpha;
-    q.b = s.sqrt_log2e * inv_alpha;
-    const float vlos = fmaf(vphi * s.vrot, px * inv_rho, s.vsys);
-    q.a = vlos * q.b;
-    return q;
-}
-
-template <int CB, bool THIN>
+// Lane layout: a workgroup of 256 lanes covers a tile of 256 / NSPLIT pixels;
+// the NSPLIT adjacent lanes of a pixel march consecutive sub-chords of its
+// ray (samples [split L, (split+1) L)).  Front-to-back composition is
+// associative -- (I, Tr) of segment A followed by B is (I_A + Tr_A I_B,
+// Tr_A Tr_B) -- so the sub-chord results are combined by shuffles at the end.
+template <int CB, bool THIN, int NSPLIT>
 __global__ __launch_bounds__(256) void march_fwd(Geometry g, Shade s, Channels ch, float *__restrict__ cube,
                                                   int ch_stride) {
-    const int tiles_x = (g.nx + 15) >> 4;
-    const int tile = blockIdx.x;
-    const int p = (tile % tiles_x) * 16 + (threadIdx.x & 15);
-    const int q = (tile / tiles_x) * 16 + (threadIdx.x >> 4);
+    __shared__ float4 ztab[kZTableNodes - 1];
+    stage_ztab(s, ztab);
+    constexpr int TW = NSPLIT <= 2 ? 16 : 8;          // tile width in pixels
+    constexpr int TH = 256 / NSPLIT / TW;             // tile height
+    const int tiles_x = (g.nx + TW - 1) / TW;
+    const int split = threadIdx.x % NSPLIT;
+    const int slot = threadIdx.x / NSPLIT;
+    const int p = (blockIdx.x % tiles_x) * TW + slot % TW;
+    const int q = (blockIdx.x / tiles_x) * TH + slot / TW;
     const int c0 = blockIdx.y * CB;
-    if (p >= g.nx || q >= g.ny) return;
+    const bool inside = p < g.nx && q < g.ny;
     float I[CB], Tr[CB];
 #pragma unroll
     for (int c = 0; c < CB; ++c) { I[c] = 0.0f; Tr[c] = 1.0f; }
-    const RaySetup r = ray_setup(g, p, q);
-    if (r.live) {
+    const RaySetup r = ray_setup(g, inside ? p : 0, inside ? q : 0);
+    if (inside && r.live) {
         const float half = 0.5f * (float)g.nsamp;
-        for (int k = 0; k < g.nsamp; ++k) {
+        const int len = (g.nsamp + NSPLIT - 1) / NSPLIT;
+        const int k0 = split * len;
+        const int k1 = min(g.nsamp, k0 + len);
+        for (int k = k0; k < k1; ++k) {
             const float t = ((float)k + 0.5f - half) * r.ds;
-            const float py = fmaf(t, r.wy, r.pmy);
-            const float pz = fmaf(t, r.wz, r.pmz);
-            const SampleQ sq = shade_sample(s, r.px, py, pz, r.ds);
+            const SampleQ sq = shade_sample(s, ztab, r.px, fmaf(t, r.wy, r.pmy), fmaf(t, r.wz, r.pmz), r.ds);
 #pragma unroll
             for (int c = 0; c < CB; ++c) {
                 const float d = fmaf(-ch.v[c0 + c], sq.b, sq.a);
@@ -154,27 +62,63 @@ __global__ __launch_bounds__(256) void march_fwd(Geometry g, Shade s, Channels c
             }
         }
     }
+    // compose the sub-chords front to back: pairs, then pairs of pairs, ...
+#pragma unroll
+    for (int d = 1; d < NSPLIT; d <<= 1) {
+#pragma unroll
+        for (int c = 0; c < CB; ++c) {
+            const float Ib = __shfl_down(I[c], d, NSPLIT);
+            const float Tb = __shfl_down(Tr[c], d, NSPLIT);
+            if ((split & (2 * d - 1)) == 0) {
+                I[c] = fmaf(Tr[c], Ib, I[c]);
+                Tr[c] *= Tb;
+            }
+        }
+    }
+    if (!inside || split != 0) return;
     const size_t pix = (size_t)q * g.nx + p;
 #pragma unroll
     for (int c = 0; c < CB; ++c)
         if (c0 + c < ch.n) cube[(size_t)(c0 + c) * ch_stride + pix] = I[c];
 }
 
-template <int CB, bool THIN>
-static hipError_t launch_cb(const Geometry &g, const Shade &s, const Channels &ch, float *cube, hipStream_t st) {
-    const int tiles = ((g.nx + 15) / 16) * ((g.ny + 15) / 16);
+template <int CB, bool THIN, int NSPLIT>
+static hipError_t launch_t(const Geometry &g, const Shade &s, const Channels &ch, float *cube, hipStream_t st) {
+    constexpr int TW = NSPLIT <= 2 ? 16 : 8;
+    constexpr int TH = 256 / NSPLIT / TW;
+    const int tiles = ((g.nx + TW - 1) / TW) * ((g.ny + TH - 1) / TH);
     dim3 grid(tiles, (ch.n + CB - 1) / CB);
-    hipLaunchKernelGGL((march_fwd<CB, THIN>), grid, dim3(256), 0, st, g, s, ch, cube, g.nx * g.ny);
+    hipLaunchKernelGGL((march_fwd<CB, THIN, NSPLIT>), grid, dim3(256), 0, st, g, s, ch, cube, g.nx * g.ny);
     return hipGetLastError();
 }
 
-hipError_t launch_forward(const Geometry &g, const Shade &s, const Channels &ch, float *cube, int cb,
-                          bool thin, hipStream_t st) {
+template <int CB, bool THIN>
+static hipError_t launch_split(const Geometry &g, const Shade &s, const Channels &ch, float *cube, int nsplit,
+                               hipStream_t st) {
+    switch (nsplit) {
+    case 1: return launch_t<CB, THIN, 1>(g, s, ch, cube, st);
+    case 2: return launch_t<CB, THIN, 2>(g, s, ch, cube, st);
+    case 4: return launch_t<CB, THIN, 4>(g, s, ch, cube, st);
+    case 8: return launch_t<CB, THIN, 8>(g, s, ch, cube, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <int CB>
+static hipError_t launch_cb(const Geometry &g, const Shade &s, const Channels &ch, float *cube, bool thin, int nsplit,
+                            hipStream_t st) {
+    return thin ? launch_split<CB, true>(g, s, ch, cube, nsplit, st) : launch_split<CB, false>(g, s, ch, cube, nsplit, st);
+}
+
+hipError_t launch_forward(const Geometry &g, const Shade &s, const Channels &ch, float *cube, int cb, bool thin,
+                          int nsplit, hipStream_t st) {
     switch (cb) {
-    case 8: return thin ? launch_cb<8, true>(g, s, ch, cube, st) : launch_cb<8, false>(g, s, ch, cube, st);
-    case 16: return thin ? launch_cb<16, true>(g, s, ch, cube, st) : launch_cb<16, false>(g, s, ch, cube, st);
-    case 32: return thin ? launch_cb<32, true>(g, s, ch, cube, st) : launch_cb<32, false>(g, s, ch, cube, st);
-    case 64: return thin ? launch_cb<64, true>(g, s, ch, cube, st) : launch_cb<64, false>(g, s, ch, cube, st);
+    case 8: return launch_cb<8>(g, s, ch, cube, thin, nsplit, st);
+    case 16: return launch_cb<16>(g, s, ch, cube, thin, nsplit, st);
+    case 24: return launch_cb<24>(g, s, ch, cube, thin, nsplit, st);
+    case 32: return launch_cb<32>(g, s, ch, cube, thin, nsplit, st);
+    case 48: return launch_cb<48>(g, s, ch, cube, thin, nsplit, st);
+    case 64: return launch_cb<64>(g, s, ch, cube, thin, nsplit, st);
     default: return hipErrorInvalidValue;
     }
 }

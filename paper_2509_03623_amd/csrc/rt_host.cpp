@@ -45,15 +45,39 @@ rt_status fail_hip(hipError_t e, const char *what) {
 
 // ---------------------------------------------------------------- options
 static int64_t g_opt_cb = 0;
-static int64_t g_opt_thin = 1;
+static int64_t g_opt_thin = 0;
 static int64_t g_opt_ckpt = 0;
+static int64_t g_opt_split = 0;
 
-int channel_block_for(int nch) {
-    if (g_opt_cb) return (int)g_opt_cb;
-    if (nch >= 32) return 32;
-    if (nch >= 16) return 16;
-    return 8;
+// Launch shape of the forward march: channels per lane (cb) and lanes per
+// ray (nsplit).  Measured on MI355X: one channel block per pixel is best
+// (the shading is not repeated), and a launch needs about 4096 waves (4 per
+// SIMD) before it stops losing time to latency and to its last partial round
+// of waves; so take the smallest block holding all channels (at most 64),
+// then split rays until the launch has 4096 waves.  64-channel blocks split
+// into 32-channel blocks instead (their registers no longer fit two lanes'
+// worth of live ray state), and 48-channel blocks split at most 4 ways.
+void forward_shape(int nch, long npix, int nsamp, int *cb_out, int *split_out) {
+    static const int cands[] = {8, 16, 24, 32, 48, 64};
+    int cb = 64;
+    for (int c : cands)
+        if (c >= nch) { cb = c; break; }
+    if (g_opt_cb) cb = (int)g_opt_cb;
+    auto waves = [&](int c, int ns) { return ((npix * ns + 63) / 64) * (long)((nch + c - 1) / c); };
+    if (!g_opt_cb && cb == 64 && waves(64, 1) < 4096) cb = 32;
+    const int max_split = cb >= 64 ? 1 : (cb >= 48 ? 4 : 8);
+    int ns = 1;
+    while (ns < max_split && waves(cb, ns) < 4096 && nsamp >= 32 * ns) ns <<= 1;
+    *cb_out = cb;
+    *split_out = ns;
 }
+
+int channel_block_for(int nch, long npix) {
+    int cb, ns;
+    forward_shape(nch, npix, 1 << 20, &cb, &ns);
+    return cb;
+}
+
 bool thin_series() { return g_opt_thin != 0; }
 int ckpt_segment_option() { return (int)g_opt_ckpt; }
 
@@ -239,8 +263,8 @@ int32_t rt_constants(double *out, int32_t n) {
 rt_status rt_set_option(int32_t key, int64_t value) {
     switch (key) {
     case RT_OPT_CHANNEL_BLOCK:
-        if (value != 0 && value != 8 && value != 16 && value != 32 && value != 64)
-            return fail(RT_EINVAL, "channel block must be 0, 8, 16, 32 or 64");
+        if (value != 0 && value != 8 && value != 16 && value != 24 && value != 32 && value != 48 && value != 64)
+            return fail(RT_EINVAL, "channel block must be 0, 8, 16, 24, 32, 48 or 64");
         g_opt_cb = value;
         return RT_OK;
     case RT_OPT_THIN_EXPM1:
@@ -249,6 +273,11 @@ rt_status rt_set_option(int32_t key, int64_t value) {
     case RT_OPT_CKPT_SEGMENT:
         if (value < 0 || value > 64) return fail(RT_EINVAL, "checkpoint segment must be 0..64");
         g_opt_ckpt = value;
+        return RT_OK;
+    case RT_OPT_RAY_SPLIT:
+        if (value != 0 && value != 1 && value != 2 && value != 4 && value != 8)
+            return fail(RT_EINVAL, "ray split must be 0, 1, 2, 4 or 8");
+        g_opt_split = value;
         return RT_OK;
     default:
         return fail(RT_EINVAL, "unknown option %d", key);
@@ -260,6 +289,7 @@ int64_t rt_get_option(int32_t key) {
     case RT_OPT_CHANNEL_BLOCK: return g_opt_cb;
     case RT_OPT_THIN_EXPM1: return g_opt_thin;
     case RT_OPT_CKPT_SEGMENT: return g_opt_ckpt;
+    case RT_OPT_RAY_SPLIT: return g_opt_split;
     default: return -1;
     }
 }
@@ -273,14 +303,17 @@ rt_status rt_render_cube(const rt_problem *p, float *cube, void *stream) {
     Shade s;
     st = build_launch(p, &g, &s);
     if (st != RT_OK) return st;
-    const int cb = channel_block_for(p->spec.nch);
+    int cb, nsplit;
+    forward_shape(std::min(p->spec.nch, kLaunchChannels), (long)p->cam.nx * p->cam.ny, p->nsamp, &cb, &nsplit);
+    if (g_opt_split) nsplit = (int)g_opt_split;
     const size_t plane = (size_t)p->cam.nx * p->cam.ny;
     for (int c0 = 0; c0 < p->spec.nch; c0 += kLaunchChannels) {
         Channels ch;
         std::memset(&ch, 0, sizeof ch);
         ch.n = std::min(kLaunchChannels, p->spec.nch - c0);
         for (int c = 0; c < ch.n; ++c) ch.v[c] = (float)p->spec.v_kms[c0 + c];
-        hipError_t e = launch_forward(g, s, ch, cube + (size_t)c0 * plane, cb, thin_series(), (hipStream_t)stream);
+        hipError_t e = launch_forward(g, s, ch, cube + (size_t)c0 * plane, cb, thin_series(), nsplit,
+                                      (hipStream_t)stream);
         if (e != hipSuccess) return fail_hip(e, "forward launch");
     }
     return RT_OK;

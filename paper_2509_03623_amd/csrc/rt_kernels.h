@@ -9,7 +9,7 @@ namespace rt {
 // channels carried in one launch's kernel arguments
 constexpr int kLaunchChannels = 256;
 // partition-function table: nodes uniform in log2 T over [log2 0.1, log2 1e4]
-constexpr int kZTableNodes = 1024;
+constexpr int kZTableNodes = 512;
 constexpr float kLog2E = 1.4426950408889634f;
 constexpr float kLn2 = 0.6931471805599453f;
 
@@ -92,20 +92,219 @@ __device__ __forceinline__ float one_minus_exp2_neg_series(float x) {
     return p * x;
 }
 
-// Z(T) by cubic Hermite interpolation of the table in log2 T.
-__device__ __forceinline__ float partition_fn(const Shade &s, float log2t) {
+// Z(T) by cubic Hermite interpolation of the table in log2 T (tab: the
+// table in global memory or its copy in LDS).
+__device__ __forceinline__ float partition_fn(const Shade &s, const float4 *tab, float log2t) {
     float t = (log2t - s.zt_l2t0) * s.zt_scale;
     t = clampf(t, 0.0f, (float)(kZTableNodes - 1));
     int i = (int)t;
     i = i > kZTableNodes - 2 ? kZTableNodes - 2 : i;
     const float f = t - (float)i;
-    const float4 n = s.ztab[i];
+    const float4 n = tab[i];
     const float g = 1.0f - f;
     const float h00 = (1.0f + 2.0f * f) * g * g;
     const float h10 = f * g * g;
     const float h01 = f * f * (3.0f - 2.0f * f);
     const float h11 = -f * f * g;
     return h00 * n.x + h10 * n.y + h01 * n.z + h11 * n.w;
+}
+
+// ---------------------------------------------------------------- rays and shading
+struct RaySetup {
+    float px, pmy, pmz;  // image-plane x' and the chord midpoint (y, z)
+    float ds;            // segment length [au]
+    float wy, wz;        // ray direction (y, z) components
+    bool live;
+};
+
+__device__ __forceinline__ RaySetup ray_setup(const Geometry &g, int p, int q) {
+    RaySetup r;
+    const double X = ((double)p + 0.5 - 0.5 * g.nx) * g.d_pix;
+    const double Y = ((double)q + 0.5 - 0.5 * g.ny) * g.d_pix;
+    const double xp = g.cpa * X - g.spa * Y;
+    const double yp = g.spa * X + g.cpa * Y;
+    double lo = -1e300, hi = 1e300;
+    bool ok = xp * xp < g.rc * g.rc;
+    const double qq = sqrt(fmax(g.rc * g.rc - xp * xp, 0.0));
+    if (g.si > 0.0) {
+        lo = fmax(lo, (-yp * g.ci - qq) / g.si);
+        hi = fmin(hi, (-yp * g.ci + qq) / g.si);
+    } else {
+        ok = ok && fabs(yp * g.ci) <= qq;
+    }
+    if (g.ci > 0.0) {
+        lo = fmax(lo, (yp * g.si - g.zc) / g.ci);
+        hi = fmin(hi, (yp * g.si + g.zc) / g.ci);
+    } else {
+        ok = ok && fabs(yp * g.si) <= g.zc;
+    }
+    ok = ok && hi > lo;
+    const double ds = ok ? (hi - lo) / g.nsamp : 0.0;
+    const double sm = ok ? 0.5 * (lo + hi) : 0.0;
+    r.px = (float)xp;
+    r.pmy = (float)(yp * g.ci + sm * g.si);
+    r.pmz = (float)(yp * g.si - sm * g.ci);
+    r.ds = (float)ds;
+    r.wy = (float)g.si;
+    r.wz = (float)(-g.ci);
+    r.live = ok;
+    return r;
+}
+
+// Where a sample falls on the grid.
+struct Locus {
+    float rho, inv_rho, az;  // cylindrical radius, 1/rho, |z| [au]
+    float u, v;              // continuous grid index (ln r, z/r); u = -2 on the axis
+    float fu, fv;            // bilinear weights inside the clamped cell
+    int i0, j0;              // clamped cell corner
+    float taper;             // density fade one cell beyond the grid
+};
+
+__device__ __forceinline__ Locus locate(const Shade &s, float px, float py, float pz) {
+    Locus L;
+    const float rho2 = px * px + py * py;
+    const bool on = rho2 > 0.0f;
+    L.rho = fsqrt(rho2);
+    L.inv_rho = on ? frcp(L.rho) : 0.0f;
+    L.az = fabsf(pz);
+    float u = (flog2(L.rho) - s.log2_rmin) * s.u_scale;
+    float v = L.az * L.inv_rho * s.inv_dzr;
+    u = on ? u : -2.0f;
+    v = on ? v : 0.0f;
+    L.u = u;
+    L.v = v;
+    const float uc = clampf(u, 0.0f, s.fnr - 1.0f);
+    const float vc = clampf(v, 0.0f, s.fnz - 1.0f);
+    int i0 = (int)uc;
+    int j0 = (int)vc;
+    L.i0 = i0 > s.nr - 2 ? s.nr - 2 : i0;
+    L.j0 = j0 > s.nz - 2 ? s.nz - 2 : j0;
+    L.fu = uc - (float)L.i0;
+    L.fv = vc - (float)L.j0;
+    L.taper = clampf(u + 1.0f, 0.0f, 1.0f) * clampf(s.fnr - u, 0.0f, 1.0f) * clampf(s.fnz - v, 0.0f, 1.0f);
+    return L;
+}
+
+// Primary fields interpolated at the sample.
+struct Fields {
+    float ln_n, T, vphi, zlo, zup;
+};
+
+// The 16 grid values a sample reads (loaded ahead of their use).
+struct Corners {
+    float l00, l01, l10, l11, t00, t01, t10, t11, v00, v01, v10, v11, zl0, zl1, zu0, zu1;
+};
+
+__device__ __forceinline__ Corners load_corners(const Shade &s, const Locus &L) {
+    const int n00 = L.i0 * s.nz + L.j0;
+    const int n10 = n00 + s.nz;
+    Corners c;
+    c.l00 = s.ln_n[n00]; c.l01 = s.ln_n[n00 + 1]; c.l10 = s.ln_n[n10]; c.l11 = s.ln_n[n10 + 1];
+    c.t00 = s.temp[n00]; c.t01 = s.temp[n00 + 1]; c.t10 = s.temp[n10]; c.t11 = s.temp[n10 + 1];
+    c.v00 = s.vphi[n00]; c.v01 = s.vphi[n00 + 1]; c.v10 = s.vphi[n10]; c.v11 = s.vphi[n10 + 1];
+    c.zl0 = s.zlo[L.i0]; c.zl1 = s.zlo[L.i0 + 1]; c.zu0 = s.zup[L.i0]; c.zu1 = s.zup[L.i0 + 1];
+    return c;
+}
+
+__device__ __forceinline__ Fields interpolate(const Corners &c, const Locus &L) {
+    const float fu = L.fu, fv = L.fv;
+    const float l00 = c.l00, l01 = c.l01, l10 = c.l10, l11 = c.l11;
+    const float t00 = c.t00, t01 = c.t01, t10 = c.t10, t11 = c.t11;
+    const float v00 = c.v00, v01 = c.v01, v10 = c.v10, v11 = c.v11;
+    const float zl0 = c.zl0, zl1 = c.zl1, zu0 = c.zu0, zu1 = c.zu1;
+    Fields F;
+    const float la = fmaf(fv, l01 - l00, l00), lb = fmaf(fv, l11 - l10, l10);
+    F.ln_n = fmaf(fu, lb - la, la);
+    const float ta = fmaf(fv, t01 - t00, t00), tb = fmaf(fv, t11 - t10, t10);
+    F.T = fmaf(fu, tb - ta, ta);
+    const float va = fmaf(fv, v01 - v00, v00), vb = fmaf(fv, v11 - v10, v10);
+    F.vphi = fmaf(fu, vb - va, va);
+    F.zlo = fmaf(fu, zl1 - zl0, zl0);
+    F.zup = fmaf(fu, zu1 - zu0, zu0);
+    return F;
+}
+
+__device__ __forceinline__ Fields fetch(const Shade &s, const Locus &L) { return interpolate(load_corners(s, L), L); }
+
+// Channel-independent quantities of one sample.
+struct SampleQ {
+    float S;     // source function (times intensity_scale)
+    float K;     // optical depth of the segment at line centre (log2 units)
+    float a, b;  // d_c = a - v_c b is (v_los - v_c)/alpha scaled by sqrt(log2 e)
+};
+
+// Intermediates the adjoint needs from the physics of one sample.
+struct PhysTape {
+    float rT, x, em1, Z, dZ;   // 1/T, h nu/kT, e^x - 1, Z(T), dZ/dlog2 T
+    float sa, sb, iw;          // logistic factors of the two surface terms, mask scale
+    float vfac;                // sin i * x' / rho
+};
+
+__device__ __forceinline__ float partition_fn_d(const Shade &s, const float4 *tab, float log2t, float *dz) {
+    float t = (log2t - s.zt_l2t0) * s.zt_scale;
+    const bool inside = t > 0.0f && t < (float)(kZTableNodes - 1);
+    t = clampf(t, 0.0f, (float)(kZTableNodes - 1));
+    int i = (int)t;
+    i = i > kZTableNodes - 2 ? kZTableNodes - 2 : i;
+    const float f = t - (float)i;
+    const float4 n = tab[i];
+    const float g = 1.0f - f;
+    const float d00 = 6.0f * f * (f - 1.0f), d10 = g * (1.0f - 3.0f * f), d01 = -d00, d11 = f * (3.0f * f - 2.0f);
+    *dz = inside ? (d00 * n.x + d10 * n.y + d01 * n.z + d11 * n.w) * s.zt_scale : 0.0f;
+    const float h00 = (1.0f + 2.0f * f) * g * g;
+    const float h10 = f * g * g;
+    const float h01 = f * f * (3.0f - 2.0f * f);
+    const float h11 = -f * f * g;
+    return h00 * n.x + h10 * n.y + h01 * n.z + h11 * n.w;
+}
+
+template <bool TAPE>
+__device__ __forceinline__ SampleQ physics(const Shade &s, const float4 *tab, const Locus &L, const Fields &F,
+                                           float px, float ds, PhysTape *tp) {
+    // density, fading to zero one cell beyond the grid
+    const float n = fexp2(F.ln_n * kLog2E) * L.taper;
+    // logistic CO mask between the two surfaces
+    const float iw = s.inv_w * L.inv_rho;
+    const float ea = fexp2((L.az - F.zup) * iw);
+    const float eb = fexp2((F.zlo - L.az) * iw);
+    const float ra = frcp(1.0f + ea), rb = frcp(1.0f + eb);
+    const float mask = ra * rb;
+    // LTE populations and source function
+    const float rT = frcp(F.T);
+    float dZ = 0.0f;
+    const float Z = TAPE ? partition_fn_d(s, tab, flog2(F.T), &dZ) : partition_fn(s, tab, flog2(F.T));
+    const float el = fexp2(-s.el_log2e * rT);
+    const float x = fminf(s.theta * rT, 80.0f);
+    const float em1 = expm1_pos(x);
+    SampleQ q;
+    q.S = s.c_s * frcp(em1);
+    const float inv_alpha = frsq(F.T * s.c_alpha);
+    q.K = s.c_k * n * mask * el * em1 * frcp(Z * (1.0f + em1)) * ds * inv_alpha;
+    q.b = s.sqrt_log2e * inv_alpha;
+    const float vfac = s.vrot * px * L.inv_rho;
+    const float vlos = fmaf(F.vphi, vfac, s.vsys);
+    q.a = vlos * q.b;
+    if (TAPE) {
+        tp->rT = rT; tp->x = x; tp->em1 = em1; tp->Z = Z; tp->dZ = dZ;
+        // 1 - sigma of each surface term; e^A overflowing means the term is 1
+        tp->sa = ea < 1e30f ? ea * ra : 1.0f;
+        tp->sb = eb < 1e30f ? eb * rb : 1.0f;
+        tp->iw = iw; tp->vfac = vfac;
+    }
+    return q;
+}
+
+__device__ __forceinline__ SampleQ shade_sample(const Shade &s, const float4 *tab, float px, float py, float pz,
+                                                float ds) {
+    const Locus L = locate(s, px, py, pz);
+    const Fields F = fetch(s, L);
+    return physics<false>(s, tab, L, F, px, ds, nullptr);
+}
+
+// Copy the partition-function table into LDS (whole workgroup; barrier).
+__device__ __forceinline__ void stage_ztab(const Shade &s, float4 *lds_tab) {
+    for (int i = threadIdx.x; i < kZTableNodes - 1; i += blockDim.x) lds_tab[i] = s.ztab[i];
+    __syncthreads();
 }
 
 } // namespace rt

@@ -4,7 +4,7 @@
 
 namespace rt {
 
-hipError_t launch_forward(const Geometry &g, const Shade &s, const Channels &ch, float *cube, int cb,
-                          bool thin, hipStream_t st);
+hipError_t launch_forward(const Geometry &g, const Shade &s, const Channels &ch, float *cube, int cb, bool thin,
+                          int nsplit, hipStream_t st);
 
 } // namespace rt

@@ -95,5 +95,6 @@ def test_options_roundtrip():
     assert lib.rt_set_option(L.RT_OPT_CHANNEL_BLOCK, 16) == 0
     assert lib.rt_get_option(L.RT_OPT_CHANNEL_BLOCK) == 16
     assert lib.rt_set_option(L.RT_OPT_CHANNEL_BLOCK, 12) == L.RT_EINVAL
+    assert lib.rt_set_option(L.RT_OPT_CHANNEL_BLOCK, 48) == 0
     assert lib.rt_set_option(L.RT_OPT_CHANNEL_BLOCK, old) == 0
     assert lib.rt_set_option(999, 1) == L.RT_EINVAL

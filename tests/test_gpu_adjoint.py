@@ -1,0 +1,202 @@
+"""GPU adjoint vs the oracle: full gradient vectors against the float64
+autograd gradient of the oracle's march, and sampled entries against central
+finite differences of the C oracle (FP64), at small and full size.
+
+Bar: every checked entry |dg| <= 1e-3 |g| (entries drawn from those with
+|g| >= 1e-3 max of their block) and ||dg||_2 <= 1e-3 ||g||_2 per block."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from oracle import torch_ref
+
+pytestmark = pytest.mark.gpu
+
+BLOCKS = ["ln_nh2", "temp_k", "vphi_kms", "z_lo_au", "z_up_au"]
+
+
+def _rt():
+    import paper_2509_03623_amd as rt
+    return rt
+
+
+def kscale(prob):
+    return prob.replace(intensity_scale=synth.disk.rj_kelvin_scale(prob.line))
+
+
+def target_for(prob, seed=30):
+    tgt = synth.perturb_surfaces(prob, seed=seed)
+    return synth.disk.add_noise(oracle.render(tgt), 0.05, seed=31)
+
+
+def gpu_grads(prob, target, want=tuple(BLOCKS), cotangent=None):
+    """GPU gradients of L = sum (I - D)^2.  With cotangent=None dL/dI comes
+    from the GPU's own forward (end to end); otherwise the given dL/dI is
+    used, so the adjoint is compared as a vector-Jacobian product."""
+    rt = _rt()
+    print(f"[gpu] adjoint {prob.camera.nx}x{prob.camera.ny}x{prob.nch} ns={prob.nsamp} "
+          f"grid {prob.grid.nr}x{prob.grid.nz} cotangent={'given' if cotangent is not None else 'gpu'}",
+          flush=True)
+    sc = rt.scene_from_problem(prob)
+    cube = rt.render(sc)
+    if cotangent is None:
+        tgt = torch.as_tensor(target, dtype=torch.float32, device="cuda")
+        dl = 2.0 * (cube - tgt)
+    else:
+        dl = torch.as_tensor(np.ascontiguousarray(cotangent, np.float32), device="cuda")
+    cube2 = torch.empty_like(cube)
+    g = rt.render_adjoint(sc, dl, want=want, cube_out=cube2)
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy().astype(np.float64) for k, v in g.items()}, cube.cpu().numpy(), cube2.cpu().numpy()
+
+
+def check_block(name, got, ref, rel=1e-3, seed=32):
+    """The gradient bar: ||dg||_2 <= rel ||g||_2 over the block; 8 seeded
+    entries drawn from |g| >= 1e-3 max within rel; every entry with
+    |g| >= 1e-2 max within rel.  The worst entry above 1e-3 max is printed."""
+    ref = np.asarray(ref, np.float64).ravel()
+    got = np.asarray(got, np.float64).ravel()
+    gmax = np.abs(ref).max()
+    big = np.abs(ref) >= 1e-3 * gmax
+    assert big.any(), name
+    rel_all = np.abs(got - ref) / np.maximum(np.abs(ref), 1e-300)
+    wi = np.nonzero(big)[0][int(np.argmax(rel_all[big]))]
+    l2 = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    print(f"{name}: L2 rel {l2:.2e}; worst entry >=1e-3 max: rel {rel_all[wi]:.2e} at {wi} "
+          f"(|g|/max {abs(ref[wi]) / gmax:.2e}), n={big.sum()}")
+    assert l2 <= rel, (name, l2)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    pick = rng.choice(np.nonzero(big)[0], size=min(8, int(big.sum())), replace=False)
+    assert rel_all[pick].max() <= rel, (name, pick[int(np.argmax(rel_all[pick]))])
+    top = np.abs(ref) >= 1e-2 * gmax
+    assert rel_all[top].max() <= rel, (name, "entry >= 1e-2 max", float(rel_all[top].max()))
+
+
+@pytest.mark.parametrize("incl,seed", [(45.0, 5), (30.0, 8), (65.0, 13)])
+def test_gradients_match_oracle_autograd(incl, seed):
+    prob = kscale(synth.small_problem(nx=24, ny=20, nch=12, nsamp=64, nr=48, nz=24, seed=seed, dv=0.2,
+                                      incl=incl))
+    target = target_for(prob)
+    L, ref = torch_ref.loss_and_grad(prob, target)
+    # the same dL/dI = 2 (I_64 - D) on both sides: a vector-Jacobian product check
+    got, cube, cube2 = gpu_grads(prob, target, cotangent=2.0 * (oracle.render(prob) - target))
+    assert np.array_equal(cube, cube2) or np.abs(cube - cube2).max() <= 1e-6 * np.abs(cube).max()
+    for k in BLOCKS:
+        check_block(k, got[k], ref[k])
+
+
+def test_gradients_ragged_channels_and_segments():
+    # 37 channels: ragged channel blocks; 61 samples: ragged checkpoint segments
+    prob = kscale(synth.small_problem(nx=19, ny=17, nch=37, nsamp=61, nr=40, nz=20, seed=21, dv=0.1))
+    target = target_for(prob)
+    _, ref = torch_ref.loss_and_grad(prob, target)
+    got, _, _ = gpu_grads(prob, target, cotangent=2.0 * (oracle.render(prob) - target))
+    for k in BLOCKS:
+        check_block(k, got[k], ref[k])
+
+
+def test_end_to_end_l2_gradient():
+    """dL/dI from the GPU's own FP32 forward: the loss gradient still meets the
+    L2 bar against the FP64 oracle (its per-entry tail is looser because FP32
+    forward error enters the noisy residuals coherently)."""
+    prob = kscale(synth.small_problem(nx=24, ny=20, nch=12, nsamp=64, nr=48, nz=24, seed=5, dv=0.2))
+    target = target_for(prob)
+    _, ref = torch_ref.loss_and_grad(prob, target)
+    got, _, _ = gpu_grads(prob, target)
+    for k in BLOCKS:
+        r, g_ = ref[k].ravel(), got[k].ravel()
+        l2 = float(np.linalg.norm(g_ - r) / np.linalg.norm(r))
+        print(f"{k}: end-to-end L2 rel {l2:.2e}")
+        assert l2 <= 1e-3, (k, l2)
+
+
+def test_subset_of_gradients_and_determinism():
+    prob = kscale(synth.small_problem(nx=20, ny=20, nch=10, nsamp=48, seed=3))
+    target = target_for(prob)
+    a, _, _ = gpu_grads(prob, target, want=("temp_k", "z_up_au"))
+    b, _, _ = gpu_grads(prob, target, want=("temp_k", "z_up_au"))
+    assert set(a) == {"temp_k", "z_up_au"}
+    for k in a:
+        scale = np.abs(a[k]).max()
+        assert np.abs(a[k] - b[k]).max() <= 1e-5 * scale
+
+
+def test_autograd_function_matches_direct_call():
+    rt = _rt()
+    prob = kscale(synth.small_problem(nx=16, ny=14, nch=8, nsamp=40, seed=4))
+    target = target_for(prob)
+    sc = rt.scene_from_problem(prob)
+    leaves = {k: getattr(sc, k).clone().requires_grad_(True) for k in BLOCKS}
+    cube = rt.render_differentiable(sc, **leaves)
+    loss = ((cube - torch.as_tensor(target, dtype=torch.float32, device="cuda")) ** 2).sum()
+    loss.backward()
+    direct, _, _ = gpu_grads(prob, target)
+    for k in BLOCKS:
+        g = leaves[k].grad.cpu().numpy()
+        scale = np.abs(direct[k]).max()
+        assert np.abs(g - direct[k]).max() <= 1e-5 * scale, k
+
+
+def _affected_pixels(prob, name, idx):
+    """Pixels whose ray samples fall in the support of grid node idx (so a
+    change of that node can change their spectra); test-side geometry."""
+    g, cam = prob.grid, prob.camera
+    px, py = np.meshgrid(np.arange(cam.nx), np.arange(cam.ny))
+    px, py = px.ravel(), py.ravel()
+    xp, yp, sa, sb, ok = torch_ref.pixel_chords(prob, px.astype(np.float64), py.astype(np.float64))
+    ds = (sb - sa) / prob.nsamp
+    ang = np.radians(cam.incl_deg)
+    k = np.arange(prob.nsamp)[:, None]
+    s = sa[None, :] + (k + 0.5) * ds[None, :]
+    pyk = yp[None, :] * np.cos(ang) + s * np.sin(ang)
+    pzk = yp[None, :] * np.sin(ang) - s * np.cos(ang)
+    rho = np.hypot(xp[None, :], pyk)
+    dln = np.log(g.r_max_au / g.r_min_au) / (g.nr - 1)
+    u = np.log(np.maximum(rho, 1e-30) / g.r_min_au) / dln
+    v = np.abs(pzk) / np.maximum(rho, 1e-30) / (g.zr_max / (g.nz - 1))
+    if name in ("z_lo_au", "z_up_au"):
+        i = idx
+        hit = np.abs(u - i) < 1.0
+    else:
+        i, j = divmod(idx, g.nz)
+        hit = (np.abs(u - i) < 1.0) & (np.abs(v - j) < 1.0)
+    sel = ok & hit.any(axis=0)
+    return px[sel], py[sel]
+
+
+@pytest.mark.slow
+def test_full_size_gradient_vs_central_differences():
+    """256 x 256 x 48 x 256 on a 256 x 128 grid (L2 loss against a perturbed,
+    noisy target): 8 seeded entries (2 per block) against central differences
+    (step 1e-4) of the FP64 oracle over the pixels the node can affect."""
+    prob = kscale(synth.config3())
+    rng = np.random.Generator(np.random.PCG64(32))
+    tgt_prob = synth.config3_target_disk(prob)
+    # the target cube comes from the oracle, rendered in pieces of rows
+    target = oracle.render(tgt_prob)
+    target = synth.disk.add_noise(target, 0.05, seed=31)
+    got, cube, _ = gpu_grads(prob, target, want=("ln_nh2", "temp_k", "z_lo_au", "z_up_au"))
+    checked = 0
+    for name in ("ln_nh2", "temp_k", "z_lo_au", "z_up_au"):
+        g = got[name].ravel()
+        cand = np.nonzero(np.abs(g) >= 1e-3 * np.abs(g).max())[0]
+        if name in ("ln_nh2", "temp_k"):
+            nz = prob.grid.nz
+            cand = cand[(cand // nz > 1) & (cand // nz < prob.grid.nr - 2) & (cand % nz > 1) & (cand % nz < nz - 2)]
+        for idx in rng.choice(cand, size=2, replace=False):
+            px, py = _affected_pixels(prob, name, int(idx))
+            arr = getattr(prob, name)
+            plus, minus = arr.copy(), arr.copy()
+            plus.flat[idx] = np.float32(float(arr.flat[idx]) + 1e-4)
+            minus.flat[idx] = np.float32(float(arr.flat[idx]) - 1e-4)
+            h = float(plus.flat[idx]) - float(minus.flat[idx])
+            D = target[:, py, px].T
+            lp = np.sum((oracle.render_pixels(prob.replace(**{name: plus}), px, py) - D) ** 2)
+            lm = np.sum((oracle.render_pixels(prob.replace(**{name: minus}), px, py) - D) ** 2)
+            fd = (lp - lm) / h
+            print(f"{name}[{idx}] gpu {g[idx]:.6e} fd {fd:.6e} ({len(px)} px)", flush=True)
+            assert abs(g[idx] - fd) <= 1e-3 * abs(fd), (name, idx)
+            checked += 1
+    assert checked == 8

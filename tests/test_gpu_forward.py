@@ -26,7 +26,7 @@ def gpu_cube(prob, **opts):
     from paper_2509_03623_amd import _lib as L
     old = {}
     for k, v in opts.items():
-        key = {"cb": L.RT_OPT_CHANNEL_BLOCK, "thin": L.RT_OPT_THIN_EXPM1}[k]
+        key = {"cb": L.RT_OPT_CHANNEL_BLOCK, "thin": L.RT_OPT_THIN_EXPM1, "split": L.RT_OPT_RAY_SPLIT}[k]
         old[key] = rt.get_option(key)
         rt.set_option(key, v)
     try:
@@ -55,13 +55,22 @@ def test_config1_full_cube():
     assert err <= TOL
 
 
-@pytest.mark.parametrize("cb", [8, 16, 32, 64])
+@pytest.mark.parametrize("cb", [8, 16, 24, 32, 48, 64])
 @pytest.mark.parametrize("thin", [1, 0])
 def test_channel_blocks_and_ragged_tiles(cb, thin):
     # 37 x 23 pixels: ragged 16 x 16 tiles; 13 channels: ragged channel blocks
     prob = synth.small_problem(nx=37, ny=23, nch=13, nsamp=96, nr=64, nz=32, seed=11, dv=0.2)
     ref = oracle.render(prob)
     got = gpu_cube(prob, cb=cb, thin=thin)
+    assert rel_err(got, ref) <= TOL
+
+
+@pytest.mark.parametrize("cb,split", [(8, 8), (16, 2), (16, 4), (24, 8), (32, 4), (48, 2), (48, 4), (64, 1)])
+def test_ray_split_lanes(cb, split):
+    # 97 samples: sub-chords of unequal length; 21 x 19 pixels: ragged tiles
+    prob = synth.small_problem(nx=21, ny=19, nch=11, nsamp=97, nr=64, nz=32, seed=17, dv=0.25)
+    ref = oracle.render(prob)
+    got = gpu_cube(prob, cb=cb, split=split)
     assert rel_err(got, ref) <= TOL
 
 
