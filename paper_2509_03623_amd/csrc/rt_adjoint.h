@@ -19,6 +19,6 @@ hipError_t launch_adj_tape(const Geometry &g, const Shade &s, float4 *tape, floa
 hipError_t launch_adj_march(int cb, int kseg, int nsamp, int npix, const Channels &ch, const float4 *tape,
                             const float *dl, float *ckpt, float4 *cot, float *cube_out, hipStream_t st);
 hipError_t launch_adj_chain(const Geometry &g, const Shade &s, const float4 *rays, const float4 *cot, int nblk,
-                            const GradAcc &go, hipStream_t st);
+                            const GradAcc &go, float4 *dO, hipStream_t st);
 
 } // namespace rt

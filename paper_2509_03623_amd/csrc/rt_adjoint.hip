@@ -35,7 +35,10 @@ __global__ __launch_bounds__(256) void adj_tape(Geometry g, Shade s, float4 *__r
         float4 o = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         if (r.live) {
             const float t = ((float)k + 0.5f - half) * r.ds;
-            const SampleQ q = shade_sample(s, ztab, r.px, fmaf(t, r.wy, r.pmy), fmaf(t, r.wz, r.pmz), r.ds);
+            const SampleQ q = s.mlp_o ? shade_sample<true>(s, ztab, r.px, fmaf(t, r.wy, r.pmy), fmaf(t, r.wz, r.pmz),
+                                                           r.ds, (size_t)k * npix + pix)
+                                      : shade_sample<false>(s, ztab, r.px, fmaf(t, r.wy, r.pmy), fmaf(t, r.wz, r.pmz), r.ds,
+                                           (size_t)k * npix + pix);
             o = make_float4(q.S, q.K, q.a, q.b);
         }
         tape[(size_t)k * npix + pix] = o;
@@ -142,7 +145,7 @@ __device__ __forceinline__ void scatter4(double *dst, int n00, int n10, float gv
 
 __global__ __launch_bounds__(256) void adj_chain(Geometry g, Shade s, const float4 *__restrict__ rays,
                                                  const float4 *__restrict__ cot, int nblk, GradAcc go,
-                                                 int lds_surfaces) {
+                                                 int lds_surfaces, float4 *__restrict__ dO) {
     extern __shared__ double lds[];  // [2][nr] surface gradients when lds_surfaces
     __shared__ float4 ztab[kZTableNodes - 1];
     stage_ztab(s, ztab);
@@ -163,13 +166,21 @@ __global__ __launch_bounds__(256) void adj_chain(Geometry g, Shade s, const floa
             const float4 t = cot[((size_t)b * g.nsamp + k) * npix + pix];
             c.x += t.x; c.y += t.y; c.z += t.z; c.w += t.w;
         }
+        float4 dout = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         if (r.w > 0.0f && (c.x != 0.0f || c.y != 0.0f || c.z != 0.0f || c.w != 0.0f)) {
             const float ds = r.w;
             const float t = ((float)k + 0.5f - 0.5f * (float)g.nsamp) * ds;
             const float wy = (float)g.si, wz = (float)(-g.ci);
             const float py = fmaf(t, wy, r.y), pz = fmaf(t, wz, r.z);
             const Locus L = locate(s, r.x, py, pz);
-            const Fields F = fetch(s, L);
+            Fields F = fetch(s, L);
+            float4 o = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            float tfac = 1.0f, t_grid = F.T;
+            if (s.mlp_o) {
+                o = s.mlp_o[idx];
+                apply_mlp(s, F, L, o);
+                tfac = F.T / t_grid;
+            }
             PhysTape tp;
             const SampleQ q = physics<true>(s, ztab, L, F, r.x, ds, &tp);
             const float gS = c.x, gK = c.y, ga = c.z, gb = c.w;
@@ -177,10 +188,23 @@ __global__ __launch_bounds__(256) void adj_chain(Geometry g, Shade s, const floa
             const float dlnK_dT = tp.rT * (s.el_log2e * kLn2 * tp.rT - tp.x / tp.em1 -
                                            tp.dZ / (tp.Z * kLn2) - 0.5f);
             const float dS_dT = q.S * (1.0f + tp.em1) / tp.em1 * tp.x * tp.rT;
-            const float gT = gS * dS_dT + gKK * dlnK_dT - 0.5f * tp.rT * (gb * q.b + ga * q.a);
+            float gT = gS * dS_dT + gKK * dlnK_dT - 0.5f * tp.rT * (gb * q.b + ga * q.a);
             const float gV = ga * q.b * tp.vfac;
-            const float gzu = gKK * tp.sa * tp.iw * kLn2;
-            const float gzl = -gKK * tp.sb * tp.iw * kLn2;
+            float gzu = gKK * tp.sa * tp.iw * kLn2;
+            float gzl = -gKK * tp.sb * tp.iw * kLn2;
+            if (s.mlp_o) {
+                // network outputs: z_up = zr rho sigma(o0), z_lo = zr rho sigma(o1),
+                // T = T_grid exp(0.5 tanh(o2)); the grid surfaces are not used
+                const float s0 = sigmoidf_(o.x), s0c = sigmoidf_(-o.x);
+                const float s1 = sigmoidf_(o.y), s1c = sigmoidf_(-o.y);
+                const float th = tanhf_(o.z);
+                dout.x = gzu * s.zr_max * L.rho * s0 * s0c;
+                dout.y = gzl * s.zr_max * L.rho * s1 * s1c;
+                dout.z = gT * F.T * 0.5f * (1.0f - th * th);
+                gT *= tfac;
+                gzu = 0.0f;
+                gzl = 0.0f;
+            }
             const float fu = L.fu, fv = L.fv;
             const float w00 = (1.0f - fu) * (1.0f - fv), w01 = (1.0f - fu) * fv, w10 = fu * (1.0f - fv), w11 = fu * fv;
             const int n00 = L.i0 * s.nz + L.j0, n10 = n00 + s.nz;
@@ -192,6 +216,7 @@ __global__ __launch_bounds__(256) void adj_chain(Geometry g, Shade s, const floa
             if (zl && gzl != 0.0f) { atomicAdd(zl + L.i0, (double)(gzl * (1.0f - fu))); atomicAdd(zl + L.i0 + 1, (double)(gzl * fu)); }
             if (zu && gzu != 0.0f) { atomicAdd(zu + L.i0, (double)(gzu * (1.0f - fu))); atomicAdd(zu + L.i0 + 1, (double)(gzu * fu)); }
         }
+        if (dO) dO[idx] = dout;
     }
     if (lds_surfaces) {
         __syncthreads();
@@ -263,12 +288,12 @@ hipError_t launch_adj_march(int cb, int kseg, int nsamp, int npix, const Channel
 }
 
 hipError_t launch_adj_chain(const Geometry &g, const Shade &s, const float4 *rays, const float4 *cot, int nblk,
-                            const GradAcc &go, hipStream_t st) {
+                            const GradAcc &go, float4 *dO, hipStream_t st) {
     const size_t total = (size_t)g.nsamp * g.nx * g.ny;
     const int lds_surf = (s.nr <= 2048) ? 1 : 0;
     const size_t shmem = lds_surf ? sizeof(double) * 2 * s.nr : 0;
     hipLaunchKernelGGL(adj_chain, dim3((unsigned)((total + 255) / 256)), dim3(256), shmem, st, g, s, rays, cot, nblk,
-                       go, lds_surf);
+                       go, lds_surf, dO);
     return hipGetLastError();
 }
 

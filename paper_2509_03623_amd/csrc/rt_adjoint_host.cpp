@@ -25,11 +25,13 @@ struct Scratch {
     ~Scratch() { if (p) (void)hipFreeAsync(p, st); }
 };
 
-rt_status adjoint_grid(const rt_problem *p, const float *dl, const rt_grads *g, float *cube_opt, hipStream_t st) {
+rt_status adjoint_core(const rt_problem *p, const float *dl, const rt_grads *g, float *cube_opt, hipStream_t st,
+                       const float4 *mlp_o, float4 *dO) {
     Geometry geo;
     Shade sh;
     rt_status rs = build_launch(p, &geo, &sh);
     if (rs != RT_OK) return rs;
+    sh.mlp_o = mlp_o;
     const int npix = p->cam.nx * p->cam.ny;
     const int ns = p->nsamp;
     const size_t nn = (size_t)p->grid.nr * p->grid.nz, nr = (size_t)p->grid.nr;
@@ -71,7 +73,7 @@ rt_status adjoint_grid(const rt_problem *p, const float *dl, const rt_grads *g, 
         if ((e = launch_adj_march(cb, kseg, ns, npix, ch, tape, dl + (size_t)c0 * plane, ckpt, cot,
                                   cube_opt ? cube_opt + (size_t)c0 * plane : nullptr, st)) != hipSuccess)
             return fail_hip(e, "adjoint march");
-        if ((e = launch_adj_chain(geo, sh, rays, cot, nblk, go, st)) != hipSuccess)
+        if ((e = launch_adj_chain(geo, sh, rays, cot, nblk, go, c0 == 0 ? dO : nullptr, st)) != hipSuccess)
             return fail_hip(e, "adjoint chain");
     }
     if ((e = to_float_async(ab, g->d_ln_nh2, nn, st)) != hipSuccess ||
@@ -81,6 +83,10 @@ rt_status adjoint_grid(const rt_problem *p, const float *dl, const rt_grads *g, 
         (e = to_float_async(ab + 3 * nn + nr, g->d_z_up_au, nr, st)) != hipSuccess)
         return fail_hip(e, "gradient output");
     return RT_OK;
+}
+
+rt_status adjoint_grid(const rt_problem *p, const float *dl, const rt_grads *g, float *cube_opt, hipStream_t st) {
+    return adjoint_core(p, dl, g, cube_opt, st, nullptr, nullptr);
 }
 
 } // namespace rt

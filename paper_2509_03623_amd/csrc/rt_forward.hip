@@ -18,7 +18,7 @@ namespace rt {
 // ray (samples [split L, (split+1) L)).  Front-to-back composition is
 // associative -- (I, Tr) of segment A followed by B is (I_A + Tr_A I_B,
 // Tr_A Tr_B) -- so the sub-chord results are combined by shuffles at the end.
-template <int CB, bool THIN, int NSPLIT>
+template <int CB, bool THIN, int NSPLIT, bool NEURAL>
 __global__ __launch_bounds__(256) void march_fwd(Geometry g, Shade s, Channels ch, float *__restrict__ cube,
                                                   int ch_stride) {
     __shared__ float4 ztab[kZTableNodes - 1];
@@ -43,7 +43,8 @@ __global__ __launch_bounds__(256) void march_fwd(Geometry g, Shade s, Channels c
         const int k1 = min(g.nsamp, k0 + len);
         for (int k = k0; k < k1; ++k) {
             const float t = ((float)k + 0.5f - half) * r.ds;
-            const SampleQ sq = shade_sample(s, ztab, r.px, fmaf(t, r.wy, r.pmy), fmaf(t, r.wz, r.pmz), r.ds);
+            const SampleQ sq = shade_sample<NEURAL>(s, ztab, r.px, fmaf(t, r.wy, r.pmy), fmaf(t, r.wz, r.pmz), r.ds,
+                                            (size_t)k * g.nx * g.ny + (size_t)q * g.nx + p);
 #pragma unroll
             for (int c = 0; c < CB; ++c) {
                 const float d = fmaf(-ch.v[c0 + c], sq.b, sq.a);
@@ -88,7 +89,10 @@ static hipError_t launch_t(const Geometry &g, const Shade &s, const Channels &ch
     constexpr int TH = 256 / NSPLIT / TW;
     const int tiles = ((g.nx + TW - 1) / TW) * ((g.ny + TH - 1) / TH);
     dim3 grid(tiles, (ch.n + CB - 1) / CB);
-    hipLaunchKernelGGL((march_fwd<CB, THIN, NSPLIT>), grid, dim3(256), 0, st, g, s, ch, cube, g.nx * g.ny);
+    if (s.mlp_o)
+        hipLaunchKernelGGL((march_fwd<CB, THIN, NSPLIT, true>), grid, dim3(256), 0, st, g, s, ch, cube, g.nx * g.ny);
+    else
+        hipLaunchKernelGGL((march_fwd<CB, THIN, NSPLIT, false>), grid, dim3(256), 0, st, g, s, ch, cube, g.nx * g.ny);
     return hipGetLastError();
 }
 

@@ -242,6 +242,25 @@ rt_status build_launch(const rt_problem *p, Geometry *g, Shade *s) {
     s->vrot = (float)g->si;
     s->vsys = (float)p->spec.v_sys_kms;
     s->thin_thr = (float)(0.125 * log2e);
+    s->zr_max = (float)gr.zr_max;
+    s->mlp_o = nullptr;
+    return RT_OK;
+}
+
+// Forward march of the whole cube, one launch per chunk of channels.
+rt_status march_cube(const rt_problem *p, const Geometry &g, const Shade &s, float *cube, hipStream_t stream) {
+    int cb, nsplit;
+    forward_shape(std::min(p->spec.nch, kLaunchChannels), (long)p->cam.nx * p->cam.ny, p->nsamp, &cb, &nsplit);
+    if (g_opt_split) nsplit = (int)g_opt_split;
+    const size_t plane = (size_t)p->cam.nx * p->cam.ny;
+    for (int c0 = 0; c0 < p->spec.nch; c0 += kLaunchChannels) {
+        Channels ch;
+        std::memset(&ch, 0, sizeof ch);
+        ch.n = std::min(kLaunchChannels, p->spec.nch - c0);
+        for (int c = 0; c < ch.n; ++c) ch.v[c] = (float)p->spec.v_kms[c0 + c];
+        hipError_t e = launch_forward(g, s, ch, cube + (size_t)c0 * plane, cb, thin_series(), nsplit, stream);
+        if (e != hipSuccess) return fail_hip(e, "forward launch");
+    }
     return RT_OK;
 }
 
@@ -303,20 +322,7 @@ rt_status rt_render_cube(const rt_problem *p, float *cube, void *stream) {
     Shade s;
     st = build_launch(p, &g, &s);
     if (st != RT_OK) return st;
-    int cb, nsplit;
-    forward_shape(std::min(p->spec.nch, kLaunchChannels), (long)p->cam.nx * p->cam.ny, p->nsamp, &cb, &nsplit);
-    if (g_opt_split) nsplit = (int)g_opt_split;
-    const size_t plane = (size_t)p->cam.nx * p->cam.ny;
-    for (int c0 = 0; c0 < p->spec.nch; c0 += kLaunchChannels) {
-        Channels ch;
-        std::memset(&ch, 0, sizeof ch);
-        ch.n = std::min(kLaunchChannels, p->spec.nch - c0);
-        for (int c = 0; c < ch.n; ++c) ch.v[c] = (float)p->spec.v_kms[c0 + c];
-        hipError_t e = launch_forward(g, s, ch, cube + (size_t)c0 * plane, cb, thin_series(), nsplit,
-                                      (hipStream_t)stream);
-        if (e != hipSuccess) return fail_hip(e, "forward launch");
-    }
-    return RT_OK;
+    return march_cube(p, g, s, cube, (hipStream_t)stream);
 }
 
 } // extern "C"

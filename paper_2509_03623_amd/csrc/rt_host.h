@@ -17,6 +17,9 @@ bool thin_series();
 int ckpt_segment_option();
 
 rt_status render_cube_mlp(const rt_problem *p, float *cube, hipStream_t st);
+rt_status march_cube(const rt_problem *p, const Geometry &g, const Shade &s, float *cube, hipStream_t st);
+rt_status adjoint_core(const rt_problem *p, const float *dl, const rt_grads *g, float *cube_opt, hipStream_t st,
+                       const float4 *mlp_o, float4 *dO);
 rt_status adjoint_mlp(const rt_problem *p, const float *dl, const rt_grads *g, float *cube_opt, hipStream_t st);
 rt_status adjoint_grid(const rt_problem *p, const float *dl, const rt_grads *g, float *cube_opt, hipStream_t st);
 

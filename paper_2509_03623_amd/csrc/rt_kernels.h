@@ -44,6 +44,8 @@ struct Shade {
     float vrot;              // sin i
     float vsys;              // systemic velocity [km/s]
     float thin_thr;          // dtau (log2 units) below which 1 - e^-dtau uses the series
+    float zr_max;            // (z/r) of the top grid row
+    const float4 *mlp_o;     // neural CO layer outputs [nsamp][npix] (o0, o1, o2, -); NULL = grid surfaces
 };
 
 struct Channels {
@@ -226,6 +228,18 @@ __device__ __forceinline__ Fields interpolate(const Corners &c, const Locus &L) 
 
 __device__ __forceinline__ Fields fetch(const Shade &s, const Locus &L) { return interpolate(load_corners(s, L), L); }
 
+__device__ __forceinline__ float sigmoidf_(float x) { return frcp(1.0f + fexp2(-x * kLog2E)); }
+__device__ __forceinline__ float tanhf_(float x) { return 1.0f - 2.0f * frcp(1.0f + fexp2(2.0f * kLog2E * x)); }
+
+// Neural CO layer: the network's outputs at the sample replace the two
+// surfaces (z = zr_max rho sigma(o)) and scale the temperature by
+// exp(0.5 tanh(o2)).
+__device__ __forceinline__ void apply_mlp(const Shade &s, Fields &F, const Locus &L, float4 o) {
+    F.zup = s.zr_max * L.rho * sigmoidf_(o.x);
+    F.zlo = s.zr_max * L.rho * sigmoidf_(o.y);
+    F.T *= fexp2(0.5f * kLog2E * tanhf_(o.z));
+}
+
 // Channel-independent quantities of one sample.
 struct SampleQ {
     float S;     // source function (times intensity_scale)
@@ -294,10 +308,12 @@ __device__ __forceinline__ SampleQ physics(const Shade &s, const float4 *tab, co
     return q;
 }
 
+template <bool NEURAL>
 __device__ __forceinline__ SampleQ shade_sample(const Shade &s, const float4 *tab, float px, float py, float pz,
-                                                float ds) {
+                                                float ds, size_t m) {
     const Locus L = locate(s, px, py, pz);
-    const Fields F = fetch(s, L);
+    Fields F = fetch(s, L);
+    if (NEURAL) apply_mlp(s, F, L, s.mlp_o[m]);
     return physics<false>(s, tab, L, F, px, ds, nullptr);
 }
 

@@ -1,0 +1,28 @@
+// rt_mlp.h -- neural CO layer kernels (internal).
+#pragma once
+#include "../../include/rtcube.h"
+#include "rt_kernels.h"
+
+namespace rt {
+
+// Prepared network: per hidden layer l the weights in the kernel's element
+// type, row-major [128][K_l] (W) and transposed [K_l][128] (WT), float
+// biases; the output layer in float; offsets of each layer in the flat
+// float32 layout; the 16 Fourier frequencies.
+struct MlpDev {
+    const void *W[4];
+    const void *WT[4];
+    const float *b[4];
+    const float *W5, *b5;
+    int off[5];
+    float freq[16];
+};
+
+size_t mlp_prep_bytes(int precision);
+hipError_t mlp_prepare(const float *flat, int precision, void *buf, MlpDev *w, hipStream_t st);
+hipError_t mlp_forward(const Geometry &g, const Shade &s, const MlpDev &w, int precision, size_t M, float4 *out,
+                       hipStream_t st);
+hipError_t mlp_backward(const Geometry &g, const Shade &s, const MlpDev &w, int precision, size_t M,
+                        const float4 *dO, float *dW, hipStream_t st);
+
+} // namespace rt

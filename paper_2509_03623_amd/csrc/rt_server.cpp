@@ -1,14 +1,5 @@
-// rt_stubs.cpp -- entry points whose kernels are not in this build yet.
+// rt_server.cpp -- continuous-batching render server (placeholder entry points).
 #include "rt_host.h"
-
-namespace rt {
-rt_status render_cube_mlp(const rt_problem *, float *, hipStream_t) {
-    return fail(RT_EINVAL, "neural CO layer not available in this build");
-}
-rt_status adjoint_mlp(const rt_problem *, const float *, const rt_grads *, float *, hipStream_t) {
-    return fail(RT_EINVAL, "neural CO layer not available in this build");
-}
-} // namespace rt
 
 using namespace rt;
 extern "C" {

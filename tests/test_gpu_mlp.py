@@ -1,0 +1,102 @@
+"""Neural CO layer (network evaluated at every pixel-sample on the matrix
+cores) vs the FP64 oracle.
+
+Bars: FP32 path -- cube max |dI| <= 1e-5 peak is the FP32 norm; gradients
+L2 <= 1e-3 per block.  BF16 path -- cube relative L2 <= 1e-2 and gradient
+cosine >= 0.99 against FP64."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from oracle import torch_ref
+
+pytestmark = pytest.mark.gpu
+
+
+def _rt():
+    import paper_2509_03623_amd as rt
+    return rt
+
+
+def mlp_problem(**kw):
+    args = dict(nx=24, ny=20, nch=12, nsamp=64, nr=48, nz=24, seed=5, dv=0.2, mlp_seed=4)
+    args.update(kw)
+    prob = synth.small_problem(**args)
+    return prob.replace(intensity_scale=synth.disk.rj_kelvin_scale(prob.line))
+
+
+def gpu_cube(prob, precision):
+    rt = _rt()
+    print(f"[gpu] neural render {prob.camera.nx}x{prob.camera.ny}x{prob.nch} ns={prob.nsamp} prec={precision}",
+          flush=True)
+    sc = rt.scene_from_problem(prob, mlp_precision=precision)
+    cube = rt.render(sc)
+    torch.cuda.synchronize()
+    return cube.cpu().numpy().astype(np.float64)
+
+
+@pytest.mark.parametrize("incl", [45.0, 62.0])
+def test_fp32_network_forward(incl):
+    rt = _rt()
+    prob = mlp_problem(incl=incl)
+    ref = oracle.render(prob)
+    got = gpu_cube(prob, rt.RT_MLP_FP32)
+    err = float(np.abs(got - ref).max() / ref.max())
+    l2 = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    print(f"fp32 network: max|dI|/peak {err:.2e}, rel L2 {l2:.2e}")
+    assert ref.max() > 1.0
+    assert err <= 1e-5
+
+
+def test_bf16_network_forward():
+    rt = _rt()
+    prob = mlp_problem()
+    ref = oracle.render(prob)
+    got = gpu_cube(prob, rt.RT_MLP_BF16)
+    l2 = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    print(f"bf16 network: rel L2 {l2:.2e}, max|dI|/peak {np.abs(got - ref).max() / ref.max():.2e}")
+    assert l2 <= 1e-2
+
+
+def _grads(prob, precision, cotangent):
+    rt = _rt()
+    sc = rt.scene_from_problem(prob, mlp_precision=precision)
+    dl = torch.as_tensor(np.ascontiguousarray(cotangent, np.float32), device="cuda")
+    g = rt.render_adjoint(sc, dl, want=("ln_nh2", "temp_k", "vphi_kms", "mlp_w"))
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy().astype(np.float64) for k, v in g.items()}
+
+
+def _cos(a, b):
+    a, b = a.ravel(), b.ravel()
+    return float(np.dot(a, b) / (np.linalg.norm(a) * np.linalg.norm(b)))
+
+
+def test_network_gradients_fp32_and_bf16():
+    rt = _rt()
+    prob = mlp_problem(nx=20, ny=16, nch=10, nsamp=48)
+    tgt = synth.disk.add_noise(oracle.render(prob.replace(mlp_w=synth.make_mlp_weights(99))), 0.05, seed=31)
+    _, ref = torch_ref.loss_and_grad(prob, tgt)
+    cot = 2.0 * (oracle.render(prob) - tgt)
+    g32 = _grads(prob, rt.RT_MLP_FP32, cot)
+    g16 = _grads(prob, rt.RT_MLP_BF16, cot)
+    for k in ("ln_nh2", "temp_k", "vphi_kms", "mlp_w"):
+        l2 = float(np.linalg.norm(g32[k] - ref[k]) / np.linalg.norm(ref[k]))
+        c16 = _cos(g16[k], ref[k])
+        print(f"{k}: fp32 L2 rel {l2:.2e}; bf16 cosine {c16:.5f}")
+        assert l2 <= 1e-3, (k, l2)
+        assert c16 >= 0.99, (k, c16)
+    assert np.abs(g32["mlp_w"]).max() > 0
+
+
+def test_network_surface_gradients_are_zero():
+    """With the network the grid surfaces are not used: their gradients are 0."""
+    rt = _rt()
+    prob = mlp_problem(nx=12, ny=10, nch=6, nsamp=32)
+    sc = rt.scene_from_problem(prob, mlp_precision=rt.RT_MLP_BF16)
+    cube = rt.render(sc)
+    g = rt.render_adjoint(sc, torch.ones_like(cube), want=("z_lo_au", "z_up_au"))
+    torch.cuda.synchronize()
+    assert float(g["z_lo_au"].abs().max()) == 0.0 and float(g["z_up_au"].abs().max()) == 0.0
