@@ -93,6 +93,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--serve-seconds", type=float, default=8.0,
+                    help="length of the Poisson request trace (200 req/s) for the serving leg; 0 = skip")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the renderer is a single-GPU build (rays are independent, "
@@ -157,6 +159,9 @@ def main():
             out["fwd_adjoint"] = bench_adjoint(rt, synth, dev, args)
         except rt.RtError as e:
             out["fwd_adjoint"] = {"error": str(e)}
+    if args.serve_seconds > 0:
+        out["served"], out["serial"] = bench_serving(rt, synth, dev, args.serve_seconds)
+        out["served_vs_serial_throughput"] = out["served"]["ray_samples_per_s"] / out["serial"]["ray_samples_per_s"]
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds)
     print(json.dumps(out), flush=True)
@@ -185,6 +190,93 @@ def bench_adjoint(rt, synth, dev, args):
     dt = (time.perf_counter() - t0) / steps
     return {"ray_samples_per_s": sc.ray_samples / dt, "ms_per_step": dt * 1e3,
             "workload": "forward + adjoint 256x256 px x 48 ch x 256 samples, L2 loss"}
+
+
+def bench_serving(rt, synth, dev, seconds, rate=200.0, seed=5, pool=16):
+    """Poisson request stream (rate req/s for `seconds`): each request a disk
+    of the full-size family (one of `pool` pre-generated seeded disks) with
+    pixels in {64..512}^2, channels in {16..128}, 128-512 samples, 25% with
+    forward+adjoint gradients of an L2 loss.  Served by the continuous-
+    batching server, then replayed one request at a time on the same trace."""
+    import numpy as np
+    import torch
+    trace = synth.make_trace(rate_hz=rate, duration_s=seconds, seed=seed)
+    bases = [rt.scene_from_problem(synth.config2(3000 + i, nx=64, ny=64, nch=16, nsamp=128), device=dev)
+             for i in range(pool)]
+    targets, grads = {}, {}
+
+    def request(r):
+        b = bases[r["disk_seed"] % pool]
+        nch = r["nch"]
+        v = (np.arange(nch) - (nch - 1) / 2.0) * 0.1
+        sc = b.replace(nx=r["nx"], ny=r["ny"], v_kms=v, nsamp=r["nsamp"])
+        key = (r["nch"], r["ny"], r["nx"])
+        if r["grad"] and key not in targets:
+            targets[key] = torch.zeros(key, device=dev)
+        return sc, key
+
+    for b in bases:
+        grads_b = {k: torch.empty_like(getattr(b, k)) for k in ("ln_nh2", "temp_k", "z_lo_au", "z_up_au")}
+        grads[id(b)] = grads_b
+    reqs = [request(r) for r in trace]
+    torch.cuda.synchronize()
+    total_rs = sum(sc.ray_samples for sc, _ in reqs)
+    ngrad = sum(1 for r in trace if r["grad"])
+
+    # served
+    lat = []
+    with rt.Server(hbm_budget_bytes=96 << 30, max_slots=64, streams=4) as sv:
+        sc0, _ = reqs[0]
+        sv.wait(sv.submit(sc0, torch.empty(sc0.nch, sc0.ny, sc0.nx, device=dev)))
+        outstanding = {}
+        t0 = time.perf_counter()
+        for r, (sc, key) in zip(trace, reqs):
+            while time.perf_counter() - t0 < r["t_arrive"]:
+                time.sleep(2e-4)
+            cube = torch.empty(key, device=dev)
+            if r["grad"]:
+                b = bases[r["disk_seed"] % pool]
+                t = sv.submit(sc, cube, target=targets[key], grads=grads[id(b)])
+            else:
+                t = sv.submit(sc, cube)
+            outstanding[t] = cube
+            for tk in [tk for tk in outstanding if sv.poll(tk)["state"] in ("done", "failed")]:
+                outstanding.pop(tk)
+        infos = []
+        for tk in list(sv._keep.keys()):
+            sv.wait(tk, timeout_s=120)
+        # every ticket's timing
+        for tk in range(2, 2 + len(trace)):
+            infos.append(sv.poll(tk))
+    t_sub = np.array([i["t_submit_ns"] for i in infos], dtype=np.float64)
+    t_done = np.array([i["t_done_ns"] for i in infos], dtype=np.float64)
+    lat = (t_done - t_sub) * 1e-6
+    makespan = (t_done.max() - t_sub.min()) * 1e-9
+    served = {"ray_samples_per_s": total_rs / makespan, "p50_ms": float(np.percentile(lat, 50)),
+              "p99_ms": float(np.percentile(lat, 99)), "requests": len(trace), "grad_requests": ngrad,
+              "makespan_s": makespan, "failed": int(sum(1 for i in infos if i["state"] != "done")),
+              "trace": f"Poisson {rate:g} req/s for {seconds:g} s, seed {seed}"}
+
+    # serial: the same trace, one request at a time in arrival order
+    lat_s = []
+    t0 = time.perf_counter()
+    first = None
+    for r, (sc, key) in zip(trace, reqs):
+        now = time.perf_counter() - t0
+        if now < r["t_arrive"]:
+            time.sleep(r["t_arrive"] - now)
+        start = max(time.perf_counter() - t0, r["t_arrive"])
+        first = start if first is None else first
+        cube = rt.render(sc)
+        if r["grad"]:
+            b = bases[r["disk_seed"] % pool]
+            rt.render_adjoint(sc, 2.0 * (cube - targets[key]), want=("ln_nh2", "temp_k", "z_lo_au", "z_up_au"))
+        torch.cuda.synchronize()
+        lat_s.append((time.perf_counter() - t0 - r["t_arrive"]) * 1e3)
+    span = time.perf_counter() - t0 - trace[0]["t_arrive"]
+    serial = {"ray_samples_per_s": total_rs / span, "p50_ms": float(np.percentile(lat_s, 50)),
+              "p99_ms": float(np.percentile(lat_s, 99)), "makespan_s": span}
+    return served, serial
 
 
 if __name__ == "__main__":

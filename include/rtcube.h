@@ -150,11 +150,16 @@ rt_status rt_render_cube_adjoint(const rt_problem *p, const float *dl_dcube, con
                                  float *cube_opt, void *stream);
 
 /* ---------------------------------------------------------------- server */
-/* Continuous-batching render server on one GPU.  Requests are admitted while
- * their HBM footprint fits the budget and a slot is free; admitted requests
- * are cut into tile work items that persistent launches pull from a device
- * queue, so work of different requests overlaps on the device.  A request's
- * forward cube is bitwise the one rt_render_cube gives. */
+/* Continuous-batching render server on one GPU.  Requests are admitted in
+ * arrival order while their HBM footprint (inputs, outputs and library
+ * scratch) fits the budget and a slot is free.  Admitted plain forward
+ * requests are cut into (tile, channel block) work items that one persistent
+ * launch pulls from a device counter; gradient and neural-layer requests run
+ * on streams of their own; requests that arrive meanwhile start on the next
+ * idle stream, so work of different requests overlaps on the device.  A
+ * request's forward cube depends only on the request (bitwise the same alone
+ * and in any mix) and equals rt_render_cube's to FP32 rounding.  The caller's
+ * device buffers must stay valid until the ticket is done or cancelled. */
 typedef struct rt_server rt_server;
 
 typedef struct {

@@ -9,3 +9,4 @@ from .render import (  # noqa: F401
     Scene, scene_from_problem, render, render_adjoint, Render, render_differentiable,
     set_option, get_option, constants,
 )
+from .server import Server  # noqa: F401

@@ -1,0 +1,23 @@
+// rt_serve.h -- device side of the render server (internal).
+#pragma once
+#include <algorithm>
+
+#include "rt_kernels.h"
+
+namespace rt {
+
+// One request of a persistent forward batch.
+struct ServeDesc {
+    Geometry g;
+    Shade s;
+    const float *vch;     // channel velocities, padded to a multiple of 16
+    float *cube;          // [nch][ny][nx]
+    int32_t nch, nblk, tiles_x;
+    uint32_t item0;       // first work item of this request in the batch
+};
+
+hipError_t launch_serve_fwd(const ServeDesc *descs, int nreq, uint32_t nitems, uint32_t *counter, int nwg,
+                            hipStream_t st);
+hipError_t launch_l2_loss(const float *cube, const float *target, float *dl, size_t n, double *loss, hipStream_t st);
+
+} // namespace rt

@@ -1,0 +1,116 @@
+// rt_serve.hip -- device side of the render server: a persistent forward
+// launch over the work items of every request in a batch, and the fused L2
+// loss / cotangent of forward+adjoint requests.
+//
+// A batch holds up to max_slots requests; its work items are (request,
+// 16 x 16 pixel tile, 16-channel block) in request order.  The launch has a
+// fixed number of workgroups; each pulls the next item index from a device
+// counter until the batch is exhausted, so items of small and large requests
+// of the batch share the GPU.  Every wave exits once the counter passes the
+// item count.
+#include "rt_serve.h"
+
+namespace rt {
+
+constexpr int kServeCB = 16;
+
+__global__ __launch_bounds__(256) void serve_fwd(const ServeDesc *__restrict__ descs, int nreq, uint32_t nitems,
+                                                 uint32_t *__restrict__ counter) {
+    __shared__ float4 ztab[kZTableNodes - 1];
+    __shared__ uint32_t s_item;
+    __shared__ const float4 *s_tab;
+    if (threadIdx.x == 0) s_tab = nullptr;
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) s_item = atomicAdd(counter, 1u);
+        __syncthreads();
+        const uint32_t item = __builtin_amdgcn_readfirstlane(s_item);   // uniform: scalar from here on
+        if (item >= nitems) break;
+        // request of this item: last descriptor whose first item <= item
+        int lo = 0, hi = nreq - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (descs[mid].item0 <= item) lo = mid; else hi = mid - 1;
+        }
+        // the request index is the same for every lane: keep its descriptor in
+        // scalar registers for the whole item
+        const ServeDesc D = descs[__builtin_amdgcn_readfirstlane(lo)];
+        if (s_tab != D.s.ztab) {     // uniform: every lane reads the same s_tab
+            __syncthreads();
+            for (int i = threadIdx.x; i < kZTableNodes - 1; i += 256) ztab[i] = D.s.ztab[i];
+            __syncthreads();
+            if (threadIdx.x == 0) s_tab = D.s.ztab;
+        }
+        const uint32_t local = item - D.item0;
+        const int blk = (int)(local % (uint32_t)D.nblk);
+        const int tile = (int)(local / (uint32_t)D.nblk);
+        const Geometry &g = D.g;
+        const int p = (tile % D.tiles_x) * 16 + (threadIdx.x & 15);
+        const int q = (tile / D.tiles_x) * 16 + (threadIdx.x >> 4);
+        const int c0 = blk * kServeCB;
+        if (p < g.nx && q < g.ny) {
+            float I[kServeCB], Tr[kServeCB];
+#pragma unroll
+            for (int c = 0; c < kServeCB; ++c) { I[c] = 0.0f; Tr[c] = 1.0f; }
+            float vc[kServeCB];
+#pragma unroll
+            for (int c = 0; c < kServeCB; ++c) vc[c] = D.vch[c0 + c];
+            const RaySetup r = ray_setup(g, p, q);
+            if (r.live) {
+                const float half = 0.5f * (float)g.nsamp;
+                for (int k = 0; k < g.nsamp; ++k) {
+                    const float t = ((float)k + 0.5f - half) * r.ds;
+                    const SampleQ sq = shade_sample<false>(D.s, ztab, r.px, fmaf(t, r.wy, r.pmy),
+                                                           fmaf(t, r.wz, r.pmz), r.ds, 0);
+#pragma unroll
+                    for (int c = 0; c < kServeCB; ++c) {
+                        const float d = fmaf(-vc[c], sq.b, sq.a);
+                        const float att = fexp2(-(sq.K * fexp2(-(d * d))));
+                        I[c] = fmaf(Tr[c] * (1.0f - att), sq.S, I[c]);
+                        Tr[c] *= att;
+                    }
+                }
+            }
+            const size_t plane = (size_t)g.nx * g.ny, pix = (size_t)q * g.nx + p;
+#pragma unroll
+            for (int c = 0; c < kServeCB; ++c)
+                if (c0 + c < D.nch) D.cube[(size_t)(c0 + c) * plane + pix] = I[c];
+        }
+    }
+}
+
+hipError_t launch_serve_fwd(const ServeDesc *descs, int nreq, uint32_t nitems, uint32_t *counter, int nwg,
+                            hipStream_t st) {
+    hipLaunchKernelGGL(serve_fwd, dim3(nwg), dim3(256), 0, st, descs, nreq, nitems, counter);
+    return hipGetLastError();
+}
+
+// dl = 2 (cube - target); L += sum (cube - target)^2 (double atomics)
+__global__ __launch_bounds__(256) void l2_loss(const float *__restrict__ cube, const float *__restrict__ target,
+                                               float *__restrict__ dl, size_t n, double *__restrict__ loss) {
+    __shared__ double part[256];
+    double acc = 0.0;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+        const float r = cube[i] - target[i];
+        dl[i] = 2.0f * r;
+        acc += (double)r * (double)r;
+    }
+    part[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) part[threadIdx.x] += part[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicAdd(loss, part[0]);
+}
+
+__global__ void zero_double(double *p) { *p = 0.0; }
+
+hipError_t launch_l2_loss(const float *cube, const float *target, float *dl, size_t n, double *loss, hipStream_t st) {
+    hipLaunchKernelGGL(zero_double, dim3(1), dim3(1), 0, st, loss);
+    const int blocks = (int)std::min<size_t>((n + 255) / 256, 2048);
+    hipLaunchKernelGGL(l2_loss, dim3(blocks), dim3(256), 0, st, cube, target, dl, n, loss);
+    return hipGetLastError();
+}
+
+} // namespace rt

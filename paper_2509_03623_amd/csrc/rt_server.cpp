@@ -1,12 +1,422 @@
-// rt_server.cpp -- continuous-batching render server (placeholder entry points).
+// rt_server.cpp -- continuous-batching render server on one GPU.
+//
+// rt_submit validates a request on the host, deep-copies its problem and
+// queues it.  A scheduler thread
+//   1. retires finished launches (event queries) and frees their budget/slots,
+//   2. admits queued requests in arrival order while their HBM footprint fits
+//      the budget and a slot is free,
+//   3. starts admitted work on an idle stream: every admitted plain forward
+//      request goes into one persistent launch whose workgroups pull
+//      (request, tile, channel block) items from a device counter; a request
+//      with a gradient (forward, fused L2 loss + cotangent, adjoint) or with
+//      the neural CO layer runs on a stream of its own.
+// Requests that arrive while launches run are admitted as budget and slots
+// free up and start on the next idle stream, so their work overlaps on the
+// device with what is already running.  A forward cube depends only on its
+// own request (each ray is marched by one lane with the same code whatever
+// else is in the batch).
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "rt_adjoint.h"
 #include "rt_host.h"
+#include "rt_serve.h"
 
 using namespace rt;
-extern "C" {
-rt_status rt_server_create(const rt_server_cfg *, rt_server **) { return fail(RT_EINVAL, "server not available"); }
-rt_status rt_submit(rt_server *, const rt_request *, uint64_t *) { return fail(RT_EINVAL, "server not available"); }
-rt_status rt_poll(rt_server *, uint64_t, rt_ticket_info *) { return fail(RT_EINVAL, "server not available"); }
-rt_status rt_wait(rt_server *, uint64_t, rt_ticket_info *, uint64_t) { return fail(RT_EINVAL, "server not available"); }
-rt_status rt_cancel(rt_server *, uint64_t) { return fail(RT_EINVAL, "server not available"); }
-rt_status rt_server_destroy(rt_server *) { return fail(RT_EINVAL, "server not available"); }
+
+namespace {
+
+uint64_t now_ns() {
+    return (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(
+               std::chrono::steady_clock::now().time_since_epoch()).count();
 }
+
+struct Req {
+    uint64_t id = 0;
+    rt_request rq{};
+    std::vector<double> lev_e, lev_g, vk;
+    rt_mlp mlp{};
+    int state = RT_TICKET_QUEUED;
+    int status = RT_PENDING;
+    uint64_t t_submit = 0, t_admit = 0, t_done = 0;
+    double loss = 0.0;
+    uint64_t footprint = 0, ray_samples = 0;
+    bool own_stream = false;   // gradient or neural request
+};
+
+struct Lane {
+    hipStream_t st = nullptr;
+    hipEvent_t ev = nullptr;
+    bool busy = false;
+    std::vector<Req *> reqs;
+    ServeDesc *d_desc = nullptr, *h_desc = nullptr;
+    float *d_vch = nullptr, *h_vch = nullptr;
+    size_t vch_cap = 0;
+    uint32_t *d_counter = nullptr;
+    double *d_loss = nullptr, *h_loss = nullptr;
+    float *dl = nullptr;       // cotangent of a gradient request (stream-ordered allocation)
+};
+
+__global__ void zero_u32(uint32_t *p) { *p = 0u; }
+
+} // namespace
+
+struct rt_server {
+    rt_server_cfg cfg{};
+    int ncu = 0;
+    std::thread th;
+    std::mutex mu;
+    std::condition_variable cv;
+    bool stop = false;
+    uint64_t next_id = 1;
+    std::map<uint64_t, std::unique_ptr<Req>> tickets;
+    std::deque<Req *> pending, admitted;
+    uint64_t budget_used = 0;
+    int slots_used = 0;
+    std::vector<Lane> lanes;
+};
+
+namespace {
+
+// Device memory a request occupies while it runs: its inputs and outputs and
+// the library's scratch.
+uint64_t footprint(const rt_request &r) {
+    const rt_problem &p = r.problem;
+    const uint64_t nn = (uint64_t)p.grid.nr * p.grid.nz, nr = p.grid.nr;
+    const uint64_t npix = (uint64_t)p.cam.nx * p.cam.ny, cube = 4ull * p.spec.nch * npix;
+    const uint64_t M = npix * p.nsamp;
+    uint64_t b = 4 * (3 * nn + 2 * nr) + cube;
+    if (p.mlp) b += 4ull * RT_MLP_PARAMS + 16 * M + (1u << 20);
+    if (r.kind == RT_REQ_FWD_ADJ) {
+        const int ch = std::min(p.spec.nch, kLaunchChannels);
+        const int cb = ch > 8 ? 16 : 8, kseg = 8;
+        const uint64_t nblk = (ch + cb - 1) / cb, nseg = (p.nsamp + kseg - 1) / kseg;
+        b += 2 * cube + 4 * (3 * nn + 2 * nr) + 8 * (3 * nn + 2 * nr);   // target, dl, grads, accumulators
+        b += 16 * M + 16 * npix + 4 * nseg * nblk * cb * npix + 16 * nblk * M;   // tape, rays, checkpoints, cotangents
+        if (p.mlp) b += 16 * M + 4ull * RT_MLP_PARAMS;
+    }
+    return b;
+}
+
+void finish(rt_server *sv, Req *r, int status) {
+    r->status = status;
+    r->state = status == RT_OK ? RT_TICKET_DONE : RT_TICKET_FAILED;
+    r->t_done = now_ns();
+    sv->budget_used -= r->footprint;
+    sv->slots_used -= 1;
+}
+
+rt_status lane_vch_capacity(Lane &L, size_t n) {
+    if (n <= L.vch_cap) return RT_OK;
+    if (L.d_vch) (void)hipFree(L.d_vch);
+    if (L.h_vch) (void)hipHostFree(L.h_vch);
+    L.d_vch = nullptr;
+    L.h_vch = nullptr;
+    L.vch_cap = 0;
+    hipError_t e = hipMalloc(&L.d_vch, n * sizeof(float));
+    if (e == hipSuccess) e = hipHostMalloc(&L.h_vch, n * sizeof(float), hipHostMallocDefault);
+    if (e != hipSuccess) return fail_hip(e, "server channel buffers");
+    L.vch_cap = n;
+    return RT_OK;
+}
+
+// one persistent launch over every request of the batch
+rt_status launch_batch(rt_server *sv, Lane &L, std::vector<Req *> &batch) {
+    size_t nv = 0;
+    for (Req *r : batch) nv += (size_t)(r->rq.problem.spec.nch + 15) / 16 * 16;
+    rt_status rs = lane_vch_capacity(L, nv);
+    if (rs != RT_OK) return rs;
+    uint32_t items = 0;
+    size_t vo = 0;
+    for (size_t i = 0; i < batch.size(); ++i) {
+        const rt_problem &p = batch[i]->rq.problem;
+        ServeDesc &D = L.h_desc[i];
+        std::memset(&D, 0, sizeof D);
+        rs = build_launch(&p, &D.g, &D.s);
+        if (rs != RT_OK) return rs;
+        const int nch = p.spec.nch, padded = (nch + 15) / 16 * 16;
+        for (int c = 0; c < padded; ++c) L.h_vch[vo + c] = c < nch ? (float)p.spec.v_kms[c] : 0.0f;
+        D.vch = L.d_vch + vo;
+        vo += padded;
+        D.cube = batch[i]->rq.cube;
+        D.nch = nch;
+        D.nblk = padded / 16;
+        D.tiles_x = (p.cam.nx + 15) / 16;
+        D.item0 = items;
+        items += (uint32_t)(D.tiles_x * ((p.cam.ny + 15) / 16) * D.nblk);
+    }
+    hipError_t e = hipMemcpyAsync(L.d_desc, L.h_desc, sizeof(ServeDesc) * batch.size(), hipMemcpyHostToDevice, L.st);
+    if (e == hipSuccess) e = hipMemcpyAsync(L.d_vch, L.h_vch, sizeof(float) * vo, hipMemcpyHostToDevice, L.st);
+    if (e != hipSuccess) return fail_hip(e, "server upload");
+    hipLaunchKernelGGL(zero_u32, dim3(1), dim3(1), 0, L.st, L.d_counter);
+    if ((e = hipGetLastError()) != hipSuccess) return fail_hip(e, "server counter");
+    e = launch_serve_fwd(L.d_desc, (int)batch.size(), items, L.d_counter, sv->ncu * 4, L.st);
+    if (e != hipSuccess) return fail_hip(e, "server batch launch");
+    return RT_OK;
+}
+
+// a request on a stream of its own: neural forward, or forward + L2 loss + adjoint
+rt_status launch_single(Lane &L, Req *r) {
+    const rt_request &q = r->rq;
+    const rt_problem *p = &q.problem;
+    rt_status rs;
+    if (p->mlp) {
+        rs = render_cube_mlp(p, q.cube, L.st);
+    } else {
+        Geometry g;
+        Shade s;
+        rs = build_launch(p, &g, &s);
+        if (rs == RT_OK) rs = march_cube(p, g, s, q.cube, L.st);
+    }
+    if (rs != RT_OK || q.kind != RT_REQ_FWD_ADJ) return rs;
+    const size_t n = (size_t)p->spec.nch * p->cam.nx * p->cam.ny;
+    hipError_t e = hipMallocAsync((void **)&L.dl, n * sizeof(float), L.st);
+    if (e != hipSuccess) { L.dl = nullptr; return fail_hip(e, "server cotangent"); }
+    if ((e = launch_l2_loss(q.cube, q.target, L.dl, n, L.d_loss, L.st)) != hipSuccess) return fail_hip(e, "loss");
+    rs = p->mlp ? adjoint_mlp(p, L.dl, &q.grads, nullptr, L.st) : adjoint_grid(p, L.dl, &q.grads, nullptr, L.st);
+    if (rs != RT_OK) return rs;
+    e = hipFreeAsync(L.dl, L.st);
+    L.dl = nullptr;
+    if (e == hipSuccess) e = hipMemcpyAsync(L.h_loss, L.d_loss, sizeof(double), hipMemcpyDeviceToHost, L.st);
+    if (e != hipSuccess) return fail_hip(e, "loss readback");
+    return RT_OK;
+}
+
+void scheduler(rt_server *sv) {
+    (void)hipSetDevice(sv->cfg.device);
+    std::unique_lock<std::mutex> lk(sv->mu);
+    for (;;) {
+        bool progress = false;
+        // 1. retire finished launches
+        for (Lane &L : sv->lanes) {
+            if (!L.busy) continue;
+            const hipError_t q = hipEventQuery(L.ev);
+            if (q == hipErrorNotReady) continue;
+            for (Req *r : L.reqs) {
+                if (r->rq.kind == RT_REQ_FWD_ADJ) r->loss = *L.h_loss;
+                finish(sv, r, q == hipSuccess ? RT_OK : RT_EDEVICE);
+            }
+            L.reqs.clear();
+            L.busy = false;
+            progress = true;
+        }
+        // 2. admission in arrival order, by footprint and slots
+        while (!sv->pending.empty()) {
+            Req *r = sv->pending.front();
+            if (sv->slots_used >= sv->cfg.max_slots || sv->budget_used + r->footprint > sv->cfg.hbm_budget_bytes)
+                break;
+            sv->pending.pop_front();
+            sv->budget_used += r->footprint;
+            sv->slots_used += 1;
+            r->state = RT_TICKET_RUNNING;
+            r->t_admit = now_ns();
+            sv->admitted.push_back(r);
+            progress = true;
+        }
+        // 3. start admitted work on idle streams
+        for (Lane &L : sv->lanes) {
+            if (L.busy || sv->admitted.empty()) continue;
+            std::vector<Req *> batch;
+            if (sv->admitted.front()->own_stream) {
+                batch.push_back(sv->admitted.front());
+                sv->admitted.pop_front();
+            } else {
+                for (auto it = sv->admitted.begin(); it != sv->admitted.end();) {
+                    if (!(*it)->own_stream && (int)batch.size() < sv->cfg.max_slots) {
+                        batch.push_back(*it);
+                        it = sv->admitted.erase(it);
+                    } else {
+                        ++it;
+                    }
+                }
+            }
+            rt_status rs = batch.front()->own_stream ? launch_single(L, batch.front()) : launch_batch(sv, L, batch);
+            hipError_t e = hipSuccess;
+            if (rs == RT_OK) e = hipEventRecord(L.ev, L.st);
+            if (rs != RT_OK || e != hipSuccess) {
+                // the stream may hold partial work: wait for it, then fail the requests
+                (void)hipStreamSynchronize(L.st);
+                for (Req *r : batch) finish(sv, r, rs != RT_OK ? rs : RT_EDEVICE);
+                continue;
+            }
+            L.reqs = batch;
+            L.busy = true;
+            progress = true;
+        }
+        if (progress) sv->cv.notify_all();
+        bool idle = sv->pending.empty() && sv->admitted.empty();
+        for (Lane &L : sv->lanes) idle = idle && !L.busy;
+        if (sv->stop && idle) break;
+        if (!progress) sv->cv.wait_for(lk, std::chrono::microseconds(idle ? 2000 : 50));
+    }
+}
+
+} // namespace
+
+extern "C" {
+
+rt_status rt_server_create(const rt_server_cfg *cfg, rt_server **out) {
+    if (!cfg || !out) return fail(RT_EINVAL, "NULL argument");
+    if (cfg->max_slots < 1 || cfg->max_slots > 1024) return fail(RT_EINVAL, "max_slots must be 1..1024");
+    if (cfg->max_pending < 1) return fail(RT_EINVAL, "max_pending must be >= 1");
+    if (cfg->streams < 1 || cfg->streams > 8) return fail(RT_EINVAL, "streams must be 1..8");
+    if (cfg->hbm_budget_bytes == 0) return fail(RT_EINVAL, "hbm_budget_bytes must be > 0");
+    hipError_t e = hipSetDevice(cfg->device);
+    if (e != hipSuccess) return fail_hip(e, "hipSetDevice");
+    std::unique_ptr<rt_server> sv(new rt_server);
+    sv->cfg = *cfg;
+    e = hipDeviceGetAttribute(&sv->ncu, hipDeviceAttributeMultiprocessorCount, cfg->device);
+    if (e != hipSuccess) return fail_hip(e, "device query");
+    sv->lanes.resize(cfg->streams);
+    for (Lane &L : sv->lanes) {
+        if ((e = hipStreamCreateWithFlags(&L.st, hipStreamNonBlocking)) != hipSuccess ||
+            (e = hipEventCreateWithFlags(&L.ev, hipEventDisableTiming)) != hipSuccess ||
+            (e = hipMalloc(&L.d_desc, sizeof(ServeDesc) * cfg->max_slots)) != hipSuccess ||
+            (e = hipHostMalloc(&L.h_desc, sizeof(ServeDesc) * cfg->max_slots, hipHostMallocDefault)) != hipSuccess ||
+            (e = hipMalloc(&L.d_counter, sizeof(uint32_t))) != hipSuccess ||
+            (e = hipMalloc(&L.d_loss, sizeof(double))) != hipSuccess ||
+            (e = hipHostMalloc(&L.h_loss, sizeof(double), hipHostMallocDefault)) != hipSuccess) {
+            rt_status st = fail_hip(e, "server resources");
+            rt_server_destroy(sv.release());
+            return st;
+        }
+        *L.h_loss = 0.0;
+    }
+    rt_server *p = sv.release();
+    p->th = std::thread(scheduler, p);
+    *out = p;
+    return RT_OK;
+}
+
+rt_status rt_submit(rt_server *sv, const rt_request *rq, uint64_t *ticket) {
+    if (!sv || !rq || !ticket) return fail(RT_EINVAL, "NULL argument");
+    rt_status st = validate(&rq->problem);
+    if (st != RT_OK) return st;
+    if (rq->kind != RT_REQ_FWD && rq->kind != RT_REQ_FWD_ADJ) return fail(RT_EINVAL, "unknown request kind");
+    if (!rq->cube) return fail(RT_EINVAL, "cube is NULL");
+    if (rq->kind == RT_REQ_FWD_ADJ) {
+        if (!rq->target) return fail(RT_EINVAL, "target is NULL");
+        if (rq->problem.spec.nch > kLaunchChannels)
+            return fail(RT_EINVAL, "gradient requests take at most %d channels", kLaunchChannels);
+        if (rq->grads.d_mlp && !rq->problem.mlp) return fail(RT_EINVAL, "d_mlp requested without a network");
+    }
+    std::unique_ptr<Req> r(new Req);
+    r->rq = *rq;
+    const rt_problem &p = rq->problem;
+    r->lev_e.assign(p.line.lev_e_k, p.line.lev_e_k + p.line.nlev);
+    r->lev_g.assign(p.line.lev_g, p.line.lev_g + p.line.nlev);
+    r->vk.assign(p.spec.v_kms, p.spec.v_kms + p.spec.nch);
+    r->rq.problem.line.lev_e_k = r->lev_e.data();
+    r->rq.problem.line.lev_g = r->lev_g.data();
+    r->rq.problem.spec.v_kms = r->vk.data();
+    if (p.mlp) {
+        r->mlp = *p.mlp;
+        r->rq.problem.mlp = &r->mlp;
+    }
+    r->own_stream = rq->kind == RT_REQ_FWD_ADJ || p.mlp != nullptr;
+    r->footprint = footprint(*rq);
+    r->ray_samples = (uint64_t)p.cam.nx * p.cam.ny * p.spec.nch * p.nsamp;
+    std::lock_guard<std::mutex> lk(sv->mu);
+    if (sv->stop) return fail(RT_ECANCELED, "server is shutting down");
+    if (r->footprint > sv->cfg.hbm_budget_bytes)
+        return fail(RT_ETOOBIG, "request needs %llu bytes, budget is %llu", (unsigned long long)r->footprint,
+                    (unsigned long long)sv->cfg.hbm_budget_bytes);
+    if ((int)sv->pending.size() >= sv->cfg.max_pending) return fail(RT_EAGAIN, "pending queue is full");
+    r->id = sv->next_id++;
+    r->t_submit = now_ns();
+    *ticket = r->id;
+    sv->pending.push_back(r.get());
+    sv->tickets[r->id] = std::move(r);
+    sv->cv.notify_all();
+    return RT_OK;
+}
+
+static void fill_info(const Req *r, rt_ticket_info *info) {
+    info->state = r->state;
+    info->status = r->status;
+    info->t_submit_ns = r->t_submit;
+    info->t_admit_ns = r->t_admit;
+    info->t_done_ns = r->t_done;
+    info->loss = r->loss;
+    info->ray_samples = r->ray_samples;
+}
+
+rt_status rt_poll(rt_server *sv, uint64_t ticket, rt_ticket_info *info) {
+    if (!sv || !info) return fail(RT_EINVAL, "NULL argument");
+    std::lock_guard<std::mutex> lk(sv->mu);
+    auto it = sv->tickets.find(ticket);
+    if (it == sv->tickets.end()) return fail(RT_ENOTFOUND, "unknown ticket %llu", (unsigned long long)ticket);
+    fill_info(it->second.get(), info);
+    return RT_OK;
+}
+
+rt_status rt_wait(rt_server *sv, uint64_t ticket, rt_ticket_info *info, uint64_t timeout_ns) {
+    if (!sv || !info) return fail(RT_EINVAL, "NULL argument");
+    std::unique_lock<std::mutex> lk(sv->mu);
+    auto it = sv->tickets.find(ticket);
+    if (it == sv->tickets.end()) return fail(RT_ENOTFOUND, "unknown ticket %llu", (unsigned long long)ticket);
+    Req *r = it->second.get();
+    const auto deadline = std::chrono::steady_clock::now() + std::chrono::nanoseconds(timeout_ns);
+    while (r->state == RT_TICKET_QUEUED || r->state == RT_TICKET_RUNNING) {
+        if (sv->cv.wait_until(lk, deadline) == std::cv_status::timeout) break;
+    }
+    fill_info(r, info);
+    return (r->state == RT_TICKET_QUEUED || r->state == RT_TICKET_RUNNING) ? RT_PENDING : RT_OK;
+}
+
+rt_status rt_cancel(rt_server *sv, uint64_t ticket) {
+    if (!sv) return fail(RT_EINVAL, "NULL argument");
+    std::lock_guard<std::mutex> lk(sv->mu);
+    auto it = sv->tickets.find(ticket);
+    if (it == sv->tickets.end()) return fail(RT_ENOTFOUND, "unknown ticket %llu", (unsigned long long)ticket);
+    Req *r = it->second.get();
+    if (r->state != RT_TICKET_QUEUED) return fail(RT_EINVAL, "request already admitted or finished");
+    for (auto q = sv->pending.begin(); q != sv->pending.end(); ++q)
+        if (*q == r) { sv->pending.erase(q); break; }
+    r->state = RT_TICKET_CANCELED;
+    r->status = RT_ECANCELED;
+    r->t_done = now_ns();
+    sv->cv.notify_all();
+    return RT_OK;
+}
+
+rt_status rt_server_destroy(rt_server *sv) {
+    if (!sv) return fail(RT_EINVAL, "NULL argument");
+    {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        sv->stop = true;
+        for (Req *r : sv->pending) {
+            r->state = RT_TICKET_CANCELED;
+            r->status = RT_ECANCELED;
+            r->t_done = now_ns();
+        }
+        sv->pending.clear();
+        sv->cv.notify_all();
+    }
+    if (sv->th.joinable()) sv->th.join();
+    for (Lane &L : sv->lanes) {
+        if (L.st) (void)hipStreamSynchronize(L.st);
+        if (L.ev) (void)hipEventDestroy(L.ev);
+        if (L.st) (void)hipStreamDestroy(L.st);
+        if (L.d_desc) (void)hipFree(L.d_desc);
+        if (L.h_desc) (void)hipHostFree(L.h_desc);
+        if (L.d_vch) (void)hipFree(L.d_vch);
+        if (L.h_vch) (void)hipHostFree(L.h_vch);
+        if (L.d_counter) (void)hipFree(L.d_counter);
+        if (L.d_loss) (void)hipFree(L.d_loss);
+        if (L.h_loss) (void)hipHostFree(L.h_loss);
+    }
+    delete sv;
+    return RT_OK;
+}
+
+} // extern "C"

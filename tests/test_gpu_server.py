@@ -1,0 +1,178 @@
+"""Render server: results do not depend on the mix, gradient requests match
+the direct adjoint, admission by footprint and slots, the error paths
+(too big, queue full, cancel, unknown ticket), and served throughput above
+one-request-at-a-time on a mixed stream."""
+import time
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _rt():
+    import paper_2509_03623_amd as rt
+    return rt
+
+
+def scene(nx, nch, nsamp, seed=2003, **kw):
+    rt = _rt()
+    prob = synth.config2(seed, nx=nx, ny=nx, nch=nch, nsamp=nsamp, nr=64, nz=32, **kw)
+    return prob, rt.scene_from_problem(prob)
+
+
+def empty_cube(sc):
+    return torch.full((sc.nch, sc.ny, sc.nx), float("nan"), device="cuda")
+
+
+def test_forward_alone_equals_in_mix():
+    rt = _rt()
+    prob, sc = scene(48, 20, 96)
+    print("[gpu] server alone vs mix", flush=True)
+    with rt.Server(max_slots=16, streams=3) as sv:
+        a = empty_cube(sc)
+        t = sv.submit(sc, a)
+        assert sv.wait(t)["state"] == "done"
+        alone = a.clone()
+        # the same request again among others of other sizes, and a gradient request
+        others = [scene(n, c, s, seed=2004 + i) for i, (n, c, s) in enumerate([(64, 16, 128), (32, 33, 80),
+                                                                             (96, 8, 64), (40, 64, 120)])]
+        outs = [empty_cube(s2) for _, s2 in others]
+        ts = [sv.submit(s2, o) for (_, s2), o in zip(others, outs)]
+        gp, gsc = scene(40, 12, 64, seed=2010)
+        gc = empty_cube(gsc)
+        gt = sv.submit(gsc, gc, target=torch.zeros_like(gc),
+                       grads={"temp_k": torch.empty_like(gsc.temp_k)})
+        b = empty_cube(sc)
+        tb = sv.submit(sc, b)
+        for x in ts + [gt, tb]:
+            assert sv.wait(x)["state"] == "done"
+    torch.cuda.synchronize()
+    assert torch.equal(alone, b)
+    ref = oracle.render(prob)
+    got = alone.cpu().numpy().astype(np.float64)
+    assert np.abs(got - ref).max() <= 1e-5 * ref.max()
+    direct = rt.render(sc).cpu().numpy().astype(np.float64)
+    assert np.abs(got - direct).max() <= 1e-6 * np.abs(direct).max()
+    for (p2, s2), o in zip(others, outs):
+        r2 = oracle.render(p2)
+        assert np.abs(o.cpu().numpy() - r2).max() <= 1e-5 * r2.max()
+
+
+def test_gradient_request_matches_direct_adjoint():
+    rt = _rt()
+    prob, sc = scene(40, 12, 64, seed=2011)
+    sc = sc.replace(intensity_scale=synth.disk.rj_kelvin_scale(prob.line))
+    target = rt.render(sc) * 0.9
+    keys = ("ln_nh2", "temp_k", "vphi_kms", "z_lo_au", "z_up_au")
+    grads = {k: torch.empty_like(getattr(sc, k)) for k in keys}
+    cube = empty_cube(sc)
+    print("[gpu] server gradient request", flush=True)
+    with rt.Server(max_slots=4, streams=2) as sv:
+        info = sv.wait(sv.submit(sc, cube, target=target, grads=grads))
+    assert info["state"] == "done"
+    direct_cube = rt.render(sc)
+    loss = float(((direct_cube.double() - target.double()) ** 2).sum())
+    assert info["loss"] == pytest.approx(loss, rel=1e-5)
+    ref = rt.render_adjoint(sc, 2.0 * (direct_cube - target), want=keys)
+    for k in keys:
+        d = float((grads[k] - ref[k]).abs().max())
+        assert d <= 1e-5 * float(ref[k].abs().max()) + 1e-30, k
+
+
+def test_admission_by_budget_and_slots():
+    rt = _rt()
+    _, sc = scene(128, 32, 256)
+    print("[gpu] server admission", flush=True)
+    # a budget that holds one of these requests at a time
+    with rt.Server(hbm_budget_bytes=3 << 20, max_slots=8, streams=4) as sv:
+        cubes = [empty_cube(sc) for _ in range(3)]
+        ts = [sv.submit(sc, c) for c in cubes]
+        infos = [sv.wait(t) for t in ts]
+    assert all(i["state"] == "done" for i in infos)
+    for a, b in zip(infos, infos[1:]):
+        assert b["t_admit_ns"] >= a["t_done_ns"]
+    with rt.Server(max_slots=1, streams=4) as sv:
+        cubes = [empty_cube(sc) for _ in range(3)]
+        infos = [sv.wait(t) for t in [sv.submit(sc, c) for c in cubes]]
+    for a, b in zip(infos, infos[1:]):
+        assert b["t_admit_ns"] >= a["t_done_ns"]
+
+
+def test_error_paths():
+    rt = _rt()
+    from paper_2509_03623_amd import _lib as L
+    _, big = scene(512, 64, 512)
+    _, small = scene(32, 8, 64)
+    print("[gpu] server error paths", flush=True)
+    with rt.Server(hbm_budget_bytes=4 << 20, max_slots=1, max_pending=1, streams=1) as sv:
+        with pytest.raises(rt.RtError) as e:
+            sv.submit(big, empty_cube(big))
+        assert e.value.status == L.RT_ETOOBIG
+        with pytest.raises(rt.RtError) as e:
+            sv.poll(123456)
+        assert e.value.status == L.RT_ENOTFOUND
+    with rt.Server(max_slots=1, max_pending=1, streams=1) as sv:
+        # one long request runs; one waits in the queue; the next finds it full
+        t0 = sv.submit(big, empty_cube(big))
+        deadline = time.time() + 10.0
+        while sv.poll(t0)["state"] == "queued" and time.time() < deadline:
+            time.sleep(1e-4)
+        t1 = sv.submit(small, empty_cube(small))
+        with pytest.raises(rt.RtError) as e:
+            sv.submit(small, empty_cube(small))
+        assert e.value.status == L.RT_EAGAIN
+        sv.cancel(t1)
+        i1 = sv.poll(t1)
+        assert i1["state"] == "canceled" and i1["status"] == L.RT_ECANCELED
+        assert sv.wait(t0)["state"] == "done"
+        with pytest.raises(rt.RtError):
+            sv.cancel(t0)
+
+
+def test_destroy_drains_admitted_work():
+    """Destroying the server finishes what was admitted and cancels what was
+    still queued; an admitted request's cube is complete afterwards."""
+    rt = _rt()
+    _, sc = scene(96, 16, 128)
+    sv = rt.Server(max_slots=8, streams=2)
+    cubes = [empty_cube(sc) for _ in range(4)]
+    ts = [sv.submit(sc, c) for c in cubes]
+    deadline = time.time() + 10.0
+    while sv.poll(ts[0])["state"] == "queued" and time.time() < deadline:
+        time.sleep(1e-4)
+    sv.close()
+    torch.cuda.synchronize()
+    assert not torch.isnan(cubes[0]).any()
+    for c in cubes[1:]:
+        assert bool(torch.isnan(c).all()) or not bool(torch.isnan(c).any())
+
+
+def test_served_stream_beats_serial():
+    """A burst of mixed small and medium forward requests: the server's
+    makespan is shorter than rendering them one at a time."""
+    rt = _rt()
+    sizes = [(64, 16, 128), (128, 32, 256), (64, 64, 200), (256, 16, 160), (128, 16, 300), (64, 32, 128)] * 4
+    scenes = [scene(n, c, s, seed=2020 + i % 6)[1] for i, (n, c, s) in enumerate(sizes)]
+    outs = [empty_cube(s) for s in scenes]
+    for s, o in zip(scenes, outs):       # warm-up of both paths
+        rt.render(s, out=o)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s, o in zip(scenes, outs):
+        rt.render(s, out=o)
+        torch.cuda.synchronize()
+    serial = time.perf_counter() - t0
+    with rt.Server(max_slots=64, streams=4) as sv:
+        sv.wait(sv.submit(scenes[0], outs[0]))
+        t0 = time.perf_counter()
+        ts = [sv.submit(s, o) for s, o in zip(scenes, outs)]
+        for t in ts:
+            assert sv.wait(t)["state"] == "done"
+        served = time.perf_counter() - t0
+    print(f"burst of {len(sizes)}: serial {serial * 1e3:.2f} ms, served {served * 1e3:.2f} ms")
+    assert served < serial
