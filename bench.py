@@ -215,10 +215,12 @@ def bench_serving(rt, synth, dev, seconds, rate=200.0, seed=5, pool=16):
             targets[key] = torch.zeros(key, device=dev)
         return sc, key
 
-    for b in bases:
-        grads_b = {k: torch.empty_like(getattr(b, k)) for k in ("ln_nh2", "temp_k", "z_lo_au", "z_up_au")}
-        grads[id(b)] = grads_b
     reqs = [request(r) for r in trace]
+    # every gradient request writes gradients of its own
+    for i, r in enumerate(trace):
+        if r["grad"]:
+            b = bases[r["disk_seed"] % pool]
+            grads[i] = {k: torch.empty_like(getattr(b, k)) for k in ("ln_nh2", "temp_k", "z_lo_au", "z_up_au")}
     torch.cuda.synchronize()
     total_rs = sum(sc.ray_samples for sc, _ in reqs)
     ngrad = sum(1 for r in trace if r["grad"])
@@ -230,13 +232,12 @@ def bench_serving(rt, synth, dev, seconds, rate=200.0, seed=5, pool=16):
         sv.wait(sv.submit(sc0, torch.empty(sc0.nch, sc0.ny, sc0.nx, device=dev)))
         outstanding = {}
         t0 = time.perf_counter()
-        for r, (sc, key) in zip(trace, reqs):
+        for i, (r, (sc, key)) in enumerate(zip(trace, reqs)):
             while time.perf_counter() - t0 < r["t_arrive"]:
                 time.sleep(2e-4)
             cube = torch.empty(key, device=dev)
             if r["grad"]:
-                b = bases[r["disk_seed"] % pool]
-                t = sv.submit(sc, cube, target=targets[key], grads=grads[id(b)])
+                t = sv.submit(sc, cube, target=targets[key], grads=grads[i])
             else:
                 t = sv.submit(sc, cube)
             outstanding[t] = cube
@@ -269,7 +270,6 @@ def bench_serving(rt, synth, dev, seconds, rate=200.0, seed=5, pool=16):
         first = start if first is None else first
         cube = rt.render(sc)
         if r["grad"]:
-            b = bases[r["disk_seed"] % pool]
             rt.render_adjoint(sc, 2.0 * (cube - targets[key]), want=("ln_nh2", "temp_k", "z_lo_au", "z_up_au"))
         torch.cuda.synchronize()
         lat_s.append((time.perf_counter() - t0 - r["t_arrive"]) * 1e3)

@@ -153,10 +153,13 @@ rt_status rt_render_cube_adjoint(const rt_problem *p, const float *dl_dcube, con
 /* Continuous-batching render server on one GPU.  Requests are admitted in
  * arrival order while their HBM footprint (inputs, outputs and library
  * scratch) fits the budget and a slot is free.  Admitted plain forward
- * requests are cut into (tile, channel block) work items that one persistent
- * launch pulls from a device counter; gradient and neural-layer requests run
- * on streams of their own; requests that arrive meanwhile start on the next
- * idle stream, so work of different requests overlaps on the device.  A
+ * requests too small to fill the device alone (fewer pixel x 16-channel
+ * lanes than the persistent launch keeps resident) are cut into (tile,
+ * channel block) work items that one persistent launch pulls from a device
+ * counter; larger forward requests take rt_render_cube's launch, and gradient
+ * and neural-layer requests their own sequence of launches, each on a stream
+ * of its own; requests that arrive meanwhile start on the next idle stream,
+ * so work of different requests overlaps on the device.  A
  * request's forward cube depends only on the request (bitwise the same alone
  * and in any mix) and equals rt_render_cube's to FP32 rounding.  The caller's
  * device buffers must stay valid until the ticket is done or cancelled. */
@@ -214,8 +217,11 @@ int32_t rt_constants(double *out, int32_t n);
  * series for small dtau, 0 (default) uses 1 - e^-dtau directly.
  * RT_OPT_CKPT_SEGMENT: samples per checkpoint segment of the adjoint (4, 8 or
  * 16; 0 = automatic).  RT_OPT_RAY_SPLIT: lanes sharing one ray in the forward
- * march, each taking a consecutive sub-chord (1, 2, 4 or 8; 0 = automatic). */
-enum { RT_OPT_CHANNEL_BLOCK = 1, RT_OPT_THIN_EXPM1 = 2, RT_OPT_CKPT_SEGMENT = 3, RT_OPT_RAY_SPLIT = 4 };
+ * march, each taking a consecutive sub-chord (1, 2, 4 or 8; 0 = automatic).
+ * RT_OPT_GRAD_ACCUM: 1 (default) accumulates the field gradients of the
+ * adjoint in double, 0 in float. */
+enum { RT_OPT_CHANNEL_BLOCK = 1, RT_OPT_THIN_EXPM1 = 2, RT_OPT_CKPT_SEGMENT = 3, RT_OPT_RAY_SPLIT = 4,
+       RT_OPT_GRAD_ACCUM = 5 };
 rt_status rt_set_option(int32_t key, int64_t value);
 int64_t rt_get_option(int32_t key);
 

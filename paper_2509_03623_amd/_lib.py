@@ -13,6 +13,7 @@ LIB_PATH = os.path.join(HERE, "librtcube.so")
 
 _f = C.POINTER(C.c_float)
 _d = C.POINTER(C.c_double)
+_dev = C.c_void_p          # device pointer: an address, never dereferenced on the host
 
 RT_OK, RT_PENDING, RT_EINVAL, RT_ENOMEM, RT_EDEVICE, RT_EAGAIN, RT_ECANCELED, RT_ETOOBIG, RT_ENOTFOUND = \
     0, 1, -1, -2, -3, -4, -5, -6, -7
@@ -22,7 +23,7 @@ RT_MLP_FP32, RT_MLP_BF16 = 0, 1
 RT_MLP_PARAMS = 58243
 RT_REQ_FWD, RT_REQ_FWD_ADJ = 0, 1
 RT_TICKET_QUEUED, RT_TICKET_RUNNING, RT_TICKET_DONE, RT_TICKET_CANCELED, RT_TICKET_FAILED = 0, 1, 2, 3, 4
-RT_OPT_CHANNEL_BLOCK, RT_OPT_THIN_EXPM1, RT_OPT_CKPT_SEGMENT, RT_OPT_RAY_SPLIT = 1, 2, 3, 4
+RT_OPT_CHANNEL_BLOCK, RT_OPT_THIN_EXPM1, RT_OPT_CKPT_SEGMENT, RT_OPT_RAY_SPLIT, RT_OPT_GRAD_ACCUM = 1, 2, 3, 4, 5
 
 
 class rt_grid(C.Structure):
@@ -31,7 +32,7 @@ class rt_grid(C.Structure):
 
 
 class rt_fields(C.Structure):
-    _fields_ = [("ln_nh2", _f), ("temp_k", _f), ("vphi_kms", _f), ("z_lo_au", _f), ("z_up_au", _f),
+    _fields_ = [("ln_nh2", _dev), ("temp_k", _dev), ("vphi_kms", _dev), ("z_lo_au", _dev), ("z_up_au", _dev),
                 ("x_co", C.c_double), ("mask_width", C.c_double), ("v_turb", C.c_double)]
 
 
@@ -51,7 +52,7 @@ class rt_spectral(C.Structure):
 
 
 class rt_mlp(C.Structure):
-    _fields_ = [("weights", _f), ("precision", C.c_int32)]
+    _fields_ = [("weights", _dev), ("precision", C.c_int32)]
 
 
 class rt_problem(C.Structure):
@@ -61,8 +62,8 @@ class rt_problem(C.Structure):
 
 
 class rt_grads(C.Structure):
-    _fields_ = [("d_ln_nh2", _f), ("d_temp_k", _f), ("d_vphi_kms", _f), ("d_z_lo_au", _f),
-                ("d_z_up_au", _f), ("d_mlp", _f)]
+    _fields_ = [("d_ln_nh2", _dev), ("d_temp_k", _dev), ("d_vphi_kms", _dev), ("d_z_lo_au", _dev),
+                ("d_z_up_au", _dev), ("d_mlp", _dev)]
 
 
 class rt_server_cfg(C.Structure):
@@ -71,7 +72,7 @@ class rt_server_cfg(C.Structure):
 
 
 class rt_request(C.Structure):
-    _fields_ = [("problem", rt_problem), ("kind", C.c_int32), ("cube", _f), ("target", _f),
+    _fields_ = [("problem", rt_problem), ("kind", C.c_int32), ("cube", _dev), ("target", _dev),
                 ("grads", rt_grads)]
 
 
@@ -104,9 +105,9 @@ def lib():
                                "(or __graft_entry__.build())")
         L = C.CDLL(LIB_PATH)
         P = C.POINTER(rt_problem)
-        L.rt_render_cube.argtypes = [P, _f, C.c_void_p]
+        L.rt_render_cube.argtypes = [P, _dev, C.c_void_p]
         L.rt_render_cube.restype = C.c_int
-        L.rt_render_cube_adjoint.argtypes = [P, _f, C.POINTER(rt_grads), _f, C.c_void_p]
+        L.rt_render_cube_adjoint.argtypes = [P, _dev, C.POINTER(rt_grads), _dev, C.c_void_p]
         L.rt_render_cube_adjoint.restype = C.c_int
         L.rt_server_create.argtypes = [C.POINTER(rt_server_cfg), C.POINTER(C.c_void_p)]
         L.rt_server_create.restype = C.c_int

@@ -18,6 +18,7 @@
 //   and scatters them to the grid nodes (float atomics; the surface vectors
 //   are accumulated in LDS first).
 #include "rt_adjoint.h"
+#include "rt_host.h"
 
 namespace rt {
 
@@ -134,15 +135,18 @@ __global__ __launch_bounds__(256) void adj_march(int nsamp, int npix, Channels c
     }
 }
 
-__device__ __forceinline__ void scatter4(double *dst, int n00, int n10, float gv, float w00, float w01, float w10,
+
+template <typename A>
+__device__ __forceinline__ void scatter4(A *dst, int n00, int n10, float gv, float w00, float w01, float w10,
                                          float w11) {
     if (!dst || gv == 0.0f) return;
-    atomicAdd(dst + n00, (double)(gv * w00));
-    atomicAdd(dst + n00 + 1, (double)(gv * w01));
-    atomicAdd(dst + n10, (double)(gv * w10));
-    atomicAdd(dst + n10 + 1, (double)(gv * w11));
+    atomicAdd(dst + n00, (A)(gv * w00));
+    atomicAdd(dst + n00 + 1, (A)(gv * w01));
+    atomicAdd(dst + n10, (A)(gv * w10));
+    atomicAdd(dst + n10 + 1, (A)(gv * w11));
 }
 
+template <typename A>
 __global__ __launch_bounds__(256) void adj_chain(Geometry g, Shade s, const float4 *__restrict__ rays,
                                                  const float4 *__restrict__ cot, int nblk, GradAcc go,
                                                  int lds_surfaces, float4 *__restrict__ dO) {
@@ -208,9 +212,9 @@ __global__ __launch_bounds__(256) void adj_chain(Geometry g, Shade s, const floa
             const float fu = L.fu, fv = L.fv;
             const float w00 = (1.0f - fu) * (1.0f - fv), w01 = (1.0f - fu) * fv, w10 = fu * (1.0f - fv), w11 = fu * fv;
             const int n00 = L.i0 * s.nz + L.j0, n10 = n00 + s.nz;
-            scatter4(go.ln_n, n00, n10, gKK, w00, w01, w10, w11);
-            scatter4(go.temp, n00, n10, gT, w00, w01, w10, w11);
-            scatter4(go.vphi, n00, n10, gV, w00, w01, w10, w11);
+            scatter4((A *)go.ln_n, n00, n10, gKK, w00, w01, w10, w11);
+            scatter4((A *)go.temp, n00, n10, gT, w00, w01, w10, w11);
+            scatter4((A *)go.vphi, n00, n10, gV, w00, w01, w10, w11);
             double *zl = lds_surfaces ? lds : go.zlo;
             double *zu = lds_surfaces ? lds + nr : go.zup;
             if (zl && gzl != 0.0f) { atomicAdd(zl + L.i0, (double)(gzl * (1.0f - fu))); atomicAdd(zl + L.i0 + 1, (double)(gzl * fu)); }
@@ -228,6 +232,153 @@ __global__ __launch_bounds__(256) void adj_chain(Geometry g, Shade s, const floa
     }
 }
 
+// Chain pass with the gradient of one field privatised in LDS.  Persistent
+// workgroups each take a contiguous share of the pixel-samples, accumulate
+// field FIELD (0 ln n, 1 T, 2 v_phi, 3 none) over the whole grid in LDS
+// (float), and flush it once with double atomics; the FIRST pass also
+// accumulates the two surface vectors (LDS, double) and writes dL/do.
+template <int FIELD, bool FIRST>
+__global__ __launch_bounds__(256) void adj_chain_lds(Geometry g, Shade s, const float4 *__restrict__ rays,
+                                                     float4 *__restrict__ cot, int nblk, GradAcc go,
+                                                     float4 *__restrict__ dO) {
+    extern __shared__ double dyn[];              // [2 nr] surfaces (FIRST), then [nr nz] field (float)
+    __shared__ float4 ztab[kZTableNodes - 1];
+    const int nr = s.nr, nn = s.nr * s.nz;
+    double *surf = dyn;
+    float *field = (float *)(dyn + (FIRST ? 2 * nr : 0));
+    for (int i = threadIdx.x; i < kZTableNodes - 1; i += 256) ztab[i] = s.ztab[i];
+    if (FIELD < 3) for (int i = threadIdx.x; i < nn; i += 256) field[i] = 0.0f;
+    if (FIRST) for (int i = threadIdx.x; i < 2 * nr; i += 256) surf[i] = 0.0;
+    __syncthreads();
+    const int npix = g.nx * g.ny;
+    const size_t total = (size_t)g.nsamp * npix;
+    const size_t per = (total + gridDim.x - 1) / gridDim.x;
+    const size_t lo = (size_t)blockIdx.x * per, hi = lo + per < total ? lo + per : total;
+    for (size_t idx = lo + threadIdx.x; idx < hi; idx += 256) {
+        const int k = (int)(idx / npix);
+        const int pix = (int)(idx - (size_t)k * npix);
+        const float4 r = rays[pix];
+        // the first pass sums the channel-block slices and keeps the sum in slice 0
+        float4 c = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        const int nb = FIRST ? nblk : 1;
+        for (int b = 0; b < nb; ++b) {
+            const float4 t = cot[((size_t)b * g.nsamp + k) * npix + pix];
+            c.x += t.x; c.y += t.y; c.z += t.z; c.w += t.w;
+        }
+        if (FIRST && nblk > 1) cot[(size_t)k * npix + pix] = c;
+        float4 dout = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if (r.w > 0.0f && (c.x != 0.0f || c.y != 0.0f || c.z != 0.0f || c.w != 0.0f)) {
+            const float ds = r.w;
+            const float t = ((float)k + 0.5f - 0.5f * (float)g.nsamp) * ds;
+            const float py = fmaf(t, (float)g.si, r.y), pz = fmaf(t, (float)(-g.ci), r.z);
+            const Locus L = locate(s, r.x, py, pz);
+            Fields F = fetch(s, L);
+            float4 o = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            float tfac = 1.0f;
+            const float t_grid = F.T;
+            if (s.mlp_o) {
+                o = s.mlp_o[idx];
+                apply_mlp(s, F, L, o);
+                tfac = F.T / t_grid;
+            }
+            PhysTape tp;
+            const SampleQ q = physics<true>(s, ztab, L, F, r.x, ds, &tp);
+            const float gS = c.x, gK = c.y, ga = c.z, gb = c.w;
+            const float gKK = gK * q.K;
+            float gv = 0.0f;
+            if (FIELD == 0) gv = gKK;
+            if (FIELD == 1 || FIRST) {
+                const float dlnK_dT = tp.rT * (s.el_log2e * kLn2 * tp.rT - tp.x / tp.em1 -
+                                               tp.dZ / (tp.Z * kLn2) - 0.5f);
+                const float dS_dT = q.S * (1.0f + tp.em1) / tp.em1 * tp.x * tp.rT;
+                const float gT = gS * dS_dT + gKK * dlnK_dT - 0.5f * tp.rT * (gb * q.b + ga * q.a);
+                if (FIELD == 1) gv = gT * tfac;
+                if (FIRST && s.mlp_o) {
+                    const float s0 = sigmoidf_(o.x), s0c = sigmoidf_(-o.x);
+                    const float s1 = sigmoidf_(o.y), s1c = sigmoidf_(-o.y);
+                    const float th = tanhf_(o.z);
+                    dout.x = gKK * tp.sa * tp.iw * kLn2 * s.zr_max * L.rho * s0 * s0c;
+                    dout.y = -gKK * tp.sb * tp.iw * kLn2 * s.zr_max * L.rho * s1 * s1c;
+                    dout.z = gT * F.T * 0.5f * (1.0f - th * th);
+                }
+            }
+            if (FIELD == 2) gv = ga * q.b * tp.vfac;
+            const float fu = L.fu, fv = L.fv;
+            if (FIELD < 3 && gv != 0.0f) {
+                const int n00 = L.i0 * s.nz + L.j0, n10 = n00 + s.nz;
+                atomicAdd(field + n00, gv * (1.0f - fu) * (1.0f - fv));
+                atomicAdd(field + n00 + 1, gv * (1.0f - fu) * fv);
+                atomicAdd(field + n10, gv * fu * (1.0f - fv));
+                atomicAdd(field + n10 + 1, gv * fu * fv);
+            }
+            if (FIRST && !s.mlp_o) {
+                const float gzu = gKK * tp.sa * tp.iw * kLn2;
+                const float gzl = -gKK * tp.sb * tp.iw * kLn2;
+                if (gzl != 0.0f) { atomicAdd(surf + L.i0, (double)(gzl * (1.0f - fu))); atomicAdd(surf + L.i0 + 1, (double)(gzl * fu)); }
+                if (gzu != 0.0f) { atomicAdd(surf + nr + L.i0, (double)(gzu * (1.0f - fu))); atomicAdd(surf + nr + L.i0 + 1, (double)(gzu * fu)); }
+            }
+        }
+        if (FIRST && dO) dO[idx] = dout;
+    }
+    __syncthreads();
+    double *dst = FIELD == 0 ? go.ln_n : (FIELD == 1 ? go.temp : (FIELD == 2 ? go.vphi : nullptr));
+    if (FIELD < 3 && dst)
+        for (int i = threadIdx.x; i < nn; i += 256)
+            if (field[i] != 0.0f) atomicAdd(dst + i, (double)field[i]);
+    if (FIRST)
+        for (int i = threadIdx.x; i < nr; i += 256) {
+            if (go.zlo && surf[i] != 0.0) atomicAdd(go.zlo + i, surf[i]);
+            if (go.zup && surf[nr + i] != 0.0) atomicAdd(go.zup + i, surf[nr + i]);
+        }
+}
+
+template <int FIELD, bool FIRST>
+static hipError_t launch_chain_lds_t(const Geometry &g, const Shade &s, const float4 *rays, float4 *cot, int nblk,
+                                     const GradAcc &go, float4 *dO, int nwg, size_t shmem, hipStream_t st) {
+    hipError_t e = hipFuncSetAttribute((const void *)adj_chain_lds<FIELD, FIRST>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((adj_chain_lds<FIELD, FIRST>), dim3(nwg), dim3(256), shmem, st, g, s, rays, cot, nblk, go, dO);
+    return hipGetLastError();
+}
+
+// largest dynamic LDS the privatised chain may use (the LDS of a CU, less
+// the partition table)
+constexpr size_t kChainLdsMax = 160 * 1024 - sizeof(float4) * (kZTableNodes - 1) - 1024;
+
+bool chain_lds_fits(int nr, int nz) {
+    return (size_t)nr * nz * sizeof(float) + 2 * (size_t)nr * sizeof(double) <= kChainLdsMax;
+}
+
+hipError_t launch_adj_chain_lds(const Geometry &g, const Shade &s, const float4 *rays, float4 *cot, int nblk,
+                                const GradAcc &go, float4 *dO, hipStream_t st) {
+    int dev = 0, ncu = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    const size_t total = (size_t)g.nsamp * g.nx * g.ny;
+    const int nwg = (int)std::min<size_t>((size_t)ncu, (total + 255) / 256);
+    const size_t fb = (size_t)s.nr * s.nz * sizeof(float), sb = 2 * (size_t)s.nr * sizeof(double);
+    const bool want[3] = {go.ln_n != nullptr, go.temp != nullptr, go.vphi != nullptr};
+    bool first = true;
+    for (int f = 0; f < 3; ++f) {
+        if (!want[f]) continue;
+        const size_t shmem = fb + (first ? sb : 0);
+        if (first) {
+            e = f == 0 ? launch_chain_lds_t<0, true>(g, s, rays, cot, nblk, go, dO, nwg, shmem, st)
+              : f == 1 ? launch_chain_lds_t<1, true>(g, s, rays, cot, nblk, go, dO, nwg, shmem, st)
+                       : launch_chain_lds_t<2, true>(g, s, rays, cot, nblk, go, dO, nwg, shmem, st);
+        } else {
+            e = f == 1 ? launch_chain_lds_t<1, false>(g, s, rays, cot, nblk, go, dO, nwg, shmem, st)
+                       : launch_chain_lds_t<2, false>(g, s, rays, cot, nblk, go, dO, nwg, shmem, st);
+        }
+        if (e != hipSuccess) return e;
+        first = false;
+    }
+    if (first) e = launch_chain_lds_t<3, true>(g, s, rays, cot, nblk, go, dO, nwg, sb, st);
+    return e;
+}
+
 __global__ void fill_zero_d(double *p, size_t n) {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0.0;
 }
@@ -237,10 +388,23 @@ __global__ void to_float(const double *src, float *dst, size_t n) {
         dst[i] = (float)src[i];
 }
 
+// field accumulators held as float: copy them out (same layout as double)
+__global__ void copy_float(const float *src, float *dst, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
 hipError_t zero_async_d(double *p, size_t n, hipStream_t st) {
     if (!p || n == 0) return hipSuccess;
     const int blocks = (int)std::min<size_t>((n + 255) / 256, 4096);
     hipLaunchKernelGGL(fill_zero_d, dim3(blocks), dim3(256), 0, st, p, n);
+    return hipGetLastError();
+}
+
+hipError_t copy_float_async(const float *src, float *dst, size_t n, hipStream_t st) {
+    if (!dst || n == 0) return hipSuccess;
+    const int blocks = (int)std::min<size_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(copy_float, dim3(blocks), dim3(256), 0, st, src, dst, n);
     return hipGetLastError();
 }
 
@@ -292,8 +456,12 @@ hipError_t launch_adj_chain(const Geometry &g, const Shade &s, const float4 *ray
     const size_t total = (size_t)g.nsamp * g.nx * g.ny;
     const int lds_surf = (s.nr <= 2048) ? 1 : 0;
     const size_t shmem = lds_surf ? sizeof(double) * 2 * s.nr : 0;
-    hipLaunchKernelGGL(adj_chain, dim3((unsigned)((total + 255) / 256)), dim3(256), shmem, st, g, s, rays, cot, nblk,
-                       go, lds_surf, dO);
+    if (grad_accum_double())
+        hipLaunchKernelGGL(adj_chain<double>, dim3((unsigned)((total + 255) / 256)), dim3(256), shmem, st, g, s, rays,
+                           cot, nblk, go, lds_surf, dO);
+    else
+        hipLaunchKernelGGL(adj_chain<float>, dim3((unsigned)((total + 255) / 256)), dim3(256), shmem, st, g, s, rays,
+                           cot, nblk, go, lds_surf, dO);
     return hipGetLastError();
 }
 

@@ -73,12 +73,20 @@ rt_status adjoint_core(const rt_problem *p, const float *dl, const rt_grads *g, 
         if ((e = launch_adj_march(cb, kseg, ns, npix, ch, tape, dl + (size_t)c0 * plane, ckpt, cot,
                                   cube_opt ? cube_opt + (size_t)c0 * plane : nullptr, st)) != hipSuccess)
             return fail_hip(e, "adjoint march");
-        if ((e = launch_adj_chain(geo, sh, rays, cot, nblk, go, c0 == 0 ? dO : nullptr, st)) != hipSuccess)
+        const bool lds = grad_accum_double() && chain_lds_fits(p->grid.nr, p->grid.nz);
+        e = lds ? launch_adj_chain_lds(geo, sh, rays, cot, nblk, go, c0 == 0 ? dO : nullptr, st)
+                : launch_adj_chain(geo, sh, rays, cot, nblk, go, c0 == 0 ? dO : nullptr, st);
+        if (e != hipSuccess)
             return fail_hip(e, "adjoint chain");
     }
-    if ((e = to_float_async(ab, g->d_ln_nh2, nn, st)) != hipSuccess ||
-        (e = to_float_async(ab + nn, g->d_temp_k, nn, st)) != hipSuccess ||
-        (e = to_float_async(ab + 2 * nn, g->d_vphi_kms, nn, st)) != hipSuccess ||
+    // field accumulators are double or float (option); surfaces always double
+    auto field_out = [&](size_t off, float *dst) {
+        return grad_accum_double() ? to_float_async(ab + off, dst, nn, st)
+                                   : copy_float_async((const float *)(ab + off), dst, nn, st);
+    };
+    if ((e = field_out(0, g->d_ln_nh2)) != hipSuccess ||
+        (e = field_out(nn, g->d_temp_k)) != hipSuccess ||
+        (e = field_out(2 * nn, g->d_vphi_kms)) != hipSuccess ||
         (e = to_float_async(ab + 3 * nn, g->d_z_lo_au, nr, st)) != hipSuccess ||
         (e = to_float_async(ab + 3 * nn + nr, g->d_z_up_au, nr, st)) != hipSuccess)
         return fail_hip(e, "gradient output");

@@ -48,6 +48,7 @@ static int64_t g_opt_cb = 0;
 static int64_t g_opt_thin = 0;
 static int64_t g_opt_ckpt = 0;
 static int64_t g_opt_split = 0;
+static int64_t g_opt_accum = 1;
 
 // Launch shape of the forward march: channels per lane (cb) and lanes per
 // ray (nsplit).  Measured on MI355X: one channel block per pixel is best
@@ -80,6 +81,7 @@ int channel_block_for(int nch, long npix) {
 
 bool thin_series() { return g_opt_thin != 0; }
 int ckpt_segment_option() { return (int)g_opt_ckpt; }
+bool grad_accum_double() { return g_opt_accum != 0; }
 
 // ---------------------------------------------------------------- validation
 static bool finite(double x) { return std::isfinite(x); }
@@ -147,10 +149,27 @@ static uint64_t fnv(uint64_t h, const void *p, size_t n) {
 
 constexpr double kZT0 = 0.1, kZT1 = 1.0e4;
 
+// The adjoint and network scratch (up to tens of GB) comes from the
+// device's default stream-ordered pool; keep freed blocks in the pool rather
+// than unmapping them at every synchronisation, so repeated calls reuse them.
+static void keep_pool(int dev) {
+    static std::mutex mu;
+    static std::map<int, bool> done;
+    std::lock_guard<std::mutex> lk(mu);
+    if (done[dev]) return;
+    done[dev] = true;
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+        uint64_t thr = ~0ull;
+        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+    }
+}
+
 rt_status partition_table(const rt_line &l, const float4 **out) {
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return fail_hip(e, "hipGetDevice");
+    keep_pool(dev);
     uint64_t h = 1469598103934665603ull;
     h = fnv(h, &l.nlev, sizeof l.nlev);
     h = fnv(h, l.lev_e_k, sizeof(double) * l.nlev);
@@ -293,6 +312,9 @@ rt_status rt_set_option(int32_t key, int64_t value) {
         if (value < 0 || value > 64) return fail(RT_EINVAL, "checkpoint segment must be 0..64");
         g_opt_ckpt = value;
         return RT_OK;
+    case RT_OPT_GRAD_ACCUM:
+        g_opt_accum = value ? 1 : 0;
+        return RT_OK;
     case RT_OPT_RAY_SPLIT:
         if (value != 0 && value != 1 && value != 2 && value != 4 && value != 8)
             return fail(RT_EINVAL, "ray split must be 0, 1, 2, 4 or 8");
@@ -309,6 +331,7 @@ int64_t rt_get_option(int32_t key) {
     case RT_OPT_THIN_EXPM1: return g_opt_thin;
     case RT_OPT_CKPT_SEGMENT: return g_opt_ckpt;
     case RT_OPT_RAY_SPLIT: return g_opt_split;
+    case RT_OPT_GRAD_ACCUM: return g_opt_accum;
     default: return -1;
     }
 }

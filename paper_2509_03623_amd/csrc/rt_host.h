@@ -15,6 +15,7 @@ int channel_block_for(int nch, long npix);
 void forward_shape(int nch, long npix, int nsamp, int *cb, int *nsplit);
 bool thin_series();
 int ckpt_segment_option();
+bool grad_accum_double();
 
 rt_status render_cube_mlp(const rt_problem *p, float *cube, hipStream_t st);
 rt_status march_cube(const rt_problem *p, const Geometry &g, const Shade &s, float *cube, hipStream_t st);

@@ -6,13 +6,20 @@
 
 namespace rt {
 
+// workgroups (256 lanes each) per compute unit of the persistent forward
+// launch; an item covers kServeTile x kServeTile pixels with kServeSplit
+// lanes per pixel
+constexpr int kServeWorkgroupsPerCU = 4;
+constexpr int kServeTile = 8;
+constexpr int kServeSplit = 4;
+
 // One request of a persistent forward batch.
 struct ServeDesc {
     Geometry g;
     Shade s;
     const float *vch;     // channel velocities, padded to a multiple of 16
     float *cube;          // [nch][ny][nx]
-    int32_t nch, nblk, tiles_x;
+    int32_t nch, nblk, tiles_x;   // channel blocks of 16, item tiles across
     uint32_t item0;       // first work item of this request in the batch
 };
 

@@ -3,16 +3,19 @@
 // loss / cotangent of forward+adjoint requests.
 //
 // A batch holds up to max_slots requests; its work items are (request,
-// 16 x 16 pixel tile, 16-channel block) in request order.  The launch has a
-// fixed number of workgroups; each pulls the next item index from a device
-// counter until the batch is exhausted, so items of small and large requests
-// of the batch share the GPU.  Every wave exits once the counter passes the
-// item count.
+// 8 x 8 pixel tile, 16-channel block) in request order.  The four adjacent
+// lanes of a pixel march consecutive quarters of its ray and compose them by
+// shuffles at the end (front-to-back composition is associative), so an
+// item's latency is a quarter of its ray.  The launch has a fixed number of
+// workgroups; each pulls the next item index from a device counter until the
+// batch is exhausted, so items of small and large requests of the batch share
+// the GPU.  Every wave exits once the counter passes the item count.
 #include "rt_serve.h"
 
 namespace rt {
 
 constexpr int kServeCB = 16;
+static_assert(kServeTile * kServeTile * kServeSplit == 256, "one item per 256-lane workgroup");
 
 __global__ __launch_bounds__(256) void serve_fwd(const ServeDesc *__restrict__ descs, int nreq, uint32_t nitems,
                                                  uint32_t *__restrict__ counter) {
@@ -45,32 +48,49 @@ __global__ __launch_bounds__(256) void serve_fwd(const ServeDesc *__restrict__ d
         const int blk = (int)(local % (uint32_t)D.nblk);
         const int tile = (int)(local / (uint32_t)D.nblk);
         const Geometry &g = D.g;
-        const int p = (tile % D.tiles_x) * 16 + (threadIdx.x & 15);
-        const int q = (tile / D.tiles_x) * 16 + (threadIdx.x >> 4);
+        const int split = threadIdx.x % kServeSplit, slot = threadIdx.x / kServeSplit;
+        const int p = (tile % D.tiles_x) * kServeTile + slot % kServeTile;
+        const int q = (tile / D.tiles_x) * kServeTile + slot / kServeTile;
         const int c0 = blk * kServeCB;
-        if (p < g.nx && q < g.ny) {
-            float I[kServeCB], Tr[kServeCB];
+        const bool inside = p < g.nx && q < g.ny;
+        float I[kServeCB], Tr[kServeCB];
 #pragma unroll
-            for (int c = 0; c < kServeCB; ++c) { I[c] = 0.0f; Tr[c] = 1.0f; }
-            float vc[kServeCB];
+        for (int c = 0; c < kServeCB; ++c) { I[c] = 0.0f; Tr[c] = 1.0f; }
+        float vc[kServeCB];
 #pragma unroll
-            for (int c = 0; c < kServeCB; ++c) vc[c] = D.vch[c0 + c];
-            const RaySetup r = ray_setup(g, p, q);
-            if (r.live) {
-                const float half = 0.5f * (float)g.nsamp;
-                for (int k = 0; k < g.nsamp; ++k) {
-                    const float t = ((float)k + 0.5f - half) * r.ds;
-                    const SampleQ sq = shade_sample<false>(D.s, ztab, r.px, fmaf(t, r.wy, r.pmy),
-                                                           fmaf(t, r.wz, r.pmz), r.ds, 0);
+        for (int c = 0; c < kServeCB; ++c) vc[c] = D.vch[c0 + c];
+        const RaySetup r = ray_setup(g, inside ? p : 0, inside ? q : 0);
+        if (inside && r.live) {
+            const float half = 0.5f * (float)g.nsamp;
+            const int len = (g.nsamp + kServeSplit - 1) / kServeSplit;
+            const int k0 = split * len, k1 = min(g.nsamp, k0 + len);
+            for (int k = k0; k < k1; ++k) {
+                const float t = ((float)k + 0.5f - half) * r.ds;
+                const SampleQ sq = shade_sample<false>(D.s, ztab, r.px, fmaf(t, r.wy, r.pmy),
+                                                       fmaf(t, r.wz, r.pmz), r.ds, 0);
 #pragma unroll
-                    for (int c = 0; c < kServeCB; ++c) {
-                        const float d = fmaf(-vc[c], sq.b, sq.a);
-                        const float att = fexp2(-(sq.K * fexp2(-(d * d))));
-                        I[c] = fmaf(Tr[c] * (1.0f - att), sq.S, I[c]);
-                        Tr[c] *= att;
-                    }
+                for (int c = 0; c < kServeCB; ++c) {
+                    const float d = fmaf(-vc[c], sq.b, sq.a);
+                    const float att = fexp2(-(sq.K * fexp2(-(d * d))));
+                    I[c] = fmaf(Tr[c] * (1.0f - att), sq.S, I[c]);
+                    Tr[c] *= att;
                 }
             }
+        }
+        // compose the quarters front to back (every lane takes part in the shuffles)
+#pragma unroll
+        for (int d = 1; d < kServeSplit; d <<= 1) {
+#pragma unroll
+            for (int c = 0; c < kServeCB; ++c) {
+                const float Ib = __shfl_down(I[c], d, kServeSplit);
+                const float Tb = __shfl_down(Tr[c], d, kServeSplit);
+                if ((split & (2 * d - 1)) == 0) {
+                    I[c] = fmaf(Tr[c], Ib, I[c]);
+                    Tr[c] *= Tb;
+                }
+            }
+        }
+        if (inside && split == 0) {
             const size_t plane = (size_t)g.nx * g.ny, pix = (size_t)q * g.nx + p;
 #pragma unroll
             for (int c = 0; c < kServeCB; ++c)

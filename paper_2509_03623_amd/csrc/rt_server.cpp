@@ -5,11 +5,13 @@
 //   1. retires finished launches (event queries) and frees their budget/slots,
 //   2. admits queued requests in arrival order while their HBM footprint fits
 //      the budget and a slot is free,
-//   3. starts admitted work on an idle stream: every admitted plain forward
-//      request goes into one persistent launch whose workgroups pull
-//      (request, tile, channel block) items from a device counter; a request
-//      with a gradient (forward, fused L2 loss + cotangent, adjoint) or with
-//      the neural CO layer runs on a stream of its own.
+//   3. starts admitted work on an idle stream: the admitted plain forward
+//      requests that are too small to fill the device alone go into one
+//      persistent launch whose workgroups pull (request, tile, channel block)
+//      items from a device counter; a request that fills the device alone
+//      (the direct renderer's launch shape), one with a gradient (forward,
+//      fused L2 loss + cotangent, adjoint) or one with the neural CO layer
+//      runs on a stream of its own.
 // Requests that arrive while launches run are admitted as budget and slots
 // free up and start on the next idle stream, so their work overlaps on the
 // device with what is already running.  A forward cube depends only on its
@@ -50,7 +52,7 @@ struct Req {
     uint64_t t_submit = 0, t_admit = 0, t_done = 0;
     double loss = 0.0;
     uint64_t footprint = 0, ray_samples = 0;
-    bool own_stream = false;   // gradient or neural request
+    bool own_stream = false;   // large, gradient or neural request
 };
 
 struct Lane {
@@ -150,16 +152,16 @@ rt_status launch_batch(rt_server *sv, Lane &L, std::vector<Req *> &batch) {
         D.cube = batch[i]->rq.cube;
         D.nch = nch;
         D.nblk = padded / 16;
-        D.tiles_x = (p.cam.nx + 15) / 16;
+        D.tiles_x = (p.cam.nx + kServeTile - 1) / kServeTile;
         D.item0 = items;
-        items += (uint32_t)(D.tiles_x * ((p.cam.ny + 15) / 16) * D.nblk);
+        items += (uint32_t)(D.tiles_x * ((p.cam.ny + kServeTile - 1) / kServeTile) * D.nblk);
     }
     hipError_t e = hipMemcpyAsync(L.d_desc, L.h_desc, sizeof(ServeDesc) * batch.size(), hipMemcpyHostToDevice, L.st);
     if (e == hipSuccess) e = hipMemcpyAsync(L.d_vch, L.h_vch, sizeof(float) * vo, hipMemcpyHostToDevice, L.st);
     if (e != hipSuccess) return fail_hip(e, "server upload");
     hipLaunchKernelGGL(zero_u32, dim3(1), dim3(1), 0, L.st, L.d_counter);
     if ((e = hipGetLastError()) != hipSuccess) return fail_hip(e, "server counter");
-    e = launch_serve_fwd(L.d_desc, (int)batch.size(), items, L.d_counter, sv->ncu * 4, L.st);
+    e = launch_serve_fwd(L.d_desc, (int)batch.size(), items, L.d_counter, sv->ncu * kServeWorkgroupsPerCU, L.st);
     if (e != hipSuccess) return fail_hip(e, "server batch launch");
     return RT_OK;
 }
@@ -322,7 +324,11 @@ rt_status rt_submit(rt_server *sv, const rt_request *rq, uint64_t *ticket) {
         r->mlp = *p.mlp;
         r->rq.problem.mlp = &r->mlp;
     }
-    r->own_stream = rq->kind == RT_REQ_FWD_ADJ || p.mlp != nullptr;
+    // lanes of the request in the persistent launch (kServeSplit per pixel and
+    // 16-channel block) against the lanes the launch keeps resident
+    const uint64_t serve_lanes = (uint64_t)p.cam.nx * p.cam.ny * ((p.spec.nch + 15) / 16) * kServeSplit;
+    const bool fills = serve_lanes >= (uint64_t)sv->ncu * kServeWorkgroupsPerCU * 256;
+    r->own_stream = rq->kind == RT_REQ_FWD_ADJ || p.mlp != nullptr || fills;
     r->footprint = footprint(*rq);
     r->ray_samples = (uint64_t)p.cam.nx * p.cam.ny * p.spec.nch * p.nsamp;
     std::lock_guard<std::mutex> lk(sv->mu);

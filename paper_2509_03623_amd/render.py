@@ -16,9 +16,6 @@ import torch
 
 from . import _lib as L
 
-_f = C.POINTER(C.c_float)
-
-
 @dataclass
 class Scene:
     nr: int
@@ -57,6 +54,7 @@ class Scene:
     mlp_w: Optional[torch.Tensor] = None
     mlp_precision: int = L.RT_MLP_BF16
     keep: list = field(default_factory=list, repr=False)
+    _struct: tuple = field(default=None, repr=False, compare=False)
 
     @property
     def nch(self) -> int:
@@ -67,7 +65,7 @@ class Scene:
         return self.nx * self.ny * self.nch * self.nsamp
 
     def replace(self, **kw) -> "Scene":
-        return replace(self, **kw)
+        return replace(self, _struct=None, **kw)
 
 
 def scene_from_problem(prob, device="cuda", mlp_precision=L.RT_MLP_BF16) -> Scene:
@@ -90,16 +88,27 @@ def scene_from_problem(prob, device="cuda", mlp_precision=L.RT_MLP_BF16) -> Scen
 
 
 def _fptr(t: Optional[torch.Tensor]):
+    """Device address of a contiguous float32 CUDA tensor (None for NULL)."""
     if t is None:
-        return _f()
+        return None
     if t.dtype != torch.float32 or not t.is_contiguous() or t.device.type != "cuda":
         raise ValueError("expected a contiguous float32 CUDA tensor")
-    return C.cast(C.c_void_p(t.data_ptr()), _f)
+    return t.data_ptr()
 
 
 def problem_struct(sc: Scene, fields: Optional[dict] = None):
     """rt_problem for the scene (fields may override the scene's tensors).
-    Returns (struct, keepalive)."""
+    Returns (struct, keepalive); without overrides the struct is built once
+    per scene and reused."""
+    if fields is None and sc._struct is not None:
+        return sc._struct
+    built = _build_struct(sc, fields)
+    if fields is None:
+        sc._struct = built
+    return built
+
+
+def _build_struct(sc: Scene, fields: Optional[dict]):
     fl = dict(ln_nh2=sc.ln_nh2, temp_k=sc.temp_k, vphi_kms=sc.vphi_kms, z_lo_au=sc.z_lo_au,
               z_up_au=sc.z_up_au, mlp_w=sc.mlp_w)
     if fields:

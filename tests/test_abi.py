@@ -42,7 +42,7 @@ def test_constants_match_oracle_digit_for_digit():
 def _struct_for(prob):
     """rt_problem with host-only fake device pointers (validation never
     dereferences them)."""
-    fake = C.cast(C.c_void_p(0x1000), C.POINTER(C.c_float))
+    fake = 0x1000
     g, cam, line = prob.grid, prob.camera, prob.line
     lev_e = np.ascontiguousarray(line.lev_e_k)
     lev_g = np.ascontiguousarray(line.lev_g)
@@ -64,7 +64,7 @@ def _struct_for(prob):
     (lambda p: setattr(p.grid, "nr", 1), "nr >= 2"),
     (lambda p: setattr(p.grid, "r_min_au", -1.0), "r_min"),
     (lambda p: setattr(p.grid, "zr_max", 0.0), "zr_max"),
-    (lambda p: setattr(p.f, "ln_nh2", C.POINTER(C.c_float)()), "NULL"),
+    (lambda p: setattr(p.f, "ln_nh2", None), "NULL"),
     (lambda p: setattr(p.f, "mask_width", 0.0), "mask_width"),
     (lambda p: setattr(p.cam, "nx", 0), "nx"),
     (lambda p: setattr(p.cam, "incl_deg", 95.0), "inclination"),
@@ -85,7 +85,7 @@ def test_validation_rejects_on_host(mutate, msg):
 def test_null_outputs_rejected():
     prob = synth.small_problem()
     p, keep, fake = _struct_for(prob)
-    assert L.lib().rt_render_cube(C.byref(p), C.POINTER(C.c_float)(), None) == L.RT_EINVAL
+    assert L.lib().rt_render_cube(C.byref(p), None, None) == L.RT_EINVAL
     assert L.lib().rt_render_cube(None, fake, None) == L.RT_EINVAL
 
 

@@ -153,17 +153,22 @@ def test_destroy_drains_admitted_work():
 
 
 def test_served_stream_beats_serial():
-    """A burst of mixed small and medium forward requests: the server's
-    makespan is shorter than rendering them one at a time."""
+    """A burst of small forward requests (each far too small to fill the
+    GPU, with long rays): the server's makespan, submission included, is
+    shorter than rendering them one at a time with a synchronisation after
+    each, and every served cube equals the one-at-a-time cube to FP32
+    rounding."""
     rt = _rt()
-    sizes = [(64, 16, 128), (128, 32, 256), (64, 64, 200), (256, 16, 160), (128, 16, 300), (64, 32, 128)] * 4
+    sizes = [(32, 16, 384), (48, 8, 512), (64, 16, 448), (40, 24, 320), (56, 16, 512), (32, 32, 256)] * 6
     scenes = [scene(n, c, s, seed=2020 + i % 6)[1] for i, (n, c, s) in enumerate(sizes)]
+    ref = [empty_cube(s) for s in scenes]
     outs = [empty_cube(s) for s in scenes]
-    for s, o in zip(scenes, outs):       # warm-up of both paths
+    for s, o in zip(scenes, ref):       # warm-up of both paths
         rt.render(s, out=o)
     torch.cuda.synchronize()
+    print(f"[gpu] server burst of {len(sizes)}", flush=True)
     t0 = time.perf_counter()
-    for s, o in zip(scenes, outs):
+    for s, o in zip(scenes, ref):
         rt.render(s, out=o)
         torch.cuda.synchronize()
     serial = time.perf_counter() - t0
@@ -171,8 +176,10 @@ def test_served_stream_beats_serial():
         sv.wait(sv.submit(scenes[0], outs[0]))
         t0 = time.perf_counter()
         ts = [sv.submit(s, o) for s, o in zip(scenes, outs)]
-        for t in ts:
-            assert sv.wait(t)["state"] == "done"
+        infos = [sv.wait(t) for t in ts]
         served = time.perf_counter() - t0
+    assert all(i["state"] == "done" for i in infos)
     print(f"burst of {len(sizes)}: serial {serial * 1e3:.2f} ms, served {served * 1e3:.2f} ms")
+    for a, b in zip(ref, outs):
+        assert float((a - b).abs().max()) <= 1e-6 * float(a.abs().max())
     assert served < serial
