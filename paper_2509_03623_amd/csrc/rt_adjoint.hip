@@ -37,9 +37,9 @@ __global__ __launch_bounds__(256) void adj_tape(Geometry g, Shade s, float4 *__r
         if (r.live) {
             const float t = ((float)k + 0.5f - half) * r.ds;
             const SampleQ q = s.mlp_o ? shade_sample<true>(s, ztab, r.px, fmaf(t, r.wy, r.pmy), fmaf(t, r.wz, r.pmz),
-                                                           r.ds, (size_t)k * npix + pix)
+                                                           r.ds, o_index(s, k, pix))
                                       : shade_sample<false>(s, ztab, r.px, fmaf(t, r.wy, r.pmy), fmaf(t, r.wz, r.pmz), r.ds,
-                                           (size_t)k * npix + pix);
+                                                            0);
             o = make_float4(q.S, q.K, q.a, q.b);
         }
         tape[(size_t)k * npix + pix] = o;
@@ -47,9 +47,10 @@ __global__ __launch_bounds__(256) void adj_tape(Geometry g, Shade s, float4 *__r
 }
 
 template <int CB, int KSEG>
-__global__ __launch_bounds__(256) void adj_march(int nsamp, int npix, Channels ch, const float4 *__restrict__ tape,
-                                                 const float *__restrict__ dl_dcube, float *__restrict__ ckpt,
-                                                 float4 *__restrict__ cot, float *__restrict__ cube_out) {
+__global__ __launch_bounds__(256) void adj_march(int nsamp, int npix, int plane, Channels ch,
+                                                 const float4 *__restrict__ tape, const float *__restrict__ dl_dcube,
+                                                 float *__restrict__ ckpt, float4 *__restrict__ cot,
+                                                 float *__restrict__ cube_out) {
     const int pix = blockIdx.x * 256 + threadIdx.x;
     if (pix >= npix) return;
     const int blk = blockIdx.y, nblk = gridDim.y;
@@ -58,7 +59,7 @@ __global__ __launch_bounds__(256) void adj_march(int nsamp, int npix, Channels c
     float w[CB], Tr[CB], I[CB];
 #pragma unroll
     for (int c = 0; c < CB; ++c) {
-        w[c] = (c0 + c < ch.n) ? dl_dcube[(size_t)(c0 + c) * npix + pix] : 0.0f;
+        w[c] = (c0 + c < ch.n) ? dl_dcube[(size_t)(c0 + c) * plane + pix] : 0.0f;
         Tr[c] = 1.0f;
         I[c] = 0.0f;
     }
@@ -84,7 +85,7 @@ __global__ __launch_bounds__(256) void adj_march(int nsamp, int npix, Channels c
     if (cube_out) {
 #pragma unroll
         for (int c = 0; c < CB; ++c)
-            if (c0 + c < ch.n) cube_out[(size_t)(c0 + c) * npix + pix] = I[c];
+            if (c0 + c < ch.n) cube_out[(size_t)(c0 + c) * plane + pix] = I[c];
     }
     // reverse sweep, one segment at a time
     float J[CB];
@@ -181,7 +182,7 @@ __global__ __launch_bounds__(256) void adj_chain(Geometry g, Shade s, const floa
             float4 o = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
             float tfac = 1.0f, t_grid = F.T;
             if (s.mlp_o) {
-                o = s.mlp_o[idx];
+                o = s.mlp_o[o_index(s, k, pix)];
                 apply_mlp(s, F, L, o);
                 tfac = F.T / t_grid;
             }
@@ -220,7 +221,7 @@ __global__ __launch_bounds__(256) void adj_chain(Geometry g, Shade s, const floa
             if (zl && gzl != 0.0f) { atomicAdd(zl + L.i0, (double)(gzl * (1.0f - fu))); atomicAdd(zl + L.i0 + 1, (double)(gzl * fu)); }
             if (zu && gzu != 0.0f) { atomicAdd(zu + L.i0, (double)(gzu * (1.0f - fu))); atomicAdd(zu + L.i0 + 1, (double)(gzu * fu)); }
         }
-        if (dO) dO[idx] = dout;
+        if (dO) dO[o_index(s, k, pix)] = dout;
     }
     if (lds_surfaces) {
         __syncthreads();
@@ -277,7 +278,7 @@ __global__ __launch_bounds__(256) void adj_chain_lds(Geometry g, Shade s, const 
             float tfac = 1.0f;
             const float t_grid = F.T;
             if (s.mlp_o) {
-                o = s.mlp_o[idx];
+                o = s.mlp_o[o_index(s, k, pix)];
                 apply_mlp(s, F, L, o);
                 tfac = F.T / t_grid;
             }
@@ -318,7 +319,7 @@ __global__ __launch_bounds__(256) void adj_chain_lds(Geometry g, Shade s, const 
                 if (gzu != 0.0f) { atomicAdd(surf + nr + L.i0, (double)(gzu * (1.0f - fu))); atomicAdd(surf + nr + L.i0 + 1, (double)(gzu * fu)); }
             }
         }
-        if (FIRST && dO) dO[idx] = dout;
+        if (FIRST && dO) dO[o_index(s, k, pix)] = dout;
     }
     __syncthreads();
     double *dst = FIELD == 0 ? go.ln_n : (FIELD == 1 ? go.temp : (FIELD == 2 ? go.vphi : nullptr));
@@ -433,17 +434,18 @@ hipError_t launch_adj_tape(const Geometry &g, const Shade &s, float4 *tape, floa
 }
 
 template <int CB, int KSEG>
-static hipError_t launch_march_t(int nsamp, int npix, const Channels &ch, const float4 *tape, const float *dl,
-                                 float *ckpt, float4 *cot, float *cube_out, hipStream_t st) {
+static hipError_t launch_march_t(int nsamp, int npix, int plane, const Channels &ch, const float4 *tape,
+                                 const float *dl, float *ckpt, float4 *cot, float *cube_out, hipStream_t st) {
     dim3 grid((npix + 255) / 256, (ch.n + CB - 1) / CB);
-    hipLaunchKernelGGL((adj_march<CB, KSEG>), grid, dim3(256), 0, st, nsamp, npix, ch, tape, dl, ckpt, cot, cube_out);
+    hipLaunchKernelGGL((adj_march<CB, KSEG>), grid, dim3(256), 0, st, nsamp, npix, plane, ch, tape, dl, ckpt, cot,
+                       cube_out);
     return hipGetLastError();
 }
 
-hipError_t launch_adj_march(int cb, int kseg, int nsamp, int npix, const Channels &ch, const float4 *tape,
+hipError_t launch_adj_march(int cb, int kseg, int nsamp, int npix, int plane, const Channels &ch, const float4 *tape,
                             const float *dl, float *ckpt, float4 *cot, float *cube_out, hipStream_t st) {
 #define RT_MARCH_CASE(C, K) \
-    if (cb == C && kseg == K) return launch_march_t<C, K>(nsamp, npix, ch, tape, dl, ckpt, cot, cube_out, st);
+    if (cb == C && kseg == K) return launch_march_t<C, K>(nsamp, npix, plane, ch, tape, dl, ckpt, cot, cube_out, st);
     RT_MARCH_CASE(8, 4) RT_MARCH_CASE(8, 8) RT_MARCH_CASE(8, 16)
     RT_MARCH_CASE(16, 4) RT_MARCH_CASE(16, 8)
     RT_MARCH_CASE(32, 4)

@@ -11,19 +11,23 @@
 namespace rt {
 
 // channels per lane and samples per checkpoint segment of the reverse march
-static void adjoint_shape(int nch, int *cb, int *kseg) {
+void adjoint_shape(int nch, int *cb, int *kseg) {
     *cb = nch > 8 ? 16 : 8;
-    *kseg = 8;
+    *kseg = 4;
     const int opt = ckpt_segment_option();
     if (opt == 4 || opt == 8 || opt == 16) *kseg = opt;
     if (*cb == 16 && *kseg == 16) *kseg = 8;
 }
 
-struct Scratch {
-    void *p = nullptr;
-    hipStream_t st = nullptr;
-    ~Scratch() { if (p) (void)hipFreeAsync(p, st); }
-};
+size_t adjoint_bytes_per_pixel(int nch, int nsamp) {
+    int cb, kseg;
+    adjoint_shape(std::min(nch, kLaunchChannels), &cb, &kseg);
+    const size_t ch = std::min(nch, kLaunchChannels), nblk = (ch + cb - 1) / cb;
+    const size_t nseg = ((size_t)nsamp + kseg - 1) / kseg;
+    // tape, ray set-up, transmission checkpoints, per-block cotangents
+    return 16 * (size_t)nsamp + 16 + 4 * nseg * nblk * cb + 16 * nblk * (size_t)nsamp;
+}
+
 
 rt_status adjoint_core(const rt_problem *p, const float *dl, const rt_grads *g, float *cube_opt, hipStream_t st,
                        const float4 *mlp_o, float4 *dO) {
@@ -38,11 +42,8 @@ rt_status adjoint_core(const rt_problem *p, const float *dl, const rt_grads *g, 
     hipError_t e;
     // gradients accumulate in double, then overwrite the caller's float outputs
     const size_t acc_n = 3 * nn + 2 * nr;
-    Scratch acc;
-    acc.st = st;
-    e = hipMallocAsync(&acc.p, sizeof(double) * acc_n, st);
-    if (e != hipSuccess) { acc.p = nullptr; return fail_hip(e, "gradient accumulators"); }
-    double *ab = (double *)acc.p;
+    double *ab = (double *)stream_workspace(st, kWsGradAcc, sizeof(double) * acc_n, &e);
+    if (!ab) return fail_hip(e, "gradient accumulators");
     if ((e = zero_async_d(ab, acc_n, st)) != hipSuccess) return fail_hip(e, "zero");
     GradAcc go{g->d_ln_nh2 ? ab : nullptr, g->d_temp_k ? ab + nn : nullptr, g->d_vphi_kms ? ab + 2 * nn : nullptr,
                g->d_z_lo_au ? ab + 3 * nn : nullptr, g->d_z_up_au ? ab + 3 * nn + nr : nullptr};
@@ -50,34 +51,45 @@ rt_status adjoint_core(const rt_problem *p, const float *dl, const rt_grads *g, 
     adjoint_shape(std::min(p->spec.nch, kLaunchChannels), &cb, &kseg);
     const int nseg = (ns + kseg - 1) / kseg;
     const size_t plane = (size_t)npix;
+    const int nx = p->cam.nx, ny = p->cam.ny;
+    // bands of image rows whose scratch fits the cap (at least one row)
+    const size_t row_bytes = adjoint_bytes_per_pixel(p->spec.nch, ns) * (size_t)nx;
+    const int band = (int)std::max<size_t>(1, std::min<size_t>((size_t)ny, adjoint_scratch_cap() / row_bytes));
+    const bool lds = grad_accum_double() && chain_lds_fits(p->grid.nr, p->grid.nz);
     for (int c0 = 0; c0 < p->spec.nch; c0 += kLaunchChannels) {
         Channels ch;
         std::memset(&ch, 0, sizeof ch);
         ch.n = std::min(kLaunchChannels, p->spec.nch - c0);
         for (int c = 0; c < ch.n; ++c) ch.v[c] = (float)p->spec.v_kms[c0 + c];
         const int nblk = (ch.n + cb - 1) / cb;
-        const size_t tape_b = sizeof(float4) * (size_t)ns * npix;
-        const size_t rays_b = sizeof(float4) * (size_t)npix;
-        const size_t ckpt_b = sizeof(float) * (size_t)nseg * nblk * cb * npix;
-        const size_t cot_b = sizeof(float4) * (size_t)nblk * ns * npix;
-        Scratch ws;
-        ws.st = st;
-        e = hipMallocAsync(&ws.p, tape_b + rays_b + ckpt_b + cot_b, st);
-        if (e != hipSuccess) { ws.p = nullptr; return fail_hip(e, "adjoint scratch"); }
-        char *base = (char *)ws.p;
-        float4 *tape = (float4 *)base;
-        float4 *rays = (float4 *)(base + tape_b);
-        float *ckpt = (float *)(base + tape_b + rays_b);
-        float4 *cot = (float4 *)(base + tape_b + rays_b + ckpt_b);
-        if ((e = launch_adj_tape(geo, sh, tape, rays, st)) != hipSuccess) return fail_hip(e, "adjoint tape");
-        if ((e = launch_adj_march(cb, kseg, ns, npix, ch, tape, dl + (size_t)c0 * plane, ckpt, cot,
-                                  cube_opt ? cube_opt + (size_t)c0 * plane : nullptr, st)) != hipSuccess)
-            return fail_hip(e, "adjoint march");
-        const bool lds = grad_accum_double() && chain_lds_fits(p->grid.nr, p->grid.nz);
-        e = lds ? launch_adj_chain_lds(geo, sh, rays, cot, nblk, go, c0 == 0 ? dO : nullptr, st)
-                : launch_adj_chain(geo, sh, rays, cot, nblk, go, c0 == 0 ? dO : nullptr, st);
-        if (e != hipSuccess)
-            return fail_hip(e, "adjoint chain");
+        for (int q0 = 0; q0 < ny; q0 += band) {
+            const int rows = std::min(band, ny - q0);
+            const int bpix = rows * nx;
+            const size_t pix0 = (size_t)q0 * nx;
+            Geometry gb = geo;
+            gb.ny = rows;
+            gb.yc = 0.5 * ny - q0;
+            Shade sb = sh;
+            sb.o_pix0 = (int64_t)pix0;
+            const size_t tape_b = sizeof(float4) * (size_t)ns * bpix;
+            const size_t rays_b = sizeof(float4) * (size_t)bpix;
+            const size_t ckpt_b = sizeof(float) * (size_t)nseg * nblk * cb * bpix;
+            const size_t cot_b = sizeof(float4) * (size_t)nblk * ns * bpix;
+            char *base = (char *)stream_workspace(st, kWsAdjoint, tape_b + rays_b + ckpt_b + cot_b, &e);
+            if (!base) return fail_hip(e, "adjoint scratch");
+            float4 *tape = (float4 *)base;
+            float4 *rays = (float4 *)(base + tape_b);
+            float *ckpt = (float *)(base + tape_b + rays_b);
+            float4 *cot = (float4 *)(base + tape_b + rays_b + ckpt_b);
+            if ((e = launch_adj_tape(gb, sb, tape, rays, st)) != hipSuccess) return fail_hip(e, "adjoint tape");
+            if ((e = launch_adj_march(cb, kseg, ns, bpix, (int)plane, ch, tape, dl + (size_t)c0 * plane + pix0, ckpt,
+                                      cot, cube_opt ? cube_opt + (size_t)c0 * plane + pix0 : nullptr, st)) != hipSuccess)
+                return fail_hip(e, "adjoint march");
+            float4 *dOc = c0 == 0 ? dO : nullptr;
+            e = lds ? launch_adj_chain_lds(gb, sb, rays, cot, nblk, go, dOc, st)
+                    : launch_adj_chain(gb, sb, rays, cot, nblk, go, dOc, st);
+            if (e != hipSuccess) return fail_hip(e, "adjoint chain");
+        }
     }
     // field accumulators are double or float (option); surfaces always double
     auto field_out = [&](size_t off, float *dst) {

@@ -44,7 +44,7 @@ __global__ __launch_bounds__(256) void march_fwd(Geometry g, Shade s, Channels c
         for (int k = k0; k < k1; ++k) {
             const float t = ((float)k + 0.5f - half) * r.ds;
             const SampleQ sq = shade_sample<NEURAL>(s, ztab, r.px, fmaf(t, r.wy, r.pmy), fmaf(t, r.wz, r.pmz), r.ds,
-                                            (size_t)k * g.nx * g.ny + (size_t)q * g.nx + p);
+                                            o_index(s, k, q * g.nx + p));
 #pragma unroll
             for (int c = 0; c < CB; ++c) {
                 const float d = fmaf(-ch.v[c0 + c], sq.b, sq.a);

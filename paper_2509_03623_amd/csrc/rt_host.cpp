@@ -49,6 +49,7 @@ static int64_t g_opt_thin = 0;
 static int64_t g_opt_ckpt = 0;
 static int64_t g_opt_split = 0;
 static int64_t g_opt_accum = 1;
+static int64_t g_opt_adj_cap = 0;
 
 // Launch shape of the forward march: channels per lane (cb) and lanes per
 // ray (nsplit).  Measured on MI355X: one channel block per pixel is best
@@ -82,6 +83,7 @@ int channel_block_for(int nch, long npix) {
 bool thin_series() { return g_opt_thin != 0; }
 int ckpt_segment_option() { return (int)g_opt_ckpt; }
 bool grad_accum_double() { return g_opt_accum != 0; }
+size_t adjoint_scratch_cap() { return g_opt_adj_cap > 0 ? (size_t)g_opt_adj_cap : kAdjointScratchCap; }
 
 // ---------------------------------------------------------------- validation
 static bool finite(double x) { return std::isfinite(x); }
@@ -165,6 +167,65 @@ static void keep_pool(int dev) {
     }
 }
 
+namespace {
+struct WsKey {
+    int dev;
+    hipStream_t st;
+    int slot;
+    bool operator<(const WsKey &o) const {
+        if (dev != o.dev) return dev < o.dev;
+        if (st != o.st) return st < o.st;
+        return slot < o.slot;
+    }
+};
+struct WsBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+std::mutex g_ws_mu;
+std::map<WsKey, WsBuf> g_ws;
+} // namespace
+
+void *stream_workspace(hipStream_t st, int slot, size_t bytes, hipError_t *err) {
+    *err = hipSuccess;
+    int dev = 0;
+    if ((*err = hipGetDevice(&dev)) != hipSuccess) return nullptr;
+    keep_pool(dev);
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    WsBuf &b = g_ws[{dev, st, slot}];
+    if (b.bytes >= bytes && b.p) return b.p;
+    // grow in 64 MiB steps; the old buffer is released in stream order, after
+    // the work already queued on this stream that may still use it
+    const size_t want = (bytes + (64u << 20) - 1) / (64u << 20) * (64u << 20);
+    if (b.p) {
+        if ((*err = hipFreeAsync(b.p, st)) != hipSuccess) return nullptr;
+        b.p = nullptr;
+        b.bytes = 0;
+    }
+    if ((*err = hipMallocAsync(&b.p, want, st)) != hipSuccess) {
+        b.p = nullptr;
+        return nullptr;
+    }
+    b.bytes = want;
+    return b.p;
+}
+
+void release_stream_workspaces(hipStream_t st) {
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    for (auto it = g_ws.begin(); it != g_ws.end();) {
+        if (it->first.st == st) {
+            int cur = 0;
+            (void)hipGetDevice(&cur);
+            (void)hipSetDevice(it->first.dev);
+            (void)hipFreeAsync(it->second.p, st);
+            (void)hipSetDevice(cur);
+            it = g_ws.erase(it);
+        } else {
+            ++it;
+        }
+    }
+}
+
 rt_status partition_table(const rt_line &l, const float4 **out) {
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
@@ -222,6 +283,8 @@ rt_status build_launch(const rt_problem *p, Geometry *g, Shade *s) {
     g->zc = (gr.zr_max + dzr) * g->rc;
     g->nx = p->cam.nx;
     g->ny = p->cam.ny;
+    g->xc = 0.5 * p->cam.nx;
+    g->yc = 0.5 * p->cam.ny;
     g->nsamp = p->nsamp;
 
     std::memset(s, 0, sizeof *s);
@@ -263,6 +326,8 @@ rt_status build_launch(const rt_problem *p, Geometry *g, Shade *s) {
     s->thin_thr = (float)(0.125 * log2e);
     s->zr_max = (float)gr.zr_max;
     s->mlp_o = nullptr;
+    s->o_plane = (int64_t)p->cam.nx * p->cam.ny;
+    s->o_pix0 = 0;
     return RT_OK;
 }
 
@@ -315,6 +380,10 @@ rt_status rt_set_option(int32_t key, int64_t value) {
     case RT_OPT_GRAD_ACCUM:
         g_opt_accum = value ? 1 : 0;
         return RT_OK;
+    case RT_OPT_ADJ_SCRATCH_CAP:
+        if (value < 0) return fail(RT_EINVAL, "scratch cap must be >= 0");
+        g_opt_adj_cap = value;
+        return RT_OK;
     case RT_OPT_RAY_SPLIT:
         if (value != 0 && value != 1 && value != 2 && value != 4 && value != 8)
             return fail(RT_EINVAL, "ray split must be 0, 1, 2, 4 or 8");
@@ -332,6 +401,7 @@ int64_t rt_get_option(int32_t key) {
     case RT_OPT_CKPT_SEGMENT: return g_opt_ckpt;
     case RT_OPT_RAY_SPLIT: return g_opt_split;
     case RT_OPT_GRAD_ACCUM: return g_opt_accum;
+    case RT_OPT_ADJ_SCRATCH_CAP: return g_opt_adj_cap;
     default: return -1;
     }
 }

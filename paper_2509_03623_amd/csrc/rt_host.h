@@ -13,9 +13,25 @@ rt_status validate(const rt_problem *p);
 rt_status build_launch(const rt_problem *p, Geometry *g, Shade *s);
 int channel_block_for(int nch, long npix);
 void forward_shape(int nch, long npix, int nsamp, int *cb, int *nsplit);
+// channels per lane and samples per checkpoint segment of the reverse march
+void adjoint_shape(int nch, int *cb, int *kseg);
 bool thin_series();
 int ckpt_segment_option();
 bool grad_accum_double();
+
+// Device scratch kept with a stream: the buffer of (current device, stream,
+// slot) is grown on demand with stream-ordered allocation and reused by later
+// calls on that stream, so steady-state calls allocate nothing.  Calls that
+// share a stream must be issued from one host thread at a time.
+void *stream_workspace(hipStream_t st, int slot, size_t bytes, hipError_t *err);
+void release_stream_workspaces(hipStream_t st);
+constexpr int kWsAdjoint = 0, kWsGradAcc = 1;
+// default largest adjoint scratch (tape, checkpoints, cotangents) of one pass
+// over a band of image rows; larger images are processed band by band
+constexpr size_t kAdjointScratchCap = (size_t)8 << 30;
+size_t adjoint_scratch_cap();
+// bytes of adjoint scratch per pixel for nch channels and nsamp samples
+size_t adjoint_bytes_per_pixel(int nch, int nsamp);
 
 rt_status render_cube_mlp(const rt_problem *p, float *cube, hipStream_t st);
 rt_status march_cube(const rt_problem *p, const Geometry &g, const Shade &s, float *cube, hipStream_t st);

@@ -20,7 +20,8 @@ struct Geometry {
     double cpa, spa;         // position-angle rotation
     double si, ci;           // sin / cos inclination
     double rc, zc;           // bounding cylinder radius and half height [au]
-    int32_t nx, ny, nsamp;
+    double xc, yc;           // image centre in pixels from the first column / row of this launch
+    int32_t nx, ny, nsamp;   // pixels of this launch (a band of rows of the image when chunked)
     int32_t pad_;
 };
 
@@ -45,8 +46,14 @@ struct Shade {
     float vsys;              // systemic velocity [km/s]
     float thin_thr;          // dtau (log2 units) below which 1 - e^-dtau uses the series
     float zr_max;            // (z/r) of the top grid row
-    const float4 *mlp_o;     // neural CO layer outputs [nsamp][npix] (o0, o1, o2, -); NULL = grid surfaces
+    const float4 *mlp_o;     // neural CO layer outputs [nsamp][image pixels] (o0, o1, o2, -); NULL = grid surfaces
+    int64_t o_plane, o_pix0; // output of sample k, pixel pix of the launch: mlp_o[k o_plane + o_pix0 + pix]
 };
+
+// index of a launch's (sample, pixel) in the image-wide network outputs
+__device__ __forceinline__ size_t o_index(const Shade &s, int k, int pix) {
+    return (size_t)k * (size_t)s.o_plane + (size_t)s.o_pix0 + (size_t)pix;
+}
 
 struct Channels {
     int32_t n;               // channels in this launch
@@ -121,8 +128,8 @@ struct RaySetup {
 
 __device__ __forceinline__ RaySetup ray_setup(const Geometry &g, int p, int q) {
     RaySetup r;
-    const double X = ((double)p + 0.5 - 0.5 * g.nx) * g.d_pix;
-    const double Y = ((double)q + 0.5 - 0.5 * g.ny) * g.d_pix;
+    const double X = ((double)p + 0.5 - g.xc) * g.d_pix;
+    const double Y = ((double)q + 0.5 - g.yc) * g.d_pix;
     const double xp = g.cpa * X - g.spa * Y;
     const double yp = g.spa * X + g.cpa * Y;
     double lo = -1e300, hi = 1e300;

@@ -100,10 +100,10 @@ uint64_t footprint(const rt_request &r) {
     if (p.mlp) b += 4ull * RT_MLP_PARAMS + 16 * M + (1u << 20);
     if (r.kind == RT_REQ_FWD_ADJ) {
         const int ch = std::min(p.spec.nch, kLaunchChannels);
-        const int cb = ch > 8 ? 16 : 8, kseg = 8;
-        const uint64_t nblk = (ch + cb - 1) / cb, nseg = (p.nsamp + kseg - 1) / kseg;
         b += 2 * cube + 4 * (3 * nn + 2 * nr) + 8 * (3 * nn + 2 * nr);   // target, dl, grads, accumulators
-        b += 16 * M + 16 * npix + 4 * nseg * nblk * cb * npix + 16 * nblk * M;   // tape, rays, checkpoints, cotangents
+        // tape, rays, checkpoints, cotangents of one band of rows
+        const uint64_t row = adjoint_bytes_per_pixel(ch, p.nsamp) * (uint64_t)p.cam.nx;
+        b += std::min<uint64_t>(row * p.cam.ny, std::max<uint64_t>(row, adjoint_scratch_cap() / row * row));
         if (p.mlp) b += 16 * M + 4ull * RT_MLP_PARAMS;
     }
     return b;
@@ -241,9 +241,13 @@ void scheduler(rt_server *sv) {
                     }
                 }
             }
+            // launch without holding the lock, so submissions are not held up
+            // (the batch and the lane belong to this thread until then)
+            lk.unlock();
             rt_status rs = batch.front()->own_stream ? launch_single(L, batch.front()) : launch_batch(sv, L, batch);
             hipError_t e = hipSuccess;
             if (rs == RT_OK) e = hipEventRecord(L.ev, L.st);
+            lk.lock();
             if (rs != RT_OK || e != hipSuccess) {
                 // the stream may hold partial work: wait for it, then fail the requests
                 (void)hipStreamSynchronize(L.st);
@@ -292,6 +296,12 @@ rt_status rt_server_create(const rt_server_cfg *cfg, rt_server **out) {
             return st;
         }
         *L.h_loss = 0.0;
+        // channel velocities of a full batch of up to kLaunchChannels-channel requests
+        rt_status rs = lane_vch_capacity(L, (size_t)cfg->max_slots * kLaunchChannels);
+        if (rs != RT_OK) {
+            rt_server_destroy(sv.release());
+            return rs;
+        }
     }
     rt_server *p = sv.release();
     p->th = std::thread(scheduler, p);
@@ -410,6 +420,7 @@ rt_status rt_server_destroy(rt_server *sv) {
     }
     if (sv->th.joinable()) sv->th.join();
     for (Lane &L : sv->lanes) {
+        if (L.st) release_stream_workspaces(L.st);
         if (L.st) (void)hipStreamSynchronize(L.st);
         if (L.ev) (void)hipEventDestroy(L.ev);
         if (L.st) (void)hipStreamDestroy(L.st);

@@ -97,4 +97,8 @@ def test_options_roundtrip():
     assert lib.rt_set_option(L.RT_OPT_CHANNEL_BLOCK, 12) == L.RT_EINVAL
     assert lib.rt_set_option(L.RT_OPT_CHANNEL_BLOCK, 48) == 0
     assert lib.rt_set_option(L.RT_OPT_CHANNEL_BLOCK, old) == 0
+    assert lib.rt_set_option(L.RT_OPT_ADJ_SCRATCH_CAP, -1) == L.RT_EINVAL
+    assert lib.rt_set_option(L.RT_OPT_ADJ_SCRATCH_CAP, 1 << 20) == 0
+    assert lib.rt_get_option(L.RT_OPT_ADJ_SCRATCH_CAP) == 1 << 20
+    assert lib.rt_set_option(L.RT_OPT_ADJ_SCRATCH_CAP, 0) == 0
     assert lib.rt_set_option(999, 1) == L.RT_EINVAL

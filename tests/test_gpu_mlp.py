@@ -100,3 +100,22 @@ def test_network_surface_gradients_are_zero():
     g = rt.render_adjoint(sc, torch.ones_like(cube), want=("z_lo_au", "z_up_au"))
     torch.cuda.synchronize()
     assert float(g["z_lo_au"].abs().max()) == 0.0 and float(g["z_up_au"].abs().max()) == 0.0
+
+
+def test_network_adjoint_in_row_bands():
+    """The network adjoint differentiated in bands of one row equals the
+    single-pass adjoint (network outputs indexed image-wide in every band)."""
+    rt = _rt()
+    from paper_2509_03623_amd import _lib as L
+    prob = mlp_problem(nx=14, ny=11, nch=9, nsamp=40)
+    cot = np.random.Generator(np.random.PCG64(7)).standard_normal((9, 11, 14))
+    whole = _grads(prob, rt.RT_MLP_FP32, cot)
+    rt.set_option(L.RT_OPT_ADJ_SCRATCH_CAP, 1)
+    try:
+        banded = _grads(prob, rt.RT_MLP_FP32, cot)
+    finally:
+        rt.set_option(L.RT_OPT_ADJ_SCRATCH_CAP, 0)
+    for k in whole:
+        scale = np.abs(whole[k]).max()
+        assert scale > 0, k
+        assert np.abs(banded[k] - whole[k]).max() <= 1e-5 * scale, k
