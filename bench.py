@@ -4,8 +4,10 @@ A step is one full-size forward render: 512 x 512 pixels x 64 channels x 512
 samples per ray through a 256 x 128 (r, z/r) disk (seeded parametric disk
 with three density gaps), inputs resident in HBM.  Prints one JSON line with
 ray-samples/s, the roofline of the dominant kernel (the forward march), the
-forward+adjoint rate on the 256 x 256 x 48 x 256 case, and the FP64 oracle
-timed on a bounded sample of the same workload.
+forward rate over eight seeded disks of the family, the forward+adjoint rate
+at 256 x 256 x 48 x 256 and at full size, the served stream (latency and
+capacity against one request at a time), and the FP64 oracle timed on a
+bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -34,6 +36,10 @@ LOOP_FLOP, LOOP_VALU, LOOP_TRANS = 11, 7, 2
 # a lane: position, grid fetch and bilinear interpolation, density, CO mask,
 # partition function, populations, source function, width, projected velocity.
 SHADE_FLOP, SHADE_VALU, SHADE_TRANS = 150, 100, 14
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def algorithmic(nch: int, cb: int):
@@ -92,8 +98,10 @@ def main():
     ap.add_argument("--seed", type=int, default=2000)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-disks", action="store_true", help="skip the forward rate over eight seeded disks")
+    ap.add_argument("--no-mlp", action="store_true", help="skip the neural CO layer leg")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--serve-seconds", type=float, default=8.0,
+    ap.add_argument("--serve-seconds", type=float, default=10.0,
                     help="length of the Poisson request trace (200 req/s) for the serving leg; 0 = skip")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -154,129 +162,206 @@ def main():
                      "kernel": "march_fwd", "kernel_ms": kern_ms,
                      "flop_per_ray_sample": flop, "issue_slots_per_ray_sample": slots},
     }
+    log(f"forward {ms_per_step:.3f} ms/step, {value:.3e} ray-samples/s")
+    if not args.no_disks:
+        log("forward over eight disks")
+        out["disks"] = bench_disks(rt, synth, dev, range(2000, 2008), max(5, args.steps // 2))
+    if not args.no_mlp:
+        log("neural CO layer")
+        out["neural"] = bench_mlp(rt, synth, dev, args)
     if not args.no_adjoint:
+        log("forward + adjoint")
         try:
             out["fwd_adjoint"] = bench_adjoint(rt, synth, dev, args)
         except rt.RtError as e:
             out["fwd_adjoint"] = {"error": str(e)}
     if args.serve_seconds > 0:
-        out["served"], out["serial"] = bench_serving(rt, synth, dev, args.serve_seconds)
-        out["served_vs_serial_throughput"] = out["served"]["ray_samples_per_s"] / out["serial"]["ray_samples_per_s"]
+        log(f"served stream ({args.serve_seconds:g} s trace, then the serial replay and the saturated runs)")
+        out["served"], out["serial"], out["saturated"] = bench_serving(rt, synth, dev, args.serve_seconds)
+        out["served_vs_serial_throughput"] = (out["saturated"]["served_ray_samples_per_s"] /
+                                              out["saturated"]["serial_ray_samples_per_s"])
     if not args.no_cpu:
+        log("oracle on the host cores")
         out["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 
 def bench_adjoint(rt, synth, dev, args):
-    """Forward + adjoint on the 256 x 256 x 48 x 256 case (L2 loss)."""
+    """Forward + adjoint (L2 loss): the 256 x 256 x 48 x 256 gradient case and
+    the full-size 512 x 512 x 64 x 512 render."""
     import torch
-    prob = synth.config3()
-    sc = rt.scene_from_problem(prob, device=dev)
-    tgt = rt.render(sc.replace(z_up_au=sc.z_up_au * 1.05))
-    steps = max(3, args.steps // 2)
+    out = {}
+    for name, prob in (("256x256x48ch_256s", synth.config3()), ("512x512x64ch_512s", synth.config2(args.seed))):
+        sc = rt.scene_from_problem(prob, device=dev)
+        tgt = rt.render(sc.replace(z_up_au=sc.z_up_au * 1.05))
+        steps = max(3, args.steps // 2)
 
-    def step():
-        cube = rt.render(sc)
-        dl = 2.0 * (cube - tgt)
-        return rt.render_adjoint(sc, dl, want=("ln_nh2", "temp_k", "z_lo_au", "z_up_au"))
+        def step():
+            cube = rt.render(sc)
+            dl = 2.0 * (cube - tgt)
+            return rt.render_adjoint(sc, dl, want=("ln_nh2", "temp_k", "z_lo_au", "z_up_au"))
 
-    for _ in range(max(1, args.warmup // 2)):
-        step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        step()
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / steps
-    return {"ray_samples_per_s": sc.ray_samples / dt, "ms_per_step": dt * 1e3,
-            "workload": "forward + adjoint 256x256 px x 48 ch x 256 samples, L2 loss"}
+        for _ in range(max(1, args.warmup // 2)):
+            step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        out[name] = {"ray_samples_per_s": sc.ray_samples / dt, "ms_per_step": dt * 1e3, "steps": steps,
+                     "grads": "ln n_H2, T, z_lo, z_up"}
+    return out
 
 
-def bench_serving(rt, synth, dev, seconds, rate=200.0, seed=5, pool=16):
-    """Poisson request stream (rate req/s for `seconds`): each request a disk
-    of the full-size family (one of `pool` pre-generated seeded disks) with
-    pixels in {64..512}^2, channels in {16..128}, 128-512 samples, 25% with
-    forward+adjoint gradients of an L2 loss.  Served by the continuous-
-    batching server, then replayed one request at a time on the same trace."""
+def bench_mlp(rt, synth, dev, args):
+    """Neural CO layer at 256 x 256 x 32 x 256: the network evaluated at every
+    pixel-sample on the matrix cores, then the march; forward and
+    forward + adjoint to the network weights, BF16 and FP32 paths."""
+    import torch
+    prob = synth.config4()
+    out = {}
+    for name, prec in (("bf16", rt.RT_MLP_BF16), ("fp32", rt.RT_MLP_FP32)):
+        sc = rt.scene_from_problem(prob, device=dev, mlp_precision=prec)
+        cube = torch.empty(sc.nch, sc.ny, sc.nx, device=dev)
+        dl = torch.ones_like(cube)
+        steps = max(3, args.steps // 4)
+        res = {}
+        for leg in ("forward", "forward_adjoint"):
+            def step():
+                rt.render(sc, out=cube)
+                if leg == "forward_adjoint":
+                    rt.render_adjoint(sc, dl, want=("temp_k", "mlp_w"))
+            step()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                step()
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / steps
+            res[leg] = {"ms": dt * 1e3, "ray_samples_per_s": sc.ray_samples / dt,
+                        "network_evals_per_s": sc.nx * sc.ny * sc.nsamp / dt}
+        out[name] = res
+    return out
+
+
+def bench_disks(rt, synth, dev, seeds, steps):
+    """Forward ray-samples/s on each full-size disk (seeded M*, inclination,
+    temperature index and gaps): the spread over disk geometry."""
+    import numpy as np
+    import torch
+    rates = {}
+    for sd in seeds:
+        prob = synth.config2(sd)
+        sc = rt.scene_from_problem(prob, device=dev)
+        cube = torch.empty(sc.nch, sc.ny, sc.nx, device=dev)
+        rt.render(sc, out=cube)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            rt.render(sc, out=cube)
+        torch.cuda.synchronize()
+        rates[str(sd)] = sc.ray_samples * steps / (time.perf_counter() - t0)
+    v = np.array(list(rates.values()))
+    return {"median_ray_samples_per_s": float(np.median(v)), "min": float(v.min()), "max": float(v.max()),
+            "per_seed": rates}
+
+
+def bench_serving(rt, synth, dev, seconds, rate=200.0, seed=5, pool=16, saturated=600):
+    """Served stream of the full-size disk family: each request one of `pool`
+    pre-generated seeded disks with pixels in {64..512}^2, channels in
+    {16..128}, 128-512 samples, 25% with forward+adjoint gradients of an L2
+    loss.
+
+    Open loop: Poisson arrivals at `rate` req/s for `seconds`, served by the
+    continuous-batching server, then replayed one request at a time (FIFO) on
+    the same arrival times: latency p50/p99 and ray-samples per second of
+    makespan.  Saturated: the first `saturated` requests of the trace all
+    submitted at once, served vs one at a time: the capacity of each."""
     import numpy as np
     import torch
     trace = synth.make_trace(rate_hz=rate, duration_s=seconds, seed=seed)
     bases = [rt.scene_from_problem(synth.config2(3000 + i, nx=64, ny=64, nch=16, nsamp=128), device=dev)
              for i in range(pool)]
-    targets, grads = {}, {}
-
-    def request(r):
+    keys = ("ln_nh2", "temp_k", "z_lo_au", "z_up_au")
+    targets, reqs = {}, []
+    for r in trace:
         b = bases[r["disk_seed"] % pool]
         nch = r["nch"]
         v = (np.arange(nch) - (nch - 1) / 2.0) * 0.1
         sc = b.replace(nx=r["nx"], ny=r["ny"], v_kms=v, nsamp=r["nsamp"])
-        key = (r["nch"], r["ny"], r["nx"])
+        key = (nch, r["ny"], r["nx"])
         if r["grad"] and key not in targets:
             targets[key] = torch.zeros(key, device=dev)
-        return sc, key
-
-    reqs = [request(r) for r in trace]
-    # every gradient request writes gradients of its own
-    for i, r in enumerate(trace):
-        if r["grad"]:
-            b = bases[r["disk_seed"] % pool]
-            grads[i] = {k: torch.empty_like(getattr(b, k)) for k in ("ln_nh2", "temp_k", "z_lo_au", "z_up_au")}
+        # every gradient request writes gradients of its own
+        g = {k: torch.empty_like(getattr(b, k)) for k in keys} if r["grad"] else None
+        reqs.append((sc, key, g))
     torch.cuda.synchronize()
-    total_rs = sum(sc.ray_samples for sc, _ in reqs)
-    ngrad = sum(1 for r in trace if r["grad"])
 
-    # served
-    lat = []
-    with rt.Server(hbm_budget_bytes=96 << 30, max_slots=64, streams=4) as sv:
-        sc0, _ = reqs[0]
-        sv.wait(sv.submit(sc0, torch.empty(sc0.nch, sc0.ny, sc0.nx, device=dev)))
-        outstanding = {}
-        t0 = time.perf_counter()
-        for i, (r, (sc, key)) in enumerate(zip(trace, reqs)):
-            while time.perf_counter() - t0 < r["t_arrive"]:
-                time.sleep(2e-4)
-            cube = torch.empty(key, device=dev)
-            if r["grad"]:
-                t = sv.submit(sc, cube, target=targets[key], grads=grads[i])
-            else:
-                t = sv.submit(sc, cube)
-            outstanding[t] = cube
-            for tk in [tk for tk in outstanding if sv.poll(tk)["state"] in ("done", "failed")]:
-                outstanding.pop(tk)
-        infos = []
-        for tk in list(sv._keep.keys()):
-            sv.wait(tk, timeout_s=120)
-        # every ticket's timing
-        for tk in range(2, 2 + len(trace)):
-            infos.append(sv.poll(tk))
-    t_sub = np.array([i["t_submit_ns"] for i in infos], dtype=np.float64)
-    t_done = np.array([i["t_done_ns"] for i in infos], dtype=np.float64)
-    lat = (t_done - t_sub) * 1e-6
-    makespan = (t_done.max() - t_sub.min()) * 1e-9
-    served = {"ray_samples_per_s": total_rs / makespan, "p50_ms": float(np.percentile(lat, 50)),
-              "p99_ms": float(np.percentile(lat, 99)), "requests": len(trace), "grad_requests": ngrad,
-              "makespan_s": makespan, "failed": int(sum(1 for i in infos if i["state"] != "done")),
-              "trace": f"Poisson {rate:g} req/s for {seconds:g} s, seed {seed}"}
+    def submit(sv, i):
+        sc, key, g = reqs[i]
+        cube = torch.empty(key, device=dev)
+        if g is not None:
+            return sv.submit(sc, cube, target=targets[key], grads=g)
+        return sv.submit(sc, cube)
 
-    # serial: the same trace, one request at a time in arrival order
-    lat_s = []
-    t0 = time.perf_counter()
-    first = None
-    for r, (sc, key) in zip(trace, reqs):
-        now = time.perf_counter() - t0
-        if now < r["t_arrive"]:
-            time.sleep(r["t_arrive"] - now)
-        start = max(time.perf_counter() - t0, r["t_arrive"])
-        first = start if first is None else first
+    def serial_one(i):
+        sc, key, g = reqs[i]
         cube = rt.render(sc)
-        if r["grad"]:
-            rt.render_adjoint(sc, 2.0 * (cube - targets[key]), want=("ln_nh2", "temp_k", "z_lo_au", "z_up_au"))
+        if g is not None:
+            rt.render_adjoint(sc, 2.0 * (cube - targets[key]), want=keys)
         torch.cuda.synchronize()
-        lat_s.append((time.perf_counter() - t0 - r["t_arrive"]) * 1e3)
-    span = time.perf_counter() - t0 - trace[0]["t_arrive"]
-    serial = {"ray_samples_per_s": total_rs / span, "p50_ms": float(np.percentile(lat_s, 50)),
-              "p99_ms": float(np.percentile(lat_s, 99)), "makespan_s": span}
-    return served, serial
+
+    def served_run(order, arrivals):
+        with rt.Server(hbm_budget_bytes=96 << 30, max_slots=64, streams=4) as sv:
+            sv.wait(submit(sv, order[0]))
+            t0 = time.perf_counter()
+            tickets = []
+            for i, ta in zip(order, arrivals):
+                while time.perf_counter() - t0 < ta:
+                    time.sleep(2e-4)
+                tickets.append(submit(sv, i))
+            infos = [sv.wait(t, timeout_s=300) for t in tickets]
+        t_sub = np.array([x["t_submit_ns"] for x in infos], dtype=np.float64)
+        t_done = np.array([x["t_done_ns"] for x in infos], dtype=np.float64)
+        return (t_done - t_sub) * 1e-6, (t_done.max() - t_sub.min()) * 1e-9, sum(x["state"] != "done" for x in infos)
+
+    def serial_run(order, arrivals):
+        lat = []
+        t0 = time.perf_counter()
+        for i, ta in zip(order, arrivals):
+            now = time.perf_counter() - t0
+            if now < ta:
+                time.sleep(ta - now)
+            serial_one(i)
+            lat.append((time.perf_counter() - t0 - ta) * 1e3)
+        return np.array(lat), time.perf_counter() - t0 - arrivals[0]
+
+    for i in range(min(len(reqs), 32)):      # warm-up of the direct path
+        serial_one(i)
+    order = list(range(len(trace)))
+    arrivals = [r["t_arrive"] - trace[0]["t_arrive"] for r in trace]
+    total_rs = sum(sc.ray_samples for sc, _, _ in reqs)
+    ngrad = sum(1 for r in trace if r["grad"])
+    lat, span, failed = served_run(order, arrivals)
+    served = {"ray_samples_per_s": total_rs / span, "p50_ms": float(np.percentile(lat, 50)),
+              "p99_ms": float(np.percentile(lat, 99)), "requests": len(trace), "grad_requests": ngrad,
+              "makespan_s": span, "failed": int(failed),
+              "trace": f"Poisson {rate:g} req/s for {seconds:g} s, seed {seed}"}
+    lat_s, span_s = serial_run(order, arrivals)
+    serial = {"ray_samples_per_s": total_rs / span_s, "p50_ms": float(np.percentile(lat_s, 50)),
+              "p99_ms": float(np.percentile(lat_s, 99)), "makespan_s": span_s}
+    # saturated: every request of the head of the trace at time 0
+    head = order[:min(saturated, len(order))]
+    rs_head = sum(reqs[i][0].ray_samples for i in head)
+    zeros = [0.0] * len(head)
+    lat_h, span_h, failed_h = served_run(head, zeros)
+    _, span_hs = serial_run(head, zeros)
+    sat = {"requests": len(head), "grad_requests": sum(1 for i in head if trace[i]["grad"]),
+           "served_ray_samples_per_s": rs_head / span_h, "serial_ray_samples_per_s": rs_head / span_hs,
+           "served_makespan_s": span_h, "serial_makespan_s": span_hs, "served_p99_ms": float(np.percentile(lat_h, 99)),
+           "failed": int(failed_h)}
+    return served, serial, sat
 
 
 if __name__ == "__main__":
