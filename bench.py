@@ -38,6 +38,35 @@ LOOP_FLOP, LOOP_VALU, LOOP_TRANS = 11, 7, 2
 SHADE_FLOP, SHADE_VALU, SHADE_TRANS = 150, 100, 14
 
 
+# HBM traffic of one forward launch on the full-size render of disk 2000,
+# from two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch)
+# of `bench.py --copy-probe`, each scaled by what the same counter reads for
+# a 1 GiB device-to-device copy (FETCH_SIZE 524 308 KiB -> x2.0000,
+# WRITE_SIZE 1 048 576 KiB -> x1.0000).  Valid only for the kernel sources it
+# was taken on: the hash of those files is checked at run time.
+FWD_TRAFFIC = {"sources": ("paper_2509_03623_amd/csrc/rt_forward.hip", "paper_2509_03623_amd/csrc/rt_kernels.h",
+                           "paper_2509_03623_amd/csrc/rt_launch.h"),
+               "sha256": "5e3d79517883a52699726ac6582c9a5035d03cc2d44f530b04d55d915fab5b2e",
+               "fetch_kib": 1237.3, "fetch_scale": 1048576 / 524308.2,
+               "write_kib": 65536.0, "write_scale": 1.0}
+
+
+def measured_traffic(seed: int):
+    """HBM bytes per forward launch, or None if the kernel has changed since
+    the counters were taken (or the workload differs)."""
+    import hashlib
+    if seed != 2000:
+        return None
+    h = hashlib.sha256()
+    for f in FWD_TRAFFIC["sources"]:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest() != FWD_TRAFFIC["sha256"]:
+        return None
+    return 1024.0 * (FWD_TRAFFIC["fetch_kib"] * FWD_TRAFFIC["fetch_scale"] +
+                     FWD_TRAFFIC["write_kib"] * FWD_TRAFFIC["write_scale"])
+
+
 def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -100,6 +129,9 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-disks", action="store_true", help="skip the forward rate over eight seeded disks")
     ap.add_argument("--no-mlp", action="store_true", help="skip the neural CO layer leg")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="first copy 1 GiB device to device three times (a kernel of known traffic, to scale "
+                         "hardware byte counters)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--serve-seconds", type=float, default=10.0,
                     help="length of the Poisson request trace (200 req/s) for the serving leg; 0 = skip")
@@ -117,6 +149,13 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.copy_probe:
+        src = torch.ones(1 << 28, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     prob = synth.config2(args.seed)
     sc = rt.scene_from_problem(prob, device=dev)
     cube = torch.empty(sc.nch, sc.ny, sc.nx, device=dev)
@@ -158,9 +197,10 @@ def main():
                                f"seeded disk {args.seed} (3 gaps, incl {prob.camera.incl_deg:.1f} deg)",
                    "global_batch": 1, "ray_samples": rs, "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None,
+                     "frac": achieved / peak, "traffic": measured_traffic(args.seed),
                      "kernel": "march_fwd", "kernel_ms": kern_ms,
-                     "flop_per_ray_sample": flop, "issue_slots_per_ray_sample": slots},
+                     "flop_per_ray_sample": flop, "issue_slots_per_ray_sample": slots,
+                     "hbm_bytes_algorithmic": 4 * sc.nch * sc.nx * sc.ny + 4 * (3 * sc.nr * sc.nz + 2 * sc.nr)},
     }
     log(f"forward {ms_per_step:.3f} ms/step, {value:.3e} ray-samples/s")
     if not args.no_disks:
