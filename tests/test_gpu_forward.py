@@ -147,3 +147,15 @@ def test_full_size_sampled_pixels():
     print("config2 sampled max|dI|/peak(sample) =", err)
     assert ref.max() > 0
     assert err <= TOL
+
+
+def test_paper_fixed_parameter_preset():
+    """The HD 163296 preset of the paper's fixed-parameter table (PA 312 deg,
+    v_LSR 5.76 km/s, 47.5 deg, 122 pc) at PA 312 and PA 132: GPU vs oracle,
+    and the 180 deg turn between them."""
+    import test_golden_preset as gp
+    a_ref = oracle.render(gp.preset())
+    a = gpu_cube(gp.preset())
+    b = gpu_cube(gp.preset(pa=132.0))
+    assert rel_err(a, a_ref) <= TOL
+    assert np.abs(b - a[:, ::-1, ::-1]).max() <= TOL * a_ref.max()
