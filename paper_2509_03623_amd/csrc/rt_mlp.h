@@ -16,6 +16,10 @@ struct MlpDev {
     const float *W5, *b5;
     int off[5];
     float freq[16];
+    // BF16 only: the hidden layers as the A operand of the transposed product
+    // (output neurons as rows), rows padded for LDS, input order of layers
+    // 1..3 permuted to the accumulator layout of the layer before
+    const void *Wr;
 };
 
 size_t mlp_prep_bytes(int precision);

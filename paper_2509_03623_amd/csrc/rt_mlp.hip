@@ -12,6 +12,16 @@
 //   straight from the prepared layout.  Bias + SiLU are fused on the
 //   accumulators.  T = bf16 (v_mfma_f32_16x16x32_bf16) or float
 //   (v_mfma_f32_16x16x4f32), FP32 accumulation in both.
+// mlp_fwd_rr (BF16): persistent workgroups holding all hidden weights in LDS;
+//   each wave evaluates 64 points at a time with the transposed product
+//   Z^T = W H^T, output neurons as MFMA rows and points as columns.  The
+//   accumulator of a 16-neuron output tile leaves every lane with 4
+//   consecutive neurons of one point; two such tiles are exactly the 8
+//   operand values a lane supplies for one 32-deep K chunk of the next layer,
+//   once that layer's input order is permuted to match (done when the
+//   weights are prepared).  Activations therefore never leave registers; the
+//   output layer is evaluated in FP32 on the VALU and reduced across the
+//   four lane groups by shuffles.
 // mlp_bwd<T, P>: persistent workgroups; each recomputes the forward of its
 //   tiles (keeping pre-activations and transposed activations in LDS),
 //   backpropagates dL/do through the layers on MFMA, and accumulates the
@@ -175,6 +185,190 @@ __global__ __launch_bounds__(512) void mlp_fwd(Geometry g, Shade s, MlpDev w, si
     tile_forward<T, P, false>(L, g, s, w, (size_t)blockIdx.x * P, M, out);
 }
 
+// ---------------------------------------------------------------- register-resident BF16 forward
+constexpr int kRrRow0 = kF + 8;        // padded row of layer 0 (bf16 elements)
+constexpr int kRrRow = kW + 8;         // padded row of layers 1..3
+// 16-point column tiles per wave and lanes per workgroup (one workgroup per
+// CU, the weights filling most of its LDS); 4 x 512 measured fastest of
+// 2 x 1024, 2 x 768 and 4 x 512
+constexpr int kRrTiles = 4;
+constexpr int kRrThreads = 512;
+constexpr size_t kRrWeightElems = (size_t)kW * kRrRow0 + 3 * (size_t)kW * kRrRow;
+constexpr size_t kRrLds = kRrWeightElems * 2 + 4 * (4 * kW) + 4 * (3 * kW) + 16;
+
+// input slot s of a 32-deep K chunk -> neuron of the previous layer: lane
+// group g holds slots 8g..8g+7 = neurons 4g..4g+3 of the chunk's first
+// 16-neuron output tile and 4g..4g+3 of its second
+__host__ __device__ constexpr int rr_perm(int s) {
+    return (s & ~31) + 16 * ((s & 7) >> 2) + 4 * ((s >> 3) & 3) + (s & 3);
+}
+
+// Layer 0 is scaled by log2(e) so that its pre-activation comes out as
+// log2(e) z; layers 1..3 take log2(e) SiLU(z) as input and need no scale.
+__global__ void mlp_prep_rr(const float *__restrict__ flat, MlpDev w) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    __bf16 *Wr = (__bf16 *)w.Wr;
+    if (i < kW * kRrRow0) {
+        const int o = i / kRrRow0, k = i - o * kRrRow0;
+        Wr[i] = (__bf16)(k < kF ? kLog2E * flat[w.off[0] + o * kF + k] : 0.0f);
+    }
+    for (int l = 1; l < 4; ++l) {
+        if (i < kW * kRrRow) {
+            const int o = i / kRrRow, k = i - o * kRrRow;
+            Wr[(size_t)kW * kRrRow0 + (size_t)(l - 1) * kW * kRrRow + i] =
+                (__bf16)(k < kW ? flat[w.off[l] + o * kW + rr_perm(k)] : 0.0f);
+        }
+    }
+}
+
+// One hidden layer of the register-resident forward for the NP column tiles
+// of a wave: z' = W h' + b' (the weights and biases carry the log2(e) scale
+// of the prepared layout, so z' = log2(e) z), h' = z' sigma(z) -- i.e.
+// log2(e) SiLU(z), the scale being absorbed by the next layer's prepared
+// weights.  The accumulators start from the biases.  The last layer feeds
+// the FP32 output layer instead of the next operands.
+template <int NP>
+__device__ __forceinline__ void rr_layer(const bf16x8 (&hin)[4][NP], bf16x8 (&hout)[4][NP], float (&o)[3][NP],
+                                         const __bf16 *sW, const float *sB, const float *sW5, int l, int lg, int lc,
+                                         bool last) {
+    typedef MM<__bf16> mm;
+    const int nk = l == 0 ? kF / 32 : kW / 32;
+    const int row = l == 0 ? kRrRow0 : kRrRow;
+    const __bf16 *Wl = sW + (l == 0 ? 0 : (size_t)kW * kRrRow0 + (size_t)(l - 1) * kW * kRrRow);
+    const float *bl = sB + l * kW;
+#pragma unroll
+    for (int cp = 0; cp < 4; ++cp) {           // output tiles 2cp, 2cp+1
+        floatx4 acc[2][NP];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const floatx4 b4 = *(const floatx4 *)(bl + 32 * cp + 16 * h + 4 * lg);
+#pragma unroll
+            for (int tp = 0; tp < NP; ++tp) acc[h][tp] = b4;
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            if (c >= nk) break;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const bf16x8 a = *(const bf16x8 *)(Wl + (size_t)(32 * cp + 16 * h + lc) * row + 32 * c + 8 * lg);
+#pragma unroll
+                for (int tp = 0; tp < NP; ++tp) acc[h][tp] = mm::mfma(a, hin[c][tp], acc[h][tp]);
+            }
+        }
+        if (!last) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int tp = 0; tp < NP; ++tp)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const float z = acc[h][tp][i];
+                        hout[cp][tp][4 * h + i] = (__bf16)(z * frcp(1.0f + fexp2(-z)));
+                    }
+        } else {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int n = 32 * cp + 16 * h + 4 * lg;
+                const floatx4 w0 = *(const floatx4 *)(sW5 + n), w1 = *(const floatx4 *)(sW5 + kW + n),
+                              w2 = *(const floatx4 *)(sW5 + 2 * kW + n);
+#pragma unroll
+                for (int tp = 0; tp < NP; ++tp)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const float z = acc[h][tp][i];
+                        const float hv = z * frcp(1.0f + fexp2(-z));
+                        o[0][tp] = fmaf(hv, w0[i], o[0][tp]);
+                        o[1][tp] = fmaf(hv, w1[i], o[1][tp]);
+                        o[2][tp] = fmaf(hv, w2[i], o[2][tp]);
+                    }
+            }
+        }
+    }
+}
+
+template <int NP, int NT>
+__global__ __launch_bounds__(NT) void mlp_fwd_rr(Geometry g, Shade s, MlpDev w, size_t M, float4 *__restrict__ out) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char rr_lds[];
+    __bf16 *sW = (__bf16 *)rr_lds;                                  // layer 0, then layers 1..3
+    float *sB = (float *)(rr_lds + kRrWeightElems * 2);             // [4][128]
+    float *sW5 = sB + 4 * kW;                                       // [3][128]
+    float *sB5 = sW5 + 3 * kW;                                      // [3]
+    constexpr int PTS = NT / 64 * NP * 16;                          // points per workgroup pass
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int lg = lane >> 4, lc = lane & 15;
+    {
+        const uint4 *src = (const uint4 *)w.Wr;
+        uint4 *dst = (uint4 *)sW;
+        for (size_t i = tid; i < kRrWeightElems / 8; i += NT) dst[i] = src[i];
+        for (int i = tid; i < 4 * kW; i += NT) sB[i] = kLog2E * w.b[i / kW][i % kW];
+        for (int i = tid; i < 3 * kW; i += NT) sW5[i] = kLn2 * w.W5[i];
+        if (tid < 3) sB5[tid] = w.b5[tid];
+    }
+    __syncthreads();
+    typedef MM<__bf16> mm;
+    for (size_t base = (size_t)blockIdx.x * PTS; base < M; base += (size_t)gridDim.x * PTS) {
+        const size_t mw = base + (size_t)wv * (NP * 16);     // this wave's points
+        float rh = 0.0f, zh = 0.0f;
+        if (lane < NP * 16 && mw + lane < M) point_coords(g, s, mw + lane, &rh, &zh);
+        // layer-0 operands: features of chunk c (0: r, 1: z); lane group g
+        // supplies slots 8g..8g+7 = sin (g < 2) or cos (g >= 2) of
+        // frequencies 8 (g & 1) .. 8 (g & 1) + 7.  Lanes g and g ^ 2 share
+        // the work: each evaluates four frequencies (hardware sine and cosine
+        // of the phase reduced to one period) and passes the partner the half
+        // it needs.
+        bf16x8 hin[4][NP];
+        const int fb = 8 * (lg & 1) + (lg < 2 ? 0 : 4);
+#pragma unroll
+        for (int tp = 0; tp < NP; ++tp) {
+            const float cr = __shfl(rh, tp * 16 + lc), cz = __shfl(zh, tp * 16 + lc);
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                float own[4], sent[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    // sin(pi f x) = sin(2 pi t) with t = (f x mod 2) / 2 in [0, 1)
+                    const float x = w.freq[fb + q] * (c == 0 ? cr : cz);
+                    const float t = 0.5f * (x - 2.0f * floorf(0.5f * x));
+                    const float sv = __builtin_amdgcn_sinf(t), cv = __builtin_amdgcn_cosf(t);
+                    own[q] = lg < 2 ? sv : cv;
+                    sent[q] = lg < 2 ? cv : sv;
+                }
+                bf16x8 f;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const float r = __shfl_xor(sent[q], 32);
+                    f[q] = (__bf16)(lg < 2 ? own[q] : r);
+                    f[4 + q] = (__bf16)(lg < 2 ? r : own[q]);
+                }
+                hin[c][tp] = f;
+            }
+        }
+        float o[3][NP];
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+#pragma unroll
+            for (int tp = 0; tp < NP; ++tp) o[j][tp] = 0.0f;
+        bf16x8 hb[4][NP];
+        // layers in pairs, activations ping-ponging between hin and hb
+#pragma unroll 1
+        for (int lp = 0; lp < 2; ++lp) {
+            rr_layer<NP>(hin, hb, o, sW, sB, sW5, 2 * lp, lg, lc, false);
+            rr_layer<NP>(hb, hin, o, sW, sB, sW5, 2 * lp + 1, lg, lc, lp == 1);
+        }
+        // sum the four lane groups' partial outputs; group 0 writes
+#pragma unroll
+        for (int tp = 0; tp < NP; ++tp) {
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                o[j][tp] += __shfl_xor(o[j][tp], 16);
+                o[j][tp] += __shfl_xor(o[j][tp], 32);
+            }
+            const size_t m = mw + (size_t)tp * 16 + lc;
+            if (lg == 0 && m < M) out[m] = make_float4(o[0][tp] + sB5[0], o[1][tp] + sB5[1], o[2][tp] + sB5[2], 0.0f);
+        }
+    }
+}
+
 template <typename T, int P>
 __global__ __launch_bounds__(512) void mlp_bwd(Geometry g, Shade s, MlpDev w, size_t M, const float4 *__restrict__ dO,
                                                float *__restrict__ dW) {
@@ -316,6 +510,7 @@ size_t mlp_prep_bytes(int precision) {
     const size_t es = precision == RT_MLP_BF16 ? 2 : 4;
     size_t n = 0;
     for (int l = 0; l < 4; ++l) n += 2 * es * (size_t)kW * kLayerIn[l] + 4 * kW;
+    if (precision == RT_MLP_BF16) n += 2 * kRrWeightElems + 256;
     return n + 4 * (3 * kW + 3) + 256 * 8;
 }
 
@@ -334,11 +529,14 @@ hipError_t mlp_prepare(const float *flat, int precision, void *buf, MlpDev *w, h
     w->off[4] = off;
     w->W5 = (const float *)take(4 * 3 * kW);
     w->b5 = (const float *)take(4 * 3);
+    w->Wr = precision == RT_MLP_BF16 ? take(2 * kRrWeightElems) : nullptr;
     for (int q = 0; q < 16; ++q) w->freq[q] = (float)std::exp2(3.0 * q / 15.0);
     const int n = kW * kW;
-    if (precision == RT_MLP_BF16)
+    if (precision == RT_MLP_BF16) {
         hipLaunchKernelGGL(mlp_prep<__bf16>, dim3((n + 255) / 256), dim3(256), 0, st, flat, *w);
-    else
+        const int nr = kW * kRrRow;
+        hipLaunchKernelGGL(mlp_prep_rr, dim3((nr + 255) / 256), dim3(256), 0, st, flat, *w);
+    } else
         hipLaunchKernelGGL(mlp_prep<float>, dim3((n + 255) / 256), dim3(256), 0, st, flat, *w);
     return hipGetLastError();
 }
@@ -346,8 +544,17 @@ hipError_t mlp_prepare(const float *flat, int precision, void *buf, MlpDev *w, h
 hipError_t mlp_forward(const Geometry &g, const Shade &s, const MlpDev &w, int precision, size_t M, float4 *out,
                        hipStream_t st) {
     if (precision == RT_MLP_BF16) {
-        constexpr int P = 64;
-        hipLaunchKernelGGL((mlp_fwd<__bf16, P>), dim3((unsigned)((M + P - 1) / P)), dim3(512), 0, st, g, s, w, M, out);
+        int dev = 0, ncu = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+        constexpr int NP = kRrTiles, NT = kRrThreads;
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute((const void *)mlp_fwd_rr<NP, NT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)kRrLds);
+        if (e != hipSuccess) return e;
+        constexpr size_t pts = NT / 64 * NP * 16;
+        const unsigned grid = (unsigned)std::min<size_t>((M + pts - 1) / pts, (size_t)ncu);
+        hipLaunchKernelGGL((mlp_fwd_rr<NP, NT>), dim3(grid), dim3(NT), kRrLds, st, g, s, w, M, out);
     } else {
         constexpr int P = 32;
         hipLaunchKernelGGL((mlp_fwd<float, P>), dim3((unsigned)((M + P - 1) / P)), dim3(512), 0, st, g, s, w, M, out);
