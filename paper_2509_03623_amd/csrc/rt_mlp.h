@@ -20,6 +20,9 @@ struct MlpDev {
     // (output neurons as rows), rows padded for LDS, input order of layers
     // 1..3 permuted to the accumulator layout of the layer before
     const void *Wr;
+    // BF16 only: layers 1..3 transposed for the backward pass, [in][out slot]
+    // with the output order permuted like the accumulator packing
+    const void *WrT;
 };
 
 size_t mlp_prep_bytes(int precision);

@@ -5,6 +5,9 @@
 // evaluated at every (pixel, sample) point of the render, point index
 // m = k * npix + pix.
 //
+// The BF16 path runs mlp_fwd_rr and mlp_bwd_rr; the FP32 reference path runs
+// mlp_fwd<float> and mlp_bwd<float>.
+//
 // mlp_fwd<T, P>: a workgroup of 8 waves evaluates a tile of P points.  Layer
 //   outputs are 16 x 16 MFMA tiles: wave w owns output columns [16w, 16w+16)
 //   for every 16-point row tile; activations go through LDS between layers
@@ -22,6 +25,7 @@
 //   weights are prepared).  Activations therefore never leave registers; the
 //   output layer is evaluated in FP32 on the VALU and reduced across the
 //   four lane groups by shuffles.
+// mlp_bwd_rr (BF16): see its definition below.
 // mlp_bwd<T, P>: persistent workgroups; each recomputes the forward of its
 //   tiles (keeping pre-activations and transposed activations in LDS),
 //   backpropagates dL/do through the layers on MFMA, and accumulates the
@@ -212,11 +216,14 @@ __global__ void mlp_prep_rr(const float *__restrict__ flat, MlpDev w) {
         const int o = i / kRrRow0, k = i - o * kRrRow0;
         Wr[i] = (__bf16)(k < kF ? kLog2E * flat[w.off[0] + o * kF + k] : 0.0f);
     }
+    __bf16 *WrT = (__bf16 *)w.WrT;
     for (int l = 1; l < 4; ++l) {
         if (i < kW * kRrRow) {
             const int o = i / kRrRow, k = i - o * kRrRow;
             Wr[(size_t)kW * kRrRow0 + (size_t)(l - 1) * kW * kRrRow + i] =
                 (__bf16)(k < kW ? flat[w.off[l] + o * kW + rr_perm(k)] : 0.0f);
+            // transposed: row = input neuron o, column = output slot k
+            WrT[(size_t)(l - 1) * kW * kRrRow + i] = (__bf16)(k < kW ? flat[w.off[l] + rr_perm(k) * kW + o] : 0.0f);
         }
     }
 }
@@ -369,6 +376,312 @@ __global__ __launch_bounds__(NT) void mlp_fwd_rr(Geometry g, Shade s, MlpDev w, 
     }
 }
 
+// ---------------------------------------------------------------- register-resident BF16 backward
+// mlp_bwd_rr: one workgroup of four waves per CU, each wave with the full
+// register file of its SIMD.  A wave takes 16 points per pass (the workgroup
+// 64): it recomputes the forward with the transposed product (weights read
+// as A operands from L2), keeping z' of every layer in registers as BF16;
+// walks back through the layers (dL/dh' of the layer below by the product
+// with the transposed weights, the SiLU derivative recomputed from z'); and
+// for the weight gradient, which sums over points, writes dL/dz' and h' of
+// the pass into LDS as point-major rows, so that after a barrier each wave
+// accumulates its own slice of every layer's gradient (32 output rows of the
+// hidden layers, two 16-column tiles of the output layer) in MFMA
+// accumulators over all 64 points.  Bias gradients are row sums of the same
+// LDS rows.  Everything is flushed with atomics once, at the end.
+constexpr int kBrPts = 64;                 // points per workgroup pass
+// global-memory views (the pass loop launders the weight pointers, which
+// would otherwise turn their loads into flat loads)
+typedef const __attribute__((address_space(1))) __bf16 gbf16;
+typedef const __attribute__((address_space(1))) bf16x8 gbf16x8;
+constexpr int kBrStride = kBrPts + 8;      // LDS row of the point-major buffers (bf16)
+
+__device__ __forceinline__ void br_features(bf16x8 (&feat)[2], const MlpDev &w, float cr, float cz, int lg) {
+    const int fb = 8 * (lg & 1) + (lg < 2 ? 0 : 4);
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        float own[4], sent[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const float x = w.freq[fb + q] * (c == 0 ? cr : cz);
+            const float t = 0.5f * (x - 2.0f * floorf(0.5f * x));
+            const float sv = __builtin_amdgcn_sinf(t), cv = __builtin_amdgcn_cosf(t);
+            own[q] = lg < 2 ? sv : cv;
+            sent[q] = lg < 2 ? cv : sv;
+        }
+        bf16x8 f;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const float r = __shfl_xor(sent[q], 32);
+            f[q] = (__bf16)(lg < 2 ? own[q] : r);
+            f[4 + q] = (__bf16)(lg < 2 ? r : own[q]);
+        }
+        feat[c] = f;
+    }
+}
+
+// h' = z' sigma(z) and dL/dz' = dL/dh' SiLU'(z) of one neuron, z = ln2 z'
+__device__ __forceinline__ void br_act_grad(__bf16 zq16, float dh, bf16x8 &hp, bf16x8 &dz, int e) {
+    const float zq = (float)zq16;
+    const float sg = frcp(1.0f + fexp2(-zq));
+    const float z = kLn2 * zq;
+    hp[e] = (__bf16)(zq * sg);
+    dz[e] = (__bf16)(dh * (sg * (1.0f + z * (1.0f - sg))));
+}
+
+// point-major write of 32 accumulator-layout values (neurons 16t + 4lg + i,
+// t = 2cp + h, element 4h + i of pair cp) of the lane's point
+__device__ __forceinline__ void br_write_rows(__bf16 *X, const bf16x8 (&v)[4], int lg, int col) {
+#pragma unroll
+    for (int cp = 0; cp < 4; ++cp)
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) X[(32 * cp + 16 * h + 4 * lg + i) * kBrStride + col] = v[cp][4 * h + i];
+}
+
+// dW slice of one hidden layer: rows [32 wv, 32 wv + 32) of XD against the
+// NI 16-row tiles of XH, over the 64 points
+template <int NI>
+__device__ __forceinline__ void br_dw(floatx4 (&acc)[2][NI], const __bf16 *XD, const __bf16 *XH, int wv, int lg,
+                                      int lc) {
+    typedef MM<__bf16> mm;
+#pragma unroll
+    for (int kc = 0; kc < kBrPts / 32; ++kc) {
+        const bf16x8 a0 = *(const bf16x8 *)(XD + (32 * wv + lc) * kBrStride + 32 * kc + 8 * lg);
+        const bf16x8 a1 = *(const bf16x8 *)(XD + (32 * wv + 16 + lc) * kBrStride + 32 * kc + 8 * lg);
+#pragma unroll
+        for (int it = 0; it < NI; ++it) {
+            const bf16x8 b = *(const bf16x8 *)(XH + (16 * it + lc) * kBrStride + 32 * kc + 8 * lg);
+            acc[0][it] = mm::mfma(a0, b, acc[0][it]);
+            acc[1][it] = mm::mfma(a1, b, acc[1][it]);
+        }
+    }
+}
+
+// sum over the 64 points of LDS row r (two lanes per row, 32 points each)
+__device__ __forceinline__ float br_rowsum(const __bf16 *X, int r, int half) {
+    float sum = 0.0f;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const bf16x8 v = *(const bf16x8 *)(X + r * kBrStride + 32 * half + 8 * q);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) sum += (float)v[j];
+    }
+    return sum + __shfl_xor(sum, 1);
+}
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void mlp_bwd_rr(
+    Geometry g, Shade s, MlpDev w, size_t M, const float4 *__restrict__ dO, float *__restrict__ dW) {
+    typedef MM<__bf16> mm;
+    __shared__ __attribute__((aligned(16))) __bf16 XD[kW * kBrStride];   // dL/dz' (or dL/do) rows x points
+    __shared__ __attribute__((aligned(16))) __bf16 XH[kW * kBrStride];   // h' (or features) rows x points
+    __shared__ __attribute__((aligned(16))) float sB[4 * kW];
+    __shared__ __attribute__((aligned(16))) float sW5[3 * kW];
+    // lane-private parking of z' (4 layers x 4 operand packs) and the two
+    // feature packs between the forward and the backward of a pass
+    __shared__ bf16x8 ZP[18][256];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int lg = lane >> 4, lc = lane & 15;
+    for (int i = tid; i < 4 * kW; i += 256) sB[i] = kLog2E * w.b[i / kW][i % kW];
+    for (int i = tid; i < 3 * kW; i += 256) sW5[i] = kLn2 * w.W5[i];
+    floatx4 g0[2][4], g1[2][8], g2[2][8], g3[2][8], g4[2][1];
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+#pragma unroll
+        for (int b = 0; b < 4; ++b) g0[a][b] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int b = 0; b < 8; ++b) { g1[a][b] = g0[a][0]; g2[a][b] = g0[a][0]; g3[a][b] = g0[a][0]; }
+        g4[a][0] = g0[a][0];
+    }
+    float db0 = 0.0f, db1 = 0.0f, db2 = 0.0f, db3 = 0.0f, db5 = 0.0f;
+    const int brow = 32 * wv + (lane >> 1), bhalf = lane & 1;     // bias row of this lane
+    const int col = 16 * wv + lc;                                 // this lane's point within the pass
+    __syncthreads();
+    for (size_t base = (size_t)blockIdx.x * kBrPts; base < M; base += (size_t)gridDim.x * kBrPts) {
+        // the weight operands are the same every pass: hide that from the
+        // compiler, or it keeps all 208 fragments in registers across passes
+        uint64_t wr_u = (uint64_t)w.Wr, wrt_u = (uint64_t)w.WrT;
+        asm volatile("" : "+s"(wr_u), "+s"(wrt_u));
+        const gbf16 *Wr = (const gbf16 *)wr_u;
+        const gbf16 *WrT = (const gbf16 *)wrt_u;
+        const size_t m = base + col;
+        float rh = 0.0f, zh = 0.0f;
+        if (lane < 16 && m < M) point_coords(g, s, m, &rh, &zh);
+        bf16x8 hin[4];
+        {
+            bf16x8 feat[2];
+            br_features(feat, w, __shfl(rh, lc), __shfl(zh, lc), lg);
+            ZP[16][tid] = feat[0];
+            ZP[17][tid] = feat[1];
+            hin[0] = feat[0];
+            hin[1] = feat[1];
+        }
+        // ---- forward, parking z' of every layer
+#pragma unroll
+        for (int l = 0; l < 4; ++l) {
+            const int nk = l == 0 ? kF / 32 : kW / 32;
+            const int row = l == 0 ? kRrRow0 : kRrRow;
+            const gbf16 *Wl = Wr + (l == 0 ? 0 : (size_t)kW * kRrRow0 + (size_t)(l - 1) * kW * kRrRow);
+            bf16x8 hout[4];
+#pragma unroll
+            for (int cp = 0; cp < 4; ++cp) {
+                floatx4 acc[2];
+#pragma unroll
+                for (int h = 0; h < 2; ++h) acc[h] = *(const floatx4 *)(sB + l * kW + 32 * cp + 16 * h + 4 * lg);
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    if (c >= nk) break;
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        const bf16x8 a = *(const gbf16x8 *)(Wl + (size_t)(32 * cp + 16 * h + lc) * row + 32 * c + 8 * lg);
+                        acc[h] = mm::mfma(a, hin[c], acc[h]);
+                    }
+                }
+                bf16x8 zq;
+#pragma unroll
+                for (int h = 0; h < 2; ++h)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const float z = acc[h][i];
+                        zq[4 * h + i] = (__bf16)z;
+                        if (l < 3) hout[cp][4 * h + i] = (__bf16)(z * frcp(1.0f + fexp2(-z)));
+                    }
+                ZP[4 * l + cp][tid] = zq;
+            }
+            if (l < 3) {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) hin[c] = hout[c];
+            }
+        }
+        // ---- output layer: dL/dh'_3 = W5'^T dL/do, then h'_3 and dL/dz'_3
+        const float4 d = m < M ? dO[m] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        bf16x8 hp[4], dz[4], dzu[4];   // h' and dL/dz' of the current layer, dL/dz' of the layer above
+#pragma unroll
+        for (int cp = 0; cp < 4; ++cp) {
+            const bf16x8 zq = ZP[12 + cp][tid];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int n = 32 * cp + 16 * (e >> 2) + 4 * lg + (e & 3);
+                const float dh = fmaf(sW5[n], d.x, fmaf(sW5[kW + n], d.y, sW5[2 * kW + n] * d.z));
+                br_act_grad(zq[e], dh, hp[cp], dz[cp], e);
+            }
+        }
+#pragma unroll
+        for (int l = 3; l >= 0; --l) {
+            // gradient of the layer above (the output layer when l == 3):
+            // its dL/dz' and this layer's h', point-major, into LDS
+            br_write_rows(XH, hp, lg, col);
+            if (l == 3) {
+                if (lg == 0) {
+                    XD[0 * kBrStride + col] = (__bf16)d.x;
+                    XD[1 * kBrStride + col] = (__bf16)d.y;
+                    XD[2 * kBrStride + col] = (__bf16)d.z;
+                } else {
+                    // rows 3..15 are zero padding of the 16-row tile
+#pragma unroll
+                    for (int r = 0; r < 5; ++r) {
+                        const int rr = 3 + 5 * (lg - 1) + r;
+                        if (rr < 16) XD[rr * kBrStride + col] = (__bf16)0.0f;
+                    }
+                }
+            } else {
+                br_write_rows(XD, dzu, lg, col);
+            }
+            __syncthreads();
+            if (l == 3) {
+#pragma unroll
+                for (int kc = 0; kc < kBrPts / 32; ++kc) {
+                    const bf16x8 a = *(const bf16x8 *)(XD + lc * kBrStride + 32 * kc + 8 * lg);
+#pragma unroll
+                    for (int q = 0; q < 2; ++q) {
+                        const bf16x8 b = *(const bf16x8 *)(XH + (16 * (wv + 4 * q) + lc) * kBrStride + 32 * kc + 8 * lg);
+                        g4[q][0] = mm::mfma(a, b, g4[q][0]);
+                    }
+                }
+                if (wv == 0) {
+                    const float v = br_rowsum(XD, lane >> 1, bhalf);   // rows 0..2 are dL/do
+                    if (lane < 6) db5 += v;
+                }
+            } else if (l == 2) {
+                br_dw<8>(g3, XD, XH, wv, lg, lc);
+                db3 += br_rowsum(XD, brow, bhalf);
+            } else if (l == 1) {
+                br_dw<8>(g2, XD, XH, wv, lg, lc);
+                db2 += br_rowsum(XD, brow, bhalf);
+            } else {
+                br_dw<8>(g1, XD, XH, wv, lg, lc);
+                db1 += br_rowsum(XD, brow, bhalf);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int c = 0; c < 4; ++c) dzu[c] = dz[c];
+            // dL/dh' of the layer below through the transposed weights, and
+            // at once its h' and dL/dz'
+            if (l >= 1) {
+                const gbf16 *WT = WrT + (size_t)(l - 1) * kW * kRrRow;
+#pragma unroll
+                for (int cp = 0; cp < 4; ++cp) {
+                        floatx4 acc[2] = {floatx4{0.0f, 0.0f, 0.0f, 0.0f}, floatx4{0.0f, 0.0f, 0.0f, 0.0f}};
+#pragma unroll
+                    for (int c = 0; c < 4; ++c)
+#pragma unroll
+                        for (int h = 0; h < 2; ++h) {
+                            const bf16x8 a = *(const gbf16x8 *)(WT + (size_t)(32 * cp + 16 * h + lc) * kRrRow + 32 * c + 8 * lg);
+                            acc[h] = mm::mfma(a, dzu[c], acc[h]);
+                        }
+                    const bf16x8 zq = ZP[4 * (l - 1) + cp][tid];
+#pragma unroll
+                    for (int h = 0; h < 2; ++h)
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) br_act_grad(zq[4 * h + i], acc[h][i], hp[cp], dz[cp], 4 * h + i);
+                }
+            }
+        }
+        // ---- layer 0: features and dz'_0
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const bf16x8 f = ZP[16 + c][tid];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) XH[(32 * c + 8 * lg + j) * kBrStride + col] = f[j];
+        }
+        br_write_rows(XD, dz, lg, col);
+        __syncthreads();
+        br_dw<4>(g0, XD, XH, wv, lg, lc);
+        db0 += br_rowsum(XD, brow, bhalf);
+        __syncthreads();
+    }
+    // ---- flush: flat layout per layer W [out][in] then b [out]
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int o = 32 * wv + 16 * a + 4 * lg + i;
+#pragma unroll
+            for (int it = 0; it < 4; ++it) atomicAdd(dW + w.off[0] + o * kF + 16 * it + lc, kLog2E * g0[a][it][i]);
+#pragma unroll
+            for (int it = 0; it < 8; ++it) {
+                atomicAdd(dW + w.off[1] + o * kW + 16 * it + lc, g1[a][it][i]);
+                atomicAdd(dW + w.off[2] + o * kW + 16 * it + lc, g2[a][it][i]);
+                atomicAdd(dW + w.off[3] + o * kW + 16 * it + lc, g3[a][it][i]);
+            }
+        }
+    if (bhalf == 0) {
+        atomicAdd(dW + w.off[0] + kW * kF + brow, kLog2E * db0);
+        atomicAdd(dW + w.off[1] + kW * kW + brow, kLog2E * db1);
+        atomicAdd(dW + w.off[2] + kW * kW + brow, kLog2E * db2);
+        atomicAdd(dW + w.off[3] + kW * kW + brow, kLog2E * db3);
+    }
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int j = 4 * lg + i;
+            if (j < 3) atomicAdd(dW + w.off[4] + j * kW + 16 * (wv + 4 * q) + lc, kLn2 * g4[q][0][i]);
+        }
+    if (wv == 0 && lane < 6 && bhalf == 0) atomicAdd(dW + w.off[4] + 3 * kW + (lane >> 1), db5);
+}
+
 template <typename T, int P>
 __global__ __launch_bounds__(512) void mlp_bwd(Geometry g, Shade s, MlpDev w, size_t M, const float4 *__restrict__ dO,
                                                float *__restrict__ dW) {
@@ -510,7 +823,7 @@ size_t mlp_prep_bytes(int precision) {
     const size_t es = precision == RT_MLP_BF16 ? 2 : 4;
     size_t n = 0;
     for (int l = 0; l < 4; ++l) n += 2 * es * (size_t)kW * kLayerIn[l] + 4 * kW;
-    if (precision == RT_MLP_BF16) n += 2 * kRrWeightElems + 256;
+    if (precision == RT_MLP_BF16) n += 2 * kRrWeightElems + 256 + 2 * 3 * (size_t)kW * kRrRow + 256;
     return n + 4 * (3 * kW + 3) + 256 * 8;
 }
 
@@ -530,6 +843,7 @@ hipError_t mlp_prepare(const float *flat, int precision, void *buf, MlpDev *w, h
     w->W5 = (const float *)take(4 * 3 * kW);
     w->b5 = (const float *)take(4 * 3);
     w->Wr = precision == RT_MLP_BF16 ? take(2 * kRrWeightElems) : nullptr;
+    w->WrT = precision == RT_MLP_BF16 ? take(2 * 3 * (size_t)kW * kRrRow) : nullptr;
     for (int q = 0; q < 16; ++q) w->freq[q] = (float)std::exp2(3.0 * q / 15.0);
     const int n = kW * kW;
     if (precision == RT_MLP_BF16) {
@@ -569,10 +883,9 @@ hipError_t mlp_backward(const Geometry &g, const Shade &s, const MlpDev &w, int 
     if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return e;
     if (precision == RT_MLP_BF16) {
-        constexpr int P = 32;
-        const size_t ntiles = (M + P - 1) / P;
-        const unsigned grid = (unsigned)std::min<size_t>(ntiles, (size_t)ncu);
-        hipLaunchKernelGGL((mlp_bwd<__bf16, P>), dim3(grid), dim3(512), 0, st, g, s, w, M, dO, dW);
+        const size_t passes = (M + kBrPts - 1) / kBrPts;
+        const unsigned grid = (unsigned)std::min<size_t>(passes, (size_t)ncu);
+        hipLaunchKernelGGL(mlp_bwd_rr, dim3(grid), dim3(256), 0, st, g, s, w, M, dO, dW);
     } else {
         constexpr int P = 16;
         const size_t ntiles = (M + P - 1) / P;
