@@ -119,3 +119,33 @@ def test_network_adjoint_in_row_bands():
         scale = np.abs(whole[k]).max()
         assert scale > 0, k
         assert np.abs(banded[k] - whole[k]).max() <= 1e-5 * scale, k
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_full_size_network_render_sampled_pixels(precision):
+    """The 256 x 256 x 32-channel x 256-sample network render in the launch
+    configuration the benchmark times, checked on 96 seeded pixels against
+    the FP64 oracle (network evaluated in float64 at every sample): the FP32
+    path at the FP32 bar (max |dI| <= 1e-5 peak of the sample), the BF16
+    path at relative L2 <= 1e-2."""
+    rt = _rt()
+    prob = synth.config4()
+    prec = rt.RT_MLP_FP32 if precision == "fp32" else rt.RT_MLP_BF16
+    print(f"[gpu] full-size network render prec={precision}", flush=True)
+    sc = rt.scene_from_problem(prob, mlp_precision=prec)
+    cube = rt.render(sc)
+    torch.cuda.synchronize()
+    rng = np.random.Generator(np.random.PCG64(44))
+    # pixels over the disk (the inner two thirds of the image) plus a few anywhere
+    px = np.concatenate([rng.integers(43, 213, 80), rng.integers(0, 256, 16)])
+    py = np.concatenate([rng.integers(43, 213, 80), rng.integers(0, 256, 16)])
+    ref = oracle.render_pixels(prob, px, py)
+    got = cube.cpu().numpy().astype(np.float64)[:, py, px].T
+    assert ref.max() > 0
+    err = float(np.abs(got - ref).max() / ref.max())
+    l2 = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    print(f"{precision}: max|dI|/peak {err:.2e}, rel L2 {l2:.2e}")
+    if precision == "fp32":
+        assert err <= 1e-5
+    else:
+        assert l2 <= 1e-2
