@@ -112,6 +112,9 @@ __global__ __launch_bounds__(256) void adj_march(int nsamp, int npix, int plane,
             const int k = seg * KSEG + kk;
             if (k >= nsamp) continue;
             const float S = Q[kk].x, K = Q[kk].y, a = Q[kk].z, b = Q[kk].w;
+            // the ln2 of dtau = ln2 K g is applied once per sample: to cK at
+            // the end, and folded into Km for the chain to d
+            const float Km = K * (-2.0f * kLn2 * kLn2);
             float cS = 0.0f, cK = 0.0f, ca = 0.0f, cb = 0.0f;
 #pragma unroll
             for (int c = 0; c < CB; ++c) {
@@ -119,19 +122,22 @@ __global__ __launch_bounds__(256) void adj_march(int nsamp, int npix, int plane,
                 const float d = fmaf(-vc, b, a);
                 const float gk = fexp2(-(d * d));
                 const float att = fexp2(-(K * gk));
-                const float om = 1.0f - att;
                 const float t0 = TrK[kk][c];
                 const float t1 = t0 * att;
-                cS = fmaf(w[c] * t0, om, cS);
-                // dL/d(dtau) with dtau = ln2 K g, g = 2^-d^2
-                const float gg = w[c] * t1 * (S - J[c]) * kLn2 * gk;
-                J[c] = fmaf(att, J[c], S * om);
+                const float smj = S - J[c];
+                // dI/dS = Tr_k (1 - att)  (as a difference of transmissions it
+                // keeps t1 live longer: one occupancy step fewer)
+                cS = fmaf(w[c] * t0, 1.0f - att, cS);
+                // dL/d(dtau) / ln2, with dtau = ln2 K g, g = 2^-d^2
+                const float gg = w[c] * t1 * smj * gk;
+                // J_k-1 = S (1 - att) + att J_k = S - att (S - J_k)
+                J[c] = fmaf(-att, smj, S);
                 cK += gg;
-                const float gd = gg * K * (-2.0f * kLn2) * d;
+                const float gd = gg * Km * d;
                 ca += gd;
                 cb = fmaf(-vc, gd, cb);
             }
-            cot[((size_t)blk * nsamp + k) * npix + pix] = make_float4(cS, cK, ca, cb);
+            cot[((size_t)blk * nsamp + k) * npix + pix] = make_float4(cS, cK * kLn2, ca, cb);
         }
     }
 }

@@ -184,3 +184,32 @@ def test_served_stream_beats_serial():
     for a, b in zip(ref, outs):
         assert float((a - b).abs().max()) <= 1e-6 * float(a.abs().max())
     assert served < serial
+
+
+def test_neural_requests_match_direct_calls():
+    """Requests with the neural CO layer (BF16 network) through the server:
+    the forward cube equals rt_render_cube's bitwise, and a gradient request
+    gives the direct adjoint's network-weight gradient."""
+    rt = _rt()
+    prob = synth.small_problem(nx=24, ny=20, nch=12, nsamp=64, nr=48, nz=24, seed=5, dv=0.2, mlp_seed=4)
+    sc = rt.scene_from_problem(prob, mlp_precision=rt.RT_MLP_BF16)
+    direct = rt.render(sc)
+    target = direct * 0.9
+    ref = rt.render_adjoint(sc, 2.0 * (direct - target), want=("temp_k", "mlp_w"))
+    torch.cuda.synchronize()
+    print("[gpu] server neural requests", flush=True)
+    cube_f, cube_g = empty_cube(sc), empty_cube(sc)
+    grads = {"temp_k": torch.empty_like(sc.temp_k), "mlp_w": torch.empty_like(sc.mlp_w)}
+    with rt.Server(max_slots=8, streams=2) as sv:
+        tf = sv.submit(sc, cube_f)
+        tg = sv.submit(sc, cube_g, target=target, grads=grads)
+        assert sv.wait(tf)["state"] == "done"
+        info = sv.wait(tg)
+    assert info["state"] == "done"
+    torch.cuda.synchronize()
+    assert torch.equal(cube_f, direct)
+    assert torch.equal(cube_g, direct)
+    assert info["loss"] == pytest.approx(float(((direct.double() - target.double()) ** 2).sum()), rel=1e-5)
+    for k in ("temp_k", "mlp_w"):
+        d = float((grads[k] - ref[k]).abs().max())
+        assert d <= 1e-4 * float(ref[k].abs().max()), k
