@@ -227,30 +227,39 @@ def main():
 
 
 def bench_adjoint(rt, synth, dev, args):
-    """Forward + adjoint (L2 loss): the 256 x 256 x 48 x 256 gradient case and
-    the full-size 512 x 512 x 64 x 512 render."""
+    """Forward + adjoint of an L2 loss, on the 256 x 256 x 48 x 256 gradient
+    case and the full-size 512 x 512 x 64 x 512 render: fused (one call: the
+    reverse march forms dL/dI from its own forward sweep) and separate
+    (forward render, loss in torch, adjoint)."""
     import torch
     out = {}
+    want = ("ln_nh2", "temp_k", "z_lo_au", "z_up_au")
     for name, prob in (("256x256x48ch_256s", synth.config3()), ("512x512x64ch_512s", synth.config2(args.seed))):
         sc = rt.scene_from_problem(prob, device=dev)
         tgt = rt.render(sc.replace(z_up_au=sc.z_up_au * 1.05))
         steps = max(3, args.steps // 2)
+        cube = torch.empty_like(tgt)
 
-        def step():
-            cube = rt.render(sc)
-            dl = 2.0 * (cube - tgt)
-            return rt.render_adjoint(sc, dl, want=("ln_nh2", "temp_k", "z_lo_au", "z_up_au"))
+        def separate():
+            c = rt.render(sc)
+            dl = 2.0 * (c - tgt)
+            return rt.render_adjoint(sc, dl, want=want)
 
-        for _ in range(max(1, args.warmup // 2)):
-            step()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            step()
-        torch.cuda.synchronize()
-        dt = (time.perf_counter() - t0) / steps
-        out[name] = {"ray_samples_per_s": sc.ray_samples / dt, "ms_per_step": dt * 1e3, "steps": steps,
-                     "grads": "ln n_H2, T, z_lo, z_up"}
+        def fused():
+            return rt.render_l2_adjoint(sc, tgt, want=want, cube_out=cube)
+
+        res = {}
+        for leg, step in (("fused", fused), ("separate", separate)):
+            for _ in range(max(1, args.warmup // 2)):
+                step()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                step()
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / steps
+            res[leg] = {"ray_samples_per_s": sc.ray_samples / dt, "ms_per_step": dt * 1e3}
+        out[name] = dict(res, steps=steps, grads="ln n_H2, T, z_lo, z_up")
     return out
 
 

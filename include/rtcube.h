@@ -149,6 +149,17 @@ rt_status rt_render_cube(const rt_problem *p, float *cube, void *stream);
 rt_status rt_render_cube_adjoint(const rt_problem *p, const float *dl_dcube, const rt_grads *g,
                                  float *cube_opt, void *stream);
 
+/* Forward + L2 loss + adjoint in one pass (the fitting step of Fig.
+ * radjax_pipeline with an L2 pixel loss, Methods > Neural temperature
+ * recovery): L = sum (cube - target)^2 over [nch][ny][nx].  Writes the cube
+ * (device, required), the requested gradients of L as rt_render_cube_adjoint
+ * does for dL/dcube = 2 (cube - target), and, if loss != NULL, L to *loss
+ * (device pointer to one double).  The reverse march forms dL/dcube from its
+ * own forward sweep, so no separate forward render is run.  target: device,
+ * [nch][ny][nx].  At most 256 channels per call. */
+rt_status rt_render_cube_l2_adjoint(const rt_problem *p, const float *target, const rt_grads *g, float *cube,
+                                    double *loss, void *stream);
+
 /* ---------------------------------------------------------------- server */
 /* Continuous-batching render server on one GPU.  Requests are admitted in
  * arrival order while their HBM footprint (inputs, outputs and library

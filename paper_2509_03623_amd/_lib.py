@@ -84,7 +84,7 @@ class rt_ticket_info(C.Structure):
 
 
 # every symbol declared in include/rtcube.h
-EXPORTS = ["rt_render_cube", "rt_render_cube_adjoint", "rt_server_create", "rt_submit", "rt_poll", "rt_wait",
+EXPORTS = ["rt_render_cube", "rt_render_cube_adjoint", "rt_render_cube_l2_adjoint", "rt_server_create", "rt_submit", "rt_poll", "rt_wait",
            "rt_cancel", "rt_server_destroy", "rt_last_error", "rt_abi_version", "rt_constants",
            "rt_set_option", "rt_get_option"]
 
@@ -110,6 +110,8 @@ def lib():
         L.rt_render_cube.restype = C.c_int
         L.rt_render_cube_adjoint.argtypes = [P, _dev, C.POINTER(rt_grads), _dev, C.c_void_p]
         L.rt_render_cube_adjoint.restype = C.c_int
+        L.rt_render_cube_l2_adjoint.argtypes = [P, _dev, C.POINTER(rt_grads), _dev, _dev, C.c_void_p]
+        L.rt_render_cube_l2_adjoint.restype = C.c_int
         L.rt_server_create.argtypes = [C.POINTER(rt_server_cfg), C.POINTER(C.c_void_p)]
         L.rt_server_create.restype = C.c_int
         L.rt_submit.argtypes = [C.c_void_p, C.POINTER(rt_request), C.POINTER(C.c_uint64)]

@@ -46,11 +46,14 @@ __global__ __launch_bounds__(256) void adj_tape(Geometry g, Shade s, float4 *__r
     }
 }
 
+// dl_dcube: the cotangent dL/dI; or, with target != NULL, the cotangent of
+// the L2 loss sum (I - D)^2 is formed from the forward sweep's own I:
+// dL/dI = 2 (I - D).
 template <int CB, int KSEG>
 __global__ __launch_bounds__(256) void adj_march(int nsamp, int npix, int plane, Channels ch,
                                                  const float4 *__restrict__ tape, const float *__restrict__ dl_dcube,
-                                                 float *__restrict__ ckpt, float4 *__restrict__ cot,
-                                                 float *__restrict__ cube_out) {
+                                                 const float *__restrict__ target, float *__restrict__ ckpt,
+                                                 float4 *__restrict__ cot, float *__restrict__ cube_out) {
     const int pix = blockIdx.x * 256 + threadIdx.x;
     if (pix >= npix) return;
     const int blk = blockIdx.y, nblk = gridDim.y;
@@ -59,7 +62,6 @@ __global__ __launch_bounds__(256) void adj_march(int nsamp, int npix, int plane,
     float w[CB], Tr[CB], I[CB];
 #pragma unroll
     for (int c = 0; c < CB; ++c) {
-        w[c] = (c0 + c < ch.n) ? dl_dcube[(size_t)(c0 + c) * plane + pix] : 0.0f;
         Tr[c] = 1.0f;
         I[c] = 0.0f;
     }
@@ -86,6 +88,11 @@ __global__ __launch_bounds__(256) void adj_march(int nsamp, int npix, int plane,
 #pragma unroll
         for (int c = 0; c < CB; ++c)
             if (c0 + c < ch.n) cube_out[(size_t)(c0 + c) * plane + pix] = I[c];
+    }
+#pragma unroll
+    for (int c = 0; c < CB; ++c) {
+        const size_t i = (size_t)(c0 + c) * plane + pix;
+        w[c] = c0 + c >= ch.n ? 0.0f : (target ? 2.0f * (I[c] - target[i]) : dl_dcube[i]);
     }
     // reverse sweep, one segment at a time
     float J[CB];
@@ -441,17 +448,19 @@ hipError_t launch_adj_tape(const Geometry &g, const Shade &s, float4 *tape, floa
 
 template <int CB, int KSEG>
 static hipError_t launch_march_t(int nsamp, int npix, int plane, const Channels &ch, const float4 *tape,
-                                 const float *dl, float *ckpt, float4 *cot, float *cube_out, hipStream_t st) {
+                                 const float *dl, const float *target, float *ckpt, float4 *cot, float *cube_out,
+                                 hipStream_t st) {
     dim3 grid((npix + 255) / 256, (ch.n + CB - 1) / CB);
-    hipLaunchKernelGGL((adj_march<CB, KSEG>), grid, dim3(256), 0, st, nsamp, npix, plane, ch, tape, dl, ckpt, cot,
-                       cube_out);
+    hipLaunchKernelGGL((adj_march<CB, KSEG>), grid, dim3(256), 0, st, nsamp, npix, plane, ch, tape, dl, target, ckpt,
+                       cot, cube_out);
     return hipGetLastError();
 }
 
 hipError_t launch_adj_march(int cb, int kseg, int nsamp, int npix, int plane, const Channels &ch, const float4 *tape,
-                            const float *dl, float *ckpt, float4 *cot, float *cube_out, hipStream_t st) {
+                            const float *dl, const float *target, float *ckpt, float4 *cot, float *cube_out,
+                            hipStream_t st) {
 #define RT_MARCH_CASE(C, K) \
-    if (cb == C && kseg == K) return launch_march_t<C, K>(nsamp, npix, plane, ch, tape, dl, ckpt, cot, cube_out, st);
+    if (cb == C && kseg == K) return launch_march_t<C, K>(nsamp, npix, plane, ch, tape, dl, target, ckpt, cot, cube_out, st);
     RT_MARCH_CASE(8, 4) RT_MARCH_CASE(8, 8) RT_MARCH_CASE(8, 16)
     RT_MARCH_CASE(16, 4) RT_MARCH_CASE(16, 8)
     RT_MARCH_CASE(32, 4)

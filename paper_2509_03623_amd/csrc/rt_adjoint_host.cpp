@@ -30,7 +30,7 @@ size_t adjoint_bytes_per_pixel(int nch, int nsamp) {
 
 
 rt_status adjoint_core(const rt_problem *p, const float *dl, const rt_grads *g, float *cube_opt, hipStream_t st,
-                       const float4 *mlp_o, float4 *dO) {
+                       const float4 *mlp_o, float4 *dO, const float *target) {
     Geometry geo;
     Shade sh;
     rt_status rs = build_launch(p, &geo, &sh);
@@ -82,8 +82,10 @@ rt_status adjoint_core(const rt_problem *p, const float *dl, const rt_grads *g, 
             float *ckpt = (float *)(base + tape_b + rays_b);
             float4 *cot = (float4 *)(base + tape_b + rays_b + ckpt_b);
             if ((e = launch_adj_tape(gb, sb, tape, rays, st)) != hipSuccess) return fail_hip(e, "adjoint tape");
-            if ((e = launch_adj_march(cb, kseg, ns, bpix, (int)plane, ch, tape, dl + (size_t)c0 * plane + pix0, ckpt,
-                                      cot, cube_opt ? cube_opt + (size_t)c0 * plane + pix0 : nullptr, st)) != hipSuccess)
+            const size_t off = (size_t)c0 * plane + pix0;
+            if ((e = launch_adj_march(cb, kseg, ns, bpix, (int)plane, ch, tape, dl ? dl + off : nullptr,
+                                      target ? target + off : nullptr, ckpt, cot,
+                                      cube_opt ? cube_opt + off : nullptr, st)) != hipSuccess)
                 return fail_hip(e, "adjoint march");
             float4 *dOc = c0 == 0 ? dO : nullptr;
             e = lds ? launch_adj_chain_lds(gb, sb, rays, cot, nblk, go, dOc, st)
@@ -105,13 +107,32 @@ rt_status adjoint_core(const rt_problem *p, const float *dl, const rt_grads *g, 
     return RT_OK;
 }
 
-rt_status adjoint_grid(const rt_problem *p, const float *dl, const rt_grads *g, float *cube_opt, hipStream_t st) {
-    return adjoint_core(p, dl, g, cube_opt, st, nullptr, nullptr);
+rt_status adjoint_grid(const rt_problem *p, const float *dl, const rt_grads *g, float *cube_opt, hipStream_t st,
+                       const float *target) {
+    return adjoint_core(p, dl, g, cube_opt, st, nullptr, nullptr, target);
 }
 
 } // namespace rt
 
 using namespace rt;
+
+extern "C" rt_status rt_render_cube_l2_adjoint(const rt_problem *p, const float *target, const rt_grads *g,
+                                               float *cube, double *loss, void *stream) {
+    rt_status st = validate(p);
+    if (st != RT_OK) return st;
+    if (!target || !cube) return fail(RT_EINVAL, "target and cube must not be NULL");
+    if (!g) return fail(RT_EINVAL, "grads is NULL");
+    if (p->spec.nch > kLaunchChannels)
+        return fail(RT_EINVAL, "the fused L2 adjoint takes at most %d channels per call", kLaunchChannels);
+    hipStream_t s = (hipStream_t)stream;
+    if (p->mlp) st = adjoint_mlp(p, nullptr, g, cube, s, target);
+    else if (g->d_mlp) return fail(RT_EINVAL, "d_mlp requested but the problem has no network");
+    else st = adjoint_grid(p, nullptr, g, cube, s, target);
+    if (st != RT_OK || !loss) return st;
+    const size_t n = (size_t)p->spec.nch * p->cam.nx * p->cam.ny;
+    const hipError_t e = launch_l2_value(cube, target, n, loss, s);
+    return e == hipSuccess ? RT_OK : fail_hip(e, "loss");
+}
 
 extern "C" rt_status rt_render_cube_adjoint(const rt_problem *p, const float *dl_dcube, const rt_grads *g,
                                             float *cube_opt, void *stream) {

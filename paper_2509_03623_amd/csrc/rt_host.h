@@ -35,9 +35,16 @@ size_t adjoint_bytes_per_pixel(int nch, int nsamp);
 
 rt_status render_cube_mlp(const rt_problem *p, float *cube, hipStream_t st);
 rt_status march_cube(const rt_problem *p, const Geometry &g, const Shade &s, float *cube, hipStream_t st);
+// dl = dL/dcube; or dl == NULL and target != NULL: the cotangent of the L2
+// loss sum (cube - target)^2, formed inside the reverse march from its own
+// forward sweep (cube_opt then receives the cube)
 rt_status adjoint_core(const rt_problem *p, const float *dl, const rt_grads *g, float *cube_opt, hipStream_t st,
-                       const float4 *mlp_o, float4 *dO);
-rt_status adjoint_mlp(const rt_problem *p, const float *dl, const rt_grads *g, float *cube_opt, hipStream_t st);
-rt_status adjoint_grid(const rt_problem *p, const float *dl, const rt_grads *g, float *cube_opt, hipStream_t st);
+                       const float4 *mlp_o, float4 *dO, const float *target = nullptr);
+rt_status adjoint_mlp(const rt_problem *p, const float *dl, const rt_grads *g, float *cube_opt, hipStream_t st,
+                      const float *target = nullptr);
+rt_status adjoint_grid(const rt_problem *p, const float *dl, const rt_grads *g, float *cube_opt, hipStream_t st,
+                       const float *target = nullptr);
+// sum (cube - target)^2 into loss (device double), after the cube is written
+hipError_t launch_l2_value(const float *cube, const float *target, size_t n, double *loss, hipStream_t st);
 
 } // namespace rt

@@ -48,7 +48,8 @@ rt_status render_cube_mlp(const rt_problem *p, float *cube, hipStream_t st) {
     return march_cube(p, geo, sh, cube, st);
 }
 
-rt_status adjoint_mlp(const rt_problem *p, const float *dl, const rt_grads *g, float *cube_opt, hipStream_t st) {
+rt_status adjoint_mlp(const rt_problem *p, const float *dl, const rt_grads *g, float *cube_opt, hipStream_t st,
+                      const float *target) {
     if (p->spec.nch > kLaunchChannels)
         return fail(RT_EINVAL, "the neural CO layer adjoint takes at most %d channels per call", kLaunchChannels);
     Geometry geo;
@@ -59,7 +60,7 @@ rt_status adjoint_mlp(const rt_problem *p, const float *dl, const rt_grads *g, f
     void *dO = nullptr;
     rt_status rs = mlp_setup(p, &geo, &sh, &w, &ws, &o, sizeof(float4), &dO, st);
     if (rs != RT_OK) return rs;
-    rs = adjoint_core(p, dl, g, cube_opt, st, o, (float4 *)dO);
+    rs = adjoint_core(p, dl, g, cube_opt, st, o, (float4 *)dO, target);
     if (rs != RT_OK) return rs;
     if (g->d_mlp) {
         hipError_t e = zero_async(g->d_mlp, RT_MLP_PARAMS, st);

@@ -10,6 +10,7 @@
 // workgroups; each pulls the next item index from a device counter until the
 // batch is exhausted, so items of small and large requests of the batch share
 // the GPU.  Every wave exits once the counter passes the item count.
+#include "rt_host.h"
 #include "rt_serve.h"
 
 namespace rt {
@@ -125,6 +126,31 @@ __global__ __launch_bounds__(256) void l2_loss(const float *__restrict__ cube, c
 }
 
 __global__ void zero_double(double *p) { *p = 0.0; }
+
+// L = sum (cube - target)^2 (double atomics)
+__global__ __launch_bounds__(256) void l2_value(const float *__restrict__ cube, const float *__restrict__ target,
+                                                size_t n, double *__restrict__ loss) {
+    __shared__ double part[256];
+    double acc = 0.0;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+        const double r = (double)cube[i] - (double)target[i];
+        acc += r * r;
+    }
+    part[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) part[threadIdx.x] += part[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicAdd(loss, part[0]);
+}
+
+hipError_t launch_l2_value(const float *cube, const float *target, size_t n, double *loss, hipStream_t st) {
+    hipLaunchKernelGGL(zero_double, dim3(1), dim3(1), 0, st, loss);
+    const int blocks = (int)std::min<size_t>((n + 255) / 256, 2048);
+    hipLaunchKernelGGL(l2_value, dim3(blocks), dim3(256), 0, st, cube, target, n, loss);
+    return hipGetLastError();
+}
 
 hipError_t launch_l2_loss(const float *cube, const float *target, float *dl, size_t n, double *loss, hipStream_t st) {
     hipLaunchKernelGGL(zero_double, dim3(1), dim3(1), 0, st, loss);

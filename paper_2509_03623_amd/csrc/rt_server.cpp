@@ -65,7 +65,6 @@ struct Lane {
     size_t vch_cap = 0;
     uint32_t *d_counter = nullptr;
     double *d_loss = nullptr, *h_loss = nullptr;
-    float *dl = nullptr;       // cotangent of a gradient request (stream-ordered allocation)
 };
 
 __global__ void zero_u32(uint32_t *p) { *p = 0u; }
@@ -100,7 +99,7 @@ uint64_t footprint(const rt_request &r) {
     if (p.mlp) b += 4ull * RT_MLP_PARAMS + 16 * M + (1u << 20);
     if (r.kind == RT_REQ_FWD_ADJ) {
         const int ch = std::min(p.spec.nch, kLaunchChannels);
-        b += 2 * cube + 4 * (3 * nn + 2 * nr) + 8 * (3 * nn + 2 * nr);   // target, dl, grads, accumulators
+        b += cube + 4 * (3 * nn + 2 * nr) + 8 * (3 * nn + 2 * nr);   // target, grads, accumulators
         // tape, rays, checkpoints, cotangents of one band of rows
         const uint64_t row = adjoint_bytes_per_pixel(ch, p.nsamp) * (uint64_t)p.cam.nx;
         b += std::min<uint64_t>(row * p.cam.ny, std::max<uint64_t>(row, adjoint_scratch_cap() / row * row));
@@ -166,31 +165,29 @@ rt_status launch_batch(rt_server *sv, Lane &L, std::vector<Req *> &batch) {
     return RT_OK;
 }
 
-// a request on a stream of its own: neural forward, or forward + L2 loss + adjoint
+// a request on a stream of its own: a large or neural forward, or the fused
+// forward + L2 loss + adjoint (the reverse march forms dL/dI = 2 (I - D) from
+// its own forward sweep and writes the cube)
 rt_status launch_single(Lane &L, Req *r) {
     const rt_request &q = r->rq;
     const rt_problem *p = &q.problem;
     rt_status rs;
-    if (p->mlp) {
-        rs = render_cube_mlp(p, q.cube, L.st);
-    } else {
-        Geometry g;
-        Shade s;
-        rs = build_launch(p, &g, &s);
-        if (rs == RT_OK) rs = march_cube(p, g, s, q.cube, L.st);
+    if (q.kind == RT_REQ_FWD_ADJ) {
+        rs = p->mlp ? adjoint_mlp(p, nullptr, &q.grads, q.cube, L.st, q.target)
+                    : adjoint_grid(p, nullptr, &q.grads, q.cube, L.st, q.target);
+        if (rs != RT_OK) return rs;
+        const size_t n = (size_t)p->spec.nch * p->cam.nx * p->cam.ny;
+        hipError_t e = launch_l2_value(q.cube, q.target, n, L.d_loss, L.st);
+        if (e == hipSuccess) e = hipMemcpyAsync(L.h_loss, L.d_loss, sizeof(double), hipMemcpyDeviceToHost, L.st);
+        if (e != hipSuccess) return fail_hip(e, "loss");
+        return RT_OK;
     }
-    if (rs != RT_OK || q.kind != RT_REQ_FWD_ADJ) return rs;
-    const size_t n = (size_t)p->spec.nch * p->cam.nx * p->cam.ny;
-    hipError_t e = hipMallocAsync((void **)&L.dl, n * sizeof(float), L.st);
-    if (e != hipSuccess) { L.dl = nullptr; return fail_hip(e, "server cotangent"); }
-    if ((e = launch_l2_loss(q.cube, q.target, L.dl, n, L.d_loss, L.st)) != hipSuccess) return fail_hip(e, "loss");
-    rs = p->mlp ? adjoint_mlp(p, L.dl, &q.grads, nullptr, L.st) : adjoint_grid(p, L.dl, &q.grads, nullptr, L.st);
-    if (rs != RT_OK) return rs;
-    e = hipFreeAsync(L.dl, L.st);
-    L.dl = nullptr;
-    if (e == hipSuccess) e = hipMemcpyAsync(L.h_loss, L.d_loss, sizeof(double), hipMemcpyDeviceToHost, L.st);
-    if (e != hipSuccess) return fail_hip(e, "loss readback");
-    return RT_OK;
+    if (p->mlp) return render_cube_mlp(p, q.cube, L.st);
+    Geometry g;
+    Shade s;
+    rs = build_launch(p, &g, &s);
+    if (rs == RT_OK) rs = march_cube(p, g, s, q.cube, L.st);
+    return rs;
 }
 
 void scheduler(rt_server *sv) {

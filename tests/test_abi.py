@@ -19,7 +19,7 @@ HEADER = os.path.join(os.path.dirname(__file__), "..", "include", "rtcube.h")
 def declared_functions():
     src = open(HEADER).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(rt_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(rt_[a-z0-9_]+)\s*\(", src)))
 
 
 def test_library_exports_every_declared_symbol():
@@ -87,6 +87,10 @@ def test_null_outputs_rejected():
     p, keep, fake = _struct_for(prob)
     assert L.lib().rt_render_cube(C.byref(p), None, None) == L.RT_EINVAL
     assert L.lib().rt_render_cube(None, fake, None) == L.RT_EINVAL
+    g = L.rt_grads()
+    assert L.lib().rt_render_cube_l2_adjoint(C.byref(p), None, C.byref(g), fake, None, None) == L.RT_EINVAL
+    assert L.lib().rt_render_cube_l2_adjoint(C.byref(p), fake, C.byref(g), None, None, None) == L.RT_EINVAL
+    assert L.lib().rt_render_cube_l2_adjoint(C.byref(p), fake, None, fake, None, None) == L.RT_EINVAL
 
 
 def test_options_roundtrip():

@@ -225,3 +225,37 @@ def test_full_size_gradient_vs_central_differences():
             assert abs(g[idx] - fd) <= 1e-3 * abs(fd), (name, idx)
             checked += 1
     assert checked == 8
+
+
+@pytest.mark.parametrize("cap", [0, 400_000])
+def test_fused_l2_adjoint_equals_render_plus_adjoint(cap):
+    """rt_render_cube_l2_adjoint (one pass: the reverse march forms
+    dL/dI = 2 (I - D) from its own forward sweep) against rt_render_cube, the
+    loss in FP64 on the host, and rt_render_cube_adjoint with that cotangent;
+    also with the image differentiated in row bands."""
+    rt = _rt()
+    from paper_2509_03623_amd import _lib as L
+    prob = kscale(synth.small_problem(nx=19, ny=17, nch=37, nsamp=61, nr=40, nz=20, seed=21, dv=0.1))
+    target = target_for(prob)
+    sc = rt.scene_from_problem(prob)
+    tgt = torch.as_tensor(target, dtype=torch.float32, device="cuda")
+    print(f"[gpu] fused L2 adjoint cap={cap}", flush=True)
+    rt.set_option(L.RT_OPT_ADJ_SCRATCH_CAP, cap)
+    try:
+        cube, loss, g = rt.render_l2_adjoint(sc, tgt, want=BLOCKS)
+    finally:
+        rt.set_option(L.RT_OPT_ADJ_SCRATCH_CAP, 0)
+    direct = rt.render(sc)
+    ref = rt.render_adjoint(sc, 2.0 * (direct - tgt), want=BLOCKS)
+    torch.cuda.synchronize()
+    scale = float(direct.abs().max())
+    assert float((cube - direct).abs().max()) <= 1e-6 * scale
+    l_ref = float(((direct.double() - tgt.double()) ** 2).sum())
+    assert float(loss.item()) == pytest.approx(l_ref, rel=1e-5)
+    for k in BLOCKS:
+        s_ = float(ref[k].abs().max())
+        assert float((g[k] - ref[k]).abs().max()) <= 1e-4 * s_, k
+    _, oref = torch_ref.loss_and_grad(prob, target)
+    for k in BLOCKS:
+        r, g_ = oref[k].ravel(), g[k].cpu().numpy().astype(np.float64).ravel()
+        assert float(np.linalg.norm(g_ - r) / np.linalg.norm(r)) <= 1e-3, k
