@@ -29,13 +29,15 @@ if ROOT not in sys.path:
 LANE_SLOTS_PER_S = 256 * 128 * 2.4e9
 TRANS_SLOTS = 4
 # Algorithmic work of one ray-sample in the channel loop: d = a - v b (FMA),
-# d^2, g = 2^-d^2, x = K g, att = 2^-x, 1 - att, Tr (1 - att), I += . S (FMA),
-# Tr *= att  ->  11 FLOP (FMA = 2, transcendental = 1) in 7 VALU + 2 TRANS.
-LOOP_FLOP, LOOP_VALU, LOOP_TRANS = 11, 7, 2
+# x = K 2^-d^2 = 2^(log2 K - d^2) (FMA + exp2), att = 2^-x, 1 - att,
+# Tr (1 - att), I += . S (FMA), Tr *= att  ->  11 FLOP (FMA = 2,
+# transcendental = 1) in 6 VALU + 2 TRANS.
+LOOP_FLOP, LOOP_VALU, LOOP_TRANS = 11, 6, 2
 # Channel-independent shading of one pixel-sample, shared by the channels of
 # a lane: position, grid fetch and bilinear interpolation, density, CO mask,
-# partition function, populations, source function, width, projected velocity.
-SHADE_FLOP, SHADE_VALU, SHADE_TRANS = 150, 100, 14
+# partition function, populations, source function, width, projected
+# velocity, log2 of the line-centre depth.
+SHADE_FLOP, SHADE_VALU, SHADE_TRANS = 151, 100, 15
 
 
 # HBM traffic of one forward launch on the full-size render of disk 2000,

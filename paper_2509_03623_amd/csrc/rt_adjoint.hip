@@ -74,10 +74,11 @@ __global__ __launch_bounds__(256) void adj_march(int nsamp, int npix, int plane,
             const int k = seg * KSEG + kk;
             if (k < nsamp) {
                 const float4 q = tape[(size_t)k * npix + pix];
+                const float lK = flog2(q.y);    // K 2^-d^2 = 2^(log2 K - d^2)
 #pragma unroll
                 for (int c = 0; c < CB; ++c) {
                     const float d = fmaf(-ch.v[c0 + c], q.w, q.z);
-                    const float att = fexp2(-(q.y * fexp2(-(d * d))));
+                    const float att = fexp2(-fexp2(fmaf(-d, d, lK)));
                     I[c] = fmaf(Tr[c] * (1.0f - att), q.x, I[c]);
                     Tr[c] *= att;
                 }
@@ -107,11 +108,12 @@ __global__ __launch_bounds__(256) void adj_march(int nsamp, int npix, int plane,
         for (int kk = 0; kk < KSEG; ++kk) {
             const int k = seg * KSEG + kk;
             Q[kk] = k < nsamp ? tape[(size_t)k * npix + pix] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            const float lK = flog2(Q[kk].y);
 #pragma unroll
             for (int c = 0; c < CB; ++c) {
                 TrK[kk][c] = Tr[c];
                 const float d = fmaf(-ch.v[c0 + c], Q[kk].w, Q[kk].z);
-                Tr[c] *= fexp2(-(Q[kk].y * fexp2(-(d * d))));
+                Tr[c] *= fexp2(-fexp2(fmaf(-d, d, lK)));
             }
         }
 #pragma unroll
