@@ -43,13 +43,13 @@ SHADE_FLOP, SHADE_VALU, SHADE_TRANS = 151, 100, 15
 # HBM traffic of one forward launch on the full-size render of disk 2000,
 # from two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch)
 # of `bench.py --copy-probe`, each scaled by what the same counter reads for
-# a 1 GiB device-to-device copy (FETCH_SIZE 524 308 KiB -> x2.0000,
+# a 1 GiB device-to-device copy (FETCH_SIZE 524 304 KiB -> x2.0000,
 # WRITE_SIZE 1 048 576 KiB -> x1.0000).  Valid only for the kernel sources it
 # was taken on: the hash of those files is checked at run time.
 FWD_TRAFFIC = {"sources": ("paper_2509_03623_amd/csrc/rt_forward.hip", "paper_2509_03623_amd/csrc/rt_kernels.h",
                            "paper_2509_03623_amd/csrc/rt_launch.h"),
-               "sha256": "5e3d79517883a52699726ac6582c9a5035d03cc2d44f530b04d55d915fab5b2e",
-               "fetch_kib": 1237.3, "fetch_scale": 1048576 / 524308.2,
+               "sha256": "dfa0a9ad4b8c05969b1bd0ac5619c155321e9d63a1b281c07ba8d04fbfe7b939",
+               "fetch_kib": 1266.0, "fetch_scale": 1048576 / 524303.5,
                "write_kib": 65536.0, "write_scale": 1.0}
 
 
