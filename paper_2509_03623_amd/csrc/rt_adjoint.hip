@@ -248,13 +248,17 @@ __global__ __launch_bounds__(256) void adj_chain(Geometry g, Shade s, const floa
     }
 }
 
+// lanes per workgroup of the privatised chain pass: one workgroup fills a CU's
+// LDS, so it brings sixteen waves to keep the CU busy
+constexpr int kChainThreads = 1024;
+
 // Chain pass with the gradient of one field privatised in LDS.  Persistent
 // workgroups each take a contiguous share of the pixel-samples, accumulate
 // field FIELD (0 ln n, 1 T, 2 v_phi, 3 none) over the whole grid in LDS
 // (float), and flush it once with double atomics; the FIRST pass also
 // accumulates the two surface vectors (LDS, double) and writes dL/do.
 template <int FIELD, bool FIRST>
-__global__ __launch_bounds__(256) void adj_chain_lds(Geometry g, Shade s, const float4 *__restrict__ rays,
+__global__ __launch_bounds__(kChainThreads) void adj_chain_lds(Geometry g, Shade s, const float4 *__restrict__ rays,
                                                      float4 *__restrict__ cot, int nblk, GradAcc go,
                                                      float4 *__restrict__ dO) {
     extern __shared__ double dyn[];              // [2 nr] surfaces (FIRST), then [nr nz] field (float)
@@ -262,15 +266,15 @@ __global__ __launch_bounds__(256) void adj_chain_lds(Geometry g, Shade s, const 
     const int nr = s.nr, nn = s.nr * s.nz;
     double *surf = dyn;
     float *field = (float *)(dyn + (FIRST ? 2 * nr : 0));
-    for (int i = threadIdx.x; i < kZTableNodes - 1; i += 256) ztab[i] = s.ztab[i];
-    if (FIELD < 3) for (int i = threadIdx.x; i < nn; i += 256) field[i] = 0.0f;
-    if (FIRST) for (int i = threadIdx.x; i < 2 * nr; i += 256) surf[i] = 0.0;
+    for (int i = threadIdx.x; i < kZTableNodes - 1; i += kChainThreads) ztab[i] = s.ztab[i];
+    if (FIELD < 3) for (int i = threadIdx.x; i < nn; i += kChainThreads) field[i] = 0.0f;
+    if (FIRST) for (int i = threadIdx.x; i < 2 * nr; i += kChainThreads) surf[i] = 0.0;
     __syncthreads();
     const int npix = g.nx * g.ny;
     const size_t total = (size_t)g.nsamp * npix;
     const size_t per = (total + gridDim.x - 1) / gridDim.x;
     const size_t lo = (size_t)blockIdx.x * per, hi = lo + per < total ? lo + per : total;
-    for (size_t idx = lo + threadIdx.x; idx < hi; idx += 256) {
+    for (size_t idx = lo + threadIdx.x; idx < hi; idx += kChainThreads) {
         const int k = (int)(idx / npix);
         const int pix = (int)(idx - (size_t)k * npix);
         const float4 r = rays[pix];
@@ -339,10 +343,10 @@ __global__ __launch_bounds__(256) void adj_chain_lds(Geometry g, Shade s, const 
     __syncthreads();
     double *dst = FIELD == 0 ? go.ln_n : (FIELD == 1 ? go.temp : (FIELD == 2 ? go.vphi : nullptr));
     if (FIELD < 3 && dst)
-        for (int i = threadIdx.x; i < nn; i += 256)
+        for (int i = threadIdx.x; i < nn; i += kChainThreads)
             if (field[i] != 0.0f) atomicAdd(dst + i, (double)field[i]);
     if (FIRST)
-        for (int i = threadIdx.x; i < nr; i += 256) {
+        for (int i = threadIdx.x; i < nr; i += kChainThreads) {
             if (go.zlo && surf[i] != 0.0) atomicAdd(go.zlo + i, surf[i]);
             if (go.zup && surf[nr + i] != 0.0) atomicAdd(go.zup + i, surf[nr + i]);
         }
@@ -354,7 +358,7 @@ static hipError_t launch_chain_lds_t(const Geometry &g, const Shade &s, const fl
     hipError_t e = hipFuncSetAttribute((const void *)adj_chain_lds<FIELD, FIRST>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((adj_chain_lds<FIELD, FIRST>), dim3(nwg), dim3(256), shmem, st, g, s, rays, cot, nblk, go, dO);
+    hipLaunchKernelGGL((adj_chain_lds<FIELD, FIRST>), dim3(nwg), dim3(kChainThreads), shmem, st, g, s, rays, cot, nblk, go, dO);
     return hipGetLastError();
 }
 
@@ -373,7 +377,7 @@ hipError_t launch_adj_chain_lds(const Geometry &g, const Shade &s, const float4 
     if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return e;
     const size_t total = (size_t)g.nsamp * g.nx * g.ny;
-    const int nwg = (int)std::min<size_t>((size_t)ncu, (total + 255) / 256);
+    const int nwg = (int)std::min<size_t>((size_t)ncu, (total + kChainThreads - 1) / kChainThreads);
     const size_t fb = (size_t)s.nr * s.nz * sizeof(float), sb = 2 * (size_t)s.nr * sizeof(double);
     const bool want[3] = {go.ln_n != nullptr, go.temp != nullptr, go.vphi != nullptr};
     bool first = true;
