@@ -22,6 +22,8 @@
 
 namespace rt {
 
+// blockIdx.y selects a chunk of the samples, so short images still give the
+// GPU enough lanes
 __global__ __launch_bounds__(256) void adj_tape(Geometry g, Shade s, float4 *__restrict__ tape,
                                                 float4 *__restrict__ rays) {
     __shared__ float4 ztab[kZTableNodes - 1];
@@ -30,9 +32,11 @@ __global__ __launch_bounds__(256) void adj_tape(Geometry g, Shade s, float4 *__r
     const int pix = blockIdx.x * 256 + threadIdx.x;
     if (pix >= npix) return;
     const RaySetup r = ray_setup(g, pix % g.nx, pix / g.nx);
-    rays[pix] = make_float4(r.px, r.pmy, r.pmz, r.live ? r.ds : 0.0f);
+    if (blockIdx.y == 0) rays[pix] = make_float4(r.px, r.pmy, r.pmz, r.live ? r.ds : 0.0f);
     const float half = 0.5f * (float)g.nsamp;
-    for (int k = 0; k < g.nsamp; ++k) {
+    const int len = (g.nsamp + gridDim.y - 1) / gridDim.y;
+    const int k0 = blockIdx.y * len, k1 = min(g.nsamp, k0 + len);
+    for (int k = k0; k < k1; ++k) {
         float4 o = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         if (r.live) {
             const float t = ((float)k + 0.5f - half) * r.ds;
@@ -448,7 +452,11 @@ hipError_t zero_async(float *p, size_t n, hipStream_t st) {
 
 hipError_t launch_adj_tape(const Geometry &g, const Shade &s, float4 *tape, float4 *rays, hipStream_t st) {
     const int npix = g.nx * g.ny;
-    hipLaunchKernelGGL(adj_tape, dim3((npix + 255) / 256), dim3(256), 0, st, g, s, tape, rays);
+    const int tiles = (npix + 255) / 256;
+    // sample chunks until about 16 waves per CU (of at least 32 samples each)
+    int chunks = 1;
+    while (chunks < 16 && (long)tiles * 4 * chunks < 16L * 256 && g.nsamp >= 64 * chunks) chunks *= 2;
+    hipLaunchKernelGGL(adj_tape, dim3(tiles, chunks), dim3(256), 0, st, g, s, tape, rays);
     return hipGetLastError();
 }
 
