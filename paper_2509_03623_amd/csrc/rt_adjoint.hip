@@ -475,9 +475,9 @@ hipError_t launch_adj_march(int cb, int kseg, int nsamp, int npix, int plane, co
                             hipStream_t st) {
 #define RT_MARCH_CASE(C, K) \
     if (cb == C && kseg == K) return launch_march_t<C, K>(nsamp, npix, plane, ch, tape, dl, target, ckpt, cot, cube_out, st);
-    RT_MARCH_CASE(8, 4) RT_MARCH_CASE(8, 8) RT_MARCH_CASE(8, 16)
-    RT_MARCH_CASE(16, 4) RT_MARCH_CASE(16, 8)
-    RT_MARCH_CASE(32, 4)
+    RT_MARCH_CASE(8, 2) RT_MARCH_CASE(8, 4) RT_MARCH_CASE(8, 8) RT_MARCH_CASE(8, 16)
+    RT_MARCH_CASE(16, 2) RT_MARCH_CASE(16, 4) RT_MARCH_CASE(16, 8)
+    RT_MARCH_CASE(32, 2) RT_MARCH_CASE(32, 4)
 #undef RT_MARCH_CASE
     return hipErrorInvalidValue;
 }

@@ -50,6 +50,7 @@ static int64_t g_opt_ckpt = 0;
 static int64_t g_opt_split = 0;
 static int64_t g_opt_accum = 1;
 static int64_t g_opt_adj_cap = 0;
+static int64_t g_opt_adj_cb = 0;
 
 // Launch shape of the forward march: channels per lane (cb) and lanes per
 // ray (nsplit).  Measured on MI355X: one channel block per pixel is best
@@ -83,6 +84,7 @@ int channel_block_for(int nch, long npix) {
 bool thin_series() { return g_opt_thin != 0; }
 int ckpt_segment_option() { return (int)g_opt_ckpt; }
 bool grad_accum_double() { return g_opt_accum != 0; }
+int adjoint_block_option() { return (int)g_opt_adj_cb; }
 size_t adjoint_scratch_cap() { return g_opt_adj_cap > 0 ? (size_t)g_opt_adj_cap : kAdjointScratchCap; }
 
 // ---------------------------------------------------------------- validation
@@ -384,6 +386,11 @@ rt_status rt_set_option(int32_t key, int64_t value) {
         if (value < 0) return fail(RT_EINVAL, "scratch cap must be >= 0");
         g_opt_adj_cap = value;
         return RT_OK;
+    case RT_OPT_ADJ_CHANNEL_BLOCK:
+        if (value != 0 && value != 8 && value != 16 && value != 32)
+            return fail(RT_EINVAL, "adjoint channel block must be 0, 8, 16 or 32");
+        g_opt_adj_cb = value;
+        return RT_OK;
     case RT_OPT_RAY_SPLIT:
         if (value != 0 && value != 1 && value != 2 && value != 4 && value != 8)
             return fail(RT_EINVAL, "ray split must be 0, 1, 2, 4 or 8");
@@ -402,6 +409,7 @@ int64_t rt_get_option(int32_t key) {
     case RT_OPT_RAY_SPLIT: return g_opt_split;
     case RT_OPT_GRAD_ACCUM: return g_opt_accum;
     case RT_OPT_ADJ_SCRATCH_CAP: return g_opt_adj_cap;
+    case RT_OPT_ADJ_CHANNEL_BLOCK: return g_opt_adj_cb;
     default: return -1;
     }
 }

@@ -14,9 +14,10 @@ rt_status build_launch(const rt_problem *p, Geometry *g, Shade *s);
 int channel_block_for(int nch, long npix);
 void forward_shape(int nch, long npix, int nsamp, int *cb, int *nsplit);
 // channels per lane and samples per checkpoint segment of the reverse march
-void adjoint_shape(int nch, int *cb, int *kseg);
+void adjoint_shape(int nch, long npix, int *cb, int *kseg);
 bool thin_series();
 int ckpt_segment_option();
+int adjoint_block_option();
 bool grad_accum_double();
 
 // Device scratch kept with a stream: the buffer of (current device, stream,
@@ -31,7 +32,7 @@ constexpr int kWsAdjoint = 0, kWsGradAcc = 1;
 constexpr size_t kAdjointScratchCap = (size_t)8 << 30;
 size_t adjoint_scratch_cap();
 // bytes of adjoint scratch per pixel for nch channels and nsamp samples
-size_t adjoint_bytes_per_pixel(int nch, int nsamp);
+size_t adjoint_bytes_per_pixel(int nch, long npix, int nsamp);
 
 rt_status render_cube_mlp(const rt_problem *p, float *cube, hipStream_t st);
 rt_status march_cube(const rt_problem *p, const Geometry &g, const Shade &s, float *cube, hipStream_t st);

@@ -259,3 +259,24 @@ def test_fused_l2_adjoint_equals_render_plus_adjoint(cap):
     for k in BLOCKS:
         r, g_ = oref[k].ravel(), g[k].cpu().numpy().astype(np.float64).ravel()
         assert float(np.linalg.norm(g_ - r) / np.linalg.norm(r)) <= 1e-3, k
+
+
+@pytest.mark.parametrize("cb,kseg", [(8, 2), (8, 16), (16, 2), (16, 8), (32, 2), (32, 4)])
+def test_reverse_march_shapes(cb, kseg):
+    """Every instantiated (channels per lane, samples per checkpoint segment)
+    of the reverse march against the oracle's gradient (37 channels: ragged
+    blocks; 61 samples: ragged segments)."""
+    rt = _rt()
+    from paper_2509_03623_amd import _lib as L
+    prob = kscale(synth.small_problem(nx=19, ny=17, nch=37, nsamp=61, nr=40, nz=20, seed=21, dv=0.1))
+    target = target_for(prob)
+    _, ref = torch_ref.loss_and_grad(prob, target)
+    rt.set_option(L.RT_OPT_ADJ_CHANNEL_BLOCK, cb)
+    rt.set_option(L.RT_OPT_CKPT_SEGMENT, kseg)
+    try:
+        got, _, _ = gpu_grads(prob, target, cotangent=2.0 * (oracle.render(prob) - target))
+    finally:
+        rt.set_option(L.RT_OPT_ADJ_CHANNEL_BLOCK, 0)
+        rt.set_option(L.RT_OPT_CKPT_SEGMENT, 0)
+    for k in BLOCKS:
+        check_block(k, got[k], ref[k])
