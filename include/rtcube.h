@@ -142,10 +142,13 @@ rt_status rt_render_cube(const rt_problem *p, float *cube, void *stream);
 
 /* Vector-Jacobian product of rt_render_cube: given dL/dcube [nch][ny][nx],
  * write the requested gradients of L w.r.t. the fields, surfaces and network
- * weights.  cube_opt (may be NULL) receives the forward cube.  The reverse
- * sweep recomputes each segment of samples from optical-depth checkpoints
- * instead of storing every sample.  Gradients use float atomics, so their
- * last bits may vary from run to run. */
+ * weights.  cube_opt (may be NULL) receives the forward cube.  Nothing per
+ * sample and channel is stored: the reverse sweep recomputes every sample's
+ * line terms from a per-sample tape and rebuilds its transmission from the
+ * ray's total optical depth (the single checkpoint per ray and channel) minus
+ * the depth behind it, or, with RT_OPT_CKPT_SEGMENT, from transmission
+ * checkpoints every few samples.  Gradients use atomics, so their last bits
+ * may vary from run to run. */
 rt_status rt_render_cube_adjoint(const rt_problem *p, const float *dl_dcube, const rt_grads *g,
                                  float *cube_opt, void *stream);
 
@@ -226,9 +229,13 @@ int32_t rt_constants(double *out, int32_t n);
  * the forward march (8, 16, 24, 32, 48 or 64; 0 = automatic).
  * RT_OPT_THIN_EXPM1: 1 evaluates 1 - e^-dtau of the forward march with a
  * series for small dtau, 0 (default) uses 1 - e^-dtau directly.
- * RT_OPT_CKPT_SEGMENT: samples per checkpoint segment of the adjoint (2, 4,
- * 8 or 16; 0 = automatic).  RT_OPT_ADJ_CHANNEL_BLOCK: channels per lane of
- * the adjoint's reverse march (8, 16 or 32; 0 = automatic).  RT_OPT_RAY_SPLIT: lanes sharing one ray in the forward
+ * RT_OPT_CKPT_SEGMENT: 0 (default) runs the adjoint's reverse march without
+ * checkpoints, rebuilding each transmission from the ray's total optical
+ * depth and the depth behind the sample; 2, 4, 8 or 16 selects the march
+ * that stores the transmission every that many samples and recomputes each
+ * segment from its checkpoint.  RT_OPT_ADJ_CHANNEL_BLOCK: channels per lane of
+ * the adjoint's reverse march (8, 16, 24 or 32; 0 = automatic; 24 only without
+ * checkpoints).  RT_OPT_RAY_SPLIT: lanes sharing one ray in the forward
  * march, each taking a consecutive sub-chord (1, 2, 4 or 8; 0 = automatic).
  * RT_OPT_GRAD_ACCUM: 1 (default) accumulates the field gradients of the
  * adjoint in double, 0 in float.  RT_OPT_ADJ_SCRATCH_CAP: bytes of adjoint

@@ -12,7 +12,15 @@
 //       J_{k-1} = S_k (1 - a_k) + a_k J_k,
 //   giving dI/dS_k = Tr_k (1 - a_k) and dI/ddtau_k = Tr_{k+1} (S_k - J_k)
 //   without the cancellation of I minus a prefix sum.  Channel sums of the
-//   per-sample cotangents (S, K, a, b) are written per channel block.
+//   per-sample cotangents (S, ln K, a, b) are written per channel block.
+// Pass B without checkpoints (adj_march_tau<CB, CUBE>, the default): the
+//   optical depth is additive, so the transmission in front of sample k is
+//   2^-(tau_tot - tau_suf(k)) with tau_suf the depth behind it.  A first
+//   back-to-front sweep adds up tau_tot (and, when the intensity is wanted,
+//   runs the J recurrence to the observer); the second sweep re-accumulates
+//   tau_suf in the same order, so the only state kept per (ray, channel) is
+//   the total depth, in a register, and nothing is written but the
+//   cotangents.
 // Pass C (adj_chain): one lane per pixel-sample recomputes the shading with
 //   its local derivatives, chains the cotangents to the interpolated fields
 //   and scatters them to the grid nodes (float atomics; the surface vectors
@@ -150,8 +158,126 @@ __global__ __launch_bounds__(256) void adj_march(int nsamp, int npix, int plane,
                 ca += gd;
                 cb = fmaf(-vc, gd, cb);
             }
-            cot[((size_t)blk * nsamp + k) * npix + pix] = make_float4(cS, cK * kLn2, ca, cb);
+            // the K slot carries dL/d ln K = K dL/dK
+            cot[((size_t)blk * nsamp + k) * npix + pix] = make_float4(cS, cK * (kLn2 * K), ca, cb);
         }
+    }
+}
+
+// Checkpoint-free reverse march.  Per sample and channel, with x = K 2^-d^2
+// the depth in log2 units (att = 2^-x) and t1 = Tr_{k+1}, t0 = Tr_k:
+//   dL/dS     += w t0 (1 - att)
+//   dL/dln K  += ln2 w t1 (S - J_k) x
+//   dL/dd      = -2 ln2^2 w t1 (S - J_k) x d, to a as 1 and to b as -v.
+// The prefix depth tau_tot - tau_suf is the small difference of two large
+// sums when the back of the ray is thick (tau_tot reaches 10^4 at line
+// centre), so both sums carry the rounding error of every addition in a
+// second float (Fast2Sum, exact when the larger operand comes first).
+// Sweep 1 sums tau_tot = th + tl, ordering the operands; sweep 2 starts its
+// running sum at -th and its error at -tl and adds the same x back to front,
+// where the running sum (minus the prefix depth plus x) is never the smaller
+// operand, so after sample k the pair holds minus the prefix depth of k to
+// within one rounding of the prefix itself.
+// Work items: one lane per pixel; the channel blocks of one 256-pixel tile
+// take workgroup ids 8 apart, so they run on one XCD at about the same time
+// and share the tile's tape through its L2.
+template <int CB, bool CUBE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CB <= 8 ? 6 : CB <= 16 ? 4 : CB <= 24 ? 3 : 2)))
+void adj_march_tau(int nsamp, int npix, int plane, int nblk, Channels ch,
+                                                     const float4 *__restrict__ tape,
+                                                     const float *__restrict__ dl_dcube,
+                                                     const float *__restrict__ target, float4 *__restrict__ cot,
+                                                     float *__restrict__ cube_out) {
+    const int id = blockIdx.x, r8 = id >> 3;
+    const int blk = r8 % nblk;
+    const int pix = ((r8 / nblk) * 8 + (id & 7)) * 256 + threadIdx.x;
+    if (pix >= npix) return;
+    const int c0 = blk * CB;
+    float th[CB], tl[CB], w[CB];
+    {
+        // sweep 1, back to front: total depth and (CUBE) J, which reaches I
+        float J[CB];
+#pragma unroll
+        for (int c = 0; c < CB; ++c) {
+            th[c] = 0.0f;
+            tl[c] = 0.0f;
+            J[c] = 0.0f;
+        }
+        // the next sample's tape entry is loaded one iteration ahead
+        float4 qn = tape[(size_t)(nsamp - 1) * npix + pix];
+#pragma unroll 1
+        for (int k = nsamp - 1; k >= 0; --k) {
+            const float4 q = qn;
+            qn = tape[(size_t)max(k - 1, 0) * npix + pix];
+            const float lK = flog2(q.y);
+#pragma unroll
+            for (int c = 0; c < CB; ++c) {
+                const float d = fmaf(-ch.v[c0 + c], q.w, q.z);
+                const float x = fexp2(fmaf(-d, d, lK));
+                // the error of th + x, exact with the larger operand first
+                // (both are >= 0, so their bit patterns order like the values)
+                const float sum = th[c] + x;
+                const unsigned ut = __float_as_uint(th[c]), ux = __float_as_uint(x);
+                tl[c] += __uint_as_float(min(ut, ux)) - (sum - __uint_as_float(max(ut, ux)));
+                th[c] = sum;
+                if (CUBE) J[c] = fmaf(-fexp2(-x), q.x - J[c], q.x);
+            }
+        }
+        // padding channels of the last block read a valid channel's plane and
+        // get w = 0
+#pragma unroll
+        for (int c = 0; c < CB; ++c) {
+            const bool valid = c0 + c < ch.n;
+            const size_t i = (size_t)min(c0 + c, ch.n - 1) * plane + pix;
+            if (CUBE && cube_out && valid) cube_out[i] = J[c];
+            const float wc = CUBE && target ? 2.0f * (J[c] - target[i]) : dl_dcube[i];
+            w[c] = valid ? wc : 0.0f;
+        }
+    }
+    // sweep 2, back to front: (sh, sl) = -(prefix depth) in front of the
+    // current sample; u = w Tr
+    float J[CB], u[CB];
+    float *const sh = th, *const sl = tl;
+#pragma unroll
+    for (int c = 0; c < CB; ++c) {
+        sh[c] = -th[c];
+        sl[c] = -tl[c];
+        J[c] = 0.0f;
+        u[c] = w[c] * fexp2(sh[c] + sl[c]);
+    }
+    float4 qn = tape[(size_t)(nsamp - 1) * npix + pix];
+#pragma unroll 1
+    for (int k = nsamp - 1; k >= 0; --k) {
+        const float4 q = qn;
+        qn = tape[(size_t)max(k - 1, 0) * npix + pix];
+        const float S = q.x, a = q.z, b = q.w;
+        const float lK = flog2(q.y);
+        // channel sums in two interleaved halves (shorter dependency chains)
+        float cS[2] = {0.0f, 0.0f}, cX[2] = {0.0f, 0.0f}, ca[2] = {0.0f, 0.0f}, cb[2] = {0.0f, 0.0f};
+#pragma unroll
+        for (int c = 0; c < CB; ++c) {
+            const int h = c & 1;
+            const float vc = ch.v[c0 + c];
+            const float d = fmaf(-vc, b, a);
+            const float x = fexp2(fmaf(-d, d, lK));
+            const float att = fexp2(-x);
+            const float smj = S - J[c];
+            const float gg = u[c] * smj * x;
+            J[c] = fmaf(-att, smj, S);
+            const float sum = sh[c] + x;
+            sl[c] += x - (sum - sh[c]);
+            sh[c] = sum;
+            const float u0 = w[c] * fexp2(sum + sl[c]);
+            cS[h] = fmaf(u0, 1.0f - att, cS[h]);
+            cX[h] += gg;
+            const float gd = gg * d;
+            ca[h] += gd;
+            cb[h] = fmaf(-vc, gd, cb[h]);
+            u[c] = u0;
+        }
+        const float m = -2.0f * kLn2 * kLn2;
+        cot[((size_t)blk * nsamp + k) * npix + pix] =
+            make_float4(cS[0] + cS[1], (cX[0] + cX[1]) * kLn2, (ca[0] + ca[1]) * m, (cb[0] + cb[1]) * m);
     }
 }
 
@@ -208,7 +334,7 @@ __global__ __launch_bounds__(256) void adj_chain(Geometry g, Shade s, const floa
             PhysTape tp;
             const SampleQ q = physics<true>(s, ztab, L, F, r.x, ds, &tp);
             const float gS = c.x, gK = c.y, ga = c.z, gb = c.w;
-            const float gKK = gK * q.K;                       // dK/d ln n = K
+            const float gKK = gK;  // dL/d ln K, and d ln K / d ln n = 1
             const float dlnK_dT = tp.rT * (s.el_log2e * kLn2 * tp.rT - tp.x / tp.em1 -
                                            tp.dZ / (tp.Z * kLn2) - 0.5f);
             const float dS_dT = q.S * (1.0f + tp.em1) / tp.em1 * tp.x * tp.rT;
@@ -308,7 +434,7 @@ __global__ __launch_bounds__(kChainThreads) void adj_chain_lds(Geometry g, Shade
             PhysTape tp;
             const SampleQ q = physics<true>(s, ztab, L, F, r.x, ds, &tp);
             const float gS = c.x, gK = c.y, ga = c.z, gb = c.w;
-            const float gKK = gK * q.K;
+            const float gKK = gK;
             float gv = 0.0f;
             if (FIELD == 0) gv = gKK;
             if (FIELD == 1 || FIRST) {
@@ -470,9 +596,29 @@ static hipError_t launch_march_t(int nsamp, int npix, int plane, const Channels 
     return hipGetLastError();
 }
 
+template <int CB, bool CUBE>
+static hipError_t launch_tau_t(int nsamp, int npix, int plane, const Channels &ch, const float4 *tape, const float *dl,
+                               const float *target, float4 *cot, float *cube_out, hipStream_t st) {
+    const int nblk = (ch.n + CB - 1) / CB;
+    const long ids = (long)((npix + 255) / 256 + 7) / 8 * 8 * nblk;
+    hipLaunchKernelGGL((adj_march_tau<CB, CUBE>), dim3((unsigned)ids), dim3(256), 0, st, nsamp, npix, plane, nblk, ch,
+                       tape, dl, target, cot, cube_out);
+    return hipGetLastError();
+}
+
 hipError_t launch_adj_march(int cb, int kseg, int nsamp, int npix, int plane, const Channels &ch, const float4 *tape,
                             const float *dl, const float *target, float *ckpt, float4 *cot, float *cube_out,
                             hipStream_t st) {
+    if (kseg == 0) {
+        const bool cube = target || cube_out;
+#define RT_TAU_CASE(C)                                                                                  \
+    if (cb == C)                                                                                       \
+        return cube ? launch_tau_t<C, true>(nsamp, npix, plane, ch, tape, dl, target, cot, cube_out, st) \
+                    : launch_tau_t<C, false>(nsamp, npix, plane, ch, tape, dl, target, cot, cube_out, st);
+        RT_TAU_CASE(8) RT_TAU_CASE(16) RT_TAU_CASE(24) RT_TAU_CASE(32)
+#undef RT_TAU_CASE
+        return hipErrorInvalidValue;
+    }
 #define RT_MARCH_CASE(C, K) \
     if (cb == C && kseg == K) return launch_march_t<C, K>(nsamp, npix, plane, ch, tape, dl, target, ckpt, cot, cube_out, st);
     RT_MARCH_CASE(8, 2) RT_MARCH_CASE(8, 4) RT_MARCH_CASE(8, 8) RT_MARCH_CASE(8, 16)

@@ -10,28 +10,35 @@
 
 namespace rt {
 
-// channels per lane and samples per checkpoint segment of the reverse march
-// 32 channels per lane when that pads no more than 16 would and the image
-// still gives at least 2048 waves (measured fastest at 512^2 x 64); else 16,
-// or 8 for at most 8 channels
-void adjoint_shape(int nch, long npix, int *cb, int *kseg) {
+// Reverse-march shape (measured): the largest block of {32, 24, 16} channels
+// per lane that pads at most an eighth of the channels and still gives 2048
+// waves; 32 only when the march forms the intensity (without it the 32-wide
+// form spills registers); else 16, or 8 for at most 8 channels.  The
+// checkpointed march (option) takes 8, 16 or 32 channels per lane.
+void adjoint_shape(int nch, long npix, bool cube, int *cb, int *kseg) {
     *cb = nch > 8 ? 16 : 8;
-    const int pad16 = (nch + 15) / 16 * 16 - nch, pad32 = (nch + 31) / 32 * 32 - nch;
-    if (nch > 16 && pad32 <= pad16 && npix * ((nch + 31) / 32) >= 2048L * 64) *cb = 32;
+    for (const int c : {32, 24}) {
+        const int nblk = (nch + c - 1) / c, pad = nblk * c - nch;
+        if ((c == 32 && !cube) || nch <= 16 || 8 * pad > nch || npix * nblk < 2048L * 64) continue;
+        *cb = c;
+        break;
+    }
     const int ocb = adjoint_block_option();
-    if (ocb == 8 || ocb == 16 || ocb == 32) *cb = ocb;
-    *kseg = 4;
+    if (ocb == 8 || ocb == 16 || ocb == 24 || ocb == 32) *cb = ocb;
+    *kseg = 0;
     const int opt = ckpt_segment_option();
     if (opt == 2 || opt == 4 || opt == 8 || opt == 16) *kseg = opt;
+    // the checkpointed march has no 24-channel form
+    if (*kseg && *cb == 24) *cb = 16;
     if (*cb == 16 && *kseg == 16) *kseg = 8;
     if (*cb == 32 && *kseg > 4) *kseg = 4;
 }
 
-size_t adjoint_bytes_per_pixel(int nch, long npix, int nsamp) {
+size_t adjoint_bytes_per_pixel(int nch, long npix, int nsamp, bool cube) {
     int cb, kseg;
-    adjoint_shape(std::min(nch, kLaunchChannels), npix, &cb, &kseg);
+    adjoint_shape(std::min(nch, kLaunchChannels), npix, cube, &cb, &kseg);
     const size_t ch = std::min(nch, kLaunchChannels), nblk = (ch + cb - 1) / cb;
-    const size_t nseg = ((size_t)nsamp + kseg - 1) / kseg;
+    const size_t nseg = kseg ? ((size_t)nsamp + kseg - 1) / kseg : 0;
     // tape, ray set-up, transmission checkpoints, per-block cotangents
     return 16 * (size_t)nsamp + 16 + 4 * nseg * nblk * cb + 16 * nblk * (size_t)nsamp;
 }
@@ -56,13 +63,18 @@ rt_status adjoint_core(const rt_problem *p, const float *dl, const rt_grads *g, 
     GradAcc go{g->d_ln_nh2 ? ab : nullptr, g->d_temp_k ? ab + nn : nullptr, g->d_vphi_kms ? ab + 2 * nn : nullptr,
                g->d_z_lo_au ? ab + 3 * nn : nullptr, g->d_z_up_au ? ab + 3 * nn + nr : nullptr};
     int cb, kseg;
-    adjoint_shape(std::min(p->spec.nch, kLaunchChannels), (long)p->cam.nx * p->cam.ny, &cb, &kseg);
-    const int nseg = (ns + kseg - 1) / kseg;
+    const bool cube = target || cube_opt;
+    adjoint_shape(std::min(p->spec.nch, kLaunchChannels), (long)p->cam.nx * p->cam.ny, cube, &cb, &kseg);
+    const int nseg = kseg ? (ns + kseg - 1) / kseg : 0;
     const size_t plane = (size_t)npix;
     const int nx = p->cam.nx, ny = p->cam.ny;
     // bands of image rows whose scratch fits the cap (at least one row)
-    const size_t row_bytes = adjoint_bytes_per_pixel(p->spec.nch, (long)nx * ny, ns) * (size_t)nx;
-    const int band = (int)std::max<size_t>(1, std::min<size_t>((size_t)ny, adjoint_scratch_cap() / row_bytes));
+    const size_t row_bytes = adjoint_bytes_per_pixel(p->spec.nch, (long)nx * ny, ns, cube) * (size_t)nx;
+    // (as few bands as the cap allows, of equal height: a thin last band
+    // would march its full rays on too few lanes)
+    const int band_max = (int)std::max<size_t>(1, std::min<size_t>((size_t)ny, adjoint_scratch_cap() / row_bytes));
+    const int nband = (ny + band_max - 1) / band_max;
+    const int band = (ny + nband - 1) / nband;
     const bool lds = grad_accum_double() && chain_lds_fits(p->grid.nr, p->grid.nz);
     for (int c0 = 0; c0 < p->spec.nch; c0 += kLaunchChannels) {
         Channels ch;

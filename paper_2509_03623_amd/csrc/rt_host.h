@@ -13,8 +13,10 @@ rt_status validate(const rt_problem *p);
 rt_status build_launch(const rt_problem *p, Geometry *g, Shade *s);
 int channel_block_for(int nch, long npix);
 void forward_shape(int nch, long npix, int nsamp, int *cb, int *nsplit);
-// channels per lane and samples per checkpoint segment of the reverse march
-void adjoint_shape(int nch, long npix, int *cb, int *kseg);
+// channels per lane and samples per checkpoint segment (0: none) of the
+// reverse march; cube: the march also forms the intensity (fused L2 loss or
+// a requested cube)
+void adjoint_shape(int nch, long npix, bool cube, int *cb, int *kseg);
 bool thin_series();
 int ckpt_segment_option();
 int adjoint_block_option();
@@ -32,7 +34,7 @@ constexpr int kWsAdjoint = 0, kWsGradAcc = 1;
 constexpr size_t kAdjointScratchCap = (size_t)8 << 30;
 size_t adjoint_scratch_cap();
 // bytes of adjoint scratch per pixel for nch channels and nsamp samples
-size_t adjoint_bytes_per_pixel(int nch, long npix, int nsamp);
+size_t adjoint_bytes_per_pixel(int nch, long npix, int nsamp, bool cube);
 
 rt_status render_cube_mlp(const rt_problem *p, float *cube, hipStream_t st);
 rt_status march_cube(const rt_problem *p, const Geometry &g, const Shade &s, float *cube, hipStream_t st);

@@ -100,8 +100,9 @@ uint64_t footprint(const rt_request &r) {
     if (r.kind == RT_REQ_FWD_ADJ) {
         const int ch = std::min(p.spec.nch, kLaunchChannels);
         b += cube + 4 * (3 * nn + 2 * nr) + 8 * (3 * nn + 2 * nr);   // target, grads, accumulators
-        // tape, rays, checkpoints, cotangents of one band of rows
-        const uint64_t row = adjoint_bytes_per_pixel(ch, (long)npix, p.nsamp) * (uint64_t)p.cam.nx;
+        // tape, rays, checkpoints, cotangents of one band of rows (gradient
+        // requests run the fused L2 adjoint, which forms the cube)
+        const uint64_t row = adjoint_bytes_per_pixel(ch, (long)npix, p.nsamp, true) * (uint64_t)p.cam.nx;
         b += std::min<uint64_t>(row * p.cam.ny, std::max<uint64_t>(row, adjoint_scratch_cap() / row * row));
         if (p.mlp) b += 16 * M + 4ull * RT_MLP_PARAMS;
     }

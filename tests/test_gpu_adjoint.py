@@ -261,11 +261,11 @@ def test_fused_l2_adjoint_equals_render_plus_adjoint(cap):
         assert float(np.linalg.norm(g_ - r) / np.linalg.norm(r)) <= 1e-3, k
 
 
-@pytest.mark.parametrize("cb,kseg", [(8, 2), (8, 16), (16, 2), (16, 8), (32, 2), (32, 4)])
+@pytest.mark.parametrize("cb,kseg", [(8, 0), (16, 0), (24, 0), (32, 0), (8, 2), (8, 16), (16, 2), (16, 8), (32, 2), (32, 4)])
 def test_reverse_march_shapes(cb, kseg):
-    """Every instantiated (channels per lane, samples per checkpoint segment)
-    of the reverse march against the oracle's gradient (37 channels: ragged
-    blocks; 61 samples: ragged segments)."""
+    """Every instantiated (channels per lane, samples per checkpoint segment;
+    0 = the checkpoint-free march) of the reverse march against the oracle's
+    gradient (37 channels: ragged blocks; 61 samples: ragged segments)."""
     rt = _rt()
     from paper_2509_03623_amd import _lib as L
     prob = kscale(synth.small_problem(nx=19, ny=17, nch=37, nsamp=61, nr=40, nz=20, seed=21, dv=0.1))
