@@ -235,7 +235,10 @@ int32_t rt_constants(double *out, int32_t n);
  * that stores the transmission every that many samples and recomputes each
  * segment from its checkpoint.  RT_OPT_ADJ_CHANNEL_BLOCK: channels per lane of
  * the adjoint's reverse march (8, 16, 24 or 32; 0 = automatic; 24 only without
- * checkpoints).  RT_OPT_RAY_SPLIT: lanes sharing one ray in the forward
+ * checkpoints).  RT_OPT_ADJ_PIXEL_LANES: lanes sharing one pixel in the
+ * checkpoint-free reverse march, each with its own channel block, their
+ * per-sample sums added across the lanes (1 or 2; 0 = automatic).
+ * RT_OPT_RAY_SPLIT: lanes sharing one ray in the forward
  * march, each taking a consecutive sub-chord (1, 2, 4 or 8; 0 = automatic).
  * RT_OPT_GRAD_ACCUM: 1 (default) accumulates the field gradients of the
  * adjoint in double, 0 in float.  RT_OPT_ADJ_SCRATCH_CAP: bytes of adjoint
@@ -244,7 +247,8 @@ int32_t rt_constants(double *out, int32_t n);
  * rows, at least one row per band (0 = default, 8 GiB).  The library keeps
  * that scratch with the stream it ran on and reuses it on later calls. */
 enum { RT_OPT_CHANNEL_BLOCK = 1, RT_OPT_THIN_EXPM1 = 2, RT_OPT_CKPT_SEGMENT = 3, RT_OPT_RAY_SPLIT = 4,
-       RT_OPT_GRAD_ACCUM = 5, RT_OPT_ADJ_SCRATCH_CAP = 6, RT_OPT_ADJ_CHANNEL_BLOCK = 7 };
+       RT_OPT_GRAD_ACCUM = 5, RT_OPT_ADJ_SCRATCH_CAP = 6, RT_OPT_ADJ_CHANNEL_BLOCK = 7,
+       RT_OPT_ADJ_PIXEL_LANES = 8 };
 rt_status rt_set_option(int32_t key, int64_t value);
 int64_t rt_get_option(int32_t key);
 

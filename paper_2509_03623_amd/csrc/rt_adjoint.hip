@@ -178,21 +178,40 @@ __global__ __launch_bounds__(256) void adj_march(int nsamp, int npix, int plane,
 // where the running sum (minus the prefix depth plus x) is never the smaller
 // operand, so after sample k the pair holds minus the prefix depth of k to
 // within one rounding of the prefix itself.
-// Work items: one lane per pixel; the channel blocks of one 256-pixel tile
-// take workgroup ids 8 apart, so they run on one XCD at about the same time
-// and share the tile's tape through its L2.
-template <int CB, bool CUBE>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CB <= 8 ? 6 : CB <= 16 ? 4 : CB <= 24 ? 3 : 2)))
-void adj_march_tau(int nsamp, int npix, int plane, int nblk, Channels ch,
-                                                     const float4 *__restrict__ tape,
-                                                     const float *__restrict__ dl_dcube,
-                                                     const float *__restrict__ target, float4 *__restrict__ cot,
-                                                     float *__restrict__ cube_out) {
+// value of the other lane of an adjacent pair (DPP quad permutation 1,0,3,2)
+__device__ __forceinline__ float swap_pair(float x) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0xB1, 0xF, 0xF, false));
+}
+
+// Work items: G adjacent lanes per pixel, each with CB channels (G = 2: the
+// pair's channel sums are added across the two lanes, so one cotangent slice
+// is written per G CB channels and the pair reads each tape entry once); the
+// channel blocks of one tile take workgroup ids 8 apart, so they run on one
+// XCD at about the same time and share the tile's tape through its L2.
+template <int CB, int G, bool CUBE>
+__global__ __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(CB * G <= 8 ? 6 : CB <= 16 && G == 1 ? 4 : CB <= 24 && G == 1 ? 3 : 2)))
+void adj_march_tau(int nsamp, int npix, int plane, int nblk, Channels ch, const float4 *__restrict__ tape,
+                   const float *__restrict__ dl_dcube, const float *__restrict__ target, float4 *__restrict__ cot,
+                   float *__restrict__ cube_out) {
+    static_assert(G == 1 || G == 2, "one or two lanes per pixel");
     const int id = blockIdx.x, r8 = id >> 3;
     const int blk = r8 % nblk;
-    const int pix = ((r8 / nblk) * 8 + (id & 7)) * 256 + threadIdx.x;
-    if (pix >= npix) return;
-    const int c0 = blk * CB;
+    const int g = G == 1 ? 0 : (int)(threadIdx.x & 1);
+    const int pix = ((r8 / nblk) * 8 + (id & 7)) * (256 / G) + (int)threadIdx.x / G;
+    if (pix >= npix) return;   // both lanes of a pixel leave together
+    const int c0 = (blk * G + g) * CB;
+    // channel velocities: scalar registers with one lane per pixel, vector
+    // registers when the lanes of a pixel take different channels
+    float vv[G > 1 ? CB : 1];
+    if constexpr (G > 1) {
+#pragma unroll
+        for (int c = 0; c < CB; ++c) vv[c] = g ? ch.v[blk * G * CB + CB + c] : ch.v[blk * G * CB + c];
+    }
+    auto vel = [&](int c) -> float {
+        if constexpr (G > 1) return vv[c];
+        else return ch.v[c0 + c];
+    };
     float th[CB], tl[CB], w[CB];
     {
         // sweep 1, back to front: total depth and (CUBE) J, which reaches I
@@ -212,7 +231,7 @@ void adj_march_tau(int nsamp, int npix, int plane, int nblk, Channels ch,
             const float lK = flog2(q.y);
 #pragma unroll
             for (int c = 0; c < CB; ++c) {
-                const float d = fmaf(-ch.v[c0 + c], q.w, q.z);
+                const float d = fmaf(-vel(c), q.w, q.z);
                 const float x = fexp2(fmaf(-d, d, lK));
                 // the error of th + x, exact with the larger operand first
                 // (both are >= 0, so their bit patterns order like the values)
@@ -257,7 +276,7 @@ void adj_march_tau(int nsamp, int npix, int plane, int nblk, Channels ch,
 #pragma unroll
         for (int c = 0; c < CB; ++c) {
             const int h = c & 1;
-            const float vc = ch.v[c0 + c];
+            const float vc = vel(c);
             const float d = fmaf(-vc, b, a);
             const float x = fexp2(fmaf(-d, d, lK));
             const float att = fexp2(-x);
@@ -276,8 +295,14 @@ void adj_march_tau(int nsamp, int npix, int plane, int nblk, Channels ch,
             u[c] = u0;
         }
         const float m = -2.0f * kLn2 * kLn2;
-        cot[((size_t)blk * nsamp + k) * npix + pix] =
-            make_float4(cS[0] + cS[1], (cX[0] + cX[1]) * kLn2, (ca[0] + ca[1]) * m, (cb[0] + cb[1]) * m);
+        float4 o = make_float4(cS[0] + cS[1], (cX[0] + cX[1]) * kLn2, (ca[0] + ca[1]) * m, (cb[0] + cb[1]) * m);
+        if constexpr (G == 2) {
+            o.x += swap_pair(o.x);
+            o.y += swap_pair(o.y);
+            o.z += swap_pair(o.z);
+            o.w += swap_pair(o.w);
+        }
+        if (g == 0) cot[((size_t)blk * nsamp + k) * npix + pix] = o;
     }
 }
 
@@ -596,29 +621,32 @@ static hipError_t launch_march_t(int nsamp, int npix, int plane, const Channels 
     return hipGetLastError();
 }
 
-template <int CB, bool CUBE>
+template <int CB, int G, bool CUBE>
 static hipError_t launch_tau_t(int nsamp, int npix, int plane, const Channels &ch, const float4 *tape, const float *dl,
                                const float *target, float4 *cot, float *cube_out, hipStream_t st) {
-    const int nblk = (ch.n + CB - 1) / CB;
-    const long ids = (long)((npix + 255) / 256 + 7) / 8 * 8 * nblk;
-    hipLaunchKernelGGL((adj_march_tau<CB, CUBE>), dim3((unsigned)ids), dim3(256), 0, st, nsamp, npix, plane, nblk, ch,
-                       tape, dl, target, cot, cube_out);
+    const int nblk = (ch.n + G * CB - 1) / (G * CB);
+    const long tiles = (npix + 256 / G - 1) / (256 / G);
+    const long ids = (tiles + 7) / 8 * 8 * nblk;
+    hipLaunchKernelGGL((adj_march_tau<CB, G, CUBE>), dim3((unsigned)ids), dim3(256), 0, st, nsamp, npix, plane, nblk,
+                       ch, tape, dl, target, cot, cube_out);
     return hipGetLastError();
 }
 
-hipError_t launch_adj_march(int cb, int kseg, int nsamp, int npix, int plane, const Channels &ch, const float4 *tape,
-                            const float *dl, const float *target, float *ckpt, float4 *cot, float *cube_out,
-                            hipStream_t st) {
+hipError_t launch_adj_march(int cb, int kseg, int lanes, int nsamp, int npix, int plane, const Channels &ch,
+                            const float4 *tape, const float *dl, const float *target, float *ckpt, float4 *cot,
+                            float *cube_out, hipStream_t st) {
     if (kseg == 0) {
         const bool cube = target || cube_out;
-#define RT_TAU_CASE(C)                                                                                  \
-    if (cb == C)                                                                                       \
-        return cube ? launch_tau_t<C, true>(nsamp, npix, plane, ch, tape, dl, target, cot, cube_out, st) \
-                    : launch_tau_t<C, false>(nsamp, npix, plane, ch, tape, dl, target, cot, cube_out, st);
-        RT_TAU_CASE(8) RT_TAU_CASE(16) RT_TAU_CASE(24) RT_TAU_CASE(32)
+#define RT_TAU_CASE(C, G)                                                                                  \
+    if (cb == C && lanes == G)                                                                            \
+        return cube ? launch_tau_t<C, G, true>(nsamp, npix, plane, ch, tape, dl, target, cot, cube_out, st) \
+                    : launch_tau_t<C, G, false>(nsamp, npix, plane, ch, tape, dl, target, cot, cube_out, st);
+        RT_TAU_CASE(8, 1) RT_TAU_CASE(16, 1) RT_TAU_CASE(24, 1) RT_TAU_CASE(32, 1)
+        RT_TAU_CASE(16, 2) RT_TAU_CASE(24, 2) RT_TAU_CASE(32, 2)
 #undef RT_TAU_CASE
         return hipErrorInvalidValue;
     }
+    if (lanes != 1) return hipErrorInvalidValue;
 #define RT_MARCH_CASE(C, K) \
     if (cb == C && kseg == K) return launch_march_t<C, K>(nsamp, npix, plane, ch, tape, dl, target, ckpt, cot, cube_out, st);
     RT_MARCH_CASE(8, 2) RT_MARCH_CASE(8, 4) RT_MARCH_CASE(8, 8) RT_MARCH_CASE(8, 16)

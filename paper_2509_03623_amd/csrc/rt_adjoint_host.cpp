@@ -10,34 +10,52 @@
 
 namespace rt {
 
-// Reverse-march shape (measured): the largest block of {32, 24, 16} channels
-// per lane that pads at most an eighth of the channels and still gives 2048
-// waves; 32 only when the march forms the intensity (without it the 32-wide
-// form spills registers); else 16, or 8 for at most 8 channels.  The
-// checkpointed march (option) takes 8, 16 or 32 channels per lane.
-void adjoint_shape(int nch, long npix, bool cube, int *cb, int *kseg) {
+// Reverse-march shape (measured): the first of (channels per lane, lanes per
+// pixel) = (32, 2), (24, 2), (16, 2), (32, 1), (24, 1) whose channel group
+// pads at most an eighth of the channels and still gives 2048 waves; (32, 1)
+// only when the march forms the intensity (without it that form spills
+// registers); else (16, 1), or (8, 1) for at most 8 channels.  Pairs write one
+// cotangent slice per 2 CB channels (at 512^2 x 64: 10.9 ms fused with
+// (32, 2) against 11.8 ms with (32, 1)).  The checkpointed march (option)
+// takes 8, 16 or 32 channels per lane and one lane per pixel.
+void adjoint_shape(int nch, long npix, bool cube, int *cb, int *lanes, int *kseg) {
     *cb = nch > 8 ? 16 : 8;
-    for (const int c : {32, 24}) {
-        const int nblk = (nch + c - 1) / c, pad = nblk * c - nch;
-        if ((c == 32 && !cube) || nch <= 16 || 8 * pad > nch || npix * nblk < 2048L * 64) continue;
+    *lanes = 1;
+    static const int cand[][2] = {{32, 2}, {24, 2}, {16, 2}, {32, 1}, {24, 1}};
+    for (const auto &cl : cand) {
+        const int c = cl[0], gl = cl[1], grp = c * gl;
+        const int nblk = (nch + grp - 1) / grp, pad = nblk * grp - nch;
+        if ((c == 32 && gl == 1 && !cube) || nch <= 16 || 8 * pad > nch || npix * nblk * gl < 2048L * 64) continue;
         *cb = c;
+        *lanes = gl;
         break;
     }
     const int ocb = adjoint_block_option();
     if (ocb == 8 || ocb == 16 || ocb == 24 || ocb == 32) *cb = ocb;
+    const int olanes = adjoint_lanes_option();
+    if (olanes == 1 || olanes == 2) *lanes = olanes;
+    if (*lanes == 2 && *cb == 8) {
+        // no 2 x 8 form: a pair asked for explicitly widens the block,
+        // otherwise the 8-channel block keeps one lane per pixel
+        if (olanes == 2) *cb = 16;
+        else *lanes = 1;
+    }
     *kseg = 0;
     const int opt = ckpt_segment_option();
     if (opt == 2 || opt == 4 || opt == 8 || opt == 16) *kseg = opt;
-    // the checkpointed march has no 24-channel form
-    if (*kseg && *cb == 24) *cb = 16;
-    if (*cb == 16 && *kseg == 16) *kseg = 8;
-    if (*cb == 32 && *kseg > 4) *kseg = 4;
+    if (*kseg) {
+        // the checkpointed march has no 24-channel and no paired form
+        *lanes = 1;
+        if (*cb == 24) *cb = 16;
+        if (*cb == 16 && *kseg == 16) *kseg = 8;
+        if (*cb == 32 && *kseg > 4) *kseg = 4;
+    }
 }
 
 size_t adjoint_bytes_per_pixel(int nch, long npix, int nsamp, bool cube) {
-    int cb, kseg;
-    adjoint_shape(std::min(nch, kLaunchChannels), npix, cube, &cb, &kseg);
-    const size_t ch = std::min(nch, kLaunchChannels), nblk = (ch + cb - 1) / cb;
+    int cb, lanes, kseg;
+    adjoint_shape(std::min(nch, kLaunchChannels), npix, cube, &cb, &lanes, &kseg);
+    const size_t ch = std::min(nch, kLaunchChannels), nblk = (ch + lanes * cb - 1) / (lanes * cb);
     const size_t nseg = kseg ? ((size_t)nsamp + kseg - 1) / kseg : 0;
     // tape, ray set-up, transmission checkpoints, per-block cotangents
     return 16 * (size_t)nsamp + 16 + 4 * nseg * nblk * cb + 16 * nblk * (size_t)nsamp;
@@ -62,9 +80,9 @@ rt_status adjoint_core(const rt_problem *p, const float *dl, const rt_grads *g, 
     if ((e = zero_async_d(ab, acc_n, st)) != hipSuccess) return fail_hip(e, "zero");
     GradAcc go{g->d_ln_nh2 ? ab : nullptr, g->d_temp_k ? ab + nn : nullptr, g->d_vphi_kms ? ab + 2 * nn : nullptr,
                g->d_z_lo_au ? ab + 3 * nn : nullptr, g->d_z_up_au ? ab + 3 * nn + nr : nullptr};
-    int cb, kseg;
+    int cb, lanes, kseg;
     const bool cube = target || cube_opt;
-    adjoint_shape(std::min(p->spec.nch, kLaunchChannels), (long)p->cam.nx * p->cam.ny, cube, &cb, &kseg);
+    adjoint_shape(std::min(p->spec.nch, kLaunchChannels), (long)p->cam.nx * p->cam.ny, cube, &cb, &lanes, &kseg);
     const int nseg = kseg ? (ns + kseg - 1) / kseg : 0;
     const size_t plane = (size_t)npix;
     const int nx = p->cam.nx, ny = p->cam.ny;
@@ -81,7 +99,7 @@ rt_status adjoint_core(const rt_problem *p, const float *dl, const rt_grads *g, 
         std::memset(&ch, 0, sizeof ch);
         ch.n = std::min(kLaunchChannels, p->spec.nch - c0);
         for (int c = 0; c < ch.n; ++c) ch.v[c] = (float)p->spec.v_kms[c0 + c];
-        const int nblk = (ch.n + cb - 1) / cb;
+        const int nblk = (ch.n + lanes * cb - 1) / (lanes * cb);   // cotangent slices
         for (int q0 = 0; q0 < ny; q0 += band) {
             const int rows = std::min(band, ny - q0);
             const int bpix = rows * nx;
@@ -103,7 +121,7 @@ rt_status adjoint_core(const rt_problem *p, const float *dl, const rt_grads *g, 
             float4 *cot = (float4 *)(base + tape_b + rays_b + ckpt_b);
             if ((e = launch_adj_tape(gb, sb, tape, rays, st)) != hipSuccess) return fail_hip(e, "adjoint tape");
             const size_t off = (size_t)c0 * plane + pix0;
-            if ((e = launch_adj_march(cb, kseg, ns, bpix, (int)plane, ch, tape, dl ? dl + off : nullptr,
+            if ((e = launch_adj_march(cb, kseg, lanes, ns, bpix, (int)plane, ch, tape, dl ? dl + off : nullptr,
                                       target ? target + off : nullptr, ckpt, cot,
                                       cube_opt ? cube_opt + off : nullptr, st)) != hipSuccess)
                 return fail_hip(e, "adjoint march");

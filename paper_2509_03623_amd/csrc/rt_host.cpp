@@ -51,6 +51,7 @@ static int64_t g_opt_split = 0;
 static int64_t g_opt_accum = 1;
 static int64_t g_opt_adj_cap = 0;
 static int64_t g_opt_adj_cb = 0;
+static int64_t g_opt_adj_lanes = 0;
 
 // Launch shape of the forward march: channels per lane (cb) and lanes per
 // ray (nsplit).  Measured on MI355X: one channel block per pixel is best
@@ -85,6 +86,7 @@ bool thin_series() { return g_opt_thin != 0; }
 int ckpt_segment_option() { return (int)g_opt_ckpt; }
 bool grad_accum_double() { return g_opt_accum != 0; }
 int adjoint_block_option() { return (int)g_opt_adj_cb; }
+int adjoint_lanes_option() { return (int)g_opt_adj_lanes; }
 size_t adjoint_scratch_cap() { return g_opt_adj_cap > 0 ? (size_t)g_opt_adj_cap : kAdjointScratchCap; }
 
 // ---------------------------------------------------------------- validation
@@ -391,6 +393,11 @@ rt_status rt_set_option(int32_t key, int64_t value) {
             return fail(RT_EINVAL, "adjoint channel block must be 0, 8, 16, 24 or 32");
         g_opt_adj_cb = value;
         return RT_OK;
+    case RT_OPT_ADJ_PIXEL_LANES:
+        if (value != 0 && value != 1 && value != 2)
+            return fail(RT_EINVAL, "adjoint lanes per pixel must be 0, 1 or 2");
+        g_opt_adj_lanes = value;
+        return RT_OK;
     case RT_OPT_RAY_SPLIT:
         if (value != 0 && value != 1 && value != 2 && value != 4 && value != 8)
             return fail(RT_EINVAL, "ray split must be 0, 1, 2, 4 or 8");
@@ -410,6 +417,7 @@ int64_t rt_get_option(int32_t key) {
     case RT_OPT_GRAD_ACCUM: return g_opt_accum;
     case RT_OPT_ADJ_SCRATCH_CAP: return g_opt_adj_cap;
     case RT_OPT_ADJ_CHANNEL_BLOCK: return g_opt_adj_cb;
+    case RT_OPT_ADJ_PIXEL_LANES: return g_opt_adj_lanes;
     default: return -1;
     }
 }

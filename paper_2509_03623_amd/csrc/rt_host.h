@@ -13,13 +13,14 @@ rt_status validate(const rt_problem *p);
 rt_status build_launch(const rt_problem *p, Geometry *g, Shade *s);
 int channel_block_for(int nch, long npix);
 void forward_shape(int nch, long npix, int nsamp, int *cb, int *nsplit);
-// channels per lane and samples per checkpoint segment (0: none) of the
-// reverse march; cube: the march also forms the intensity (fused L2 loss or
-// a requested cube)
-void adjoint_shape(int nch, long npix, bool cube, int *cb, int *kseg);
+// channels per lane, lanes per pixel and samples per checkpoint segment (0:
+// none) of the reverse march; cube: the march also forms the intensity (fused
+// L2 loss or a requested cube)
+void adjoint_shape(int nch, long npix, bool cube, int *cb, int *lanes, int *kseg);
 bool thin_series();
 int ckpt_segment_option();
 int adjoint_block_option();
+int adjoint_lanes_option();
 bool grad_accum_double();
 
 // Device scratch kept with a stream: the buffer of (current device, stream,

@@ -55,10 +55,15 @@ __device__ __forceinline__ size_t o_index(const Shade &s, int k, int pix) {
     return (size_t)k * (size_t)s.o_plane + (size_t)s.o_pix0 + (size_t)pix;
 }
 
+// Velocities of one launch's channels.  A kernel's last channel block may
+// extend past n (and past kLaunchChannels, e.g. 11 blocks of 24 for 256
+// channels); those padding lanes read the zeros after the n velocities, so
+// the array runs one largest block (64) beyond kLaunchChannels.  Filled by
+// the host after zeroing the whole struct.
 struct Channels {
     int32_t n;               // channels in this launch
     int32_t pad_;
-    float v[kLaunchChannels];
+    float v[kLaunchChannels + 64];
 };
 
 // ---------------------------------------------------------------- math

@@ -109,4 +109,8 @@ def test_options_roundtrip():
     assert lib.rt_set_option(L.RT_OPT_ADJ_CHANNEL_BLOCK, 32) == 0
     assert lib.rt_get_option(L.RT_OPT_ADJ_CHANNEL_BLOCK) == 32
     assert lib.rt_set_option(L.RT_OPT_ADJ_CHANNEL_BLOCK, 0) == 0
+    assert lib.rt_set_option(L.RT_OPT_ADJ_PIXEL_LANES, 3) == L.RT_EINVAL
+    assert lib.rt_set_option(L.RT_OPT_ADJ_PIXEL_LANES, 2) == 0
+    assert lib.rt_get_option(L.RT_OPT_ADJ_PIXEL_LANES) == 2
+    assert lib.rt_set_option(L.RT_OPT_ADJ_PIXEL_LANES, 0) == 0
     assert lib.rt_set_option(999, 1) == L.RT_EINVAL

@@ -261,22 +261,27 @@ def test_fused_l2_adjoint_equals_render_plus_adjoint(cap):
         assert float(np.linalg.norm(g_ - r) / np.linalg.norm(r)) <= 1e-3, k
 
 
-@pytest.mark.parametrize("cb,kseg", [(8, 0), (16, 0), (24, 0), (32, 0), (8, 2), (8, 16), (16, 2), (16, 8), (32, 2), (32, 4)])
-def test_reverse_march_shapes(cb, kseg):
-    """Every instantiated (channels per lane, samples per checkpoint segment;
-    0 = the checkpoint-free march) of the reverse march against the oracle's
-    gradient (37 channels: ragged blocks; 61 samples: ragged segments)."""
+@pytest.mark.parametrize("cb,lanes,kseg", [(8, 1, 0), (16, 1, 0), (24, 1, 0), (32, 1, 0), (16, 2, 0), (24, 2, 0),
+                                            (32, 2, 0), (8, 1, 2), (8, 1, 16), (16, 1, 2), (16, 1, 8), (32, 1, 2),
+                                            (32, 1, 4)])
+def test_reverse_march_shapes(cb, lanes, kseg):
+    """Every instantiated (channels per lane, lanes per pixel, samples per
+    checkpoint segment; 0 = the checkpoint-free march) of the reverse march
+    against the oracle's gradient (37 channels: ragged blocks; 61 samples:
+    ragged segments)."""
     rt = _rt()
     from paper_2509_03623_amd import _lib as L
     prob = kscale(synth.small_problem(nx=19, ny=17, nch=37, nsamp=61, nr=40, nz=20, seed=21, dv=0.1))
     target = target_for(prob)
     _, ref = torch_ref.loss_and_grad(prob, target)
     rt.set_option(L.RT_OPT_ADJ_CHANNEL_BLOCK, cb)
+    rt.set_option(L.RT_OPT_ADJ_PIXEL_LANES, lanes)
     rt.set_option(L.RT_OPT_CKPT_SEGMENT, kseg)
     try:
         got, _, _ = gpu_grads(prob, target, cotangent=2.0 * (oracle.render(prob) - target))
     finally:
         rt.set_option(L.RT_OPT_ADJ_CHANNEL_BLOCK, 0)
+        rt.set_option(L.RT_OPT_ADJ_PIXEL_LANES, 0)
         rt.set_option(L.RT_OPT_CKPT_SEGMENT, 0)
     for k in BLOCKS:
         check_block(k, got[k], ref[k])
