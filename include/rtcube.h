@@ -163,6 +163,56 @@ rt_status rt_render_cube_adjoint(const rt_problem *p, const float *dl_dcube, con
 rt_status rt_render_cube_l2_adjoint(const rt_problem *p, const float *target, const rt_grads *g, float *cube,
                                     double *loss, void *stream);
 
+/* ------------------------------------------------------- derived fields */
+/* Fields derived from a temperature grid, as the physics-informed
+ * constraints of Methods > Neural temperature recovery derive them (equations
+ * of Methods > Parametric disk modeling):
+ *   - n_H2 from vertical hydrostatic equilibrium, Eq. gas_density_temp,
+ *     integrated up each column from the midplane and normalised so that the
+ *     column holds the tapered power-law surface density
+ *     Sigma(r) = Sigma0 (r/r_c)^-gamma exp(-(r/r_c)^(2-gamma)),
+ *     Sigma0 = M_gas (2 - gamma) / (2 pi r_c^2); n_H2 = rho / (mu m_H);
+ *   - the vertical H2 column of Eq. column_density and from it the CO surfaces
+ *     of Eq. co_layer: z_up where 0.706 N_H2 = n_dissoc, z_lo where
+ *     T = t_freeze;
+ *   - v_phi from gravity and the radial pressure gradient,
+ *     Eq. gas_velocity_pressure, with P = n_H2 k_B T.
+ * Discretisation on the render grid (rt_grid): per radial node, the trapezoid
+ * rule on the z/r nodes for the gravity term and the column (the log-T term
+ * of the hydrostatic equation exactly); z_up log-linear in N between the last
+ * node above the threshold and the next (linear to the top node, where
+ * N = 0), -zr_max r when even the midplane is below it; z_lo linear in T
+ * between the last cold and the first warm node, -zr_max r for a warm
+ * midplane, 2 zr_max r for a column never warm; d ln P / d ln r at fixed
+ * height as central differences of ln(n T) along ln r and z/r on the node
+ * grid (one-sided at its edges); v_phi = sqrt(max(v^2, 0)).  The outputs are
+ * the ln_nh2, vphi_kms, z_lo_au and z_up_au of rt_fields.  Computed in FP32. */
+typedef struct {
+    rt_grid grid;
+    const float *temp_k;                 /* [nr][nz] device, > 0 */
+    double mstar_msun;                   /* stellar mass, >= 0 */
+    double mgas_msun, rc_au, gamma;      /* Sigma(r): M_gas > 0, r_c > 0, gamma < 2 */
+    double mu;                           /* mean molecular weight, m_mol = mu m_H */
+    double t_freeze_k, n_dissoc_cm2;     /* CO-layer thresholds, > 0 */
+} rt_derive;
+
+typedef struct {
+    float *ln_nh2, *vphi_kms;            /* [nr][nz] device */
+    float *z_lo_au, *z_up_au;            /* [nr] device */
+} rt_derived;
+
+/* Write every field of *out (all four required). */
+rt_status rt_derive_fields(const rt_derive *d, const rt_derived *out, void *stream);
+
+/* Vector-Jacobian product of rt_derive_fields: cot holds dL/d(each output)
+ * (read only; a NULL member counts as zero); d_temp_k [nr][nz] receives dL/dT
+ * through the derived fields (overwritten; the direct temperature gradient of
+ * rt_render_cube_adjoint is separate, and the caller adds the two).  The
+ * surfaces are differentiated with their bracketing nodes held at those the
+ * forward picks at this temperature.  Scratch of 5 nr nz floats is kept with
+ * the stream. */
+rt_status rt_derive_fields_adjoint(const rt_derive *d, const rt_derived *cot, float *d_temp_k, void *stream);
+
 /* ---------------------------------------------------------------- server */
 /* Continuous-batching render server on one GPU.  Requests are admitted in
  * arrival order while their HBM footprint (inputs, outputs and library

@@ -83,8 +83,19 @@ class rt_ticket_info(C.Structure):
                 ("ray_samples", C.c_uint64)]
 
 
+class rt_derive(C.Structure):
+    _fields_ = [("grid", rt_grid), ("temp_k", _dev), ("mstar_msun", C.c_double), ("mgas_msun", C.c_double),
+                ("rc_au", C.c_double), ("gamma", C.c_double), ("mu", C.c_double), ("t_freeze_k", C.c_double),
+                ("n_dissoc_cm2", C.c_double)]
+
+
+class rt_derived(C.Structure):
+    _fields_ = [("ln_nh2", _dev), ("vphi_kms", _dev), ("z_lo_au", _dev), ("z_up_au", _dev)]
+
+
 # every symbol declared in include/rtcube.h
-EXPORTS = ["rt_render_cube", "rt_render_cube_adjoint", "rt_render_cube_l2_adjoint", "rt_server_create", "rt_submit", "rt_poll", "rt_wait",
+EXPORTS = ["rt_render_cube", "rt_render_cube_adjoint", "rt_render_cube_l2_adjoint", "rt_derive_fields",
+           "rt_derive_fields_adjoint", "rt_server_create", "rt_submit", "rt_poll", "rt_wait",
            "rt_cancel", "rt_server_destroy", "rt_last_error", "rt_abi_version", "rt_constants",
            "rt_set_option", "rt_get_option"]
 
@@ -112,6 +123,10 @@ def lib():
         L.rt_render_cube_adjoint.restype = C.c_int
         L.rt_render_cube_l2_adjoint.argtypes = [P, _dev, C.POINTER(rt_grads), _dev, _dev, C.c_void_p]
         L.rt_render_cube_l2_adjoint.restype = C.c_int
+        L.rt_derive_fields.argtypes = [C.POINTER(rt_derive), C.POINTER(rt_derived), C.c_void_p]
+        L.rt_derive_fields.restype = C.c_int
+        L.rt_derive_fields_adjoint.argtypes = [C.POINTER(rt_derive), C.POINTER(rt_derived), _dev, C.c_void_p]
+        L.rt_derive_fields_adjoint.restype = C.c_int
         L.rt_server_create.argtypes = [C.POINTER(rt_server_cfg), C.POINTER(C.c_void_p)]
         L.rt_server_create.restype = C.c_int
         L.rt_submit.argtypes = [C.c_void_p, C.POINTER(rt_request), C.POINTER(C.c_uint64)]

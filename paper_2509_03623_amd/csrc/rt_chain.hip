@@ -1,0 +1,378 @@
+// rt_chain.hip -- fields derived from a temperature grid, and their adjoint.
+//
+// Methods, "Parametric Disk Modeling" (Eqs. gas_density_temp, column_density,
+// co_layer, gas_velocity_pressure) as used by "Neural Temperature Recovery"
+// (physics-informed constraints): n_H2 from vertical hydrostatic equilibrium
+// normalised to the surface density, the CO surfaces from the vertical column
+// and the freeze-out temperature, v_phi from gravity and the radial pressure
+// gradient.  The discretisation is stated in include/rtcube.h.
+//
+// The work is a few operations per grid node (3.3e4 nodes at 256 x 128), so
+// the scans along each column run in one lane per radial node and the
+// stencils in one lane per node; a call is a handful of microsecond-scale
+// launches next to a render of milliseconds.  Lengths are in au inside the
+// kernels (cm^3-scale powers would overflow float), with the unit factors
+// folded into the constants on the host.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+
+#include "../../include/rtcube.h"
+#include "rt_host.h"
+#include "rt_kernels.h"
+
+namespace rt {
+
+namespace {
+
+// cgs constants (CODATA 2018, IAU 2015 nominal)
+constexpr double kG = 6.67430e-8, kMsun = 1.98847e33, kAu = 1.495978707e13, kKb = 1.380649e-16,
+                 kMh = 1.6735575e-24;
+constexpr double kPhotoFactor = 0.706;   // vertical H2 column -> total gas column
+
+struct ChainArgs {
+    int nr, nz;
+    float r_min, dlog2r;      // r_i = r_min 2^(i dlog2r)
+    float du;                 // ln r step
+    float dzeta, zr_max;      // z/r step and top
+    float cg;                 // G M m_mol / (k_B au): gravity integrand in K au^-1 with lengths in au
+    float cn;                 // -ln(au) - ln(m_mol): ln n = ln Sigma - ln(2 int e^l dz[au]) + l + cn
+    float ln_sig0, gamma, inv_rc;   // ln Sigma = ln_sig0 - gamma ln x - x^(2 - gamma), x = r / r_c
+    float au_cm;              // column increments: n [cm^-3] dz [au] au_cm
+    float thr, ln_thr;        // N_dissoc / 0.706 and its log
+    float t_freeze;
+    float cv;                 // G M / au in (km/s)^2 au: v_K^2 = cv r^2 / (r^2 + z^2)^(3/2)
+    float ct;                 // k_B / m_mol in (km/s)^2 / K
+};
+
+__device__ __forceinline__ float node_r(const ChainArgs &a, int i) { return a.r_min * exp2f((float)i * a.dlog2r); }
+
+// the gravity integrand g z / T of node height z (au) for column radius r
+__device__ __forceinline__ float grav_h(const ChainArgs &a, float r, float z, float T) {
+    const float q = r * r + z * z;
+    return a.cg * z / (T * q * sqrtf(q));
+}
+
+__device__ __forceinline__ float ln_sigma(const ChainArgs &a, float r) {
+    const float lx = logf(r * a.inv_rc);
+    return a.ln_sig0 - a.gamma * lx - expf((2.0f - a.gamma) * lx);
+}
+
+// Per column: l_j = ln rho_j - ln rho_0 into lout, and ln rho_0 + cn returned.
+__device__ float column_ell(const ChainArgs &a, const float *Tc, float r, float *lout, float *h_out) {
+    const float dz = a.dzeta * r;
+    const float lnT0 = logf(Tc[0]);
+    float I = 0.0f, hprev = 0.0f, eprev = 1.0f, trap = 0.0f;
+    for (int j = 0; j < a.nz; ++j) {
+        const float T = Tc[j];
+        const float h = grav_h(a, r, (float)j * dz, T);
+        if (j > 0) I += 0.5f * (hprev + h) * dz;
+        const float l = -I - logf(T) + lnT0;
+        const float e = expf(l);
+        if (j > 0) trap += 0.5f * (eprev + e) * dz;
+        lout[j] = l;
+        if (h_out) h_out[j] = h;
+        hprev = h;
+        eprev = e;
+    }
+    return ln_sigma(a, r) - logf(2.0f * trap) + a.cn;
+}
+
+struct Crossings {
+    int up_a;          // node below the photodissociation crossing (-1: midplane unshielded)
+    float Na, Nb;      // columns at up_a and up_a + 1
+    int lo_b;          // first warm node (-1: warm midplane, nz: never warm)
+};
+
+// downward column from ln n (in ln_n[j]) and the two crossings; writes the surfaces
+__device__ Crossings column_surfaces(const ChainArgs &a, const float *ln_n, const float *Tc, float r, float *zlo,
+                                     float *zup) {
+    const float dz = a.dzeta * r;
+    Crossings c{-1, 0.0f, 0.0f, -1};
+    float N = 0.0f, nprev = expf(ln_n[a.nz - 1]);
+    bool found = false;
+    for (int j = a.nz - 2; j >= 0; --j) {
+        const float n = expf(ln_n[j]);
+        const float Nn = N + 0.5f * (n + nprev) * dz * a.au_cm;
+        if (!found && Nn > a.thr) {
+            found = true;
+            c.up_a = j;
+            c.Na = Nn;
+            c.Nb = N;
+        }
+        N = Nn;
+        nprev = n;
+    }
+    if (!found) {
+        *zup = -a.zr_max * r;
+    } else {
+        const float f = c.Nb > 0.0f ? (a.ln_thr - logf(c.Na)) / (logf(c.Nb) - logf(c.Na)) : (a.thr - c.Na) / (c.Nb - c.Na);
+        *zup = ((float)c.up_a + f) * dz;
+    }
+    if (Tc[0] > a.t_freeze) {
+        c.lo_b = -1;
+        *zlo = -a.zr_max * r;
+    } else {
+        int b = a.nz;
+        for (int j = 1; j < a.nz; ++j)
+            if (Tc[j] > a.t_freeze) { b = j; break; }
+        c.lo_b = b;
+        if (b == a.nz) *zlo = 2.0f * a.zr_max * r;
+        else *zlo = ((float)(b - 1) + (a.t_freeze - Tc[b - 1]) / (Tc[b] - Tc[b - 1])) * dz;
+    }
+    return c;
+}
+
+__global__ __launch_bounds__(64) void chain_columns(ChainArgs a, const float *__restrict__ T, float *__restrict__ ln_n,
+                                                    float *__restrict__ zlo, float *__restrict__ zup) {
+    const int i = blockIdx.x * 64 + threadIdx.x;
+    if (i >= a.nr) return;
+    const float r = node_r(a, i);
+    const float *Tc = T + (size_t)i * a.nz;
+    float *out = ln_n + (size_t)i * a.nz;
+    const float L0 = column_ell(a, Tc, r, out, nullptr);
+    for (int j = 0; j < a.nz; ++j) out[j] += L0;
+    column_surfaces(a, out, Tc, r, zlo + i, zup + i);
+}
+
+__device__ __forceinline__ float lnP(const float *ln_n, const float *T, int nz, int i, int j) {
+    return ln_n[(size_t)i * nz + j] + logf(T[(size_t)i * nz + j]);
+}
+
+// d ln P / d u and d ln P / d zeta at node (i, j): central differences, one-sided at the edges
+__device__ __forceinline__ void dlnP(const ChainArgs &a, const float *ln_n, const float *T, int i, int j, float *du,
+                                     float *dzeta) {
+    const int il = max(i - 1, 0), ih = min(i + 1, a.nr - 1);
+    const int jl = max(j - 1, 0), jh = min(j + 1, a.nz - 1);
+    *du = (lnP(ln_n, T, a.nz, ih, j) - lnP(ln_n, T, a.nz, il, j)) / ((float)(ih - il) * a.du);
+    *dzeta = (lnP(ln_n, T, a.nz, i, jh) - lnP(ln_n, T, a.nz, i, jl)) / ((float)(jh - jl) * a.dzeta);
+}
+
+__device__ __forceinline__ float vphi2(const ChainArgs &a, float r, float zeta, float T, float du, float dzeta) {
+    const float z = zeta * r;
+    const float q = r * r + z * z;
+    return a.cv * r * r / (q * sqrtf(q)) + a.ct * T * (du - zeta * dzeta);
+}
+
+__global__ __launch_bounds__(256) void chain_vphi(ChainArgs a, const float *__restrict__ T,
+                                                  const float *__restrict__ ln_n, float *__restrict__ vphi) {
+    const int idx = blockIdx.x * 256 + threadIdx.x;
+    if (idx >= a.nr * a.nz) return;
+    const int i = idx / a.nz, j = idx - i * a.nz;
+    float du, dz;
+    dlnP(a, ln_n, T, i, j, &du, &dz);
+    const float v2 = vphi2(a, node_r(a, i), (float)j * a.dzeta, T[idx], du, dz);
+    vphi[idx] = v2 > 0.0f ? sqrtf(v2) : 0.0f;
+}
+
+// ---- adjoint
+
+// per node: cotangents of the two difference quotients (eu, ez) and the
+// direct temperature term of v^2 (gT)
+__global__ __launch_bounds__(256) void chain_vphi_adj(ChainArgs a, const float *__restrict__ T,
+                                                      const float *__restrict__ ln_n, const float *__restrict__ vbar,
+                                                      float *__restrict__ eu, float *__restrict__ ez,
+                                                      float *__restrict__ gT) {
+    const int idx = blockIdx.x * 256 + threadIdx.x;
+    if (idx >= a.nr * a.nz) return;
+    const int i = idx / a.nz, j = idx - i * a.nz;
+    float du, dz;
+    dlnP(a, ln_n, T, i, j, &du, &dz);
+    const float zeta = (float)j * a.dzeta;
+    const float v2 = vphi2(a, node_r(a, i), zeta, T[idx], du, dz);
+    const float vb2 = (vbar && v2 > 0.0f) ? vbar[idx] * 0.5f / sqrtf(v2) : 0.0f;
+    gT[idx] = vb2 * a.ct * (du - zeta * dz);
+    eu[idx] = vb2 * a.ct * T[idx];
+    ez[idx] = -vb2 * a.ct * T[idx] * zeta;
+}
+
+// per node: gather the difference-quotient cotangents into d/d ln P, then
+// split it into d/d ln n (gn) and d/dT (added to gT)
+__global__ __launch_bounds__(256) void chain_lnp_adj(ChainArgs a, const float *__restrict__ T,
+                                                     const float *__restrict__ eu, const float *__restrict__ ez,
+                                                     float *__restrict__ gn, float *__restrict__ gT) {
+    const int idx = blockIdx.x * 256 + threadIdx.x;
+    if (idx >= a.nr * a.nz) return;
+    const int i = idx / a.nz, j = idx - i * a.nz;
+    float g = 0.0f;
+    for (int ii = max(i - 1, 0); ii <= min(i + 1, a.nr - 1); ++ii) {
+        const int il = max(ii - 1, 0), ih = min(ii + 1, a.nr - 1);
+        const float w = ((ih == i) ? 1.0f : 0.0f) - ((il == i) ? 1.0f : 0.0f);
+        if (w != 0.0f) g += w * eu[(size_t)ii * a.nz + j] / ((float)(ih - il) * a.du);
+    }
+    for (int jj = max(j - 1, 0); jj <= min(j + 1, a.nz - 1); ++jj) {
+        const int jl = max(jj - 1, 0), jh = min(jj + 1, a.nz - 1);
+        const float w = ((jh == j) ? 1.0f : 0.0f) - ((jl == j) ? 1.0f : 0.0f);
+        if (w != 0.0f) g += w * ez[(size_t)i * a.nz + jj] / ((float)(jh - jl) * a.dzeta);
+    }
+    gn[idx] = g;
+    gT[idx] += g / T[idx];
+}
+
+// per column: reverse of the column pass (crossings held fixed).  ls is a
+// column-length scratch row per radial node.
+__global__ __launch_bounds__(64) void chain_columns_adj(ChainArgs a, const float *__restrict__ T,
+                                                        const float *__restrict__ nbar, const float *__restrict__ zlobar,
+                                                        const float *__restrict__ zupbar,
+                                                        const float *__restrict__ gn, const float *__restrict__ gT,
+                                                        float *__restrict__ ls, float *__restrict__ lnn_s,
+                                                        float *__restrict__ dT) {
+    const int i = blockIdx.x * 64 + threadIdx.x;
+    if (i >= a.nr) return;
+    const int nz = a.nz;
+    const float r = node_r(a, i);
+    const float dz = a.dzeta * r;
+    const size_t o = (size_t)i * nz;
+    const float *Tc = T + o;
+    float *L = ls + o;          // l_j, then its cotangent
+    float *lnn = lnn_s + o;     // ln n_j
+    const float L0 = column_ell(a, Tc, r, L, nullptr);
+    for (int j = 0; j < nz; ++j) lnn[j] = L[j] + L0;
+    float zl, zu;
+    const Crossings c = column_surfaces(a, lnn, Tc, r, &zl, &zu);
+    // photodissociation surface -> the two columns it interpolates
+    float Nab = 0.0f, Nbb = 0.0f;
+    const float zub = zupbar ? zupbar[i] : 0.0f;
+    if (c.up_a >= 0 && zub != 0.0f) {
+        if (c.Nb > 0.0f) {
+            const float la = logf(c.Na), lb = logf(c.Nb), d = lb - la;
+            Nab = zub * dz * ((a.ln_thr - lb) / (d * d)) / c.Na;
+            Nbb = zub * dz * (-(a.ln_thr - la) / (d * d)) / c.Nb;
+        } else {
+            const float d = c.Nb - c.Na;
+            Nab = zub * dz * ((a.thr - c.Nb) / (d * d));
+            Nbb = zub * dz * (-(a.thr - c.Na) / (d * d));
+        }
+    }
+    // d L / d ln n_j: given, from v_phi, and from the two columns (N_k sums the
+    // trapezoid segments from node k up: n_j enters the segments below and
+    // above it)
+    const int ka = c.up_a, kb = c.up_a + 1;
+    auto dN_dn = [&](int k, int j) {   // d N_k / d n_j without the factor dz au/2
+        return (float)((j >= k + 1) ? 1 : 0) + (float)((j >= k && j <= nz - 2) ? 1 : 0);
+    };
+    float Gsum = 0.0f, trap = 0.0f;
+    for (int j = 0; j < nz; ++j) {
+        float g = (nbar ? nbar[o + j] : 0.0f) + gn[o + j];
+        if (ka >= 0) g += expf(lnn[j]) * 0.5f * dz * a.au_cm * (Nab * dN_dn(ka, j) + Nbb * dN_dn(kb, j));
+        Gsum += g;
+        const float w = (j == 0 || j == nz - 1) ? 0.5f : 1.0f;
+        trap += w * expf(L[j]);
+        lnn[j] = g;   // from here on: the cotangent of ln n
+    }
+    // ln n_j = l_j + ln rho_0 + const, ln rho_0 = ln Sigma - ln(2 dz sum w_j e^l_j)
+    for (int j = 0; j < nz; ++j) {
+        const float w = (j == 0 || j == nz - 1) ? 0.5f : 1.0f;
+        L[j] = lnn[j] - Gsum * w * expf(L[j]) / trap;
+    }
+    // l_j = -I_j - ln T_j + ln T_0; I_j = sum over segments below j of (h_s + h_s+1) dz / 2
+    float R = 0.0f, Rnext = 0.0f;   // suffix sums of the cotangent of l
+    const float t_f = a.t_freeze;
+    const float zlb = zlobar ? zlobar[i] : 0.0f;
+    for (int k = nz - 1; k >= 0; --k) {
+        Rnext = R;
+        R += L[k];
+        const float hb = -0.5f * dz * ((k <= nz - 2 ? Rnext : 0.0f) + (k >= 1 ? R : 0.0f));
+        const float Tk = Tc[k];
+        const float h = grav_h(a, r, (float)k * dz, Tk);
+        float g = -L[k] / Tk - hb * h / Tk + gT[o + k];
+        // freeze-out surface: linear in T between nodes lo_b - 1 and lo_b
+        if (zlb != 0.0f && c.lo_b > 0 && c.lo_b < nz) {
+            const int b = c.lo_b, aa = b - 1;
+            const float d = Tc[b] - Tc[aa];
+            if (k == aa) g += zlb * dz * (t_f - Tc[b]) / (d * d);
+            if (k == b) g -= zlb * dz * (t_f - Tc[aa]) / (d * d);
+        }
+        dT[o + k] = g;
+    }
+    dT[o] += R / Tc[0];
+}
+
+ChainArgs chain_args(const rt_derive *d) {
+    const rt_grid &g = d->grid;
+    ChainArgs a;
+    a.nr = g.nr;
+    a.nz = g.nz;
+    a.r_min = (float)g.r_min_au;
+    a.dlog2r = (float)(std::log2(g.r_max_au / g.r_min_au) / (g.nr - 1));
+    a.du = (float)(std::log(g.r_max_au / g.r_min_au) / (g.nr - 1));
+    a.dzeta = (float)(g.zr_max / (g.nz - 1));
+    a.zr_max = (float)g.zr_max;
+    const double m_mol = d->mu * kMh;
+    a.cg = (float)(kG * d->mstar_msun * kMsun * m_mol / (kKb * kAu));
+    a.cn = (float)(-std::log(kAu) - std::log(m_mol));
+    const double rc = d->rc_au * kAu;
+    a.ln_sig0 = (float)std::log(d->mgas_msun * kMsun * (2.0 - d->gamma) / (2.0 * M_PI * rc * rc));
+    a.gamma = (float)d->gamma;
+    a.inv_rc = (float)(1.0 / d->rc_au);
+    a.au_cm = (float)kAu;
+    a.thr = (float)(d->n_dissoc_cm2 / kPhotoFactor);
+    a.ln_thr = (float)std::log(d->n_dissoc_cm2 / kPhotoFactor);
+    a.t_freeze = (float)d->t_freeze_k;
+    a.cv = (float)(kG * d->mstar_msun * kMsun / kAu / 1e10);
+    a.ct = (float)(kKb / m_mol / 1e10);
+    return a;
+}
+
+rt_status validate_derive(const rt_derive *d) {
+    if (!d) return fail(RT_EINVAL, "derive parameters are NULL");
+    const rt_grid &g = d->grid;
+    if (g.nr < 2 || g.nz < 2) return fail(RT_EINVAL, "grid needs nr, nz >= 2");
+    if (!(g.r_min_au > 0.0) || !(g.r_max_au > g.r_min_au) || !(g.zr_max > 0.0))
+        return fail(RT_EINVAL, "grid needs 0 < r_min < r_max and zr_max > 0");
+    if ((size_t)g.nr * g.nz > (size_t)1 << 28) return fail(RT_EINVAL, "grid too large");
+    if (!d->temp_k) return fail(RT_EINVAL, "temp_k is NULL");
+    if (!(d->mstar_msun >= 0.0) || !(d->mgas_msun > 0.0) || !(d->rc_au > 0.0) || !(d->gamma < 2.0) || !(d->mu > 0.0))
+        return fail(RT_EINVAL, "need mstar >= 0, mgas > 0, rc > 0, gamma < 2, mu > 0");
+    if (!(d->t_freeze_k > 0.0) || !(d->n_dissoc_cm2 > 0.0)) return fail(RT_EINVAL, "thresholds must be > 0");
+    return RT_OK;
+}
+
+} // namespace
+
+} // namespace rt
+
+using namespace rt;
+
+extern "C" rt_status rt_derive_fields(const rt_derive *d, const rt_derived *out, void *stream) {
+    rt_status st = validate_derive(d);
+    if (st != RT_OK) return st;
+    if (!out || !out->ln_nh2 || !out->vphi_kms || !out->z_lo_au || !out->z_up_au)
+        return fail(RT_EINVAL, "every derived output must be given");
+    const ChainArgs a = chain_args(d);
+    hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(chain_columns, dim3((a.nr + 63) / 64), dim3(64), 0, s, a, d->temp_k, out->ln_nh2, out->z_lo_au,
+                       out->z_up_au);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail_hip(e, "derive columns");
+    const int n = a.nr * a.nz;
+    hipLaunchKernelGGL(chain_vphi, dim3((n + 255) / 256), dim3(256), 0, s, a, d->temp_k, out->ln_nh2, out->vphi_kms);
+    e = hipGetLastError();
+    return e == hipSuccess ? RT_OK : fail_hip(e, "derive v_phi");
+}
+
+extern "C" rt_status rt_derive_fields_adjoint(const rt_derive *d, const rt_derived *cot, float *d_temp_k,
+                                              void *stream) {
+    rt_status st = validate_derive(d);
+    if (st != RT_OK) return st;
+    if (!cot) return fail(RT_EINVAL, "cotangents are NULL");
+    if (!d_temp_k) return fail(RT_EINVAL, "d_temp_k is NULL");
+    const ChainArgs a = chain_args(d);
+    hipStream_t s = (hipStream_t)stream;
+    const size_t n = (size_t)a.nr * a.nz;
+    hipError_t e;
+    // scratch: eu / l, ez / ln n, gn, gT, and the forward ln n for the stencils
+    float *w = (float *)stream_workspace(s, kWsChain, sizeof(float) * 5 * n, &e);
+    if (!w) return fail_hip(e, "derive scratch");
+    float *eu = w, *ez = w + n, *gn = w + 2 * n, *gT = w + 3 * n, *lnn = w + 4 * n;
+    // forward ln n (and surfaces into discarded slots of gn) for the v_phi stencils
+    hipLaunchKernelGGL(chain_columns, dim3((a.nr + 63) / 64), dim3(64), 0, s, a, d->temp_k, lnn, gn, gn + a.nr);
+    hipLaunchKernelGGL(chain_vphi_adj, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a, d->temp_k, lnn,
+                       cot->vphi_kms, eu, ez, gT);
+    hipLaunchKernelGGL(chain_lnp_adj, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a, d->temp_k, eu, ez, gn, gT);
+    hipLaunchKernelGGL(chain_columns_adj, dim3((a.nr + 63) / 64), dim3(64), 0, s, a, d->temp_k, cot->ln_nh2,
+                       cot->z_lo_au, cot->z_up_au, gn, gT, eu, ez, d_temp_k);
+    e = hipGetLastError();
+    return e == hipSuccess ? RT_OK : fail_hip(e, "derive adjoint");
+}

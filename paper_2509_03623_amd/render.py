@@ -250,3 +250,72 @@ def constants() -> dict:
     out = (C.c_double * 6)()
     L.lib().rt_constants(out, 6)
     return dict(zip(["h", "k_B", "c", "amu", "au", "pi"], list(out)))
+
+
+@dataclass
+class DiskPhysics:
+    """Parameters of the fields derived from a temperature grid (rt_derive
+    without the grid and the temperature)."""
+    mstar_msun: float
+    mgas_msun: float
+    rc_au: float
+    gamma: float
+    mu: float = 2.37
+    t_freeze_k: float = 20.0
+    n_dissoc_cm2: float = 1e21
+
+
+def _derive_struct(grid, temp_k: torch.Tensor, phys: DiskPhysics):
+    nr, nz, r_min, r_max, zr_max = grid
+    if temp_k.shape != (nr, nz):
+        raise ValueError("temperature grid has the wrong shape")
+    g = L.rt_grid(int(nr), int(nz), float(r_min), float(r_max), float(zr_max))
+    return L.rt_derive(g, _fptr(temp_k), phys.mstar_msun, phys.mgas_msun, phys.rc_au, phys.gamma, phys.mu,
+                       phys.t_freeze_k, phys.n_dissoc_cm2)
+
+
+def derive_fields(grid, temp_k: torch.Tensor, phys: DiskPhysics, stream=None) -> dict:
+    """ln_nh2, vphi_kms [nr, nz] and z_lo_au, z_up_au [nr] derived from the
+    temperature grid; grid = (nr, nz, r_min_au, r_max_au, zr_max)."""
+    nr, nz = int(grid[0]), int(grid[1])
+    T = temp_k.contiguous()
+    dev = T.device
+    out = dict(ln_nh2=torch.empty(nr, nz, dtype=torch.float32, device=dev),
+               vphi_kms=torch.empty(nr, nz, dtype=torch.float32, device=dev),
+               z_lo_au=torch.empty(nr, dtype=torch.float32, device=dev),
+               z_up_au=torch.empty(nr, dtype=torch.float32, device=dev))
+    d = _derive_struct(grid, T, phys)
+    o = L.rt_derived(_fptr(out["ln_nh2"]), _fptr(out["vphi_kms"]), _fptr(out["z_lo_au"]), _fptr(out["z_up_au"]))
+    L.check(L.lib().rt_derive_fields(C.byref(d), C.byref(o), C.c_void_p(_stream(stream))))
+    return out
+
+
+def derive_fields_adjoint(grid, temp_k: torch.Tensor, phys: DiskPhysics, cot: dict, stream=None) -> torch.Tensor:
+    """dL/dT through the derived fields, given dL/d(each output) (missing
+    keys count as zero)."""
+    T = temp_k.contiguous()
+    c = {k: (None if cot.get(k) is None else cot[k].contiguous().to(torch.float32))
+         for k in ("ln_nh2", "vphi_kms", "z_lo_au", "z_up_au")}
+    dT = torch.empty_like(T)
+    d = _derive_struct(grid, T, phys)
+    o = L.rt_derived(_fptr(c["ln_nh2"]), _fptr(c["vphi_kms"]), _fptr(c["z_lo_au"]), _fptr(c["z_up_au"]))
+    L.check(L.lib().rt_derive_fields_adjoint(C.byref(d), C.byref(o), _fptr(dT), C.c_void_p(_stream(stream))))
+    return dT
+
+
+class DeriveFields(torch.autograd.Function):
+    """(ln_nh2, vphi_kms, z_lo_au, z_up_au) = DeriveFields.apply(grid, phys, temp_k)."""
+
+    @staticmethod
+    def forward(ctx, grid, phys, temp_k):
+        T = temp_k.detach().contiguous()
+        ctx.grid, ctx.phys = grid, phys
+        ctx.save_for_backward(T)
+        out = derive_fields(grid, T, phys)
+        return out["ln_nh2"], out["vphi_kms"], out["z_lo_au"], out["z_up_au"]
+
+    @staticmethod
+    def backward(ctx, g_n, g_v, g_lo, g_up):
+        (T,) = ctx.saved_tensors
+        cot = dict(ln_nh2=g_n, vphi_kms=g_v, z_lo_au=g_lo, z_up_au=g_up)
+        return None, None, derive_fields_adjoint(ctx.grid, T, ctx.phys, cot)

@@ -114,3 +114,33 @@ def test_options_roundtrip():
     assert lib.rt_get_option(L.RT_OPT_ADJ_PIXEL_LANES) == 2
     assert lib.rt_set_option(L.RT_OPT_ADJ_PIXEL_LANES, 0) == 0
     assert lib.rt_set_option(999, 1) == L.RT_EINVAL
+
+
+@pytest.mark.parametrize("mutate,msg", [
+    (lambda d: setattr(d.grid, "nr", 1), "nr"),
+    (lambda d: setattr(d.grid, "r_max_au", 0.5), "r_min"),
+    (lambda d: setattr(d, "temp_k", None), "temp_k"),
+    (lambda d: setattr(d, "gamma", 2.0), "gamma"),
+    (lambda d: setattr(d, "mgas_msun", 0.0), "mgas"),
+    (lambda d: setattr(d, "mstar_msun", -1.0), "mstar"),
+    (lambda d: setattr(d, "t_freeze_k", 0.0), "thresholds"),
+])
+def test_derive_validation_rejects_on_host(mutate, msg):
+    """rt_derive_fields / _adjoint reject bad arguments before any device work
+    (fake device pointers are never dereferenced)."""
+    fake = C.c_void_p(0x1000)
+    d = L.rt_derive(L.rt_grid(8, 6, 1.0, 600.0, 0.5), fake, 2.0, 0.09, 150.0, 1.0, 2.37, 20.0, 1e21)
+    mutate(d)
+    out = L.rt_derived(fake, fake, fake, fake)
+    assert L.lib().rt_derive_fields(C.byref(d), C.byref(out), None) == L.RT_EINVAL
+    assert msg in L.lib().rt_last_error().decode()
+    assert L.lib().rt_derive_fields_adjoint(C.byref(d), C.byref(out), fake, None) == L.RT_EINVAL
+
+
+def test_derive_null_outputs_rejected():
+    fake = C.c_void_p(0x1000)
+    d = L.rt_derive(L.rt_grid(8, 6, 1.0, 600.0, 0.5), fake, 2.0, 0.09, 150.0, 1.0, 2.37, 20.0, 1e21)
+    assert L.lib().rt_derive_fields(C.byref(d), None, None) == L.RT_EINVAL
+    assert L.lib().rt_derive_fields(C.byref(d), C.byref(L.rt_derived(fake, None, fake, fake)), None) == L.RT_EINVAL
+    assert L.lib().rt_derive_fields_adjoint(C.byref(d), None, fake, None) == L.RT_EINVAL
+    assert L.lib().rt_derive_fields_adjoint(C.byref(d), C.byref(L.rt_derived()), None, None) == L.RT_EINVAL
