@@ -217,6 +217,7 @@ def main():
             out["fwd_adjoint"] = bench_adjoint(rt, synth, dev, args)
         except rt.RtError as e:
             out["fwd_adjoint"] = {"error": str(e)}
+        out["derived_fields"] = bench_derived(rt, synth, dev, args)
     if args.serve_seconds > 0:
         log(f"served stream ({args.serve_seconds:g} s trace, then the serial replay and the saturated runs)")
         out["served"], out["serial"], out["saturated"] = bench_serving(rt, synth, dev, args.serve_seconds)
@@ -262,6 +263,50 @@ def bench_adjoint(rt, synth, dev, args):
             dt = (time.perf_counter() - t0) / steps
             res[leg] = {"ray_samples_per_s": sc.ray_samples / dt, "ms_per_step": dt * 1e3}
         out[name] = dict(res, steps=steps, grads="ln n_H2, T, z_lo, z_up")
+    return out
+
+
+def bench_derived(rt, synth, dev, args):
+    """Fields derived from a temperature grid (hydrostatic density, column,
+    CO surfaces, v_phi with the pressure term) on the 256 x 128 grid: forward
+    and adjoint alone, and the temperature-fitting step at 256 x 256 x 48 x
+    256 -- derive, fused render + L2 + adjoint, adjoint of the derivation --
+    giving dL/dT through the derived fields and directly."""
+    import numpy as np
+    import torch
+    prob = synth.config3()
+    gs = prob.grid
+    grid = (gs.nr, gs.nz, gs.r_min_au, gs.r_max_au, gs.zr_max)
+    p = synth.disk.DiskParams()
+    phys = rt.DiskPhysics(p.mstar_msun, p.mgas_msun, p.rc_au, p.gamma, synth.disk.MU_GAS, p.t_freeze_k, p.n_dissoc)
+    T = torch.tensor(prob.temp_k, device=dev)
+    sc = rt.scene_from_problem(prob, device=dev)
+    d0 = rt.derive_fields(grid, T, phys)
+    tgt = rt.render(sc.replace(**{k: d0[k] for k in ("ln_nh2", "vphi_kms", "z_lo_au")},
+                               z_up_au=d0["z_up_au"] * 1.05))
+    cube = torch.empty_like(tgt)
+    want = ("ln_nh2", "temp_k", "vphi_kms", "z_lo_au", "z_up_au")
+
+    def fit_step():
+        d = rt.derive_fields(grid, T, phys)
+        _, loss, g = rt.render_l2_adjoint(sc.replace(**d), tgt, want=want, cube_out=cube)
+        return g["temp_k"] + rt.derive_fields_adjoint(grid, T, phys, g)
+
+    cot = {k: torch.ones_like(v) for k, v in d0.items()}
+    legs = (("forward", lambda: rt.derive_fields(grid, T, phys)),
+            ("adjoint", lambda: rt.derive_fields_adjoint(grid, T, phys, cot)),
+            ("fit_step_256x256x48ch_256s", fit_step))
+    out = {"grid": f"{gs.nr}x{gs.nz}"}
+    for name, f in legs:
+        steps = 50 if name != legs[-1][0] else max(3, args.steps // 2)
+        for _ in range(3):
+            f()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            f()
+        torch.cuda.synchronize()
+        out[name + "_ms"] = (time.perf_counter() - t0) / steps * 1e3
     return out
 
 

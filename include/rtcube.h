@@ -188,7 +188,7 @@ rt_status rt_render_cube_l2_adjoint(const rt_problem *p, const float *target, co
  * grid (one-sided at its edges); v_phi = sqrt(max(v^2, 0)).  The outputs are
  * the ln_nh2, vphi_kms, z_lo_au and z_up_au of rt_fields.  Computed in FP32. */
 typedef struct {
-    rt_grid grid;
+    rt_grid grid;                        /* nz <= 2048 */
     const float *temp_k;                 /* [nr][nz] device, > 0 */
     double mstar_msun;                   /* stellar mass, >= 0 */
     double mgas_msun, rc_au, gamma;      /* Sigma(r): M_gas > 0, r_c > 0, gamma < 2 */

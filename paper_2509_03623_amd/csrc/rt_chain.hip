@@ -7,10 +7,11 @@
 // and the freeze-out temperature, v_phi from gravity and the radial pressure
 // gradient.  The discretisation is stated in include/rtcube.h.
 //
-// The work is a few operations per grid node (3.3e4 nodes at 256 x 128), so
-// the scans along each column run in one lane per radial node and the
-// stencils in one lane per node; a call is a handful of microsecond-scale
-// launches next to a render of milliseconds.  Lengths are in au inside the
+// The work is a few operations per grid node (3.3e4 nodes at 256 x 128): the
+// scans along a column run in one lane of a workgroup that stages the
+// column's rows in LDS (one workgroup per radial node), the stencils in one
+// lane per node; a call is a few launches of tens of microseconds next to a
+// render of milliseconds.  Lengths are in au inside the
 // kernels (cm^3-scale powers would overflow float), with the unit factors
 // folded into the constants on the host.
 #include <hip/hip_runtime.h>
@@ -30,6 +31,9 @@ namespace {
 constexpr double kG = 6.67430e-8, kMsun = 1.98847e33, kAu = 1.495978707e13, kKb = 1.380649e-16,
                  kMh = 1.6735575e-24;
 constexpr double kPhotoFactor = 0.706;   // vertical H2 column -> total gas column
+
+// largest column staged in LDS (5 rows of floats: 40 KiB)
+constexpr int kChainMaxNz = 2048;
 
 struct ChainArgs {
     int nr, nz;
@@ -124,16 +128,24 @@ __device__ Crossings column_surfaces(const ChainArgs &a, const float *ln_n, cons
     return c;
 }
 
+// One 64-lane workgroup per radial node: the column's rows are staged in LDS
+// by the whole workgroup (coalesced), lane 0 runs the scans from LDS.
 __global__ __launch_bounds__(64) void chain_columns(ChainArgs a, const float *__restrict__ T, float *__restrict__ ln_n,
                                                     float *__restrict__ zlo, float *__restrict__ zup) {
-    const int i = blockIdx.x * 64 + threadIdx.x;
-    if (i >= a.nr) return;
-    const float r = node_r(a, i);
-    const float *Tc = T + (size_t)i * a.nz;
-    float *out = ln_n + (size_t)i * a.nz;
-    const float L0 = column_ell(a, Tc, r, out, nullptr);
-    for (int j = 0; j < a.nz; ++j) out[j] += L0;
-    column_surfaces(a, out, Tc, r, zlo + i, zup + i);
+    extern __shared__ float sm[];
+    const int i = blockIdx.x, nz = a.nz;
+    float *sT = sm, *sL = sm + nz;
+    const size_t o = (size_t)i * nz;
+    for (int j = threadIdx.x; j < nz; j += 64) sT[j] = T[o + j];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const float r = node_r(a, i);
+        const float L0 = column_ell(a, sT, r, sL, nullptr);
+        for (int j = 0; j < nz; ++j) sL[j] += L0;
+        column_surfaces(a, sL, sT, r, zlo + i, zup + i);
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < nz; j += 64) ln_n[o + j] = sL[j];
 }
 
 __device__ __forceinline__ float lnP(const float *ln_n, const float *T, int nz, int i, int j) {
@@ -210,83 +222,90 @@ __global__ __launch_bounds__(256) void chain_lnp_adj(ChainArgs a, const float *_
     gT[idx] += g / T[idx];
 }
 
-// per column: reverse of the column pass (crossings held fixed).  ls is a
-// column-length scratch row per radial node.
+// per column: reverse of the column pass (crossings held fixed); one
+// 64-lane workgroup per radial node, rows staged in LDS, lane 0 scans
 __global__ __launch_bounds__(64) void chain_columns_adj(ChainArgs a, const float *__restrict__ T,
                                                         const float *__restrict__ nbar, const float *__restrict__ zlobar,
                                                         const float *__restrict__ zupbar,
                                                         const float *__restrict__ gn, const float *__restrict__ gT,
-                                                        float *__restrict__ ls, float *__restrict__ lnn_s,
                                                         float *__restrict__ dT) {
-    const int i = blockIdx.x * 64 + threadIdx.x;
-    if (i >= a.nr) return;
-    const int nz = a.nz;
-    const float r = node_r(a, i);
-    const float dz = a.dzeta * r;
+    extern __shared__ float sm[];
+    const int i = blockIdx.x, nz = a.nz;
     const size_t o = (size_t)i * nz;
-    const float *Tc = T + o;
-    float *L = ls + o;          // l_j, then its cotangent
-    float *lnn = lnn_s + o;     // ln n_j
-    const float L0 = column_ell(a, Tc, r, L, nullptr);
-    for (int j = 0; j < nz; ++j) lnn[j] = L[j] + L0;
-    float zl, zu;
-    const Crossings c = column_surfaces(a, lnn, Tc, r, &zl, &zu);
-    // photodissociation surface -> the two columns it interpolates
-    float Nab = 0.0f, Nbb = 0.0f;
-    const float zub = zupbar ? zupbar[i] : 0.0f;
-    if (c.up_a >= 0 && zub != 0.0f) {
-        if (c.Nb > 0.0f) {
-            const float la = logf(c.Na), lb = logf(c.Nb), d = lb - la;
-            Nab = zub * dz * ((a.ln_thr - lb) / (d * d)) / c.Na;
-            Nbb = zub * dz * (-(a.ln_thr - la) / (d * d)) / c.Nb;
-        } else {
-            const float d = c.Nb - c.Na;
-            Nab = zub * dz * ((a.thr - c.Nb) / (d * d));
-            Nbb = zub * dz * (-(a.thr - c.Na) / (d * d));
+    float *Tc = sm, *L = sm + nz, *lnn = sm + 2 * nz, *sg = sm + 3 * nz, *sgT = sm + 4 * nz;
+    for (int j = threadIdx.x; j < nz; j += 64) {
+        Tc[j] = T[o + j];
+        sg[j] = (nbar ? nbar[o + j] : 0.0f) + gn[o + j];
+        sgT[j] = gT[o + j];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const float r = node_r(a, i);
+        const float dz = a.dzeta * r;
+        // L: l_j, then its cotangent; lnn: ln n_j, then its cotangent
+        const float L0 = column_ell(a, Tc, r, L, nullptr);
+        for (int j = 0; j < nz; ++j) lnn[j] = L[j] + L0;
+        float zl, zu;
+        const Crossings c = column_surfaces(a, lnn, Tc, r, &zl, &zu);
+        // photodissociation surface -> the two columns it interpolates
+        float Nab = 0.0f, Nbb = 0.0f;
+        const float zub = zupbar ? zupbar[i] : 0.0f;
+        if (c.up_a >= 0 && zub != 0.0f) {
+            if (c.Nb > 0.0f) {
+                const float la = logf(c.Na), lb = logf(c.Nb), d = lb - la;
+                Nab = zub * dz * ((a.ln_thr - lb) / (d * d)) / c.Na;
+                Nbb = zub * dz * (-(a.ln_thr - la) / (d * d)) / c.Nb;
+            } else {
+                const float d = c.Nb - c.Na;
+                Nab = zub * dz * ((a.thr - c.Nb) / (d * d));
+                Nbb = zub * dz * (-(a.thr - c.Na) / (d * d));
+            }
         }
-    }
-    // d L / d ln n_j: given, from v_phi, and from the two columns (N_k sums the
-    // trapezoid segments from node k up: n_j enters the segments below and
-    // above it)
-    const int ka = c.up_a, kb = c.up_a + 1;
-    auto dN_dn = [&](int k, int j) {   // d N_k / d n_j without the factor dz au/2
-        return (float)((j >= k + 1) ? 1 : 0) + (float)((j >= k && j <= nz - 2) ? 1 : 0);
-    };
-    float Gsum = 0.0f, trap = 0.0f;
-    for (int j = 0; j < nz; ++j) {
-        float g = (nbar ? nbar[o + j] : 0.0f) + gn[o + j];
-        if (ka >= 0) g += expf(lnn[j]) * 0.5f * dz * a.au_cm * (Nab * dN_dn(ka, j) + Nbb * dN_dn(kb, j));
-        Gsum += g;
-        const float w = (j == 0 || j == nz - 1) ? 0.5f : 1.0f;
-        trap += w * expf(L[j]);
-        lnn[j] = g;   // from here on: the cotangent of ln n
-    }
-    // ln n_j = l_j + ln rho_0 + const, ln rho_0 = ln Sigma - ln(2 dz sum w_j e^l_j)
-    for (int j = 0; j < nz; ++j) {
-        const float w = (j == 0 || j == nz - 1) ? 0.5f : 1.0f;
-        L[j] = lnn[j] - Gsum * w * expf(L[j]) / trap;
-    }
-    // l_j = -I_j - ln T_j + ln T_0; I_j = sum over segments below j of (h_s + h_s+1) dz / 2
-    float R = 0.0f, Rnext = 0.0f;   // suffix sums of the cotangent of l
-    const float t_f = a.t_freeze;
-    const float zlb = zlobar ? zlobar[i] : 0.0f;
-    for (int k = nz - 1; k >= 0; --k) {
-        Rnext = R;
-        R += L[k];
-        const float hb = -0.5f * dz * ((k <= nz - 2 ? Rnext : 0.0f) + (k >= 1 ? R : 0.0f));
-        const float Tk = Tc[k];
-        const float h = grav_h(a, r, (float)k * dz, Tk);
-        float g = -L[k] / Tk - hb * h / Tk + gT[o + k];
-        // freeze-out surface: linear in T between nodes lo_b - 1 and lo_b
-        if (zlb != 0.0f && c.lo_b > 0 && c.lo_b < nz) {
-            const int b = c.lo_b, aa = b - 1;
-            const float d = Tc[b] - Tc[aa];
-            if (k == aa) g += zlb * dz * (t_f - Tc[b]) / (d * d);
-            if (k == b) g -= zlb * dz * (t_f - Tc[aa]) / (d * d);
+        // d L / d ln n_j: given plus from v_phi (sg), and from the two columns
+        // (N_k sums the trapezoid segments from node k up: n_j enters the
+        // segments below and above it)
+        const int ka = c.up_a, kb = c.up_a + 1;
+        auto dN_dn = [&](int k, int j) {   // d N_k / d n_j without the factor dz au / 2
+            return (float)((j >= k + 1) ? 1 : 0) + (float)((j >= k && j <= nz - 2) ? 1 : 0);
+        };
+        float Gsum = 0.0f, trap = 0.0f;
+        for (int j = 0; j < nz; ++j) {
+            float g = sg[j];
+            if (ka >= 0) g += expf(lnn[j]) * 0.5f * dz * a.au_cm * (Nab * dN_dn(ka, j) + Nbb * dN_dn(kb, j));
+            Gsum += g;
+            const float w = (j == 0 || j == nz - 1) ? 0.5f : 1.0f;
+            trap += w * expf(L[j]);
+            lnn[j] = g;
         }
-        dT[o + k] = g;
+        // ln n_j = l_j + ln rho_0 + const, ln rho_0 = ln Sigma - ln(2 dz sum w_j e^l_j)
+        for (int j = 0; j < nz; ++j) {
+            const float w = (j == 0 || j == nz - 1) ? 0.5f : 1.0f;
+            L[j] = lnn[j] - Gsum * w * expf(L[j]) / trap;
+        }
+        // l_j = -I_j - ln T_j + ln T_0; I_j = sum over segments below j of (h_s + h_s+1) dz / 2
+        float R = 0.0f, Rnext = 0.0f;   // suffix sums of the cotangent of l
+        const float t_f = a.t_freeze;
+        const float zlb = zlobar ? zlobar[i] : 0.0f;
+        for (int k = nz - 1; k >= 0; --k) {
+            Rnext = R;
+            R += L[k];
+            const float hb = -0.5f * dz * ((k <= nz - 2 ? Rnext : 0.0f) + (k >= 1 ? R : 0.0f));
+            const float Tk = Tc[k];
+            const float h = grav_h(a, r, (float)k * dz, Tk);
+            float g = -L[k] / Tk - hb * h / Tk + sgT[k];
+            // freeze-out surface: linear in T between nodes lo_b - 1 and lo_b
+            if (zlb != 0.0f && c.lo_b > 0 && c.lo_b < nz) {
+                const int b = c.lo_b, aa = b - 1;
+                const float d = Tc[b] - Tc[aa];
+                if (k == aa) g += zlb * dz * (t_f - Tc[b]) / (d * d);
+                if (k == b) g -= zlb * dz * (t_f - Tc[aa]) / (d * d);
+            }
+            sg[k] = g;
+        }
+        sg[0] += R / Tc[0];
     }
-    dT[o] += R / Tc[0];
+    __syncthreads();
+    for (int j = threadIdx.x; j < nz; j += 64) dT[o + j] = sg[j];
 }
 
 ChainArgs chain_args(const rt_derive *d) {
@@ -322,6 +341,7 @@ rt_status validate_derive(const rt_derive *d) {
     if (!(g.r_min_au > 0.0) || !(g.r_max_au > g.r_min_au) || !(g.zr_max > 0.0))
         return fail(RT_EINVAL, "grid needs 0 < r_min < r_max and zr_max > 0");
     if ((size_t)g.nr * g.nz > (size_t)1 << 28) return fail(RT_EINVAL, "grid too large");
+    if (g.nz > kChainMaxNz) return fail(RT_EINVAL, "derived fields take at most %d z/r nodes", kChainMaxNz);
     if (!d->temp_k) return fail(RT_EINVAL, "temp_k is NULL");
     if (!(d->mstar_msun >= 0.0) || !(d->mgas_msun > 0.0) || !(d->rc_au > 0.0) || !(d->gamma < 2.0) || !(d->mu > 0.0))
         return fail(RT_EINVAL, "need mstar >= 0, mgas > 0, rc > 0, gamma < 2, mu > 0");
@@ -342,8 +362,8 @@ extern "C" rt_status rt_derive_fields(const rt_derive *d, const rt_derived *out,
         return fail(RT_EINVAL, "every derived output must be given");
     const ChainArgs a = chain_args(d);
     hipStream_t s = (hipStream_t)stream;
-    hipLaunchKernelGGL(chain_columns, dim3((a.nr + 63) / 64), dim3(64), 0, s, a, d->temp_k, out->ln_nh2, out->z_lo_au,
-                       out->z_up_au);
+    hipLaunchKernelGGL(chain_columns, dim3(a.nr), dim3(64), 2 * sizeof(float) * a.nz, s, a, d->temp_k, out->ln_nh2,
+                       out->z_lo_au, out->z_up_au);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail_hip(e, "derive columns");
     const int n = a.nr * a.nz;
@@ -362,17 +382,18 @@ extern "C" rt_status rt_derive_fields_adjoint(const rt_derive *d, const rt_deriv
     hipStream_t s = (hipStream_t)stream;
     const size_t n = (size_t)a.nr * a.nz;
     hipError_t e;
-    // scratch: eu / l, ez / ln n, gn, gT, and the forward ln n for the stencils
+    // scratch: eu, ez, gn, gT, and the forward ln n for the stencils
     float *w = (float *)stream_workspace(s, kWsChain, sizeof(float) * 5 * n, &e);
     if (!w) return fail_hip(e, "derive scratch");
     float *eu = w, *ez = w + n, *gn = w + 2 * n, *gT = w + 3 * n, *lnn = w + 4 * n;
     // forward ln n (and surfaces into discarded slots of gn) for the v_phi stencils
-    hipLaunchKernelGGL(chain_columns, dim3((a.nr + 63) / 64), dim3(64), 0, s, a, d->temp_k, lnn, gn, gn + a.nr);
+    hipLaunchKernelGGL(chain_columns, dim3(a.nr), dim3(64), 2 * sizeof(float) * a.nz, s, a, d->temp_k, lnn, gn,
+                       gn + a.nr);
     hipLaunchKernelGGL(chain_vphi_adj, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a, d->temp_k, lnn,
                        cot->vphi_kms, eu, ez, gT);
     hipLaunchKernelGGL(chain_lnp_adj, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a, d->temp_k, eu, ez, gn, gT);
-    hipLaunchKernelGGL(chain_columns_adj, dim3((a.nr + 63) / 64), dim3(64), 0, s, a, d->temp_k, cot->ln_nh2,
-                       cot->z_lo_au, cot->z_up_au, gn, gT, eu, ez, d_temp_k);
+    hipLaunchKernelGGL(chain_columns_adj, dim3(a.nr), dim3(64), 5 * sizeof(float) * a.nz, s, a, d->temp_k,
+                       cot->ln_nh2, cot->z_lo_au, cot->z_up_au, gn, gT, d_temp_k);
     e = hipGetLastError();
     return e == hipSuccess ? RT_OK : fail_hip(e, "derive adjoint");
 }

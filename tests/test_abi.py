@@ -124,6 +124,7 @@ def test_options_roundtrip():
     (lambda d: setattr(d, "mgas_msun", 0.0), "mgas"),
     (lambda d: setattr(d, "mstar_msun", -1.0), "mstar"),
     (lambda d: setattr(d, "t_freeze_k", 0.0), "thresholds"),
+    (lambda d: setattr(d.grid, "nz", 4096), "z/r nodes"),
 ])
 def test_derive_validation_rejects_on_host(mutate, msg):
     """rt_derive_fields / _adjoint reject bad arguments before any device work
