@@ -40,3 +40,37 @@ def make_mlp_weights(seed: int = 4, out_bias=(0.6, 0.1, None)) -> np.ndarray:
                     b[k] = np.log(f / (1 - f))
         parts.append(b)
     return np.concatenate([p.ravel() for p in parts]).astype(np.float32)
+
+
+# Neural temperature field of the paper (Methods, "Neural Temperature
+# Recovery"): sinusoidal encoding of degree 4 on the two normalised grid
+# coordinates (16 features) -> 4 ReLU layers of width 64 -> 1 output.
+NT_L = 4
+NT_IN = 4 * NT_L
+NT_WIDTH = 64
+NT_DEPTH = 4
+
+
+def nt_layer_shapes():
+    dims = [NT_IN] + [NT_WIDTH] * NT_DEPTH + [1]
+    return [(dims[i + 1], dims[i]) for i in range(len(dims) - 1)]
+
+
+def nt_param_count() -> int:
+    return sum(o * i + o for o, i in nt_layer_shapes())
+
+
+def make_neural_t_weights(seed: int = 6, t_init_k: float = 30.0) -> np.ndarray:
+    """He-normal hidden weights (ReLU), Xavier-normal output layer, zero
+    hidden biases, output bias putting the initial temperature near t_init_k
+    on the 5..400 K sigmoid range."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    parts = []
+    shapes = nt_layer_shapes()
+    for li, (o, i) in enumerate(shapes):
+        last = li == len(shapes) - 1
+        std = np.sqrt(2.0 / (i + o)) if last else np.sqrt(2.0 / i)
+        parts.append(rng.standard_normal((o, i)) * std)
+        f = (t_init_k - 5.0) / 395.0
+        parts.append(np.full(o, np.log(f / (1 - f))) if last else np.zeros(o))
+    return np.concatenate([p.ravel() for p in parts]).astype(np.float32)
