@@ -213,6 +213,37 @@ rt_status rt_derive_fields(const rt_derive *d, const rt_derived *out, void *stre
  * the stream. */
 rt_status rt_derive_fields_adjoint(const rt_derive *d, const rt_derived *cot, float *d_temp_k, void *stream);
 
+/* --------------------------------------------------- neural temperature */
+/* The neural temperature field of Methods > Neural temperature recovery on the
+ * nodes of the render grid: T = 5 + 395 sigma(o) K, o = MLP(gamma(x_r, x_z)),
+ * with the sinusoidal encoding of degree 4 of the normalised node coordinates
+ * x_r = i/(nr-1), x_z = j/(nz-1): sin(2^k pi x_r), cos(2^k pi x_r),
+ * sin(2^k pi x_z), cos(2^k pi x_z) for k = 0..3 (16 features in that order),
+ * then four fully connected layers of 64 units with ReLU and one output.
+ * Weights: float32 device array of RT_NT_PARAMS, per layer W [out][in] then
+ * b [out].  FP32. */
+#define RT_NT_PARAMS 13633
+
+/* temp_k [nr][nz] = T at every node (nr, nz >= 2). */
+rt_status rt_neural_temperature(const rt_grid *grid, const float *weights, float *temp_k, void *stream);
+
+/* Vector-Jacobian product: d_weights [RT_NT_PARAMS] = (dT/dweights)^T
+ * d_temp_k (overwritten; sums over nodes in a fixed order, so the result is
+ * reproducible).  Scratch of about 2100 bytes per node is kept with the
+ * stream. */
+rt_status rt_neural_temperature_adjoint(const rt_grid *grid, const float *weights, const float *d_temp_k,
+                                        float *d_weights, void *stream);
+
+/* Adam (Kingma & Ba) on n float32 parameters in place, with first / second
+ * moment buffers m and v (zero before step 1) and step >= 1 the 1-based step
+ * count for the bias corrections; the gradient is multiplied by grad_scale
+ * first (e.g. 1/sigma^2 turning an L2 gradient into a chi^2 one). */
+typedef struct {
+    double lr, beta1, beta2, eps, grad_scale;
+} rt_adam;
+rt_status rt_adam_step(float *params, float *m, float *v, const float *grad, int64_t n, const rt_adam *opt,
+                       int64_t step, void *stream);
+
 /* ---------------------------------------------------------------- server */
 /* Continuous-batching render server on one GPU.  Requests are admitted in
  * arrival order while their HBM footprint (inputs, outputs and library

@@ -10,3 +10,6 @@ from .render import (  # noqa: F401
     set_option, get_option, constants, DiskPhysics, derive_fields, derive_fields_adjoint, DeriveFields,
 )
 from .server import Server  # noqa: F401
+from .fit import (  # noqa: F401
+    neural_temperature, neural_temperature_adjoint, NeuralTemperature, Adam, poly_lr, fit_step,
+)

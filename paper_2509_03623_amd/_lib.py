@@ -93,9 +93,17 @@ class rt_derived(C.Structure):
     _fields_ = [("ln_nh2", _dev), ("vphi_kms", _dev), ("z_lo_au", _dev), ("z_up_au", _dev)]
 
 
+class rt_adam(C.Structure):
+    _fields_ = [("lr", C.c_double), ("beta1", C.c_double), ("beta2", C.c_double), ("eps", C.c_double),
+                ("grad_scale", C.c_double)]
+
+
+RT_NT_PARAMS = 13633
+
 # every symbol declared in include/rtcube.h
 EXPORTS = ["rt_render_cube", "rt_render_cube_adjoint", "rt_render_cube_l2_adjoint", "rt_derive_fields",
-           "rt_derive_fields_adjoint", "rt_server_create", "rt_submit", "rt_poll", "rt_wait",
+           "rt_derive_fields_adjoint", "rt_neural_temperature", "rt_neural_temperature_adjoint", "rt_adam_step",
+           "rt_server_create", "rt_submit", "rt_poll", "rt_wait",
            "rt_cancel", "rt_server_destroy", "rt_last_error", "rt_abi_version", "rt_constants",
            "rt_set_option", "rt_get_option"]
 
@@ -127,6 +135,12 @@ def lib():
         L.rt_derive_fields.restype = C.c_int
         L.rt_derive_fields_adjoint.argtypes = [C.POINTER(rt_derive), C.POINTER(rt_derived), _dev, C.c_void_p]
         L.rt_derive_fields_adjoint.restype = C.c_int
+        L.rt_neural_temperature.argtypes = [C.POINTER(rt_grid), _dev, _dev, C.c_void_p]
+        L.rt_neural_temperature.restype = C.c_int
+        L.rt_neural_temperature_adjoint.argtypes = [C.POINTER(rt_grid), _dev, _dev, _dev, C.c_void_p]
+        L.rt_neural_temperature_adjoint.restype = C.c_int
+        L.rt_adam_step.argtypes = [_dev, _dev, _dev, _dev, C.c_int64, C.POINTER(rt_adam), C.c_int64, C.c_void_p]
+        L.rt_adam_step.restype = C.c_int
         L.rt_server_create.argtypes = [C.POINTER(rt_server_cfg), C.POINTER(C.c_void_p)]
         L.rt_server_create.restype = C.c_int
         L.rt_submit.argtypes = [C.c_void_p, C.POINTER(rt_request), C.POINTER(C.c_uint64)]

@@ -1,0 +1,297 @@
+// rt_neural_t.hip -- the neural temperature field of Methods, "Neural
+// Temperature Recovery" on the render grid's nodes, its vector-Jacobian
+// product to the weights, and the Adam step.
+//
+// T(r, |z|) = 5 + 395 sigma(o), o = MLP(gamma(x_r, x_z)): sinusoidal encoding
+// of degree 4 of the normalised node coordinates (16 features), four ReLU
+// layers of 64 units, one output.  The grid has 3.3e4 nodes at 256 x 128 and
+// the network 1.4e4 weights (4.4e8 multiply-adds per evaluation), so this is
+// plain FP32 VALU work: a workgroup of 128 nodes keeps each node's
+// activations in its own LDS column and accumulates 16 outputs at a time in
+// registers against weights staged in LDS (read as broadcasts).  The weight
+// gradient sums outer products over the nodes: split over node chunks into
+// partial sums, then reduced in a fixed order (deterministic).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "../../include/rtcube.h"
+#include "rt_host.h"
+
+namespace rt {
+
+namespace {
+
+constexpr int kNtL = 4, kNtIn = 4 * kNtL, kNtW = 64, kNtThreads = 128;
+// flat layout: per layer W [out][in] then b [out]
+constexpr int layer_in(int l) { return l == 0 ? kNtIn : kNtW; }
+constexpr int layer_out(int l) { return l == 4 ? 1 : kNtW; }
+constexpr int layer_off(int l) {
+    int o = 0;
+    for (int k = 0; k < l; ++k) o += layer_in(k) * layer_out(k) + layer_out(k);
+    return o;
+}
+static_assert(layer_off(5) == RT_NT_PARAMS, "neural temperature parameter count");
+// activation rows per node: 16 features, 4 x 64 hidden, the output o
+constexpr int kActRows = kNtIn + 4 * kNtW + 1;
+constexpr int kDeltaRows = 4 * kNtW + 1;
+constexpr int kNtChunk = 1024;   // nodes per partial sum of the weight gradient
+
+__device__ __forceinline__ void node_features(int n, int nr, int nz, float *f) {
+    const int i = n / nz, j = n - i * nz;
+    const float x[2] = {(float)i / (float)(nr - 1), (float)j / (float)(nz - 1)};
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int k = 0; k < kNtL; ++k) {
+            float s, co;
+            sincospif((float)(1 << k) * x[c], &s, &co);
+            f[8 * c + k] = s;
+            f[8 * c + kNtL + k] = co;
+        }
+}
+
+// LDS: per layer l the transposed weights WT_l [in][out] then b_l (forward),
+// or W_l [out][in] (backward); then two activation buffers [64][kNtThreads].
+__device__ __forceinline__ void stage_weights(const float *W, float *sw, bool transposed) {
+    for (int p = threadIdx.x; p < RT_NT_PARAMS; p += kNtThreads) {
+        int l = 0;
+        while (l < 4 && p >= layer_off(l + 1)) ++l;
+        const int q = p - layer_off(l), in = layer_in(l), out = layer_out(l);
+        int dst = p;
+        if (transposed && q < in * out) {
+            const int a = q / in, b = q - a * in;     // W[a][b]
+            dst = layer_off(l) + b * out + a;         // WT[b][a]
+        }
+        sw[dst] = W[p];
+    }
+}
+
+// one dense layer for this lane's node: out[a] = act(sum_b W[a][b] in[b] + b[a]),
+// with in / out columns of the LDS buffers and WT [in][out] in LDS
+template <int IN, int OUT, bool RELU>
+__device__ __forceinline__ void dense(const float *wt, const float *bias, const float *hin, float *hout, int t) {
+    constexpr int C = OUT < 16 ? OUT : 16;
+#pragma unroll
+    for (int a0 = 0; a0 < OUT; a0 += C) {
+        float acc[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) acc[c] = bias[a0 + c];
+#pragma unroll 4
+        for (int b = 0; b < IN; ++b) {
+            const float h = hin[b * kNtThreads + t];
+#pragma unroll
+            for (int c = 0; c < C; ++c) acc[c] = fmaf(wt[b * OUT + a0 + c], h, acc[c]);
+        }
+#pragma unroll
+        for (int c = 0; c < C; ++c) hout[(a0 + c) * kNtThreads + t] = RELU ? fmaxf(acc[c], 0.0f) : acc[c];
+    }
+}
+
+__global__ __launch_bounds__(kNtThreads) void nt_fwd(int nr, int nz, const float *__restrict__ W,
+                                                     float *__restrict__ T, float *__restrict__ act) {
+    extern __shared__ float sm[];
+    float *sw = sm, *h0 = sm + RT_NT_PARAMS, *h1 = h0 + kNtW * kNtThreads;
+    stage_weights(W, sw, true);
+    const int N = nr * nz, t = threadIdx.x;
+    const int n = blockIdx.x * kNtThreads + t;
+    const int nn = n < N ? n : N - 1;   // lanes past the end compute a copy and store nothing
+    float f[kNtIn];
+    node_features(nn, nr, nz, f);
+#pragma unroll
+    for (int b = 0; b < kNtIn; ++b) h0[b * kNtThreads + t] = f[b];
+    __syncthreads();
+    dense<kNtIn, kNtW, true>(sw + layer_off(0), sw + layer_off(0) + kNtIn * kNtW, h0, h1, t);
+    dense<kNtW, kNtW, true>(sw + layer_off(1), sw + layer_off(1) + kNtW * kNtW, h1, h0, t);
+    if (act && n < N)
+        for (int a = 0; a < kNtW; ++a) act[(size_t)(kNtIn + a) * N + n] = h1[a * kNtThreads + t];
+    dense<kNtW, kNtW, true>(sw + layer_off(2), sw + layer_off(2) + kNtW * kNtW, h0, h1, t);
+    if (act && n < N)
+        for (int a = 0; a < kNtW; ++a) act[(size_t)(kNtIn + kNtW + a) * N + n] = h0[a * kNtThreads + t];
+    dense<kNtW, kNtW, true>(sw + layer_off(3), sw + layer_off(3) + kNtW * kNtW, h1, h0, t);
+    if (act && n < N) {
+        for (int a = 0; a < kNtW; ++a) {
+            act[(size_t)(kNtIn + 2 * kNtW + a) * N + n] = h1[a * kNtThreads + t];
+            act[(size_t)(kNtIn + 3 * kNtW + a) * N + n] = h0[a * kNtThreads + t];
+        }
+        for (int b = 0; b < kNtIn; ++b) act[(size_t)b * N + n] = f[b];
+    }
+    dense<kNtW, 1, false>(sw + layer_off(4), sw + layer_off(4) + kNtW, h0, h1, t);
+    const float o = h1[t];
+    if (n < N) {
+        T[n] = 5.0f + 395.0f / (1.0f + expf(-o));
+        if (act) act[(size_t)(kActRows - 1) * N + n] = o;
+    }
+}
+
+// backward through the layers for this lane's node: delta rows (dL/dz of
+// hidden layers 1..4, then dL/do) into `delta` [kDeltaRows][N]
+__global__ __launch_bounds__(kNtThreads) void nt_delta(int N, const float *__restrict__ W,
+                                                       const float *__restrict__ dT, const float *__restrict__ act,
+                                                       float *__restrict__ delta) {
+    extern __shared__ float sm[];
+    float *sw = sm, *d0 = sm + RT_NT_PARAMS, *d1 = d0 + kNtW * kNtThreads;
+    stage_weights(W, sw, false);
+    __syncthreads();
+    const int t = threadIdx.x, n = blockIdx.x * kNtThreads + t;
+    const int nn = n < N ? n : N - 1;
+    const float o = act[(size_t)(kActRows - 1) * N + nn];
+    const float s = 1.0f / (1.0f + expf(-o));
+    const float dlo = (n < N ? dT[n] : 0.0f) * 395.0f * s * (1.0f - s);
+    if (n < N) delta[(size_t)(kDeltaRows - 1) * N + n] = dlo;
+    // dL/dz_4 = W_4^T dL/do masked by h_4 > 0
+    const float *w4 = sw + layer_off(4);
+    for (int a = 0; a < kNtW; ++a) {
+        const float h = act[(size_t)(kNtIn + 3 * kNtW + a) * N + nn];
+        d0[a * kNtThreads + t] = h > 0.0f ? w4[a] * dlo : 0.0f;
+    }
+    if (n < N)
+        for (int a = 0; a < kNtW; ++a) delta[(size_t)(3 * kNtW + a) * N + n] = d0[a * kNtThreads + t];
+    // dL/dz_l = W_l^T dL/dz_{l+1} masked by h_l > 0, for l = 3, 2, 1 (W_l maps h_l to z_{l+1})
+    float *cur = d0, *nxt = d1;
+    for (int l = 3; l >= 1; --l) {
+        const float *wl = sw + layer_off(l);   // W_l [out][in]
+        for (int b0 = 0; b0 < kNtW; b0 += 16) {
+            float acc[16];
+#pragma unroll
+            for (int c = 0; c < 16; ++c) acc[c] = 0.0f;
+#pragma unroll 4
+            for (int a = 0; a < kNtW; ++a) {
+                const float g = cur[a * kNtThreads + t];
+#pragma unroll
+                for (int c = 0; c < 16; ++c) acc[c] = fmaf(wl[a * kNtW + b0 + c], g, acc[c]);
+            }
+#pragma unroll
+            for (int c = 0; c < 16; ++c) {
+                const float h = act[(size_t)(kNtIn + (l - 1) * kNtW + b0 + c) * N + nn];
+                nxt[(b0 + c) * kNtThreads + t] = h > 0.0f ? acc[c] : 0.0f;
+            }
+        }
+        if (n < N)
+            for (int b = 0; b < kNtW; ++b) delta[(size_t)((l - 1) * kNtW + b) * N + n] = nxt[b * kNtThreads + t];
+        float *tmp = cur;
+        cur = nxt;
+        nxt = tmp;
+    }
+}
+
+// partial weight gradient over one chunk of nodes: for parameter p of layer
+// l, W_l[a][b] gets sum_n dz_{l+1}[a][n] in_l[b][n], b_l[a] gets sum_n dz_{l+1}[a][n]
+__global__ __launch_bounds__(256) void nt_wgrad(int N, const float *__restrict__ act, const float *__restrict__ delta,
+                                                float *__restrict__ partial) {
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p >= RT_NT_PARAMS) return;
+    int l = 0;
+    while (l < 4 && p >= layer_off(l + 1)) ++l;
+    const int q = p - layer_off(l), in = layer_in(l);
+    const bool bias = q >= in * layer_out(l);
+    const int a = bias ? q - in * layer_out(l) : q / in, b = bias ? 0 : q - a * in;
+    // rows: dz_{l+1} is delta row l * 64 + a (dL/do for l = 4); in_l is the
+    // features (l = 0) or h_l = act row 16 + (l - 1) * 64 + b
+    const float *A = delta + (size_t)(l == 4 ? kDeltaRows - 1 : l * kNtW + a) * N;
+    const float *B = act + (size_t)(l == 0 ? b : kNtIn + (l - 1) * kNtW + b) * N;
+    const int n0 = blockIdx.y * kNtChunk, n1 = min(N, n0 + kNtChunk);
+    float acc = 0.0f;
+    if (bias)
+        for (int n = n0; n < n1; ++n) acc += A[n];
+    else
+        for (int n = n0; n < n1; ++n) acc = fmaf(A[n], B[n], acc);
+    partial[(size_t)blockIdx.y * RT_NT_PARAMS + p] = acc;
+}
+
+__global__ __launch_bounds__(256) void nt_wreduce(int chunks, const float *__restrict__ partial,
+                                                  float *__restrict__ dW) {
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p >= RT_NT_PARAMS) return;
+    float s = 0.0f;
+    for (int c = 0; c < chunks; ++c) s += partial[(size_t)c * RT_NT_PARAMS + p];
+    dW[p] = s;
+}
+
+__global__ __launch_bounds__(256) void nt_adam(int64_t n, float *__restrict__ p, float *__restrict__ m,
+                                               float *__restrict__ v, const float *__restrict__ g, float lr, float b1,
+                                               float b2, float eps, float gscale, float c1, float c2) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i] * gscale;
+    const float mi = fmaf(b1, m[i], (1.0f - b1) * gi);
+    const float vi = fmaf(b2, v[i], (1.0f - b2) * gi * gi);
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi * c1) / (sqrtf(vi * c2) + eps);
+}
+
+rt_status validate_nt_grid(const rt_grid *g) {
+    if (!g) return fail(RT_EINVAL, "grid is NULL");
+    if (g->nr < 2 || g->nz < 2) return fail(RT_EINVAL, "grid needs nr, nz >= 2");
+    if ((size_t)g->nr * g->nz > (size_t)1 << 26) return fail(RT_EINVAL, "grid too large for the neural temperature");
+    return RT_OK;
+}
+
+constexpr size_t kNtLds = sizeof(float) * (RT_NT_PARAMS + 2 * kNtW * kNtThreads);
+
+hipError_t nt_lds_attr() {
+    hipError_t e = hipFuncSetAttribute((const void *)nt_fwd, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kNtLds);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void *)nt_delta, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kNtLds);
+    return e;
+}
+
+} // namespace
+
+} // namespace rt
+
+using namespace rt;
+
+extern "C" rt_status rt_neural_temperature(const rt_grid *grid, const float *weights, float *temp_k, void *stream) {
+    rt_status st = validate_nt_grid(grid);
+    if (st != RT_OK) return st;
+    if (!weights || !temp_k) return fail(RT_EINVAL, "weights and temp_k must not be NULL");
+    hipError_t e = nt_lds_attr();
+    if (e != hipSuccess) return fail_hip(e, "neural temperature attributes");
+    const int N = grid->nr * grid->nz;
+    hipLaunchKernelGGL(nt_fwd, dim3((N + kNtThreads - 1) / kNtThreads), dim3(kNtThreads), kNtLds, (hipStream_t)stream,
+                       grid->nr, grid->nz, weights, temp_k, (float *)nullptr);
+    e = hipGetLastError();
+    return e == hipSuccess ? RT_OK : fail_hip(e, "neural temperature");
+}
+
+extern "C" rt_status rt_neural_temperature_adjoint(const rt_grid *grid, const float *weights, const float *d_temp_k,
+                                                   float *d_weights, void *stream) {
+    rt_status st = validate_nt_grid(grid);
+    if (st != RT_OK) return st;
+    if (!weights || !d_temp_k || !d_weights) return fail(RT_EINVAL, "weights, d_temp_k and d_weights must not be NULL");
+    hipError_t e = nt_lds_attr();
+    if (e != hipSuccess) return fail_hip(e, "neural temperature attributes");
+    hipStream_t s = (hipStream_t)stream;
+    const int N = grid->nr * grid->nz;
+    const int chunks = (N + kNtChunk - 1) / kNtChunk;
+    const size_t act_n = (size_t)kActRows * N, del_n = (size_t)kDeltaRows * N, part_n = (size_t)chunks * RT_NT_PARAMS;
+    float *w = (float *)stream_workspace(s, kWsNeuralT, sizeof(float) * (act_n + del_n + part_n + N), &e);
+    if (!w) return fail_hip(e, "neural temperature scratch");
+    float *act = w, *del = w + act_n, *part = del + del_n, *Tn = part + part_n;
+    const int blocks = (N + kNtThreads - 1) / kNtThreads;
+    hipLaunchKernelGGL(nt_fwd, dim3(blocks), dim3(kNtThreads), kNtLds, s, grid->nr, grid->nz, weights, Tn, act);
+    hipLaunchKernelGGL(nt_delta, dim3(blocks), dim3(kNtThreads), kNtLds, s, N, weights, d_temp_k, act, del);
+    hipLaunchKernelGGL(nt_wgrad, dim3((RT_NT_PARAMS + 255) / 256, chunks), dim3(256), 0, s, N, act, del, part);
+    hipLaunchKernelGGL(nt_wreduce, dim3((RT_NT_PARAMS + 255) / 256), dim3(256), 0, s, chunks, part, d_weights);
+    e = hipGetLastError();
+    return e == hipSuccess ? RT_OK : fail_hip(e, "neural temperature adjoint");
+}
+
+extern "C" rt_status rt_adam_step(float *params, float *m, float *v, const float *grad, int64_t n, const rt_adam *opt,
+                                  int64_t step, void *stream) {
+    if (!params || !m || !v || !grad || !opt) return fail(RT_EINVAL, "Adam arguments must not be NULL");
+    if (n < 0) return fail(RT_EINVAL, "parameter count must be >= 0");
+    if (step < 1) return fail(RT_EINVAL, "Adam steps count from 1");
+    if (!(opt->beta1 >= 0.0 && opt->beta1 < 1.0) || !(opt->beta2 >= 0.0 && opt->beta2 < 1.0) || !(opt->eps > 0.0))
+        return fail(RT_EINVAL, "need 0 <= beta1, beta2 < 1 and eps > 0");
+    if (n == 0) return RT_OK;
+    const float c1 = (float)(1.0 / (1.0 - std::pow(opt->beta1, (double)step)));
+    const float c2 = (float)(1.0 / (1.0 - std::pow(opt->beta2, (double)step)));
+    hipLaunchKernelGGL(nt_adam, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream, n, params, m, v,
+                       grad, (float)opt->lr, (float)opt->beta1, (float)opt->beta2, (float)opt->eps,
+                       (float)opt->grad_scale, c1, c2);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? RT_OK : fail_hip(e, "Adam step");
+}
