@@ -218,6 +218,8 @@ def main():
         except rt.RtError as e:
             out["fwd_adjoint"] = {"error": str(e)}
         out["derived_fields"] = bench_derived(rt, synth, dev, args)
+        log("neural-temperature fitting step")
+        out["neural_t_fit"] = bench_fit(rt, synth, dev, args)
     if args.serve_seconds > 0:
         log(f"served stream ({args.serve_seconds:g} s trace, then the serial replay and the saturated runs)")
         out["served"], out["serial"], out["saturated"] = bench_serving(rt, synth, dev, args.serve_seconds)
@@ -308,6 +310,46 @@ def bench_derived(rt, synth, dev, args):
         torch.cuda.synchronize()
         out[name + "_ms"] = (time.perf_counter() - t0) / steps * 1e3
     return out
+
+
+def bench_fit(rt, synth, dev, args):
+    """The neural-temperature fitting step of Methods, "Neural Temperature
+    Recovery", at 256 x 256 px x 256 samples on a 115-channel cube (0.04 km/s),
+    a random batch of 50 slices per step, chi^2 with sigma = 1.5 % of peak:
+    network -> T, derived fields, fused render + L2 + adjoint on the batch,
+    derived-field and network adjoints, Adam.  The target is the same disk's
+    parametric temperature pushed through the derived fields."""
+    import numpy as np
+    import torch
+    prob = synth.config3(nch=115, dv=0.04)
+    gs = prob.grid
+    grid = (gs.nr, gs.nz, gs.r_min_au, gs.r_max_au, gs.zr_max)
+    p = synth.disk.DiskParams()
+    phys = rt.DiskPhysics(p.mstar_msun, p.mgas_msun, p.rc_au, p.gamma, synth.disk.MU_GAS, p.t_freeze_k, p.n_dissoc)
+    sc = rt.scene_from_problem(prob, device=dev)
+    T_true = torch.tensor(prob.temp_k, device=dev)
+    target = rt.render(sc.replace(temp_k=T_true, **rt.derive_fields(grid, T_true, phys)))
+    sigma = 0.015 * float(target.abs().max())
+    w = torch.tensor(synth.mlp.make_neural_t_weights(6), device=dev)
+    opt = rt.Adam(w)
+    rng = np.random.Generator(np.random.PCG64(7))
+    batch = 50
+    steps = max(5, args.steps // 2)
+    chans = [np.sort(rng.choice(sc.nch, size=batch, replace=False)) for _ in range(steps + 2)]
+    for t in range(2):
+        rt.fit_step(sc, grid, phys, opt, target, chans[t], sigma, 1e-4)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    chi2 = []
+    for t in range(steps):
+        c2, _ = rt.fit_step(sc, grid, phys, opt, target, chans[t + 2], sigma, rt.poly_lr(t, 30000))
+        chi2.append(c2)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    rs = sc.nx * sc.ny * batch * sc.nsamp
+    return {"workload": "256x256 px, 115 ch (0.04 km/s), 256 samples, batch 50, 256x128 grid",
+            "ms_per_step": dt * 1e3, "ray_samples_per_s": rs / dt, "steps": steps,
+            "chi2_first": float(chi2[0].item()), "chi2_last": float(chi2[-1].item())}
 
 
 def bench_mlp(rt, synth, dev, args):

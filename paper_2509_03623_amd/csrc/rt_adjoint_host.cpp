@@ -10,25 +10,28 @@
 
 namespace rt {
 
-// Reverse-march shape (measured): the first of (channels per lane, lanes per
-// pixel) = (32, 2), (24, 2), (16, 2), (32, 1), (24, 1) whose channel group
-// pads at most an eighth of the channels and still gives 2048 waves; (32, 1)
-// only when the march forms the intensity (without it that form spills
-// registers); else (16, 1), or (8, 1) for at most 8 channels.  Pairs write one
-// cotangent slice per 2 CB channels (at 512^2 x 64: 10.9 ms fused with
-// (32, 2) against 11.8 ms with (32, 1)).  The checkpointed march (option)
-// takes 8, 16 or 32 channels per lane and one lane per pixel.
+// Reverse-march shape (measured): of (channels per lane, lanes per pixel) =
+// (32, 2), (24, 2), (16, 2), (32, 1), (24, 1) that still give 2048 waves, the
+// one padding the fewest channels, the earlier in that order on a tie;
+// (32, 1) only when the march forms the intensity (without it that form
+// spills registers); else (16, 1), or (8, 1) for at most 8 channels.  Pairs
+// write one cotangent slice per 2 CB channels (at 512^2 x 64: 10.9 ms fused
+// with (32, 2) against 11.8 ms with (32, 1)).  The checkpointed march
+// (option) takes 8, 16 or 32 channels per lane and one lane per pixel.
 void adjoint_shape(int nch, long npix, bool cube, int *cb, int *lanes, int *kseg) {
     *cb = nch > 8 ? 16 : 8;
     *lanes = 1;
     static const int cand[][2] = {{32, 2}, {24, 2}, {16, 2}, {32, 1}, {24, 1}};
+    int best = 1 << 30;
     for (const auto &cl : cand) {
         const int c = cl[0], gl = cl[1], grp = c * gl;
-        const int nblk = (nch + grp - 1) / grp, pad = nblk * grp - nch;
-        if ((c == 32 && gl == 1 && !cube) || nch <= 16 || 8 * pad > nch || npix * nblk * gl < 2048L * 64) continue;
-        *cb = c;
-        *lanes = gl;
-        break;
+        const int nblk = (nch + grp - 1) / grp, padded = nblk * grp;
+        if ((c == 32 && gl == 1 && !cube) || nch <= 16 || npix * nblk * gl < 2048L * 64) continue;
+        if (padded < best) {
+            best = padded;
+            *cb = c;
+            *lanes = gl;
+        }
     }
     const int ocb = adjoint_block_option();
     if (ocb == 8 || ocb == 16 || ocb == 24 || ocb == 32) *cb = ocb;

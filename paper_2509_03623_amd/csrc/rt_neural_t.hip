@@ -9,8 +9,9 @@
 // plain FP32 VALU work: a workgroup of 128 nodes keeps each node's
 // activations in its own LDS column and accumulates 16 outputs at a time in
 // registers against weights staged in LDS (read as broadcasts).  The weight
-// gradient sums outer products over the nodes: split over node chunks into
-// partial sums, then reduced in a fixed order (deterministic).
+// gradient sums outer products over the nodes: per layer and chunk of 128
+// nodes in LDS into partial sums, then reduced in a fixed order
+// (deterministic).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -35,7 +36,7 @@ static_assert(layer_off(5) == RT_NT_PARAMS, "neural temperature parameter count"
 // activation rows per node: 16 features, 4 x 64 hidden, the output o
 constexpr int kActRows = kNtIn + 4 * kNtW + 1;
 constexpr int kDeltaRows = 4 * kNtW + 1;
-constexpr int kNtChunk = 1024;   // nodes per partial sum of the weight gradient
+constexpr int kNtChunk = 128;    // nodes per partial sum of the weight gradient
 
 __device__ __forceinline__ void node_features(int n, int nr, int nz, float *f) {
     const int i = n / nz, j = n - i * nz;
@@ -175,28 +176,43 @@ __global__ __launch_bounds__(kNtThreads) void nt_delta(int N, const float *__res
     }
 }
 
-// partial weight gradient over one chunk of nodes: for parameter p of layer
-// l, W_l[a][b] gets sum_n dz_{l+1}[a][n] in_l[b][n], b_l[a] gets sum_n dz_{l+1}[a][n]
+// partial weight gradient of layer blockIdx.y over one chunk of kNtChunk
+// nodes: W_l[a][b] gets sum_n dz_{l+1}[a][n] in_l[b][n] and b_l[a] gets
+// sum_n dz_{l+1}[a][n].  The chunk's rows of dz_{l+1} (delta rows l 64 + a,
+// or dL/do for the output layer) and of in_l (the features, or h_l) are
+// staged in LDS; each lane accumulates up to 16 (a, b) entries.
 __global__ __launch_bounds__(256) void nt_wgrad(int N, const float *__restrict__ act, const float *__restrict__ delta,
                                                 float *__restrict__ partial) {
-    const int p = blockIdx.x * 256 + threadIdx.x;
-    if (p >= RT_NT_PARAMS) return;
-    int l = 0;
-    while (l < 4 && p >= layer_off(l + 1)) ++l;
-    const int q = p - layer_off(l), in = layer_in(l);
-    const bool bias = q >= in * layer_out(l);
-    const int a = bias ? q - in * layer_out(l) : q / in, b = bias ? 0 : q - a * in;
-    // rows: dz_{l+1} is delta row l * 64 + a (dL/do for l = 4); in_l is the
-    // features (l = 0) or h_l = act row 16 + (l - 1) * 64 + b
-    const float *A = delta + (size_t)(l == 4 ? kDeltaRows - 1 : l * kNtW + a) * N;
-    const float *B = act + (size_t)(l == 0 ? b : kNtIn + (l - 1) * kNtW + b) * N;
-    const int n0 = blockIdx.y * kNtChunk, n1 = min(N, n0 + kNtChunk);
-    float acc = 0.0f;
-    if (bias)
-        for (int n = n0; n < n1; ++n) acc += A[n];
-    else
-        for (int n = n0; n < n1; ++n) acc = fmaf(A[n], B[n], acc);
-    partial[(size_t)blockIdx.y * RT_NT_PARAMS + p] = acc;
+    __shared__ float sA[kNtW][kNtChunk + 1], sB[kNtW][kNtChunk + 1];
+    const int l = blockIdx.y, M = layer_out(l), K = layer_in(l);
+    const int n0 = blockIdx.x * kNtChunk, t = threadIdx.x;
+    for (int idx = t; idx < kNtW * kNtChunk; idx += 256) {
+        const int r = idx / kNtChunk, k = idx - r * kNtChunk, n = n0 + k;
+        if (r < M) sA[r][k] = n < N ? delta[(size_t)(l == 4 ? kDeltaRows - 1 : l * kNtW + r) * N + n] : 0.0f;
+        if (r < K) sB[r][k] = n < N ? act[(size_t)(l == 0 ? r : kNtIn + (l - 1) * kNtW + r) * N + n] : 0.0f;
+    }
+    __syncthreads();
+    // lane -> row a and a run of nb consecutive columns b0..
+    const int per = (M * K + 255) / 256;          // 16 (64 x 64), 4 (64 x 16), 1 (1 x 64)
+    const int runs = K / per;
+    const int a = t / runs, b0 = (t - a * runs) * per;
+    float *out = partial + (size_t)blockIdx.x * RT_NT_PARAMS + layer_off(l);
+    if (a < M) {
+        float acc[16], bias = 0.0f;
+#pragma unroll
+        for (int c = 0; c < 16; ++c) acc[c] = 0.0f;
+        for (int k = 0; k < kNtChunk; ++k) {
+            const float g = sA[a][k];
+            bias += g;
+#pragma unroll
+            for (int c = 0; c < 16; ++c)
+                if (c < per) acc[c] = fmaf(g, sB[b0 + c][k], acc[c]);
+        }
+#pragma unroll
+        for (int c = 0; c < 16; ++c)
+            if (c < per) out[a * K + b0 + c] = acc[c];
+        if (b0 == 0) out[M * K + a] = bias;
+    }
 }
 
 __global__ __launch_bounds__(256) void nt_wreduce(int chunks, const float *__restrict__ partial,
@@ -273,7 +289,7 @@ extern "C" rt_status rt_neural_temperature_adjoint(const rt_grid *grid, const fl
     const int blocks = (N + kNtThreads - 1) / kNtThreads;
     hipLaunchKernelGGL(nt_fwd, dim3(blocks), dim3(kNtThreads), kNtLds, s, grid->nr, grid->nz, weights, Tn, act);
     hipLaunchKernelGGL(nt_delta, dim3(blocks), dim3(kNtThreads), kNtLds, s, N, weights, d_temp_k, act, del);
-    hipLaunchKernelGGL(nt_wgrad, dim3((RT_NT_PARAMS + 255) / 256, chunks), dim3(256), 0, s, N, act, del, part);
+    hipLaunchKernelGGL(nt_wgrad, dim3(chunks, 5), dim3(256), 0, s, N, act, del, part);
     hipLaunchKernelGGL(nt_wreduce, dim3((RT_NT_PARAMS + 255) / 256), dim3(256), 0, s, chunks, part, d_weights);
     e = hipGetLastError();
     return e == hipSuccess ? RT_OK : fail_hip(e, "neural temperature adjoint");
