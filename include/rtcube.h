@@ -201,6 +201,15 @@ typedef struct {
     float *z_lo_au, *z_up_au;            /* [nr] device */
 } rt_derived;
 
+/* The two-layer temperature of Methods > Parametric disk modeling at every
+ * node: T_mid = t_mid0 (r/r_scale)^q, T_atm = t_atm0 (r/r_scale)^q,
+ * T = T_atm + (T_mid - T_atm) cos^(2 delta)(pi z / (2 z_q)) below
+ * z_q = zq0 (r/r_scale)^1.3 and T_atm above (a single power-law index). */
+typedef struct {
+    double t_mid0_k, t_atm0_k, q, r_scale_au, zq0_au, delta;
+} rt_param_temp;
+rt_status rt_parametric_temperature(const rt_grid *grid, const rt_param_temp *pt, float *temp_k, void *stream);
+
 /* Write every field of *out (all four required). */
 rt_status rt_derive_fields(const rt_derive *d, const rt_derived *out, void *stream);
 
@@ -268,18 +277,21 @@ typedef struct {
     int32_t streams;             /* launches in flight at once (1..8) */
 } rt_server_cfg;
 
-enum { RT_REQ_FWD = 0, RT_REQ_FWD_ADJ = 1 };
+enum { RT_REQ_FWD = 0, RT_REQ_FWD_ADJ = 1, RT_REQ_FWD_LOSS = 2 };
 enum { RT_TICKET_QUEUED = 0, RT_TICKET_RUNNING = 1, RT_TICKET_DONE = 2, RT_TICKET_CANCELED = 3,
        RT_TICKET_FAILED = 4 };
 
 /* kind RT_REQ_FWD renders into cube; RT_REQ_FWD_ADJ also takes target
  * [nch][ny][nx] and writes the gradients of L = sum (cube - target)^2 into
- * grads (L itself is reported by rt_poll). */
+ * grads (L itself is reported by rt_poll); RT_REQ_FWD_LOSS renders and
+ * reports L without gradients (a likelihood evaluation, e.g. one walker of an
+ * ensemble sampler), batched with the other small forwards, L summed on the
+ * device in FP64. */
 typedef struct {
     rt_problem problem;          /* host copy is taken at submit time */
     int32_t kind;
     float *cube;                 /* device, [nch][ny][nx] */
-    const float *target;         /* device, RT_REQ_FWD_ADJ only */
+    const float *target;         /* device, RT_REQ_FWD_ADJ and RT_REQ_FWD_LOSS */
     rt_grads grads;              /* device, RT_REQ_FWD_ADJ only */
 } rt_request;
 
@@ -287,7 +299,7 @@ typedef struct {
     int32_t state;               /* RT_TICKET_* */
     int32_t status;              /* rt_status of the request */
     uint64_t t_submit_ns, t_admit_ns, t_done_ns;   /* steady-clock stamps */
-    double loss;                 /* RT_REQ_FWD_ADJ: L once done */
+    double loss;                 /* RT_REQ_FWD_ADJ / RT_REQ_FWD_LOSS: L once done */
     uint64_t ray_samples;
 } rt_ticket_info;
 

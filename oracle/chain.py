@@ -165,3 +165,20 @@ def derive_fields(T, grid, mstar_msun, mgas_msun, rc_au, gamma, mu, t_freeze_k, 
     N = column(torch.exp(ln_n), r, zr)
     z_lo, z_up = co_surfaces(N, T, r, zr, zr_max, t_freeze_k, n_dissoc)
     return dict(ln_nh2=ln_n, vphi_kms=vphi_kms(ln_n, T, r, zr, mstar_msun, mu), z_lo_au=z_lo, z_up_au=z_up)
+
+
+def parametric_temperature(nr, nz, r_min_au, r_max_au, zr_max, t_mid0_k, t_atm0_k, q, r_scale_au, zq0_au, delta):
+    """Two-layer temperature of Methods, "Parametric Disk Modeling": midplane
+    and atmosphere radial power laws T_mid = t_mid0 (r/r_scale)^q, T_atm =
+    t_atm0 (r/r_scale)^q, blended as T_atm + (T_mid - T_atm) cos^(2 delta)(pi
+    z / (2 z_q)) below z_q(r) = zq0 (r/r_scale)^1.3 and T_atm above, at the
+    grid nodes (float64 numpy [nr][nz])."""
+    r, zr = nodes(nr, nz, r_min_au, r_max_au, zr_max)
+    R, ZR = np.meshgrid(r, zr, indexing="ij")
+    z = ZR * R
+    x = R / r_scale_au
+    t_mid = t_mid0_k * x ** q
+    t_atm = t_atm0_k * x ** q
+    zq = zq0_au * x ** 1.3
+    blend = np.where(z < zq, np.cos(np.pi * z / (2.0 * zq)) ** (2.0 * delta), 0.0)
+    return t_atm + (t_mid - t_atm) * blend

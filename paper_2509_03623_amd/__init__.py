@@ -7,7 +7,7 @@ and streams).
 from ._lib import RtError, lib, RT_MLP_BF16, RT_MLP_FP32, RT_MLP_PARAMS  # noqa: F401
 from .render import (  # noqa: F401
     Scene, scene_from_problem, render, render_adjoint, render_l2_adjoint, Render, render_differentiable,
-    set_option, get_option, constants, DiskPhysics, derive_fields, derive_fields_adjoint, DeriveFields,
+    set_option, get_option, constants, DiskPhysics, derive_fields, derive_fields_adjoint, DeriveFields, parametric_temperature,
 )
 from .server import Server  # noqa: F401
 from .fit import (  # noqa: F401

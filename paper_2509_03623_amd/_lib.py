@@ -21,7 +21,7 @@ STATUS_NAMES = {0: "RT_OK", 1: "RT_PENDING", -1: "RT_EINVAL", -2: "RT_ENOMEM", -
                 -4: "RT_EAGAIN", -5: "RT_ECANCELED", -6: "RT_ETOOBIG", -7: "RT_ENOTFOUND"}
 RT_MLP_FP32, RT_MLP_BF16 = 0, 1
 RT_MLP_PARAMS = 58243
-RT_REQ_FWD, RT_REQ_FWD_ADJ = 0, 1
+RT_REQ_FWD, RT_REQ_FWD_ADJ, RT_REQ_FWD_LOSS = 0, 1, 2
 RT_TICKET_QUEUED, RT_TICKET_RUNNING, RT_TICKET_DONE, RT_TICKET_CANCELED, RT_TICKET_FAILED = 0, 1, 2, 3, 4
 RT_OPT_CHANNEL_BLOCK, RT_OPT_THIN_EXPM1, RT_OPT_CKPT_SEGMENT, RT_OPT_RAY_SPLIT, RT_OPT_GRAD_ACCUM = 1, 2, 3, 4, 5
 RT_OPT_ADJ_SCRATCH_CAP, RT_OPT_ADJ_CHANNEL_BLOCK, RT_OPT_ADJ_PIXEL_LANES = 6, 7, 8
@@ -93,6 +93,11 @@ class rt_derived(C.Structure):
     _fields_ = [("ln_nh2", _dev), ("vphi_kms", _dev), ("z_lo_au", _dev), ("z_up_au", _dev)]
 
 
+class rt_param_temp(C.Structure):
+    _fields_ = [("t_mid0_k", C.c_double), ("t_atm0_k", C.c_double), ("q", C.c_double), ("r_scale_au", C.c_double),
+                ("zq0_au", C.c_double), ("delta", C.c_double)]
+
+
 class rt_adam(C.Structure):
     _fields_ = [("lr", C.c_double), ("beta1", C.c_double), ("beta2", C.c_double), ("eps", C.c_double),
                 ("grad_scale", C.c_double)]
@@ -102,7 +107,7 @@ RT_NT_PARAMS = 13633
 
 # every symbol declared in include/rtcube.h
 EXPORTS = ["rt_render_cube", "rt_render_cube_adjoint", "rt_render_cube_l2_adjoint", "rt_derive_fields",
-           "rt_derive_fields_adjoint", "rt_neural_temperature", "rt_neural_temperature_adjoint", "rt_adam_step",
+           "rt_derive_fields_adjoint", "rt_parametric_temperature", "rt_neural_temperature", "rt_neural_temperature_adjoint", "rt_adam_step",
            "rt_server_create", "rt_submit", "rt_poll", "rt_wait",
            "rt_cancel", "rt_server_destroy", "rt_last_error", "rt_abi_version", "rt_constants",
            "rt_set_option", "rt_get_option"]
@@ -135,6 +140,8 @@ def lib():
         L.rt_derive_fields.restype = C.c_int
         L.rt_derive_fields_adjoint.argtypes = [C.POINTER(rt_derive), C.POINTER(rt_derived), _dev, C.c_void_p]
         L.rt_derive_fields_adjoint.restype = C.c_int
+        L.rt_parametric_temperature.argtypes = [C.POINTER(rt_grid), C.POINTER(rt_param_temp), _dev, C.c_void_p]
+        L.rt_parametric_temperature.restype = C.c_int
         L.rt_neural_temperature.argtypes = [C.POINTER(rt_grid), _dev, _dev, C.c_void_p]
         L.rt_neural_temperature.restype = C.c_int
         L.rt_neural_temperature_adjoint.argtypes = [C.POINTER(rt_grid), _dev, _dev, _dev, C.c_void_p]

@@ -308,6 +308,26 @@ __global__ __launch_bounds__(64) void chain_columns_adj(ChainArgs a, const float
     for (int j = threadIdx.x; j < nz; j += 64) dT[o + j] = sg[j];
 }
 
+// two-layer parametric temperature at every node (one lane per node)
+__global__ __launch_bounds__(256) void parametric_t(int nr, int nz, float r_min, float dlog2r, float dzeta,
+                                                    rt_param_temp pt, float *__restrict__ T) {
+    const int idx = blockIdx.x * 256 + threadIdx.x;
+    if (idx >= nr * nz) return;
+    const int i = idx / nz, j = idx - i * nz;
+    const float r = r_min * exp2f((float)i * dlog2r);
+    const float z = (float)j * dzeta * r;
+    const float lx = logf(r / (float)pt.r_scale_au);
+    const float px = expf((float)pt.q * lx);
+    const float tmid = (float)pt.t_mid0_k * px, tatm = (float)pt.t_atm0_k * px;
+    const float zq = (float)pt.zq0_au * expf(1.3f * lx);
+    float blend = 0.0f;
+    if (z < zq) {
+        const float c = cospif(0.5f * z / zq);
+        blend = c > 0.0f ? expf(2.0f * (float)pt.delta * logf(c)) : 0.0f;
+    }
+    T[idx] = tatm + (tmid - tatm) * blend;
+}
+
 ChainArgs chain_args(const rt_derive *d) {
     const rt_grid &g = d->grid;
     ChainArgs a;
@@ -396,4 +416,21 @@ extern "C" rt_status rt_derive_fields_adjoint(const rt_derive *d, const rt_deriv
                        cot->ln_nh2, cot->z_lo_au, cot->z_up_au, gn, gT, d_temp_k);
     e = hipGetLastError();
     return e == hipSuccess ? RT_OK : fail_hip(e, "derive adjoint");
+}
+
+extern "C" rt_status rt_parametric_temperature(const rt_grid *grid, const rt_param_temp *pt, float *temp_k,
+                                               void *stream) {
+    if (!grid || !pt || !temp_k) return fail(RT_EINVAL, "grid, parameters and temp_k must not be NULL");
+    if (grid->nr < 2 || grid->nz < 2 || !(grid->r_min_au > 0.0) || !(grid->r_max_au > grid->r_min_au) ||
+        !(grid->zr_max > 0.0))
+        return fail(RT_EINVAL, "grid needs nr, nz >= 2, 0 < r_min < r_max, zr_max > 0");
+    if (!(pt->t_mid0_k > 0.0) || !(pt->t_atm0_k > 0.0) || !(pt->r_scale_au > 0.0) || !(pt->zq0_au > 0.0) ||
+        !(pt->delta > 0.0))
+        return fail(RT_EINVAL, "temperatures, r_scale, zq0 and delta must be > 0");
+    const int n = grid->nr * grid->nz;
+    hipLaunchKernelGGL(parametric_t, dim3((n + 255) / 256), dim3(256), 0, (hipStream_t)stream, grid->nr, grid->nz,
+                       (float)grid->r_min_au, (float)(std::log2(grid->r_max_au / grid->r_min_au) / (grid->nr - 1)),
+                       (float)(grid->zr_max / (grid->nz - 1)), *pt, temp_k);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? RT_OK : fail_hip(e, "parametric temperature");
 }

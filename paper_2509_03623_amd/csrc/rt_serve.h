@@ -21,10 +21,14 @@ struct ServeDesc {
     float *cube;          // [nch][ny][nx]
     int32_t nch, nblk, tiles_x;   // channel blocks of 16, item tiles across
     uint32_t item0;       // first work item of this request in the batch
+    const float *target;  // L = sum (cube - target)^2 into *loss (NULL: no loss)
+    double *loss;
 };
 
 hipError_t launch_serve_fwd(const ServeDesc *descs, int nreq, uint32_t nitems, uint32_t *counter, int nwg,
                             hipStream_t st);
 hipError_t launch_l2_loss(const float *cube, const float *target, float *dl, size_t n, double *loss, hipStream_t st);
+// L of every request of a batch that has a target (descs on the device, losses zeroed first)
+hipError_t launch_l2_batch(const ServeDesc *descs, int nreq, double *losses, size_t max_n, hipStream_t st);
 
 } // namespace rt

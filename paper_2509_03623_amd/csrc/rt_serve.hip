@@ -153,6 +153,38 @@ hipError_t launch_l2_value(const float *cube, const float *target, size_t n, dou
     return hipGetLastError();
 }
 
+__global__ void zero_doubles(double *p, int n) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0.0;
+}
+
+// blockIdx.y = request of the batch; each request's elements grid-strided
+// over blockIdx.x, block partial sums added with FP64 atomics
+__global__ __launch_bounds__(256) void l2_batch(const ServeDesc *__restrict__ descs) {
+    const ServeDesc &D = descs[blockIdx.y];
+    if (!D.target) return;
+    __shared__ double part[256];
+    const size_t n = (size_t)D.nch * D.g.nx * D.g.ny;
+    double acc = 0.0;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+        const double r = (double)D.cube[i] - (double)D.target[i];
+        acc += r * r;
+    }
+    part[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) part[threadIdx.x] += part[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicAdd(D.loss, part[0]);
+}
+
+hipError_t launch_l2_batch(const ServeDesc *descs, int nreq, double *losses, size_t max_n, hipStream_t st) {
+    hipLaunchKernelGGL(zero_doubles, dim3(1), dim3(256), 0, st, losses, nreq);
+    const int blocks = (int)std::min<size_t>((max_n + 255) / 256, 256);
+    hipLaunchKernelGGL(l2_batch, dim3(blocks, nreq), dim3(256), 0, st, descs);
+    return hipGetLastError();
+}
+
 hipError_t launch_l2_loss(const float *cube, const float *target, float *dl, size_t n, double *loss, hipStream_t st) {
     hipLaunchKernelGGL(zero_double, dim3(1), dim3(1), 0, st, loss);
     const int blocks = (int)std::min<size_t>((n + 255) / 256, 2048);

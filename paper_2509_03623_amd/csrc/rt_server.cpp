@@ -97,6 +97,7 @@ uint64_t footprint(const rt_request &r) {
     const uint64_t M = npix * p.nsamp;
     uint64_t b = 4 * (3 * nn + 2 * nr) + cube;
     if (p.mlp) b += 4ull * RT_MLP_PARAMS + 16 * M + (1u << 20);
+    if (r.kind == RT_REQ_FWD_LOSS) b += cube;   // target
     if (r.kind == RT_REQ_FWD_ADJ) {
         const int ch = std::min(p.spec.nch, kLaunchChannels);
         b += cube + 4 * (3 * nn + 2 * nr) + 8 * (3 * nn + 2 * nr);   // target, grads, accumulators
@@ -138,7 +139,8 @@ rt_status launch_batch(rt_server *sv, Lane &L, std::vector<Req *> &batch) {
     rt_status rs = lane_vch_capacity(L, nv);
     if (rs != RT_OK) return rs;
     uint32_t items = 0;
-    size_t vo = 0;
+    size_t vo = 0, max_n = 0;
+    bool with_loss = false;
     for (size_t i = 0; i < batch.size(); ++i) {
         const rt_problem &p = batch[i]->rq.problem;
         ServeDesc &D = L.h_desc[i];
@@ -154,6 +156,12 @@ rt_status launch_batch(rt_server *sv, Lane &L, std::vector<Req *> &batch) {
         D.nblk = padded / 16;
         D.tiles_x = (p.cam.nx + kServeTile - 1) / kServeTile;
         D.item0 = items;
+        if (batch[i]->rq.kind == RT_REQ_FWD_LOSS) {
+            D.target = batch[i]->rq.target;
+            D.loss = L.d_loss + i;
+            with_loss = true;
+            max_n = std::max(max_n, (size_t)nch * p.cam.nx * p.cam.ny);
+        }
         items += (uint32_t)(D.tiles_x * ((p.cam.ny + kServeTile - 1) / kServeTile) * D.nblk);
     }
     hipError_t e = hipMemcpyAsync(L.d_desc, L.h_desc, sizeof(ServeDesc) * batch.size(), hipMemcpyHostToDevice, L.st);
@@ -163,6 +171,12 @@ rt_status launch_batch(rt_server *sv, Lane &L, std::vector<Req *> &batch) {
     if ((e = hipGetLastError()) != hipSuccess) return fail_hip(e, "server counter");
     e = launch_serve_fwd(L.d_desc, (int)batch.size(), items, L.d_counter, sv->ncu * kServeWorkgroupsPerCU, L.st);
     if (e != hipSuccess) return fail_hip(e, "server batch launch");
+    if (with_loss) {
+        e = launch_l2_batch(L.d_desc, (int)batch.size(), L.d_loss, max_n, L.st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(L.h_loss, L.d_loss, sizeof(double) * batch.size(), hipMemcpyDeviceToHost, L.st);
+        if (e != hipSuccess) return fail_hip(e, "server batch loss");
+    }
     return RT_OK;
 }
 
@@ -183,12 +197,19 @@ rt_status launch_single(Lane &L, Req *r) {
         if (e != hipSuccess) return fail_hip(e, "loss");
         return RT_OK;
     }
-    if (p->mlp) return render_cube_mlp(p, q.cube, L.st);
-    Geometry g;
-    Shade s;
-    rs = build_launch(p, &g, &s);
-    if (rs == RT_OK) rs = march_cube(p, g, s, q.cube, L.st);
-    return rs;
+    if (p->mlp) {
+        rs = render_cube_mlp(p, q.cube, L.st);
+    } else {
+        Geometry g;
+        Shade s;
+        rs = build_launch(p, &g, &s);
+        if (rs == RT_OK) rs = march_cube(p, g, s, q.cube, L.st);
+    }
+    if (rs != RT_OK || q.kind != RT_REQ_FWD_LOSS) return rs;
+    const size_t n = (size_t)p->spec.nch * p->cam.nx * p->cam.ny;
+    hipError_t e = launch_l2_value(q.cube, q.target, n, L.d_loss, L.st);
+    if (e == hipSuccess) e = hipMemcpyAsync(L.h_loss, L.d_loss, sizeof(double), hipMemcpyDeviceToHost, L.st);
+    return e == hipSuccess ? RT_OK : fail_hip(e, "loss");
 }
 
 void scheduler(rt_server *sv) {
@@ -201,8 +222,9 @@ void scheduler(rt_server *sv) {
             if (!L.busy) continue;
             const hipError_t q = hipEventQuery(L.ev);
             if (q == hipErrorNotReady) continue;
-            for (Req *r : L.reqs) {
-                if (r->rq.kind == RT_REQ_FWD_ADJ) r->loss = *L.h_loss;
+            for (size_t i = 0; i < L.reqs.size(); ++i) {
+                Req *r = L.reqs[i];
+                if (r->rq.kind != RT_REQ_FWD) r->loss = L.h_loss[i];
                 finish(sv, r, q == hipSuccess ? RT_OK : RT_EDEVICE);
             }
             L.reqs.clear();
@@ -287,13 +309,13 @@ rt_status rt_server_create(const rt_server_cfg *cfg, rt_server **out) {
             (e = hipMalloc(&L.d_desc, sizeof(ServeDesc) * cfg->max_slots)) != hipSuccess ||
             (e = hipHostMalloc(&L.h_desc, sizeof(ServeDesc) * cfg->max_slots, hipHostMallocDefault)) != hipSuccess ||
             (e = hipMalloc(&L.d_counter, sizeof(uint32_t))) != hipSuccess ||
-            (e = hipMalloc(&L.d_loss, sizeof(double))) != hipSuccess ||
-            (e = hipHostMalloc(&L.h_loss, sizeof(double), hipHostMallocDefault)) != hipSuccess) {
+            (e = hipMalloc(&L.d_loss, sizeof(double) * cfg->max_slots)) != hipSuccess ||
+            (e = hipHostMalloc(&L.h_loss, sizeof(double) * cfg->max_slots, hipHostMallocDefault)) != hipSuccess) {
             rt_status st = fail_hip(e, "server resources");
             rt_server_destroy(sv.release());
             return st;
         }
-        *L.h_loss = 0.0;
+        for (int i = 0; i < cfg->max_slots; ++i) L.h_loss[i] = 0.0;
         // channel velocities of a full batch of up to kLaunchChannels-channel requests
         rt_status rs = lane_vch_capacity(L, (size_t)cfg->max_slots * kLaunchChannels);
         if (rs != RT_OK) {
@@ -311,8 +333,10 @@ rt_status rt_submit(rt_server *sv, const rt_request *rq, uint64_t *ticket) {
     if (!sv || !rq || !ticket) return fail(RT_EINVAL, "NULL argument");
     rt_status st = validate(&rq->problem);
     if (st != RT_OK) return st;
-    if (rq->kind != RT_REQ_FWD && rq->kind != RT_REQ_FWD_ADJ) return fail(RT_EINVAL, "unknown request kind");
+    if (rq->kind != RT_REQ_FWD && rq->kind != RT_REQ_FWD_ADJ && rq->kind != RT_REQ_FWD_LOSS)
+        return fail(RT_EINVAL, "unknown request kind");
     if (!rq->cube) return fail(RT_EINVAL, "cube is NULL");
+    if (rq->kind == RT_REQ_FWD_LOSS && !rq->target) return fail(RT_EINVAL, "target is NULL");
     if (rq->kind == RT_REQ_FWD_ADJ) {
         if (!rq->target) return fail(RT_EINVAL, "target is NULL");
         if (rq->problem.spec.nch > kLaunchChannels)

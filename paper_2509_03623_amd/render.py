@@ -319,3 +319,14 @@ class DeriveFields(torch.autograd.Function):
         (T,) = ctx.saved_tensors
         cot = dict(ln_nh2=g_n, vphi_kms=g_v, z_lo_au=g_lo, z_up_au=g_up)
         return None, None, derive_fields_adjoint(ctx.grid, T, ctx.phys, cot)
+
+
+def parametric_temperature(grid, t_mid0_k, t_atm0_k, q, r_scale_au, zq0_au, delta, device="cuda",
+                           stream=None) -> torch.Tensor:
+    """Two-layer parametric temperature [nr, nz] at the grid nodes."""
+    nr, nz, r_min, r_max, zr_max = grid
+    T = torch.empty(int(nr), int(nz), dtype=torch.float32, device=device)
+    g = L.rt_grid(int(nr), int(nz), float(r_min), float(r_max), float(zr_max))
+    pt = L.rt_param_temp(t_mid0_k, t_atm0_k, q, r_scale_au, zq0_au, delta)
+    L.check(L.lib().rt_parametric_temperature(C.byref(g), C.byref(pt), _fptr(T), C.c_void_p(_stream(stream))))
+    return T

@@ -25,13 +25,17 @@ class Server:
         self._keep = {}
 
     def submit(self, sc: Scene, cube: torch.Tensor, target: Optional[torch.Tensor] = None,
-               grads: Optional[dict] = None) -> int:
+               grads: Optional[dict] = None, loss_only: bool = False) -> int:
         """Queue a render into cube [nch, ny, nx]; with target, also the
-        gradients of sum (cube - target)^2 into the tensors of grads."""
+        gradients of L = sum (cube - target)^2 into the tensors of grads, or
+        with loss_only just L (reported by poll / wait)."""
         p, keep = problem_struct(sc)
         rq = L.rt_request()
         rq.problem = p
-        rq.kind = L.RT_REQ_FWD if target is None else L.RT_REQ_FWD_ADJ
+        if target is None:
+            rq.kind = L.RT_REQ_FWD
+        else:
+            rq.kind = L.RT_REQ_FWD_LOSS if loss_only else L.RT_REQ_FWD_ADJ
         rq.cube = _fptr(cube)
         rq.target = _fptr(target)
         g = grads or {}

@@ -182,3 +182,21 @@ def test_chain_gradient_matches_central_differences():
         with torch.no_grad():
             fd = (loss(torch.as_tensor(tp)) - loss(torch.as_tensor(tm))).item() / (2 * h)
         assert g[i, j] == pytest.approx(fd, rel=1e-5, abs=1e-9 * np.abs(g).max()), (i, j)
+
+
+def test_parametric_temperature_special_heights():
+    """Midplane: T_mid; at and above z_q: T_atm; delta = 1 at z_q / 2:
+    cos^2(pi/4) = 1/2, the mean of the two layers."""
+    nr, nz = 5, 401
+    args = dict(t_mid0_k=30.0, t_atm0_k=70.0, q=-0.5, r_scale_au=100.0, zq0_au=12.0, delta=1.0)
+    T = C.parametric_temperature(nr, nz, 10.0, 400.0, 0.5, **args)
+    r, zr = C.nodes(nr, nz, 10.0, 400.0, 0.5)
+    x = r / 100.0
+    np.testing.assert_allclose(T[:, 0], 30.0 * x ** -0.5, rtol=1e-14)
+    zq = 12.0 * x ** 1.3
+    z = r[:, None] * zr[None, :]
+    above = z >= zq[:, None]
+    np.testing.assert_allclose(T[above], (70.0 * x[:, None] ** -0.5 * np.ones((1, nz)))[above], rtol=1e-14)
+    # r = 100 au: x = 1, z_q = 12 au; the node at z = 6 au is z/r = 0.06 -> j = 0.06 / 0.5 * 400 = 48
+    T1 = C.parametric_temperature(2, 401, 100.0, 400.0, 0.5, **args)
+    assert T1[0, 48] == pytest.approx(50.0, rel=1e-12)

@@ -126,3 +126,13 @@ def test_temperature_gradient_through_derived_fields_and_render():
     ((c - torch.tensor(target, dtype=torch.float32, device="cuda")) ** 2).sum().backward()
     torch.cuda.synchronize()
     _check_grad("end-to-end dL/dT", Tg.grad.cpu().numpy(), ref, rel=2e-3)
+
+
+@pytest.mark.parametrize("grid,args", [((64, 48, 1.0, 600.0, 0.5), (30.0, 60.0, -0.5, 100.0, 70.0, 2.0)),
+                                       ((33, 21, 5.0, 300.0, 0.4), (18.0, 45.0, -0.3, 150.0, 40.0, 1.0))])
+def test_parametric_temperature_matches_oracle(grid, args):
+    rt = _rt()
+    T = rt.parametric_temperature(grid, *args)
+    torch.cuda.synchronize()
+    ref = OC.parametric_temperature(*grid, *args)
+    np.testing.assert_allclose(T.cpu().numpy(), ref, rtol=2e-6)

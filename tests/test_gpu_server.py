@@ -216,3 +216,36 @@ def test_neural_requests_match_direct_calls():
     for k in ("temp_k", "mlp_w"):
         d = float((grads[k] - ref[k]).abs().max())
         assert d <= 1e-4 * float(ref[k].abs().max()), k
+
+
+def test_loss_requests_match_direct_render_and_loss():
+    """RT_REQ_FWD_LOSS: the cube of the batched launch and L = sum (cube -
+    target)^2 summed on the device, against rt_render_cube and an FP64 host
+    sum; the same request alone and inside a batch of walkers and forwards."""
+    rt = _rt()
+    print("[gpu] server loss-only requests", flush=True)
+    walkers = [scene(40 + 8 * (i % 3), 12 + 4 * (i % 4), 64 + 16 * (i % 2), seed=2020 + i) for i in range(10)]
+    targets = [rt.render(sc) * 1.03 + 0.01 for _, sc in walkers]
+    direct = [rt.render(sc) for _, sc in walkers]
+    torch.cuda.synchronize()
+    ref_loss = [float(((d.double() - t.double()) ** 2).sum()) for d, t in zip(direct, targets)]
+    with rt.Server(max_slots=32, streams=3) as sv:
+        c0 = empty_cube(walkers[0][1])
+        t0 = sv.submit(walkers[0][1], c0, target=targets[0], loss_only=True)
+        alone = sv.wait(t0)
+        assert alone["state"] == "done"
+        outs = [empty_cube(sc) for _, sc in walkers]
+        extra = [scene(56, 20, 96, seed=2040 + i) for i in range(3)]
+        eouts = [empty_cube(sc) for _, sc in extra]
+        ts = [sv.submit(sc, o, target=t, loss_only=True) for (_, sc), o, t in zip(walkers, outs, targets)]
+        te = [sv.submit(sc, o) for (_, sc), o in zip(extra, eouts)]
+        infos = [sv.wait(t) for t in ts]
+        for t in te:
+            assert sv.wait(t)["state"] == "done"
+    torch.cuda.synchronize()
+    assert alone["loss"] == pytest.approx(ref_loss[0], rel=1e-6)
+    for i, (info, o) in enumerate(zip(infos, outs)):
+        assert info["state"] == "done", i
+        assert float((o - direct[i]).abs().max()) <= 1e-6 * float(direct[i].abs().max()), i
+        assert info["loss"] == pytest.approx(ref_loss[i], rel=1e-6), i
+    assert infos[0]["loss"] == pytest.approx(alone["loss"], rel=1e-12)
