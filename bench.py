@@ -220,6 +220,8 @@ def main():
         out["derived_fields"] = bench_derived(rt, synth, dev, args)
         log("neural-temperature fitting step")
         out["neural_t_fit"] = bench_fit(rt, synth, dev, args)
+        log("ensemble-sampler iteration (60 walkers)")
+        out["walkers"] = bench_walkers(rt, synth, dev, args)
     if args.serve_seconds > 0:
         log(f"served stream ({args.serve_seconds:g} s trace, then the serial replay and the saturated runs)")
         out["served"], out["serial"], out["saturated"] = bench_serving(rt, synth, dev, args.serve_seconds)
@@ -350,6 +352,61 @@ def bench_fit(rt, synth, dev, args):
     return {"workload": "256x256 px, 115 ch (0.04 km/s), 256 samples, batch 50, 256x128 grid",
             "ms_per_step": dt * 1e3, "ray_samples_per_s": rs / dt, "steps": steps,
             "chi2_first": float(chi2[0].item()), "chi2_last": float(chi2[-1].item())}
+
+
+def bench_walkers(rt, synth, dev, args, nwalk=60, iters=3):
+    """One iteration of an ensemble sampler's likelihood evaluations (Methods,
+    "MCMC inference": 60 walkers): per walker a two-layer parametric
+    temperature and stellar mass perturbed around the truth, the derived fields
+    on the device, and the render of 128 x 128 px x 32 ch x 256 samples with
+    L = sum (cube - observed)^2 -- served as loss-only requests (batched into
+    the persistent launch) against one at a time (render, then the loss)."""
+    import numpy as np
+    import torch
+    prob = synth.config2(2000, nx=128, ny=128, nch=32, nsamp=256)
+    gs = prob.grid
+    grid = (gs.nr, gs.nz, gs.r_min_au, gs.r_max_au, gs.zr_max)
+    sc0 = rt.scene_from_problem(prob, device=dev)
+    p = synth.disk.DiskParams()
+    truth = np.array([30.0, 60.0, -0.5, 100.0, 70.0, 2.0, p.mstar_msun])
+
+    def fields(th):
+        T = rt.parametric_temperature(grid, *th[:6], device=dev)
+        phys = rt.DiskPhysics(th[6], p.mgas_msun, p.rc_au, p.gamma, synth.disk.MU_GAS, p.t_freeze_k, p.n_dissoc)
+        return dict(temp_k=T, **rt.derive_fields(grid, T, phys))
+
+    observed = rt.render(sc0.replace(**fields(truth)))
+    rng = np.random.Generator(np.random.PCG64(21))
+    walkers = [truth * (1.0 + 0.05 * rng.standard_normal(truth.shape)) for _ in range(nwalk)]
+    cubes = [torch.empty_like(observed) for _ in range(nwalk)]
+    out = {"walkers": nwalk, "workload": "128x128 px x 32 ch x 256 samples per walker, 256x128 grid"}
+    rs = sc0.ray_samples * nwalk
+    with rt.Server(max_slots=nwalk, streams=4) as sv:
+        def served():
+            scs = [sc0.replace(**fields(th)) for th in walkers]
+            torch.cuda.synchronize()
+            ts = [sv.submit(sc, c, target=observed, loss_only=True) for sc, c in zip(scs, cubes)]
+            return [sv.wait(t)["loss"] for t in ts]
+
+        def serial():
+            losses = []
+            for th, c in zip(walkers, cubes):
+                rt.render(sc0.replace(**fields(th)), out=c)
+                losses.append(float(((c.double() - observed.double()) ** 2).sum()))
+            return losses
+
+        for name, f in (("served", served), ("serial", serial)):
+            f()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(iters):
+                losses = f()
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / iters
+            out[name] = {"ms_per_iteration": dt * 1e3, "walkers_per_s": nwalk / dt, "ray_samples_per_s": rs / dt}
+        out["best_walker_loss_over_truth_scale"] = float(min(losses) / float((observed.double() ** 2).sum()))
+    out["served_vs_serial"] = out["served"]["walkers_per_s"] / out["serial"]["walkers_per_s"]
+    return out
 
 
 def bench_mlp(rt, synth, dev, args):
