@@ -346,3 +346,195 @@ int orc_constants(double *out, int n)
     for (int i = 0; i < n && i < 6; ++i) out[i] = v[i];
     return 6;
 }
+
+/* ============================================================ 3-D spherical grid
+ *
+ * Fields on a spherical node grid (r log-spaced on [r_min, r_max], polar angle
+ * theta linear on [theta_min, theta_max], azimuth phi_k = 2 pi k / nphi,
+ * periodic), layout [nr][ntheta][nphi]: ln n_H2, T, the velocity components
+ * (v_r, v_theta, v_phi) and the CO abundance x_CO.  Trilinear interpolation in
+ * (ln r, theta, phi), clamped to the edge in r and theta, periodic in phi; the
+ * density fades linearly to zero one cell beyond the radial and polar ranges.
+ * Every ray's chord through the sphere r <= r_max e^dln is cut into nsamp
+ * equal segments; the line physics is that of the 2-D march with
+ * n_CO = x_CO n_H2 and v_los = v_sys + v . w (w = (0, sin i, -cos i), the ray
+ * direction in the disk frame). */
+typedef struct {
+    int32_t nr, nt, np;
+    double r_min_au, r_max_au, th_min, th_max;
+    const float *ln_nh2, *temp_k, *v_r, *v_t, *v_p, *x_co;   /* [nr][nt][np] */
+    double v_turb;
+    double nu0_hz, a_ul, g_u, g_l, e_u_k, e_l_k, m_co_amu, m_mol_amu;
+    int32_t nlev;
+    const double *lev_e_k, *lev_g;
+    int32_t nx, ny;
+    double fov_au, incl_deg, pa_deg;
+    int32_t nch;
+    const double *v_kms;
+    double v_sys_kms;
+    int32_t nsamp;
+    double intensity_scale;
+} orc_problem3;
+
+static void sample_point3(const orc_problem3 *P, double px, double py, double pz, orc_sample *o)
+{
+    memset(o, 0, sizeof *o);
+    const double r = sqrt(px * px + py * py + pz * pz);
+    if (r == 0.0) return;
+    const double rho = sqrt(px * px + py * py);
+    const double th = acos(clampd(pz / r, -1.0, 1.0));
+    double ph = atan2(py, px);
+    if (ph < 0.0) ph += 2.0 * ORC_PI;
+    const double dln = log(P->r_max_au / P->r_min_au) / (P->nr - 1);
+    const double dth = (P->th_max - P->th_min) / (P->nt - 1);
+    const double dph = 2.0 * ORC_PI / P->np;
+    const double u = log(r / P->r_min_au) / dln, w = (th - P->th_min) / dth, s = ph / dph;
+    const double uc = clampd(u, 0.0, P->nr - 1), wc = clampd(w, 0.0, P->nt - 1);
+    int i0 = (int)floor(uc); if (i0 > P->nr - 2) i0 = P->nr - 2;
+    int j0 = (int)floor(wc); if (j0 > P->nt - 2) j0 = P->nt - 2;
+    int k0 = (int)floor(s);
+    const double fu = uc - i0, fw = wc - j0, fs = s - k0;
+    k0 = ((k0 % P->np) + P->np) % P->np;
+    const int k1 = (k0 + 1) % P->np;
+    double wgt[8];
+    size_t idx[8];
+    int m = 0;
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b)
+            for (int c = 0; c < 2; ++c) {
+                wgt[m] = (a ? fu : 1 - fu) * (b ? fw : 1 - fw) * (c ? fs : 1 - fs);
+                idx[m] = ((size_t)(i0 + a) * P->nt + (j0 + b)) * P->np + (c ? k1 : k0);
+                ++m;
+            }
+#define TRI(F) (wgt[0] * (double)(F)[idx[0]] + wgt[1] * (double)(F)[idx[1]] + wgt[2] * (double)(F)[idx[2]] + \
+                wgt[3] * (double)(F)[idx[3]] + wgt[4] * (double)(F)[idx[4]] + wgt[5] * (double)(F)[idx[5]] + \
+                wgt[6] * (double)(F)[idx[6]] + wgt[7] * (double)(F)[idx[7]])
+    const double ln_n = TRI(P->ln_nh2), t = TRI(P->temp_k), xco = TRI(P->x_co);
+    const double vr = TRI(P->v_r), vt = TRI(P->v_t), vp = TRI(P->v_p);
+#undef TRI
+    const double taper = clampd(u + 1.0, 0.0, 1.0) * clampd(P->nr - u, 0.0, 1.0) * clampd(w + 1.0, 0.0, 1.0) *
+                         clampd(P->nt - w, 0.0, 1.0);
+    const double nco = xco * exp(ln_n) * taper;
+    double zpart = 0.0;
+    for (int j = 0; j < P->nlev; ++j) zpart += P->lev_g[j] * exp(-P->lev_e_k[j] / t);
+    const double nu = nco * P->g_u * exp(-P->e_u_k / t) / zpart;
+    const double nl = nco * P->g_l * exp(-P->e_l_k / t) / zpart;
+    const double nu0 = P->nu0_hz;
+    const double bul = P->a_ul * ORC_C * ORC_C / (2.0 * ORC_H * nu0 * nu0 * nu0);
+    const double blu = P->g_u / P->g_l * bul;
+    const double pre = ORC_H * nu0 / (4.0 * ORC_PI);
+    const double jbar = pre * nu * P->a_ul;
+    const double kbar = pre * (nl * blu - nu * bul);
+    o->kbar = kbar;
+    o->S = kbar > 0.0 ? jbar / kbar : 0.0;
+    o->nu = nu;
+    const double thv = 2.0 * ORC_KB * t / (P->m_co_amu * ORC_AMU);
+    const double cs2 = 2.0 * ORC_KB * t / (P->m_mol_amu * ORC_AMU);
+    o->alpha = sqrt(thv + P->v_turb * P->v_turb * cs2) / 1e5;
+    /* unit vectors at the sample, projected on the ray direction w */
+    const double ang = P->incl_deg * ORC_PI / 180.0;
+    const double si = sin(ang), ci = cos(ang);
+    double vw = vr * (py * si - pz * ci) / r;
+    if (rho > 0.0) {
+        const double cth = pz / r, sth = rho / r;
+        vw += vt * (cth * (py / rho) * si + sth * ci);       /* theta-hat = (cos th cos ph, cos th sin ph, -sin th) */
+        vw += vp * (px / rho) * si;                          /* phi-hat = (-sin ph, cos ph, 0) */
+    }
+    o->vlos = P->v_sys_kms + vw;
+}
+
+static void march3(const orc_problem3 *P, int p, int q, double *I, double *S_out, double *dtau_out,
+                   double *chord_out)
+{
+    const int nch = P->nch;
+    double *tr = (double *)malloc(sizeof(double) * nch);
+    for (int c = 0; c < nch; ++c) { I[c] = 0.0; tr[c] = 1.0; }
+    const double d = P->fov_au / P->nx;
+    const double X = (p + 0.5 - 0.5 * P->nx) * d, Y = (q + 0.5 - 0.5 * P->ny) * d;
+    const double pa = P->pa_deg * ORC_PI / 180.0;
+    const double xp = cos(pa) * X - sin(pa) * Y, yp = sin(pa) * X + cos(pa) * Y;
+    const double dln = log(P->r_max_au / P->r_min_au) / (P->nr - 1);
+    const double Rc = P->r_max_au * exp(dln);
+    const double h2 = Rc * Rc - xp * xp - yp * yp;
+    if (!(h2 > 0.0)) {
+        if (chord_out) { chord_out[0] = chord_out[1] = chord_out[2] = 0.0; }
+        if (S_out) for (int k = 0; k < P->nsamp; ++k) S_out[k] = 0.0;
+        if (dtau_out) for (int k = 0; k < P->nsamp * nch; ++k) dtau_out[k] = 0.0;
+        free(tr);
+        return;
+    }
+    const double sa = -sqrt(h2), sb = sqrt(h2), ds = (sb - sa) / P->nsamp;
+    if (chord_out) { chord_out[0] = sa; chord_out[1] = sb; chord_out[2] = ds; }
+    const double ds_cm = ds * ORC_AU;
+    const double ang = P->incl_deg * ORC_PI / 180.0;
+    const double si = sin(ang), ci = cos(ang);
+    for (int k = 0; k < P->nsamp; ++k) {
+        const double s = sa + (k + 0.5) * ds;
+        const double px = xp, py = yp * ci + s * si, pz = yp * si - s * ci;
+        orc_sample smp;
+        sample_point3(P, px, py, pz, &smp);
+        if (S_out) S_out[k] = smp.S;
+        for (int c = 0; c < nch; ++c) {
+            double dtau = 0.0;
+            if (smp.alpha > 0.0) {
+                const double dd = (smp.vlos - P->v_kms[c]) / smp.alpha;
+                dtau = smp.kbar * (ORC_C / P->nu0_hz) / (smp.alpha * 1e5 * sqrt(ORC_PI)) * exp(-dd * dd) * ds_cm;
+            }
+            if (dtau_out) dtau_out[(size_t)k * nch + c] = dtau;
+            I[c] += tr[c] * smp.S * (-expm1(-dtau));
+            tr[c] *= exp(-dtau);
+        }
+    }
+    for (int c = 0; c < nch; ++c) I[c] *= P->intensity_scale;
+    free(tr);
+}
+
+int orc_render3(const orc_problem3 *P, double *cube, int nthreads)
+{
+    if (!P || !cube || P->nr < 2 || P->nt < 2 || P->np < 1 || P->nx < 1 || P->ny < 1 || P->nch < 1 || P->nsamp < 1)
+        return -1;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 1)
+#endif
+    for (int q = 0; q < P->ny; ++q) {
+        double *I = (double *)malloc(sizeof(double) * P->nch);
+        for (int p = 0; p < P->nx; ++p) {
+            march3(P, p, q, I, NULL, NULL, NULL);
+            for (int c = 0; c < P->nch; ++c) cube[((size_t)c * P->ny + q) * P->nx + p] = I[c];
+        }
+        free(I);
+    }
+    (void)nthreads;
+    return 0;
+}
+
+int orc_render3_pixels(const orc_problem3 *P, int npix, const int32_t *px, const int32_t *py, double *out,
+                       int nthreads)
+{
+    if (!P || !out || npix < 0) return -1;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 1)
+#endif
+    for (int n = 0; n < npix; ++n) march3(P, px[n], py[n], out + (size_t)n * P->nch, NULL, NULL, NULL);
+    (void)nthreads;
+    return 0;
+}
+
+int orc_ray_dump3(const orc_problem3 *P, int p, int q, double *I, double *S, double *dtau, double *ch)
+{
+    if (!P) return -1;
+    march3(P, p, q, I, S, dtau, ch);
+    return 0;
+}
+
+/* One point of a 3-D problem: out = {S, kbar, alpha, vlos, n_u}. */
+int orc_sample_point3(const orc_problem3 *P, double px, double py, double pz, double *out)
+{
+    if (!P || !out) return -1;
+    orc_sample s;
+    sample_point3(P, px, py, pz, &s);
+    out[0] = s.S; out[1] = s.kbar; out[2] = s.alpha; out[3] = s.vlos; out[4] = s.nu;
+    return 0;
+}

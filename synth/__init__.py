@@ -13,3 +13,4 @@ from .disk import (  # noqa: F401
 )
 from .mlp import mlp_param_count, make_mlp_weights, MLP_WIDTH, MLP_DEPTH, MLP_NFREQ  # noqa: F401
 from .trace import make_trace  # noqa: F401
+from . import disk3d  # noqa: F401
