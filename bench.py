@@ -131,6 +131,7 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-disks", action="store_true", help="skip the forward rate over eight seeded disks")
     ap.add_argument("--no-mlp", action="store_true", help="skip the neural CO layer leg")
+    ap.add_argument("--no-3d", action="store_true", help="skip the 3-D spherical-grid leg")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first copy 1 GiB device to device three times (a kernel of known traffic, to scale "
                          "hardware byte counters)")
@@ -211,6 +212,9 @@ def main():
     if not args.no_mlp:
         log("neural CO layer")
         out["neural"] = bench_mlp(rt, synth, dev, args)
+    if not args.no_3d:
+        log("3-D spherical grid 512x96x256 (channel and image-size sweeps)")
+        out["render3d"] = bench_render3d(rt, dev, args)
     if not args.no_adjoint:
         log("forward + adjoint")
         try:
@@ -231,6 +235,78 @@ def main():
         log("oracle on the host cores")
         out["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds)
     print(json.dumps(out), flush=True)
+
+
+def bench_render3d(rt, dev, args):
+    """Forward march over a seeded non-axisymmetric disk on the 512 x 96 x 256
+    spherical grid of the paper's runtime benchmark, 512 samples per ray:
+    256^2 pixels at 20, 64 and 128 channels, and 20 channels at 128^2, 256^2
+    and 512^2 pixels.  The node packing (six planes -> interleaved records,
+    once per snapshot) is timed on its own.  Ray-samples count every pixel;
+    live_fraction is the share of rays that cross the bounding sphere (the
+    others do no work)."""
+    import math
+    import numpy as np
+    import torch
+    from synth import disk3d as S3
+    grid = S3.Grid3Spec(512, 96, 256)
+    base = S3.make_problem3(grid, seed=65, nx=256, ny=256, nch=20, dv=0.25, nsamp=512, incl=40.0, pa=30.0)
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a, np.float32), device=dev)
+    planes = [t(a) for a in (base.ln_nh2, base.temp_k, base.x_co, base.v_r_kms, base.v_theta_kms, base.v_phi_kms)]
+    sc0 = rt.scene3d_from_problem(base, device=dev)
+    nodes = sc0.nodes
+    steps = max(5, args.steps // 2)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        rt.pack_fields3d(sc0.grid, *planes, out=nodes)
+    e1.record()
+    torch.cuda.synchronize()
+    pack_ms = e0.elapsed_time(e1) / steps
+    out = {"grid": "512x96x256", "nsamp": 512, "pack_ms": pack_ms,
+           "pack_gb_per_s": (24 + 32) * nodes.numel() / 8 / (pack_ms * 1e-3) / 1e9}
+    rc = grid.r_max_au * math.exp(math.log(grid.r_max_au / grid.r_min_au) / (grid.nr - 1))
+    legs = [("256x256x20ch", 256, 20), ("256x256x64ch", 256, 64), ("256x256x128ch", 256, 128),
+            ("128x128x20ch", 128, 20), ("512x512x20ch", 512, 20)]
+    for name, npx, nch in legs:
+        sc = sc0.replace(nx=npx, ny=npx, v_kms=synth_channels(nch, 0.25))
+        cube = torch.empty(nch, npx, npx, device=dev)
+        for _ in range(2):
+            rt.render3d(sc, out=cube)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e0.record()
+        for _ in range(steps):
+            rt.render3d(sc, out=cube)
+        e1.record()
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / steps
+        kern = e0.elapsed_time(e1) / steps * 1e-3
+        d = sc.fov_au / npx
+        xy = (np.arange(npx) + 0.5 - npx / 2) * d
+        live = float(np.mean(xy[:, None] ** 2 + xy[None, :] ** 2 < rc * rc))
+        cb, ns = auto_shape(nch, npx * npx, 512)
+        out[name] = {"ms": wall * 1e3, "kernel_ms": kern * 1e3, "ray_samples_per_s": sc.ray_samples / wall,
+                     "live_fraction": live, "channel_block": cb, "ray_split": ns}
+        log(f"3-D {name}: {wall * 1e3:.3f} ms, {sc.ray_samples / wall:.3e} ray-samples/s")
+    if not args.no_cpu:
+        import oracle
+        rng = np.random.Generator(np.random.PCG64(98))
+        n = 2000
+        px, py = rng.integers(0, 256, n).astype(np.int32), rng.integers(0, 256, n).astype(np.int32)
+        ncores = os.cpu_count() or 1
+        t0 = time.perf_counter()
+        oracle.render3_pixels(base, px, py, nthreads=ncores)
+        dt = time.perf_counter() - t0
+        out["cpu_oracle"] = {"ray_samples_per_s": n * 20 * 512 / dt, "cores": ncores,
+                             "sample": f"{n} seeded random pixels of 256x256x20ch, FP64 scalar C, OpenMP"}
+    return out
+
+
+def synth_channels(nch, dv):
+    import numpy as np
+    return (np.arange(nch, dtype=np.float64) - (nch - 1) / 2.0) * dv
 
 
 def bench_adjoint(rt, synth, dev, args):

@@ -310,6 +310,59 @@ rt_status rt_wait(rt_server *sv, uint64_t ticket, rt_ticket_info *info, uint64_t
 rt_status rt_cancel(rt_server *sv, uint64_t ticket);
 rt_status rt_server_destroy(rt_server *sv);   /* drains admitted work, cancels the rest */
 
+/* ---------------------------------------------------------------- 3-D spherical grid
+ *
+ * Non-axisymmetric fields (a hydrodynamic snapshot of T, n and v on a
+ * spherical grid, as in the paper's runtime benchmark, Results "Runtime"):
+ * the same LTE line physics and formal solution as the axisymmetric
+ * renderer, with
+ *   - nodes r_i = r_min (r_max/r_min)^(i/(nr-1)), theta_j = th_min + j (th_max -
+ *     th_min)/(nt-1) (polar angle from +z), phi_k = 2 pi k / np (from +x
+ *     towards +y); every field trilinear in (ln r, theta, phi) index space,
+ *     clamped to the edge in r and theta, periodic in phi; n_H2 fades
+ *     linearly to zero one cell beyond the radial and polar node ranges;
+ *   - n_CO = x_CO n_H2 with x_CO a field (no surfaces, no mask);
+ *   - v_los = v_sys + v . w, w = (0, sin i, -cos i), with v = v_r e_r +
+ *     v_theta e_theta + v_phi e_phi (the polar and azimuthal terms vanish on
+ *     the z axis);
+ *   - each ray's chord through the sphere r <= r_max e^dln is cut into nsamp
+ *     equal segments; camera, pixels and channels as in the axisymmetric
+ *     renderer; inclination 0..180 deg (180: seen from -z).
+ */
+typedef struct {
+    int32_t nr, nt, np;        /* nr, nt >= 2; np >= 1; nr nt np <= 2^28 */
+    double r_min_au, r_max_au; /* 0 < r_min_au < r_max_au */
+    double th_min, th_max;     /* polar angle of the first and last theta node [rad], 0 <= th_min < th_max <= pi */
+} rt_grid3d;
+
+/* Fields of the march: nodes = [nr][nt][np] records of 8 floats {ln n_H2
+ * [cm^-3], T [K] (> 0), x_CO, v_r, v_theta, v_phi [km/s], 0, 0} as written by
+ * rt_pack_fields3d (device, 16-byte aligned, nr nt np 32 bytes). */
+typedef struct {
+    rt_grid3d grid;
+    const float *nodes;
+    double v_turb;             /* turbulent Mach number, >= 0 */
+    rt_line line;
+    rt_camera cam;
+    rt_spectral spec;
+    int32_t nsamp;             /* samples per ray, >= 1 */
+    double intensity_scale;    /* output = scale * I_nu */
+} rt_problem3d;
+
+/* Interleave six field planes [nr][nt][np] (device float32; ln_nh2, temp_k,
+ * x_co required; NULL velocity planes are zero) into the node records of
+ * rt_problem3d.nodes (device, caller-allocated nr nt np 8 floats, 16-byte
+ * aligned).  RT_EINVAL on a bad grid or pointer. */
+rt_status rt_pack_fields3d(const rt_grid3d *grid, const float *ln_nh2, const float *temp_k, const float *x_co,
+                           const float *v_r, const float *v_theta, const float *v_phi, float *nodes, void *stream);
+
+/* Render the cube [nch][ny][nx] (device float32) of a 3-D problem (Methods,
+ * "Line Radiative Transfer": the discrete formal solution along each ray).
+ * RT_OPT_CHANNEL_BLOCK and RT_OPT_RAY_SPLIT apply as in rt_render_cube;
+ * 1 - e^-dtau is evaluated directly.  RT_EINVAL on invalid arguments,
+ * RT_EDEVICE if a launch fails. */
+rt_status rt_render_cube_3d(const rt_problem3d *p, float *cube, void *stream);
+
 /* ---------------------------------------------------------------- misc */
 const char *rt_last_error(void);
 int32_t rt_abi_version(void);

@@ -84,6 +84,7 @@ int channel_block_for(int nch, long npix) {
 
 bool thin_series() { return g_opt_thin != 0; }
 int ckpt_segment_option() { return (int)g_opt_ckpt; }
+int ray_split_option() { return (int)g_opt_split; }
 bool grad_accum_double() { return g_opt_accum != 0; }
 int adjoint_block_option() { return (int)g_opt_adj_cb; }
 int adjoint_lanes_option() { return (int)g_opt_adj_lanes; }
@@ -91,6 +92,33 @@ size_t adjoint_scratch_cap() { return g_opt_adj_cap > 0 ? (size_t)g_opt_adj_cap 
 
 // ---------------------------------------------------------------- validation
 static bool finite(double x) { return std::isfinite(x); }
+
+// line, camera, spectral axis and sampling, shared by every renderer
+rt_status validate_view(const rt_line &l, const rt_camera &c, const rt_spectral &s, int32_t nsamp,
+                        double intensity_scale, double max_incl_deg) {
+    if (!(finite(l.nu0_hz) && l.nu0_hz > 0 && finite(l.a_ul) && l.a_ul >= 0 && l.g_u > 0 && l.g_l > 0 &&
+          finite(l.g_u) && finite(l.g_l) && finite(l.e_u_k) && finite(l.e_l_k) && l.e_l_k >= 0 &&
+          l.m_co_amu > 0 && l.m_mol_amu > 0 && finite(l.m_co_amu) && finite(l.m_mol_amu)))
+        return fail(RT_EINVAL, "invalid line data");
+    if (l.nlev < 1 || !l.lev_e_k || !l.lev_g) return fail(RT_EINVAL, "level table missing");
+    for (int i = 0; i < l.nlev; ++i)
+        if (!(finite(l.lev_e_k[i]) && l.lev_e_k[i] >= 0 && finite(l.lev_g[i]) && l.lev_g[i] >= 0))
+            return fail(RT_EINVAL, "invalid level %d", i);
+    if (c.nx < 1 || c.ny < 1) return fail(RT_EINVAL, "need nx, ny >= 1");
+    if ((int64_t)c.nx * c.ny > (int64_t)1 << 30) return fail(RT_EINVAL, "image too large");
+    if (!(finite(c.fov_au) && c.fov_au > 0)) return fail(RT_EINVAL, "need fov_au > 0");
+    if (!(finite(c.incl_deg) && c.incl_deg >= 0 && c.incl_deg <= max_incl_deg))
+        return fail(RT_EINVAL, "inclination must be within [0, %g] deg", max_incl_deg);
+    if (!finite(c.pa_deg)) return fail(RT_EINVAL, "position angle not finite");
+    if (s.nch < 1 || s.nch > RT_MAX_CHANNELS) return fail(RT_EINVAL, "need 1 <= nch <= %d", RT_MAX_CHANNELS);
+    if (!s.v_kms) return fail(RT_EINVAL, "channel velocities missing");
+    for (int i = 0; i < s.nch; ++i)
+        if (!finite(s.v_kms[i])) return fail(RT_EINVAL, "channel %d velocity not finite", i);
+    if (!finite(s.v_sys_kms)) return fail(RT_EINVAL, "v_sys not finite");
+    if (nsamp < 1 || nsamp > (1 << 20)) return fail(RT_EINVAL, "need 1 <= nsamp <= 2^20");
+    if (!finite(intensity_scale)) return fail(RT_EINVAL, "intensity_scale not finite");
+    return RT_OK;
+}
 
 rt_status validate(const rt_problem *p) {
     if (!p) return fail(RT_EINVAL, "problem is NULL");
@@ -106,30 +134,8 @@ rt_status validate(const rt_problem *p) {
     if (!(finite(f.x_co) && f.x_co >= 0)) return fail(RT_EINVAL, "need x_co >= 0");
     if (!(finite(f.mask_width) && f.mask_width > 0)) return fail(RT_EINVAL, "need mask_width > 0");
     if (!(finite(f.v_turb) && f.v_turb >= 0)) return fail(RT_EINVAL, "need v_turb >= 0");
-    const rt_line &l = p->line;
-    if (!(finite(l.nu0_hz) && l.nu0_hz > 0 && finite(l.a_ul) && l.a_ul >= 0 && l.g_u > 0 && l.g_l > 0 &&
-          finite(l.g_u) && finite(l.g_l) && finite(l.e_u_k) && finite(l.e_l_k) && l.e_l_k >= 0 &&
-          l.m_co_amu > 0 && l.m_mol_amu > 0 && finite(l.m_co_amu) && finite(l.m_mol_amu)))
-        return fail(RT_EINVAL, "invalid line data");
-    if (l.nlev < 1 || !l.lev_e_k || !l.lev_g) return fail(RT_EINVAL, "level table missing");
-    for (int i = 0; i < l.nlev; ++i)
-        if (!(finite(l.lev_e_k[i]) && l.lev_e_k[i] >= 0 && finite(l.lev_g[i]) && l.lev_g[i] >= 0))
-            return fail(RT_EINVAL, "invalid level %d", i);
-    const rt_camera &c = p->cam;
-    if (c.nx < 1 || c.ny < 1) return fail(RT_EINVAL, "need nx, ny >= 1");
-    if ((int64_t)c.nx * c.ny > (int64_t)1 << 30) return fail(RT_EINVAL, "image too large");
-    if (!(finite(c.fov_au) && c.fov_au > 0)) return fail(RT_EINVAL, "need fov_au > 0");
-    if (!(finite(c.incl_deg) && c.incl_deg >= 0 && c.incl_deg <= 90))
-        return fail(RT_EINVAL, "inclination must be within [0, 90] deg");
-    if (!finite(c.pa_deg)) return fail(RT_EINVAL, "position angle not finite");
-    const rt_spectral &s = p->spec;
-    if (s.nch < 1 || s.nch > RT_MAX_CHANNELS) return fail(RT_EINVAL, "need 1 <= nch <= %d", RT_MAX_CHANNELS);
-    if (!s.v_kms) return fail(RT_EINVAL, "channel velocities missing");
-    for (int i = 0; i < s.nch; ++i)
-        if (!finite(s.v_kms[i])) return fail(RT_EINVAL, "channel %d velocity not finite", i);
-    if (!finite(s.v_sys_kms)) return fail(RT_EINVAL, "v_sys not finite");
-    if (p->nsamp < 1 || p->nsamp > (1 << 20)) return fail(RT_EINVAL, "need 1 <= nsamp <= 2^20");
-    if (!finite(p->intensity_scale)) return fail(RT_EINVAL, "intensity_scale not finite");
+    rt_status st = validate_view(p->line, p->cam, p->spec, p->nsamp, p->intensity_scale, 90.0);
+    if (st != RT_OK) return st;
     if (p->mlp) {
         if (!p->mlp->weights) return fail(RT_EINVAL, "mlp weights missing");
         if (p->mlp->precision != RT_MLP_FP32 && p->mlp->precision != RT_MLP_BF16)

@@ -10,6 +10,10 @@ namespace rt {
 rt_status fail(rt_status st, const char *fmt, ...);
 rt_status fail_hip(hipError_t e, const char *what);
 rt_status validate(const rt_problem *p);
+rt_status validate_view(const rt_line &l, const rt_camera &c, const rt_spectral &s, int32_t nsamp,
+                        double intensity_scale, double max_incl_deg);
+// Z(T) table of the line's levels on the current device (built once per level set)
+rt_status partition_table(const rt_line &l, const float4 **out);
 rt_status build_launch(const rt_problem *p, Geometry *g, Shade *s);
 int channel_block_for(int nch, long npix);
 void forward_shape(int nch, long npix, int nsamp, int *cb, int *nsplit);
@@ -19,6 +23,7 @@ void forward_shape(int nch, long npix, int nsamp, int *cb, int *nsplit);
 void adjoint_shape(int nch, long npix, bool cube, int *cb, int *lanes, int *kseg);
 bool thin_series();
 int ckpt_segment_option();
+int ray_split_option();
 int adjoint_block_option();
 int adjoint_lanes_option();
 bool grad_accum_double();

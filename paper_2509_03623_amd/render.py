@@ -330,3 +330,113 @@ def parametric_temperature(grid, t_mid0_k, t_atm0_k, q, r_scale_au, zq0_au, delt
     pt = L.rt_param_temp(t_mid0_k, t_atm0_k, q, r_scale_au, zq0_au, delta)
     L.check(L.lib().rt_parametric_temperature(C.byref(g), C.byref(pt), _fptr(T), C.c_void_p(_stream(stream))))
     return T
+
+
+# ---------------------------------------------------------------- 3-D spherical grid
+
+@dataclass
+class Scene3d:
+    """A 3-D problem with its packed node records resident on the GPU.
+    grid = (nr, nt, np, r_min_au, r_max_au, th_min, th_max); nodes: [nr, nt,
+    np, 8] float32 from pack_fields3d."""
+    grid: tuple
+    nodes: torch.Tensor
+    v_turb: float
+    nu0_hz: float
+    a_ul: float
+    g_u: float
+    g_l: float
+    e_u_k: float
+    e_l_k: float
+    m_co_amu: float
+    m_mol_amu: float
+    lev_e_k: np.ndarray
+    lev_g: np.ndarray
+    nx: int
+    ny: int
+    fov_au: float
+    incl_deg: float
+    pa_deg: float
+    dist_pc: float
+    v_kms: np.ndarray
+    v_sys_kms: float
+    nsamp: int
+    intensity_scale: float = 1.0
+
+    @property
+    def nch(self) -> int:
+        return int(len(self.v_kms))
+
+    @property
+    def ray_samples(self) -> int:
+        return self.nx * self.ny * self.nch * self.nsamp
+
+    def replace(self, **kw) -> "Scene3d":
+        return replace(self, **kw)
+
+
+def _grid3d(grid) -> "L.rt_grid3d":
+    nr, nt, nph, r_min, r_max, th_min, th_max = grid
+    return L.rt_grid3d(int(nr), int(nt), int(nph), float(r_min), float(r_max), float(th_min), float(th_max))
+
+
+def pack_fields3d(grid, ln_nh2, temp_k, x_co, v_r=None, v_theta=None, v_phi=None, out=None,
+                  stream=None) -> torch.Tensor:
+    """Interleave the six [nr, nt, np] planes into the node records [nr, nt, np, 8]."""
+    nr, nt, nph = (int(v) for v in grid[:3])
+    n = nr * nt * nph
+    for name, t in (("ln_nh2", ln_nh2), ("temp_k", temp_k), ("x_co", x_co), ("v_r", v_r), ("v_theta", v_theta),
+                    ("v_phi", v_phi)):
+        if t is not None and t.numel() != n:
+            raise ValueError(f"{name} has {t.numel()} elements, expected {n}")
+    if out is None:
+        out = torch.empty(nr, nt, nph, 8, dtype=torch.float32, device=ln_nh2.device)
+    if out.numel() != 8 * n:
+        raise ValueError("node buffer has the wrong size")
+    g = _grid3d(grid)
+    L.check(L.lib().rt_pack_fields3d(C.byref(g), _fptr(ln_nh2), _fptr(temp_k), _fptr(x_co), _fptr(v_r),
+                                     _fptr(v_theta), _fptr(v_phi), _fptr(out), C.c_void_p(_stream(stream))))
+    return out
+
+
+def scene3d_from_problem(prob, device="cuda") -> Scene3d:
+    """Copy a 3-D problem (attributes as in synth.disk3d.Problem3) to the GPU and pack its fields."""
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a, np.float32), device=device)
+    g, cam, line = prob.grid, prob.camera, prob.line
+    grid = (g.nr, g.nt, g.nphi, g.r_min_au, g.r_max_au, g.th_min, g.th_max)
+    nodes = pack_fields3d(grid, t(prob.ln_nh2), t(prob.temp_k), t(prob.x_co), t(prob.v_r_kms),
+                          t(prob.v_theta_kms), t(prob.v_phi_kms))
+    return Scene3d(grid=grid, nodes=nodes, v_turb=prob.v_turb, nu0_hz=line.nu0_hz, a_ul=line.a_ul, g_u=line.g_u,
+                   g_l=line.g_l, e_u_k=line.e_u_k, e_l_k=line.e_l_k, m_co_amu=line.m_co_amu,
+                   m_mol_amu=line.m_mol_amu, lev_e_k=np.ascontiguousarray(line.lev_e_k, np.float64),
+                   lev_g=np.ascontiguousarray(line.lev_g, np.float64), nx=cam.nx, ny=cam.ny, fov_au=cam.fov_au,
+                   incl_deg=cam.incl_deg, pa_deg=cam.pa_deg, dist_pc=cam.dist_pc,
+                   v_kms=np.ascontiguousarray(prob.v_kms, np.float64), v_sys_kms=prob.v_sys_kms,
+                   nsamp=prob.nsamp, intensity_scale=prob.intensity_scale)
+
+
+def render3d(sc: Scene3d, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """Cube [nch, ny, nx] (float32) of a 3-D scene."""
+    nr, nt, nph = (int(v) for v in sc.grid[:3])
+    if sc.nodes.numel() != 8 * nr * nt * nph:
+        raise ValueError("node records do not match the grid")
+    if out is None:
+        out = torch.empty(sc.nch, sc.ny, sc.nx, dtype=torch.float32, device=sc.nodes.device)
+    if out.shape != (sc.nch, sc.ny, sc.nx):
+        raise ValueError("output has the wrong shape")
+    lev_e = np.ascontiguousarray(sc.lev_e_k, np.float64)
+    lev_g = np.ascontiguousarray(sc.lev_g, np.float64)
+    vk = np.ascontiguousarray(sc.v_kms, np.float64)
+    p = L.rt_problem3d()
+    p.grid = _grid3d(sc.grid)
+    p.nodes = _fptr(sc.nodes)
+    p.v_turb = sc.v_turb
+    p.line = L.rt_line(sc.nu0_hz, sc.a_ul, sc.g_u, sc.g_l, sc.e_u_k, sc.e_l_k, sc.m_co_amu, sc.m_mol_amu,
+                       len(lev_e), lev_e.ctypes.data_as(C.POINTER(C.c_double)),
+                       lev_g.ctypes.data_as(C.POINTER(C.c_double)))
+    p.cam = L.rt_camera(sc.nx, sc.ny, sc.fov_au, sc.incl_deg, sc.pa_deg, sc.dist_pc)
+    p.spec = L.rt_spectral(len(vk), vk.ctypes.data_as(C.POINTER(C.c_double)), sc.v_sys_kms)
+    p.nsamp = sc.nsamp
+    p.intensity_scale = sc.intensity_scale
+    L.check(L.lib().rt_render_cube_3d(C.byref(p), _fptr(out), C.c_void_p(_stream(stream))))
+    return out

@@ -145,3 +145,58 @@ def test_derive_null_outputs_rejected():
     assert L.lib().rt_derive_fields(C.byref(d), C.byref(L.rt_derived(fake, None, fake, fake)), None) == L.RT_EINVAL
     assert L.lib().rt_derive_fields_adjoint(C.byref(d), None, fake, None) == L.RT_EINVAL
     assert L.lib().rt_derive_fields_adjoint(C.byref(d), C.byref(L.rt_derived()), None, None) == L.RT_EINVAL
+
+
+def _problem3d():
+    line = synth.disk.co21_line()
+    lev_e = np.ascontiguousarray(line.lev_e_k, np.float64)
+    lev_g = np.ascontiguousarray(line.lev_g, np.float64)
+    vk = np.linspace(-1.0, 1.0, 5)
+    p = L.rt_problem3d()
+    p.grid = L.rt_grid3d(16, 8, 12, 5.0, 400.0, 1.0, 2.1)
+    p.nodes = 0x1000
+    p.v_turb = 0.05
+    p.line = L.rt_line(line.nu0_hz, line.a_ul, line.g_u, line.g_l, line.e_u_k, line.e_l_k, line.m_co_amu,
+                       line.m_mol_amu, len(lev_e), lev_e.ctypes.data_as(C.POINTER(C.c_double)),
+                       lev_g.ctypes.data_as(C.POINTER(C.c_double)))
+    p.cam = L.rt_camera(8, 8, 900.0, 120.0, 0.0, 100.0)
+    p.spec = L.rt_spectral(len(vk), vk.ctypes.data_as(C.POINTER(C.c_double)), 0.0)
+    p.nsamp = 64
+    p.intensity_scale = 1.0
+    return p, (lev_e, lev_g, vk)
+
+
+@pytest.mark.parametrize("mutate,msg", [
+    (lambda p: setattr(p.grid, "nt", 1), "nt >= 2"),
+    (lambda p: setattr(p.grid, "np", 0), "np >= 1"),
+    (lambda p: setattr(p.grid, "th_max", 3.5), "pi"),
+    (lambda p: setattr(p.grid, "th_min", 2.5), "th_min < th_max"),
+    (lambda p: setattr(p.grid, "r_min_au", 0.0), "r_min"),
+    (lambda p: (setattr(p.grid, "nr", 4096), setattr(p.grid, "nt", 4096), setattr(p.grid, "np", 32)), "2^28"),
+    (lambda p: setattr(p, "nodes", None), "nodes"),
+    (lambda p: setattr(p, "nodes", 0x1004), "aligned"),
+    (lambda p: setattr(p, "v_turb", -1.0), "v_turb"),
+    (lambda p: setattr(p.cam, "incl_deg", 181.0), "inclination"),
+    (lambda p: setattr(p, "nsamp", 0), "nsamp"),
+    (lambda p: setattr(p.spec, "nch", 0), "nch"),
+])
+def test_render3d_validation_rejects_on_host(mutate, msg):
+    p, keep = _problem3d()
+    mutate(p)
+    assert L.lib().rt_render_cube_3d(C.byref(p), C.c_void_p(0x2000), None) == L.RT_EINVAL
+    assert msg in L.lib().rt_last_error().decode()
+
+
+def test_render3d_null_cube_and_pack_validation():
+    p, keep = _problem3d()
+    assert L.lib().rt_render_cube_3d(C.byref(p), None, None) == L.RT_EINVAL
+    assert L.lib().rt_render_cube_3d(None, C.c_void_p(0x2000), None) == L.RT_EINVAL
+    fake = C.c_void_p(0x1000)
+    g = L.rt_grid3d(16, 8, 12, 5.0, 400.0, 1.0, 2.1)
+    lib = L.lib()
+    assert lib.rt_pack_fields3d(C.byref(g), fake, fake, None, None, None, None, fake, None) == L.RT_EINVAL
+    assert "required" in lib.rt_last_error().decode()
+    assert lib.rt_pack_fields3d(C.byref(g), fake, fake, fake, None, None, None, None, None) == L.RT_EINVAL
+    assert lib.rt_pack_fields3d(C.byref(g), fake, fake, fake, None, None, None, C.c_void_p(0x1008), None) == L.RT_EINVAL
+    bad = L.rt_grid3d(16, 8, 12, 5.0, 400.0, 0.0, 4.0)
+    assert lib.rt_pack_fields3d(C.byref(bad), fake, fake, fake, None, None, None, fake, None) == L.RT_EINVAL
