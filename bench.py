@@ -38,18 +38,23 @@ LOOP_FLOP, LOOP_VALU, LOOP_TRANS = 11, 6, 2
 # partition function, populations, source function, width, projected
 # velocity, log2 of the line-centre depth.
 SHADE_FLOP, SHADE_VALU, SHADE_TRANS = 151, 100, 15
+# The 3-D march's shading of one pixel-sample (spherical coordinates, radial
+# refinement, two atan2, trilinear fetch of six fields, physics, projected
+# velocity), counted in the compiled sample loop of march3_fwd<24, 4>: 307
+# VALU + 16 transcendental = 371 issue slots, shared by a lane's channels.
+SHADE3_SLOTS = 307 + 4 * 16
 
 
 # HBM traffic of one forward launch on the full-size render of disk 2000,
 # from two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch)
 # of `bench.py --copy-probe`, each scaled by what the same counter reads for
-# a 1 GiB device-to-device copy (FETCH_SIZE 524 304 KiB -> x2.0000,
+# a 1 GiB device-to-device copy (FETCH_SIZE 524 302 KiB -> x2.0000,
 # WRITE_SIZE 1 048 576 KiB -> x1.0000).  Valid only for the kernel sources it
 # was taken on: the hash of those files is checked at run time.
 FWD_TRAFFIC = {"sources": ("paper_2509_03623_amd/csrc/rt_forward.hip", "paper_2509_03623_amd/csrc/rt_kernels.h",
                            "paper_2509_03623_amd/csrc/rt_launch.h"),
-               "sha256": "dfa0a9ad4b8c05969b1bd0ac5619c155321e9d63a1b281c07ba8d04fbfe7b939",
-               "fetch_kib": 1266.0, "fetch_scale": 1048576 / 524303.5,
+               "sha256": "88562a102f664e17f4603de17902d7063fca80ec8ca1107169c56536bdc774e8",
+               "fetch_kib": 1239.2, "fetch_scale": 1048576 / 524302.4,
                "write_kib": 65536.0, "write_scale": 1.0}
 
 
@@ -132,6 +137,8 @@ def main():
     ap.add_argument("--no-disks", action="store_true", help="skip the forward rate over eight seeded disks")
     ap.add_argument("--no-mlp", action="store_true", help="skip the neural CO layer leg")
     ap.add_argument("--no-3d", action="store_true", help="skip the 3-D spherical-grid leg")
+    ap.add_argument("--only", choices=("render3d",), default=None,
+                    help="run one leg alone and print its JSON (for profiling)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first copy 1 GiB device to device three times (a kernel of known traffic, to scale "
                          "hardware byte counters)")
@@ -159,6 +166,9 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.only == "render3d":
+        print(json.dumps({"render3d": bench_render3d(rt, dev, args)}), flush=True)
+        return
     prob = synth.config2(args.seed)
     sc = rt.scene_from_problem(prob, device=dev)
     cube = torch.empty(sc.nch, sc.ny, sc.nx, device=dev)
@@ -287,8 +297,12 @@ def bench_render3d(rt, dev, args):
         xy = (np.arange(npx) + 0.5 - npx / 2) * d
         live = float(np.mean(xy[:, None] ** 2 + xy[None, :] ** 2 < rc * rc))
         cb, ns = auto_shape(nch, npx * npx, 512)
+        nchb = -(-nch // cb)
+        slots = live * npx * npx * 512 * nchb * (cb * (LOOP_VALU + TRANS_SLOTS * LOOP_TRANS) + SHADE3_SLOTS)
+        hbm = 24 * grid.nr * grid.nt * grid.nphi + 4 * nch * npx * npx
         out[name] = {"ms": wall * 1e3, "kernel_ms": kern * 1e3, "ray_samples_per_s": sc.ray_samples / wall,
-                     "live_fraction": live, "channel_block": cb, "ray_split": ns}
+                     "live_fraction": live, "channel_block": cb, "ray_split": ns,
+                     "alu_frac": slots / LANE_SLOTS_PER_S / kern, "hbm_frac": hbm / kern / 8e12}
         log(f"3-D {name}: {wall * 1e3:.3f} ms, {sc.ray_samples / wall:.3e} ray-samples/s")
     if not args.no_cpu:
         import oracle
