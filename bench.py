@@ -137,6 +137,7 @@ def main():
     ap.add_argument("--no-disks", action="store_true", help="skip the forward rate over eight seeded disks")
     ap.add_argument("--no-mlp", action="store_true", help="skip the neural CO layer leg")
     ap.add_argument("--no-3d", action="store_true", help="skip the 3-D spherical-grid leg")
+    ap.add_argument("--no-beam", action="store_true", help="skip the beam-convolution leg")
     ap.add_argument("--only", choices=("render3d",), default=None,
                     help="run one leg alone and print its JSON (for profiling)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -222,6 +223,9 @@ def main():
     if not args.no_mlp:
         log("neural CO layer")
         out["neural"] = bench_mlp(rt, synth, dev, args)
+    if not args.no_beam:
+        log("beam convolution of the full-size cube")
+        out["beam"] = bench_beam(rt, cube, args)
     if not args.no_3d:
         log("3-D spherical grid 512x96x256 (channel and image-size sweeps)")
         out["render3d"] = bench_render3d(rt, dev, args)
@@ -316,6 +320,30 @@ def bench_render3d(rt, dev, args):
         out["cpu_oracle"] = {"ray_samples_per_s": n * 20 * 512 / dt, "cores": ncores,
                              "sample": f"{n} seeded random pixels of 256x256x20ch, FP64 scalar C, OpenMP"}
     return out
+
+
+def bench_beam(rt, cube, args, beam=(6.0, 4.0, 30.0)):
+    """The full-size cube (512^2 x 64) convolved with a 6 x 4 px beam at
+    30 deg: (2R+1)^2 FMAs per output (R = 8), against the FP32 issue rate."""
+    import math
+    import torch
+    out = torch.empty_like(cube)
+    steps = max(5, args.steps // 2)
+    for _ in range(2):
+        rt.beam_convolve(cube, *beam, out=out)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        rt.beam_convolve(cube, *beam, out=out)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    R = math.ceil(3.0 * beam[0] / (2.0 * math.sqrt(2.0 * math.log(2.0))))
+    fma = (2 * R + 1) ** 2 * cube.numel()
+    return {"ms": ms, "beam_px": list(beam), "radius": R, "outputs_per_s": cube.numel() / (ms * 1e-3),
+            "tflop_per_s": 2 * fma / (ms * 1e-3) / 1e12, "alu_frac": fma / LANE_SLOTS_PER_S / (ms * 1e-3),
+            "hbm_gb_per_s": 8 * cube.numel() / (ms * 1e-3) / 1e9}
 
 
 def synth_channels(nch, dv):

@@ -363,6 +363,31 @@ rt_status rt_pack_fields3d(const rt_grid3d *grid, const float *ln_nh2, const flo
  * RT_EDEVICE if a launch fails. */
 rt_status rt_render_cube_3d(const rt_problem3d *p, float *cube, void *stream);
 
+/* ---------------------------------------------------------------- beam convolution
+ *
+ * A model cube is compared with an interferometric image at the image's
+ * resolution (Methods, MCMC inference: model cubes against the observed
+ * channel maps; the paper does not give the convolution, read here as
+ * follows).  Every channel map is convolved with an elliptical Gaussian of
+ * full widths at half maximum bmaj_px >= bmin_px (pixels), major axis at
+ * position angle bpa_deg from +y towards -x, sampled at integer pixel offsets
+ * within |dx|, |dy| <= R = ceil(3 bmaj_px / (2 sqrt(2 ln 2))), normalised to
+ * unit sum; pixels outside the image count as zero.  The operator is its own
+ * adjoint (point-symmetric kernel, zero padding): dL/din = rt_beam_convolve
+ * of dL/dout.
+ */
+#define RT_BEAM_MAX_RADIUS 24    /* R <= 24 pixels: bmaj_px <= 18.8 */
+typedef struct {
+    double bmaj_px, bmin_px, bpa_deg;
+} rt_beam;
+
+/* out = beam * in for a cube [nch][ny][nx] (device float32, nch <= 65535);
+ * in and out must not overlap.  The weights live in a library-owned
+ * per-stream scratch buffer.  RT_EINVAL on invalid sizes, beams or overlap,
+ * RT_ENOMEM / RT_EDEVICE if the scratch or a launch fails. */
+rt_status rt_beam_convolve(const float *in, float *out, int32_t nch, int32_t ny, int32_t nx, const rt_beam *beam,
+                           void *stream);
+
 /* ---------------------------------------------------------------- misc */
 const char *rt_last_error(void);
 int32_t rt_abi_version(void);

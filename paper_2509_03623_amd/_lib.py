@@ -111,6 +111,13 @@ class rt_grid3d(C.Structure):
                 ("r_max_au", C.c_double), ("th_min", C.c_double), ("th_max", C.c_double)]
 
 
+class rt_beam(C.Structure):
+    _fields_ = [("bmaj_px", C.c_double), ("bmin_px", C.c_double), ("bpa_deg", C.c_double)]
+
+
+RT_BEAM_MAX_RADIUS = 24
+
+
 class rt_problem3d(C.Structure):
     _fields_ = [("grid", rt_grid3d), ("nodes", _dev), ("v_turb", C.c_double), ("line", rt_line),
                 ("cam", rt_camera), ("spec", rt_spectral), ("nsamp", C.c_int32), ("intensity_scale", C.c_double)]
@@ -118,7 +125,7 @@ class rt_problem3d(C.Structure):
 # every symbol declared in include/rtcube.h
 EXPORTS = ["rt_render_cube", "rt_render_cube_adjoint", "rt_render_cube_l2_adjoint", "rt_derive_fields",
            "rt_derive_fields_adjoint", "rt_parametric_temperature", "rt_neural_temperature", "rt_neural_temperature_adjoint", "rt_adam_step",
-           "rt_pack_fields3d", "rt_render_cube_3d",
+           "rt_pack_fields3d", "rt_render_cube_3d", "rt_beam_convolve",
            "rt_server_create", "rt_submit", "rt_poll", "rt_wait",
            "rt_cancel", "rt_server_destroy", "rt_last_error", "rt_abi_version", "rt_constants",
            "rt_set_option", "rt_get_option"]
@@ -163,6 +170,8 @@ def lib():
         L.rt_pack_fields3d.restype = C.c_int
         L.rt_render_cube_3d.argtypes = [C.POINTER(rt_problem3d), _dev, C.c_void_p]
         L.rt_render_cube_3d.restype = C.c_int
+        L.rt_beam_convolve.argtypes = [_dev, _dev, C.c_int32, C.c_int32, C.c_int32, C.POINTER(rt_beam), C.c_void_p]
+        L.rt_beam_convolve.restype = C.c_int
         L.rt_server_create.argtypes = [C.POINTER(rt_server_cfg), C.POINTER(C.c_void_p)]
         L.rt_server_create.restype = C.c_int
         L.rt_submit.argtypes = [C.c_void_p, C.POINTER(rt_request), C.POINTER(C.c_uint64)]

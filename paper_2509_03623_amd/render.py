@@ -440,3 +440,33 @@ def render3d(sc: Scene3d, out: Optional[torch.Tensor] = None, stream=None) -> to
     p.intensity_scale = sc.intensity_scale
     L.check(L.lib().rt_render_cube_3d(C.byref(p), _fptr(out), C.c_void_p(_stream(stream))))
     return out
+
+
+# ---------------------------------------------------------------- beam convolution
+
+def beam_convolve(cube: torch.Tensor, bmaj_px: float, bmin_px: float, bpa_deg: float,
+                  out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """cube [nch, ny, nx] convolved with the normalised elliptical Gaussian beam."""
+    if cube.dim() != 3:
+        raise ValueError("expected a cube [nch, ny, nx]")
+    if out is None:
+        out = torch.empty_like(cube)
+    if out.shape != cube.shape:
+        raise ValueError("output has the wrong shape")
+    b = L.rt_beam(float(bmaj_px), float(bmin_px), float(bpa_deg))
+    nch, ny, nx = cube.shape
+    L.check(L.lib().rt_beam_convolve(_fptr(cube), _fptr(out), nch, ny, nx, C.byref(b), C.c_void_p(_stream(stream))))
+    return out
+
+
+class BeamConvolve(torch.autograd.Function):
+    """BeamConvolve.apply(cube, bmaj_px, bmin_px, bpa_deg); the operator is its own adjoint."""
+
+    @staticmethod
+    def forward(ctx, cube, bmaj_px, bmin_px, bpa_deg):
+        ctx.beam = (bmaj_px, bmin_px, bpa_deg)
+        return beam_convolve(cube.detach().contiguous(), bmaj_px, bmin_px, bpa_deg)
+
+    @staticmethod
+    def backward(ctx, g):
+        return beam_convolve(g.contiguous(), *ctx.beam), None, None, None

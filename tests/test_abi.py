@@ -200,3 +200,21 @@ def test_render3d_null_cube_and_pack_validation():
     assert lib.rt_pack_fields3d(C.byref(g), fake, fake, fake, None, None, None, C.c_void_p(0x1008), None) == L.RT_EINVAL
     bad = L.rt_grid3d(16, 8, 12, 5.0, 400.0, 0.0, 4.0)
     assert lib.rt_pack_fields3d(C.byref(bad), fake, fake, fake, None, None, None, fake, None) == L.RT_EINVAL
+
+
+@pytest.mark.parametrize("args,msg", [
+    ((0x1000, 0x100000, 0, 8, 8, (4.0, 3.0, 0.0)), "nch"),
+    ((0x1000, 0x100000, 1, 8, 8, (3.0, 4.0, 0.0)), "bmin_px <= bmaj_px"),
+    ((0x1000, 0x100000, 1, 8, 8, (4.0, 0.0, 0.0)), "0 < bmin_px"),
+    ((0x1000, 0x100000, 1, 8, 8, (4.0, 3.0, float("nan"))), "finite"),
+    ((0x1000, 0x100000, 1, 8, 8, (40.0, 3.0, 0.0)), "radius"),
+    ((0x1000, 0x1010, 1, 8, 8, (4.0, 3.0, 0.0)), "overlap"),
+    ((None, 0x100000, 1, 8, 8, (4.0, 3.0, 0.0)), "required"),
+    ((0x1000, 0x100000, 70000, 8, 8, (4.0, 3.0, 0.0)), "too large"),
+])
+def test_beam_validation_rejects_on_host(args, msg):
+    src, dst, nch, ny, nx, b = args
+    beam = L.rt_beam(*b)
+    assert L.lib().rt_beam_convolve(src, dst, nch, ny, nx, C.byref(beam), None) == L.RT_EINVAL
+    assert msg in L.lib().rt_last_error().decode()
+    assert L.lib().rt_beam_convolve(0x1000, 0x100000, 1, 8, 8, None, None) == L.RT_EINVAL
