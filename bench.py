@@ -99,6 +99,16 @@ def auto_shape(nch: int, npix: int, nsamp: int):
     return cb, ns
 
 
+def auto_shape3(nch: int, npix: int, nsamp: int):
+    """The library's automatic (channel block, ray split) of the 3-D march."""
+    cb = next((c for c in (8, 16, 24, 32, 48, 64) if c >= nch), 64)
+    waves = lambda ns: ((npix * ns + 63) // 64) * ((nch + cb - 1) // cb)
+    ns = 1
+    while ns < 8 and waves(2 * ns) < 4096 and nsamp >= 64 * ns:
+        ns *= 2
+    return cb, ns
+
+
 def cpu_baseline(prob, seconds=12.0):
     """FP64 oracle on seeded pixels of the same workload, all host cores."""
     import numpy as np
@@ -300,7 +310,7 @@ def bench_render3d(rt, dev, args):
         d = sc.fov_au / npx
         xy = (np.arange(npx) + 0.5 - npx / 2) * d
         live = float(np.mean(xy[:, None] ** 2 + xy[None, :] ** 2 < rc * rc))
-        cb, ns = auto_shape(nch, npx * npx, 512)
+        cb, ns = auto_shape3(nch, npx * npx, 512)
         nchb = -(-nch // cb)
         slots = live * npx * npx * 512 * nchb * (cb * (LOOP_VALU + TRANS_SLOTS * LOOP_TRANS) + SHADE3_SLOTS)
         hbm = 24 * grid.nr * grid.nt * grid.nphi + 4 * nch * npx * npx

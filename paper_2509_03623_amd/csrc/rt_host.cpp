@@ -85,6 +85,7 @@ int channel_block_for(int nch, long npix) {
 bool thin_series() { return g_opt_thin != 0; }
 int ckpt_segment_option() { return (int)g_opt_ckpt; }
 int ray_split_option() { return (int)g_opt_split; }
+int channel_block_option() { return (int)g_opt_cb; }
 bool grad_accum_double() { return g_opt_accum != 0; }
 int adjoint_block_option() { return (int)g_opt_adj_cb; }
 int adjoint_lanes_option() { return (int)g_opt_adj_lanes; }

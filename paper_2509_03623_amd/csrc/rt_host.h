@@ -24,6 +24,7 @@ void adjoint_shape(int nch, long npix, bool cube, int *cb, int *lanes, int *kseg
 bool thin_series();
 int ckpt_segment_option();
 int ray_split_option();
+int channel_block_option();
 int adjoint_block_option();
 int adjoint_lanes_option();
 bool grad_accum_double();
