@@ -488,7 +488,8 @@ def bench_walkers(rt, synth, dev, args, nwalk=60, iters=3):
     temperature and stellar mass perturbed around the truth, the derived fields
     on the device, and the render of 128 x 128 px x 32 ch x 256 samples with
     L = sum (cube - observed)^2 -- served as loss-only requests (batched into
-    the persistent launch) against one at a time (render, then the loss)."""
+    the persistent launch) against one at a time (render, then the loss);
+    and the same with the model cube convolved with a beam before the loss."""
     import numpy as np
     import torch
     prob = synth.config2(2000, nx=128, ny=128, nch=32, nsamp=256)
@@ -523,7 +524,26 @@ def bench_walkers(rt, synth, dev, args, nwalk=60, iters=3):
                 losses.append(float(((c.double() - observed.double()) ** 2).sum()))
             return losses
 
-        for name, f in (("served", served), ("serial", serial)):
+        beam = (4.0, 3.0, 30.0)
+        observed_b = rt.beam_convolve(observed, *beam)
+        tmp = torch.empty_like(observed)
+
+        def served_beam():
+            scs = [sc0.replace(**fields(th)) for th in walkers]
+            torch.cuda.synchronize()
+            ts = [sv.submit(sc, c, target=observed_b, loss_only=True, beam=beam) for sc, c in zip(scs, cubes)]
+            return [sv.wait(t)["loss"] for t in ts]
+
+        def serial_beam():
+            losses = []
+            for th, c in zip(walkers, cubes):
+                rt.render(sc0.replace(**fields(th)), out=tmp)
+                rt.beam_convolve(tmp, *beam, out=c)
+                losses.append(float(((c.double() - observed_b.double()) ** 2).sum()))
+            return losses
+
+        for name, f in (("served", served), ("serial", serial), ("served_beam", served_beam),
+                        ("serial_beam", serial_beam)):
             f()
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -534,6 +554,7 @@ def bench_walkers(rt, synth, dev, args, nwalk=60, iters=3):
             out[name] = {"ms_per_iteration": dt * 1e3, "walkers_per_s": nwalk / dt, "ray_samples_per_s": rs / dt}
         out["best_walker_loss_over_truth_scale"] = float(min(losses) / float((observed.double() ** 2).sum()))
     out["served_vs_serial"] = out["served"]["walkers_per_s"] / out["serial"]["walkers_per_s"]
+    out["beam"] = "4 x 3 px at 30 deg (model and observed cubes convolved; *_beam legs)"
     return out
 
 

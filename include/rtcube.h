@@ -106,6 +106,13 @@ typedef struct {
     double v_sys_kms;
 } rt_spectral;
 
+/* Restoring beam of an image (see rt_beam_convolve): FWHM bmaj_px >= bmin_px
+ * in pixels, major axis at bpa_deg from +y towards -x. */
+#define RT_BEAM_MAX_RADIUS 24    /* R <= 24 pixels: bmaj_px <= 18.8 */
+typedef struct {
+    double bmaj_px, bmin_px, bpa_deg;
+} rt_beam;
+
 /* Neural CO layer (optional): 16 Fourier frequencies 2^(3k/15) on the two
  * normalised grid coordinates, 4 SiLU hidden layers of width 128, 3 outputs
  * giving z_up = zr_max r sigma(o0), z_lo = zr_max r sigma(o1) and
@@ -293,6 +300,9 @@ typedef struct {
     float *cube;                 /* device, [nch][ny][nx] */
     const float *target;         /* device, RT_REQ_FWD_ADJ and RT_REQ_FWD_LOSS */
     rt_grads grads;              /* device, RT_REQ_FWD_ADJ only */
+    rt_beam beam;                /* RT_REQ_FWD_LOSS only: bmaj_px > 0 convolves the rendered cube with
+                                    this beam before the loss (cube then holds the convolved cube);
+                                    all zero = no beam */
 } rt_request;
 
 typedef struct {
@@ -376,11 +386,6 @@ rt_status rt_render_cube_3d(const rt_problem3d *p, float *cube, void *stream);
  * adjoint (point-symmetric kernel, zero padding): dL/din = rt_beam_convolve
  * of dL/dout.
  */
-#define RT_BEAM_MAX_RADIUS 24    /* R <= 24 pixels: bmaj_px <= 18.8 */
-typedef struct {
-    double bmaj_px, bmin_px, bpa_deg;
-} rt_beam;
-
 /* out = beam * in for a cube [nch][ny][nx] (device float32, nch <= 65535);
  * in and out must not overlap.  The weights live in a library-owned
  * per-stream scratch buffer.  RT_EINVAL on invalid sizes, beams or overlap,

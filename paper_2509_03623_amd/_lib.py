@@ -72,9 +72,16 @@ class rt_server_cfg(C.Structure):
                 ("device", C.c_int32), ("streams", C.c_int32)]
 
 
+class rt_beam(C.Structure):
+    _fields_ = [("bmaj_px", C.c_double), ("bmin_px", C.c_double), ("bpa_deg", C.c_double)]
+
+
+RT_BEAM_MAX_RADIUS = 24
+
+
 class rt_request(C.Structure):
     _fields_ = [("problem", rt_problem), ("kind", C.c_int32), ("cube", _dev), ("target", _dev),
-                ("grads", rt_grads)]
+                ("grads", rt_grads), ("beam", rt_beam)]
 
 
 class rt_ticket_info(C.Structure):
@@ -109,13 +116,6 @@ RT_NT_PARAMS = 13633
 class rt_grid3d(C.Structure):
     _fields_ = [("nr", C.c_int32), ("nt", C.c_int32), ("np", C.c_int32), ("r_min_au", C.c_double),
                 ("r_max_au", C.c_double), ("th_min", C.c_double), ("th_max", C.c_double)]
-
-
-class rt_beam(C.Structure):
-    _fields_ = [("bmaj_px", C.c_double), ("bmin_px", C.c_double), ("bpa_deg", C.c_double)]
-
-
-RT_BEAM_MAX_RADIUS = 24
 
 
 class rt_problem3d(C.Structure):

@@ -122,19 +122,42 @@ __global__ __launch_bounds__(256) void beam_conv(const float *__restrict__ in, f
 
 using namespace rt;
 
+namespace rt {
+
+rt_status validate_beam(const rt_beam &b) {
+    if (!(std::isfinite(b.bmaj_px) && std::isfinite(b.bmin_px) && std::isfinite(b.bpa_deg) && b.bmin_px > 0.0 &&
+          b.bmaj_px >= b.bmin_px))
+        return fail(RT_EINVAL, "need 0 < bmin_px <= bmaj_px and a finite bpa_deg");
+    const int R = (int)std::ceil(3.0 * b.bmaj_px / (2.0 * std::sqrt(2.0 * std::log(2.0))));
+    if (R > RT_BEAM_MAX_RADIUS) return fail(RT_EINVAL, "beam support radius %d exceeds %d pixels", R, RT_BEAM_MAX_RADIUS);
+    return RT_OK;
+}
+
+rt_status beam_in_place(float *cube, int nch, int ny, int nx, const rt_beam &b, hipStream_t st) {
+    const size_t bytes = (size_t)nch * nx * ny * sizeof(float);
+    hipError_t e;
+    float *tmp = (float *)stream_workspace(st, kWsBeamCube, bytes, &e);
+    if (!tmp) return fail_hip(e, "beam cube workspace");
+    rt_status rs = rt_beam_convolve(cube, tmp, nch, ny, nx, &b, st);
+    if (rs != RT_OK) return rs;
+    e = hipMemcpyAsync(cube, tmp, bytes, hipMemcpyDeviceToDevice, st);
+    return e == hipSuccess ? RT_OK : fail_hip(e, "beam copy");
+}
+
+} // namespace rt
+
 extern "C" rt_status rt_beam_convolve(const float *in, float *out, int32_t nch, int32_t ny, int32_t nx,
                                       const rt_beam *beam, void *stream) {
     if (!in || !out) return fail(RT_EINVAL, "in and out are required");
     if (!beam) return fail(RT_EINVAL, "beam is NULL");
     if (nch < 1 || ny < 1 || nx < 1) return fail(RT_EINVAL, "need nch, ny, nx >= 1");
     if (nch > 65535 || (int64_t)nx * ny > (int64_t)1 << 30) return fail(RT_EINVAL, "cube too large");
+    rt_status vs = validate_beam(*beam);
+    if (vs != RT_OK) return vs;
     const double bmaj = beam->bmaj_px, bmin = beam->bmin_px, bpa = beam->bpa_deg;
-    if (!(std::isfinite(bmaj) && std::isfinite(bmin) && std::isfinite(bpa) && bmin > 0.0 && bmaj >= bmin))
-        return fail(RT_EINVAL, "need 0 < bmin_px <= bmaj_px and a finite bpa_deg");
     const double fw = 2.0 * std::sqrt(2.0 * std::log(2.0));
     const double smaj = bmaj / fw, smin = bmin / fw;
     const int R = (int)std::ceil(3.0 * smaj);
-    if (R > RT_BEAM_MAX_RADIUS) return fail(RT_EINVAL, "beam support radius %d exceeds %d pixels", R, RT_BEAM_MAX_RADIUS);
     const size_t bytes = (size_t)nch * nx * ny * sizeof(float);
     const char *a = (const char *)in, *b = (const char *)out;
     if (a < b + bytes && b < a + bytes) return fail(RT_EINVAL, "in and out overlap");

@@ -35,7 +35,7 @@ bool grad_accum_double();
 // share a stream must be issued from one host thread at a time.
 void *stream_workspace(hipStream_t st, int slot, size_t bytes, hipError_t *err);
 void release_stream_workspaces(hipStream_t st);
-constexpr int kWsAdjoint = 0, kWsGradAcc = 1, kWsChain = 2, kWsNeuralT = 3, kWsBeam = 4;
+constexpr int kWsAdjoint = 0, kWsGradAcc = 1, kWsChain = 2, kWsNeuralT = 3, kWsBeam = 4, kWsBeamCube = 5;
 // default largest adjoint scratch (tape, checkpoints, cotangents) of one pass
 // over a band of image rows; larger images are processed band by band
 constexpr size_t kAdjointScratchCap = (size_t)8 << 30;
@@ -44,6 +44,10 @@ size_t adjoint_scratch_cap();
 size_t adjoint_bytes_per_pixel(int nch, long npix, int nsamp, bool cube);
 
 rt_status render_cube_mlp(const rt_problem *p, float *cube, hipStream_t st);
+// beam checks shared by rt_beam_convolve and the server's submit
+rt_status validate_beam(const rt_beam &b);
+// cube <- beam * cube through the stream's scratch (slot kWsBeamCube)
+rt_status beam_in_place(float *cube, int nch, int ny, int nx, const rt_beam &b, hipStream_t st);
 rt_status march_cube(const rt_problem *p, const Geometry &g, const Shade &s, float *cube, hipStream_t st);
 // dl = dL/dcube; or dl == NULL and target != NULL: the cotangent of the L2
 // loss sum (cube - target)^2, formed inside the reverse march from its own

@@ -98,6 +98,7 @@ uint64_t footprint(const rt_request &r) {
     uint64_t b = 4 * (3 * nn + 2 * nr) + cube;
     if (p.mlp) b += 4ull * RT_MLP_PARAMS + 16 * M + (1u << 20);
     if (r.kind == RT_REQ_FWD_LOSS) b += cube;   // target
+    if (r.kind == RT_REQ_FWD_LOSS && r.beam.bmaj_px > 0.0) b += cube;   // convolved cube
     if (r.kind == RT_REQ_FWD_ADJ) {
         const int ch = std::min(p.spec.nch, kLaunchChannels);
         b += cube + 4 * (3 * nn + 2 * nr) + 8 * (3 * nn + 2 * nr);   // target, grads, accumulators
@@ -171,6 +172,12 @@ rt_status launch_batch(rt_server *sv, Lane &L, std::vector<Req *> &batch) {
     if ((e = hipGetLastError()) != hipSuccess) return fail_hip(e, "server counter");
     e = launch_serve_fwd(L.d_desc, (int)batch.size(), items, L.d_counter, sv->ncu * kServeWorkgroupsPerCU, L.st);
     if (e != hipSuccess) return fail_hip(e, "server batch launch");
+    for (Req *r : batch) {
+        const rt_request &q = r->rq;
+        if (q.kind != RT_REQ_FWD_LOSS || !(q.beam.bmaj_px > 0.0)) continue;
+        rs = beam_in_place(q.cube, q.problem.spec.nch, q.problem.cam.ny, q.problem.cam.nx, q.beam, L.st);
+        if (rs != RT_OK) return rs;
+    }
     if (with_loss) {
         e = launch_l2_batch(L.d_desc, (int)batch.size(), L.d_loss, max_n, L.st);
         if (e == hipSuccess)
@@ -206,6 +213,10 @@ rt_status launch_single(Lane &L, Req *r) {
         if (rs == RT_OK) rs = march_cube(p, g, s, q.cube, L.st);
     }
     if (rs != RT_OK || q.kind != RT_REQ_FWD_LOSS) return rs;
+    if (q.beam.bmaj_px > 0.0) {
+        rs = beam_in_place(q.cube, p->spec.nch, p->cam.ny, p->cam.nx, q.beam, L.st);
+        if (rs != RT_OK) return rs;
+    }
     const size_t n = (size_t)p->spec.nch * p->cam.nx * p->cam.ny;
     hipError_t e = launch_l2_value(q.cube, q.target, n, L.d_loss, L.st);
     if (e == hipSuccess) e = hipMemcpyAsync(L.h_loss, L.d_loss, sizeof(double), hipMemcpyDeviceToHost, L.st);
@@ -337,6 +348,12 @@ rt_status rt_submit(rt_server *sv, const rt_request *rq, uint64_t *ticket) {
         return fail(RT_EINVAL, "unknown request kind");
     if (!rq->cube) return fail(RT_EINVAL, "cube is NULL");
     if (rq->kind == RT_REQ_FWD_LOSS && !rq->target) return fail(RT_EINVAL, "target is NULL");
+    const rt_beam &bm = rq->beam;
+    if (bm.bmaj_px != 0.0 || bm.bmin_px != 0.0 || bm.bpa_deg != 0.0) {
+        if (rq->kind != RT_REQ_FWD_LOSS) return fail(RT_EINVAL, "a beam applies to RT_REQ_FWD_LOSS requests only");
+        rt_status bs = validate_beam(bm);
+        if (bs != RT_OK) return bs;
+    }
     if (rq->kind == RT_REQ_FWD_ADJ) {
         if (!rq->target) return fail(RT_EINVAL, "target is NULL");
         if (rq->problem.spec.nch > kLaunchChannels)

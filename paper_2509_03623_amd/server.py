@@ -25,10 +25,12 @@ class Server:
         self._keep = {}
 
     def submit(self, sc: Scene, cube: torch.Tensor, target: Optional[torch.Tensor] = None,
-               grads: Optional[dict] = None, loss_only: bool = False) -> int:
+               grads: Optional[dict] = None, loss_only: bool = False, beam=None) -> int:
         """Queue a render into cube [nch, ny, nx]; with target, also the
         gradients of L = sum (cube - target)^2 into the tensors of grads, or
-        with loss_only just L (reported by poll / wait)."""
+        with loss_only just L (reported by poll / wait).  beam = (bmaj_px,
+        bmin_px, bpa_deg) convolves a loss_only request's cube with that beam
+        before the loss."""
         p, keep = problem_struct(sc)
         rq = L.rt_request()
         rq.problem = p
@@ -41,6 +43,8 @@ class Server:
         g = grads or {}
         rq.grads = L.rt_grads(_fptr(g.get("ln_nh2")), _fptr(g.get("temp_k")), _fptr(g.get("vphi_kms")),
                               _fptr(g.get("z_lo_au")), _fptr(g.get("z_up_au")), _fptr(g.get("mlp_w")))
+        if beam is not None:
+            rq.beam = L.rt_beam(*(float(v) for v in beam))
         t = C.c_uint64()
         L.check(L.lib().rt_submit(self._h, C.byref(rq), C.byref(t)))
         self._keep[t.value] = (sc, cube, target, g, keep)

@@ -138,7 +138,7 @@ def test_deterministic():
     assert np.array_equal(gpu_cube3(prob), gpu_cube3(prob))
 
 
-@pytest.mark.parametrize("nch", [20, 64])
+@pytest.mark.parametrize("nch", [20, 64, 128])
 def test_full_size_sampled_pixels(nch):
     """The benchmark workload (512 x 96 x 256 grid, 256^2 pixels, 512 samples
     per ray) in the launch configuration the bench times: 300 sampled pixels
@@ -157,3 +157,11 @@ def test_full_size_sampled_pixels(nch):
     err = float(np.abs(got - ref).max() / np.abs(ref).max())
     print("sampled max|dI|/peak =", err)
     assert ref.max() > 0 and err <= TOL
+
+
+def test_more_channels_than_one_launch():
+    """300 channels: two launches of at most 256 channels each."""
+    prob = S3.make_problem3(S3.Grid3Spec(20, 10, 12), seed=67, nx=13, ny=9, nch=300, dv=0.02, nsamp=64)
+    ref = oracle.render3(prob)
+    got = gpu_cube3(prob)
+    assert ref.max() > 0 and rel_err(got, ref) <= TOL

@@ -249,3 +249,36 @@ def test_loss_requests_match_direct_render_and_loss():
         assert float((o - direct[i]).abs().max()) <= 1e-6 * float(direct[i].abs().max()), i
         assert info["loss"] == pytest.approx(ref_loss[i], rel=1e-6), i
     assert infos[0]["loss"] == pytest.approx(alone["loss"], rel=1e-12)
+
+
+def test_loss_requests_with_beam():
+    """RT_REQ_FWD_LOSS with a beam: the cube is the rendered cube convolved with
+    the beam and L compares that with the target, in a batch mixing beam and
+    no-beam walkers and for a request large enough to run on its own stream;
+    against rt_render_cube + rt_beam_convolve + an FP64 host sum."""
+    rt = _rt()
+    print("[gpu] server loss-only requests with a beam", flush=True)
+    beam = (5.0, 3.0, 40.0)
+    walkers = [scene(40 + 8 * (i % 3), 12 + 4 * (i % 4), 64, seed=2060 + i) for i in range(8)]
+    walkers.append(scene(256, 48, 256, seed=2070))          # large: its own stream
+    with_beam = [i % 2 == 0 or i == 8 for i in range(len(walkers))]
+    rendered = [rt.render(sc) for _, sc in walkers]
+    direct = [rt.beam_convolve(c, *beam) if b else c for c, b in zip(rendered, with_beam)]
+    targets = [rt.render(sc) * 1.02 + 0.01 for _, sc in walkers]
+    torch.cuda.synchronize()
+    ref_loss = [float(((d.double() - t.double()) ** 2).sum()) for d, t in zip(direct, targets)]
+    with rt.Server(max_slots=32, streams=3) as sv:
+        outs = [empty_cube(sc) for _, sc in walkers]
+        ts = [sv.submit(sc, o, target=t, loss_only=True, beam=beam if b else None)
+              for (_, sc), o, t, b in zip(walkers, outs, targets, with_beam)]
+        infos = [sv.wait(t) for t in ts]
+        with pytest.raises(rt.RtError):
+            sv.submit(walkers[0][1], empty_cube(walkers[0][1]), beam=beam)       # forward-only: no beam
+        with pytest.raises(rt.RtError):
+            sv.submit(walkers[0][1], empty_cube(walkers[0][1]), target=targets[0], loss_only=True,
+                      beam=(3.0, 5.0, 0.0))                                      # bmin > bmaj
+    torch.cuda.synchronize()
+    for i, (info, o) in enumerate(zip(infos, outs)):
+        assert info["state"] == "done", i
+        assert float((o - direct[i]).abs().max()) <= 1e-6 * float(direct[i].abs().max()), i
+        assert info["loss"] == pytest.approx(ref_loss[i], rel=1e-6), i
