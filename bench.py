@@ -148,7 +148,7 @@ def main():
     ap.add_argument("--no-mlp", action="store_true", help="skip the neural CO layer leg")
     ap.add_argument("--no-3d", action="store_true", help="skip the 3-D spherical-grid leg")
     ap.add_argument("--no-beam", action="store_true", help="skip the beam-convolution leg")
-    ap.add_argument("--only", choices=("render3d",), default=None,
+    ap.add_argument("--only", choices=("render3d", "beam"), default=None,
                     help="run one leg alone and print its JSON (for profiling)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first copy 1 GiB device to device three times (a kernel of known traffic, to scale "
@@ -179,6 +179,12 @@ def main():
         del src, dst
     if args.only == "render3d":
         print(json.dumps({"render3d": bench_render3d(rt, dev, args)}), flush=True)
+        return
+    if args.only == "beam":
+        prob = synth.config2(args.seed)
+        sc = rt.scene_from_problem(prob, device=dev)
+        cube = rt.render(sc)
+        print(json.dumps({"beam": bench_beam(rt, cube, args)}), flush=True)
         return
     prob = synth.config2(args.seed)
     sc = rt.scene_from_problem(prob, device=dev)
