@@ -109,8 +109,10 @@ def auto_shape3(nch: int, npix: int, nsamp: int):
     return cb, ns
 
 
-def cpu_baseline(prob, seconds=12.0):
-    """FP64 oracle on seeded pixels of the same workload, all host cores."""
+def cpu_baseline(prob, live, seconds=12.0):
+    """FP64 oracle on seeded pixels of the same workload, all host cores;
+    live: [ny, nx] mask of the rays that cross the grid (the others have no
+    samples and are not counted)."""
     import numpy as np
     import oracle
     ncores = os.cpu_count() or 1
@@ -119,7 +121,7 @@ def cpu_baseline(prob, seconds=12.0):
     per_pix = prob.nch * prob.nsamp
     n = 256
     t_used = 0.0
-    done = 0
+    done = done_live = 0
     while t_used < seconds:
         px = rng.integers(0, nx, n)
         py = rng.integers(0, ny, n)
@@ -128,12 +130,14 @@ def cpu_baseline(prob, seconds=12.0):
         dt = time.perf_counter() - t0
         t_used += dt
         done += n
+        done_live += int(live[py, px].sum())
         n = int(min(max(n * 2, 64), max(64, n * (seconds - t_used) / max(dt, 1e-3))))
         if n < 64:
             break
-    return dict(value=done * per_pix / t_used, unit="ray-samples/s", cores=ncores, kind="oracle",
-                sample=f"{done} seeded random pixels of the 512x512x64ch x512-sample disk "
-                       f"({done * per_pix:.3g} ray-samples, {t_used:.1f} s, FP64 scalar C, OpenMP)")
+    return dict(value=done_live * per_pix / t_used, unit="ray-samples/s", cores=ncores, kind="oracle",
+                sample=f"{done} seeded random pixels ({done_live} crossing the grid) of the 512x512x64ch "
+                       f"x512-sample disk ({done_live * per_pix:.3g} ray-samples, {t_used:.1f} s, FP64 scalar C, "
+                       f"OpenMP)")
 
 
 def main():
@@ -225,7 +229,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "forward render 512x512 px x 64 ch x 512 samples/ray, 256x128 (r,z/r) grid, "
                                f"seeded disk {args.seed} (3 gaps, incl {prob.camera.incl_deg:.1f} deg)",
-                   "global_batch": 1, "ray_samples": rs, "parallelism": "single GPU"},
+                   "global_batch": 1, "ray_samples": rs, "live_fraction": float(sc.live_mask().mean()),
+                   "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": measured_traffic(args.seed),
                      "kernel": "march_fwd", "kernel_ms": kern_ms,
@@ -263,7 +268,7 @@ def main():
                                               out["saturated"]["serial_ray_samples_per_s"])
     if not args.no_cpu:
         log("oracle on the host cores")
-        out["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(prob, sc.live_mask(), args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 
@@ -329,12 +334,14 @@ def bench_render3d(rt, dev, args):
         rng = np.random.Generator(np.random.PCG64(98))
         n = 2000
         px, py = rng.integers(0, 256, n).astype(np.int32), rng.integers(0, 256, n).astype(np.int32)
+        nlive = int(sc0.live_mask()[py, px].sum())
         ncores = os.cpu_count() or 1
         t0 = time.perf_counter()
         oracle.render3_pixels(base, px, py, nthreads=ncores)
         dt = time.perf_counter() - t0
-        out["cpu_oracle"] = {"ray_samples_per_s": n * 20 * 512 / dt, "cores": ncores,
-                             "sample": f"{n} seeded random pixels of 256x256x20ch, FP64 scalar C, OpenMP"}
+        out["cpu_oracle"] = {"ray_samples_per_s": nlive * 20 * 512 / dt, "cores": ncores,
+                             "sample": f"{n} seeded random pixels ({nlive} crossing the grid) of 256x256x20ch, "
+                                       "FP64 scalar C, OpenMP"}
     return out
 
 
@@ -482,7 +489,7 @@ def bench_fit(rt, synth, dev, args):
         chi2.append(c2)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / steps
-    rs = sc.nx * sc.ny * batch * sc.nsamp
+    rs = int(sc.live_mask().sum()) * batch * sc.nsamp
     return {"workload": "256x256 px, 115 ch (0.04 km/s), 256 samples, batch 50, 256x128 grid",
             "ms_per_step": dt * 1e3, "ray_samples_per_s": rs / dt, "steps": steps,
             "chi2_first": float(chi2[0].item()), "chi2_last": float(chi2[-1].item())}

@@ -310,7 +310,8 @@ typedef struct {
     int32_t status;              /* rt_status of the request */
     uint64_t t_submit_ns, t_admit_ns, t_done_ns;   /* steady-clock stamps */
     double loss;                 /* RT_REQ_FWD_ADJ / RT_REQ_FWD_LOSS: L once done */
-    uint64_t ray_samples;
+    uint64_t ray_samples;        /* nx ny nch nsamp of the request (nominal: rays that miss the grid
+                                    have no samples and do no work) */
 } rt_ticket_info;
 
 rt_status rt_server_create(const rt_server_cfg *cfg, rt_server **out);

@@ -8,6 +8,7 @@ torch.autograd.Function whose backward is the library's adjoint.
 from __future__ import annotations
 
 import ctypes as C
+import math
 from dataclasses import dataclass, field, replace
 from typing import Optional
 
@@ -55,17 +56,57 @@ class Scene:
     mlp_precision: int = L.RT_MLP_BF16
     keep: list = field(default_factory=list, repr=False)
     _struct: tuple = field(default=None, repr=False, compare=False)
+    _live: int = field(default=None, repr=False, compare=False)
 
     @property
     def nch(self) -> int:
         return int(len(self.v_kms))
 
+    def live_mask(self) -> np.ndarray:
+        """[ny, nx] bool: pixels whose ray crosses the grid's bounding cylinder
+        (r <= r_max e^dln, |z| <= (zr_max + d(z/r)) r_max e^dln), the same test
+        as the march's ray set-up.  The other rays have no samples (their
+        intensity is exactly zero) and no work is done for them."""
+        dln = math.log(self.r_max_au / self.r_min_au) / (self.nr - 1)
+        rc = self.r_max_au * math.exp(dln)
+        zc = (self.zr_max + self.zr_max / (self.nz - 1)) * rc
+        ang, pa = math.radians(self.incl_deg), math.radians(self.pa_deg)
+        si, ci = math.sin(ang), math.cos(ang)
+        if self.incl_deg == 0.0:
+            si, ci = 0.0, 1.0
+        if self.incl_deg == 90.0:
+            si, ci = 1.0, 0.0
+        d = self.fov_au / self.nx
+        X = (np.arange(self.nx) + 0.5 - 0.5 * self.nx) * d
+        Y = (np.arange(self.ny) + 0.5 - 0.5 * self.ny) * d
+        X, Y = np.meshgrid(X, Y)
+        xp = math.cos(pa) * X - math.sin(pa) * Y
+        yp = math.sin(pa) * X + math.cos(pa) * Y
+        ok = xp * xp < rc * rc
+        qq = np.sqrt(np.maximum(rc * rc - xp * xp, 0.0))
+        lo = np.full(xp.shape, -1e300)
+        hi = np.full(xp.shape, 1e300)
+        if si > 0.0:
+            lo = np.maximum(lo, (-yp * ci - qq) / si)
+            hi = np.minimum(hi, (-yp * ci + qq) / si)
+        else:
+            ok &= np.abs(yp * ci) <= qq
+        if ci > 0.0:
+            lo = np.maximum(lo, (yp * si - zc) / ci)
+            hi = np.minimum(hi, (yp * si + zc) / ci)
+        else:
+            ok &= np.abs(yp * si) <= zc
+        return ok & (hi > lo)
+
     @property
     def ray_samples(self) -> int:
-        return self.nx * self.ny * self.nch * self.nsamp
+        """(pixel, channel, sample) triples of the rays that cross the grid."""
+        if self._live is None:
+            self._live = int(self.live_mask().sum())
+        return self._live * self.nch * self.nsamp
 
     def replace(self, **kw) -> "Scene":
-        return replace(self, _struct=None, **kw)
+        return replace(self, _struct=None, _live=None, **kw)
 
 
 def scene_from_problem(prob, device="cuda", mlp_precision=L.RT_MLP_BF16) -> Scene:
@@ -367,9 +408,19 @@ class Scene3d:
     def nch(self) -> int:
         return int(len(self.v_kms))
 
+    def live_mask(self) -> np.ndarray:
+        """[ny, nx] bool: pixels whose ray crosses the bounding sphere r <= r_max e^dln."""
+        nr, r_min, r_max = int(self.grid[0]), float(self.grid[3]), float(self.grid[4])
+        rc = r_max * math.exp(math.log(r_max / r_min) / (nr - 1))
+        d = self.fov_au / self.nx
+        X = (np.arange(self.nx) + 0.5 - 0.5 * self.nx) * d
+        Y = (np.arange(self.ny) + 0.5 - 0.5 * self.ny) * d
+        return X[None, :] ** 2 + Y[:, None] ** 2 < rc * rc
+
     @property
     def ray_samples(self) -> int:
-        return self.nx * self.ny * self.nch * self.nsamp
+        """(pixel, channel, sample) triples of the rays that cross the grid."""
+        return int(self.live_mask().sum()) * self.nch * self.nsamp
 
     def replace(self, **kw) -> "Scene3d":
         return replace(self, **kw)
