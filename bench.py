@@ -12,6 +12,7 @@ bounded sample of the same workload.
 from __future__ import annotations
 
 import argparse
+import gc
 import json
 import os
 import sys
@@ -103,8 +104,8 @@ def auto_shape3(nch: int, npix: int, nsamp: int):
     """The library's automatic (channel block, ray split) of the 3-D march."""
     cb = next((c for c in (8, 16, 24, 32, 48, 64) if c >= nch), 64)
     waves = lambda ns: ((npix * ns + 63) // 64) * ((nch + cb - 1) // cb)
-    ns = 1
-    while ns < 8 and waves(2 * ns) < 4096 and nsamp >= 64 * ns:
+    ns = 2 if nsamp >= 128 else 1
+    while ns < 8 and waves(2 * ns) <= 1024 and nsamp >= 128 * ns:
         ns *= 2
     return cb, ns
 
@@ -310,6 +311,10 @@ def bench_render3d(rt, dev, args):
         for _ in range(2):
             rt.render3d(sc, out=cube)
         torch.cuda.synchronize()
+        # no collector pause inside the short timed loop (one such pause, 1.2 ms
+        # on the host, left the GPU idle and added 0.24 ms to a 5-call average)
+        gc.collect()
+        gc.disable()
         t0 = time.perf_counter()
         e0.record()
         for _ in range(steps):
@@ -317,6 +322,7 @@ def bench_render3d(rt, dev, args):
         e1.record()
         torch.cuda.synchronize()
         wall = (time.perf_counter() - t0) / steps
+        gc.enable()
         kern = e0.elapsed_time(e1) / steps * 1e-3
         d = sc.fov_au / npx
         xy = (np.arange(npx) + 0.5 - npx / 2) * d
@@ -356,11 +362,14 @@ def bench_beam(rt, cube, args, beam=(6.0, 4.0, 30.0)):
         rt.beam_convolve(cube, *beam, out=out)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    gc.collect()
+    gc.disable()
     e0.record()
     for _ in range(steps):
         rt.beam_convolve(cube, *beam, out=out)
     e1.record()
     torch.cuda.synchronize()
+    gc.enable()
     ms = e0.elapsed_time(e1) / steps
     R = math.ceil(3.0 * beam[0] / (2.0 * math.sqrt(2.0 * math.log(2.0))))
     fma = (2 * R + 1) ** 2 * cube.numel()

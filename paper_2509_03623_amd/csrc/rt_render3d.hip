@@ -319,19 +319,21 @@ static rt_status radius_table(const rt_grid3d &g, const float **out) {
 // Launch shape of the 3-D march.  Its shading (two atan2, sixteen scattered
 // loads, the physics) costs ~25 channels' worth of issue slots per sample, so
 // a pixel's channels stay in one block (the smallest of 8..64 holding them,
-// never split into two 32-channel blocks as the axisymmetric march does);
-// rays are then split while the launch stays under 4096 waves.  Measured at
-// 256^2 pixels on the 512 x 96 x 256 grid: 20 ch (24, 2) 0.75 ms against
-// (24, 4) 0.85; 64 ch (64, 2) 1.00 against (32, 2) 1.52; 128 ch (64, 1) 2.04
-// against (32, 1) 2.96.
+// never split into two 32-channel blocks as the axisymmetric march does).
+// Two lanes per ray (two half-chords in flight per pixel) were best at every
+// image size measured; rays split further only while the launch stays at or
+// under 1024 waves.  Measured on the 512 x 96 x 256 grid (ms): 256^2 x 20 ch
+// (24, 2) 0.75 against (24, 4) 0.85; 256^2 x 64 (64, 2) 1.00 against (32, 2)
+// 1.52; 256^2 x 128 (64, 2) 1.89 against (32, 1) 2.96; 512^2 x 20 (24, 2)
+// 2.17 against (24, 1) 2.38; 128^2 x 20 (24, 4) 0.33 against (24, 8) 0.37.
 static void forward_shape3(int nch, long npix, int nsamp, int *cb_out, int *split_out) {
     static const int cands[] = {8, 16, 24, 32, 48, 64};
     int cb = 64;
     for (int c : cands)
         if (c >= nch) { cb = c; break; }
     auto waves = [&](int ns) { return ((npix * ns + 63) / 64) * (long)((nch + cb - 1) / cb); };
-    int ns = 1;
-    while (ns < 8 && waves(2 * ns) < 4096 && nsamp >= 64 * ns) ns <<= 1;
+    int ns = nsamp >= 128 ? 2 : 1;
+    while (ns < 8 && waves(2 * ns) <= 1024 && nsamp >= 128 * ns) ns <<= 1;
     *cb_out = cb;
     *split_out = ns;
 }
