@@ -200,6 +200,8 @@ def main():
     stream = torch.cuda.current_stream()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
+    gc.collect()
+    gc.disable()
     t0 = time.perf_counter()
     e0.record(stream)
     for _ in range(args.steps):
@@ -207,6 +209,7 @@ def main():
     e1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    gc.enable()
     kern_ms = e0.elapsed_time(e1) / args.steps
     ms_per_step = wall * 1e3 / args.steps
     rs = sc.ray_samples
