@@ -7,8 +7,11 @@
 // layers of 64 units, one output.  The grid has 3.3e4 nodes at 256 x 128 and
 // the network 1.4e4 weights (4.4e8 multiply-adds per evaluation), so this is
 // plain FP32 VALU work: a workgroup of 128 nodes keeps each node's
-// activations in its own LDS column and accumulates 16 outputs at a time in
-// registers against weights staged in LDS (read as broadcasts).  The weight
+// activations in its own LDS column, and four lanes per node each accumulate
+// a 16-output slice of every layer in registers against weights staged in
+// LDS (read as broadcasts: the lanes of a wave share their slice).  Four
+// lanes per node give 8 waves per CU where one lane per node gave 2, with
+// the same LDS (weights + two activation buffers).  The weight
 // gradient sums outer products over the nodes: per layer and chunk of 128
 // nodes in LDS into partial sums, then reduced in a fixed order
 // (deterministic).
@@ -23,7 +26,9 @@ namespace rt {
 
 namespace {
 
-constexpr int kNtL = 4, kNtIn = 4 * kNtL, kNtW = 64, kNtThreads = 128;
+constexpr int kNtL = 4, kNtIn = 4 * kNtL, kNtW = 64;
+// nodes per workgroup, lanes per node, outputs per lane
+constexpr int kNtNodes = 128, kNtQ = 4, kNtBlock = kNtNodes * kNtQ, kNtSlice = kNtW / kNtQ;
 // flat layout: per layer W [out][in] then b [out]
 constexpr int layer_in(int l) { return l == 0 ? kNtIn : kNtW; }
 constexpr int layer_out(int l) { return l == 4 ? 1 : kNtW; }
@@ -53,9 +58,9 @@ __device__ __forceinline__ void node_features(int n, int nr, int nz, float *f) {
 }
 
 // LDS: per layer l the transposed weights WT_l [in][out] then b_l (forward),
-// or W_l [out][in] (backward); then two activation buffers [64][kNtThreads].
+// or W_l [out][in] (backward); then two activation buffers [64][kNtNodes].
 __device__ __forceinline__ void stage_weights(const float *W, float *sw, bool transposed) {
-    for (int p = threadIdx.x; p < RT_NT_PARAMS; p += kNtThreads) {
+    for (int p = threadIdx.x; p < RT_NT_PARAMS; p += blockDim.x) {
         int l = 0;
         while (l < 4 && p >= layer_off(l + 1)) ++l;
         const int q = p - layer_off(l), in = layer_in(l), out = layer_out(l);
@@ -68,108 +73,124 @@ __device__ __forceinline__ void stage_weights(const float *W, float *sw, bool tr
     }
 }
 
-// one dense layer for this lane's node: out[a] = act(sum_b W[a][b] in[b] + b[a]),
-// with in / out columns of the LDS buffers and WT [in][out] in LDS
-template <int IN, int OUT, bool RELU>
-__device__ __forceinline__ void dense(const float *wt, const float *bias, const float *hin, float *hout, int t) {
-    constexpr int C = OUT < 16 ? OUT : 16;
+// one dense layer, this lane's slice of outputs a = 16 q + c of node column
+// j: out[a] = act(sum_b W[a][b] in[b] + b[a]), with WT [in][out] in LDS; the
+// slice is also left in acc
+template <int IN, bool RELU>
+__device__ __forceinline__ void dense_slice(const float *wt, const float *bias, const float *hin, float *hout, int j,
+                                            int q, float *acc) {
 #pragma unroll
-    for (int a0 = 0; a0 < OUT; a0 += C) {
-        float acc[C];
-#pragma unroll
-        for (int c = 0; c < C; ++c) acc[c] = bias[a0 + c];
+    for (int c = 0; c < kNtSlice; ++c) acc[c] = bias[q * kNtSlice + c];
 #pragma unroll 4
-        for (int b = 0; b < IN; ++b) {
-            const float h = hin[b * kNtThreads + t];
+    for (int b = 0; b < IN; ++b) {
+        const float h = hin[b * kNtNodes + j];
 #pragma unroll
-            for (int c = 0; c < C; ++c) acc[c] = fmaf(wt[b * OUT + a0 + c], h, acc[c]);
-        }
+        for (int c = 0; c < kNtSlice; ++c) acc[c] = fmaf(wt[b * kNtW + q * kNtSlice + c], h, acc[c]);
+    }
 #pragma unroll
-        for (int c = 0; c < C; ++c) hout[(a0 + c) * kNtThreads + t] = RELU ? fmaxf(acc[c], 0.0f) : acc[c];
+    for (int c = 0; c < kNtSlice; ++c) {
+        if (RELU) acc[c] = fmaxf(acc[c], 0.0f);
+        hout[(q * kNtSlice + c) * kNtNodes + j] = acc[c];
     }
 }
 
-__global__ __launch_bounds__(kNtThreads) void nt_fwd(int nr, int nz, const float *__restrict__ W,
-                                                     float *__restrict__ T, float *__restrict__ act) {
+// lane t: node column j = t mod 128, slice q = t / 128 (one slice per wave)
+__global__ __launch_bounds__(kNtBlock) void nt_fwd(int nr, int nz, const float *__restrict__ W,
+                                                   float *__restrict__ T, float *__restrict__ act) {
     extern __shared__ float sm[];
-    float *sw = sm, *h0 = sm + RT_NT_PARAMS, *h1 = h0 + kNtW * kNtThreads;
+    float *sw = sm, *h0 = sm + RT_NT_PARAMS, *h1 = h0 + kNtW * kNtNodes;
     stage_weights(W, sw, true);
-    const int N = nr * nz, t = threadIdx.x;
-    const int n = blockIdx.x * kNtThreads + t;
+    const int N = nr * nz, t = threadIdx.x, j = t % kNtNodes;
+    const int q = __builtin_amdgcn_readfirstlane(t / kNtNodes);
+    const int n = blockIdx.x * kNtNodes + j;
     const int nn = n < N ? n : N - 1;   // lanes past the end compute a copy and store nothing
-    float f[kNtIn];
-    node_features(nn, nr, nz, f);
+    const bool store = act && n < N;
+    if (q == 0) {
+        float f[kNtIn];
+        node_features(nn, nr, nz, f);
 #pragma unroll
-    for (int b = 0; b < kNtIn; ++b) h0[b * kNtThreads + t] = f[b];
-    __syncthreads();
-    dense<kNtIn, kNtW, true>(sw + layer_off(0), sw + layer_off(0) + kNtIn * kNtW, h0, h1, t);
-    dense<kNtW, kNtW, true>(sw + layer_off(1), sw + layer_off(1) + kNtW * kNtW, h1, h0, t);
-    if (act && n < N)
-        for (int a = 0; a < kNtW; ++a) act[(size_t)(kNtIn + a) * N + n] = h1[a * kNtThreads + t];
-    dense<kNtW, kNtW, true>(sw + layer_off(2), sw + layer_off(2) + kNtW * kNtW, h0, h1, t);
-    if (act && n < N)
-        for (int a = 0; a < kNtW; ++a) act[(size_t)(kNtIn + kNtW + a) * N + n] = h0[a * kNtThreads + t];
-    dense<kNtW, kNtW, true>(sw + layer_off(3), sw + layer_off(3) + kNtW * kNtW, h1, h0, t);
-    if (act && n < N) {
-        for (int a = 0; a < kNtW; ++a) {
-            act[(size_t)(kNtIn + 2 * kNtW + a) * N + n] = h1[a * kNtThreads + t];
-            act[(size_t)(kNtIn + 3 * kNtW + a) * N + n] = h0[a * kNtThreads + t];
-        }
-        for (int b = 0; b < kNtIn; ++b) act[(size_t)b * N + n] = f[b];
+        for (int b = 0; b < kNtIn; ++b) h0[b * kNtNodes + j] = f[b];
+        if (store)
+            for (int b = 0; b < kNtIn; ++b) act[(size_t)b * N + n] = f[b];
     }
-    dense<kNtW, 1, false>(sw + layer_off(4), sw + layer_off(4) + kNtW, h0, h1, t);
-    const float o = h1[t];
-    if (n < N) {
-        T[n] = 5.0f + 395.0f / (1.0f + expf(-o));
-        if (act) act[(size_t)(kActRows - 1) * N + n] = o;
+    __syncthreads();
+    float acc[kNtSlice];
+    // hidden layer l reads one buffer and writes the other; act rows 16 + 64 l + a
+    dense_slice<kNtIn, true>(sw + layer_off(0), sw + layer_off(0) + kNtIn * kNtW, h0, h1, j, q, acc);
+    if (store)
+        for (int c = 0; c < kNtSlice; ++c) act[(size_t)(kNtIn + q * kNtSlice + c) * N + n] = acc[c];
+    __syncthreads();
+    float *hin = h1, *hout = h0;
+    for (int l = 1; l < 4; ++l) {
+        dense_slice<kNtW, true>(sw + layer_off(l), sw + layer_off(l) + kNtW * kNtW, hin, hout, j, q, acc);
+        if (store)
+            for (int c = 0; c < kNtSlice; ++c)
+                act[(size_t)(kNtIn + l * kNtW + q * kNtSlice + c) * N + n] = acc[c];
+        __syncthreads();
+        float *tmp = hin;
+        hin = hout;
+        hout = tmp;
+    }
+    // output unit (one lane per node): o = b_4 + sum_b W_4[0][b] h_4[b]
+    if (q == 0) {
+        const float *w4 = sw + layer_off(4);
+        float o = w4[kNtW];
+        for (int b = 0; b < kNtW; ++b) o = fmaf(w4[b], hin[b * kNtNodes + j], o);
+        if (n < N) {
+            T[n] = 5.0f + 395.0f / (1.0f + expf(-o));
+            if (act) act[(size_t)(kActRows - 1) * N + n] = o;
+        }
     }
 }
 
-// backward through the layers for this lane's node: delta rows (dL/dz of
-// hidden layers 1..4, then dL/do) into `delta` [kDeltaRows][N]
-__global__ __launch_bounds__(kNtThreads) void nt_delta(int N, const float *__restrict__ W,
-                                                       const float *__restrict__ dT, const float *__restrict__ act,
-                                                       float *__restrict__ delta) {
+// backward through the layers for node column j, slice q: delta rows (dL/dz
+// of hidden layers 1..4, then dL/do) into `delta` [kDeltaRows][N]
+__global__ __launch_bounds__(kNtBlock) void nt_delta(int N, const float *__restrict__ W,
+                                                     const float *__restrict__ dT, const float *__restrict__ act,
+                                                     float *__restrict__ delta) {
     extern __shared__ float sm[];
-    float *sw = sm, *d0 = sm + RT_NT_PARAMS, *d1 = d0 + kNtW * kNtThreads;
+    float *sw = sm, *d0 = sm + RT_NT_PARAMS, *d1 = d0 + kNtW * kNtNodes;
     stage_weights(W, sw, false);
     __syncthreads();
-    const int t = threadIdx.x, n = blockIdx.x * kNtThreads + t;
-    const int nn = n < N ? n : N - 1;
+    const int t = threadIdx.x, j = t % kNtNodes;
+    const int q = __builtin_amdgcn_readfirstlane(t / kNtNodes);
+    const int n = blockIdx.x * kNtNodes + j, nn = n < N ? n : N - 1;
     const float o = act[(size_t)(kActRows - 1) * N + nn];
     const float s = 1.0f / (1.0f + expf(-o));
     const float dlo = (n < N ? dT[n] : 0.0f) * 395.0f * s * (1.0f - s);
-    if (n < N) delta[(size_t)(kDeltaRows - 1) * N + n] = dlo;
+    if (q == 0 && n < N) delta[(size_t)(kDeltaRows - 1) * N + n] = dlo;
     // dL/dz_4 = W_4^T dL/do masked by h_4 > 0
     const float *w4 = sw + layer_off(4);
-    for (int a = 0; a < kNtW; ++a) {
+    for (int c = 0; c < kNtSlice; ++c) {
+        const int a = q * kNtSlice + c;
         const float h = act[(size_t)(kNtIn + 3 * kNtW + a) * N + nn];
-        d0[a * kNtThreads + t] = h > 0.0f ? w4[a] * dlo : 0.0f;
+        const float v = h > 0.0f ? w4[a] * dlo : 0.0f;
+        d0[a * kNtNodes + j] = v;
+        if (n < N) delta[(size_t)(3 * kNtW + a) * N + n] = v;
     }
-    if (n < N)
-        for (int a = 0; a < kNtW; ++a) delta[(size_t)(3 * kNtW + a) * N + n] = d0[a * kNtThreads + t];
+    __syncthreads();
     // dL/dz_l = W_l^T dL/dz_{l+1} masked by h_l > 0, for l = 3, 2, 1 (W_l maps h_l to z_{l+1})
     float *cur = d0, *nxt = d1;
     for (int l = 3; l >= 1; --l) {
         const float *wl = sw + layer_off(l);   // W_l [out][in]
-        for (int b0 = 0; b0 < kNtW; b0 += 16) {
-            float acc[16];
+        float acc[kNtSlice];
 #pragma unroll
-            for (int c = 0; c < 16; ++c) acc[c] = 0.0f;
+        for (int c = 0; c < kNtSlice; ++c) acc[c] = 0.0f;
 #pragma unroll 4
-            for (int a = 0; a < kNtW; ++a) {
-                const float g = cur[a * kNtThreads + t];
+        for (int a = 0; a < kNtW; ++a) {
+            const float g = cur[a * kNtNodes + j];
 #pragma unroll
-                for (int c = 0; c < 16; ++c) acc[c] = fmaf(wl[a * kNtW + b0 + c], g, acc[c]);
-            }
-#pragma unroll
-            for (int c = 0; c < 16; ++c) {
-                const float h = act[(size_t)(kNtIn + (l - 1) * kNtW + b0 + c) * N + nn];
-                nxt[(b0 + c) * kNtThreads + t] = h > 0.0f ? acc[c] : 0.0f;
-            }
+            for (int c = 0; c < kNtSlice; ++c) acc[c] = fmaf(wl[a * kNtW + q * kNtSlice + c], g, acc[c]);
         }
-        if (n < N)
-            for (int b = 0; b < kNtW; ++b) delta[(size_t)((l - 1) * kNtW + b) * N + n] = nxt[b * kNtThreads + t];
+#pragma unroll
+        for (int c = 0; c < kNtSlice; ++c) {
+            const int b = q * kNtSlice + c;
+            const float h = act[(size_t)(kNtIn + (l - 1) * kNtW + b) * N + nn];
+            const float v = h > 0.0f ? acc[c] : 0.0f;
+            nxt[b * kNtNodes + j] = v;
+            if (n < N) delta[(size_t)((l - 1) * kNtW + b) * N + n] = v;
+        }
+        __syncthreads();
         float *tmp = cur;
         cur = nxt;
         nxt = tmp;
@@ -244,7 +265,7 @@ rt_status validate_nt_grid(const rt_grid *g) {
     return RT_OK;
 }
 
-constexpr size_t kNtLds = sizeof(float) * (RT_NT_PARAMS + 2 * kNtW * kNtThreads);
+constexpr size_t kNtLds = sizeof(float) * (RT_NT_PARAMS + 2 * kNtW * kNtNodes);
 
 hipError_t nt_lds_attr() {
     hipError_t e = hipFuncSetAttribute((const void *)nt_fwd, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kNtLds);
@@ -266,7 +287,7 @@ extern "C" rt_status rt_neural_temperature(const rt_grid *grid, const float *wei
     hipError_t e = nt_lds_attr();
     if (e != hipSuccess) return fail_hip(e, "neural temperature attributes");
     const int N = grid->nr * grid->nz;
-    hipLaunchKernelGGL(nt_fwd, dim3((N + kNtThreads - 1) / kNtThreads), dim3(kNtThreads), kNtLds, (hipStream_t)stream,
+    hipLaunchKernelGGL(nt_fwd, dim3((N + kNtNodes - 1) / kNtNodes), dim3(kNtBlock), kNtLds, (hipStream_t)stream,
                        grid->nr, grid->nz, weights, temp_k, (float *)nullptr);
     e = hipGetLastError();
     return e == hipSuccess ? RT_OK : fail_hip(e, "neural temperature");
@@ -286,9 +307,9 @@ extern "C" rt_status rt_neural_temperature_adjoint(const rt_grid *grid, const fl
     float *w = (float *)stream_workspace(s, kWsNeuralT, sizeof(float) * (act_n + del_n + part_n + N), &e);
     if (!w) return fail_hip(e, "neural temperature scratch");
     float *act = w, *del = w + act_n, *part = del + del_n, *Tn = part + part_n;
-    const int blocks = (N + kNtThreads - 1) / kNtThreads;
-    hipLaunchKernelGGL(nt_fwd, dim3(blocks), dim3(kNtThreads), kNtLds, s, grid->nr, grid->nz, weights, Tn, act);
-    hipLaunchKernelGGL(nt_delta, dim3(blocks), dim3(kNtThreads), kNtLds, s, N, weights, d_temp_k, act, del);
+    const int blocks = (N + kNtNodes - 1) / kNtNodes;
+    hipLaunchKernelGGL(nt_fwd, dim3(blocks), dim3(kNtBlock), kNtLds, s, grid->nr, grid->nz, weights, Tn, act);
+    hipLaunchKernelGGL(nt_delta, dim3(blocks), dim3(kNtBlock), kNtLds, s, N, weights, d_temp_k, act, del);
     hipLaunchKernelGGL(nt_wgrad, dim3(chunks, 5), dim3(256), 0, s, N, act, del, part);
     hipLaunchKernelGGL(nt_wreduce, dim3((RT_NT_PARAMS + 255) / 256), dim3(256), 0, s, chunks, part, d_weights);
     e = hipGetLastError();
