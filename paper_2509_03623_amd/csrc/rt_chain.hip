@@ -128,24 +128,124 @@ __device__ Crossings column_surfaces(const ChainArgs &a, const float *ln_n, cons
     return c;
 }
 
-// One 64-lane workgroup per radial node: the column's rows are staged in LDS
-// by the whole workgroup (coalesced), lane 0 runs the scans from LDS.
+// Wave-wide inclusive prefix sum of one value per lane.
+__device__ __forceinline__ float wave_incl_scan(float v) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const float u = __shfl_up(v, d, 64);
+        if (lane >= d) v += u;
+    }
+    return v;
+}
+
+// Sums over the lanes below (up) or above (down) this one, formed from the
+// shifted values so that no difference of two large partial sums is taken:
+// the downward column of the inner segments is ~1e4 times the column above
+// the photodissociation surface, and total - prefix lost it to rounding.
+__device__ __forceinline__ float wave_excl_scan_up(float v) {
+    const int lane = threadIdx.x & 63;
+    float x = __shfl_up(v, 1, 64);
+    return wave_incl_scan(lane == 0 ? 0.0f : x);
+}
+
+__device__ __forceinline__ float wave_excl_scan_down(float v) {
+    const int lane = threadIdx.x & 63;
+    float x = __shfl_down(v, 1, 64);
+    x = lane == 63 ? 0.0f : x;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const float u = __shfl_down(x, d, 64);
+        if (lane + d < 64) x += u;
+    }
+    return x;
+}
+
+// One 64-lane workgroup per radial node; the column's rows live in LDS and
+// each lane owns a contiguous segment of nodes.  The two trapezoid integrals
+// (the hydrostatic one up the column, the downward H2 column) are prefix and
+// suffix sums (segment sums, a wave scan of the segment totals, then the
+// segment again), the normalisation of the density is a wave sum, and both
+// crossings are counts: the downward column only grows towards the midplane,
+// so the nodes above the photodissociation threshold are the first up_a + 1,
+// and the first warm node is a minimum over the lanes.  The same quantities
+// as a serial scan of the column, up to the order of the roundings.
 __global__ __launch_bounds__(64) void chain_columns(ChainArgs a, const float *__restrict__ T, float *__restrict__ ln_n,
                                                     float *__restrict__ zlo, float *__restrict__ zup) {
     extern __shared__ float sm[];
-    const int i = blockIdx.x, nz = a.nz;
-    float *sT = sm, *sL = sm + nz;
+    const int i = blockIdx.x, nz = a.nz, lane = threadIdx.x;
+    float *sT = sm, *sH = sm + nz, *sL = sm + 2 * nz, *sE = sm + 3 * nz, *sN = sm + 4 * nz;
     const size_t o = (size_t)i * nz;
-    for (int j = threadIdx.x; j < nz; j += 64) sT[j] = T[o + j];
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const float r = node_r(a, i);
-        const float L0 = column_ell(a, sT, r, sL, nullptr);
-        for (int j = 0; j < nz; ++j) sL[j] += L0;
-        column_surfaces(a, sL, sT, r, zlo + i, zup + i);
+    const int per = (nz + 63) / 64, j0 = min(nz, lane * per), j1 = min(nz, j0 + per);
+    const float r = node_r(a, i), dz = a.dzeta * r;
+    for (int j = j0; j < j1; ++j) {
+        const float t = T[o + j];
+        sT[j] = t;
+        sH[j] = grav_h(a, r, (float)j * dz, t);
     }
     __syncthreads();
-    for (int j = threadIdx.x; j < nz; j += 64) ln_n[o + j] = sL[j];
+    // hydrostatic integral I_j = sum_{k=1..j} (h_{k-1} + h_k) dz / 2, l_j = -I_j - ln T_j + ln T_0
+    float seg = 0.0f;
+    for (int j = max(j0, 1); j < j1; ++j) seg += 0.5f * (sH[j - 1] + sH[j]) * dz;
+    float I = wave_excl_scan_up(seg);
+    const float lnT0 = logf(sT[0]);
+    for (int j = j0; j < j1; ++j) {
+        if (j > 0) I += 0.5f * (sH[j - 1] + sH[j]) * dz;
+        const float l = -I - logf(sT[j]) + lnT0;
+        sL[j] = l;
+        sE[j] = expf(l);
+    }
+    __syncthreads();
+    // normalisation: ln rho_0 + cn = ln Sigma - ln(2 int e^l dz) + cn
+    float tr = 0.0f;
+    for (int j = max(j0, 1); j < j1; ++j) tr += 0.5f * (sE[j - 1] + sE[j]) * dz;
+    tr = __shfl(wave_incl_scan(tr), 63, 64);
+    const float L0 = ln_sigma(a, r) - logf(2.0f * tr) + a.cn;
+    for (int j = j0; j < j1; ++j) {
+        const float ln = sL[j] + L0;
+        ln_n[o + j] = ln;
+        sE[j] = expf(ln);
+    }
+    __syncthreads();
+    // downward column N_j = sum_{k=j..nz-2} (n_k + n_{k+1}) dz au / 2 (N_{nz-1} = 0)
+    const int je = min(j1, nz - 1);
+    float cs = 0.0f;
+    for (int j = j0; j < je; ++j) cs += 0.5f * (sE[j] + sE[j + 1]) * dz * a.au_cm;
+    float N = wave_excl_scan_down(cs);       // the column of the segments above this one (higher j)
+    int above = 0;
+    for (int j = je - 1; j >= j0; --j) {
+        N += 0.5f * (sE[j] + sE[j + 1]) * dz * a.au_cm;
+        sN[j] = N;
+        above += N > a.thr ? 1 : 0;
+    }
+    if (lane == 0) sN[nz - 1] = 0.0f;
+    // first warm node above the midplane
+    int warm = nz;
+    for (int j = max(j0, 1); j < j1; ++j)
+        if (sT[j] > a.t_freeze) { warm = j; break; }
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) {
+        above += __shfl_xor(above, d, 64);
+        warm = min(warm, __shfl_xor(warm, d, 64));
+    }
+    __syncthreads();
+    if (lane == 0) {
+        const int up_a = above - 1;
+        if (up_a < 0) {
+            zup[i] = -a.zr_max * r;
+        } else {
+            const float Na = sN[up_a], Nb = sN[up_a + 1];
+            const float f = Nb > 0.0f ? (a.ln_thr - logf(Na)) / (logf(Nb) - logf(Na)) : (a.thr - Na) / (Nb - Na);
+            zup[i] = ((float)up_a + f) * dz;
+        }
+        if (sT[0] > a.t_freeze) {
+            zlo[i] = -a.zr_max * r;
+        } else if (warm == nz) {
+            zlo[i] = 2.0f * a.zr_max * r;
+        } else {
+            zlo[i] = ((float)(warm - 1) + (a.t_freeze - sT[warm - 1]) / (sT[warm] - sT[warm - 1])) * dz;
+        }
+    }
 }
 
 __device__ __forceinline__ float lnP(const float *ln_n, const float *T, int nz, int i, int j) {
@@ -382,7 +482,7 @@ extern "C" rt_status rt_derive_fields(const rt_derive *d, const rt_derived *out,
         return fail(RT_EINVAL, "every derived output must be given");
     const ChainArgs a = chain_args(d);
     hipStream_t s = (hipStream_t)stream;
-    hipLaunchKernelGGL(chain_columns, dim3(a.nr), dim3(64), 2 * sizeof(float) * a.nz, s, a, d->temp_k, out->ln_nh2,
+    hipLaunchKernelGGL(chain_columns, dim3(a.nr), dim3(64), 5 * sizeof(float) * a.nz, s, a, d->temp_k, out->ln_nh2,
                        out->z_lo_au, out->z_up_au);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail_hip(e, "derive columns");
@@ -407,7 +507,7 @@ extern "C" rt_status rt_derive_fields_adjoint(const rt_derive *d, const rt_deriv
     if (!w) return fail_hip(e, "derive scratch");
     float *eu = w, *ez = w + n, *gn = w + 2 * n, *gT = w + 3 * n, *lnn = w + 4 * n;
     // forward ln n (and surfaces into discarded slots of gn) for the v_phi stencils
-    hipLaunchKernelGGL(chain_columns, dim3(a.nr), dim3(64), 2 * sizeof(float) * a.nz, s, a, d->temp_k, lnn, gn,
+    hipLaunchKernelGGL(chain_columns, dim3(a.nr), dim3(64), 5 * sizeof(float) * a.nz, s, a, d->temp_k, lnn, gn,
                        gn + a.nr);
     hipLaunchKernelGGL(chain_vphi_adj, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a, d->temp_k, lnn,
                        cot->vphi_kms, eu, ez, gT);
