@@ -236,13 +236,26 @@ __global__ __launch_bounds__(256) void nt_wgrad(int N, const float *__restrict__
     }
 }
 
-__global__ __launch_bounds__(256) void nt_wreduce(int chunks, const float *__restrict__ partial,
-                                                  float *__restrict__ dW) {
-    const int p = blockIdx.x * 256 + threadIdx.x;
-    if (p >= RT_NT_PARAMS) return;
+// dW[p] = sum over chunks of the partials: 64 parameters per workgroup, 8
+// lanes per parameter each summing every 8th chunk, then the 8 partial sums
+// added in a fixed order (deterministic)
+constexpr int kNtRedGroups = 8;
+__global__ __launch_bounds__(64 * kNtRedGroups) void nt_wreduce(int chunks, const float *__restrict__ partial,
+                                                                float *__restrict__ dW) {
+    __shared__ float part[kNtRedGroups][64];
+    const int pl = threadIdx.x % 64, g = threadIdx.x / 64;
+    const int p = blockIdx.x * 64 + pl;
     float s = 0.0f;
-    for (int c = 0; c < chunks; ++c) s += partial[(size_t)c * RT_NT_PARAMS + p];
-    dW[p] = s;
+    if (p < RT_NT_PARAMS)
+        for (int c = g; c < chunks; c += kNtRedGroups) s += partial[(size_t)c * RT_NT_PARAMS + p];
+    part[g][pl] = s;
+    __syncthreads();
+    if (g == 0 && p < RT_NT_PARAMS) {
+        float t = 0.0f;
+#pragma unroll
+        for (int k = 0; k < kNtRedGroups; ++k) t += part[k][pl];
+        dW[p] = t;
+    }
 }
 
 __global__ __launch_bounds__(256) void nt_adam(int64_t n, float *__restrict__ p, float *__restrict__ m,
@@ -311,7 +324,7 @@ extern "C" rt_status rt_neural_temperature_adjoint(const rt_grid *grid, const fl
     hipLaunchKernelGGL(nt_fwd, dim3(blocks), dim3(kNtBlock), kNtLds, s, grid->nr, grid->nz, weights, Tn, act);
     hipLaunchKernelGGL(nt_delta, dim3(blocks), dim3(kNtBlock), kNtLds, s, N, weights, d_temp_k, act, del);
     hipLaunchKernelGGL(nt_wgrad, dim3(chunks, 5), dim3(256), 0, s, N, act, del, part);
-    hipLaunchKernelGGL(nt_wreduce, dim3((RT_NT_PARAMS + 255) / 256), dim3(256), 0, s, chunks, part, d_weights);
+    hipLaunchKernelGGL(nt_wreduce, dim3((RT_NT_PARAMS + 63) / 64), dim3(64 * kNtRedGroups), 0, s, chunks, part, d_weights);
     e = hipGetLastError();
     return e == hipSuccess ? RT_OK : fail_hip(e, "neural temperature adjoint");
 }
