@@ -201,7 +201,8 @@ __global__ __launch_bounds__(kNtBlock) void nt_delta(int N, const float *__restr
 // nodes: W_l[a][b] gets sum_n dz_{l+1}[a][n] in_l[b][n] and b_l[a] gets
 // sum_n dz_{l+1}[a][n].  The chunk's rows of dz_{l+1} (delta rows l 64 + a,
 // or dL/do for the output layer) and of in_l (the features, or h_l) are
-// staged in LDS; each lane accumulates up to 16 (a, b) entries.
+// staged in LDS; each lane accumulates up to 16 (a, b) entries (a 4 x 4 tile
+// in the 64 x 64 layers).
 __global__ __launch_bounds__(256) void nt_wgrad(int N, const float *__restrict__ act, const float *__restrict__ delta,
                                                 float *__restrict__ partial) {
     __shared__ float sA[kNtW][kNtChunk + 1], sB[kNtW][kNtChunk + 1];
@@ -213,11 +214,40 @@ __global__ __launch_bounds__(256) void nt_wgrad(int N, const float *__restrict__
         if (r < K) sB[r][k] = n < N ? act[(size_t)(l == 0 ? r : kNtIn + (l - 1) * kNtW + r) * N + n] : 0.0f;
     }
     __syncthreads();
-    // lane -> row a and a run of nb consecutive columns b0..
-    const int per = (M * K + 255) / 256;          // 16 (64 x 64), 4 (64 x 16), 1 (1 x 64)
+    float *out = partial + (size_t)blockIdx.x * RT_NT_PARAMS + layer_off(l);
+    if (M == kNtW && K == kNtW) {
+        // 64 x 64 layers: a 4 x 4 tile of (a, b) per lane, 8 LDS reads per 16 FMAs
+        const int a0 = (t / 16) * 4, b0 = (t % 16) * 4;
+        float acc[4][4], bias[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            bias[i] = 0.0f;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc[i][c] = 0.0f;
+        }
+        for (int k = 0; k < kNtChunk; ++k) {
+            float ga[4], gb[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) { ga[i] = sA[a0 + i][k]; gb[i] = sB[b0 + i][k]; }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                bias[i] += ga[i];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) acc[i][c] = fmaf(ga[i], gb[c], acc[i][c]);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) out[(a0 + i) * K + b0 + c] = acc[i][c];
+            if (b0 == 0) out[M * K + a0 + i] = bias[i];
+        }
+        return;
+    }
+    // other layers: lane -> row a and a run of `per` consecutive columns b0..
+    const int per = (M * K + 255) / 256;          // 4 (64 x 16), 1 (1 x 64)
     const int runs = K / per;
     const int a = t / runs, b0 = (t - a * runs) * per;
-    float *out = partial + (size_t)blockIdx.x * RT_NT_PARAMS + layer_off(l);
     if (a < M) {
         float acc[16], bias = 0.0f;
 #pragma unroll
