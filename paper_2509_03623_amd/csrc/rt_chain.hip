@@ -8,9 +8,8 @@
 // gradient.  The discretisation is stated in include/rtcube.h.
 //
 // The work is a few operations per grid node (3.3e4 nodes at 256 x 128): the
-// scans along a column run in one lane of a workgroup that stages the
-// column's rows in LDS (one workgroup per radial node), the stencils in one
-// lane per node; a call is a few launches of tens of microseconds next to a
+// scans along a column run in one 64-lane wave that stages the column's rows
+// in LDS (one workgroup per radial node), the stencils in one lane per node; a call is a few launches of tens of microseconds next to a
 // render of milliseconds.  Lengths are in au inside the
 // kernels (cm^3-scale powers would overflow float), with the unit factors
 // folded into the constants on the host.
@@ -44,7 +43,7 @@ struct ChainArgs {
     float cn;                 // -ln(au) - ln(m_mol): ln n = ln Sigma - ln(2 int e^l dz[au]) + l + cn
     float ln_sig0, gamma, inv_rc;   // ln Sigma = ln_sig0 - gamma ln x - x^(2 - gamma), x = r / r_c
     float au_cm;              // column increments: n [cm^-3] dz [au] au_cm
-    float thr, ln_thr;        // N_dissoc / 0.706 and its log
+    float thr;                // N_dissoc / 0.706
     float t_freeze;
     float cv;                 // G M / au in (km/s)^2 au: v_K^2 = cv r^2 / (r^2 + z^2)^(3/2)
     float ct;                 // k_B / m_mol in (km/s)^2 / K
@@ -61,71 +60,6 @@ __device__ __forceinline__ float grav_h(const ChainArgs &a, float r, float z, fl
 __device__ __forceinline__ float ln_sigma(const ChainArgs &a, float r) {
     const float lx = logf(r * a.inv_rc);
     return a.ln_sig0 - a.gamma * lx - expf((2.0f - a.gamma) * lx);
-}
-
-// Per column: l_j = ln rho_j - ln rho_0 into lout, and ln rho_0 + cn returned.
-__device__ float column_ell(const ChainArgs &a, const float *Tc, float r, float *lout, float *h_out) {
-    const float dz = a.dzeta * r;
-    const float lnT0 = logf(Tc[0]);
-    float I = 0.0f, hprev = 0.0f, eprev = 1.0f, trap = 0.0f;
-    for (int j = 0; j < a.nz; ++j) {
-        const float T = Tc[j];
-        const float h = grav_h(a, r, (float)j * dz, T);
-        if (j > 0) I += 0.5f * (hprev + h) * dz;
-        const float l = -I - logf(T) + lnT0;
-        const float e = expf(l);
-        if (j > 0) trap += 0.5f * (eprev + e) * dz;
-        lout[j] = l;
-        if (h_out) h_out[j] = h;
-        hprev = h;
-        eprev = e;
-    }
-    return ln_sigma(a, r) - logf(2.0f * trap) + a.cn;
-}
-
-struct Crossings {
-    int up_a;          // node below the photodissociation crossing (-1: midplane unshielded)
-    float Na, Nb;      // columns at up_a and up_a + 1
-    int lo_b;          // first warm node (-1: warm midplane, nz: never warm)
-};
-
-// downward column from ln n (in ln_n[j]) and the two crossings; writes the surfaces
-__device__ Crossings column_surfaces(const ChainArgs &a, const float *ln_n, const float *Tc, float r, float *zlo,
-                                     float *zup) {
-    const float dz = a.dzeta * r;
-    Crossings c{-1, 0.0f, 0.0f, -1};
-    float N = 0.0f, nprev = expf(ln_n[a.nz - 1]);
-    bool found = false;
-    for (int j = a.nz - 2; j >= 0; --j) {
-        const float n = expf(ln_n[j]);
-        const float Nn = N + 0.5f * (n + nprev) * dz * a.au_cm;
-        if (!found && Nn > a.thr) {
-            found = true;
-            c.up_a = j;
-            c.Na = Nn;
-            c.Nb = N;
-        }
-        N = Nn;
-        nprev = n;
-    }
-    if (!found) {
-        *zup = -a.zr_max * r;
-    } else {
-        const float f = c.Nb > 0.0f ? (a.ln_thr - logf(c.Na)) / (logf(c.Nb) - logf(c.Na)) : (a.thr - c.Na) / (c.Nb - c.Na);
-        *zup = ((float)c.up_a + f) * dz;
-    }
-    if (Tc[0] > a.t_freeze) {
-        c.lo_b = -1;
-        *zlo = -a.zr_max * r;
-    } else {
-        int b = a.nz;
-        for (int j = 1; j < a.nz; ++j)
-            if (Tc[j] > a.t_freeze) { b = j; break; }
-        c.lo_b = b;
-        if (b == a.nz) *zlo = 2.0f * a.zr_max * r;
-        else *zlo = ((float)(b - 1) + (a.t_freeze - Tc[b - 1]) / (Tc[b] - Tc[b - 1])) * dz;
-    }
-    return c;
 }
 
 // Wave-wide inclusive prefix sum of one value per lane.
@@ -161,19 +95,26 @@ __device__ __forceinline__ float wave_excl_scan_down(float v) {
     return x;
 }
 
-// One 64-lane workgroup per radial node; the column's rows live in LDS and
-// each lane owns a contiguous segment of nodes.  The two trapezoid integrals
-// (the hydrostatic one up the column, the downward H2 column) are prefix and
-// suffix sums (segment sums, a wave scan of the segment totals, then the
-// segment again), the normalisation of the density is a wave sum, and both
-// crossings are counts: the downward column only grows towards the midplane,
-// so the nodes above the photodissociation threshold are the first up_a + 1,
-// and the first warm node is a minimum over the lanes.  The same quantities
-// as a serial scan of the column, up to the order of the roundings.
-__global__ __launch_bounds__(64) void chain_columns(ChainArgs a, const float *__restrict__ T, float *__restrict__ ln_n,
-                                                    float *__restrict__ zlo, float *__restrict__ zup) {
-    extern __shared__ float sm[];
-    const int i = blockIdx.x, nz = a.nz, lane = threadIdx.x;
+// The column pass of radial node i by one 64-lane wave.  The column's rows
+// live in LDS and each lane owns a contiguous segment of nodes.  The two
+// trapezoid integrals (the hydrostatic one up the column, the downward H2
+// column) are prefix and suffix sums (segment sums, a wave scan of the segment
+// totals, then the segment again), the normalisation of the density is a wave
+// sum, and both crossings are counts: the downward column only grows towards
+// the midplane, so the nodes above the photodissociation threshold are the
+// first up_a + 1, and the first warm node is a minimum over the lanes.  The
+// same quantities as a serial scan of the column, up to the order of the
+// roundings.  Leaves T, h, l = ln rho - ln rho_0, n and the downward column N
+// in the five LDS rows (synchronised) and writes ln n when ln_n is given.
+struct ColumnWave {
+    int up_a;    // node below the photodissociation crossing (-1: midplane unshielded)
+    int lo_b;    // first warm node (-1: warm midplane, nz: never warm)
+    float r, dz;
+};
+
+__device__ ColumnWave column_wave(const ChainArgs &a, const float *__restrict__ T, int i, float *sm,
+                                  float *__restrict__ ln_n) {
+    const int nz = a.nz, lane = threadIdx.x;
     float *sT = sm, *sH = sm + nz, *sL = sm + 2 * nz, *sE = sm + 3 * nz, *sN = sm + 4 * nz;
     const size_t o = (size_t)i * nz;
     const int per = (nz + 63) / 64, j0 = min(nz, lane * per), j1 = min(nz, j0 + per);
@@ -201,9 +142,10 @@ __global__ __launch_bounds__(64) void chain_columns(ChainArgs a, const float *__
     for (int j = max(j0, 1); j < j1; ++j) tr += 0.5f * (sE[j - 1] + sE[j]) * dz;
     tr = __shfl(wave_incl_scan(tr), 63, 64);
     const float L0 = ln_sigma(a, r) - logf(2.0f * tr) + a.cn;
+    __syncthreads();
     for (int j = j0; j < j1; ++j) {
         const float ln = sL[j] + L0;
-        ln_n[o + j] = ln;
+        if (ln_n) ln_n[o + j] = ln;
         sE[j] = expf(ln);
     }
     __syncthreads();
@@ -229,22 +171,40 @@ __global__ __launch_bounds__(64) void chain_columns(ChainArgs a, const float *__
         warm = min(warm, __shfl_xor(warm, d, 64));
     }
     __syncthreads();
-    if (lane == 0) {
-        const int up_a = above - 1;
-        if (up_a < 0) {
-            zup[i] = -a.zr_max * r;
+    return ColumnWave{above - 1, sT[0] > a.t_freeze ? -1 : warm, r, dz};
+}
+
+// one 64-lane workgroup per radial node
+__global__ __launch_bounds__(64) void chain_columns(ChainArgs a, const float *__restrict__ T, float *__restrict__ ln_n,
+                                                    float *__restrict__ zlo, float *__restrict__ zup) {
+    extern __shared__ float sm[];
+    const int i = blockIdx.x, nz = a.nz;
+    const float *sT = sm, *sN = sm + 4 * nz;
+    const ColumnWave c = column_wave(a, T, i, sm, ln_n);
+    if (threadIdx.x != 0) return;
+    const float r = c.r, dz = c.dz;
+    if (c.up_a < 0) {
+        zup[i] = -a.zr_max * r;
+    } else {
+        const float Na = sN[c.up_a], Nb = sN[c.up_a + 1];
+        float f;
+        if (Nb > 0.0f) {
+            // ln(thr / N) of the two nodes: the logs of ratios near 1 are exact
+            // to rounding, where ln thr - ln N loses the digits of ln thr ~ 48
+            const float w = logf(a.thr / Na), u = logf(a.thr / Nb);
+            f = w / (w - u);
         } else {
-            const float Na = sN[up_a], Nb = sN[up_a + 1];
-            const float f = Nb > 0.0f ? (a.ln_thr - logf(Na)) / (logf(Nb) - logf(Na)) : (a.thr - Na) / (Nb - Na);
-            zup[i] = ((float)up_a + f) * dz;
+            f = (a.thr - Na) / (Nb - Na);
         }
-        if (sT[0] > a.t_freeze) {
-            zlo[i] = -a.zr_max * r;
-        } else if (warm == nz) {
-            zlo[i] = 2.0f * a.zr_max * r;
-        } else {
-            zlo[i] = ((float)(warm - 1) + (a.t_freeze - sT[warm - 1]) / (sT[warm] - sT[warm - 1])) * dz;
-        }
+        zup[i] = ((float)c.up_a + f) * dz;
+    }
+    if (c.lo_b < 0) {
+        zlo[i] = -a.zr_max * r;
+    } else if (c.lo_b == nz) {
+        zlo[i] = 2.0f * a.zr_max * r;
+    } else {
+        const int w = c.lo_b;
+        zlo[i] = ((float)(w - 1) + (a.t_freeze - sT[w - 1]) / (sT[w] - sT[w - 1])) * dz;
     }
 }
 
@@ -322,90 +282,92 @@ __global__ __launch_bounds__(256) void chain_lnp_adj(ChainArgs a, const float *_
     gT[idx] += g / T[idx];
 }
 
-// per column: reverse of the column pass (crossings held fixed); one
-// 64-lane workgroup per radial node, rows staged in LDS, lane 0 scans
+// per column: reverse of the column pass (crossings held fixed), one 64-lane
+// workgroup per radial node.  The forward quantities come from the same wave
+// pass as the forward kernel; the reverse is elementwise except for two wave
+// sums (the normalisation) and one suffix sum (the cotangent of the
+// hydrostatic integral), taken as segment sums and a wave scan of the segments
+// above, so no difference of large partial sums is formed.
 __global__ __launch_bounds__(64) void chain_columns_adj(ChainArgs a, const float *__restrict__ T,
                                                         const float *__restrict__ nbar, const float *__restrict__ zlobar,
                                                         const float *__restrict__ zupbar,
                                                         const float *__restrict__ gn, const float *__restrict__ gT,
                                                         float *__restrict__ dT) {
     extern __shared__ float sm[];
-    const int i = blockIdx.x, nz = a.nz;
+    const int i = blockIdx.x, nz = a.nz, lane = threadIdx.x;
     const size_t o = (size_t)i * nz;
-    float *Tc = sm, *L = sm + nz, *lnn = sm + 2 * nz, *sg = sm + 3 * nz, *sgT = sm + 4 * nz;
-    for (int j = threadIdx.x; j < nz; j += 64) {
-        Tc[j] = T[o + j];
-        sg[j] = (nbar ? nbar[o + j] : 0.0f) + gn[o + j];
-        sgT[j] = gT[o + j];
+    float *sT = sm, *sH = sm + nz, *sL = sm + 2 * nz, *sE = sm + 3 * nz;
+    const float *sN = sm + 4 * nz;
+    const ColumnWave c = column_wave(a, T, i, sm, nullptr);
+    const int per = (nz + 63) / 64, j0 = min(nz, lane * per), j1 = min(nz, j0 + per);
+    const float dz = c.dz;
+    // photodissociation surface -> the two columns it interpolates
+    const int ka = c.up_a, kb = c.up_a + 1;
+    float Nab = 0.0f, Nbb = 0.0f;
+    const float zub = zupbar ? zupbar[i] : 0.0f;
+    if (ka >= 0 && zub != 0.0f) {
+        const float Na = sN[ka], Nb = sN[kb];
+        if (Nb > 0.0f) {
+            // f = w / (w - u), w = ln(thr / Na) <= 0 <= u = ln(thr / Nb), as in the forward
+            const float w = logf(a.thr / Na), u = logf(a.thr / Nb), d = w - u;
+            Nab = zub * dz * (u / (d * d)) / Na;
+            Nbb = zub * dz * (-w / (d * d)) / Nb;
+        } else {
+            const float d = Nb - Na;
+            Nab = zub * dz * ((a.thr - Nb) / (d * d));
+            Nbb = zub * dz * (-(a.thr - Na) / (d * d));
+        }
     }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const float r = node_r(a, i);
-        const float dz = a.dzeta * r;
-        // L: l_j, then its cotangent; lnn: ln n_j, then its cotangent
-        const float L0 = column_ell(a, Tc, r, L, nullptr);
-        for (int j = 0; j < nz; ++j) lnn[j] = L[j] + L0;
-        float zl, zu;
-        const Crossings c = column_surfaces(a, lnn, Tc, r, &zl, &zu);
-        // photodissociation surface -> the two columns it interpolates
-        float Nab = 0.0f, Nbb = 0.0f;
-        const float zub = zupbar ? zupbar[i] : 0.0f;
-        if (c.up_a >= 0 && zub != 0.0f) {
-            if (c.Nb > 0.0f) {
-                const float la = logf(c.Na), lb = logf(c.Nb), d = lb - la;
-                Nab = zub * dz * ((a.ln_thr - lb) / (d * d)) / c.Na;
-                Nbb = zub * dz * (-(a.ln_thr - la) / (d * d)) / c.Nb;
-            } else {
-                const float d = c.Nb - c.Na;
-                Nab = zub * dz * ((a.thr - c.Nb) / (d * d));
-                Nbb = zub * dz * (-(a.thr - c.Na) / (d * d));
-            }
+    // d L / d ln n_j: given plus from v_phi, and from the two columns (N_k
+    // sums the trapezoid segments from node k up: n_j enters the segments
+    // below and above it); kept in sE in place of n_j
+    float gsum = 0.0f, trap = 0.0f;
+    for (int j = j0; j < j1; ++j) {
+        float g = (nbar ? nbar[o + j] : 0.0f) + gn[o + j];
+        if (ka >= 0) {
+            const float dka = (float)((j >= ka + 1) ? 1 : 0) + (float)((j >= ka && j <= nz - 2) ? 1 : 0);
+            const float dkb = (float)((j >= kb + 1) ? 1 : 0) + (float)((j >= kb && j <= nz - 2) ? 1 : 0);
+            g += sE[j] * 0.5f * dz * a.au_cm * (Nab * dka + Nbb * dkb);
         }
-        // d L / d ln n_j: given plus from v_phi (sg), and from the two columns
-        // (N_k sums the trapezoid segments from node k up: n_j enters the
-        // segments below and above it)
-        const int ka = c.up_a, kb = c.up_a + 1;
-        auto dN_dn = [&](int k, int j) {   // d N_k / d n_j without the factor dz au / 2
-            return (float)((j >= k + 1) ? 1 : 0) + (float)((j >= k && j <= nz - 2) ? 1 : 0);
-        };
-        float Gsum = 0.0f, trap = 0.0f;
-        for (int j = 0; j < nz; ++j) {
-            float g = sg[j];
-            if (ka >= 0) g += expf(lnn[j]) * 0.5f * dz * a.au_cm * (Nab * dN_dn(ka, j) + Nbb * dN_dn(kb, j));
-            Gsum += g;
-            const float w = (j == 0 || j == nz - 1) ? 0.5f : 1.0f;
-            trap += w * expf(L[j]);
-            lnn[j] = g;
-        }
-        // ln n_j = l_j + ln rho_0 + const, ln rho_0 = ln Sigma - ln(2 dz sum w_j e^l_j)
-        for (int j = 0; j < nz; ++j) {
-            const float w = (j == 0 || j == nz - 1) ? 0.5f : 1.0f;
-            L[j] = lnn[j] - Gsum * w * expf(L[j]) / trap;
-        }
-        // l_j = -I_j - ln T_j + ln T_0; I_j = sum over segments below j of (h_s + h_s+1) dz / 2
-        float R = 0.0f, Rnext = 0.0f;   // suffix sums of the cotangent of l
-        const float t_f = a.t_freeze;
-        const float zlb = zlobar ? zlobar[i] : 0.0f;
-        for (int k = nz - 1; k >= 0; --k) {
-            Rnext = R;
-            R += L[k];
-            const float hb = -0.5f * dz * ((k <= nz - 2 ? Rnext : 0.0f) + (k >= 1 ? R : 0.0f));
-            const float Tk = Tc[k];
-            const float h = grav_h(a, r, (float)k * dz, Tk);
-            float g = -L[k] / Tk - hb * h / Tk + sgT[k];
-            // freeze-out surface: linear in T between nodes lo_b - 1 and lo_b
-            if (zlb != 0.0f && c.lo_b > 0 && c.lo_b < nz) {
-                const int b = c.lo_b, aa = b - 1;
-                const float d = Tc[b] - Tc[aa];
-                if (k == aa) g += zlb * dz * (t_f - Tc[b]) / (d * d);
-                if (k == b) g -= zlb * dz * (t_f - Tc[aa]) / (d * d);
-            }
-            sg[k] = g;
-        }
-        sg[0] += R / Tc[0];
+        gsum += g;
+        trap += ((j == 0 || j == nz - 1) ? 0.5f : 1.0f) * expf(sL[j]);
+        sE[j] = g;
     }
-    __syncthreads();
-    for (int j = threadIdx.x; j < nz; j += 64) dT[o + j] = sg[j];
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) {
+        gsum += __shfl_xor(gsum, d, 64);
+        trap += __shfl_xor(trap, d, 64);
+    }
+    // ln n_j = l_j + ln rho_0 + const, ln rho_0 = ln Sigma - ln(2 dz sum w_j e^l_j):
+    // cotangent of l_j into sL
+    float seg = 0.0f;
+    for (int j = j0; j < j1; ++j) {
+        const float w = (j == 0 || j == nz - 1) ? 0.5f : 1.0f;
+        const float lb = sE[j] - gsum * w * expf(sL[j]) / trap;
+        sL[j] = lb;
+        seg += lb;
+    }
+    // l_j = -I_j - ln T_j + ln T_0, I_j = sum over the segments below j of
+    // (h_s + h_s+1) dz / 2: node k's h enters I_j for j >= k (twice for j > k)
+    float R = wave_excl_scan_down(seg);   // suffix sum of the cotangent of l from j1 up
+    const float t_f = a.t_freeze;
+    const float zlb = zlobar ? zlobar[i] : 0.0f;
+    for (int k = j1 - 1; k >= j0; --k) {
+        const float Rnext = R;
+        R += sL[k];
+        const float hb = -0.5f * dz * ((k <= nz - 2 ? Rnext : 0.0f) + (k >= 1 ? R : 0.0f));
+        const float Tk = sT[k];
+        float g = -sL[k] / Tk - hb * sH[k] / Tk + gT[o + k];
+        // freeze-out surface: linear in T between nodes lo_b - 1 and lo_b
+        if (zlb != 0.0f && c.lo_b > 0 && c.lo_b < nz) {
+            const int b = c.lo_b, aa = b - 1;
+            const float d = sT[b] - sT[aa];
+            if (k == aa) g += zlb * dz * (t_f - sT[b]) / (d * d);
+            if (k == b) g -= zlb * dz * (t_f - sT[aa]) / (d * d);
+        }
+        if (k == 0) g += R / sT[0];     // ln T_0 enters every l_j
+        dT[o + k] = g;
+    }
 }
 
 // two-layer parametric temperature at every node (one lane per node)
@@ -447,7 +409,6 @@ ChainArgs chain_args(const rt_derive *d) {
     a.inv_rc = (float)(1.0 / d->rc_au);
     a.au_cm = (float)kAu;
     a.thr = (float)(d->n_dissoc_cm2 / kPhotoFactor);
-    a.ln_thr = (float)std::log(d->n_dissoc_cm2 / kPhotoFactor);
     a.t_freeze = (float)d->t_freeze_k;
     a.cv = (float)(kG * d->mstar_msun * kMsun / kAu / 1e10);
     a.ct = (float)(kKb / m_mol / 1e10);

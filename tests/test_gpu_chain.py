@@ -74,10 +74,14 @@ def test_derived_fields_match_oracle(grid, seed):
         assert np.all(np.abs(g[k] - r[k]) <= 1e-5 * r_au + 1e-6), k
 
 
-def test_derived_fields_adjoint_matches_oracle_autograd():
+# column lengths below one node per lane, two per lane, and a ragged three
+# per lane (the top lanes of the wave own no nodes)
+@pytest.mark.parametrize("grid,seed", [((48, 24, 1.0, 600.0, 0.5), 4), ((256, 128, 1.0, 600.0, 0.5), 6),
+                                       ((40, 150, 5.0, 300.0, 0.4), 7)])
+def test_derived_fields_adjoint_matches_oracle_autograd(grid, seed):
     rt = _rt()
-    grid = (48, 24, 1.0, 600.0, 0.5)
-    T32 = _temperature(grid, 4)
+    print(f"[gpu] derived-field adjoint grid {grid} seed {seed}", flush=True)
+    T32 = _temperature(grid, seed)
     T, ref = _oracle(T32, grid, requires_grad=True)
     rng = np.random.Generator(np.random.PCG64(44))
     cot = {k: rng.standard_normal(tuple(v.shape)).astype(np.float32) for k, v in ref.items()}
