@@ -74,6 +74,22 @@ def test_channel_blocks_and_ray_split(cb, split):
     assert err <= TOL, (cb, split, err)
 
 
+@pytest.mark.parametrize("nch", [18, 20])
+@pytest.mark.parametrize("split", [1, 2, 4, 8])
+def test_partly_filled_channel_block(nch, split):
+    """18 and 20 channels (the paper's fixed-channel sweep) in the 24-channel
+    block of the launch rule: the unused channels of the block are computed
+    and dropped, at every ray split."""
+    key = f"c{nch}"
+    if key not in _CACHE:
+        prob = S3.make_problem3(S3.Grid3Spec(28, 14, 20), seed=68, nx=23, ny=17, nch=nch, dv=0.45, nsamp=120,
+                                incl=50.0, pa=-15.0)
+        _CACHE[key] = (prob, oracle.render3(prob))
+    prob, ref = _CACHE[key]
+    err = rel_err(gpu_cube3(prob, split=split), ref)
+    assert ref.max() > 0 and err <= TOL, (nch, split, err)
+
+
 @pytest.mark.parametrize("incl,pa", [(0.0, 0.0), (90.0, 0.0), (135.0, -40.0), (180.0, 10.0), (62.5, 200.0)])
 def test_inclinations(incl, pa):
     prob = S3.make_problem3(S3.Grid3Spec(24, 12, 16), seed=61, nx=21, ny=19, nch=9, dv=0.5, nsamp=100, incl=incl,
