@@ -411,8 +411,8 @@ int32_t rt_constants(double *out, int32_t n);
  * depth and the depth behind the sample; 2, 4, 8 or 16 selects the march
  * that stores the transmission every that many samples and recomputes each
  * segment from its checkpoint.  RT_OPT_ADJ_CHANNEL_BLOCK: channels per lane of
- * the adjoint's reverse march (8, 16, 24 or 32; 0 = automatic; 24 only without
- * checkpoints).  RT_OPT_ADJ_PIXEL_LANES: lanes sharing one pixel in the
+ * the adjoint's reverse march (8, 16, 24, 25 or 32; 0 = automatic; 24 and 25
+ * only without checkpoints, 25 only with two lanes per pixel).  RT_OPT_ADJ_PIXEL_LANES: lanes sharing one pixel in the
  * checkpoint-free reverse march, each with its own channel block, their
  * per-sample sums added across the lanes (1 or 2; 0 = automatic).
  * RT_OPT_RAY_SPLIT: lanes sharing one ray in the forward

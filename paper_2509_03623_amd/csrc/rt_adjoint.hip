@@ -642,7 +642,7 @@ hipError_t launch_adj_march(int cb, int kseg, int lanes, int nsamp, int npix, in
         return cube ? launch_tau_t<C, G, true>(nsamp, npix, plane, ch, tape, dl, target, cot, cube_out, st) \
                     : launch_tau_t<C, G, false>(nsamp, npix, plane, ch, tape, dl, target, cot, cube_out, st);
         RT_TAU_CASE(8, 1) RT_TAU_CASE(16, 1) RT_TAU_CASE(24, 1) RT_TAU_CASE(32, 1)
-        RT_TAU_CASE(16, 2) RT_TAU_CASE(24, 2) RT_TAU_CASE(32, 2)
+        RT_TAU_CASE(16, 2) RT_TAU_CASE(24, 2) RT_TAU_CASE(25, 2) RT_TAU_CASE(32, 2)
 #undef RT_TAU_CASE
         return hipErrorInvalidValue;
     }

@@ -11,8 +11,9 @@
 namespace rt {
 
 // Reverse-march shape (measured): of (channels per lane, lanes per pixel) =
-// (32, 2), (24, 2), (16, 2), (32, 1), (24, 1) that still give 2048 waves, the
-// one padding the fewest channels, the earlier in that order on a tie;
+// (32, 2), (24, 2), (16, 2), (32, 1), (24, 1), (25, 2) that still give 2048
+// waves, the one padding the fewest channels, the earlier in that order on a
+// tie (25 per lane is the pair form of a 50-channel batch);
 // (32, 1) only when the march forms the intensity (without it that form
 // spills registers); else (16, 1), or (8, 1) for at most 8 channels.  Pairs
 // write one cotangent slice per 2 CB channels (at 512^2 x 64: 10.9 ms fused
@@ -21,7 +22,7 @@ namespace rt {
 void adjoint_shape(int nch, long npix, bool cube, int *cb, int *lanes, int *kseg) {
     *cb = nch > 8 ? 16 : 8;
     *lanes = 1;
-    static const int cand[][2] = {{32, 2}, {24, 2}, {16, 2}, {32, 1}, {24, 1}};
+    static const int cand[][2] = {{32, 2}, {24, 2}, {16, 2}, {32, 1}, {24, 1}, {25, 2}};
     int best = 1 << 30;
     for (const auto &cl : cand) {
         const int c = cl[0], gl = cl[1], grp = c * gl;
@@ -34,9 +35,10 @@ void adjoint_shape(int nch, long npix, bool cube, int *cb, int *lanes, int *kseg
         }
     }
     const int ocb = adjoint_block_option();
-    if (ocb == 8 || ocb == 16 || ocb == 24 || ocb == 32) *cb = ocb;
+    if (ocb == 8 || ocb == 16 || ocb == 24 || ocb == 25 || ocb == 32) *cb = ocb;
     const int olanes = adjoint_lanes_option();
     if (olanes == 1 || olanes == 2) *lanes = olanes;
+    if (*cb == 25) *lanes = 2;   // 25 channels per lane only as a pair
     if (*lanes == 2 && *cb == 8) {
         // no 2 x 8 form: a pair asked for explicitly widens the block,
         // otherwise the 8-channel block keeps one lane per pixel
@@ -47,9 +49,9 @@ void adjoint_shape(int nch, long npix, bool cube, int *cb, int *lanes, int *kseg
     const int opt = ckpt_segment_option();
     if (opt == 2 || opt == 4 || opt == 8 || opt == 16) *kseg = opt;
     if (*kseg) {
-        // the checkpointed march has no 24-channel and no paired form
+        // the checkpointed march has no 24- or 25-channel and no paired form
         *lanes = 1;
-        if (*cb == 24) *cb = 16;
+        if (*cb == 24 || *cb == 25) *cb = 16;
         if (*cb == 16 && *kseg == 16) *kseg = 8;
         if (*cb == 32 && *kseg > 4) *kseg = 4;
     }

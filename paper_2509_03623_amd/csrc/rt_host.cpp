@@ -396,8 +396,8 @@ rt_status rt_set_option(int32_t key, int64_t value) {
         g_opt_adj_cap = value;
         return RT_OK;
     case RT_OPT_ADJ_CHANNEL_BLOCK:
-        if (value != 0 && value != 8 && value != 16 && value != 24 && value != 32)
-            return fail(RT_EINVAL, "adjoint channel block must be 0, 8, 16, 24 or 32");
+        if (value != 0 && value != 8 && value != 16 && value != 24 && value != 25 && value != 32)
+            return fail(RT_EINVAL, "adjoint channel block must be 0, 8, 16, 24, 25 or 32");
         g_opt_adj_cb = value;
         return RT_OK;
     case RT_OPT_ADJ_PIXEL_LANES:

@@ -106,6 +106,7 @@ def test_options_roundtrip():
     assert lib.rt_get_option(L.RT_OPT_ADJ_SCRATCH_CAP) == 1 << 20
     assert lib.rt_set_option(L.RT_OPT_ADJ_SCRATCH_CAP, 0) == 0
     assert lib.rt_set_option(L.RT_OPT_ADJ_CHANNEL_BLOCK, 12) == L.RT_EINVAL
+    assert lib.rt_set_option(L.RT_OPT_ADJ_CHANNEL_BLOCK, 25) == 0
     assert lib.rt_set_option(L.RT_OPT_ADJ_CHANNEL_BLOCK, 32) == 0
     assert lib.rt_get_option(L.RT_OPT_ADJ_CHANNEL_BLOCK) == 32
     assert lib.rt_set_option(L.RT_OPT_ADJ_CHANNEL_BLOCK, 0) == 0

@@ -262,7 +262,7 @@ def test_fused_l2_adjoint_equals_render_plus_adjoint(cap):
 
 
 @pytest.mark.parametrize("cb,lanes,kseg", [(8, 1, 0), (16, 1, 0), (24, 1, 0), (32, 1, 0), (16, 2, 0), (24, 2, 0),
-                                            (32, 2, 0), (8, 1, 2), (8, 1, 16), (16, 1, 2), (16, 1, 8), (32, 1, 2),
+                                            (25, 2, 0), (32, 2, 0), (8, 1, 2), (8, 1, 16), (16, 1, 2), (16, 1, 8), (32, 1, 2),
                                             (32, 1, 4)])
 def test_reverse_march_shapes(cb, lanes, kseg):
     """Every instantiated (channels per lane, lanes per pixel, samples per
@@ -285,3 +285,30 @@ def test_reverse_march_shapes(cb, lanes, kseg):
         rt.set_option(L.RT_OPT_CKPT_SEGMENT, 0)
     for k in BLOCKS:
         check_block(k, got[k], ref[k])
+
+
+def test_fused_fifty_channels_in_one_pair():
+    """A 50-slice batch (the neural-temperature fit's) in the 25-channel pair
+    form, which the launch rule takes for it at full image size: fused cube
+    and loss against the plain render, gradients against the oracle's."""
+    rt = _rt()
+    from paper_2509_03623_amd import _lib as L
+    prob = kscale(synth.small_problem(nx=21, ny=15, nch=50, nsamp=57, nr=40, nz=20, seed=23, dv=0.08))
+    target = target_for(prob)
+    sc = rt.scene_from_problem(prob)
+    tgt = torch.as_tensor(target, dtype=torch.float32, device="cuda")
+    print("[gpu] fused L2 adjoint, 50 channels as (25, 2)", flush=True)
+    rt.set_option(L.RT_OPT_ADJ_CHANNEL_BLOCK, 25)
+    try:
+        cube, loss, g = rt.render_l2_adjoint(sc, tgt, want=BLOCKS)
+    finally:
+        rt.set_option(L.RT_OPT_ADJ_CHANNEL_BLOCK, 0)
+    direct = rt.render(sc)
+    torch.cuda.synchronize()
+    assert float((cube - direct).abs().max()) <= 1e-6 * float(direct.abs().max())
+    l_ref = float(((direct.double() - tgt.double()) ** 2).sum())
+    assert float(loss.item()) == pytest.approx(l_ref, rel=1e-5)
+    _, oref = torch_ref.loss_and_grad(prob, target)
+    for k in BLOCKS:
+        r, g_ = oref[k].ravel(), g[k].cpu().numpy().astype(np.float64).ravel()
+        assert float(np.linalg.norm(g_ - r) / np.linalg.norm(r)) <= 1e-3, k
