@@ -408,7 +408,10 @@ __global__ __launch_bounds__(256) void adj_chain(Geometry g, Shade s, const floa
 constexpr int kChainThreads = 1024;
 
 // Chain pass with the gradient of one field privatised in LDS.  Persistent
-// workgroups each take a contiguous share of the pixel-samples, accumulate
+// workgroups take runs of 1024 consecutive pixel-samples in grid-stride
+// order, so every workgroup sees every depth along the rays (with one
+// contiguous share each, the few whose samples crossed the disk did the work
+// while those beyond it, where the cotangents vanish, sat idle), accumulate
 // field FIELD (0 ln n, 1 T, 2 v_phi, 3 none) over the whole grid in LDS
 // (float), and flush it once with double atomics; the FIRST pass also
 // accumulates the two surface vectors (LDS, double) and writes dL/do.
@@ -427,9 +430,8 @@ __global__ __launch_bounds__(kChainThreads) void adj_chain_lds(Geometry g, Shade
     __syncthreads();
     const int npix = g.nx * g.ny;
     const size_t total = (size_t)g.nsamp * npix;
-    const size_t per = (total + gridDim.x - 1) / gridDim.x;
-    const size_t lo = (size_t)blockIdx.x * per, hi = lo + per < total ? lo + per : total;
-    for (size_t idx = lo + threadIdx.x; idx < hi; idx += kChainThreads) {
+    for (size_t idx = (size_t)blockIdx.x * kChainThreads + threadIdx.x; idx < total;
+         idx += (size_t)gridDim.x * kChainThreads) {
         const int k = (int)(idx / npix);
         const int pix = (int)(idx - (size_t)k * npix);
         const float4 r = rays[pix];
