@@ -9,10 +9,11 @@
 //
 // The work is a few operations per grid node (3.3e4 nodes at 256 x 128): the
 // scans along a column run in one 64-lane wave that stages the column's rows
-// in LDS (one workgroup per radial node), the stencils in one lane per node; a call is a few launches of tens of microseconds next to a
-// render of milliseconds.  Lengths are in au inside the
-// kernels (cm^3-scale powers would overflow float), with the unit factors
-// folded into the constants on the host.
+// in LDS (one workgroup per radial node), the stencils in one lane per node;
+// a call is a few launches of tens of microseconds next to a render of
+// milliseconds.  Lengths are in au inside the kernels (cm^3-scale powers
+// would overflow float), with the unit factors folded into the constants on
+// the host.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
