@@ -52,23 +52,29 @@ class OrcProblem(C.Structure):
 _lib = None
 
 
+def load(path: str):
+    """Open a build of rt_oracle.c and declare the argument types of its 2-D
+    entry points."""
+    L = C.CDLL(path)
+    P = C.POINTER(OrcProblem)
+    L.orc_render.argtypes = [P, _d, C.c_int]
+    L.orc_render_pixels.argtypes = [P, C.c_int, C.POINTER(C.c_int32), C.POINTER(C.c_int32), _d, C.c_int]
+    L.orc_ray_dump.argtypes = [P, C.c_int, C.c_int, _d, _d, _d, _d]
+    L.orc_sample_point.argtypes = [P, C.c_double, C.c_double, C.c_double, _d]
+    L.orc_partition.argtypes = [P, C.c_double]
+    L.orc_partition.restype = C.c_double
+    L.orc_constants.argtypes = [_d, C.c_int]
+    L.orc_mlp.argtypes = [_f, C.c_double, C.c_double, _d]
+    return L
+
+
 def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             from . import build as _b
             _b.build()
-        L = C.CDLL(LIB_PATH)
-        P = C.POINTER(OrcProblem)
-        L.orc_render.argtypes = [P, _d, C.c_int]
-        L.orc_render_pixels.argtypes = [P, C.c_int, C.POINTER(C.c_int32), C.POINTER(C.c_int32), _d, C.c_int]
-        L.orc_ray_dump.argtypes = [P, C.c_int, C.c_int, _d, _d, _d, _d]
-        L.orc_sample_point.argtypes = [P, C.c_double, C.c_double, C.c_double, _d]
-        L.orc_partition.argtypes = [P, C.c_double]
-        L.orc_partition.restype = C.c_double
-        L.orc_constants.argtypes = [_d, C.c_int]
-        L.orc_mlp.argtypes = [_f, C.c_double, C.c_double, _d]
-        _lib = L
+        _lib = load(LIB_PATH)
     return _lib
 
 
