@@ -404,8 +404,11 @@ int32_t rt_constants(double *out, int32_t n);
 
 /* Tuning knobs (process-wide).  RT_OPT_CHANNEL_BLOCK: channels per lane of
  * the forward march (8, 16, 24, 32, 48 or 64; 0 = automatic).
- * RT_OPT_THIN_EXPM1: 1 evaluates 1 - e^-dtau of the forward march with a
- * series for small dtau, 0 (default) uses 1 - e^-dtau directly.
+ * RT_OPT_THIN_EXPM1: 1 (default) evaluates 1 - e^-dtau of rt_render_cube's
+ * march from its series on samples whose line-centre depth is small (below
+ * 1/32 in natural units; every other kernel always does), 0 uses
+ * 1 - e^-dtau directly everywhere (less accurate for optically thin lines,
+ * kept for comparison).
  * RT_OPT_CKPT_SEGMENT: 0 (default) runs the adjoint's reverse march without
  * checkpoints, rebuilding each transmission from the ray's total optical
  * depth and the depth behind the sample; 2, 4, 8 or 16 selects the march

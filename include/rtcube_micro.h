@@ -15,8 +15,8 @@ enum {
     RT_MICRO_EXP2 = 1,         /* v_exp_f32 */
     RT_MICRO_RCP = 2,          /* v_rcp_f32 */
     RT_MICRO_LOG2 = 3,         /* v_log_f32 */
-    RT_MICRO_LOOP_PLAIN = 4,   /* the march's channel-loop body, 1 - e^-x direct */
-    RT_MICRO_LOOP_THIN = 5,    /* the same body with the small-dtau series select */
+    RT_MICRO_LOOP_PLAIN = 4,   /* the march's channel-loop body on a thick sample (1 - e^-x direct) */
+    RT_MICRO_LOOP_THIN = 5,    /* the same body on an optically thin sample (series form) */
     RT_MICRO_EXP_FMA = 6       /* one v_exp_f32 per four v_fma_f32 */
 };
 

@@ -25,6 +25,8 @@
 //   its local derivatives, chains the cotangents to the interpolated fields
 //   and scatters them to the grid nodes (float atomics; the surface vectors
 //   are accumulated in LDS first).
+#include <type_traits>
+
 #include "rt_adjoint.h"
 #include "rt_host.h"
 
@@ -90,8 +92,9 @@ __global__ __launch_bounds__(256) void adj_march(int nsamp, int npix, int plane,
 #pragma unroll
                 for (int c = 0; c < CB; ++c) {
                     const float d = fmaf(-ch.v[c0 + c], q.w, q.z);
-                    const float att = fexp2(-fexp2(fmaf(-d, d, lK)));
-                    I[c] = fmaf(Tr[c] * (1.0f - att), q.x, I[c]);
+                    const float x = fexp2(fmaf(-d, d, lK));
+                    const float att = fexp2(-x);
+                    I[c] = fmaf(Tr[c] * om_select(x, att), q.x, I[c]);
                     Tr[c] *= att;
                 }
             }
@@ -143,16 +146,17 @@ __global__ __launch_bounds__(256) void adj_march(int nsamp, int npix, int plane,
                 const float d = fmaf(-vc, b, a);
                 const float gk = fexp2(-(d * d));
                 const float att = fexp2(-(K * gk));
+                const float om = om_select(K * gk, att);
                 const float t0 = TrK[kk][c];
                 const float t1 = t0 * att;
                 const float smj = S - J[c];
                 // dI/dS = Tr_k (1 - att)  (as a difference of transmissions it
                 // keeps t1 live longer: one occupancy step fewer)
-                cS = fmaf(w[c] * t0, 1.0f - att, cS);
+                cS = fmaf(w[c] * t0, om, cS);
                 // dL/d(dtau) / ln2, with dtau = ln2 K g, g = 2^-d^2
                 const float gg = w[c] * t1 * smj * gk;
-                // J_k-1 = S (1 - att) + att J_k = S - att (S - J_k)
-                J[c] = fmaf(-att, smj, S);
+                // J_k-1 = S (1 - att) + att J_k = J_k + (1 - att)(S - J_k)
+                J[c] = fmaf(om, smj, J[c]);
                 cK += gg;
                 const float gd = gg * Km * d;
                 ca += gd;
@@ -229,18 +233,27 @@ void adj_march_tau(int nsamp, int npix, int plane, int nblk, Channels ch, const 
             const float4 q = qn;
             qn = tape[(size_t)max(k - 1, 0) * npix + pix];
             const float lK = flog2(q.y);
+            // J_k-1 = S (1 - att) + att J_k: as S - att (S - J_k), or on a thin
+            // sample as J_k + (1 - att)(S - J_k) with the series of 1 - att
+            auto channels = [&](auto thin) {
 #pragma unroll
-            for (int c = 0; c < CB; ++c) {
-                const float d = fmaf(-vel(c), q.w, q.z);
-                const float x = fexp2(fmaf(-d, d, lK));
-                // the error of th + x, exact with the larger operand first
-                // (both are >= 0, so their bit patterns order like the values)
-                const float sum = th[c] + x;
-                const unsigned ut = __float_as_uint(th[c]), ux = __float_as_uint(x);
-                tl[c] += __uint_as_float(min(ut, ux)) - (sum - __uint_as_float(max(ut, ux)));
-                th[c] = sum;
-                if (CUBE) J[c] = fmaf(-fexp2(-x), q.x - J[c], q.x);
-            }
+                for (int c = 0; c < CB; ++c) {
+                    const float d = fmaf(-vel(c), q.w, q.z);
+                    const float x = fexp2(fmaf(-d, d, lK));
+                    // the error of th + x, exact with the larger operand first
+                    // (both are >= 0, so their bit patterns order like the values)
+                    const float sum = th[c] + x;
+                    const unsigned ut = __float_as_uint(th[c]), ux = __float_as_uint(x);
+                    tl[c] += __uint_as_float(min(ut, ux)) - (sum - __uint_as_float(max(ut, ux)));
+                    th[c] = sum;
+                    if (CUBE) {
+                        if constexpr (decltype(thin)::value) J[c] = fmaf(om_series3(x), q.x - J[c], J[c]);
+                        else J[c] = fmaf(-fexp2(-x), q.x - J[c], q.x);
+                    }
+                }
+            };
+            if (CUBE && q.y < kThinK) channels(std::true_type{});
+            else channels(std::false_type{});
         }
         // padding channels of the last block read a valid channel's plane and
         // get w = 0
@@ -273,27 +286,40 @@ void adj_march_tau(int nsamp, int npix, int plane, int nblk, Channels ch, const 
         const float lK = flog2(q.y);
         // channel sums in two interleaved halves (shorter dependency chains)
         float cS[2] = {0.0f, 0.0f}, cX[2] = {0.0f, 0.0f}, ca[2] = {0.0f, 0.0f}, cb[2] = {0.0f, 0.0f};
+        // on a thin sample 1 - att comes from its series and J_k-1 =
+        // J_k + (1 - att)(S - J_k); otherwise J_k-1 = S - att (S - J_k)
+        auto channels = [&](auto thin) {
 #pragma unroll
-        for (int c = 0; c < CB; ++c) {
-            const int h = c & 1;
-            const float vc = vel(c);
-            const float d = fmaf(-vc, b, a);
-            const float x = fexp2(fmaf(-d, d, lK));
-            const float att = fexp2(-x);
-            const float smj = S - J[c];
-            const float gg = u[c] * smj * x;
-            J[c] = fmaf(-att, smj, S);
-            const float sum = sh[c] + x;
-            sl[c] += x - (sum - sh[c]);
-            sh[c] = sum;
-            const float u0 = w[c] * fexp2(sum + sl[c]);
-            cS[h] = fmaf(u0, 1.0f - att, cS[h]);
-            cX[h] += gg;
-            const float gd = gg * d;
-            ca[h] += gd;
-            cb[h] = fmaf(-vc, gd, cb[h]);
-            u[c] = u0;
-        }
+            for (int c = 0; c < CB; ++c) {
+                const int h = c & 1;
+                const float vc = vel(c);
+                const float d = fmaf(-vc, b, a);
+                const float x = fexp2(fmaf(-d, d, lK));
+                const float smj = S - J[c];
+                const float gg = u[c] * smj * x;
+                float om;
+                if constexpr (decltype(thin)::value) {
+                    om = om_series3(x);
+                    J[c] = fmaf(om, smj, J[c]);
+                } else {
+                    const float att = fexp2(-x);
+                    om = 1.0f - att;
+                    J[c] = fmaf(-att, smj, S);
+                }
+                const float sum = sh[c] + x;
+                sl[c] += x - (sum - sh[c]);
+                sh[c] = sum;
+                const float u0 = w[c] * fexp2(sum + sl[c]);
+                cS[h] = fmaf(u0, om, cS[h]);
+                cX[h] += gg;
+                const float gd = gg * d;
+                ca[h] += gd;
+                cb[h] = fmaf(-vc, gd, cb[h]);
+                u[c] = u0;
+            }
+        };
+        if (q.y < kThinK) channels(std::true_type{});
+        else channels(std::false_type{});
         const float m = -2.0f * kLn2 * kLn2;
         float4 o = make_float4(cS[0] + cS[1], (cX[0] + cX[1]) * kLn2, (ca[0] + ca[1]) * m, (cb[0] + cb[1]) * m);
         if constexpr (G == 2) {

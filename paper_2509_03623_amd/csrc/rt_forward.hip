@@ -45,24 +45,7 @@ __global__ __launch_bounds__(256) void march_fwd(Geometry g, Shade s, Channels c
             const float t = ((float)k + 0.5f - half) * r.ds;
             const SampleQ sq = shade_sample<NEURAL>(s, ztab, r.px, fmaf(t, r.wy, r.pmy), fmaf(t, r.wz, r.pmz), r.ds,
                                             o_index(s, k, q * g.nx + p));
-            // K 2^-d^2 = 2^(log2 K - d^2): the line-centre depth enters the
-            // exponent, one multiply per channel fewer (K = 0 gives -inf, x = 0)
-            const float lK = flog2(sq.K);
-#pragma unroll
-            for (int c = 0; c < CB; ++c) {
-                const float d = fmaf(-ch.v[c0 + c], sq.b, sq.a);
-                const float x = fexp2(fmaf(-d, d, lK));
-                const float att = fexp2(-x);
-                float om = 1.0f - att;
-                if (THIN) {
-                    // keep the series unconditional so the choice is a select, not a branch
-                    float ser = one_minus_exp2_neg_series(x);
-                    asm volatile("" : "+v"(ser));
-                    om = x < s.thin_thr ? ser : om;
-                }
-                I[c] = fmaf(Tr[c] * om, sq.S, I[c]);
-                Tr[c] *= att;
-            }
+            march_sample<CB, THIN>(I, Tr, sq, [&](int c) { return ch.v[c0 + c]; });
         }
     }
     // compose the sub-chords front to back: pairs, then pairs of pairs, ...

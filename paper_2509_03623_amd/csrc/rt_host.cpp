@@ -45,7 +45,7 @@ rt_status fail_hip(hipError_t e, const char *what) {
 
 // ---------------------------------------------------------------- options
 static int64_t g_opt_cb = 0;
-static int64_t g_opt_thin = 0;
+static int64_t g_opt_thin = 1;
 static int64_t g_opt_ckpt = 0;
 static int64_t g_opt_split = 0;
 static int64_t g_opt_accum = 1;
@@ -334,7 +334,6 @@ rt_status build_launch(const rt_problem *p, Geometry *g, Shade *s) {
     s->sqrt_log2e = (float)std::sqrt(log2e);
     s->vrot = (float)g->si;
     s->vsys = (float)p->spec.v_sys_kms;
-    s->thin_thr = (float)(0.125 * log2e);
     s->zr_max = (float)gr.zr_max;
     s->mlp_o = nullptr;
     s->o_plane = (int64_t)p->cam.nx * p->cam.ny;

@@ -44,7 +44,6 @@ struct Shade {
     float sqrt_log2e;
     float vrot;              // sin i
     float vsys;              // systemic velocity [km/s]
-    float thin_thr;          // dtau (log2 units) below which 1 - e^-dtau uses the series
     float zr_max;            // (z/r) of the top grid row
     const float4 *mlp_o;     // neural CO layer outputs [nsamp][image pixels] (o0, o1, o2, -); NULL = grid surfaces
     int64_t o_plane, o_pix0; // output of sample k, pixel pix of the launch: mlp_o[k o_plane + o_pix0 + pix]
@@ -91,19 +90,20 @@ __device__ __forceinline__ float expm1_pos(float x) {
     return x < 0.5f ? series : direct;
 }
 
-// 1 - 2^-x for small x >= 0 (x in log2 units): series in y = x ln 2 through
-// y^5 (first omitted term y^6/720).
-__device__ __forceinline__ float one_minus_exp2_neg_series(float x) {
-    constexpr float c1 = 0.6931471805599453f;             //  ln2
-    constexpr float c2 = -0.2402265069591007f;            // -ln2^2/2
-    constexpr float c3 = 0.05550410866482158f;            //  ln2^3/6
-    constexpr float c4 = -0.009618129107628477f;          // -ln2^4/24
-    constexpr float c5 = 0.0013333558146428443f;          //  ln2^5/120
-    float p = fmaf(c5, x, c4);
-    p = fmaf(p, x, c3);
-    p = fmaf(p, x, c2);
-    p = fmaf(p, x, c1);
-    return p * x;
+// Optically thin samples.  1 - fl(2^-x) keeps only about ulp(1) / (x ln 2)
+// of its relative precision (at x ln 2 = 1e-4 the fourth digit; below
+// x ~ 1e-7 it is 0), so a sample whose line-centre depth K is below kThinK
+// takes 1 - 2^-x from its series in y = x ln 2 through y^3 for every channel
+// (each channel's x <= K; truncation y^4/24, so at most 1.3e-6 relative at
+// y = 1/32), while thicker samples keep 1 - 2^-x, accurate to 2e-6 relative
+// at the threshold and better above.  The series needs one exp2 fewer per
+// channel than the direct form.
+constexpr float kThinK = 0.04508422002825536f;   // y = 1/32
+__device__ __forceinline__ float om_series3(float x) {
+    constexpr float c1 = 0.6931471805599453f;      //  ln2
+    constexpr float c2 = -0.2402265069591007f;     // -ln2^2/2
+    constexpr float c3 = 0.05550410866482158f;     //  ln2^3/6
+    return fmaf(fmaf(c3, x, c2), x, c1) * x;
 }
 
 // Z(T) by cubic Hermite interpolation of the table in log2 T (tab: the
@@ -333,6 +333,39 @@ __device__ __forceinline__ SampleQ shade_sample(const Shade &s, const float4 *ta
 __device__ __forceinline__ void stage_ztab(const Shade &s, float4 *lds_tab) {
     for (int i = threadIdx.x; i < kZTableNodes - 1; i += blockDim.x) lds_tab[i] = s.ztab[i];
     __syncthreads();
+}
+
+// 1 - 2^-x given att = 2^-x, per channel: the series below kThinK
+__device__ __forceinline__ float om_select(float x, float att) { return x < kThinK ? om_series3(x) : 1.0f - att; }
+
+// One sample of the forward channel loop over CB channels held in registers:
+// d = a - v_c b, x = K 2^-d^2 = 2^(log2 K - d^2), I_c += Tr_c (1 - 2^-x) S,
+// Tr_c *= 2^-x, with the series form on thin samples (THIN; branch per
+// lane).  vel(c) gives channel c's velocity.
+template <int CB, bool THIN, class Vel>
+__device__ __forceinline__ void march_sample(float (&I)[CB], float (&Tr)[CB], const SampleQ &sq, Vel vel) {
+    // K 2^-d^2 = 2^(log2 K - d^2): the line-centre depth enters the exponent
+    // (K = 0 gives -inf, x = 0)
+    const float lK = flog2(sq.K);
+    if (THIN && sq.K < kThinK) {
+#pragma unroll
+        for (int c = 0; c < CB; ++c) {
+            const float d = fmaf(-vel(c), sq.b, sq.a);
+            const float x = fexp2(fmaf(-d, d, lK));
+            const float t = Tr[c] * om_series3(x);
+            I[c] = fmaf(t, sq.S, I[c]);
+            Tr[c] -= t;
+        }
+    } else {
+#pragma unroll
+        for (int c = 0; c < CB; ++c) {
+            const float d = fmaf(-vel(c), sq.b, sq.a);
+            const float x = fexp2(fmaf(-d, d, lK));
+            const float att = fexp2(-x);
+            I[c] = fmaf(Tr[c] * (1.0f - att), sq.S, I[c]);
+            Tr[c] *= att;
+        }
+    }
 }
 
 } // namespace rt

@@ -45,31 +45,23 @@ __global__ __launch_bounds__(256) void micro(int64_t iters, float seed, float *s
 }
 
 // The channel-loop body of the forward march on 32 channels held in
-// registers, driven by a per-iteration sample (a, K) like the real kernel.
+// registers, driven by a per-iteration sample (S, K, a, b) like the real
+// kernel: THIN keeps K below the thin-sample threshold (series form), else
+// above it (1 - 2^-x).
 template <bool THIN>
 __global__ __launch_bounds__(256) void micro_loop(int64_t iters, float seed, float *sink) {
     constexpr int CB = 32;
     float I[CB], Tr[CB];
 #pragma unroll
     for (int c = 0; c < CB; ++c) { I[c] = 0.0f; Tr[c] = 1.0f; }
-    float a = seed * (float)threadIdx.x, b = 1.2f + seed, K = 0.05f + seed, S = 1.0f + seed;
+    SampleQ q;
+    q.a = seed * (float)threadIdx.x;
+    q.b = 1.2f + seed;
+    q.K = THIN ? 0.5f * kThinK : 0.05f + seed;
+    q.S = 1.0f + seed;
     for (int64_t it = 0; it < iters; ++it) {
-        a += 0.001f;
-#pragma unroll
-        for (int c = 0; c < CB; ++c) {
-            const float d = fmaf(-(float)(c - 16) * 0.1f, b, a);
-            const float gk = fexp2(-(d * d));
-            const float x = K * gk;
-            const float att = fexp2(-x);
-            float om = 1.0f - att;
-            if (THIN) {
-                float ser = one_minus_exp2_neg_series(x);
-                asm volatile("" : "+v"(ser));
-                om = x < 0.18f ? ser : om;
-            }
-            I[c] = fmaf(Tr[c] * om, S, I[c]);
-            Tr[c] *= att;
-        }
+        q.a += 0.001f;
+        march_sample<CB, true>(I, Tr, q, [](int c) { return (float)(c - 16) * 0.1f; });
     }
     float s = 0.0f;
 #pragma unroll

@@ -205,15 +205,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CB <= 24 ? 
         for (int k = k0; k < k1; ++k) {
             const float t = ((float)k + 0.5f - half) * ds;
             const SampleQ sq = shade3(s, ztab, pxr, fmaf(t, wy, pmy), fmaf(t, wz, pmz), ds);
-            const float lK = flog2(sq.K);
-#pragma unroll
-            for (int c = 0; c < CB; ++c) {
-                const float d = fmaf(-ch.v[c0 + c], sq.b, sq.a);
-                const float x = fexp2(fmaf(-d, d, lK));
-                const float att = fexp2(-x);
-                I[c] = fmaf(Tr[c] * (1.0f - att), sq.S, I[c]);
-                Tr[c] *= att;
-            }
+            march_sample<CB, true>(I, Tr, sq, [&](int c) { return ch.v[c0 + c]; });
         }
     }
 #pragma unroll

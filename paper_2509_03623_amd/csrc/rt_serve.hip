@@ -69,14 +69,7 @@ __global__ __launch_bounds__(256) void serve_fwd(const ServeDesc *__restrict__ d
                 const float t = ((float)k + 0.5f - half) * r.ds;
                 const SampleQ sq = shade_sample<false>(D.s, ztab, r.px, fmaf(t, r.wy, r.pmy),
                                                        fmaf(t, r.wz, r.pmz), r.ds, 0);
-                const float lK = flog2(sq.K);   // K 2^-d^2 = 2^(log2 K - d^2)
-#pragma unroll
-                for (int c = 0; c < kServeCB; ++c) {
-                    const float d = fmaf(-vc[c], sq.b, sq.a);
-                    const float att = fexp2(-fexp2(fmaf(-d, d, lK)));
-                    I[c] = fmaf(Tr[c] * (1.0f - att), sq.S, I[c]);
-                    Tr[c] *= att;
-                }
+                march_sample<kServeCB, true>(I, Tr, sq, [&](int c) { return vc[c]; });
             }
         }
         // compose the quarters front to back (every lane takes part in the shuffles)
