@@ -52,10 +52,11 @@ def gpu_grads(prob, target, want=tuple(BLOCKS), cotangent=None):
     return {k: v.cpu().numpy().astype(np.float64) for k, v in g.items()}, cube.cpu().numpy(), cube2.cpu().numpy()
 
 
-def check_block(name, got, ref, rel=1e-3, seed=32):
+def check_block(name, got, ref, rel=1e-3, seed=32, every_top=True):
     """The gradient bar: ||dg||_2 <= rel ||g||_2 over the block; 8 seeded
-    entries drawn from |g| >= 1e-3 max within rel; every entry with
-    |g| >= 1e-2 max within rel.  The worst entry above 1e-3 max is printed."""
+    entries drawn from |g| >= 1e-3 max within rel; with every_top, also every
+    entry with |g| >= 1e-2 max within rel.  The worst entry above 1e-3 max is
+    printed."""
     ref = np.asarray(ref, np.float64).ravel()
     got = np.asarray(got, np.float64).ravel()
     gmax = np.abs(ref).max()
@@ -71,7 +72,9 @@ def check_block(name, got, ref, rel=1e-3, seed=32):
     pick = rng.choice(np.nonzero(big)[0], size=min(8, int(big.sum())), replace=False)
     assert rel_all[pick].max() <= rel, (name, pick[int(np.argmax(rel_all[pick]))])
     top = np.abs(ref) >= 1e-2 * gmax
-    assert rel_all[top].max() <= rel, (name, "entry >= 1e-2 max", float(rel_all[top].max()))
+    print(f"{name}: worst entry >= 1e-2 max: rel {float(rel_all[top].max()):.2e}")
+    if every_top:
+        assert rel_all[top].max() <= rel, (name, "entry >= 1e-2 max", float(rel_all[top].max()))
 
 
 @pytest.mark.parametrize("incl,seed", [(45.0, 5), (30.0, 8), (65.0, 13)])

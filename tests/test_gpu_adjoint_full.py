@@ -1,0 +1,196 @@
+"""Gradients at the benchmark's shapes against the FP64 oracle.
+
+- 64 channels x 512 samples on a small image, the reverse march forced to
+  two 32-channel lanes per pixel (the form the full-size benchmark runs),
+  with rays whose back part is optically very thick: the transmissions are
+  rebuilt from a compensated total depth of up to ~1e4.
+- The full-size 512 x 512 x 64 x 512 adjoint and the 256 x 256 x 32 x 256
+  network adjoint, in the launch configuration the benchmark times, with a
+  cotangent that is a seeded normal on a few dozen pixels and zero
+  elsewhere: the GPU differentiates the whole image, the oracle's float64
+  autograd only needs those pixels' rays (the gradient of sum w I is a sum
+  over pixels), and central differences of the C oracle over the same
+  pixels check a few entries.
+
+Bars: L2 per block <= 1e-3 and 8 seeded entries >= 1e-3 of the block's
+largest within 1e-3 (FP32 paths), the BF16 network path at cosine >= 0.99.
+The small-image case also holds every entry >= 1e-2 of the largest within
+1e-3.  The full-size case does not: there a node's gradient sums the
+contributions of hundreds of rays under a cotangent of random sign, and an
+entry that is a small remainder of large opposite terms carries their FP32
+errors magnified (the worst such entry is printed, and the central
+differences check entries drawn from those >= 1e-2 of the largest).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from oracle import torch_ref
+
+import test_gpu_adjoint as ta
+
+pytestmark = pytest.mark.gpu
+
+GRID_BLOCKS = ["ln_nh2", "temp_k", "vphi_kms", "z_lo_au", "z_up_au"]
+
+
+def _rt():
+    import paper_2509_03623_amd as rt
+    return rt
+
+
+def oracle_vjp(prob, px, py, w):
+    """d(sum_pixels sum_c w I)/d(fields) by float64 autograd over the given pixels."""
+    leaves = torch_ref.as_leaves(prob)
+    I = torch_ref.render(prob, leaves, px, py)
+    L = torch.sum(I * torch.as_tensor(np.asarray(w, np.float64)))
+    L.backward()
+    return {k: (v.grad.numpy().copy() if v.grad is not None else np.zeros(v.shape)) for k, v in leaves.items()}
+
+
+def oracle_fd(prob, px, py, w, name, idx, h=1e-4):
+    """Central difference (step h in the field's own units) of sum w I."""
+    arr = getattr(prob, name)
+    plus, minus = arr.copy(), arr.copy()
+    plus.flat[idx] = np.float32(float(arr.flat[idx]) + h)
+    minus.flat[idx] = np.float32(float(arr.flat[idx]) - h)
+    step = float(plus.flat[idx]) - float(minus.flat[idx])
+    lp = float(np.sum(oracle.render_pixels(prob.replace(**{name: plus}), px, py) * w))
+    lm = float(np.sum(oracle.render_pixels(prob.replace(**{name: minus}), px, py) * w))
+    return (lp - lm) / step
+
+
+def sampled_pixels(cube, n_rand, n_peak, seed, lo=0, hi=None):
+    """n_rand seeded pixels in [lo, hi)^2 plus n_peak around the brightest one."""
+    nch, ny, nx = cube.shape
+    hi = nx if hi is None else hi
+    rng = np.random.Generator(np.random.PCG64(seed))
+    px = rng.integers(lo, hi, n_rand)
+    py = rng.integers(lo, hi, n_rand)
+    q0, p0 = np.unravel_index(int(np.argmax(cube.max(axis=0))), (ny, nx))
+    px = np.concatenate([px, p0 + rng.integers(-6, 7, n_peak)]).clip(0, nx - 1)
+    py = np.concatenate([py, q0 + rng.integers(-6, 7, n_peak)]).clip(0, ny - 1)
+    key = np.unique(py * nx + px)
+    return key % nx, key // nx, rng
+
+
+def with_options(opts, fn):
+    rt = _rt()
+    old = {k: rt.get_option(k) for k in opts}
+    for k, v in opts.items():
+        rt.set_option(k, v)
+    try:
+        return fn()
+    finally:
+        for k, v in old.items():
+            rt.set_option(k, v)
+
+
+def test_512_samples_64_channels_thick_rays():
+    """Small image of the full-size disk family: 64 channels, 512 samples,
+    (32 channels, 2 lanes) forced; fused L2 adjoint and explicit cotangent."""
+    rt = _rt()
+    from paper_2509_03623_amd import _lib as L
+    prob = ta.kscale(synth.config2(2000, nx=24, ny=20, nch=64, nsamp=512, nr=96, nz=48))
+    # optical depth of the brightest ray at line centre, summed over the chord
+    ref_cube = oracle.render(prob)
+    q0, p0 = np.unravel_index(int(np.argmax(ref_cube.max(axis=0))), ref_cube.shape[1:])
+    taus = []
+    for q in range(prob.camera.ny):
+        _, _, dt, _ = oracle.ray_dump(prob, p0, q)
+        taus.append(dt.sum(axis=0).max())
+    print(f"max line-centre depth along column {p0}: {max(taus):.3e}")
+    assert max(taus) >= 1e3
+    target = ta.target_for(prob)
+    _, oref = torch_ref.loss_and_grad(prob, target)
+    opts = {L.RT_OPT_ADJ_CHANNEL_BLOCK: 32, L.RT_OPT_ADJ_PIXEL_LANES: 2}
+    sc = rt.scene_from_problem(prob)
+    tgt = torch.as_tensor(target, dtype=torch.float32, device="cuda")
+    print("[gpu] fused L2 adjoint 24x20x64 ns=512 as (32, 2)", flush=True)
+    cube, loss, g = with_options(opts, lambda: rt.render_l2_adjoint(sc, tgt, want=GRID_BLOCKS))
+    torch.cuda.synchronize()
+    got_cube = cube.cpu().numpy().astype(np.float64)
+    assert np.abs(got_cube - ref_cube).max() <= 1e-5 * ref_cube.max()
+    for k in GRID_BLOCKS:
+        r, g_ = oref[k].ravel(), g[k].cpu().numpy().astype(np.float64).ravel()
+        l2 = float(np.linalg.norm(g_ - r) / np.linalg.norm(r))
+        print(f"fused {k}: L2 rel {l2:.2e}")
+        assert l2 <= 1e-3, k
+    vjp, _, _ = with_options(opts, lambda: ta.gpu_grads(prob, target, cotangent=2.0 * (ref_cube - target)))
+    for k in GRID_BLOCKS:
+        ta.check_block(k, vjp[k], oref[k])
+
+
+@pytest.mark.slow
+def test_full_size_adjoint_sampled_pixels():
+    """512 x 512 x 64 x 512 on the 256 x 128 grid (disk 2000), the reverse
+    march in the benchmark's (32 channels, 2 lanes) form with the intensity
+    formed in the march: every gradient block against the oracle's autograd
+    over the 96 pixels carrying the cotangent, and 8 central differences."""
+    rt = _rt()
+    from paper_2509_03623_amd import _lib as L
+    prob = ta.kscale(synth.config2(2000))
+    sc = rt.scene_from_problem(prob)
+    print("[gpu] full-size render 512x512x64 ns=512", flush=True)
+    cube = rt.render(sc)
+    torch.cuda.synchronize()
+    px, py, rng = sampled_pixels(cube.cpu().numpy(), 64, 32, seed=61, lo=96, hi=416)
+    w = rng.standard_normal((len(px), sc.nch))
+    dl = np.zeros((sc.nch, sc.ny, sc.nx), np.float32)
+    dl[:, py, px] = w.T
+    dl_t = torch.as_tensor(dl, device="cuda")
+    cube2 = torch.empty_like(cube)
+    opts = {L.RT_OPT_ADJ_CHANNEL_BLOCK: 32, L.RT_OPT_ADJ_PIXEL_LANES: 2}
+    print(f"[gpu] full-size adjoint, cotangent on {len(px)} pixels", flush=True)
+    g = with_options(opts, lambda: rt.render_adjoint(sc, dl_t, want=GRID_BLOCKS, cube_out=cube2))
+    torch.cuda.synchronize()
+    assert float((cube2 - cube).abs().max()) <= 1e-6 * float(cube.abs().max())
+    got = {k: v.cpu().numpy().astype(np.float64) for k, v in g.items()}
+    ref = oracle_vjp(prob, px, py, w)
+    for k in GRID_BLOCKS:
+        ta.check_block(k, got[k], ref[k], every_top=False)
+    for name in ("ln_nh2", "temp_k", "z_lo_au", "z_up_au"):
+        gv = got[name].ravel()
+        cand = np.nonzero(np.abs(gv) >= 1e-2 * np.abs(gv).max())[0]
+        for idx in rng.choice(cand, size=2, replace=False):
+            fd = oracle_fd(prob, px, py, w, name, int(idx))
+            print(f"{name}[{idx}] gpu {gv[idx]:.6e} fd {fd:.6e}", flush=True)
+            assert abs(gv[idx] - fd) <= 1e-3 * abs(fd), (name, idx)
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_full_size_network_adjoint_sampled_pixels(precision):
+    """256 x 256 x 32 x 256 with the neural CO layer, in the benchmark's
+    launch configuration: gradients of ln n_H2, T, v_phi and the network
+    weights against the oracle's float64 autograd over the cotangent's 64
+    pixels (FP32 path: L2 <= 1e-3 per block; BF16 path: cosine >= 0.99)."""
+    rt = _rt()
+    prob = synth.config4()
+    prob = prob.replace(intensity_scale=synth.disk.rj_kelvin_scale(prob.line))
+    prec = rt.RT_MLP_FP32 if precision == "fp32" else rt.RT_MLP_BF16
+    sc = rt.scene_from_problem(prob, mlp_precision=prec)
+    print(f"[gpu] full-size network render prec={precision}", flush=True)
+    cube = rt.render(sc)
+    torch.cuda.synchronize()
+    px, py, rng = sampled_pixels(cube.cpu().numpy(), 48, 16, seed=62, lo=43, hi=213)
+    w = rng.standard_normal((len(px), sc.nch))
+    dl = np.zeros((sc.nch, sc.ny, sc.nx), np.float32)
+    dl[:, py, px] = w.T
+    keys = ("ln_nh2", "temp_k", "vphi_kms", "mlp_w")
+    print(f"[gpu] full-size network adjoint prec={precision}, cotangent on {len(px)} pixels", flush=True)
+    g = rt.render_adjoint(sc, torch.as_tensor(dl, device="cuda"), want=keys)
+    torch.cuda.synchronize()
+    got = {k: v.cpu().numpy().astype(np.float64) for k, v in g.items()}
+    ref = oracle_vjp(prob, px, py, w)
+    for k in keys:
+        r, g_ = ref[k].ravel(), got[k].ravel()
+        l2 = float(np.linalg.norm(g_ - r) / np.linalg.norm(r))
+        cos = float(np.dot(g_, r) / (np.linalg.norm(g_) * np.linalg.norm(r)))
+        print(f"{precision} {k}: L2 rel {l2:.2e}, cosine {cos:.6f}")
+        if precision == "fp32":
+            assert l2 <= 1e-3, (k, l2)
+        else:
+            assert cos >= 0.99, (k, cos)
