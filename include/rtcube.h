@@ -170,6 +170,24 @@ rt_status rt_render_cube_adjoint(const rt_problem *p, const float *dl_dcube, con
 rt_status rt_render_cube_l2_adjoint(const rt_problem *p, const float *target, const rt_grads *g, float *cube,
                                     double *loss, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * as rt_render_cube_l2_adjoint for grid fields (no network), but it calls no
+ * allocator.  The library's scratch for the call (partition-function table,
+ * FP64 gradient accumulators, the sample tape and cotangents of one band of
+ * image rows; the image is processed band by band) lives in one fixed device
+ * array of rt_noalloc_scratch_bytes() bytes (256 MiB) per GPU, held until
+ * the process ends.  Every call on a GPU shares that GPU's array: calls that
+ * overlap on one GPU (different streams or threads) race and must be
+ * serialised by the caller.  Each call clears what must start at zero.
+ * Returns RT_ETOOBIG, before any GPU work, when the table, the accumulators
+ * and one row of pixels do not fit the array; RT_EINVAL for a network
+ * problem, more than 256 channels or NULL target / cube / grads. */
+rt_status rt_render_cube_l2_adjoint_noalloc(const rt_problem *p, const float *target, const rt_grads *g,
+                                            float *cube, double *loss, void *stream);
+/* Size in bytes of the fixed array rt_render_cube_l2_adjoint_noalloc uses. */
+uint64_t rt_noalloc_scratch_bytes(void);
+
 /* ------------------------------------------------------- derived fields */
 /* Fields derived from a temperature grid, as the physics-informed
  * constraints of Methods > Neural temperature recovery derive them (equations

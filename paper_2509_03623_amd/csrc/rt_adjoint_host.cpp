@@ -67,20 +67,45 @@ size_t adjoint_bytes_per_pixel(int nch, long npix, int nsamp, bool cube) {
 }
 
 
+static size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
+// layout of a FixedScratch: partition table, accumulators, band scratch
+static size_t fixed_table_bytes() { return align256(sizeof(float4) * (kZTableNodes - 1)); }
+static size_t fixed_acc_bytes(const rt_problem *p) {
+    const size_t nn = (size_t)p->grid.nr * p->grid.nz, nr = (size_t)p->grid.nr;
+    return align256(sizeof(double) * (3 * nn + 2 * nr));
+}
+
+size_t fixed_scratch_min_bytes(const rt_problem *p) {
+    const size_t row = adjoint_bytes_per_pixel(p->spec.nch, (long)p->cam.nx * p->cam.ny, p->nsamp, true) *
+                       (size_t)p->cam.nx;
+    return fixed_table_bytes() + fixed_acc_bytes(p) + row;
+}
+
 rt_status adjoint_core(const rt_problem *p, const float *dl, const rt_grads *g, float *cube_opt, hipStream_t st,
-                       const float4 *mlp_o, float4 *dO, const float *target) {
+                       const float4 *mlp_o, float4 *dO, const float *target, const FixedScratch *fx) {
     Geometry geo;
     Shade sh;
-    rt_status rs = build_launch(p, &geo, &sh);
+    hipError_t e;
+    const float4 *ztab = nullptr;
+    if (fx) {
+        // the partition table goes to the head of the fixed region
+        float4 tab[kZTableNodes - 1];
+        partition_table_host(p->line, tab);
+        e = hipMemcpyAsync(fx->base, tab, sizeof tab, hipMemcpyHostToDevice, st);
+        if (e != hipSuccess) return fail_hip(e, "partition table upload");
+        ztab = (const float4 *)fx->base;
+    }
+    rt_status rs = build_launch(p, &geo, &sh, ztab);
     if (rs != RT_OK) return rs;
     sh.mlp_o = mlp_o;
     const int npix = p->cam.nx * p->cam.ny;
     const int ns = p->nsamp;
     const size_t nn = (size_t)p->grid.nr * p->grid.nz, nr = (size_t)p->grid.nr;
-    hipError_t e;
     // gradients accumulate in double, then overwrite the caller's float outputs
     const size_t acc_n = 3 * nn + 2 * nr;
-    double *ab = (double *)stream_workspace(st, kWsGradAcc, sizeof(double) * acc_n, &e);
+    double *ab = fx ? (double *)(fx->base + fixed_table_bytes())
+                    : (double *)stream_workspace(st, kWsGradAcc, sizeof(double) * acc_n, &e);
     if (!ab) return fail_hip(e, "gradient accumulators");
     if ((e = zero_async_d(ab, acc_n, st)) != hipSuccess) return fail_hip(e, "zero");
     GradAcc go{g->d_ln_nh2 ? ab : nullptr, g->d_temp_k ? ab + nn : nullptr, g->d_vphi_kms ? ab + 2 * nn : nullptr,
@@ -95,7 +120,11 @@ rt_status adjoint_core(const rt_problem *p, const float *dl, const rt_grads *g, 
     const size_t row_bytes = adjoint_bytes_per_pixel(p->spec.nch, (long)nx * ny, ns, cube) * (size_t)nx;
     // (as few bands as the cap allows, of equal height: a thin last band
     // would march its full rays on too few lanes)
-    const int band_max = (int)std::max<size_t>(1, std::min<size_t>((size_t)ny, adjoint_scratch_cap() / row_bytes));
+    const size_t fx_band = fx ? fx->bytes - fixed_table_bytes() - fixed_acc_bytes(p) : 0;
+    if (fx && fx->bytes < fixed_scratch_min_bytes(p))
+        return fail(RT_ETOOBIG, "one row of adjoint scratch does not fit the fixed region");
+    const size_t cap = fx ? fx_band : adjoint_scratch_cap();
+    const int band_max = (int)std::max<size_t>(1, std::min<size_t>((size_t)ny, cap / row_bytes));
     const int nband = (ny + band_max - 1) / band_max;
     const int band = (ny + nband - 1) / nband;
     const bool lds = grad_accum_double() && chain_lds_fits(p->grid.nr, p->grid.nz);
@@ -118,7 +147,8 @@ rt_status adjoint_core(const rt_problem *p, const float *dl, const rt_grads *g, 
             const size_t rays_b = sizeof(float4) * (size_t)bpix;
             const size_t ckpt_b = sizeof(float) * (size_t)nseg * nblk * cb * bpix;
             const size_t cot_b = sizeof(float4) * (size_t)nblk * ns * bpix;
-            char *base = (char *)stream_workspace(st, kWsAdjoint, tape_b + rays_b + ckpt_b + cot_b, &e);
+            char *base = fx ? fx->base + fixed_table_bytes() + fixed_acc_bytes(p)
+                            : (char *)stream_workspace(st, kWsAdjoint, tape_b + rays_b + ckpt_b + cot_b, &e);
             if (!base) return fail_hip(e, "adjoint scratch");
             float4 *tape = (float4 *)base;
             float4 *rays = (float4 *)(base + tape_b);

@@ -237,18 +237,7 @@ void release_stream_workspaces(hipStream_t st) {
     }
 }
 
-rt_status partition_table(const rt_line &l, const float4 **out) {
-    int dev = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e != hipSuccess) return fail_hip(e, "hipGetDevice");
-    keep_pool(dev);
-    uint64_t h = 1469598103934665603ull;
-    h = fnv(h, &l.nlev, sizeof l.nlev);
-    h = fnv(h, l.lev_e_k, sizeof(double) * l.nlev);
-    h = fnv(h, l.lev_g, sizeof(double) * l.nlev);
-    std::lock_guard<std::mutex> lk(g_ztab_mu);
-    auto it = g_ztab.find({dev, h});
-    if (it != g_ztab.end()) { *out = it->second; return RT_OK; }
+void partition_table_host(const rt_line &l, float4 *tab) {
     const int N = kZTableNodes;
     const double l0 = std::log2(kZT0), l1 = std::log2(kZT1), step = (l1 - l0) / (N - 1);
     std::vector<double> z(N), dz(N);
@@ -263,9 +252,25 @@ rt_status partition_table(const rt_line &l, const float4 **out) {
         z[i] = s;
         dz[i] = d * std::log(2.0) * step;   // dZ/d(table index)
     }
-    std::vector<float4> tab(N - 1);
     for (int i = 0; i < N - 1; ++i)
         tab[i] = make_float4((float)z[i], (float)dz[i], (float)z[i + 1], (float)dz[i + 1]);
+}
+
+rt_status partition_table(const rt_line &l, const float4 **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail_hip(e, "hipGetDevice");
+    keep_pool(dev);
+    uint64_t h = 1469598103934665603ull;
+    h = fnv(h, &l.nlev, sizeof l.nlev);
+    h = fnv(h, l.lev_e_k, sizeof(double) * l.nlev);
+    h = fnv(h, l.lev_g, sizeof(double) * l.nlev);
+    std::lock_guard<std::mutex> lk(g_ztab_mu);
+    auto it = g_ztab.find({dev, h});
+    if (it != g_ztab.end()) { *out = it->second; return RT_OK; }
+    const int N = kZTableNodes;
+    std::vector<float4> tab(N - 1);
+    partition_table_host(l, tab.data());
     float4 *d = nullptr;
     e = hipMalloc(&d, sizeof(float4) * (N - 1));
     if (e != hipSuccess) return fail_hip(e, "hipMalloc(partition table)");
@@ -277,7 +282,7 @@ rt_status partition_table(const rt_line &l, const float4 **out) {
 }
 
 // ---------------------------------------------------------------- set-up
-rt_status build_launch(const rt_problem *p, Geometry *g, Shade *s) {
+rt_status build_launch(const rt_problem *p, Geometry *g, Shade *s, const float4 *ztab) {
     const rt_grid &gr = p->grid;
     const double dln = std::log(gr.r_max_au / gr.r_min_au) / (gr.nr - 1);
     const double dzr = gr.zr_max / (gr.nz - 1);
@@ -300,9 +305,11 @@ rt_status build_launch(const rt_problem *p, Geometry *g, Shade *s) {
 
     std::memset(s, 0, sizeof *s);
     const rt_line &l = p->line;
-    const float4 *tab = nullptr;
-    rt_status st = partition_table(l, &tab);
-    if (st != RT_OK) return st;
+    const float4 *tab = ztab;
+    if (!tab) {
+        rt_status st = partition_table(l, &tab);
+        if (st != RT_OK) return st;
+    }
     s->ln_n = p->f.ln_nh2;
     s->temp = p->f.temp_k;
     s->vphi = p->f.vphi_kms;

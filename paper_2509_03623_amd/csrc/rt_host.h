@@ -14,7 +14,11 @@ rt_status validate_view(const rt_line &l, const rt_camera &c, const rt_spectral 
                         double intensity_scale, double max_incl_deg);
 // Z(T) table of the line's levels on the current device (built once per level set)
 rt_status partition_table(const rt_line &l, const float4 **out);
-rt_status build_launch(const rt_problem *p, Geometry *g, Shade *s);
+// the same table on the host: tab[kZTableNodes - 1]
+void partition_table_host(const rt_line &l, float4 *tab);
+// launch constants of a problem; ztab: a partition table already on the
+// device (NULL: the library's cached table of the line)
+rt_status build_launch(const rt_problem *p, Geometry *g, Shade *s, const float4 *ztab = nullptr);
 int channel_block_for(int nch, long npix);
 void forward_shape(int nch, long npix, int nsamp, int *cb, int *nsplit);
 // channels per lane, lanes per pixel and samples per checkpoint segment (0:
@@ -52,8 +56,19 @@ rt_status march_cube(const rt_problem *p, const Geometry &g, const Shade &s, flo
 // dl = dL/dcube; or dl == NULL and target != NULL: the cotangent of the L2
 // loss sum (cube - target)^2, formed inside the reverse march from its own
 // forward sweep (cube_opt then receives the cube)
+// A fixed device region that replaces the library's allocations in an
+// adjoint call: the partition table, the gradient accumulators and the band
+// scratch are carved from it, and the image is processed in bands of rows
+// whose scratch fits what is left.
+struct FixedScratch {
+    char *base;
+    size_t bytes;
+};
+// bytes a FixedScratch must hold at least: table, accumulators and one row
+size_t fixed_scratch_min_bytes(const rt_problem *p);
 rt_status adjoint_core(const rt_problem *p, const float *dl, const rt_grads *g, float *cube_opt, hipStream_t st,
-                       const float4 *mlp_o, float4 *dO, const float *target = nullptr);
+                       const float4 *mlp_o, float4 *dO, const float *target = nullptr,
+                       const FixedScratch *fx = nullptr);
 rt_status adjoint_mlp(const rt_problem *p, const float *dl, const rt_grads *g, float *cube_opt, hipStream_t st,
                       const float *target = nullptr);
 rt_status adjoint_grid(const rt_problem *p, const float *dl, const rt_grads *g, float *cube_opt, hipStream_t st,

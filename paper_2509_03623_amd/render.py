@@ -227,27 +227,37 @@ def render_adjoint(sc: Scene, dl_dcube: torch.Tensor, want=GRAD_KEYS, cube_out: 
 
 
 def render_l2_adjoint(sc: Scene, target: torch.Tensor, want=GRAD_KEYS, cube_out: Optional[torch.Tensor] = None,
-                      stream=None, fields=None):
+                      stream=None, fields=None, loss_out: Optional[torch.Tensor] = None, grads_out=None,
+                      noalloc: bool = False):
     """Forward + L2 loss + adjoint in one pass: (cube, loss, gradients) of
-    L = sum (cube - target)^2; loss is a one-element float64 device tensor."""
+    L = sum (cube - target)^2; loss is a one-element float64 device tensor.
+    With noalloc the library call allocates nothing (rt_render_cube_l2_
+    adjoint_noalloc: grid fields only); pass cube_out, loss_out and grads_out
+    (name -> tensor) to keep this function from allocating the outputs."""
     dev = sc.ln_nh2.device
     tgt = target.contiguous().to(torch.float32)
     if tgt.shape != (sc.nch, sc.ny, sc.nx):
         raise ValueError("target has the wrong shape")
     cube = torch.empty(sc.nch, sc.ny, sc.nx, dtype=torch.float32, device=dev) if cube_out is None else cube_out
-    loss = torch.empty(1, dtype=torch.float64, device=dev)
+    loss = torch.empty(1, dtype=torch.float64, device=dev) if loss_out is None else loss_out
     shapes = dict(ln_nh2=(sc.nr, sc.nz), temp_k=(sc.nr, sc.nz), vphi_kms=(sc.nr, sc.nz), z_lo_au=(sc.nr,),
                   z_up_au=(sc.nr,), mlp_w=(L.RT_MLP_PARAMS,))
     out = {}
-    for k in want:
-        if k == "mlp_w" and sc.mlp_w is None:
-            continue
-        out[k] = torch.empty(shapes[k], dtype=torch.float32, device=dev)
+    if grads_out is not None:
+        out = dict(grads_out)
+    else:
+        for k in want:
+            if k == "mlp_w" and sc.mlp_w is None:
+                continue
+            out[k] = torch.empty(shapes[k], dtype=torch.float32, device=dev)
+    for k, v in out.items():
+        if tuple(v.shape) != shapes[k] or v.dtype != torch.float32 or not v.is_contiguous():
+            raise ValueError(f"gradient output {k} must be a contiguous float32 tensor of shape {shapes[k]}")
     g = L.rt_grads(_fptr(out.get("ln_nh2")), _fptr(out.get("temp_k")), _fptr(out.get("vphi_kms")),
                    _fptr(out.get("z_lo_au")), _fptr(out.get("z_up_au")), _fptr(out.get("mlp_w")))
     p, keep = problem_struct(sc, fields)
-    L.check(L.lib().rt_render_cube_l2_adjoint(C.byref(p), _fptr(tgt), C.byref(g), _fptr(cube), loss.data_ptr(),
-                                              C.c_void_p(_stream(stream))))
+    fn = L.lib().rt_render_cube_l2_adjoint_noalloc if noalloc else L.lib().rt_render_cube_l2_adjoint
+    L.check(fn(C.byref(p), _fptr(tgt), C.byref(g), _fptr(cube), loss.data_ptr(), C.c_void_p(_stream(stream))))
     del keep
     return cube, loss, out
 
