@@ -28,6 +28,7 @@
 #include <type_traits>
 
 #include "rt_adjoint.h"
+#include "rt_adjoint_dev.h"
 #include "rt_host.h"
 
 namespace rt {
@@ -41,23 +42,9 @@ __global__ __launch_bounds__(256) void adj_tape(Geometry g, Shade s, float4 *__r
     const int npix = g.nx * g.ny;
     const int pix = blockIdx.x * 256 + threadIdx.x;
     if (pix >= npix) return;
-    const RaySetup r = ray_setup(g, pix % g.nx, pix / g.nx);
-    if (blockIdx.y == 0) rays[pix] = make_float4(r.px, r.pmy, r.pmz, r.live ? r.ds : 0.0f);
-    const float half = 0.5f * (float)g.nsamp;
     const int len = (g.nsamp + gridDim.y - 1) / gridDim.y;
     const int k0 = blockIdx.y * len, k1 = min(g.nsamp, k0 + len);
-    for (int k = k0; k < k1; ++k) {
-        float4 o = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        if (r.live) {
-            const float t = ((float)k + 0.5f - half) * r.ds;
-            const SampleQ q = s.mlp_o ? shade_sample<true>(s, ztab, r.px, fmaf(t, r.wy, r.pmy), fmaf(t, r.wz, r.pmz),
-                                                           r.ds, o_index(s, k, pix))
-                                      : shade_sample<false>(s, ztab, r.px, fmaf(t, r.wy, r.pmy), fmaf(t, r.wz, r.pmz), r.ds,
-                                                            0);
-            o = make_float4(q.S, q.K, q.a, q.b);
-        }
-        tape[(size_t)k * npix + pix] = o;
-    }
+    tape_pixel(g, s, ztab, pix, k0, k1, blockIdx.y == 0, tape, rays);
 }
 
 // dl_dcube: the cotangent dL/dI; or, with target != NULL, the cotangent of
@@ -182,10 +169,6 @@ __global__ __launch_bounds__(256) void adj_march(int nsamp, int npix, int plane,
 // where the running sum (minus the prefix depth plus x) is never the smaller
 // operand, so after sample k the pair holds minus the prefix depth of k to
 // within one rounding of the prefix itself.
-// value of the other lane of an adjacent pair (DPP quad permutation 1,0,3,2)
-__device__ __forceinline__ float swap_pair(float x) {
-    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0xB1, 0xF, 0xF, false));
-}
 
 // Work items: G adjacent lanes per pixel, each with CB channels (G = 2: the
 // pair's channel sums are added across the two lanes, so one cotangent slice
@@ -216,120 +199,7 @@ void adj_march_tau(int nsamp, int npix, int plane, int nblk, Channels ch, const 
         if constexpr (G > 1) return vv[c];
         else return ch.v[c0 + c];
     };
-    float th[CB], tl[CB], w[CB];
-    {
-        // sweep 1, back to front: total depth and (CUBE) J, which reaches I
-        float J[CB];
-#pragma unroll
-        for (int c = 0; c < CB; ++c) {
-            th[c] = 0.0f;
-            tl[c] = 0.0f;
-            J[c] = 0.0f;
-        }
-        // the next sample's tape entry is loaded one iteration ahead
-        float4 qn = tape[(size_t)(nsamp - 1) * npix + pix];
-#pragma unroll 1
-        for (int k = nsamp - 1; k >= 0; --k) {
-            const float4 q = qn;
-            qn = tape[(size_t)max(k - 1, 0) * npix + pix];
-            const float lK = flog2(q.y);
-            // J_k-1 = S (1 - att) + att J_k: as S - att (S - J_k), or on a thin
-            // sample as J_k + (1 - att)(S - J_k) with the series of 1 - att
-            auto channels = [&](auto thin) {
-#pragma unroll
-                for (int c = 0; c < CB; ++c) {
-                    const float d = fmaf(-vel(c), q.w, q.z);
-                    const float x = fexp2(fmaf(-d, d, lK));
-                    // the error of th + x, exact with the larger operand first
-                    // (both are >= 0, so their bit patterns order like the values)
-                    const float sum = th[c] + x;
-                    const unsigned ut = __float_as_uint(th[c]), ux = __float_as_uint(x);
-                    tl[c] += __uint_as_float(min(ut, ux)) - (sum - __uint_as_float(max(ut, ux)));
-                    th[c] = sum;
-                    if (CUBE) {
-                        if constexpr (decltype(thin)::value) J[c] = fmaf(om_series3(x), q.x - J[c], J[c]);
-                        else J[c] = fmaf(-fexp2(-x), q.x - J[c], q.x);
-                    }
-                }
-            };
-            if (CUBE && q.y < kThinK) channels(std::true_type{});
-            else channels(std::false_type{});
-        }
-        // padding channels of the last block read a valid channel's plane and
-        // get w = 0
-#pragma unroll
-        for (int c = 0; c < CB; ++c) {
-            const bool valid = c0 + c < ch.n;
-            const size_t i = (size_t)min(c0 + c, ch.n - 1) * plane + pix;
-            if (CUBE && cube_out && valid) cube_out[i] = J[c];
-            const float wc = CUBE && target ? 2.0f * (J[c] - target[i]) : dl_dcube[i];
-            w[c] = valid ? wc : 0.0f;
-        }
-    }
-    // sweep 2, back to front: (sh, sl) = -(prefix depth) in front of the
-    // current sample; u = w Tr
-    float J[CB], u[CB];
-    float *const sh = th, *const sl = tl;
-#pragma unroll
-    for (int c = 0; c < CB; ++c) {
-        sh[c] = -th[c];
-        sl[c] = -tl[c];
-        J[c] = 0.0f;
-        u[c] = w[c] * fexp2(sh[c] + sl[c]);
-    }
-    float4 qn = tape[(size_t)(nsamp - 1) * npix + pix];
-#pragma unroll 1
-    for (int k = nsamp - 1; k >= 0; --k) {
-        const float4 q = qn;
-        qn = tape[(size_t)max(k - 1, 0) * npix + pix];
-        const float S = q.x, a = q.z, b = q.w;
-        const float lK = flog2(q.y);
-        // channel sums in two interleaved halves (shorter dependency chains)
-        float cS[2] = {0.0f, 0.0f}, cX[2] = {0.0f, 0.0f}, ca[2] = {0.0f, 0.0f}, cb[2] = {0.0f, 0.0f};
-        // on a thin sample 1 - att comes from its series and J_k-1 =
-        // J_k + (1 - att)(S - J_k); otherwise J_k-1 = S - att (S - J_k)
-        auto channels = [&](auto thin) {
-#pragma unroll
-            for (int c = 0; c < CB; ++c) {
-                const int h = c & 1;
-                const float vc = vel(c);
-                const float d = fmaf(-vc, b, a);
-                const float x = fexp2(fmaf(-d, d, lK));
-                const float smj = S - J[c];
-                const float gg = u[c] * smj * x;
-                float om;
-                if constexpr (decltype(thin)::value) {
-                    om = om_series3(x);
-                    J[c] = fmaf(om, smj, J[c]);
-                } else {
-                    const float att = fexp2(-x);
-                    om = 1.0f - att;
-                    J[c] = fmaf(-att, smj, S);
-                }
-                const float sum = sh[c] + x;
-                sl[c] += x - (sum - sh[c]);
-                sh[c] = sum;
-                const float u0 = w[c] * fexp2(sum + sl[c]);
-                cS[h] = fmaf(u0, om, cS[h]);
-                cX[h] += gg;
-                const float gd = gg * d;
-                ca[h] += gd;
-                cb[h] = fmaf(-vc, gd, cb[h]);
-                u[c] = u0;
-            }
-        };
-        if (q.y < kThinK) channels(std::true_type{});
-        else channels(std::false_type{});
-        const float m = -2.0f * kLn2 * kLn2;
-        float4 o = make_float4(cS[0] + cS[1], (cX[0] + cX[1]) * kLn2, (ca[0] + ca[1]) * m, (cb[0] + cb[1]) * m);
-        if constexpr (G == 2) {
-            o.x += swap_pair(o.x);
-            o.y += swap_pair(o.y);
-            o.z += swap_pair(o.z);
-            o.w += swap_pair(o.w);
-        }
-        if (g == 0) cot[((size_t)blk * nsamp + k) * npix + pix] = o;
-    }
+    march_tau_pixel<CB, G, CUBE>(pix, blk, g, c0, ch.n, nsamp, npix, plane, vel, tape, dl_dcube, target, cot, cube_out);
 }
 
 
@@ -369,53 +239,18 @@ __global__ __launch_bounds__(256) void adj_chain(Geometry g, Shade s, const floa
         }
         float4 dout = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         if (r.w > 0.0f && (c.x != 0.0f || c.y != 0.0f || c.z != 0.0f || c.w != 0.0f)) {
-            const float ds = r.w;
-            const float t = ((float)k + 0.5f - 0.5f * (float)g.nsamp) * ds;
-            const float wy = (float)g.si, wz = (float)(-g.ci);
-            const float py = fmaf(t, wy, r.y), pz = fmaf(t, wz, r.z);
-            const Locus L = locate(s, r.x, py, pz);
-            Fields F = fetch(s, L);
-            float4 o = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-            float tfac = 1.0f, t_grid = F.T;
-            if (s.mlp_o) {
-                o = s.mlp_o[o_index(s, k, pix)];
-                apply_mlp(s, F, L, o);
-                tfac = F.T / t_grid;
-            }
-            PhysTape tp;
-            const SampleQ q = physics<true>(s, ztab, L, F, r.x, ds, &tp);
-            const float gS = c.x, gK = c.y, ga = c.z, gb = c.w;
-            const float gKK = gK;  // dL/d ln K, and d ln K / d ln n = 1
-            const float dlnK_dT = tp.rT * (s.el_log2e * kLn2 * tp.rT - tp.x / tp.em1 -
-                                           tp.dZ / (tp.Z * kLn2) - 0.5f);
-            const float dS_dT = q.S * (1.0f + tp.em1) / tp.em1 * tp.x * tp.rT;
-            float gT = gS * dS_dT + gKK * dlnK_dT - 0.5f * tp.rT * (gb * q.b + ga * q.a);
-            const float gV = ga * q.b * tp.vfac;
-            float gzu = gKK * tp.sa * tp.iw * kLn2;
-            float gzl = -gKK * tp.sb * tp.iw * kLn2;
-            if (s.mlp_o) {
-                // network outputs: z_up = zr rho sigma(o0), z_lo = zr rho sigma(o1),
-                // T = T_grid exp(0.5 tanh(o2)); the grid surfaces are not used
-                const float s0 = sigmoidf_(o.x), s0c = sigmoidf_(-o.x);
-                const float s1 = sigmoidf_(o.y), s1c = sigmoidf_(-o.y);
-                const float th = tanhf_(o.z);
-                dout.x = gzu * s.zr_max * L.rho * s0 * s0c;
-                dout.y = gzl * s.zr_max * L.rho * s1 * s1c;
-                dout.z = gT * F.T * 0.5f * (1.0f - th * th);
-                gT *= tfac;
-                gzu = 0.0f;
-                gzl = 0.0f;
-            }
-            const float fu = L.fu, fv = L.fv;
+            const ChainTerms t = chain_terms(g, s, ztab, r, c, k, pix);
+            dout = t.dout;
+            const float fu = t.fu, fv = t.fv;
             const float w00 = (1.0f - fu) * (1.0f - fv), w01 = (1.0f - fu) * fv, w10 = fu * (1.0f - fv), w11 = fu * fv;
-            const int n00 = L.i0 * s.nz + L.j0, n10 = n00 + s.nz;
-            scatter4((A *)go.ln_n, n00, n10, gKK, w00, w01, w10, w11);
-            scatter4((A *)go.temp, n00, n10, gT, w00, w01, w10, w11);
-            scatter4((A *)go.vphi, n00, n10, gV, w00, w01, w10, w11);
+            const int n00 = t.i0 * s.nz + t.j0, n10 = n00 + s.nz;
+            scatter4((A *)go.ln_n, n00, n10, t.gn, w00, w01, w10, w11);
+            scatter4((A *)go.temp, n00, n10, t.gT, w00, w01, w10, w11);
+            scatter4((A *)go.vphi, n00, n10, t.gV, w00, w01, w10, w11);
             double *zl = lds_surfaces ? lds : go.zlo;
             double *zu = lds_surfaces ? lds + nr : go.zup;
-            if (zl && gzl != 0.0f) { atomicAdd(zl + L.i0, (double)(gzl * (1.0f - fu))); atomicAdd(zl + L.i0 + 1, (double)(gzl * fu)); }
-            if (zu && gzu != 0.0f) { atomicAdd(zu + L.i0, (double)(gzu * (1.0f - fu))); atomicAdd(zu + L.i0 + 1, (double)(gzu * fu)); }
+            if (zl && t.gzl != 0.0f) { atomicAdd(zl + t.i0, (double)(t.gzl * (1.0f - fu))); atomicAdd(zl + t.i0 + 1, (double)(t.gzl * fu)); }
+            if (zu && t.gzu != 0.0f) { atomicAdd(zu + t.i0, (double)(t.gzu * (1.0f - fu))); atomicAdd(zu + t.i0 + 1, (double)(t.gzu * fu)); }
         }
         if (dO) dO[o_index(s, k, pix)] = dout;
     }

@@ -197,6 +197,9 @@ std::mutex g_ws_mu;
 std::map<WsKey, WsBuf> g_ws;
 } // namespace
 
+// workspaces grow in 64 MiB steps
+size_t workspace_round(size_t bytes) { return (bytes + (64u << 20) - 1) / (64u << 20) * (64u << 20); }
+
 void *stream_workspace(hipStream_t st, int slot, size_t bytes, hipError_t *err) {
     *err = hipSuccess;
     int dev = 0;
@@ -205,9 +208,9 @@ void *stream_workspace(hipStream_t st, int slot, size_t bytes, hipError_t *err) 
     std::lock_guard<std::mutex> lk(g_ws_mu);
     WsBuf &b = g_ws[{dev, st, slot}];
     if (b.bytes >= bytes && b.p) return b.p;
-    // grow in 64 MiB steps; the old buffer is released in stream order, after
-    // the work already queued on this stream that may still use it
-    const size_t want = (bytes + (64u << 20) - 1) / (64u << 20) * (64u << 20);
+    // the old buffer is released in stream order, after the work already
+    // queued on this stream that may still use it
+    const size_t want = workspace_round(bytes);
     if (b.p) {
         if ((*err = hipFreeAsync(b.p, st)) != hipSuccess) return nullptr;
         b.p = nullptr;

@@ -27,6 +27,37 @@ struct ServeDesc {
 
 hipError_t launch_serve_fwd(const ServeDesc *descs, int nreq, uint32_t nitems, uint32_t *counter, int nwg,
                             hipStream_t st);
+
+// Batched gradient requests (forward + L2 loss + adjoint of grid fields):
+// the reverse march runs kGradCB channels per lane, two lanes per pixel, so a
+// cotangent slice covers 2 kGradCB channels; tape items split each tile's
+// samples into kGradTapeChunks chunks; chain items are runs of 256
+// pixel-samples.
+constexpr int kGradCB = 16;
+constexpr int kGradTapeChunks = 4;
+
+struct GradDesc {
+    Geometry g;
+    Shade s;
+    const float *vch;          // channel velocities, padded to a multiple of 2 kGradCB
+    const float *target;       // [nch][ny][nx]
+    float *cube;               // [nch][ny][nx] (written by the reverse march)
+    float4 *tape, *rays, *cot; // scratch: [nsamp][npix], [npix], [nblk][nsamp][npix]
+    double *acc;               // accumulators [3 nr nz + 2 nr]: ln n, T, v_phi, z_lo, z_up
+    float *out[5];             // caller's gradient outputs in the same order (NULL: not requested)
+    double *loss;              // L of this request
+    int32_t nch, nblk;         // channels, cotangent slices (of 2 kGradCB channels)
+    uint32_t item0[3];         // first item of this request in the tape, march and chain passes
+};
+
+// scratch bytes of one batched gradient request (tape, rays, cotangents, accumulators)
+size_t grad_batch_scratch_bytes(int nch, long npix, int nsamp, long nr, long nz);
+// items of one request in the three passes
+void grad_batch_items(int nch, long npix, int nsamp, uint32_t items[3]);
+// zero -> tape -> reverse march -> chain -> outputs and losses, on one stream;
+// counters: 3 device words
+hipError_t launch_grad_batch(const GradDesc *descs, const GradDesc *host_descs, int nreq, const uint32_t nitems[3],
+                             uint32_t *counters, int nwg, hipStream_t st);
 hipError_t launch_l2_loss(const float *cube, const float *target, float *dl, size_t n, double *loss, hipStream_t st);
 // L of every request of a batch that has a target (descs on the device, losses zeroed first)
 hipError_t launch_l2_batch(const ServeDesc *descs, int nreq, double *losses, size_t max_n, hipStream_t st);

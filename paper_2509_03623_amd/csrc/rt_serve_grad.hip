@@ -1,0 +1,244 @@
+// rt_serve_grad.hip -- batched gradient requests of the render server.
+//
+// Several forward + L2 loss + adjoint requests (grid fields, uneven sizes)
+// share one sequence of launches: the accumulators of every request are
+// cleared, then three persistent launches run the adjoint's passes over the
+// work items of all requests of the batch, each workgroup pulling the next
+// item from a device counter:
+//   tape   -- (request, 256-pixel tile, chunk of samples): the shading of
+//             every sample to the request's tape;
+//   march  -- (request, 128-pixel tile, slice of 2 x 16 channels): the
+//             checkpoint-free reverse march with the intensity formed in the
+//             march, writing the cube and the per-sample cotangents;
+//   chain  -- (request, run of 256 pixel-samples): the shading's local
+//             derivatives, scattered to the request's FP64 accumulators with
+//             atomics;
+// then one launch writes every request's gradients (FP64 -> FP32) and one its
+// loss.  A request's items are those of its own problem and its results go
+// to its own buffers, so what it gets does not depend on the rest of the
+// batch beyond the order of the atomic additions.
+#include "rt_adjoint_dev.h"
+#include "rt_host.h"
+#include "rt_serve.h"
+
+namespace rt {
+
+static_assert(kGradCB == 16, "the batched reverse march is instantiated for 16 channels per lane");
+
+static size_t al256(size_t b) { return (b + 255) / 256 * 256; }
+
+size_t grad_batch_scratch_bytes(int nch, long npix, int nsamp, long nr, long nz) {
+    const size_t nblk = (size_t)(nch + 2 * kGradCB - 1) / (2 * kGradCB);
+    return al256(sizeof(float4) * (size_t)nsamp * npix) + al256(sizeof(float4) * (size_t)npix) +
+           al256(sizeof(float4) * nblk * nsamp * npix) + al256(sizeof(double) * (size_t)(3 * nr * nz + 2 * nr));
+}
+
+void grad_batch_items(int nch, long npix, int nsamp, uint32_t items[3]) {
+    const long nblk = (nch + 2 * kGradCB - 1) / (2 * kGradCB);
+    items[0] = (uint32_t)(((npix + 255) / 256) * kGradTapeChunks);
+    items[1] = (uint32_t)(((npix + 127) / 128) * nblk);
+    items[2] = (uint32_t)(((size_t)nsamp * npix + 255) / 256);
+}
+
+// the request owning item `item` of pass `pass`: the last whose first item is <= item
+__device__ __forceinline__ int owner(const GradDesc *__restrict__ descs, int nreq, int pass, uint32_t item) {
+    int lo = 0, hi = nreq - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (descs[mid].item0[pass] <= item) lo = mid; else hi = mid - 1;
+    }
+    return __builtin_amdgcn_readfirstlane(lo);
+}
+
+// a wave-uniform pointer kept in scalar registers
+template <class T>
+__device__ __forceinline__ T *uniform_ptr(T *p) {
+    const uint64_t v = (uint64_t)p;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v), hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return (T *)(((uint64_t)hi << 32) | lo);
+}
+
+// next item of a persistent launch, the same for the whole workgroup
+__device__ __forceinline__ uint32_t next_item(uint32_t *counter, uint32_t *s_item) {
+    __syncthreads();
+    if (threadIdx.x == 0) *s_item = atomicAdd(counter, 1u);
+    __syncthreads();
+    return __builtin_amdgcn_readfirstlane(*s_item);
+}
+
+// the request's partition table into LDS when it is not the one already there
+__device__ __forceinline__ void stage_table(const float4 *tab, float4 *lds, const float4 **s_tab) {
+    if (*s_tab != tab) {     // uniform: every lane reads the same s_tab
+        __syncthreads();
+        for (int i = threadIdx.x; i < kZTableNodes - 1; i += 256) lds[i] = tab[i];
+        __syncthreads();
+        if (threadIdx.x == 0) *s_tab = tab;
+    }
+}
+
+__global__ __launch_bounds__(256) void grad_zero(const GradDesc *__restrict__ descs) {
+    const GradDesc &D = descs[blockIdx.y];
+    const size_t n = 3 * (size_t)D.s.nr * D.s.nz + 2 * (size_t)D.s.nr;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) D.acc[i] = 0.0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) *D.loss = 0.0;
+}
+
+__global__ __launch_bounds__(256) void grad_tape(const GradDesc *__restrict__ descs, int nreq, uint32_t nitems,
+                                                 uint32_t *__restrict__ counter) {
+    __shared__ float4 ztab[kZTableNodes - 1];
+    __shared__ uint32_t s_item;
+    __shared__ const float4 *s_tab;
+    if (threadIdx.x == 0) s_tab = nullptr;
+    for (;;) {
+        const uint32_t item = next_item(counter, &s_item);
+        if (item >= nitems) break;
+        const GradDesc D = descs[owner(descs, nreq, 0, item)];
+        stage_table(D.s.ztab, ztab, &s_tab);
+        const uint32_t local = item - D.item0[0];
+        const int tile = (int)(local / kGradTapeChunks), chunk = (int)(local % kGradTapeChunks);
+        const int npix = D.g.nx * D.g.ny, pix = tile * 256 + (int)threadIdx.x;
+        if (pix < npix) {
+            const int len = (D.g.nsamp + kGradTapeChunks - 1) / kGradTapeChunks;
+            const int k0 = chunk * len, k1 = min(D.g.nsamp, k0 + len);
+            tape_pixel(D.g, D.s, ztab, pix, k0, k1, chunk == 0, D.tape, D.rays);
+        }
+    }
+}
+
+// (two waves per SIMD: held to three, the item loop's state spills)
+__global__ __launch_bounds__(256) void grad_march(const GradDesc *__restrict__ descs, int nreq, uint32_t nitems, uint32_t *__restrict__ counter) {
+    constexpr int CB = kGradCB;
+    __shared__ uint32_t s_item;
+    for (;;) {
+        const uint32_t item = next_item(counter, &s_item);
+        if (item >= nitems) break;
+        const GradDesc *D = descs + owner(descs, nreq, 1, item);
+        const uint32_t local = item - __builtin_amdgcn_readfirstlane(D->item0[1]);
+        const int nblk = __builtin_amdgcn_readfirstlane(D->nblk);
+        const int tile = (int)(local / (uint32_t)nblk), blk = (int)(local % (uint32_t)nblk);
+        const int npix = __builtin_amdgcn_readfirstlane(D->g.nx * D->g.ny);
+        const int nsamp = __builtin_amdgcn_readfirstlane(D->g.nsamp);
+        const int nch = __builtin_amdgcn_readfirstlane(D->nch);
+        const int g = (int)(threadIdx.x & 1);
+        const int pix = tile * 128 + (int)threadIdx.x / 2;
+        const int c0 = (blk * 2 + g) * CB;
+        if (pix < npix) {   // both lanes of a pixel take the branch together
+            const float *vch = uniform_ptr(D->vch);
+            float vv[CB];
+#pragma unroll
+            for (int c = 0; c < CB; ++c) vv[c] = vch[c0 + c];
+            auto vel = [&](int c) -> float { return vv[c]; };
+            march_tau_pixel<CB, 2, true>(pix, blk, g, c0, nch, nsamp, npix, npix, vel, uniform_ptr(D->tape), nullptr,
+                                         uniform_ptr(D->target), uniform_ptr(D->cot), uniform_ptr(D->cube));
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void grad_chain(const GradDesc *__restrict__ descs, int nreq, uint32_t nitems,
+                                                  uint32_t *__restrict__ counter) {
+    __shared__ float4 ztab[kZTableNodes - 1];
+    __shared__ uint32_t s_item;
+    __shared__ const float4 *s_tab;
+    if (threadIdx.x == 0) s_tab = nullptr;
+    for (;;) {
+        const uint32_t item = next_item(counter, &s_item);
+        if (item >= nitems) break;
+        const GradDesc D = descs[owner(descs, nreq, 2, item)];
+        stage_table(D.s.ztab, ztab, &s_tab);
+        const int npix = D.g.nx * D.g.ny, nsamp = D.g.nsamp;
+        const size_t idx = (size_t)(item - D.item0[2]) * 256 + threadIdx.x;
+        if (idx >= (size_t)nsamp * npix) continue;
+        const int k = (int)(idx / npix);
+        const int pix = (int)(idx - (size_t)k * npix);
+        const float4 rr = D.rays[pix];
+        float4 c = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        for (int b = 0; b < D.nblk; ++b) {
+            const float4 t = D.cot[((size_t)b * nsamp + k) * npix + pix];
+            c.x += t.x; c.y += t.y; c.z += t.z; c.w += t.w;
+        }
+        if (!(rr.w > 0.0f) || (c.x == 0.0f && c.y == 0.0f && c.z == 0.0f && c.w == 0.0f)) continue;
+        const ChainTerms t = chain_terms(D.g, D.s, ztab, rr, c, k, pix);
+        const size_t nn = (size_t)D.s.nr * D.s.nz;
+        const float fu = t.fu, fv = t.fv;
+        const float w[4] = {(1.0f - fu) * (1.0f - fv), (1.0f - fu) * fv, fu * (1.0f - fv), fu * fv};
+        const int n00 = t.i0 * D.s.nz + t.j0;
+        const int node[4] = {n00, n00 + 1, n00 + D.s.nz, n00 + D.s.nz + 1};
+        const float gf[3] = {t.gn, t.gT, t.gV};
+#pragma unroll
+        for (int f = 0; f < 3; ++f) {
+            if (!D.out[f] || gf[f] == 0.0f) continue;
+            double *a = D.acc + f * nn;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) atomicAdd(a + node[j], (double)(gf[f] * w[j]));
+        }
+        double *zl = D.acc + 3 * nn, *zu = zl + D.s.nr;
+        if (D.out[3] && t.gzl != 0.0f) {
+            atomicAdd(zl + t.i0, (double)(t.gzl * (1.0f - fu)));
+            atomicAdd(zl + t.i0 + 1, (double)(t.gzl * fu));
+        }
+        if (D.out[4] && t.gzu != 0.0f) {
+            atomicAdd(zu + t.i0, (double)(t.gzu * (1.0f - fu)));
+            atomicAdd(zu + t.i0 + 1, (double)(t.gzu * fu));
+        }
+    }
+}
+
+// blockIdx.y = request: its FP64 accumulators to the caller's FP32 outputs
+__global__ __launch_bounds__(256) void grad_finish(const GradDesc *__restrict__ descs) {
+    const GradDesc &D = descs[blockIdx.y];
+    const size_t nn = (size_t)D.s.nr * D.s.nz, nr = (size_t)D.s.nr;
+    const size_t off[5] = {0, nn, 2 * nn, 3 * nn, 3 * nn + nr};
+    const size_t len[5] = {nn, nn, nn, nr, nr};
+    for (int f = 0; f < 5; ++f) {
+        float *o = D.out[f];
+        if (!o) continue;
+        for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < len[f]; i += (size_t)gridDim.x * 256)
+            o[i] = (float)D.acc[off[f] + i];
+    }
+}
+
+// blockIdx.y = request: L = sum (cube - target)^2 (block sums, FP64 atomics)
+__global__ __launch_bounds__(256) void grad_loss(const GradDesc *__restrict__ descs) {
+    const GradDesc &D = descs[blockIdx.y];
+    __shared__ double part[256];
+    const size_t n = (size_t)D.nch * D.g.nx * D.g.ny;
+    double acc = 0.0;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+        const double r = (double)D.cube[i] - (double)D.target[i];
+        acc += r * r;
+    }
+    part[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) part[threadIdx.x] += part[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicAdd(D.loss, part[0]);
+}
+
+__global__ void zero_counters(uint32_t *c) {
+    if (threadIdx.x < 3) c[threadIdx.x] = 0u;
+}
+
+hipError_t launch_grad_batch(const GradDesc *descs, const GradDesc *host_descs, int nreq, const uint32_t nitems[3],
+                             uint32_t *counters, int nwg, hipStream_t st) {
+    size_t max_acc = 0, max_cube = 0;
+    for (int i = 0; i < nreq; ++i) {
+        const GradDesc &D = host_descs[i];
+        max_acc = std::max(max_acc, 3 * (size_t)D.s.nr * D.s.nz + 2 * (size_t)D.s.nr);
+        max_cube = std::max(max_cube, (size_t)D.nch * D.g.nx * D.g.ny);
+    }
+    hipLaunchKernelGGL(zero_counters, dim3(1), dim3(64), 0, st, counters);
+    hipLaunchKernelGGL(grad_zero, dim3((unsigned)std::min<size_t>((max_acc + 255) / 256, 64), nreq), dim3(256), 0, st,
+                       descs);
+    hipLaunchKernelGGL(grad_tape, dim3(nwg), dim3(256), 0, st, descs, nreq, nitems[0], counters);
+    hipLaunchKernelGGL(grad_march, dim3(nwg), dim3(256), 0, st, descs, nreq, nitems[1], counters + 1);
+    hipLaunchKernelGGL(grad_chain, dim3(nwg), dim3(256), 0, st, descs, nreq, nitems[2], counters + 2);
+    hipLaunchKernelGGL(grad_finish, dim3((unsigned)std::min<size_t>((max_acc + 255) / 256, 64), nreq), dim3(256), 0,
+                       st, descs);
+    hipLaunchKernelGGL(grad_loss, dim3((unsigned)std::min<size_t>((max_cube + 255) / 256, 128), nreq), dim3(256), 0,
+                       st, descs);
+    return hipGetLastError();
+}
+
+} // namespace rt

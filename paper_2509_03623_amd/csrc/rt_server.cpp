@@ -8,18 +8,26 @@
 //   3. starts admitted work on an idle stream: the admitted plain forward
 //      requests that are too small to fill the device alone go into one
 //      persistent launch whose workgroups pull (request, tile, channel block)
-//      items from a device counter; a request that fills the device alone
-//      (the direct renderer's launch shape), one with a gradient (forward,
-//      fused L2 loss + cotangent, adjoint) or one with the neural CO layer
-//      runs on a stream of its own.
+//      items from a device counter; the admitted gradient requests (forward,
+//      fused L2 loss + cotangent, adjoint) that are too small to fill the
+//      device alone go into one batched sequence of persistent launches
+//      (tape, reverse march, chain; rt_serve_grad.hip); a request that fills
+//      the device alone (the direct renderer's launch shape) or one with the
+//      neural CO layer runs on a stream of its own.
 // Requests that arrive while launches run are admitted as budget and slots
 // free up and start on the next idle stream, so their work overlaps on the
 // device with what is already running.  A forward cube depends only on its
 // own request (each ray is marched by one lane with the same code whatever
-// else is in the batch).
+// else is in the batch); a gradient request's routing depends only on its
+// own shape, and its result on the rest of its batch only through the order
+// of the FP64 atomic additions.  The library scratch of a launch (a stream's
+// workspaces) is released when the launch retires, so the device memory the
+// server holds beyond the callers' buffers is that of the running launches,
+// whose footprints admission keeps within the budget.
 #include <hip/hip_runtime.h>
 
 #include <chrono>
+#include <cmath>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
@@ -52,7 +60,8 @@ struct Req {
     uint64_t t_submit = 0, t_admit = 0, t_done = 0;
     double loss = 0.0;
     uint64_t footprint = 0, ray_samples = 0;
-    bool own_stream = false;   // large, gradient or neural request
+    bool own_stream = false;   // large or neural request
+    bool grad_batch = false;   // small gradient request (batched launches)
 };
 
 struct Lane {
@@ -65,6 +74,8 @@ struct Lane {
     size_t vch_cap = 0;
     uint32_t *d_counter = nullptr;
     double *d_loss = nullptr, *h_loss = nullptr;
+    GradDesc *d_gdesc = nullptr, *h_gdesc = nullptr;
+    uint32_t *d_gcount = nullptr;   // item counters of the three batched gradient passes
 };
 
 __global__ void zero_u32(uint32_t *p) { *p = 0u; }
@@ -89,8 +100,9 @@ struct rt_server {
 namespace {
 
 // Device memory a request occupies while it runs: its inputs and outputs and
-// the library's scratch.
-uint64_t footprint(const rt_request &r) {
+// the library's scratch, each stream workspace counted at the size it
+// actually holds (workspace_round).
+uint64_t footprint(const rt_request &r, bool grad_batched) {
     const rt_problem &p = r.problem;
     const uint64_t nn = (uint64_t)p.grid.nr * p.grid.nz, nr = p.grid.nr;
     const uint64_t npix = (uint64_t)p.cam.nx * p.cam.ny, cube = 4ull * p.spec.nch * npix;
@@ -98,14 +110,26 @@ uint64_t footprint(const rt_request &r) {
     uint64_t b = 4 * (3 * nn + 2 * nr) + cube;
     if (p.mlp) b += 4ull * RT_MLP_PARAMS + 16 * M + (1u << 20);
     if (r.kind == RT_REQ_FWD_LOSS) b += cube;   // target
-    if (r.kind == RT_REQ_FWD_LOSS && r.beam.bmaj_px > 0.0) b += cube;   // convolved cube
-    if (r.kind == RT_REQ_FWD_ADJ) {
+    if (r.kind == RT_REQ_FWD_LOSS && r.beam.bmaj_px > 0.0) {
+        // convolved cube and the beam's weights (stream workspaces)
+        const double sig = r.beam.bmaj_px / (2.0 * std::sqrt(2.0 * std::log(2.0)));
+        const uint64_t side = 2 * (uint64_t)std::ceil(3.0 * sig) + 1;
+        b += workspace_round(cube) + workspace_round(4 * side * side);
+    }
+    if (r.kind == RT_REQ_FWD_ADJ && !p.mlp && grad_batched) {
+        // target, grads, and the batched passes' tape, rays, cotangents,
+        // accumulators (one workspace for the whole batch: rounding each
+        // request's share up bounds it)
+        b += cube + 4 * (3 * nn + 2 * nr);
+        b += workspace_round(grad_batch_scratch_bytes(p.spec.nch, (long)npix, p.nsamp, p.grid.nr, p.grid.nz));
+    } else if (r.kind == RT_REQ_FWD_ADJ) {
         const int ch = std::min(p.spec.nch, kLaunchChannels);
-        b += cube + 4 * (3 * nn + 2 * nr) + 8 * (3 * nn + 2 * nr);   // target, grads, accumulators
+        b += cube + 4 * (3 * nn + 2 * nr) + workspace_round(8 * (3 * nn + 2 * nr));   // target, grads, accumulators
         // tape, rays, checkpoints, cotangents of one band of rows (gradient
         // requests run the fused L2 adjoint, which forms the cube)
         const uint64_t row = adjoint_bytes_per_pixel(ch, (long)npix, p.nsamp, true) * (uint64_t)p.cam.nx;
-        b += std::min<uint64_t>(row * p.cam.ny, std::max<uint64_t>(row, adjoint_scratch_cap() / row * row));
+        b += workspace_round(std::min<uint64_t>(row * p.cam.ny,
+                                                std::max<uint64_t>(row, adjoint_scratch_cap() / row * row)));
         if (p.mlp) b += 16 * M + 4ull * RT_MLP_PARAMS;
     }
     return b;
@@ -187,6 +211,70 @@ rt_status launch_batch(rt_server *sv, Lane &L, std::vector<Req *> &batch) {
     return RT_OK;
 }
 
+// one batched sequence of gradient launches over every request of the batch
+rt_status launch_grad(rt_server *sv, Lane &L, std::vector<Req *> &batch) {
+    constexpr int kPad = 2 * kGradCB;
+    size_t nv = 0, scratch = 0;
+    for (Req *r : batch) {
+        const rt_problem &p = r->rq.problem;
+        nv += (size_t)(p.spec.nch + kPad - 1) / kPad * kPad;
+        scratch += grad_batch_scratch_bytes(p.spec.nch, (long)p.cam.nx * p.cam.ny, p.nsamp, p.grid.nr, p.grid.nz);
+    }
+    rt_status rs = lane_vch_capacity(L, nv);
+    if (rs != RT_OK) return rs;
+    hipError_t e;
+    char *base = (char *)stream_workspace(L.st, kWsGradBatch, scratch, &e);
+    if (!base) return fail_hip(e, "batched gradient scratch");
+    uint32_t items[3] = {0, 0, 0};
+    size_t vo = 0;
+    auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+    for (size_t i = 0; i < batch.size(); ++i) {
+        const rt_request &q = batch[i]->rq;
+        const rt_problem &p = q.problem;
+        GradDesc &D = L.h_gdesc[i];
+        std::memset(&D, 0, sizeof D);
+        rs = build_launch(&p, &D.g, &D.s);
+        if (rs != RT_OK) return rs;
+        const int nch = p.spec.nch, padded = (nch + kPad - 1) / kPad * kPad;
+        for (int c = 0; c < padded; ++c) L.h_vch[vo + c] = c < nch ? (float)p.spec.v_kms[c] : 0.0f;
+        D.vch = L.d_vch + vo;
+        vo += padded;
+        const size_t npix = (size_t)p.cam.nx * p.cam.ny, ns = p.nsamp;
+        D.nch = nch;
+        D.nblk = padded / kPad;
+        D.target = q.target;
+        D.cube = q.cube;
+        D.tape = (float4 *)base;
+        base += al(sizeof(float4) * ns * npix);
+        D.rays = (float4 *)base;
+        base += al(sizeof(float4) * npix);
+        D.cot = (float4 *)base;
+        base += al(sizeof(float4) * D.nblk * ns * npix);
+        D.acc = (double *)base;
+        base += al(sizeof(double) * (3 * (size_t)p.grid.nr * p.grid.nz + 2 * (size_t)p.grid.nr));
+        D.out[0] = q.grads.d_ln_nh2;
+        D.out[1] = q.grads.d_temp_k;
+        D.out[2] = q.grads.d_vphi_kms;
+        D.out[3] = q.grads.d_z_lo_au;
+        D.out[4] = q.grads.d_z_up_au;
+        D.loss = L.d_loss + i;
+        uint32_t n[3];
+        grad_batch_items(nch, (long)npix, p.nsamp, n);
+        for (int k = 0; k < 3; ++k) {
+            D.item0[k] = items[k];
+            items[k] += n[k];
+        }
+    }
+    e = hipMemcpyAsync(L.d_gdesc, L.h_gdesc, sizeof(GradDesc) * batch.size(), hipMemcpyHostToDevice, L.st);
+    if (e == hipSuccess) e = hipMemcpyAsync(L.d_vch, L.h_vch, sizeof(float) * vo, hipMemcpyHostToDevice, L.st);
+    if (e != hipSuccess) return fail_hip(e, "server gradient upload");
+    e = launch_grad_batch(L.d_gdesc, L.h_gdesc, (int)batch.size(), items, L.d_gcount,
+                          sv->ncu * kServeWorkgroupsPerCU, L.st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(L.h_loss, L.d_loss, sizeof(double) * batch.size(), hipMemcpyDeviceToHost, L.st);
+    return e == hipSuccess ? RT_OK : fail_hip(e, "server gradient batch");
+}
+
 // a request on a stream of its own: a large or neural forward, or the fused
 // forward + L2 loss + adjoint (the reverse march forms dL/dI = 2 (I - D) from
 // its own forward sweep and writes the cube)
@@ -238,6 +326,8 @@ void scheduler(rt_server *sv) {
                 if (r->rq.kind != RT_REQ_FWD) r->loss = L.h_loss[i];
                 finish(sv, r, q == hipSuccess ? RT_OK : RT_EDEVICE);
             }
+            // the launch's library scratch goes back with its footprint
+            release_stream_workspaces(L.st);
             L.reqs.clear();
             L.busy = false;
             progress = true;
@@ -263,8 +353,10 @@ void scheduler(rt_server *sv) {
                 batch.push_back(sv->admitted.front());
                 sv->admitted.pop_front();
             } else {
+                // every admitted request of the front one's kind of batch
+                const bool grad = sv->admitted.front()->grad_batch;
                 for (auto it = sv->admitted.begin(); it != sv->admitted.end();) {
-                    if (!(*it)->own_stream && (int)batch.size() < sv->cfg.max_slots) {
+                    if (!(*it)->own_stream && (*it)->grad_batch == grad && (int)batch.size() < sv->cfg.max_slots) {
                         batch.push_back(*it);
                         it = sv->admitted.erase(it);
                     } else {
@@ -275,13 +367,16 @@ void scheduler(rt_server *sv) {
             // launch without holding the lock, so submissions are not held up
             // (the batch and the lane belong to this thread until then)
             lk.unlock();
-            rt_status rs = batch.front()->own_stream ? launch_single(L, batch.front()) : launch_batch(sv, L, batch);
+            Req *front = batch.front();
+            rt_status rs = front->own_stream ? launch_single(L, front)
+                         : front->grad_batch ? launch_grad(sv, L, batch) : launch_batch(sv, L, batch);
             hipError_t e = hipSuccess;
             if (rs == RT_OK) e = hipEventRecord(L.ev, L.st);
             lk.lock();
             if (rs != RT_OK || e != hipSuccess) {
                 // the stream may hold partial work: wait for it, then fail the requests
                 (void)hipStreamSynchronize(L.st);
+                release_stream_workspaces(L.st);
                 for (Req *r : batch) finish(sv, r, rs != RT_OK ? rs : RT_EDEVICE);
                 continue;
             }
@@ -321,7 +416,10 @@ rt_status rt_server_create(const rt_server_cfg *cfg, rt_server **out) {
             (e = hipHostMalloc(&L.h_desc, sizeof(ServeDesc) * cfg->max_slots, hipHostMallocDefault)) != hipSuccess ||
             (e = hipMalloc(&L.d_counter, sizeof(uint32_t))) != hipSuccess ||
             (e = hipMalloc(&L.d_loss, sizeof(double) * cfg->max_slots)) != hipSuccess ||
-            (e = hipHostMalloc(&L.h_loss, sizeof(double) * cfg->max_slots, hipHostMallocDefault)) != hipSuccess) {
+            (e = hipHostMalloc(&L.h_loss, sizeof(double) * cfg->max_slots, hipHostMallocDefault)) != hipSuccess ||
+            (e = hipMalloc(&L.d_gdesc, sizeof(GradDesc) * cfg->max_slots)) != hipSuccess ||
+            (e = hipHostMalloc(&L.h_gdesc, sizeof(GradDesc) * cfg->max_slots, hipHostMallocDefault)) != hipSuccess ||
+            (e = hipMalloc(&L.d_gcount, 3 * sizeof(uint32_t))) != hipSuccess) {
             rt_status st = fail_hip(e, "server resources");
             rt_server_destroy(sv.release());
             return st;
@@ -375,10 +473,18 @@ rt_status rt_submit(rt_server *sv, const rt_request *rq, uint64_t *ticket) {
     }
     // lanes of the request in the persistent launch (kServeSplit per pixel and
     // 16-channel block) against the lanes the launch keeps resident
+    const uint64_t device_lanes = (uint64_t)sv->ncu * kServeWorkgroupsPerCU * 256;
     const uint64_t serve_lanes = (uint64_t)p.cam.nx * p.cam.ny * ((p.spec.nch + 15) / 16) * kServeSplit;
-    const bool fills = serve_lanes >= (uint64_t)sv->ncu * kServeWorkgroupsPerCU * 256;
-    r->own_stream = rq->kind == RT_REQ_FWD_ADJ || p.mlp != nullptr || fills;
-    r->footprint = footprint(*rq);
+    // lanes of a gradient request in the batched reverse march: two per
+    // pixel and slice of 2 kGradCB channels
+    const uint64_t grad_lanes = (uint64_t)p.cam.nx * p.cam.ny * ((p.spec.nch + 2 * kGradCB - 1) / (2 * kGradCB)) * 2;
+    if (rq->kind == RT_REQ_FWD_ADJ) {
+        r->grad_batch = p.mlp == nullptr && grad_lanes < device_lanes;
+        r->own_stream = !r->grad_batch;
+    } else {
+        r->own_stream = p.mlp != nullptr || serve_lanes >= device_lanes;
+    }
+    r->footprint = footprint(*rq, r->grad_batch);
     r->ray_samples = (uint64_t)p.cam.nx * p.cam.ny * p.spec.nch * p.nsamp;
     std::lock_guard<std::mutex> lk(sv->mu);
     if (sv->stop) return fail(RT_ECANCELED, "server is shutting down");
@@ -470,6 +576,9 @@ rt_status rt_server_destroy(rt_server *sv) {
         if (L.d_counter) (void)hipFree(L.d_counter);
         if (L.d_loss) (void)hipFree(L.d_loss);
         if (L.h_loss) (void)hipHostFree(L.h_loss);
+        if (L.d_gdesc) (void)hipFree(L.d_gdesc);
+        if (L.h_gdesc) (void)hipHostFree(L.h_gdesc);
+        if (L.d_gcount) (void)hipFree(L.d_gcount);
     }
     delete sv;
     return RT_OK;

@@ -282,3 +282,129 @@ def test_loss_requests_with_beam():
         assert info["state"] == "done", i
         assert float((o - direct[i]).abs().max()) <= 1e-6 * float(direct[i].abs().max()), i
         assert info["loss"] == pytest.approx(ref_loss[i], rel=1e-6), i
+
+
+GKEYS = ("ln_nh2", "temp_k", "vphi_kms", "z_lo_au", "z_up_au")
+
+
+def grad_scene(nx, nch, nsamp, seed, nr=64, nz=32, ny=None):
+    rt = _rt()
+    prob = synth.config2(seed, nx=nx, ny=ny or nx, nch=nch, nsamp=nsamp, nr=nr, nz=nz)
+    prob = prob.replace(intensity_scale=synth.disk.rj_kelvin_scale(prob.line))
+    sc = rt.scene_from_problem(prob)
+    target = rt.render(sc.replace(z_up_au=sc.z_up_au * 1.05))
+    return prob, sc, target
+
+
+def submit_grad(sv, sc, target):
+    grads = {k: torch.full_like(getattr(sc, k), float("nan")) for k in GKEYS}
+    cube = empty_cube(sc)
+    return sv.submit(sc, cube, target=target, grads=grads), cube, grads
+
+
+def test_batched_gradient_requests_match_direct():
+    """Small gradient requests of uneven sizes (pixels, channels, samples and
+    grids) submitted together share the batched launch sequence; each result
+    against the direct fused call on the same inputs (cube and loss to 1e-6,
+    every gradient block to 1e-5 of its largest entry: the same arithmetic, a
+    different order of the FP64 atomics), and one against the FP64 oracle's
+    autograd gradient."""
+    rt = _rt()
+    from oracle import torch_ref
+    shapes = [(24, 12, 64, 48, 24), (40, 33, 96, 64, 32), (32, 20, 128, 40, 20), (56, 64, 80, 64, 32),
+              (17, 7, 61, 32, 16), (48, 16, 200, 64, 32)]
+    reqs = [grad_scene(nx, nch, ns, 2100 + i, nr=nr, nz=nz) for i, (nx, nch, ns, nr, nz) in enumerate(shapes)]
+    direct = [rt.render_l2_adjoint(sc, tgt, want=GKEYS) for _, sc, tgt in reqs]
+    torch.cuda.synchronize()
+    print(f"[gpu] server: {len(reqs)} batched gradient requests", flush=True)
+    with rt.Server(max_slots=16, streams=2) as sv:
+        subs = [submit_grad(sv, sc, tgt) for _, sc, tgt in reqs]
+        infos = [sv.wait(t) for t, _, _ in subs]
+    torch.cuda.synchronize()
+    for i, ((t, cube, grads), info, (dc, dl, dg)) in enumerate(zip(subs, infos, direct)):
+        assert info["state"] == "done", i
+        scale = float(dc.abs().max())
+        assert float((cube - dc).abs().max()) <= 1e-6 * scale, i
+        assert info["loss"] == pytest.approx(float(dl.item()), rel=1e-6), i
+        for k in GKEYS:
+            s = float(dg[k].abs().max())
+            assert float((grads[k] - dg[k]).abs().max()) <= 1e-5 * s + 1e-30, (i, k)
+    prob, sc, tgt = reqs[1]
+    _, oref = torch_ref.loss_and_grad(prob, tgt.cpu().numpy().astype(np.float64))
+    for k in GKEYS:
+        r, g = oref[k].ravel(), subs[1][2][k].cpu().numpy().astype(np.float64).ravel()
+        l2 = float(np.linalg.norm(g - r) / np.linalg.norm(r))
+        print(f"batched {k}: L2 rel vs oracle {l2:.2e}")
+        assert l2 <= 1e-3, k
+
+
+def test_gradient_request_alone_equals_in_mix():
+    """The same gradient request alone and in a mix of gradient requests of
+    other sizes, forwards and a gradient request large enough to run on its
+    own stream: cube, loss and gradients within 1e-6 (relative to the
+    largest entry of each block)."""
+    rt = _rt()
+    _, sc, tgt = grad_scene(40, 24, 96, 2200)
+    print("[gpu] server gradient alone vs mix", flush=True)
+    with rt.Server(max_slots=16, streams=3) as sv:
+        t, cube_a, grads_a = submit_grad(sv, sc, tgt)
+        alone = sv.wait(t)
+        others = [grad_scene(n, c, s, 2210 + i) for i, (n, c, s) in enumerate([(32, 16, 64), (48, 40, 80),
+                                                                               (24, 8, 128)])]
+        big = grad_scene(256, 64, 128, 2220)
+        fwd = [scene(n, c, s, seed=2230 + i) for i, (n, c, s) in enumerate([(64, 16, 128), (32, 33, 80)])]
+        subs = [submit_grad(sv, s2, t2) for _, s2, t2 in others[:2]]
+        subs.append(submit_grad(sv, big[1], big[2]))
+        fouts = [empty_cube(s2) for _, s2 in fwd]
+        fts = [sv.submit(s2, o) for (_, s2), o in zip(fwd, fouts)]
+        t2, cube_b, grads_b = submit_grad(sv, sc, tgt)
+        subs.append(submit_grad(sv, others[2][1], others[2][2]))
+        mixed = sv.wait(t2)
+        for x in [s[0] for s in subs] + fts:
+            assert sv.wait(x)["state"] == "done"
+    torch.cuda.synchronize()
+    assert alone["state"] == "done" and mixed["state"] == "done"
+    assert float((cube_a - cube_b).abs().max()) <= 1e-6 * float(cube_a.abs().max())
+    assert mixed["loss"] == pytest.approx(alone["loss"], rel=1e-6)
+    for k in GKEYS:
+        s = float(grads_a[k].abs().max())
+        d = float((grads_a[k] - grads_b[k]).abs().max())
+        print(f"{k}: alone vs mix max diff / max {d / max(s, 1e-300):.2e}")
+        assert d <= 1e-6 * s + 1e-30, k
+
+
+def test_device_memory_stays_within_budget():
+    """Gradient requests that each fill the device (their own streams),
+    through four streams with a budget that admits two at a time: the device
+    memory taken while they run, beyond the callers' buffers, stays within
+    the budget, because a stream's library scratch goes back when its request
+    retires (kept per stream, four streams would hold four requests' worth)."""
+    rt = _rt()
+    reqs = [grad_scene(256, 64, 256, 2300 + i, nr=128, nz=64) for i in range(6)]
+    bufs = [(empty_cube(sc), {k: torch.empty_like(getattr(sc, k)) for k in GKEYS}) for _, sc, _ in reqs]
+    torch.cuda.synchronize()
+    budget = 1536 << 20
+    free0 = torch.cuda.mem_get_info()[0]
+    print("[gpu] server memory bound", flush=True)
+    with rt.Server(hbm_budget_bytes=budget, max_slots=8, streams=4) as sv:
+        ts = [sv.submit(sc, c, target=tgt, grads=g) for (_, sc, tgt), (c, g) in zip(reqs, bufs)]
+        # free device memory sampled while the requests run, then after
+        low = free0
+        deadline = time.time() + 60.0
+        while time.time() < deadline:
+            low = min(low, torch.cuda.mem_get_info()[0])
+            if all(sv.poll(t)["state"] in ("done", "failed") for t in ts):
+                break
+        infos = [sv.wait(t) for t in ts]
+        torch.cuda.synchronize()
+        free1 = torch.cuda.mem_get_info()[0]
+    assert all(i["state"] == "done" for i in infos)
+    peak, after = free0 - low, free0 - free1
+    print(f"device memory taken by the server: at most {peak / 2**20:.0f} MiB while running, "
+          f"{after / 2**20:.0f} MiB after (budget {budget / 2**20:.0f} MiB)")
+    assert peak <= budget
+    assert after <= budget
+    # at most two ran at a time
+    spans = sorted((i["t_admit_ns"], i["t_done_ns"]) for i in infos)
+    for a in spans:
+        assert sum(1 for b in spans if b[0] <= a[0] < b[1]) <= 2
