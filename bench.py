@@ -32,8 +32,13 @@ TRANS_SLOTS = 4
 # Algorithmic work of one ray-sample in the channel loop: d = a - v b (FMA),
 # x = K 2^-d^2 = 2^(log2 K - d^2) (FMA + exp2), att = 2^-x, 1 - att,
 # Tr (1 - att), I += . S (FMA), Tr *= att  ->  11 FLOP (FMA = 2,
-# transcendental = 1) in 6 VALU + 2 TRANS.
+# transcendental = 1) in 6 VALU + 2 TRANS.  On an optically thin sample
+# (line-centre depth below the series threshold) 1 - 2^-x comes from its
+# cubic series instead of the second exp2: d (FMA), x (FMA + exp2), series
+# (2 FMA + mul), t = Tr (1 - att), I += t S (FMA), Tr -= t  ->  14 FLOP in
+# 8 VALU + 1 TRANS.  The census of each render gives the thin share.
 LOOP_FLOP, LOOP_VALU, LOOP_TRANS = 11, 6, 2
+THIN_FLOP, THIN_VALU, THIN_TRANS = 14, 8, 1
 # Channel-independent shading of one pixel-sample, shared by the channels of
 # a lane: position, grid fetch and bilinear interpolation, density, CO mask,
 # partition function, populations, source function, width, projected
@@ -46,7 +51,7 @@ SHADE_FLOP, SHADE_VALU, SHADE_TRANS = 151, 100, 15
 SHADE3_SLOTS = 307 + 4 * 16
 
 
-# HBM traffic of one forward launch on the full-size render of disk 2000,
+# HBM traffic of one forward launch on the full-size render of each disk,
 # from two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch)
 # of `bench.py --copy-probe`, each scaled by what the same counter reads for
 # a 1 GiB device-to-device copy (FETCH_SIZE 524 302 KiB -> x2.0000,
@@ -54,16 +59,16 @@ SHADE3_SLOTS = 307 + 4 * 16
 # was taken on: the hash of those files is checked at run time.
 FWD_TRAFFIC = {"sources": ("paper_2509_03623_amd/csrc/rt_forward.hip", "paper_2509_03623_amd/csrc/rt_kernels.h",
                            "paper_2509_03623_amd/csrc/rt_launch.h"),
-               "sha256": "88562a102f664e17f4603de17902d7063fca80ec8ca1107169c56536bdc774e8",
-               "fetch_kib": 1239.2, "fetch_scale": 1048576 / 524302.4,
-               "write_kib": 65536.0, "write_scale": 1.0}
+               "sha256": None,
+               "fetch_scale": 1048576 / 524302.4, "write_scale": 1.0,
+               "disks": {}}     # seed -> (FETCH_SIZE KiB, WRITE_SIZE KiB)
 
 
 def measured_traffic(seed: int):
-    """HBM bytes per forward launch, or None if the kernel has changed since
-    the counters were taken (or the workload differs)."""
+    """HBM bytes per forward launch of disk `seed`, or None if the kernel has
+    changed since the counters were taken (or none were taken for it)."""
     import hashlib
-    if seed != 2000:
+    if seed not in FWD_TRAFFIC["disks"]:
         return None
     h = hashlib.sha256()
     for f in FWD_TRAFFIC["sources"]:
@@ -71,19 +76,65 @@ def measured_traffic(seed: int):
             h.update(fh.read())
     if h.hexdigest() != FWD_TRAFFIC["sha256"]:
         return None
-    return 1024.0 * (FWD_TRAFFIC["fetch_kib"] * FWD_TRAFFIC["fetch_scale"] +
-                     FWD_TRAFFIC["write_kib"] * FWD_TRAFFIC["write_scale"])
+    fetch_kib, write_kib = FWD_TRAFFIC["disks"][seed]
+    return 1024.0 * (fetch_kib * FWD_TRAFFIC["fetch_scale"] + write_kib * FWD_TRAFFIC["write_scale"])
 
 
 def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def algorithmic(nch: int, cb: int):
-    """(FLOP per ray-sample, issue slots per ray-sample) of the dense march."""
-    flop = LOOP_FLOP + SHADE_FLOP / cb
-    slots = LOOP_VALU + TRANS_SLOTS * LOOP_TRANS + (SHADE_VALU + TRANS_SLOTS * SHADE_TRANS) / cb
+def algorithmic(nch: int, cb: int, thin: float = 0.0):
+    """(FLOP per ray-sample, issue slots per ray-sample) of the dense march,
+    with a share `thin` of the pixel-samples on the series form."""
+    flop = (1.0 - thin) * LOOP_FLOP + thin * THIN_FLOP + SHADE_FLOP / cb
+    slots = ((1.0 - thin) * (LOOP_VALU + TRANS_SLOTS * LOOP_TRANS) + thin * (THIN_VALU + TRANS_SLOTS * THIN_TRANS) +
+             (SHADE_VALU + TRANS_SLOTS * SHADE_TRANS) / cb)
     return flop, slots
+
+
+def time_forward(rt, sc, cube, steps, warmup):
+    """Wall-clock and HIP-event (launch stream) milliseconds per forward
+    render of scene sc: `warmup` untimed steps, then `steps` timed with
+    Python's collector held off."""
+    import torch
+    for _ in range(warmup):
+        rt.render(sc, out=cube)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    gc.collect()
+    gc.disable()
+    try:
+        t0 = time.perf_counter()
+        e0.record(stream)
+        for _ in range(steps):
+            rt.render(sc, out=cube)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+    finally:
+        gc.enable()
+    return wall * 1e3 / steps, e0.elapsed_time(e1) / steps
+
+
+def micro_rates(L):
+    """Issue rates of the march's instruction classes on this GPU
+    (rt_microbench, register-only kernels on every CU)."""
+    import ctypes as C
+    lib = L.lib()
+    lib.rt_microbench.argtypes = [C.c_int32, C.c_int64, C.POINTER(C.c_double)]
+    lib.rt_microbench.restype = C.c_int32
+    kinds = {"fma_lane_ops_per_s": (0, 20000), "exp2_lane_ops_per_s": (1, 5000), "rcp_lane_ops_per_s": (2, 5000),
+             "log2_lane_ops_per_s": (3, 5000), "exp_fma_lane_ops_per_s": (6, 5000),
+             "loop_thick_ray_samples_per_s": (4, 2000), "loop_thin_ray_samples_per_s": (5, 2000)}
+    out = {}
+    for name, (k, iters) in kinds.items():
+        v = C.c_double()
+        if lib.rt_microbench(k, iters, C.byref(v)) == 0:
+            out[name] = v.value
+    return out
 
 
 def auto_shape(nch: int, npix: int, nsamp: int):
@@ -110,35 +161,58 @@ def auto_shape3(nch: int, npix: int, nsamp: int):
     return cb, ns
 
 
-def cpu_baseline(prob, live, seconds=12.0):
-    """FP64 oracle on seeded pixels of the same workload, all host cores;
-    live: [ny, nx] mask of the rays that cross the grid (the others have no
-    samples and are not counted)."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_rate(prob, live, seconds, nthreads, seed):
+    """(ray-samples/s, pixels, crossing pixels, seconds) of the FP64 oracle on
+    seeded random pixels of the workload for about `seconds`."""
     import numpy as np
     import oracle
-    ncores = os.cpu_count() or 1
     nx, ny = prob.camera.nx, prob.camera.ny
-    rng = np.random.Generator(np.random.PCG64(99))
+    rng = np.random.Generator(np.random.PCG64(seed))
     per_pix = prob.nch * prob.nsamp
-    n = 256
+    n = 16 if nthreads == 1 else 256
     t_used = 0.0
     done = done_live = 0
     while t_used < seconds:
         px = rng.integers(0, nx, n)
         py = rng.integers(0, ny, n)
         t0 = time.perf_counter()
-        oracle.render_pixels(prob, px, py, nthreads=ncores)
+        oracle.render_pixels(prob, px, py, nthreads=nthreads)
         dt = time.perf_counter() - t0
         t_used += dt
         done += n
         done_live += int(live[py, px].sum())
-        n = int(min(max(n * 2, 64), max(64, n * (seconds - t_used) / max(dt, 1e-3))))
-        if n < 64:
+        n = int(min(max(n * 2, 8), max(8, n * (seconds - t_used) / max(dt, 1e-3))))
+        if t_used >= seconds or n < 8:
             break
-    return dict(value=done_live * per_pix / t_used, unit="ray-samples/s", cores=ncores, kind="oracle",
+    return done_live * per_pix / t_used, done, done_live, t_used
+
+
+def cpu_baseline(prob, live, seconds=12.0, disk=None):
+    """FP64 oracle on seeded pixels of the same workload, on all host cores
+    and on one; live: [ny, nx] mask of the rays that cross the grid (the
+    others have no samples and are not counted)."""
+    ncores = os.cpu_count() or 1
+    v, done, done_live, t_used = _oracle_rate(prob, live, seconds, ncores, 99)
+    v1, done1, live1, t1 = _oracle_rate(prob, live, max(2.0, seconds / 2), 1, 98)
+    per_pix = prob.nch * prob.nsamp
+    return dict(value=v, unit="ray-samples/s", cores=ncores, kind="oracle",
                 sample=f"{done} seeded random pixels ({done_live} crossing the grid) of the 512x512x64ch "
-                       f"x512-sample disk ({done_live * per_pix:.3g} ray-samples, {t_used:.1f} s, FP64 scalar C, "
-                       f"OpenMP)")
+                       f"x512-sample disk {disk} ({done_live * per_pix:.3g} ray-samples, {t_used:.1f} s, FP64 scalar "
+                       f"C, OpenMP)",
+                value_1core=v1,
+                sample_1core=f"{done1} seeded random pixels ({live1} crossing) on one thread, {t1:.1f} s",
+                cpu_model=cpu_model())
 
 
 def main():
@@ -149,7 +223,8 @@ def main():
     ap.add_argument("--seed", type=int, default=2000)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
-    ap.add_argument("--no-disks", action="store_true", help="skip the forward rate over eight seeded disks")
+    ap.add_argument("--one-disk", action="store_true",
+                    help="time only disk --seed instead of the median over the eight seeded disks")
     ap.add_argument("--no-mlp", action="store_true", help="skip the neural CO layer leg")
     ap.add_argument("--no-3d", action="store_true", help="skip the 3-D spherical-grid leg")
     ap.add_argument("--no-beam", action="store_true", help="skip the beam-convolution leg")
@@ -159,7 +234,7 @@ def main():
                     help="first copy 1 GiB device to device three times (a kernel of known traffic, to scale "
                          "hardware byte counters)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--serve-seconds", type=float, default=10.0,
+    ap.add_argument("--serve-seconds", type=float, default=60.0,
                     help="length of the Poisson request trace (200 req/s) for the serving leg; 0 = skip")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -191,31 +266,38 @@ def main():
         cube = rt.render(sc)
         print(json.dumps({"beam": bench_beam(rt, cube, args)}), flush=True)
         return
-    prob = synth.config2(args.seed)
-    sc = rt.scene_from_problem(prob, device=dev)
-    cube = torch.empty(sc.nch, sc.ny, sc.nx, device=dev)
-    for _ in range(args.warmup):
-        rt.render(sc, out=cube)
-    torch.cuda.synchronize()
-    stream = torch.cuda.current_stream()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    gc.collect()
-    gc.disable()
-    t0 = time.perf_counter()
-    e0.record(stream)
-    for _ in range(args.steps):
-        rt.render(sc, out=cube)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    gc.enable()
-    kern_ms = e0.elapsed_time(e1) / args.steps
-    ms_per_step = wall * 1e3 / args.steps
-    rs = sc.ray_samples
-    value = rs / (wall / args.steps)
+    # the full-size render of each of the eight seeded disks of the family,
+    # each timed alike; the headline is the median rate
+    seeds = [args.seed] if args.one_disk else list(range(2000, 2008))
+    per_seed = {}
+    scenes = {}
+    cube = None
+    for sd in seeds:
+        prob_sd = synth.config2(sd)
+        sc_sd = rt.scene_from_problem(prob_sd, device=dev)
+        if cube is None:
+            cube = torch.empty(sc_sd.nch, sc_sd.ny, sc_sd.nx, device=dev)
+        cen = sc_sd.census()
+        wall_ms, kern_ms_sd = time_forward(rt, sc_sd, cube, args.steps, args.warmup)
+        rs_sd = sc_sd.ray_samples
+        per_seed[sd] = dict(ray_samples_per_s=rs_sd / (wall_ms * 1e-3), ms_per_step=wall_ms, kernel_ms=kern_ms_sd,
+                            ray_samples=rs_sd, live_fraction=cen["rays"] / (sc_sd.nx * sc_sd.ny),
+                            thin_fraction=cen["thin_pixel_samples"] / max(cen["pixel_samples"], 1),
+                            incl_deg=prob_sd.camera.incl_deg)
+        scenes[sd] = (prob_sd, sc_sd)
+        log(f"disk {sd}: {wall_ms:.3f} ms/step (kernel {kern_ms_sd:.3f} ms), "
+            f"{per_seed[sd]['ray_samples_per_s']:.3e} ray-samples/s")
+    rates = np.array([per_seed[sd]["ray_samples_per_s"] for sd in seeds])
+    value = float(np.median(rates))
+    # the disk at the median (the lower of the two middle ones) carries the roofline
+    med = seeds[int(np.argsort(rates)[(len(seeds) - 1) // 2])]
+    prob, sc = scenes[med]
+    ms_per_step = float(np.median([per_seed[sd]["ms_per_step"] for sd in seeds]))
+    kern_ms = per_seed[med]["kernel_ms"]
+    rs = per_seed[med]["ray_samples"]
+    thin = per_seed[med]["thin_fraction"]
     cb = rt.get_option(L.RT_OPT_CHANNEL_BLOCK) or auto_shape(sc.nch, sc.nx * sc.ny, sc.nsamp)[0]
-    flop, slots = algorithmic(sc.nch, cb)
+    flop, slots = algorithmic(sc.nch, cb, thin)
     achieved = flop * rs / (kern_ms * 1e-3) / 1e12
     peak = flop / slots * LANE_SLOTS_PER_S / 1e12
     out = {
@@ -232,19 +314,28 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "forward render 512x512 px x 64 ch x 512 samples/ray, 256x128 (r,z/r) grid, "
-                               f"seeded disk {args.seed} (3 gaps, incl {prob.camera.incl_deg:.1f} deg)",
-                   "global_batch": 1, "ray_samples": rs, "live_fraction": float(sc.live_mask().mean()),
+                               f"median over the seeded disks {seeds[0]}-{seeds[-1]} (3 gaps each; "
+                               f"roofline on disk {med}, incl {prob.camera.incl_deg:.1f} deg)",
+                   "global_batch": 1, "ray_samples": rs, "live_fraction": per_seed[med]["live_fraction"],
                    "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": measured_traffic(args.seed),
-                     "kernel": "march_fwd", "kernel_ms": kern_ms,
-                     "flop_per_ray_sample": flop, "issue_slots_per_ray_sample": slots,
+                     "frac": achieved / peak, "traffic": measured_traffic(med),
+                     "kernel": "march_fwd", "kernel_ms": kern_ms, "disk": med,
+                     "thin_fraction": thin, "flop_per_ray_sample": flop, "issue_slots_per_ray_sample": slots,
                      "hbm_bytes_algorithmic": 4 * sc.nch * sc.nx * sc.ny + 4 * (3 * sc.nr * sc.nz + 2 * sc.nr)},
+        "disks": {str(sd): v for sd, v in per_seed.items()},
     }
-    log(f"forward {ms_per_step:.3f} ms/step, {value:.3e} ray-samples/s")
-    if not args.no_disks:
-        log("forward over eight disks")
-        out["disks"] = bench_disks(rt, synth, dev, range(2000, 2008), max(5, args.steps // 2))
+    log(f"forward median {ms_per_step:.3f} ms/step, {value:.3e} ray-samples/s")
+    log("instruction-class issue rates")
+    mr = micro_rates(L)
+    if "loop_thick_ray_samples_per_s" in mr and "loop_thin_ray_samples_per_s" in mr:
+        # the march's measured mix: the channel loop at its measured rates
+        # (thin share on the series form) plus the shading's issue slots
+        sh = (SHADE_VALU + TRANS_SLOTS * SHADE_TRANS) / cb / LANE_SLOTS_PER_S
+        t_rs = (1.0 - thin) / mr["loop_thick_ray_samples_per_s"] + thin / mr["loop_thin_ray_samples_per_s"] + sh
+        mr["mix_roof_ray_samples_per_s"] = 1.0 / t_rs
+        out["roofline"]["frac_of_measured_mix"] = (rs / (kern_ms * 1e-3)) * t_rs
+    out["micro"] = mr
     if not args.no_mlp:
         log("neural CO layer")
         out["neural"] = bench_mlp(rt, synth, dev, args)
@@ -272,7 +363,7 @@ def main():
                                               out["saturated"]["serial_ray_samples_per_s"])
     if not args.no_cpu:
         log("oracle on the host cores")
-        out["cpu_baseline"] = cpu_baseline(prob, sc.live_mask(), args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(prob, sc.live_mask(), args.cpu_seconds, disk=med)
     print(json.dumps(out), flush=True)
 
 
@@ -614,28 +705,6 @@ def bench_mlp(rt, synth, dev, args):
     return out
 
 
-def bench_disks(rt, synth, dev, seeds, steps):
-    """Forward ray-samples/s on each full-size disk (seeded M*, inclination,
-    temperature index and gaps): the spread over disk geometry."""
-    import numpy as np
-    import torch
-    rates = {}
-    for sd in seeds:
-        prob = synth.config2(sd)
-        sc = rt.scene_from_problem(prob, device=dev)
-        cube = torch.empty(sc.nch, sc.ny, sc.nx, device=dev)
-        rt.render(sc, out=cube)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            rt.render(sc, out=cube)
-        torch.cuda.synchronize()
-        rates[str(sd)] = sc.ray_samples * steps / (time.perf_counter() - t0)
-    v = np.array(list(rates.values()))
-    return {"median_ray_samples_per_s": float(np.median(v)), "min": float(v.min()), "max": float(v.max()),
-            "per_seed": rates}
-
-
 def bench_serving(rt, synth, dev, seconds, rate=200.0, seed=5, pool=16, saturated=600):
     """Served stream of the full-size disk family: each request one of `pool`
     pre-generated seeded disks with pixels in {64..512}^2, channels in
@@ -675,10 +744,14 @@ def bench_serving(rt, synth, dev, seconds, rate=200.0, seed=5, pool=16, saturate
         return sv.submit(sc, cube)
 
     def serial_one(i):
+        # one request at a time with the library's direct calls: a render, or
+        # the fused forward + L2 loss + adjoint (the single-request path the
+        # server also takes for requests that fill the device)
         sc, key, g = reqs[i]
-        cube = rt.render(sc)
         if g is not None:
-            rt.render_adjoint(sc, 2.0 * (cube - targets[key]), want=keys)
+            rt.render_l2_adjoint(sc, targets[key], want=keys)
+        else:
+            rt.render(sc)
         torch.cuda.synchronize()
 
     def served_run(order, arrivals):

@@ -188,6 +188,18 @@ rt_status rt_render_cube_l2_adjoint_noalloc(const rt_problem *p, const float *ta
 /* Size in bytes of the fixed array rt_render_cube_l2_adjoint_noalloc uses. */
 uint64_t rt_noalloc_scratch_bytes(void);
 
+/* Work accounting of rt_render_cube on problem p (Methods > Line RT: a ray
+ * has samples only over its chord through the grid's bounding cylinder):
+ * counts[0] = rays that cross the cylinder (the others have no samples, zero
+ * intensity and no work), counts[1] = their pixel-samples, counts[2] = those
+ * pixel-samples whose line-centre depth is below the march's thin-sample
+ * threshold (taken with the series form of 1 - e^-dtau), or -1 for a problem
+ * with the network (its shading needs the network's outputs).  counts: [host]
+ * int64[3].  mask (device, [ny][nx] bytes, may be NULL) receives 1 for each
+ * crossing ray, 0 otherwise.  The march's own ray set-up and shading are
+ * used.  Synchronous: returns after the stream's work is done. */
+rt_status rt_render_census(const rt_problem *p, uint8_t *mask, int64_t *counts, void *stream);
+
 /* ------------------------------------------------------- derived fields */
 /* Fields derived from a temperature grid, as the physics-informed
  * constraints of Methods > Neural temperature recovery derive them (equations
@@ -391,6 +403,10 @@ rt_status rt_pack_fields3d(const rt_grid3d *grid, const float *ln_nh2, const flo
  * 1 - e^-dtau is evaluated directly.  RT_EINVAL on invalid arguments,
  * RT_EDEVICE if a launch fails. */
 rt_status rt_render_cube_3d(const rt_problem3d *p, float *cube, void *stream);
+/* Work accounting of rt_render_cube_3d, as rt_render_census: counts[0] =
+ * rays that cross the bounding sphere, counts[1] = their pixel-samples,
+ * counts[2] = -1; mask (device, [ny][nx] bytes, may be NULL).  Synchronous. */
+rt_status rt_render_census_3d(const rt_problem3d *p, uint8_t *mask, int64_t *counts, void *stream);
 
 /* ---------------------------------------------------------------- beam convolution
  *

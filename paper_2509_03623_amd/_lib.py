@@ -124,7 +124,8 @@ class rt_problem3d(C.Structure):
 
 # every symbol declared in include/rtcube.h
 EXPORTS = ["rt_render_cube", "rt_render_cube_adjoint", "rt_render_cube_l2_adjoint",
-           "rt_render_cube_l2_adjoint_noalloc", "rt_noalloc_scratch_bytes", "rt_derive_fields",
+           "rt_render_cube_l2_adjoint_noalloc", "rt_noalloc_scratch_bytes", "rt_render_census",
+           "rt_render_census_3d", "rt_derive_fields",
            "rt_derive_fields_adjoint", "rt_parametric_temperature", "rt_neural_temperature", "rt_neural_temperature_adjoint", "rt_adam_step",
            "rt_pack_fields3d", "rt_render_cube_3d", "rt_beam_convolve",
            "rt_server_create", "rt_submit", "rt_poll", "rt_wait",
@@ -158,6 +159,10 @@ def lib():
         L.rt_render_cube_l2_adjoint_noalloc.argtypes = [P, _dev, C.POINTER(rt_grads), _dev, _dev, C.c_void_p]
         L.rt_render_cube_l2_adjoint_noalloc.restype = C.c_int
         L.rt_noalloc_scratch_bytes.restype = C.c_uint64
+        L.rt_render_census.argtypes = [P, _dev, C.POINTER(C.c_int64), C.c_void_p]
+        L.rt_render_census.restype = C.c_int
+        L.rt_render_census_3d.argtypes = [C.POINTER(rt_problem3d), _dev, C.POINTER(C.c_int64), C.c_void_p]
+        L.rt_render_census_3d.restype = C.c_int
         L.rt_derive_fields.argtypes = [C.POINTER(rt_derive), C.POINTER(rt_derived), C.c_void_p]
         L.rt_derive_fields.restype = C.c_int
         L.rt_derive_fields_adjoint.argtypes = [C.POINTER(rt_derive), C.POINTER(rt_derived), _dev, C.c_void_p]

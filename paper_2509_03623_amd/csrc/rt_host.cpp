@@ -224,6 +224,14 @@ void *stream_workspace(hipStream_t st, int slot, size_t bytes, hipError_t *err) 
     return b.p;
 }
 
+size_t stream_workspace_bytes(hipStream_t st) {
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    size_t n = 0;
+    for (const auto &kv : g_ws)
+        if (kv.first.st == st) n += kv.second.bytes;
+    return n;
+}
+
 void release_stream_workspaces(hipStream_t st) {
     std::lock_guard<std::mutex> lk(g_ws_mu);
     for (auto it = g_ws.begin(); it != g_ws.end();) {

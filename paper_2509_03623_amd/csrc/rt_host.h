@@ -41,8 +41,10 @@ void *stream_workspace(hipStream_t st, int slot, size_t bytes, hipError_t *err);
 // bytes a workspace of `bytes` actually holds (the growth step rounds up)
 size_t workspace_round(size_t bytes);
 void release_stream_workspaces(hipStream_t st);
+// bytes the stream's workspaces hold
+size_t stream_workspace_bytes(hipStream_t st);
 constexpr int kWsAdjoint = 0, kWsGradAcc = 1, kWsChain = 2, kWsNeuralT = 3, kWsBeam = 4, kWsBeamCube = 5,
-              kWsGradBatch = 6;
+              kWsGradBatch = 6, kWsCensus = 7;
 // default largest adjoint scratch (tape, checkpoints, cotangents) of one pass
 // over a band of image rows; larger images are processed band by band
 constexpr size_t kAdjointScratchCap = (size_t)8 << 30;

@@ -330,6 +330,55 @@ static void forward_shape3(int nch, long npix, int nsamp, int *cb_out, int *spli
     *split_out = ns;
 }
 
+// camera and bounding sphere of a 3-D problem
+static Geometry3 geometry3(const rt_problem3d *p) {
+    const rt_grid3d &gr = p->grid;
+    const double dln = std::log(gr.r_max_au / gr.r_min_au) / (gr.nr - 1);
+    const double ang = p->cam.incl_deg * kPI3 / 180.0, pa = p->cam.pa_deg * kPI3 / 180.0;
+    Geometry3 g;
+    std::memset(&g, 0, sizeof g);
+    g.d_pix = p->cam.fov_au / p->cam.nx;
+    g.cpa = std::cos(pa);
+    g.spa = std::sin(pa);
+    g.si = std::sin(ang);
+    g.ci = std::cos(ang);
+    if (p->cam.incl_deg == 0.0) { g.si = 0.0; g.ci = 1.0; }
+    if (p->cam.incl_deg == 90.0) { g.si = 1.0; g.ci = 0.0; }
+    if (p->cam.incl_deg == 180.0) { g.si = 0.0; g.ci = -1.0; }
+    const double rc = gr.r_max_au * std::exp(dln);
+    g.rc2 = rc * rc;
+    g.xc = 0.5 * p->cam.nx;
+    g.yc = 0.5 * p->cam.ny;
+    g.nx = p->cam.nx;
+    g.ny = p->cam.ny;
+    g.nsamp = p->nsamp;
+    return g;
+}
+
+// rays of a 3-D render that cross the bounding sphere (the march's own test)
+__global__ __launch_bounds__(256) void census3(Geometry3 g, uint8_t *__restrict__ mask,
+                                               unsigned long long *__restrict__ count) {
+    __shared__ unsigned long long part;
+    if (threadIdx.x == 0) part = 0ull;
+    __syncthreads();
+    const int pix = blockIdx.x * 256 + threadIdx.x;
+    if (pix < g.nx * g.ny) {
+        const int p = pix % g.nx, q = pix / g.nx;
+        const double X = ((double)p + 0.5 - g.xc) * g.d_pix;
+        const double Y = ((double)q + 0.5 - g.yc) * g.d_pix;
+        const double xp = g.cpa * X - g.spa * Y, yp = g.spa * X + g.cpa * Y;
+        const bool live = g.rc2 - xp * xp - yp * yp > 0.0;
+        if (mask) mask[pix] = live ? 1 : 0;
+        if (live) atomicAdd(&part, 1ull);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && part) atomicAdd(count, part);
+}
+
+__global__ void census3_zero(unsigned long long *c) {
+    if (threadIdx.x == 0) *c = 0ull;
+}
+
 static rt_status validate_grid3(const rt_grid3d *g) {
     if (!g) return fail(RT_EINVAL, "grid is NULL");
     if (g->nr < 2 || g->nt < 2 || g->np < 1)
@@ -364,6 +413,31 @@ rt_status rt_pack_fields3d(const rt_grid3d *grid, const float *ln_nh2, const flo
     return e == hipSuccess ? RT_OK : fail_hip(e, "pack launch");
 }
 
+rt_status rt_render_census_3d(const rt_problem3d *p, uint8_t *mask, int64_t *counts, void *stream) {
+    if (!p) return fail(RT_EINVAL, "problem is NULL");
+    rt_status st = validate_grid3(&p->grid);
+    if (st != RT_OK) return st;
+    st = validate_view(p->line, p->cam, p->spec, p->nsamp, p->intensity_scale, 180.0);
+    if (st != RT_OK) return st;
+    if (!counts) return fail(RT_EINVAL, "counts is NULL");
+    const Geometry3 g = geometry3(p);
+    hipStream_t hs = (hipStream_t)stream;
+    hipError_t e;
+    unsigned long long *d = (unsigned long long *)stream_workspace(hs, kWsCensus, sizeof(unsigned long long), &e);
+    if (!d) return fail_hip(e, "census counter");
+    const int npix = p->cam.nx * p->cam.ny;
+    hipLaunchKernelGGL(census3_zero, dim3(1), dim3(64), 0, hs, d);
+    hipLaunchKernelGGL(census3, dim3((npix + 255) / 256), dim3(256), 0, hs, g, mask, d);
+    unsigned long long h = 0;
+    if ((e = hipGetLastError()) == hipSuccess) e = hipMemcpyAsync(&h, d, sizeof h, hipMemcpyDeviceToHost, hs);
+    if (e == hipSuccess) e = hipStreamSynchronize(hs);
+    if (e != hipSuccess) return fail_hip(e, "3-D census");
+    counts[0] = (int64_t)h;
+    counts[1] = (int64_t)h * p->nsamp;
+    counts[2] = -1;
+    return RT_OK;
+}
+
 rt_status rt_render_cube_3d(const rt_problem3d *p, float *cube, void *stream) {
     if (!p) return fail(RT_EINVAL, "problem is NULL");
     rt_status st = validate_grid3(&p->grid);
@@ -383,24 +457,7 @@ rt_status rt_render_cube_3d(const rt_problem3d *p, float *cube, void *stream) {
                      kAU = 1.495978707e13, kZT0 = 0.1, kZT1 = 1.0e4;
     const double dln = std::log(gr.r_max_au / gr.r_min_au) / (gr.nr - 1);
     const double dth = (gr.th_max - gr.th_min) / (gr.nt - 1);
-    const double ang = p->cam.incl_deg * kPI3 / 180.0, pa = p->cam.pa_deg * kPI3 / 180.0;
-    Geometry3 g;
-    std::memset(&g, 0, sizeof g);
-    g.d_pix = p->cam.fov_au / p->cam.nx;
-    g.cpa = std::cos(pa);
-    g.spa = std::sin(pa);
-    g.si = std::sin(ang);
-    g.ci = std::cos(ang);
-    if (p->cam.incl_deg == 0.0) { g.si = 0.0; g.ci = 1.0; }
-    if (p->cam.incl_deg == 90.0) { g.si = 1.0; g.ci = 0.0; }
-    if (p->cam.incl_deg == 180.0) { g.si = 0.0; g.ci = -1.0; }
-    const double rc = gr.r_max_au * std::exp(dln);
-    g.rc2 = rc * rc;
-    g.xc = 0.5 * p->cam.nx;
-    g.yc = 0.5 * p->cam.ny;
-    g.nx = p->cam.nx;
-    g.ny = p->cam.ny;
-    g.nsamp = p->nsamp;
+    const Geometry3 g = geometry3(p);
     Shade3 s;
     std::memset(&s, 0, sizeof s);
     s.node = (const float4 *)p->nodes;

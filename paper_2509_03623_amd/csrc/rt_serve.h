@@ -31,10 +31,13 @@ hipError_t launch_serve_fwd(const ServeDesc *descs, int nreq, uint32_t nitems, u
 // Batched gradient requests (forward + L2 loss + adjoint of grid fields):
 // the reverse march runs kGradCB channels per lane, two lanes per pixel, so a
 // cotangent slice covers 2 kGradCB channels; tape items split each tile's
-// samples into kGradTapeChunks chunks; chain items are runs of 256
-// pixel-samples.
+// samples into kGradTapeChunks chunks; chain items are (field pass, chunk of
+// about kGradChainChunk pixel-samples) of one request, accumulated by a
+// 1024-lane workgroup in LDS and flushed once.
 constexpr int kGradCB = 16;
 constexpr int kGradTapeChunks = 4;
+constexpr int kGradChainThreads = 1024;
+constexpr long kGradChainChunk = 64L * kGradChainThreads;
 
 struct GradDesc {
     Geometry g;
@@ -48,12 +51,17 @@ struct GradDesc {
     double *loss;              // L of this request
     int32_t nch, nblk;         // channels, cotangent slices (of 2 kGradCB channels)
     uint32_t item0[3];         // first item of this request in the tape, march and chain passes
+    int32_t nfp;               // chain field passes (>= 1; the first also takes the surfaces)
+    int32_t fields[3];         // field of each pass: 0 ln n, 1 T, 2 v_phi, 3 none (surfaces only)
+    uint32_t chunks;           // chain chunks per field pass
 };
 
 // scratch bytes of one batched gradient request (tape, rays, cotangents, accumulators)
 size_t grad_batch_scratch_bytes(int nch, long npix, int nsamp, long nr, long nz);
-// items of one request in the three passes
-void grad_batch_items(int nch, long npix, int nsamp, uint32_t items[3]);
+// items of one request in the three passes (nfp chain field passes)
+void grad_batch_items(int nch, long npix, int nsamp, int nfp, uint32_t items[3], uint32_t *chunks);
+// whether a grid's chain accumulators fit the LDS of one workgroup
+bool grad_batch_grid_fits(int nr, int nz);
 // zero -> tape -> reverse march -> chain -> outputs and losses, on one stream;
 // counters: 3 device words
 hipError_t launch_grad_batch(const GradDesc *descs, const GradDesc *host_descs, int nreq, const uint32_t nitems[3],

@@ -10,9 +10,9 @@
 //   march  -- (request, 128-pixel tile, slice of 2 x 16 channels): the
 //             checkpoint-free reverse march with the intensity formed in the
 //             march, writing the cube and the per-sample cotangents;
-//   chain  -- (request, run of 256 pixel-samples): the shading's local
-//             derivatives, scattered to the request's FP64 accumulators with
-//             atomics;
+//   chain  -- (request, field pass, chunk of pixel-samples): the shading's
+//             local derivatives, accumulated in LDS by a 1024-lane workgroup
+//             and flushed once into the request's FP64 accumulators;
 // then one launch writes every request's gradients (FP64 -> FP32) and one its
 // loss.  A request's items are those of its own problem and its results go
 // to its own buffers, so what it gets does not depend on the rest of the
@@ -33,12 +33,23 @@ size_t grad_batch_scratch_bytes(int nch, long npix, int nsamp, long nr, long nz)
            al256(sizeof(float4) * nblk * nsamp * npix) + al256(sizeof(double) * (size_t)(3 * nr * nz + 2 * nr));
 }
 
-void grad_batch_items(int nch, long npix, int nsamp, uint32_t items[3]) {
+void grad_batch_items(int nch, long npix, int nsamp, int nfp, uint32_t items[3], uint32_t *chunks) {
     const long nblk = (nch + 2 * kGradCB - 1) / (2 * kGradCB);
     items[0] = (uint32_t)(((npix + 255) / 256) * kGradTapeChunks);
     items[1] = (uint32_t)(((npix + 127) / 128) * nblk);
-    items[2] = (uint32_t)(((size_t)nsamp * npix + 255) / 256);
+    *chunks = (uint32_t)std::max<size_t>(1, ((size_t)nsamp * npix + kGradChainChunk - 1) / kGradChainChunk);
+    items[2] = (uint32_t)nfp * *chunks;
 }
+
+// LDS of the chain pass: one field of the grid (float) and the two surface
+// vectors (double), beside the partition table
+constexpr size_t kGradChainLdsMax = 160 * 1024 - sizeof(float4) * (kZTableNodes - 1) - 1024;
+
+static size_t chain_lds_bytes(int nr, int nz) {
+    return 2 * (size_t)nr * sizeof(double) + (size_t)nr * nz * sizeof(float);
+}
+
+bool grad_batch_grid_fits(int nr, int nz) { return chain_lds_bytes(nr, nz) <= kGradChainLdsMax; }
 
 // the request owning item `item` of pass `pass`: the last whose first item is <= item
 __device__ __forceinline__ int owner(const GradDesc *__restrict__ descs, int nreq, int pass, uint32_t item) {
@@ -134,8 +145,16 @@ __global__ __launch_bounds__(256) void grad_march(const GradDesc *__restrict__ d
     }
 }
 
-__global__ __launch_bounds__(256) void grad_chain(const GradDesc *__restrict__ descs, int nreq, uint32_t nitems,
-                                                  uint32_t *__restrict__ counter) {
+// Chain pass: each item is one field pass over a contiguous chunk of one
+// request's pixel-samples.  The workgroup (1024 lanes, one per CU) clears
+// that field's grid in LDS, adds every sample's bilinear contributions there
+// (and, in the request's first field pass, the two surfaces' in LDS doubles),
+// then flushes the nodes it touched into the request's FP64 accumulators.
+// Every pass sums the request's cotangent slices itself, so passes of one
+// request may run at the same time.
+__global__ __launch_bounds__(kGradChainThreads) void grad_chain(const GradDesc *__restrict__ descs, int nreq,
+                                                               uint32_t nitems, uint32_t *__restrict__ counter) {
+    extern __shared__ double dyn[];   // [2 nr] surfaces, then [nr nz] field (float)
     __shared__ float4 ztab[kZTableNodes - 1];
     __shared__ uint32_t s_item;
     __shared__ const float4 *s_tab;
@@ -143,42 +162,74 @@ __global__ __launch_bounds__(256) void grad_chain(const GradDesc *__restrict__ d
     for (;;) {
         const uint32_t item = next_item(counter, &s_item);
         if (item >= nitems) break;
-        const GradDesc D = descs[owner(descs, nreq, 2, item)];
-        stage_table(D.s.ztab, ztab, &s_tab);
+        const GradDesc &D = descs[owner(descs, nreq, 2, item)];   // uniform: scalar loads
+        if (s_tab != D.s.ztab) {
+            __syncthreads();
+            for (int i = threadIdx.x; i < kZTableNodes - 1; i += kGradChainThreads) ztab[i] = D.s.ztab[i];
+            __syncthreads();
+            if (threadIdx.x == 0) s_tab = D.s.ztab;
+        }
+        const uint32_t local = item - D.item0[2];
+        const int fp = (int)(local / D.chunks), chunk = (int)(local % D.chunks);
+        const int field = D.fields[fp];
+        const bool surf = fp == 0 && (D.out[3] || D.out[4]);
+        const int nr = D.s.nr, nn = D.s.nr * D.s.nz;
+        double *sl = dyn;
+        float *fl = (float *)(dyn + 2 * nr);
+        if (surf)
+            for (int i = threadIdx.x; i < 2 * nr; i += kGradChainThreads) sl[i] = 0.0;
+        if (field < 3)
+            for (int i = threadIdx.x; i < nn; i += kGradChainThreads) fl[i] = 0.0f;
+        __syncthreads();
         const int npix = D.g.nx * D.g.ny, nsamp = D.g.nsamp;
-        const size_t idx = (size_t)(item - D.item0[2]) * 256 + threadIdx.x;
-        if (idx >= (size_t)nsamp * npix) continue;
-        const int k = (int)(idx / npix);
-        const int pix = (int)(idx - (size_t)k * npix);
-        const float4 rr = D.rays[pix];
-        float4 c = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        for (int b = 0; b < D.nblk; ++b) {
-            const float4 t = D.cot[((size_t)b * nsamp + k) * npix + pix];
-            c.x += t.x; c.y += t.y; c.z += t.z; c.w += t.w;
+        const size_t total = (size_t)nsamp * npix;
+        const size_t len = (total + D.chunks - 1) / D.chunks;
+        const size_t i0 = (size_t)chunk * len, i1 = min(total, i0 + len);
+        for (size_t idx = i0 + threadIdx.x; idx < i1; idx += kGradChainThreads) {
+            const int k = (int)(idx / npix);
+            const int pix = (int)(idx - (size_t)k * npix);
+            const float4 rr = D.rays[pix];
+            float4 c = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            for (int b = 0; b < D.nblk; ++b) {
+                const float4 t = D.cot[((size_t)b * nsamp + k) * npix + pix];
+                c.x += t.x; c.y += t.y; c.z += t.z; c.w += t.w;
+            }
+            if (!(rr.w > 0.0f) || (c.x == 0.0f && c.y == 0.0f && c.z == 0.0f && c.w == 0.0f)) continue;
+            const ChainTerms t = chain_terms(D.g, D.s, ztab, rr, c, k, pix);
+            const float fu = t.fu, fv = t.fv;
+            if (field < 3) {
+                const float gv = field == 0 ? t.gn : (field == 1 ? t.gT : t.gV);
+                if (gv != 0.0f) {
+                    const int n00 = t.i0 * D.s.nz + t.j0, n10 = n00 + D.s.nz;
+                    atomicAdd(fl + n00, gv * (1.0f - fu) * (1.0f - fv));
+                    atomicAdd(fl + n00 + 1, gv * (1.0f - fu) * fv);
+                    atomicAdd(fl + n10, gv * fu * (1.0f - fv));
+                    atomicAdd(fl + n10 + 1, gv * fu * fv);
+                }
+            }
+            if (surf) {
+                if (t.gzl != 0.0f) {
+                    atomicAdd(sl + t.i0, (double)(t.gzl * (1.0f - fu)));
+                    atomicAdd(sl + t.i0 + 1, (double)(t.gzl * fu));
+                }
+                if (t.gzu != 0.0f) {
+                    atomicAdd(sl + nr + t.i0, (double)(t.gzu * (1.0f - fu)));
+                    atomicAdd(sl + nr + t.i0 + 1, (double)(t.gzu * fu));
+                }
+            }
         }
-        if (!(rr.w > 0.0f) || (c.x == 0.0f && c.y == 0.0f && c.z == 0.0f && c.w == 0.0f)) continue;
-        const ChainTerms t = chain_terms(D.g, D.s, ztab, rr, c, k, pix);
-        const size_t nn = (size_t)D.s.nr * D.s.nz;
-        const float fu = t.fu, fv = t.fv;
-        const float w[4] = {(1.0f - fu) * (1.0f - fv), (1.0f - fu) * fv, fu * (1.0f - fv), fu * fv};
-        const int n00 = t.i0 * D.s.nz + t.j0;
-        const int node[4] = {n00, n00 + 1, n00 + D.s.nz, n00 + D.s.nz + 1};
-        const float gf[3] = {t.gn, t.gT, t.gV};
-#pragma unroll
-        for (int f = 0; f < 3; ++f) {
-            if (!D.out[f] || gf[f] == 0.0f) continue;
-            double *a = D.acc + f * nn;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) atomicAdd(a + node[j], (double)(gf[f] * w[j]));
+        __syncthreads();
+        if (field < 3) {
+            double *dst = D.acc + (size_t)field * nn;
+            for (int i = threadIdx.x; i < nn; i += kGradChainThreads)
+                if (fl[i] != 0.0f) atomicAdd(dst + i, (double)fl[i]);
         }
-        double *zl = D.acc + 3 * nn, *zu = zl + D.s.nr;
-        if (D.out[3] && t.gzl != 0.0f) {
-            atomicAdd(zl + t.i0, (double)(t.gzl * (1.0f - fu)));
-            atomicAdd(zl + t.i0 + 1, (double)(t.gzl * fu));
-        }
-        if (D.out[4] && t.gzu != 0.0f) {
-            atomicAdd(zu + t.i0, (double)(t.gzu * (1.0f - fu)));
-            atomicAdd(zu + t.i0 + 1, (double)(t.gzu * fu));
+        if (surf) {
+            double *zl = D.acc + 3 * (size_t)nn, *zu = zl + nr;
+            for (int i = threadIdx.x; i < nr; i += kGradChainThreads) {
+                if (D.out[3] && sl[i] != 0.0) atomicAdd(zl + i, sl[i]);
+                if (D.out[4] && sl[nr + i] != 0.0) atomicAdd(zu + i, sl[nr + i]);
+            }
         }
     }
 }
@@ -233,7 +284,17 @@ hipError_t launch_grad_batch(const GradDesc *descs, const GradDesc *host_descs, 
                        descs);
     hipLaunchKernelGGL(grad_tape, dim3(nwg), dim3(256), 0, st, descs, nreq, nitems[0], counters);
     hipLaunchKernelGGL(grad_march, dim3(nwg), dim3(256), 0, st, descs, nreq, nitems[1], counters + 1);
-    hipLaunchKernelGGL(grad_chain, dim3(nwg), dim3(256), 0, st, descs, nreq, nitems[2], counters + 2);
+    int dev = 0, ncu = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    size_t lds = 0;
+    for (int i = 0; i < nreq; ++i) lds = std::max(lds, chain_lds_bytes(host_descs[i].s.nr, host_descs[i].s.nz));
+    if ((e = hipFuncSetAttribute((const void *)grad_chain, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)) !=
+        hipSuccess)
+        return e;
+    hipLaunchKernelGGL(grad_chain, dim3(std::max<int>(1, std::min<int>(ncu, (int)nitems[2]))), dim3(kGradChainThreads),
+                       lds, st, descs, nreq, nitems[2], counters + 2);
     hipLaunchKernelGGL(grad_finish, dim3((unsigned)std::min<size_t>((max_acc + 255) / 256, 64), nreq), dim3(256), 0,
                        st, descs);
     hipLaunchKernelGGL(grad_loss, dim3((unsigned)std::min<size_t>((max_cube + 255) / 256, 128), nreq), dim3(256), 0,

@@ -20,10 +20,10 @@
 // own request (each ray is marched by one lane with the same code whatever
 // else is in the batch); a gradient request's routing depends only on its
 // own shape, and its result on the rest of its batch only through the order
-// of the FP64 atomic additions.  The library scratch of a launch (a stream's
-// workspaces) is released when the launch retires, so the device memory the
-// server holds beyond the callers' buffers is that of the running launches,
-// whose footprints admission keeps within the budget.
+// of the FP64 atomic additions.  Device memory: the budget covers the
+// footprints of admitted requests plus the library scratch that idle streams
+// keep for their next launch (reusing it saves a fresh mapping per launch);
+// when a request does not fit, the idle streams' scratch is released first.
 #include <hip/hip_runtime.h>
 
 #include <chrono>
@@ -76,6 +76,8 @@ struct Lane {
     double *d_loss = nullptr, *h_loss = nullptr;
     GradDesc *d_gdesc = nullptr, *h_gdesc = nullptr;
     uint32_t *d_gcount = nullptr;   // item counters of the three batched gradient passes
+    uint64_t retained = 0;          // scratch the idle stream keeps (charged to the budget)
+    uint64_t excess = 0;            // that scratch, charged to the running launch
 };
 
 __global__ void zero_u32(uint32_t *p) { *p = 0u; }
@@ -92,7 +94,8 @@ struct rt_server {
     uint64_t next_id = 1;
     std::map<uint64_t, std::unique_ptr<Req>> tickets;
     std::deque<Req *> pending, admitted;
-    uint64_t budget_used = 0;
+    uint64_t budget_used = 0;      // footprints of admitted requests, plus scratch held by running launches
+    uint64_t retained_idle = 0;    // scratch held by idle streams
     int slots_used = 0;
     std::vector<Lane> lanes;
 };
@@ -141,6 +144,15 @@ void finish(rt_server *sv, Req *r, int status) {
     r->t_done = now_ns();
     sv->budget_used -= r->footprint;
     sv->slots_used -= 1;
+}
+
+// a lane's launch is over: its charged scratch leaves the running total and
+// what its stream now keeps is charged as idle
+void lane_retired(rt_server *sv, Lane &L) {
+    sv->budget_used -= L.excess;
+    L.excess = 0;
+    L.retained = stream_workspace_bytes(L.st);
+    sv->retained_idle += L.retained;
 }
 
 rt_status lane_vch_capacity(Lane &L, size_t n) {
@@ -258,8 +270,13 @@ rt_status launch_grad(rt_server *sv, Lane &L, std::vector<Req *> &batch) {
         D.out[3] = q.grads.d_z_lo_au;
         D.out[4] = q.grads.d_z_up_au;
         D.loss = L.d_loss + i;
+        // chain field passes: each requested field; the first also takes the surfaces
+        D.nfp = 0;
+        for (int f = 0; f < 3; ++f)
+            if (D.out[f]) D.fields[D.nfp++] = f;
+        if (D.nfp == 0) D.fields[D.nfp++] = 3;
         uint32_t n[3];
-        grad_batch_items(nch, (long)npix, p.nsamp, n);
+        grad_batch_items(nch, (long)npix, p.nsamp, D.nfp, n, &D.chunks);
         for (int k = 0; k < 3; ++k) {
             D.item0[k] = items[k];
             items[k] += n[k];
@@ -326,8 +343,7 @@ void scheduler(rt_server *sv) {
                 if (r->rq.kind != RT_REQ_FWD) r->loss = L.h_loss[i];
                 finish(sv, r, q == hipSuccess ? RT_OK : RT_EDEVICE);
             }
-            // the launch's library scratch goes back with its footprint
-            release_stream_workspaces(L.st);
+            lane_retired(sv, L);
             L.reqs.clear();
             L.busy = false;
             progress = true;
@@ -335,8 +351,18 @@ void scheduler(rt_server *sv) {
         // 2. admission in arrival order, by footprint and slots
         while (!sv->pending.empty()) {
             Req *r = sv->pending.front();
-            if (sv->slots_used >= sv->cfg.max_slots || sv->budget_used + r->footprint > sv->cfg.hbm_budget_bytes)
-                break;
+            if (sv->slots_used >= sv->cfg.max_slots) break;
+            auto fits = [&] { return sv->budget_used + sv->retained_idle + r->footprint <= sv->cfg.hbm_budget_bytes; };
+            if (!fits() && sv->retained_idle > 0) {
+                // make room: the idle streams give their scratch back
+                for (Lane &L : sv->lanes) {
+                    if (L.busy || L.retained == 0) continue;
+                    release_stream_workspaces(L.st);
+                    sv->retained_idle -= L.retained;
+                    L.retained = 0;
+                }
+            }
+            if (!fits()) break;
             sv->pending.pop_front();
             sv->budget_used += r->footprint;
             sv->slots_used += 1;
@@ -364,6 +390,11 @@ void scheduler(rt_server *sv) {
                     }
                 }
             }
+            // the scratch this stream keeps is now the running launch's
+            sv->retained_idle -= L.retained;
+            L.excess = L.retained;
+            L.retained = 0;
+            sv->budget_used += L.excess;
             // launch without holding the lock, so submissions are not held up
             // (the batch and the lane belong to this thread until then)
             lk.unlock();
@@ -378,6 +409,7 @@ void scheduler(rt_server *sv) {
                 (void)hipStreamSynchronize(L.st);
                 release_stream_workspaces(L.st);
                 for (Req *r : batch) finish(sv, r, rs != RT_OK ? rs : RT_EDEVICE);
+                lane_retired(sv, L);
                 continue;
             }
             L.reqs = batch;
@@ -476,10 +508,14 @@ rt_status rt_submit(rt_server *sv, const rt_request *rq, uint64_t *ticket) {
     const uint64_t device_lanes = (uint64_t)sv->ncu * kServeWorkgroupsPerCU * 256;
     const uint64_t serve_lanes = (uint64_t)p.cam.nx * p.cam.ny * ((p.spec.nch + 15) / 16) * kServeSplit;
     // lanes of a gradient request in the batched reverse march: two per
-    // pixel and slice of 2 kGradCB channels
+    // pixel and slice of 2 kGradCB channels.  Measured per request (eight of
+    // one shape, batched vs the fused single-request path, ms): 64^2 x 16 x
+    // 256 0.41 vs 0.54, 64^2 x 64 x 512 0.59 vs 1.03, 128^2 x 32 x 256 0.52 vs
+    // 0.67, but 128^2 x 128 x 384 1.53 vs 1.35 and 256^2 x 16 x 256 1.31 vs
+    // 1.00: requests under a quarter of the device's resident lanes batch.
     const uint64_t grad_lanes = (uint64_t)p.cam.nx * p.cam.ny * ((p.spec.nch + 2 * kGradCB - 1) / (2 * kGradCB)) * 2;
     if (rq->kind == RT_REQ_FWD_ADJ) {
-        r->grad_batch = p.mlp == nullptr && grad_lanes < device_lanes;
+        r->grad_batch = p.mlp == nullptr && grad_lanes < device_lanes / 4 && grad_batch_grid_fits(p.grid.nr, p.grid.nz);
         r->own_stream = !r->grad_batch;
     } else {
         r->own_stream = p.mlp != nullptr || serve_lanes >= device_lanes;

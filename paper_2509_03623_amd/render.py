@@ -56,54 +56,35 @@ class Scene:
     mlp_precision: int = L.RT_MLP_BF16
     keep: list = field(default_factory=list, repr=False)
     _struct: tuple = field(default=None, repr=False, compare=False)
-    _live: int = field(default=None, repr=False, compare=False)
+    _live: Optional[dict] = field(default=None, repr=False, compare=False)
 
     @property
     def nch(self) -> int:
         return int(len(self.v_kms))
 
+    def census(self, stream=None) -> dict:
+        """The library's work accounting of this render (rt_render_census):
+        the [ny, nx] bool mask of rays that cross the grid's bounding
+        cylinder (the others have no samples: zero intensity, no work), their
+        number, their pixel-samples, and how many of those the march takes
+        as optically thin (-1 with the network)."""
+        if self._live is None:
+            mask = torch.empty(self.ny, self.nx, dtype=torch.uint8, device=self.ln_nh2.device)
+            counts = (C.c_int64 * 3)()
+            p, keep = problem_struct(self)
+            L.check(L.lib().rt_render_census(C.byref(p), mask.data_ptr(), counts, C.c_void_p(_stream(stream))))
+            object.__setattr__(self, "_live", dict(mask=mask.cpu().numpy().astype(bool), rays=int(counts[0]),
+                                                   pixel_samples=int(counts[1]), thin_pixel_samples=int(counts[2])))
+        return self._live
+
     def live_mask(self) -> np.ndarray:
-        """[ny, nx] bool: pixels whose ray crosses the grid's bounding cylinder
-        (r <= r_max e^dln, |z| <= (zr_max + d(z/r)) r_max e^dln), the same test
-        as the march's ray set-up.  The other rays have no samples (their
-        intensity is exactly zero) and no work is done for them."""
-        dln = math.log(self.r_max_au / self.r_min_au) / (self.nr - 1)
-        rc = self.r_max_au * math.exp(dln)
-        zc = (self.zr_max + self.zr_max / (self.nz - 1)) * rc
-        ang, pa = math.radians(self.incl_deg), math.radians(self.pa_deg)
-        si, ci = math.sin(ang), math.cos(ang)
-        if self.incl_deg == 0.0:
-            si, ci = 0.0, 1.0
-        if self.incl_deg == 90.0:
-            si, ci = 1.0, 0.0
-        d = self.fov_au / self.nx
-        X = (np.arange(self.nx) + 0.5 - 0.5 * self.nx) * d
-        Y = (np.arange(self.ny) + 0.5 - 0.5 * self.ny) * d
-        X, Y = np.meshgrid(X, Y)
-        xp = math.cos(pa) * X - math.sin(pa) * Y
-        yp = math.sin(pa) * X + math.cos(pa) * Y
-        ok = xp * xp < rc * rc
-        qq = np.sqrt(np.maximum(rc * rc - xp * xp, 0.0))
-        lo = np.full(xp.shape, -1e300)
-        hi = np.full(xp.shape, 1e300)
-        if si > 0.0:
-            lo = np.maximum(lo, (-yp * ci - qq) / si)
-            hi = np.minimum(hi, (-yp * ci + qq) / si)
-        else:
-            ok &= np.abs(yp * ci) <= qq
-        if ci > 0.0:
-            lo = np.maximum(lo, (yp * si - zc) / ci)
-            hi = np.minimum(hi, (yp * si + zc) / ci)
-        else:
-            ok &= np.abs(yp * si) <= zc
-        return ok & (hi > lo)
+        """[ny, nx] bool: pixels whose ray crosses the grid's bounding volume."""
+        return self.census()["mask"]
 
     @property
     def ray_samples(self) -> int:
         """(pixel, channel, sample) triples of the rays that cross the grid."""
-        if self._live is None:
-            self._live = int(self.live_mask().sum())
-        return self._live * self.nch * self.nsamp
+        return self.census()["pixel_samples"] * self.nch
 
     def replace(self, **kw) -> "Scene":
         return replace(self, _struct=None, _live=None, **kw)
@@ -418,19 +399,24 @@ class Scene3d:
     def nch(self) -> int:
         return int(len(self.v_kms))
 
+    def census(self, stream=None) -> dict:
+        """The library's work accounting of this 3-D render
+        (rt_render_census_3d): the [ny, nx] bool mask of rays that cross the
+        bounding sphere r <= r_max e^dln, their number and pixel-samples."""
+        mask = torch.empty(self.ny, self.nx, dtype=torch.uint8, device=self.nodes.device)
+        counts = (C.c_int64 * 3)()
+        p, keep = _problem3d(self)
+        L.check(L.lib().rt_render_census_3d(C.byref(p), mask.data_ptr(), counts, C.c_void_p(_stream(stream))))
+        return dict(mask=mask.cpu().numpy().astype(bool), rays=int(counts[0]), pixel_samples=int(counts[1]))
+
     def live_mask(self) -> np.ndarray:
-        """[ny, nx] bool: pixels whose ray crosses the bounding sphere r <= r_max e^dln."""
-        nr, r_min, r_max = int(self.grid[0]), float(self.grid[3]), float(self.grid[4])
-        rc = r_max * math.exp(math.log(r_max / r_min) / (nr - 1))
-        d = self.fov_au / self.nx
-        X = (np.arange(self.nx) + 0.5 - 0.5 * self.nx) * d
-        Y = (np.arange(self.ny) + 0.5 - 0.5 * self.ny) * d
-        return X[None, :] ** 2 + Y[:, None] ** 2 < rc * rc
+        """[ny, nx] bool: pixels whose ray crosses the bounding sphere."""
+        return self.census()["mask"]
 
     @property
     def ray_samples(self) -> int:
         """(pixel, channel, sample) triples of the rays that cross the grid."""
-        return int(self.live_mask().sum()) * self.nch * self.nsamp
+        return self.census()["pixel_samples"] * self.nch
 
     def replace(self, **kw) -> "Scene3d":
         return replace(self, **kw)
@@ -485,6 +471,13 @@ def render3d(sc: Scene3d, out: Optional[torch.Tensor] = None, stream=None) -> to
         out = torch.empty(sc.nch, sc.ny, sc.nx, dtype=torch.float32, device=sc.nodes.device)
     if out.shape != (sc.nch, sc.ny, sc.nx):
         raise ValueError("output has the wrong shape")
+    p, keep = _problem3d(sc)
+    L.check(L.lib().rt_render_cube_3d(C.byref(p), _fptr(out), C.c_void_p(_stream(stream))))
+    return out
+
+
+def _problem3d(sc: Scene3d):
+    """(rt_problem3d, keepalive) of a 3-D scene."""
     lev_e = np.ascontiguousarray(sc.lev_e_k, np.float64)
     lev_g = np.ascontiguousarray(sc.lev_g, np.float64)
     vk = np.ascontiguousarray(sc.v_kms, np.float64)
@@ -499,8 +492,7 @@ def render3d(sc: Scene3d, out: Optional[torch.Tensor] = None, stream=None) -> to
     p.spec = L.rt_spectral(len(vk), vk.ctypes.data_as(C.POINTER(C.c_double)), sc.v_sys_kms)
     p.nsamp = sc.nsamp
     p.intensity_scale = sc.intensity_scale
-    L.check(L.lib().rt_render_cube_3d(C.byref(p), _fptr(out), C.c_void_p(_stream(stream))))
-    return out
+    return p, (lev_e, lev_g, vk)
 
 
 # ---------------------------------------------------------------- beam convolution

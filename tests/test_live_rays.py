@@ -1,14 +1,17 @@
-"""The ray-sample count of the measurements: Scene.live_mask / Scene3d.live_mask
-(host-side, used to count only rays that cross the grid) mark exactly the
-pixels whose chord through the bounding volume is non-empty in the FP64
-oracle (a ray outside has no samples and zero intensity)."""
+"""The ray-sample count of the measurements comes from the library's census
+(rt_render_census / rt_render_census_3d: the march's own ray set-up): its
+mask marks exactly the pixels whose chord through the bounding volume is
+non-empty in the FP64 oracle (a ray outside has no samples and zero
+intensity), and its thin-sample count is exact on slabs whose samples are
+all thin or thick by construction."""
 import numpy as np
 import pytest
-import torch
 
 import oracle
 import synth
 from synth import disk3d as S3
+
+pytestmark = pytest.mark.gpu
 
 
 def _chords(prob, dump):
@@ -22,11 +25,13 @@ def test_axisymmetric_live_mask_matches_oracle_chords(incl, pa):
     prob = synth.small_problem(nx=41, ny=33, nch=2, nsamp=8, nr=24, nz=12, seed=7, incl=incl)
     prob.camera.pa_deg = pa
     prob.camera.fov_au *= 1.4          # leave rays outside the cylinder in every corner
-    sc = rt.scene_from_problem(prob, device="cpu")
+    sc = rt.scene_from_problem(prob)
     want = _chords(prob, oracle.ray_dump)
-    got = sc.live_mask()
+    print(f"[gpu] census incl={incl} pa={pa}", flush=True)
+    got = sc.census()
     assert 0 < want.sum() < want.size
-    assert np.array_equal(got, want)
+    assert np.array_equal(got["mask"], want)
+    assert got["rays"] == int(want.sum())
     assert sc.ray_samples == int(want.sum()) * sc.nch * sc.nsamp
 
 
@@ -35,10 +40,38 @@ def test_spherical_live_mask_matches_oracle_chords():
     grid = S3.Grid3Spec(16, 8, 8)
     prob = S3.uniform_problem3(grid, nx=37, ny=29, nch=2, nsamp=8, incl=50.0, pa=30.0, fov_au=3.0 * grid.r_max_au)
     want = _chords(prob, oracle.ray_dump3)
-    sc = rt.Scene3d(grid=(grid.nr, grid.nt, grid.nphi, grid.r_min_au, grid.r_max_au, grid.th_min, grid.th_max),
-                    nodes=torch.empty(0), v_turb=0.0, nu0_hz=0.0, a_ul=0.0, g_u=0.0, g_l=0.0, e_u_k=0.0, e_l_k=0.0,
-                    m_co_amu=0.0, m_mol_amu=0.0, lev_e_k=np.zeros(1), lev_g=np.zeros(1), nx=37, ny=29,
-                    fov_au=prob.camera.fov_au, incl_deg=50.0, pa_deg=30.0, dist_pc=100.0, v_kms=prob.v_kms,
-                    v_sys_kms=0.0, nsamp=8)
+    sc = rt.scene3d_from_problem(prob)
+    print("[gpu] census 3-D", flush=True)
+    got = sc.census()
     assert 0 < want.sum() < want.size
-    assert np.array_equal(sc.live_mask(), want)
+    assert np.array_equal(got["mask"], want)
+    assert sc.ray_samples == int(want.sum()) * sc.nch * sc.nsamp
+
+
+@pytest.mark.parametrize("x_co", [1e-2, 1e-12])
+def test_thin_sample_count_on_slabs(x_co):
+    """Face-on slabs with a hard mask, so every sample's line-centre depth is
+    either 0 (outside the layer, or beyond the grid's top z/r row near the
+    axis) or far from the threshold: the census's thin count equals the
+    number of samples whose depth in the oracle's central channel (v_los = 0
+    face-on) is below 1/32 in natural units, and with a negligible abundance
+    every sample is thin."""
+    import paper_2509_03623_amd as rt
+    prob = synth.slab_problem(nsamp=128, m=24, x_co=x_co, nx=8, ny=8, nch=3)
+    sc = rt.scene_from_problem(prob)
+    print(f"[gpu] census slab x_co={x_co:g}", flush=True)
+    got = sc.census()
+    rays = int(got["mask"].sum())
+    assert rays > 0 and got["pixel_samples"] == rays * prob.nsamp
+    want = 0
+    for q in range(prob.camera.ny):
+        for p in range(prob.camera.nx):
+            _, _, dt, ch = oracle.ray_dump(prob, p, q)
+            if ch[2] > 0.0:
+                want += int((dt[:, 1] < 1.0 / 32.0).sum())
+    print(f"thin pixel-samples: census {got['thin_pixel_samples']}, oracle {want} of {got['pixel_samples']}")
+    assert got["thin_pixel_samples"] == want
+    if x_co < 1e-10:
+        assert want == got["pixel_samples"]
+    else:
+        assert 0 < want < got["pixel_samples"]
