@@ -538,7 +538,7 @@ def bench_derived(rt, synth, dev, args):
     def fit_step():
         d = rt.derive_fields(grid, T, phys)
         _, loss, g = rt.render_l2_adjoint(sc.replace(**d), tgt, want=want, cube_out=cube)
-        return g["temp_k"] + rt.derive_fields_adjoint(grid, T, phys, g)
+        return rt.derive_fields_adjoint(grid, T, phys, g, add_to=g["temp_k"])
 
     cot = {k: torch.ones_like(v) for k, v in d0.items()}
     legs = (("forward", lambda: rt.derive_fields(grid, T, phys)),
@@ -595,7 +595,7 @@ def bench_fit(rt, synth, dev, args):
     rs = int(sc.live_mask().sum()) * batch * sc.nsamp
     return {"workload": "256x256 px, 115 ch (0.04 km/s), 256 samples, batch 50, 256x128 grid",
             "ms_per_step": dt * 1e3, "ray_samples_per_s": rs / dt, "steps": steps,
-            "chi2_first": float(chi2[0].item()), "chi2_last": float(chi2[-1].item())}
+            "chi2_first": float(chi2[0].item()) / sigma ** 2, "chi2_last": float(chi2[-1].item()) / sigma ** 2}
 
 
 def bench_walkers(rt, synth, dev, args, nwalk=60, iters=3):
@@ -764,6 +764,8 @@ def bench_serving(rt, synth, dev, seconds, rate=200.0, seed=5, pool=16, saturate
                     time.sleep(2e-4)
                 tickets.append(submit(sv, i))
             infos = [sv.wait(t, timeout_s=300) for t in tickets]
+            for t in tickets:
+                sv.release(t)
         t_sub = np.array([x["t_submit_ns"] for x in infos], dtype=np.float64)
         t_done = np.array([x["t_done_ns"] for x in infos], dtype=np.float64)
         return (t_done - t_sub) * 1e-6, (t_done.max() - t_sub.min()) * 1e-9, sum(x["state"] != "done" for x in infos)

@@ -258,6 +258,10 @@ rt_status rt_derive_fields(const rt_derive *d, const rt_derived *out, void *stre
  * forward picks at this temperature.  Scratch of 5 nr nz floats is kept with
  * the stream. */
 rt_status rt_derive_fields_adjoint(const rt_derive *d, const rt_derived *cot, float *d_temp_k, void *stream);
+/* The same, but the product is added to d_temp_k (which holds, say, the
+ * render's direct dL/dT), so the two parts of dL/dT of a fit through the
+ * derived fields sum on the device. */
+rt_status rt_derive_fields_adjoint_add(const rt_derive *d, const rt_derived *cot, float *d_temp_k, void *stream);
 
 /* --------------------------------------------------- neural temperature */
 /* The neural temperature field of Methods > Neural temperature recovery on the
@@ -349,6 +353,11 @@ rt_status rt_submit(rt_server *sv, const rt_request *rq, uint64_t *ticket);
 rt_status rt_poll(rt_server *sv, uint64_t ticket, rt_ticket_info *info);
 rt_status rt_wait(rt_server *sv, uint64_t ticket, rt_ticket_info *info, uint64_t timeout_ns);
 rt_status rt_cancel(rt_server *sv, uint64_t ticket);
+/* Forget a finished ticket (done, failed or canceled): the server drops the
+ * request's copies of its problem, and later rt_poll / rt_wait / rt_release
+ * of that ticket return RT_ENOTFOUND.  A queued or running ticket gives
+ * RT_EINVAL.  Without it a server keeps every ticket until rt_server_destroy. */
+rt_status rt_release(rt_server *sv, uint64_t ticket);
 rt_status rt_server_destroy(rt_server *sv);   /* drains admitted work, cancels the rest */
 
 /* ---------------------------------------------------------------- 3-D spherical grid

@@ -125,11 +125,11 @@ class rt_problem3d(C.Structure):
 # every symbol declared in include/rtcube.h
 EXPORTS = ["rt_render_cube", "rt_render_cube_adjoint", "rt_render_cube_l2_adjoint",
            "rt_render_cube_l2_adjoint_noalloc", "rt_noalloc_scratch_bytes", "rt_render_census",
-           "rt_render_census_3d", "rt_derive_fields",
+           "rt_render_census_3d", "rt_derive_fields", "rt_derive_fields_adjoint_add",
            "rt_derive_fields_adjoint", "rt_parametric_temperature", "rt_neural_temperature", "rt_neural_temperature_adjoint", "rt_adam_step",
            "rt_pack_fields3d", "rt_render_cube_3d", "rt_beam_convolve",
            "rt_server_create", "rt_submit", "rt_poll", "rt_wait",
-           "rt_cancel", "rt_server_destroy", "rt_last_error", "rt_abi_version", "rt_constants",
+           "rt_cancel", "rt_release", "rt_server_destroy", "rt_last_error", "rt_abi_version", "rt_constants",
            "rt_set_option", "rt_get_option"]
 
 _lib = None
@@ -167,6 +167,8 @@ def lib():
         L.rt_derive_fields.restype = C.c_int
         L.rt_derive_fields_adjoint.argtypes = [C.POINTER(rt_derive), C.POINTER(rt_derived), _dev, C.c_void_p]
         L.rt_derive_fields_adjoint.restype = C.c_int
+        L.rt_derive_fields_adjoint_add.argtypes = [C.POINTER(rt_derive), C.POINTER(rt_derived), _dev, C.c_void_p]
+        L.rt_derive_fields_adjoint_add.restype = C.c_int
         L.rt_parametric_temperature.argtypes = [C.POINTER(rt_grid), C.POINTER(rt_param_temp), _dev, C.c_void_p]
         L.rt_parametric_temperature.restype = C.c_int
         L.rt_neural_temperature.argtypes = [C.POINTER(rt_grid), _dev, _dev, C.c_void_p]
@@ -191,6 +193,8 @@ def lib():
         L.rt_wait.restype = C.c_int
         L.rt_cancel.argtypes = [C.c_void_p, C.c_uint64]
         L.rt_cancel.restype = C.c_int
+        L.rt_release.argtypes = [C.c_void_p, C.c_uint64]
+        L.rt_release.restype = C.c_int
         L.rt_server_destroy.argtypes = [C.c_void_p]
         L.rt_server_destroy.restype = C.c_int
         L.rt_last_error.restype = C.c_char_p

@@ -293,7 +293,7 @@ __global__ __launch_bounds__(64) void chain_columns_adj(ChainArgs a, const float
                                                         const float *__restrict__ nbar, const float *__restrict__ zlobar,
                                                         const float *__restrict__ zupbar,
                                                         const float *__restrict__ gn, const float *__restrict__ gT,
-                                                        float *__restrict__ dT) {
+                                                        float *__restrict__ dT, int accumulate) {
     extern __shared__ float sm[];
     const int i = blockIdx.x, nz = a.nz, lane = threadIdx.x;
     const size_t o = (size_t)i * nz;
@@ -367,7 +367,7 @@ __global__ __launch_bounds__(64) void chain_columns_adj(ChainArgs a, const float
             if (k == b) g -= zlb * dz * (t_f - sT[aa]) / (d * d);
         }
         if (k == 0) g += R / sT[0];     // ln T_0 enters every l_j
-        dT[o + k] = g;
+        dT[o + k] = accumulate ? dT[o + k] + g : g;
     }
 }
 
@@ -454,8 +454,8 @@ extern "C" rt_status rt_derive_fields(const rt_derive *d, const rt_derived *out,
     return e == hipSuccess ? RT_OK : fail_hip(e, "derive v_phi");
 }
 
-extern "C" rt_status rt_derive_fields_adjoint(const rt_derive *d, const rt_derived *cot, float *d_temp_k,
-                                              void *stream) {
+static rt_status derive_adjoint(const rt_derive *d, const rt_derived *cot, float *d_temp_k, int accumulate,
+                                void *stream) {
     rt_status st = validate_derive(d);
     if (st != RT_OK) return st;
     if (!cot) return fail(RT_EINVAL, "cotangents are NULL");
@@ -475,9 +475,19 @@ extern "C" rt_status rt_derive_fields_adjoint(const rt_derive *d, const rt_deriv
                        cot->vphi_kms, eu, ez, gT);
     hipLaunchKernelGGL(chain_lnp_adj, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a, d->temp_k, eu, ez, gn, gT);
     hipLaunchKernelGGL(chain_columns_adj, dim3(a.nr), dim3(64), 5 * sizeof(float) * a.nz, s, a, d->temp_k,
-                       cot->ln_nh2, cot->z_lo_au, cot->z_up_au, gn, gT, d_temp_k);
+                       cot->ln_nh2, cot->z_lo_au, cot->z_up_au, gn, gT, d_temp_k, accumulate);
     e = hipGetLastError();
     return e == hipSuccess ? RT_OK : fail_hip(e, "derive adjoint");
+}
+
+extern "C" rt_status rt_derive_fields_adjoint(const rt_derive *d, const rt_derived *cot, float *d_temp_k,
+                                              void *stream) {
+    return derive_adjoint(d, cot, d_temp_k, 0, stream);
+}
+
+extern "C" rt_status rt_derive_fields_adjoint_add(const rt_derive *d, const rt_derived *cot, float *d_temp_k,
+                                                  void *stream) {
+    return derive_adjoint(d, cot, d_temp_k, 1, stream);
 }
 
 extern "C" rt_status rt_parametric_temperature(const rt_grid *grid, const rt_param_temp *pt, float *temp_k,

@@ -586,6 +586,17 @@ rt_status rt_cancel(rt_server *sv, uint64_t ticket) {
     return RT_OK;
 }
 
+rt_status rt_release(rt_server *sv, uint64_t ticket) {
+    if (!sv) return fail(RT_EINVAL, "NULL argument");
+    std::lock_guard<std::mutex> lk(sv->mu);
+    auto it = sv->tickets.find(ticket);
+    if (it == sv->tickets.end()) return fail(RT_ENOTFOUND, "unknown ticket %llu", (unsigned long long)ticket);
+    const int st = it->second->state;
+    if (st == RT_TICKET_QUEUED || st == RT_TICKET_RUNNING) return fail(RT_EINVAL, "request has not finished");
+    sv->tickets.erase(it);
+    return RT_OK;
+}
+
 rt_status rt_server_destroy(rt_server *sv) {
     if (!sv) return fail(RT_EINVAL, "NULL argument");
     {

@@ -80,9 +80,13 @@ def poly_lr(t: int, total: int, lr0: float = 1e-4, lr1: float = 1e-6) -> float:
 
 def fit_step(sc, grid, phys: DiskPhysics, opt: Adam, target: torch.Tensor, channels: np.ndarray, sigma: float,
              lr: float):
-    """One optimisation step on the given channel slices: chi^2 =
-    sum((cube - target)/sigma)^2 over those slices; returns (chi^2 as a
-    float64 device tensor, dL/dweights)."""
+    """One optimisation step on the given channel slices of the loss chi^2 =
+    sum((cube - target)/sigma)^2 = L2 / sigma^2 over those slices.  Every
+    step runs in the library: network, derived fields, fused render + L2 +
+    adjoint, the derived fields' adjoint added onto the render's dL/dT, the
+    network's adjoint, and Adam with the gradient scaled by 1/sigma^2.
+    Returns (L2 as a one-element float64 device tensor, dL2/dweights); the
+    step's chi^2 is L2 / sigma^2."""
     w = opt.params
     T = neural_temperature(grid, w)
     fields = derive_fields(grid, T, phys)
@@ -90,8 +94,7 @@ def fit_step(sc, grid, phys: DiskPhysics, opt: Adam, target: torch.Tensor, chann
     scb = sc.replace(v_kms=np.asarray(sc.v_kms)[channels], temp_k=T, **fields)
     tgt = target.index_select(0, idx).contiguous()
     _, l2, g = render_l2_adjoint(scb, tgt, want=("ln_nh2", "temp_k", "vphi_kms", "z_lo_au", "z_up_au"))
-    dT = g["temp_k"] + derive_fields_adjoint(grid, T, phys, g)
+    dT = derive_fields_adjoint(grid, T, phys, g, add_to=g["temp_k"])
     dW = neural_temperature_adjoint(grid, w, dT)
-    inv_s2 = 1.0 / (sigma * sigma)
-    opt.step(dW, lr, grad_scale=inv_s2)
-    return l2 * inv_s2, dW * inv_s2
+    opt.step(dW, lr, grad_scale=1.0 / (sigma * sigma))
+    return l2, dW

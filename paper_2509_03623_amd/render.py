@@ -322,15 +322,24 @@ def derive_fields(grid, temp_k: torch.Tensor, phys: DiskPhysics, stream=None) ->
     return out
 
 
-def derive_fields_adjoint(grid, temp_k: torch.Tensor, phys: DiskPhysics, cot: dict, stream=None) -> torch.Tensor:
+def derive_fields_adjoint(grid, temp_k: torch.Tensor, phys: DiskPhysics, cot: dict, stream=None,
+                          add_to: Optional[torch.Tensor] = None) -> torch.Tensor:
     """dL/dT through the derived fields, given dL/d(each output) (missing
-    keys count as zero)."""
+    keys count as zero).  With add_to (a float32 [nr, nz] tensor, e.g. the
+    render's direct dL/dT) the product is added to it in place by the
+    library (rt_derive_fields_adjoint_add) and add_to is returned."""
     T = temp_k.contiguous()
     c = {k: (None if cot.get(k) is None else cot[k].contiguous().to(torch.float32))
          for k in ("ln_nh2", "vphi_kms", "z_lo_au", "z_up_au")}
-    dT = torch.empty_like(T)
     d = _derive_struct(grid, T, phys)
     o = L.rt_derived(_fptr(c["ln_nh2"]), _fptr(c["vphi_kms"]), _fptr(c["z_lo_au"]), _fptr(c["z_up_au"]))
+    if add_to is not None:
+        if add_to.shape != T.shape or add_to.dtype != torch.float32 or not add_to.is_contiguous():
+            raise ValueError("add_to must be a contiguous float32 tensor shaped like temp_k")
+        L.check(L.lib().rt_derive_fields_adjoint_add(C.byref(d), C.byref(o), _fptr(add_to),
+                                                      C.c_void_p(_stream(stream))))
+        return add_to
+    dT = torch.empty_like(T)
     L.check(L.lib().rt_derive_fields_adjoint(C.byref(d), C.byref(o), _fptr(dT), C.c_void_p(_stream(stream))))
     return dT
 

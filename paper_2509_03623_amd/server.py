@@ -1,5 +1,5 @@
 """Python handle of the C-ABI render server (rt_server_* / rt_submit /
-rt_poll / rt_wait / rt_cancel).  Keeps each request's device tensors alive
+rt_poll / rt_wait / rt_cancel / rt_release).  Keeps each request's device tensors alive
 until the request has finished."""
 from __future__ import annotations
 
@@ -70,6 +70,11 @@ class Server:
 
     def cancel(self, ticket: int) -> None:
         L.check(L.lib().rt_cancel(self._h, ticket))
+
+    def release(self, ticket: int) -> None:
+        """Forget a finished ticket (the server frees its copy of the request)."""
+        L.check(L.lib().rt_release(self._h, ticket))
+        self._keep.pop(ticket, None)
 
     def close(self) -> None:
         if self._h:

@@ -16,8 +16,8 @@ from paper_2509_03623_amd import _lib as L
 HEADER = os.path.join(os.path.dirname(__file__), "..", "include", "rtcube.h")
 
 
-def declared_functions():
-    src = open(HEADER).read()
+def declared_functions(path=HEADER):
+    src = open(path).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
     return sorted(set(re.findall(r"\b(rt_[a-z0-9_]+)\s*\(", src)))
 
@@ -29,6 +29,18 @@ def test_library_exports_every_declared_symbol():
     for n in names:
         assert hasattr(lib, n), n
     assert sorted(L.EXPORTS) == names
+
+
+def test_library_exports_every_symbol_of_every_header():
+    """Every header under include/ (the rendering API and the measurement
+    aid rtcube_micro.h) is exported by the one library."""
+    inc = os.path.join(os.path.dirname(__file__), "..", "include")
+    lib = L.lib()
+    headers = sorted(f for f in os.listdir(inc) if f.endswith(".h"))
+    assert "rtcube_micro.h" in headers
+    for h in headers:
+        for n in declared_functions(os.path.join(inc, h)):
+            assert hasattr(lib, n), (h, n)
 
 
 def test_abi_version():

@@ -90,6 +90,14 @@ def test_derived_fields_adjoint_matches_oracle_autograd(grid, seed):
                                    {k: torch.tensor(v, device="cuda") for k, v in cot.items()})
     torch.cuda.synchronize()
     _check_grad("dT through derived fields", got.cpu().numpy(), T.grad.numpy())
+    # the accumulating form adds the same product onto what the buffer holds
+    base = torch.tensor(rng.standard_normal(T32.shape).astype(np.float32), device="cuda")
+    acc = base.clone()
+    rt.derive_fields_adjoint(grid, torch.tensor(T32, device="cuda"), _phys(rt),
+                             {k: torch.tensor(v, device="cuda") for k, v in cot.items()}, add_to=acc)
+    torch.cuda.synchronize()
+    want = base.double() + got.double()
+    assert float((acc.double() - want).abs().max()) <= 1e-6 * float(want.abs().max())
     # one output at a time (NULL cotangents for the others)
     for k in cot:
         T.grad = None

@@ -408,3 +408,26 @@ def test_device_memory_stays_within_budget():
     spans = sorted((i["t_admit_ns"], i["t_done_ns"]) for i in infos)
     for a in spans:
         assert sum(1 for b in spans if b[0] <= a[0] < b[1]) <= 2
+
+
+def test_release_forgets_finished_tickets():
+    """rt_release drops a finished ticket (later calls on it: RT_ENOTFOUND)
+    and refuses one still queued or running."""
+    rt = _rt()
+    from paper_2509_03623_amd import _lib as L
+    _, sc = scene(32, 8, 64)
+    _, big = scene(512, 64, 512)
+    print("[gpu] server release", flush=True)
+    with rt.Server(max_slots=1, streams=1) as sv:
+        t0 = sv.submit(big, empty_cube(big))
+        t1 = sv.submit(sc, empty_cube(sc))
+        with pytest.raises(rt.RtError) as e:
+            sv.release(t1)                      # queued behind t0
+        assert e.value.status == L.RT_EINVAL
+        assert sv.wait(t0)["state"] == "done" and sv.wait(t1)["state"] == "done"
+        sv.release(t0)
+        sv.release(t1)
+        for t in (t0, t1):
+            with pytest.raises(rt.RtError) as e:
+                sv.poll(t)
+            assert e.value.status == L.RT_ENOTFOUND
