@@ -54,14 +54,15 @@ SHADE3_SLOTS = 307 + 4 * 16
 # HBM traffic of one forward launch on the full-size render of each disk,
 # from two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch)
 # of `bench.py --copy-probe`, each scaled by what the same counter reads for
-# a 1 GiB device-to-device copy (FETCH_SIZE 524 302 KiB -> x2.0000,
+# a 1 GiB device-to-device copy (FETCH_SIZE 524 305 KiB -> x2.0000,
 # WRITE_SIZE 1 048 576 KiB -> x1.0000).  Valid only for the kernel sources it
 # was taken on: the hash of those files is checked at run time.
 FWD_TRAFFIC = {"sources": ("paper_2509_03623_amd/csrc/rt_forward.hip", "paper_2509_03623_amd/csrc/rt_kernels.h",
                            "paper_2509_03623_amd/csrc/rt_launch.h"),
-               "sha256": None,
-               "fetch_scale": 1048576 / 524302.4, "write_scale": 1.0,
-               "disks": {}}     # seed -> (FETCH_SIZE KiB, WRITE_SIZE KiB)
+               "sha256": "3e3f2980a20aa4d3cc8c705b42cbcf4e58c43f7ce82d05c4ae98c8305e34bb4d",
+               "fetch_scale": 1048576 / 524304.5, "write_scale": 1.0,
+               # seed -> (FETCH_SIZE KiB, WRITE_SIZE KiB), mean of three launches each
+               "disks": {2000: (1053.4, 65536.0), 2001: (1164.4, 65536.0), 2002: (1018.8, 65536.0), 2003: (1008.5, 65536.0), 2004: (1068.1, 65536.0), 2005: (1084.2, 65536.0), 2006: (1123.4, 65536.0), 2007: (1145.3, 65536.0)}}
 
 
 def measured_traffic(seed: int):
@@ -228,7 +229,7 @@ def main():
     ap.add_argument("--no-mlp", action="store_true", help="skip the neural CO layer leg")
     ap.add_argument("--no-3d", action="store_true", help="skip the 3-D spherical-grid leg")
     ap.add_argument("--no-beam", action="store_true", help="skip the beam-convolution leg")
-    ap.add_argument("--only", choices=("render3d", "beam"), default=None,
+    ap.add_argument("--only", choices=("render3d", "beam", "adjoint", "mlp"), default=None,
                     help="run one leg alone and print its JSON (for profiling)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first copy 1 GiB device to device three times (a kernel of known traffic, to scale "
@@ -259,6 +260,12 @@ def main():
         del src, dst
     if args.only == "render3d":
         print(json.dumps({"render3d": bench_render3d(rt, dev, args)}), flush=True)
+        return
+    if args.only == "adjoint":
+        print(json.dumps({"fwd_adjoint": bench_adjoint(rt, synth, dev, args)}), flush=True)
+        return
+    if args.only == "mlp":
+        print(json.dumps({"neural": bench_mlp(rt, synth, dev, args)}), flush=True)
         return
     if args.only == "beam":
         prob = synth.config2(args.seed)
@@ -787,12 +794,15 @@ def bench_serving(rt, synth, dev, seconds, rate=200.0, seed=5, pool=16, saturate
     arrivals = [r["t_arrive"] - trace[0]["t_arrive"] for r in trace]
     total_rs = sum(sc.ray_samples for sc, _, _ in reqs)
     ngrad = sum(1 for r in trace if r["grad"])
+    log(f"served run of {len(trace)} requests")
     lat, span, failed = served_run(order, arrivals)
+    log(f"served: makespan {span:.2f} s; serial replay")
     served = {"ray_samples_per_s": total_rs / span, "p50_ms": float(np.percentile(lat, 50)),
               "p99_ms": float(np.percentile(lat, 99)), "requests": len(trace), "grad_requests": ngrad,
               "makespan_s": span, "failed": int(failed),
               "trace": f"Poisson {rate:g} req/s for {seconds:g} s, seed {seed}"}
     lat_s, span_s = serial_run(order, arrivals)
+    log(f"serial: makespan {span_s:.2f} s; saturated runs")
     serial = {"ray_samples_per_s": total_rs / span_s, "p50_ms": float(np.percentile(lat_s, 50)),
               "p99_ms": float(np.percentile(lat_s, 99)), "makespan_s": span_s}
     # saturated: every request of the head of the trace at time 0
