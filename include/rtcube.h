@@ -463,8 +463,9 @@ int32_t rt_constants(double *out, int32_t n);
  * per-sample sums added across the lanes (1 or 2; 0 = automatic).
  * RT_OPT_RAY_SPLIT: lanes sharing one ray in the forward
  * march, each taking a consecutive sub-chord (1, 2, 4 or 8; 0 = automatic).
- * RT_OPT_GRAD_ACCUM: 1 (default) accumulates the field gradients of the
- * adjoint in double, 0 in float.  RT_OPT_ADJ_SCRATCH_CAP: bytes of adjoint
+ * RT_OPT_GRAD_ACCUM: 0 (default) accumulates the gradients of the adjoint
+ * (per-workgroup partials in LDS, then atomics into one accumulator per node)
+ * in float, 1 in double; the partials are float either way.  RT_OPT_ADJ_SCRATCH_CAP: bytes of adjoint
  * scratch (sample tape, transmission checkpoints, cotangents) per pass; an
  * image whose scratch exceeds it is differentiated in bands of whole pixel
  * rows, at least one row per band (0 = default, 8 GiB).  The library keeps

@@ -217,13 +217,14 @@ template <typename A>
 __global__ __launch_bounds__(256) void adj_chain(Geometry g, Shade s, const float4 *__restrict__ rays,
                                                  const float4 *__restrict__ cot, int nblk, GradAcc go,
                                                  int lds_surfaces, float4 *__restrict__ dO) {
-    extern __shared__ double lds[];  // [2][nr] surface gradients when lds_surfaces
+    extern __shared__ float lds[];   // [2][nr] surface gradients when lds_surfaces
     __shared__ float4 ztab[kZTableNodes - 1];
     stage_ztab(s, ztab);
     const int npix = g.nx * g.ny;
     const int nr = s.nr;
+    A *const gzlo = (A *)go.zlo, *const gzup = (A *)go.zup;
     if (lds_surfaces) {
-        for (int i = threadIdx.x; i < 2 * nr; i += 256) lds[i] = 0.0;
+        for (int i = threadIdx.x; i < 2 * nr; i += 256) lds[i] = 0.0f;
         __syncthreads();
     }
     const size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x;
@@ -247,19 +248,22 @@ __global__ __launch_bounds__(256) void adj_chain(Geometry g, Shade s, const floa
             scatter4((A *)go.ln_n, n00, n10, t.gn, w00, w01, w10, w11);
             scatter4((A *)go.temp, n00, n10, t.gT, w00, w01, w10, w11);
             scatter4((A *)go.vphi, n00, n10, t.gV, w00, w01, w10, w11);
-            double *zl = lds_surfaces ? lds : go.zlo;
-            double *zu = lds_surfaces ? lds + nr : go.zup;
-            if (zl && t.gzl != 0.0f) { atomicAdd(zl + t.i0, (double)(t.gzl * (1.0f - fu))); atomicAdd(zl + t.i0 + 1, (double)(t.gzl * fu)); }
-            if (zu && t.gzu != 0.0f) { atomicAdd(zu + t.i0, (double)(t.gzu * (1.0f - fu))); atomicAdd(zu + t.i0 + 1, (double)(t.gzu * fu)); }
+            if (lds_surfaces) {
+                if (t.gzl != 0.0f) { atomicAdd(lds + t.i0, t.gzl * (1.0f - fu)); atomicAdd(lds + t.i0 + 1, t.gzl * fu); }
+                if (t.gzu != 0.0f) { atomicAdd(lds + nr + t.i0, t.gzu * (1.0f - fu)); atomicAdd(lds + nr + t.i0 + 1, t.gzu * fu); }
+            } else {
+                if (gzlo && t.gzl != 0.0f) { atomicAdd(gzlo + t.i0, (A)(t.gzl * (1.0f - fu))); atomicAdd(gzlo + t.i0 + 1, (A)(t.gzl * fu)); }
+                if (gzup && t.gzu != 0.0f) { atomicAdd(gzup + t.i0, (A)(t.gzu * (1.0f - fu))); atomicAdd(gzup + t.i0 + 1, (A)(t.gzu * fu)); }
+            }
         }
         if (dO) dO[o_index(s, k, pix)] = dout;
     }
     if (lds_surfaces) {
         __syncthreads();
         for (int i = threadIdx.x; i < nr; i += 256) {
-            const double a = lds[i], b = lds[nr + i];
-            if (go.zlo && a != 0.0) atomicAdd(go.zlo + i, a);
-            if (go.zup && b != 0.0) atomicAdd(go.zup + i, b);
+            const float a = lds[i], b = lds[nr + i];
+            if (gzlo && a != 0.0f) atomicAdd(gzlo + i, (A)a);
+            if (gzup && b != 0.0f) atomicAdd(gzup + i, (A)b);
         }
     }
 }
@@ -274,20 +278,21 @@ constexpr int kChainThreads = 1024;
 // contiguous share each, the few whose samples crossed the disk did the work
 // while those beyond it, where the cotangents vanish, sat idle), accumulate
 // field FIELD (0 ln n, 1 T, 2 v_phi, 3 none) over the whole grid in LDS
-// (float), and flush it once with double atomics; the FIRST pass also
-// accumulates the two surface vectors (LDS, double) and writes dL/do.
-template <int FIELD, bool FIRST>
+// (float), and flush it once with atomics into the accumulators of type A;
+// the FIRST pass also accumulates the two surface vectors (LDS, float) and
+// writes dL/do.
+template <int FIELD, bool FIRST, typename A>
 __global__ __launch_bounds__(kChainThreads) void adj_chain_lds(Geometry g, Shade s, const float4 *__restrict__ rays,
                                                      float4 *__restrict__ cot, int nblk, GradAcc go,
                                                      float4 *__restrict__ dO) {
-    extern __shared__ double dyn[];              // [2 nr] surfaces (FIRST), then [nr nz] field (float)
+    extern __shared__ float dyn[];               // [2 nr] surfaces (FIRST), then [nr nz] field
     __shared__ float4 ztab[kZTableNodes - 1];
     const int nr = s.nr, nn = s.nr * s.nz;
-    double *surf = dyn;
-    float *field = (float *)(dyn + (FIRST ? 2 * nr : 0));
+    float *surf = dyn;
+    float *field = dyn + (FIRST ? 2 * nr : 0);
     for (int i = threadIdx.x; i < kZTableNodes - 1; i += kChainThreads) ztab[i] = s.ztab[i];
     if (FIELD < 3) for (int i = threadIdx.x; i < nn; i += kChainThreads) field[i] = 0.0f;
-    if (FIRST) for (int i = threadIdx.x; i < 2 * nr; i += kChainThreads) surf[i] = 0.0;
+    if (FIRST) for (int i = threadIdx.x; i < 2 * nr; i += kChainThreads) surf[i] = 0.0f;
     __syncthreads();
     const int npix = g.nx * g.ny;
     const size_t total = (size_t)g.nsamp * npix;
@@ -352,31 +357,32 @@ __global__ __launch_bounds__(kChainThreads) void adj_chain_lds(Geometry g, Shade
             if (FIRST && !s.mlp_o) {
                 const float gzu = gKK * tp.sa * tp.iw * kLn2;
                 const float gzl = -gKK * tp.sb * tp.iw * kLn2;
-                if (gzl != 0.0f) { atomicAdd(surf + L.i0, (double)(gzl * (1.0f - fu))); atomicAdd(surf + L.i0 + 1, (double)(gzl * fu)); }
-                if (gzu != 0.0f) { atomicAdd(surf + nr + L.i0, (double)(gzu * (1.0f - fu))); atomicAdd(surf + nr + L.i0 + 1, (double)(gzu * fu)); }
+                if (gzl != 0.0f) { atomicAdd(surf + L.i0, gzl * (1.0f - fu)); atomicAdd(surf + L.i0 + 1, gzl * fu); }
+                if (gzu != 0.0f) { atomicAdd(surf + nr + L.i0, gzu * (1.0f - fu)); atomicAdd(surf + nr + L.i0 + 1, gzu * fu); }
             }
         }
         if (FIRST && dO) dO[o_index(s, k, pix)] = dout;
     }
     __syncthreads();
-    double *dst = FIELD == 0 ? go.ln_n : (FIELD == 1 ? go.temp : (FIELD == 2 ? go.vphi : nullptr));
+    A *dst = (A *)(FIELD == 0 ? go.ln_n : (FIELD == 1 ? go.temp : (FIELD == 2 ? go.vphi : nullptr)));
     if (FIELD < 3 && dst)
         for (int i = threadIdx.x; i < nn; i += kChainThreads)
-            if (field[i] != 0.0f) atomicAdd(dst + i, (double)field[i]);
+            if (field[i] != 0.0f) atomicAdd(dst + i, (A)field[i]);
     if (FIRST)
         for (int i = threadIdx.x; i < nr; i += kChainThreads) {
-            if (go.zlo && surf[i] != 0.0) atomicAdd(go.zlo + i, surf[i]);
-            if (go.zup && surf[nr + i] != 0.0) atomicAdd(go.zup + i, surf[nr + i]);
+            if (go.zlo && surf[i] != 0.0f) atomicAdd((A *)go.zlo + i, (A)surf[i]);
+            if (go.zup && surf[nr + i] != 0.0f) atomicAdd((A *)go.zup + i, (A)surf[nr + i]);
         }
 }
 
-template <int FIELD, bool FIRST>
+template <int FIELD, bool FIRST, typename A>
 static hipError_t launch_chain_lds_t(const Geometry &g, const Shade &s, const float4 *rays, float4 *cot, int nblk,
                                      const GradAcc &go, float4 *dO, int nwg, size_t shmem, hipStream_t st) {
-    hipError_t e = hipFuncSetAttribute((const void *)adj_chain_lds<FIELD, FIRST>,
+    hipError_t e = hipFuncSetAttribute((const void *)adj_chain_lds<FIELD, FIRST, A>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((adj_chain_lds<FIELD, FIRST>), dim3(nwg), dim3(kChainThreads), shmem, st, g, s, rays, cot, nblk, go, dO);
+    hipLaunchKernelGGL((adj_chain_lds<FIELD, FIRST, A>), dim3(nwg), dim3(kChainThreads), shmem, st, g, s, rays, cot,
+                       nblk, go, dO);
     return hipGetLastError();
 }
 
@@ -385,7 +391,32 @@ static hipError_t launch_chain_lds_t(const Geometry &g, const Shade &s, const fl
 constexpr size_t kChainLdsMax = 160 * 1024 - sizeof(float4) * (kZTableNodes - 1) - 1024;
 
 bool chain_lds_fits(int nr, int nz) {
-    return (size_t)nr * nz * sizeof(float) + 2 * (size_t)nr * sizeof(double) <= kChainLdsMax;
+    return (size_t)nr * nz * sizeof(float) + 2 * (size_t)nr * sizeof(float) <= kChainLdsMax;
+}
+
+template <typename A>
+static hipError_t chain_lds_passes(const Geometry &g, const Shade &s, const float4 *rays, float4 *cot, int nblk,
+                                   const GradAcc &go, float4 *dO, int nwg, hipStream_t st) {
+    const size_t fb = (size_t)s.nr * s.nz * sizeof(float), sb = 2 * (size_t)s.nr * sizeof(float);
+    const bool want[3] = {go.ln_n != nullptr, go.temp != nullptr, go.vphi != nullptr};
+    bool first = true;
+    hipError_t e = hipSuccess;
+    for (int f = 0; f < 3; ++f) {
+        if (!want[f]) continue;
+        const size_t shmem = fb + (first ? sb : 0);
+        if (first) {
+            e = f == 0 ? launch_chain_lds_t<0, true, A>(g, s, rays, cot, nblk, go, dO, nwg, shmem, st)
+              : f == 1 ? launch_chain_lds_t<1, true, A>(g, s, rays, cot, nblk, go, dO, nwg, shmem, st)
+                       : launch_chain_lds_t<2, true, A>(g, s, rays, cot, nblk, go, dO, nwg, shmem, st);
+        } else {
+            e = f == 1 ? launch_chain_lds_t<1, false, A>(g, s, rays, cot, nblk, go, dO, nwg, shmem, st)
+                       : launch_chain_lds_t<2, false, A>(g, s, rays, cot, nblk, go, dO, nwg, shmem, st);
+        }
+        if (e != hipSuccess) return e;
+        first = false;
+    }
+    if (first) e = launch_chain_lds_t<3, true, A>(g, s, rays, cot, nblk, go, dO, nwg, sb, st);
+    return e;
 }
 
 hipError_t launch_adj_chain_lds(const Geometry &g, const Shade &s, const float4 *rays, float4 *cot, int nblk,
@@ -396,25 +427,8 @@ hipError_t launch_adj_chain_lds(const Geometry &g, const Shade &s, const float4 
     if (e != hipSuccess) return e;
     const size_t total = (size_t)g.nsamp * g.nx * g.ny;
     const int nwg = (int)std::min<size_t>((size_t)ncu, (total + kChainThreads - 1) / kChainThreads);
-    const size_t fb = (size_t)s.nr * s.nz * sizeof(float), sb = 2 * (size_t)s.nr * sizeof(double);
-    const bool want[3] = {go.ln_n != nullptr, go.temp != nullptr, go.vphi != nullptr};
-    bool first = true;
-    for (int f = 0; f < 3; ++f) {
-        if (!want[f]) continue;
-        const size_t shmem = fb + (first ? sb : 0);
-        if (first) {
-            e = f == 0 ? launch_chain_lds_t<0, true>(g, s, rays, cot, nblk, go, dO, nwg, shmem, st)
-              : f == 1 ? launch_chain_lds_t<1, true>(g, s, rays, cot, nblk, go, dO, nwg, shmem, st)
-                       : launch_chain_lds_t<2, true>(g, s, rays, cot, nblk, go, dO, nwg, shmem, st);
-        } else {
-            e = f == 1 ? launch_chain_lds_t<1, false>(g, s, rays, cot, nblk, go, dO, nwg, shmem, st)
-                       : launch_chain_lds_t<2, false>(g, s, rays, cot, nblk, go, dO, nwg, shmem, st);
-        }
-        if (e != hipSuccess) return e;
-        first = false;
-    }
-    if (first) e = launch_chain_lds_t<3, true>(g, s, rays, cot, nblk, go, dO, nwg, sb, st);
-    return e;
+    return grad_accum_double() ? chain_lds_passes<double>(g, s, rays, cot, nblk, go, dO, nwg, st)
+                               : chain_lds_passes<float>(g, s, rays, cot, nblk, go, dO, nwg, st);
 }
 
 __global__ void fill_zero_d(double *p, size_t n) {
@@ -523,7 +537,7 @@ hipError_t launch_adj_chain(const Geometry &g, const Shade &s, const float4 *ray
                             const GradAcc &go, float4 *dO, hipStream_t st) {
     const size_t total = (size_t)g.nsamp * g.nx * g.ny;
     const int lds_surf = (s.nr <= 2048) ? 1 : 0;
-    const size_t shmem = lds_surf ? sizeof(double) * 2 * s.nr : 0;
+    const size_t shmem = lds_surf ? sizeof(float) * 2 * s.nr : 0;
     if (grad_accum_double())
         hipLaunchKernelGGL(adj_chain<double>, dim3((unsigned)((total + 255) / 256)), dim3(256), shmem, st, g, s, rays,
                            cot, nblk, go, lds_surf, dO);

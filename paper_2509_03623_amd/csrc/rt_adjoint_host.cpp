@@ -102,7 +102,8 @@ rt_status adjoint_core(const rt_problem *p, const float *dl, const rt_grads *g, 
     const int npix = p->cam.nx * p->cam.ny;
     const int ns = p->nsamp;
     const size_t nn = (size_t)p->grid.nr * p->grid.nz, nr = (size_t)p->grid.nr;
-    // gradients accumulate in double, then overwrite the caller's float outputs
+    // gradients accumulate in double (float with RT_OPT_GRAD_ACCUM 0), then
+    // overwrite the caller's float outputs
     const size_t acc_n = 3 * nn + 2 * nr;
     double *ab = fx ? (double *)(fx->base + fixed_table_bytes())
                     : (double *)stream_workspace(st, kWsGradAcc, sizeof(double) * acc_n, &e);
@@ -127,7 +128,7 @@ rt_status adjoint_core(const rt_problem *p, const float *dl, const rt_grads *g, 
     const int band_max = (int)std::max<size_t>(1, std::min<size_t>((size_t)ny, cap / row_bytes));
     const int nband = (ny + band_max - 1) / band_max;
     const int band = (ny + nband - 1) / nband;
-    const bool lds = grad_accum_double() && chain_lds_fits(p->grid.nr, p->grid.nz);
+    const bool lds = chain_lds_fits(p->grid.nr, p->grid.nz);
     for (int c0 = 0; c0 < p->spec.nch; c0 += kLaunchChannels) {
         Channels ch;
         std::memset(&ch, 0, sizeof ch);
@@ -166,16 +167,16 @@ rt_status adjoint_core(const rt_problem *p, const float *dl, const rt_grads *g, 
             if (e != hipSuccess) return fail_hip(e, "adjoint chain");
         }
     }
-    // field accumulators are double or float (option); surfaces always double
-    auto field_out = [&](size_t off, float *dst) {
-        return grad_accum_double() ? to_float_async(ab + off, dst, nn, st)
-                                   : copy_float_async((const float *)(ab + off), dst, nn, st);
+    // accumulators are double or float (option), at the offsets of the double layout
+    auto acc_out = [&](size_t off, float *dst, size_t n) {
+        return grad_accum_double() ? to_float_async(ab + off, dst, n, st)
+                                   : copy_float_async((const float *)(ab + off), dst, n, st);
     };
-    if ((e = field_out(0, g->d_ln_nh2)) != hipSuccess ||
-        (e = field_out(nn, g->d_temp_k)) != hipSuccess ||
-        (e = field_out(2 * nn, g->d_vphi_kms)) != hipSuccess ||
-        (e = to_float_async(ab + 3 * nn, g->d_z_lo_au, nr, st)) != hipSuccess ||
-        (e = to_float_async(ab + 3 * nn + nr, g->d_z_up_au, nr, st)) != hipSuccess)
+    if ((e = acc_out(0, g->d_ln_nh2, nn)) != hipSuccess ||
+        (e = acc_out(nn, g->d_temp_k, nn)) != hipSuccess ||
+        (e = acc_out(2 * nn, g->d_vphi_kms, nn)) != hipSuccess ||
+        (e = acc_out(3 * nn, g->d_z_lo_au, nr)) != hipSuccess ||
+        (e = acc_out(3 * nn + nr, g->d_z_up_au, nr)) != hipSuccess)
         return fail_hip(e, "gradient output");
     return RT_OK;
 }

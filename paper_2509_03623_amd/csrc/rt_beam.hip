@@ -29,16 +29,16 @@ namespace rt {
 
 constexpr int kBeamTX = 64, kBeamTY = 32, kBeamOut = 8;   // tile and outputs per lane
 
-__global__ __launch_bounds__(256) void beam_weights(float *__restrict__ w, int R, double inv_smaj, double inv_smin,
-                                                    double spa, double cpa) {
-    __shared__ double part[256];
+__global__ __launch_bounds__(256) void beam_weights(float *__restrict__ w, int R, float inv_smaj, float inv_smin,
+                                                    float spa, float cpa) {
+    __shared__ float part[256];
     const int n = 2 * R + 1, nn = n * n;
     auto weight = [&](int idx) {
-        const double dy = (double)(idx / n - R), dx = (double)(idx % n - R);
-        const double u = (-dx * spa + dy * cpa) * inv_smaj, v = (dx * cpa + dy * spa) * inv_smin;
-        return exp(-0.5 * (u * u + v * v));
+        const float dy = (float)(idx / n - R), dx = (float)(idx % n - R);
+        const float u = fmaf(-dx, spa, dy * cpa) * inv_smaj, v = fmaf(dx, cpa, dy * spa) * inv_smin;
+        return expf(-0.5f * fmaf(u, u, v * v));
     };
-    double s = 0.0;
+    float s = 0.0f;
     for (int i = threadIdx.x; i < nn; i += blockDim.x) s += weight(i);
     part[threadIdx.x] = s;
     __syncthreads();
@@ -46,8 +46,8 @@ __global__ __launch_bounds__(256) void beam_weights(float *__restrict__ w, int R
         if ((int)threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
         __syncthreads();
     }
-    const double inv = 1.0 / part[0];
-    for (int i = threadIdx.x; i < nn; i += blockDim.x) w[i] = (float)(weight(i) * inv);
+    const float inv = 1.0f / part[0];
+    for (int i = threadIdx.x; i < nn; i += blockDim.x) w[i] = weight(i) * inv;
 }
 
 __global__ __launch_bounds__(256) void beam_conv(const float *__restrict__ in, float *__restrict__ out,
@@ -167,8 +167,8 @@ extern "C" rt_status rt_beam_convolve(const float *in, float *out, int32_t nch, 
     float *w = (float *)stream_workspace(st, kWsBeam, sizeof(float) * n * n, &e);
     if (!w) return fail_hip(e, "beam workspace");
     const double pa = bpa * 3.14159265358979323846 / 180.0;
-    hipLaunchKernelGGL(beam_weights, dim3(1), dim3(256), 0, st, w, R, 1.0 / smaj, 1.0 / smin, std::sin(pa),
-                       std::cos(pa));
+    hipLaunchKernelGGL(beam_weights, dim3(1), dim3(256), 0, st, w, R, (float)(1.0 / smaj), (float)(1.0 / smin),
+                       (float)std::sin(pa), (float)std::cos(pa));
     if ((e = hipGetLastError()) != hipSuccess) return fail_hip(e, "beam weights launch");
     const int W = kBeamTX + 2 * R, H = kBeamTY + 2 * R, P = W | 1;
     const size_t lds = sizeof(float) * ((size_t)H * P + (size_t)n * n);

@@ -48,7 +48,7 @@ static int64_t g_opt_cb = 0;
 static int64_t g_opt_thin = 1;
 static int64_t g_opt_ckpt = 0;
 static int64_t g_opt_split = 0;
-static int64_t g_opt_accum = 1;
+static int64_t g_opt_accum = 0;
 static int64_t g_opt_adj_cap = 0;
 static int64_t g_opt_adj_cb = 0;
 static int64_t g_opt_adj_lanes = 0;

@@ -13,14 +13,13 @@ constexpr int kZTableNodes = 512;
 constexpr float kLog2E = 1.4426950408889634f;
 constexpr float kLn2 = 0.6931471805599453f;
 
-// Per-launch geometry.  Per-ray set-up runs in double (once per ray), the
-// samples themselves in float.
+// Per-launch geometry.  Everything, the per-ray set-up included, is float.
 struct Geometry {
-    double d_pix;            // pixel size [au]
-    double cpa, spa;         // position-angle rotation
-    double si, ci;           // sin / cos inclination
-    double rc, zc;           // bounding cylinder radius and half height [au]
-    double xc, yc;           // image centre in pixels from the first column / row of this launch
+    float d_pix;             // pixel size [au]
+    float cpa, spa;          // position-angle rotation
+    float si, ci;            // sin / cos inclination (0 and 1 exactly face-on, 1 and 0 edge-on)
+    float rc, zc;            // bounding cylinder radius and half height [au]
+    float xc, yc;            // image centre in pixels from the first column / row of this launch
     int32_t nx, ny, nsamp;   // pixels of this launch (a band of rows of the image when chunked)
     int32_t pad_;
 };
@@ -131,36 +130,63 @@ struct RaySetup {
     bool live;
 };
 
+// Chord of the ray through the bounding cylinder rho <= rc, |z| <= zc.  On
+// the ray (x', y', s) the disk-frame position is x = x', y = y' ci + s si,
+// z = y' si - s ci, so the cylinder keeps s within qq/si of s_c = -y' ci/si
+// (qq^2 = rc^2 - x'^2) and the slab within zc/ci of s_z = y' si/ci.  The
+// set-up is float and works relative to the chord's midpoint: when one
+// constraint bounds both ends, the midpoint lies on its symmetry plane
+// (y = 0 or z = 0) exactly, its other coordinate is y'/si or y'/ci (one
+// rounding), and the chord length is 2 qq/si or 2 zc/ci, free of the
+// cancellation in (s_c + h) - (s_c - h).  Chords cut by both constraints use
+// the end points directly.
 __device__ __forceinline__ RaySetup ray_setup(const Geometry &g, int p, int q) {
     RaySetup r;
-    const double X = ((double)p + 0.5 - g.xc) * g.d_pix;
-    const double Y = ((double)q + 0.5 - g.yc) * g.d_pix;
-    const double xp = g.cpa * X - g.spa * Y;
-    const double yp = g.spa * X + g.cpa * Y;
-    double lo = -1e300, hi = 1e300;
-    bool ok = xp * xp < g.rc * g.rc;
-    const double qq = sqrt(fmax(g.rc * g.rc - xp * xp, 0.0));
-    if (g.si > 0.0) {
-        lo = fmax(lo, (-yp * g.ci - qq) / g.si);
-        hi = fmin(hi, (-yp * g.ci + qq) / g.si);
+    const float X = ((float)p + 0.5f - g.xc) * g.d_pix;
+    const float Y = ((float)q + 0.5f - g.yc) * g.d_pix;
+    const float xp = fmaf(g.cpa, X, -g.spa * Y);
+    const float yp = fmaf(g.spa, X, g.cpa * Y);
+    const float q2 = fmaf(-xp, xp, g.rc * g.rc);
+    const float qq = sqrtf(fmaxf(q2, 0.0f));
+    bool ok = q2 > 0.0f;
+    const float inf = __builtin_huge_valf();
+    float loc = -inf, hic = inf, loz = -inf, hiz = inf;
+    if (g.si > 0.0f) {
+        loc = fmaf(-yp, g.ci, -qq) / g.si;
+        hic = fmaf(-yp, g.ci, qq) / g.si;
     } else {
-        ok = ok && fabs(yp * g.ci) <= qq;
+        ok = ok && fabsf(yp * g.ci) <= qq;
     }
-    if (g.ci > 0.0) {
-        lo = fmax(lo, (yp * g.si - g.zc) / g.ci);
-        hi = fmin(hi, (yp * g.si + g.zc) / g.ci);
+    if (g.ci > 0.0f) {
+        loz = fmaf(yp, g.si, -g.zc) / g.ci;
+        hiz = fmaf(yp, g.si, g.zc) / g.ci;
     } else {
-        ok = ok && fabs(yp * g.si) <= g.zc;
+        ok = ok && fabsf(yp * g.si) <= g.zc;
     }
+    const bool cyl_lo = loc >= loz, cyl_hi = hic <= hiz;
+    const float lo = cyl_lo ? loc : loz, hi = cyl_hi ? hic : hiz;
     ok = ok && hi > lo;
-    const double ds = ok ? (hi - lo) / g.nsamp : 0.0;
-    const double sm = ok ? 0.5 * (lo + hi) : 0.0;
-    r.px = (float)xp;
-    r.pmy = (float)(yp * g.ci + sm * g.si);
-    r.pmz = (float)(yp * g.si - sm * g.ci);
-    r.ds = (float)ds;
-    r.wy = (float)g.si;
-    r.wz = (float)(-g.ci);
+    float len, pmy, pmz;
+    if (cyl_lo && cyl_hi) {            // both ends on the cylinder wall
+        len = 2.0f * qq / g.si;
+        pmy = 0.0f;
+        pmz = yp / g.si;
+    } else if (!cyl_lo && !cyl_hi) {   // both ends on the slab faces
+        len = 2.0f * g.zc / g.ci;
+        pmy = yp / g.ci;
+        pmz = 0.0f;
+    } else {
+        const float sm = 0.5f * (lo + hi);
+        len = hi - lo;
+        pmy = fmaf(sm, g.si, yp * g.ci);
+        pmz = fmaf(-sm, g.ci, yp * g.si);
+    }
+    r.px = xp;
+    r.pmy = ok ? pmy : 0.0f;
+    r.pmz = ok ? pmz : 0.0f;
+    r.ds = ok ? len / (float)g.nsamp : 0.0f;
+    r.wy = g.si;
+    r.wz = -g.ci;
     r.live = ok;
     return r;
 }

@@ -84,18 +84,24 @@ __device__ __forceinline__ void point_coords(const Geometry &g, const Shade &s, 
     *zh = clampf(L.v, 0.0f, s.fnz) / (s.fnz - 1.0f);
 }
 
-// sin(pi f c), cos(pi f c) with the phase reduced in double
+// Phase f c reduced to (-2, 2) in float: the product is split exactly into
+// hi + lo with an FMA (Ogita, Rump and Oishi's TwoProduct), hi loses its even
+// integer part exactly (|hi| < 2^23), and lo is added back with one rounding,
+// so the reduced phase is the exact one rounded once.
+__device__ __forceinline__ float phase2(float f, float c) {
+    const float hi = f * c;
+    const float lo = fmaf(f, c, -hi);
+    return (hi - 2.0f * floorf(0.5f * hi)) + lo;
+}
+
+// sin(pi f c), cos(pi f c)
 template <typename T>
 __device__ __forceinline__ void write_features(T *row, const MlpDev &w, float rh, float zh) {
 #pragma unroll 4
     for (int q = 0; q < 16; ++q) {
-        double xr = (double)w.freq[q] * (double)rh;
-        double xz = (double)w.freq[q] * (double)zh;
-        xr -= 2.0 * floor(0.5 * xr);
-        xz -= 2.0 * floor(0.5 * xz);
         float sr, cr, sz, cz;
-        sincospif((float)xr, &sr, &cr);
-        sincospif((float)xz, &sz, &cz);
+        sincospif(phase2(w.freq[q], rh), &sr, &cr);
+        sincospif(phase2(w.freq[q], zh), &sz, &cz);
         row[q] = (T)sr;
         row[16 + q] = (T)cr;
         row[32 + q] = (T)sz;

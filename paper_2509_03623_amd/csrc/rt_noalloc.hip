@@ -2,7 +2,7 @@
 // allocation, for callers that cannot allocate device memory.
 //
 // Everything the call needs beyond the caller's inputs and outputs (the
-// partition-function table, the FP64 gradient accumulators and the adjoint's
+// partition-function table, the gradient accumulators and the adjoint's
 // sample tape and cotangents for one band of image rows) is carved from one
 // file-scope device array.  The array exists once per GPU, for the life of
 // the process, and every call on that GPU shares it: calls that overlap on one

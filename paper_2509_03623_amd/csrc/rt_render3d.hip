@@ -35,13 +35,30 @@
 
 namespace rt {
 
-// Per-launch camera geometry (set-up in double, once per ray).
+// Per-launch camera geometry (float, the per-ray set-up included).
 struct Geometry3 {
-    double d_pix, cpa, spa, si, ci;
-    double rc2;              // squared radius of the bounding sphere r_max e^dln [au^2]
-    double xc, yc;
+    float d_pix, cpa, spa, si, ci;
+    float rc2;               // squared radius of the bounding sphere r_max e^dln [au^2]
+    float xc, yc;
     int32_t nx, ny, nsamp, pad_;
 };
+
+// The ray through pixel (p, q) in the sky frame (x', y'), and h^2 = rc^2 -
+// x'^2 - y'^2: the chord through the bounding sphere is s in [-h, h], its
+// midpoint at s = 0 on the sky plane.
+struct Chord3 {
+    float xp, yp, h2;
+};
+
+__device__ __forceinline__ Chord3 chord3(const Geometry3 &g, int p, int q) {
+    const float X = ((float)p + 0.5f - g.xc) * g.d_pix;
+    const float Y = ((float)q + 0.5f - g.yc) * g.d_pix;
+    Chord3 c;
+    c.xp = fmaf(g.cpa, X, -g.spa * Y);
+    c.yp = fmaf(g.spa, X, g.cpa * Y);
+    c.h2 = fmaf(-c.xp, c.xp, fmaf(-c.yp, c.yp, g.rc2));
+    return c;
+}
 
 // Fields and channel-independent constants.
 struct Shade3 {
@@ -190,14 +207,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CB <= 24 ? 
 #pragma unroll
     for (int c = 0; c < CB; ++c) { I[c] = 0.0f; Tr[c] = 1.0f; }
     // ray set-up: chord through the bounding sphere, midpoint at s = 0
-    const double X = ((double)(inside ? p : 0) + 0.5 - g.xc) * g.d_pix;
-    const double Y = ((double)(inside ? q : 0) + 0.5 - g.yc) * g.d_pix;
-    const double xp = g.cpa * X - g.spa * Y, yp = g.spa * X + g.cpa * Y;
-    const double h2 = g.rc2 - xp * xp - yp * yp;
-    if (inside && h2 > 0.0) {
-        const float ds = (float)(2.0 * sqrt(h2) / g.nsamp);
-        const float pxr = (float)xp, pmy = (float)(yp * g.ci), pmz = (float)(yp * g.si);
-        const float wy = (float)g.si, wz = (float)(-g.ci);
+    const Chord3 cr = chord3(g, inside ? p : 0, inside ? q : 0);
+    if (inside && cr.h2 > 0.0f) {
+        const float ds = 2.0f * sqrtf(cr.h2) / (float)g.nsamp;
+        const float pxr = cr.xp, pmy = cr.yp * g.ci, pmz = cr.yp * g.si;
+        const float wy = g.si, wz = -g.ci;
         const float half = 0.5f * (float)g.nsamp;
         const int len = (g.nsamp + NSPLIT - 1) / NSPLIT;
         const int k0 = split * len;
@@ -364,10 +378,7 @@ __global__ __launch_bounds__(256) void census3(Geometry3 g, uint8_t *__restrict_
     const int pix = blockIdx.x * 256 + threadIdx.x;
     if (pix < g.nx * g.ny) {
         const int p = pix % g.nx, q = pix / g.nx;
-        const double X = ((double)p + 0.5 - g.xc) * g.d_pix;
-        const double Y = ((double)q + 0.5 - g.yc) * g.d_pix;
-        const double xp = g.cpa * X - g.spa * Y, yp = g.spa * X + g.cpa * Y;
-        const bool live = g.rc2 - xp * xp - yp * yp > 0.0;
+        const bool live = chord3(g, p, q).h2 > 0.0f;
         if (mask) mask[pix] = live ? 1 : 0;
         if (live) atomicAdd(&part, 1ull);
     }

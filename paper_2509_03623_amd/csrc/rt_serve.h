@@ -46,7 +46,8 @@ struct GradDesc {
     const float *target;       // [nch][ny][nx]
     float *cube;               // [nch][ny][nx] (written by the reverse march)
     float4 *tape, *rays, *cot; // scratch: [nsamp][npix], [npix], [nblk][nsamp][npix]
-    double *acc;               // accumulators [3 nr nz + 2 nr]: ln n, T, v_phi, z_lo, z_up
+    double *acc;               // accumulators [3 nr nz + 2 nr]: ln n, T, v_phi, z_lo, z_up (sized for
+                               // double; float ones, the default, use the head of it)
     float *out[5];             // caller's gradient outputs in the same order (NULL: not requested)
     double *loss;              // L of this request
     int32_t nch, nblk;         // channels, cotangent slices (of 2 kGradCB channels)

@@ -41,12 +41,12 @@ void grad_batch_items(int nch, long npix, int nsamp, int nfp, uint32_t items[3],
     items[2] = (uint32_t)nfp * *chunks;
 }
 
-// LDS of the chain pass: one field of the grid (float) and the two surface
-// vectors (double), beside the partition table
+// LDS of the chain pass: one field of the grid and the two surface vectors
+// (float), beside the partition table
 constexpr size_t kGradChainLdsMax = 160 * 1024 - sizeof(float4) * (kZTableNodes - 1) - 1024;
 
 static size_t chain_lds_bytes(int nr, int nz) {
-    return 2 * (size_t)nr * sizeof(double) + (size_t)nr * nz * sizeof(float);
+    return 2 * (size_t)nr * sizeof(float) + (size_t)nr * nz * sizeof(float);
 }
 
 bool grad_batch_grid_fits(int nr, int nz) { return chain_lds_bytes(nr, nz) <= kGradChainLdsMax; }
@@ -87,10 +87,14 @@ __device__ __forceinline__ void stage_table(const float4 *tab, float4 *lds, cons
     }
 }
 
+// accumulators of type A (float, or double with RT_OPT_GRAD_ACCUM 1) at the
+// head of the request's double-sized accumulator region
+template <typename A>
 __global__ __launch_bounds__(256) void grad_zero(const GradDesc *__restrict__ descs) {
     const GradDesc &D = descs[blockIdx.y];
     const size_t n = 3 * (size_t)D.s.nr * D.s.nz + 2 * (size_t)D.s.nr;
-    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) D.acc[i] = 0.0;
+    A *acc = (A *)D.acc;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) acc[i] = (A)0;
     if (blockIdx.x == 0 && threadIdx.x == 0) *D.loss = 0.0;
 }
 
@@ -148,13 +152,14 @@ __global__ __launch_bounds__(256) void grad_march(const GradDesc *__restrict__ d
 // Chain pass: each item is one field pass over a contiguous chunk of one
 // request's pixel-samples.  The workgroup (1024 lanes, one per CU) clears
 // that field's grid in LDS, adds every sample's bilinear contributions there
-// (and, in the request's first field pass, the two surfaces' in LDS doubles),
-// then flushes the nodes it touched into the request's FP64 accumulators.
+// (and, in the request's first field pass, the two surfaces'),
+// then flushes the nodes it touched into the request's accumulators (type A).
 // Every pass sums the request's cotangent slices itself, so passes of one
 // request may run at the same time.
+template <typename A>
 __global__ __launch_bounds__(kGradChainThreads) void grad_chain(const GradDesc *__restrict__ descs, int nreq,
                                                                uint32_t nitems, uint32_t *__restrict__ counter) {
-    extern __shared__ double dyn[];   // [2 nr] surfaces, then [nr nz] field (float)
+    extern __shared__ float dyn[];    // [2 nr] surfaces, then [nr nz] field
     __shared__ float4 ztab[kZTableNodes - 1];
     __shared__ uint32_t s_item;
     __shared__ const float4 *s_tab;
@@ -174,10 +179,10 @@ __global__ __launch_bounds__(kGradChainThreads) void grad_chain(const GradDesc *
         const int field = D.fields[fp];
         const bool surf = fp == 0 && (D.out[3] || D.out[4]);
         const int nr = D.s.nr, nn = D.s.nr * D.s.nz;
-        double *sl = dyn;
-        float *fl = (float *)(dyn + 2 * nr);
+        float *sl = dyn;
+        float *fl = dyn + 2 * nr;
         if (surf)
-            for (int i = threadIdx.x; i < 2 * nr; i += kGradChainThreads) sl[i] = 0.0;
+            for (int i = threadIdx.x; i < 2 * nr; i += kGradChainThreads) sl[i] = 0.0f;
         if (field < 3)
             for (int i = threadIdx.x; i < nn; i += kGradChainThreads) fl[i] = 0.0f;
         __syncthreads();
@@ -209,34 +214,36 @@ __global__ __launch_bounds__(kGradChainThreads) void grad_chain(const GradDesc *
             }
             if (surf) {
                 if (t.gzl != 0.0f) {
-                    atomicAdd(sl + t.i0, (double)(t.gzl * (1.0f - fu)));
-                    atomicAdd(sl + t.i0 + 1, (double)(t.gzl * fu));
+                    atomicAdd(sl + t.i0, t.gzl * (1.0f - fu));
+                    atomicAdd(sl + t.i0 + 1, t.gzl * fu);
                 }
                 if (t.gzu != 0.0f) {
-                    atomicAdd(sl + nr + t.i0, (double)(t.gzu * (1.0f - fu)));
-                    atomicAdd(sl + nr + t.i0 + 1, (double)(t.gzu * fu));
+                    atomicAdd(sl + nr + t.i0, t.gzu * (1.0f - fu));
+                    atomicAdd(sl + nr + t.i0 + 1, t.gzu * fu);
                 }
             }
         }
         __syncthreads();
         if (field < 3) {
-            double *dst = D.acc + (size_t)field * nn;
+            A *dst = (A *)D.acc + (size_t)field * nn;
             for (int i = threadIdx.x; i < nn; i += kGradChainThreads)
-                if (fl[i] != 0.0f) atomicAdd(dst + i, (double)fl[i]);
+                if (fl[i] != 0.0f) atomicAdd(dst + i, (A)fl[i]);
         }
         if (surf) {
-            double *zl = D.acc + 3 * (size_t)nn, *zu = zl + nr;
+            A *zl = (A *)D.acc + 3 * (size_t)nn, *zu = zl + nr;
             for (int i = threadIdx.x; i < nr; i += kGradChainThreads) {
-                if (D.out[3] && sl[i] != 0.0) atomicAdd(zl + i, sl[i]);
-                if (D.out[4] && sl[nr + i] != 0.0) atomicAdd(zu + i, sl[nr + i]);
+                if (D.out[3] && sl[i] != 0.0f) atomicAdd(zl + i, (A)sl[i]);
+                if (D.out[4] && sl[nr + i] != 0.0f) atomicAdd(zu + i, (A)sl[nr + i]);
             }
         }
     }
 }
 
-// blockIdx.y = request: its FP64 accumulators to the caller's FP32 outputs
+// blockIdx.y = request: its accumulators to the caller's FP32 outputs
+template <typename A>
 __global__ __launch_bounds__(256) void grad_finish(const GradDesc *__restrict__ descs) {
     const GradDesc &D = descs[blockIdx.y];
+    const A *acc = (const A *)D.acc;
     const size_t nn = (size_t)D.s.nr * D.s.nz, nr = (size_t)D.s.nr;
     const size_t off[5] = {0, nn, 2 * nn, 3 * nn, 3 * nn + nr};
     const size_t len[5] = {nn, nn, nn, nr, nr};
@@ -244,7 +251,7 @@ __global__ __launch_bounds__(256) void grad_finish(const GradDesc *__restrict__ 
         float *o = D.out[f];
         if (!o) continue;
         for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < len[f]; i += (size_t)gridDim.x * 256)
-            o[i] = (float)D.acc[off[f] + i];
+            o[i] = (float)acc[off[f] + i];
     }
 }
 
@@ -271,8 +278,9 @@ __global__ void zero_counters(uint32_t *c) {
     if (threadIdx.x < 3) c[threadIdx.x] = 0u;
 }
 
-hipError_t launch_grad_batch(const GradDesc *descs, const GradDesc *host_descs, int nreq, const uint32_t nitems[3],
-                             uint32_t *counters, int nwg, hipStream_t st) {
+template <typename A>
+static hipError_t grad_batch_t(const GradDesc *descs, const GradDesc *host_descs, int nreq, const uint32_t nitems[3],
+                              uint32_t *counters, int nwg, hipStream_t st) {
     size_t max_acc = 0, max_cube = 0;
     for (int i = 0; i < nreq; ++i) {
         const GradDesc &D = host_descs[i];
@@ -280,7 +288,7 @@ hipError_t launch_grad_batch(const GradDesc *descs, const GradDesc *host_descs, 
         max_cube = std::max(max_cube, (size_t)D.nch * D.g.nx * D.g.ny);
     }
     hipLaunchKernelGGL(zero_counters, dim3(1), dim3(64), 0, st, counters);
-    hipLaunchKernelGGL(grad_zero, dim3((unsigned)std::min<size_t>((max_acc + 255) / 256, 64), nreq), dim3(256), 0, st,
+    hipLaunchKernelGGL(grad_zero<A>, dim3((unsigned)std::min<size_t>((max_acc + 255) / 256, 64), nreq), dim3(256), 0, st,
                        descs);
     hipLaunchKernelGGL(grad_tape, dim3(nwg), dim3(256), 0, st, descs, nreq, nitems[0], counters);
     hipLaunchKernelGGL(grad_march, dim3(nwg), dim3(256), 0, st, descs, nreq, nitems[1], counters + 1);
@@ -290,16 +298,22 @@ hipError_t launch_grad_batch(const GradDesc *descs, const GradDesc *host_descs, 
     if (e != hipSuccess) return e;
     size_t lds = 0;
     for (int i = 0; i < nreq; ++i) lds = std::max(lds, chain_lds_bytes(host_descs[i].s.nr, host_descs[i].s.nz));
-    if ((e = hipFuncSetAttribute((const void *)grad_chain, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)) !=
+    if ((e = hipFuncSetAttribute((const void *)grad_chain<A>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)) !=
         hipSuccess)
         return e;
-    hipLaunchKernelGGL(grad_chain, dim3(std::max<int>(1, std::min<int>(ncu, (int)nitems[2]))), dim3(kGradChainThreads),
+    hipLaunchKernelGGL(grad_chain<A>, dim3(std::max<int>(1, std::min<int>(ncu, (int)nitems[2]))), dim3(kGradChainThreads),
                        lds, st, descs, nreq, nitems[2], counters + 2);
-    hipLaunchKernelGGL(grad_finish, dim3((unsigned)std::min<size_t>((max_acc + 255) / 256, 64), nreq), dim3(256), 0,
+    hipLaunchKernelGGL(grad_finish<A>, dim3((unsigned)std::min<size_t>((max_acc + 255) / 256, 64), nreq), dim3(256), 0,
                        st, descs);
     hipLaunchKernelGGL(grad_loss, dim3((unsigned)std::min<size_t>((max_cube + 255) / 256, 128), nreq), dim3(256), 0,
                        st, descs);
     return hipGetLastError();
+}
+
+hipError_t launch_grad_batch(const GradDesc *descs, const GradDesc *host_descs, int nreq, const uint32_t nitems[3],
+                             uint32_t *counters, int nwg, hipStream_t st) {
+    return grad_accum_double() ? grad_batch_t<double>(descs, host_descs, nreq, nitems, counters, nwg, st)
+                               : grad_batch_t<float>(descs, host_descs, nreq, nitems, counters, nwg, st);
 }
 
 } // namespace rt

@@ -125,6 +125,30 @@ def test_adjoint_in_row_bands(cap):
         check_block(k, banded[k], ref[k])
 
 
+def test_double_accumulators():
+    """RT_OPT_GRAD_ACCUM 1 (double accumulators, in the privatised chain and
+    in the global-atomic chain of grids too large for LDS) meets the same bar
+    as the float default, and the two agree to 1e-5 of each block's largest
+    entry (float atomics over ~10^2 workgroup partials per node)."""
+    rt = _rt()
+    from paper_2509_03623_amd import _lib as L
+    prob = kscale(synth.small_problem(nx=19, ny=17, nch=37, nsamp=61, nr=40, nz=20, seed=21, dv=0.1))
+    big = kscale(synth.small_problem(nx=16, ny=12, nch=6, nsamp=40, nr=260, nz=160, seed=22, dv=0.2))
+    for pr in (prob, big):
+        target = target_for(pr)
+        cot = 2.0 * (oracle.render(pr) - target)
+        f32, _, _ = gpu_grads(pr, target, cotangent=cot)
+        rt.set_option(L.RT_OPT_GRAD_ACCUM, 1)
+        try:
+            f64, _, _ = gpu_grads(pr, target, cotangent=cot)
+        finally:
+            rt.set_option(L.RT_OPT_GRAD_ACCUM, 0)
+        _, ref = torch_ref.loss_and_grad(pr, target)
+        for k in BLOCKS:
+            assert np.abs(f64[k] - f32[k]).max() <= 1e-5 * np.abs(f64[k]).max(), k
+            check_block(k, f64[k], ref[k])
+
+
 def test_end_to_end_l2_gradient():
     """dL/dI from the GPU's own FP32 forward: the loss gradient still meets the
     L2 bar against the FP64 oracle (its per-entry tail is looser because FP32
