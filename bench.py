@@ -303,7 +303,11 @@ def main():
     kern_ms = per_seed[med]["kernel_ms"]
     rs = per_seed[med]["ray_samples"]
     thin = per_seed[med]["thin_fraction"]
-    cb = rt.get_option(L.RT_OPT_CHANNEL_BLOCK) or auto_shape(sc.nch, sc.nx * sc.ny, sc.nsamp)[0]
+    cb, split = auto_shape(sc.nch, sc.nx * sc.ny, sc.nsamp)
+    cb = rt.get_option(L.RT_OPT_CHANNEL_BLOCK) or cb
+    split = rt.get_option(L.RT_OPT_RAY_SPLIT) or split
+    # 64-channel blocks on one lane per pixel run paired (uniform channels)
+    kname = "march_fwd_pair" if cb == 64 and split == 1 and rt.get_option(L.RT_OPT_FWD_PAIR) else "march_fwd"
     flop, slots = algorithmic(sc.nch, cb, thin)
     achieved = flop * rs / (kern_ms * 1e-3) / 1e12
     peak = flop / slots * LANE_SLOTS_PER_S / 1e12
@@ -327,7 +331,7 @@ def main():
                    "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": measured_traffic(med),
-                     "kernel": "march_fwd", "kernel_ms": kern_ms, "disk": med,
+                     "kernel": kname, "kernel_ms": kern_ms, "disk": med,
                      "thin_fraction": thin, "flop_per_ray_sample": flop, "issue_slots_per_ray_sample": slots,
                      "hbm_bytes_algorithmic": 4 * sc.nch * sc.nx * sc.ny + 4 * (3 * sc.nr * sc.nz + 2 * sc.nr)},
         "disks": {str(sd): v for sd, v in per_seed.items()},

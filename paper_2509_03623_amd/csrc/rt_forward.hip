@@ -68,6 +68,68 @@ __global__ __launch_bounds__(256) void march_fwd(Geometry g, Shade s, Channels c
         if (c0 + c < ch.n) cube[(size_t)(c0 + c) * ch_stride + pix] = I[c];
 }
 
+// value of the other lane of an adjacent pair (DPP quad permutation 1,0,3,2)
+__device__ __forceinline__ float pair_swap(float x) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0xB1, 0xF, 0xF, false));
+}
+
+// Paired-lane march of one 64-channel block: the two adjacent lanes of a
+// pair share one pixel, lane h holding channels c0 + 32 h ... c0 + 32 h + 31
+// in registers.  Each lane shades every other sample (lane h sample k + h of
+// each step of two) and hands its partner the shading (S, K, a, b) by a DPP
+// swap, so the shading is still evaluated once per sample for all 64
+// channels while a lane carries half the state of a 64-channel lane (4 waves
+// per SIMD instead of 3).  The upper half's velocities must be the lower
+// half's plus `shift` (uniform channel spacing): the channel velocities stay
+// wave-uniform scalars, and lane 1 folds the shift into a, since
+// d_c = a - (v_c + shift) b = (a - shift b) - v_c b.
+template <bool THIN, bool NEURAL>
+__global__ __launch_bounds__(256) void march_fwd_pair(Geometry g, Shade s, Channels ch, float shift,
+                                                       float *__restrict__ cube, int ch_stride) {
+    __shared__ float4 ztab[kZTableNodes - 1];
+    stage_ztab(s, ztab);
+    constexpr int CB = 32, TW = 16, TH = 8;           // 128 pixels per workgroup
+    const int tiles_x = (g.nx + TW - 1) / TW;
+    const int h = threadIdx.x & 1;
+    const int slot = threadIdx.x >> 1;
+    const int p = (blockIdx.x % tiles_x) * TW + slot % TW;
+    const int q = (blockIdx.x / tiles_x) * TH + slot / TW;
+    const int c0 = blockIdx.y * 2 * CB;
+    const bool inside = p < g.nx && q < g.ny;
+    float I[CB], Tr[CB];
+#pragma unroll
+    for (int c = 0; c < CB; ++c) { I[c] = 0.0f; Tr[c] = 1.0f; }
+    const RaySetup r = ray_setup(g, inside ? p : 0, inside ? q : 0);
+    // both lanes of a pair take this branch together (same pixel)
+    if (inside && r.live) {
+        const float half = 0.5f * (float)g.nsamp;
+        const float vsh = h ? shift : 0.0f;
+        const int pix = q * g.nx + p;
+        for (int k = 0; k < g.nsamp; k += 2) {
+            const int kk = min(k + h, g.nsamp - 1);
+            const float t = ((float)kk + 0.5f - half) * r.ds;
+            const SampleQ own = shade_sample<NEURAL>(s, ztab, r.px, fmaf(t, r.wy, r.pmy), fmaf(t, r.wz, r.pmz), r.ds,
+                                                     o_index(s, kk, pix));
+            SampleQ oth;
+            oth.S = pair_swap(own.S);
+            oth.K = pair_swap(own.K);
+            oth.a = pair_swap(own.a);
+            oth.b = pair_swap(own.b);
+            SampleQ q0 = h ? oth : own, q1 = h ? own : oth;
+            q0.a = fmaf(-vsh, q0.b, q0.a);
+            q1.a = fmaf(-vsh, q1.b, q1.a);
+            march_sample<CB, THIN>(I, Tr, q0, [&](int c) { return ch.v[c0 + c]; });
+            if (k + 1 < g.nsamp) march_sample<CB, THIN>(I, Tr, q1, [&](int c) { return ch.v[c0 + c]; });
+        }
+    }
+    if (!inside) return;
+    const size_t pix = (size_t)q * g.nx + p;
+    const int cl = c0 + h * CB;
+#pragma unroll
+    for (int c = 0; c < CB; ++c)
+        if (cl + c < ch.n) cube[(size_t)(cl + c) * ch_stride + pix] = I[c];
+}
+
 template <int CB, bool THIN, int NSPLIT>
 static hipError_t launch_t(const Geometry &g, const Shade &s, const Channels &ch, float *cube, hipStream_t st) {
     constexpr int TW = NSPLIT <= 2 ? 16 : 8;
@@ -110,6 +172,21 @@ hipError_t launch_forward(const Geometry &g, const Shade &s, const Channels &ch,
     case 64: return launch_cb<64>(g, s, ch, cube, thin, nsplit, st);
     default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_forward_pair(const Geometry &g, const Shade &s, const Channels &ch, float *cube, bool thin,
+                               float shift, hipStream_t st) {
+    const int tiles = ((g.nx + 15) / 16) * ((g.ny + 7) / 8);
+    dim3 grid(tiles, (ch.n + 63) / 64);
+    const int cs = g.nx * g.ny;
+    if (s.mlp_o) {
+        if (thin) hipLaunchKernelGGL((march_fwd_pair<true, true>), grid, dim3(256), 0, st, g, s, ch, shift, cube, cs);
+        else hipLaunchKernelGGL((march_fwd_pair<false, true>), grid, dim3(256), 0, st, g, s, ch, shift, cube, cs);
+    } else {
+        if (thin) hipLaunchKernelGGL((march_fwd_pair<true, false>), grid, dim3(256), 0, st, g, s, ch, shift, cube, cs);
+        else hipLaunchKernelGGL((march_fwd_pair<false, false>), grid, dim3(256), 0, st, g, s, ch, shift, cube, cs);
+    }
+    return hipGetLastError();
 }
 
 } // namespace rt

@@ -52,6 +52,7 @@ static int64_t g_opt_accum = 0;
 static int64_t g_opt_adj_cap = 0;
 static int64_t g_opt_adj_cb = 0;
 static int64_t g_opt_adj_lanes = 0;
+static int64_t g_opt_pair = 1;
 
 // Launch shape of the forward march: channels per lane (cb) and lanes per
 // ray (nsplit).  Measured on MI355X: one channel block per pixel is best
@@ -359,6 +360,23 @@ rt_status build_launch(const rt_problem *p, Geometry *g, Shade *s, const float4 
     return RT_OK;
 }
 
+// The paired-lane march needs, in every 64-channel block, the upper 32
+// velocities to be the lower 32 plus one shift (uniform spacing gives
+// 32 dv).  True, with the shift, if the n velocities v[] allow it (to 1e-9
+// of the velocity span: the float velocities the march uses round far
+// coarser).
+static bool pair_shift(const double *v, int n, double *shift) {
+    if (n <= 32) { *shift = 0.0; return true; }
+    const double sh = v[32] - v[0];
+    double span = 0.0;
+    for (int c = 0; c < n; ++c) span = std::max(span, std::fabs(v[c] - v[0]));
+    for (int b = 0; b < n; b += 64)
+        for (int c = b; c < std::min(b + 32, n - 32); ++c)
+            if (std::fabs(v[c + 32] - v[c] - sh) > 1e-9 * std::max(span, 1e-12)) return false;
+    *shift = sh;
+    return true;
+}
+
 // Forward march of the whole cube, one launch per chunk of channels.
 rt_status march_cube(const rt_problem *p, const Geometry &g, const Shade &s, float *cube, hipStream_t stream) {
     int cb, nsplit;
@@ -370,7 +388,12 @@ rt_status march_cube(const rt_problem *p, const Geometry &g, const Shade &s, flo
         std::memset(&ch, 0, sizeof ch);
         ch.n = std::min(kLaunchChannels, p->spec.nch - c0);
         for (int c = 0; c < ch.n; ++c) ch.v[c] = (float)p->spec.v_kms[c0 + c];
-        hipError_t e = launch_forward(g, s, ch, cube + (size_t)c0 * plane, cb, thin_series(), nsplit, stream);
+        double shift = 0.0;
+        hipError_t e;
+        if (cb == 64 && nsplit == 1 && g_opt_pair && pair_shift(p->spec.v_kms + c0, ch.n, &shift))
+            e = launch_forward_pair(g, s, ch, cube + (size_t)c0 * plane, thin_series(), (float)shift, stream);
+        else
+            e = launch_forward(g, s, ch, cube + (size_t)c0 * plane, cb, thin_series(), nsplit, stream);
         if (e != hipSuccess) return fail_hip(e, "forward launch");
     }
     return RT_OK;
@@ -427,6 +450,10 @@ rt_status rt_set_option(int32_t key, int64_t value) {
             return fail(RT_EINVAL, "ray split must be 0, 1, 2, 4 or 8");
         g_opt_split = value;
         return RT_OK;
+    case RT_OPT_FWD_PAIR:
+        if (value != 0 && value != 1) return fail(RT_EINVAL, "paired-lane forward must be 0 or 1");
+        g_opt_pair = value;
+        return RT_OK;
     default:
         return fail(RT_EINVAL, "unknown option %d", key);
     }
@@ -442,6 +469,7 @@ int64_t rt_get_option(int32_t key) {
     case RT_OPT_ADJ_SCRATCH_CAP: return g_opt_adj_cap;
     case RT_OPT_ADJ_CHANNEL_BLOCK: return g_opt_adj_cb;
     case RT_OPT_ADJ_PIXEL_LANES: return g_opt_adj_lanes;
+    case RT_OPT_FWD_PAIR: return g_opt_pair;
     default: return -1;
     }
 }

@@ -21,18 +21,19 @@ def _rt():
     return rt
 
 
-def gpu_cube(prob, **opts):
+def gpu_cube(prob, mlp_fp32=False, **opts):
     rt = _rt()
     from paper_2509_03623_amd import _lib as L
     old = {}
     for k, v in opts.items():
-        key = {"cb": L.RT_OPT_CHANNEL_BLOCK, "thin": L.RT_OPT_THIN_EXPM1, "split": L.RT_OPT_RAY_SPLIT}[k]
+        key = {"cb": L.RT_OPT_CHANNEL_BLOCK, "thin": L.RT_OPT_THIN_EXPM1, "split": L.RT_OPT_RAY_SPLIT,
+               "pair": L.RT_OPT_FWD_PAIR}[k]
         old[key] = rt.get_option(key)
         rt.set_option(key, v)
     try:
         print(f"[gpu] render {prob.meta.get('config')} {prob.camera.nx}x{prob.camera.ny}x{prob.nch} "
               f"ns={prob.nsamp} opts={opts}", flush=True)
-        sc = rt.scene_from_problem(prob)
+        sc = rt.scene_from_problem(prob, mlp_precision=rt.RT_MLP_FP32) if mlp_fp32 else rt.scene_from_problem(prob)
         cube = rt.render(sc)
         torch.cuda.synchronize()
         return cube.cpu().numpy().astype(np.float64)
@@ -71,6 +72,36 @@ def test_ray_split_lanes(cb, split):
     prob = synth.small_problem(nx=21, ny=19, nch=11, nsamp=97, nr=64, nz=32, seed=17, dv=0.25)
     ref = oracle.render(prob)
     got = gpu_cube(prob, cb=cb, split=split)
+    assert rel_err(got, ref) <= TOL
+
+
+@pytest.mark.parametrize("nch,thin,mlp", [(64, 1, False), (100, 1, False), (100, 0, False), (40, 1, True)])
+def test_paired_lane_march(nch, thin, mlp):
+    """64-channel blocks on two lanes per pixel (32 channels each, the
+    shading of alternate samples passed between them): two blocks with a
+    ragged second one (100 channels), an odd sample count (the last step has
+    one sample), ragged 16 x 8 tiles, the network variant (its FP32 path);
+    against the oracle and against the one-lane march of the same blocks."""
+    prob = synth.small_problem(nx=35, ny=21, nch=nch, nsamp=97, nr=64, nz=32, seed=23, dv=0.1,
+                               mlp_seed=5 if mlp else None)
+    ref = oracle.render(prob)
+    got = gpu_cube(prob, mlp_fp32=mlp, cb=64, split=1, thin=thin, pair=1)
+    one = gpu_cube(prob, mlp_fp32=mlp, cb=64, split=1, thin=thin, pair=0)
+    assert rel_err(got, ref) <= TOL
+    assert rel_err(got, one) <= 2e-6
+
+
+def test_paired_lane_march_needs_uniform_spacing():
+    """Velocities whose upper half-block is not the lower half shifted by one
+    constant take the one-lane march (bit-identical to it)."""
+    prob = synth.small_problem(nx=19, ny=17, nch=64, nsamp=40, nr=48, nz=24, seed=24, dv=0.1)
+    v = prob.v_kms.copy()
+    v[40] += 0.013
+    prob = prob.replace(v_kms=v)
+    ref = oracle.render(prob)
+    got = gpu_cube(prob, cb=64, split=1, pair=1)
+    one = gpu_cube(prob, cb=64, split=1, pair=0)
+    assert np.array_equal(got, one)
     assert rel_err(got, ref) <= TOL
 
 
