@@ -306,8 +306,10 @@ def main():
     cb, split = auto_shape(sc.nch, sc.nx * sc.ny, sc.nsamp)
     cb = rt.get_option(L.RT_OPT_CHANNEL_BLOCK) or cb
     split = rt.get_option(L.RT_OPT_RAY_SPLIT) or split
-    # 64-channel blocks on one lane per pixel run paired (uniform channels)
-    kname = "march_fwd_pair" if cb == 64 and split == 1 and rt.get_option(L.RT_OPT_FWD_PAIR) else "march_fwd"
+    # 64-channel blocks on one lane per pixel run on a group of lanes per
+    # pixel (uniform channels; 4 lanes unless set)
+    group = rt.get_option(L.RT_OPT_FWD_GROUP) or 4
+    kname = f"march_fwd_group<{group}>" if cb == 64 and split == 1 and group > 1 else "march_fwd"
     flop, slots = algorithmic(sc.nch, cb, thin)
     achieved = flop * rs / (kern_ms * 1e-3) / 1e12
     peak = flop / slots * LANE_SLOTS_PER_S / 1e12

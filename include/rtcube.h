@@ -470,14 +470,15 @@ int32_t rt_constants(double *out, int32_t n);
  * image whose scratch exceeds it is differentiated in bands of whole pixel
  * rows, at least one row per band (0 = default, 8 GiB).  The library keeps
  * that scratch with the stream it ran on and reuses it on later calls.
- * RT_OPT_FWD_PAIR: 1 (default) renders 64-channel blocks with two lanes per
- * pixel, 32 channels each, sharing each sample's shading, when every block's
- * upper 32 channel velocities are its lower 32 plus one constant (uniform
- * spacing) and the launch shape is one 64-channel lane per pixel; 0 keeps one
- * lane per pixel. */
+ * RT_OPT_FWD_GROUP: lanes per pixel of the forward march of 64-channel
+ * blocks (1, 2 or 4; 0 = automatic): with G > 1 the G lanes of a pixel hold
+ * 64/G channels each and share each sample's shading.  Used when the launch
+ * shape is one 64-channel lane per pixel and each block's channel
+ * velocities are uniformly spaced in groups of 64/G (lane m's = lane 0's +
+ * m times one constant); otherwise one lane per pixel. */
 enum { RT_OPT_CHANNEL_BLOCK = 1, RT_OPT_THIN_EXPM1 = 2, RT_OPT_CKPT_SEGMENT = 3, RT_OPT_RAY_SPLIT = 4,
        RT_OPT_GRAD_ACCUM = 5, RT_OPT_ADJ_SCRATCH_CAP = 6, RT_OPT_ADJ_CHANNEL_BLOCK = 7,
-       RT_OPT_ADJ_PIXEL_LANES = 8, RT_OPT_FWD_PAIR = 9 };
+       RT_OPT_ADJ_PIXEL_LANES = 8, RT_OPT_FWD_GROUP = 9 };
 rt_status rt_set_option(int32_t key, int64_t value);
 int64_t rt_get_option(int32_t key);
 

@@ -24,7 +24,7 @@ RT_MLP_PARAMS = 58243
 RT_REQ_FWD, RT_REQ_FWD_ADJ, RT_REQ_FWD_LOSS = 0, 1, 2
 RT_TICKET_QUEUED, RT_TICKET_RUNNING, RT_TICKET_DONE, RT_TICKET_CANCELED, RT_TICKET_FAILED = 0, 1, 2, 3, 4
 RT_OPT_CHANNEL_BLOCK, RT_OPT_THIN_EXPM1, RT_OPT_CKPT_SEGMENT, RT_OPT_RAY_SPLIT, RT_OPT_GRAD_ACCUM = 1, 2, 3, 4, 5
-RT_OPT_ADJ_SCRATCH_CAP, RT_OPT_ADJ_CHANNEL_BLOCK, RT_OPT_ADJ_PIXEL_LANES, RT_OPT_FWD_PAIR = 6, 7, 8, 9
+RT_OPT_ADJ_SCRATCH_CAP, RT_OPT_ADJ_CHANNEL_BLOCK, RT_OPT_ADJ_PIXEL_LANES, RT_OPT_FWD_GROUP = 6, 7, 8, 9
 
 
 class rt_grid(C.Structure):

@@ -8,6 +8,8 @@
 // projected velocity) and then runs the channel loop entirely in registers:
 // profile, optical depth, front-to-back accumulation of I and transmission.
 // Nothing is skipped: every (pixel, channel, sample) is evaluated.
+#include <type_traits>
+
 #include "rt_kernels.h"
 #include "rt_launch.h"
 
@@ -68,58 +70,67 @@ __global__ __launch_bounds__(256) void march_fwd(Geometry g, Shade s, Channels c
         if (c0 + c < ch.n) cube[(size_t)(c0 + c) * ch_stride + pix] = I[c];
 }
 
-// value of the other lane of an adjacent pair (DPP quad permutation 1,0,3,2)
-__device__ __forceinline__ float pair_swap(float x) {
-    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0xB1, 0xF, 0xF, false));
+// Lane j of this lane's group of G (2 or 4) adjacent lanes: a DPP quad
+// permutation that gives every lane of the group the value of its member j.
+template <int G, int J>
+__device__ __forceinline__ float group_lane(float x) {
+    constexpr int sel = G == 4 ? J * 0x55 : (J == 0 ? 0xA0 : 0xF5);   // (j,j,j,j) or (j,j,2+j,2+j)
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), sel, 0xF, 0xF, false));
 }
 
-// Paired-lane march of one 64-channel block: the two adjacent lanes of a
-// pair share one pixel, lane h holding channels c0 + 32 h ... c0 + 32 h + 31
-// in registers.  Each lane shades every other sample (lane h sample k + h of
-// each step of two) and hands its partner the shading (S, K, a, b) by a DPP
-// swap, so the shading is still evaluated once per sample for all 64
-// channels while a lane carries half the state of a 64-channel lane (4 waves
-// per SIMD instead of 3).  The upper half's velocities must be the lower
-// half's plus `shift` (uniform channel spacing): the channel velocities stay
-// wave-uniform scalars, and lane 1 folds the shift into a, since
-// d_c = a - (v_c + shift) b = (a - shift b) - v_c b.
-template <bool THIN, bool NEURAL>
-__global__ __launch_bounds__(256) void march_fwd_pair(Geometry g, Shade s, Channels ch, float shift,
-                                                       float *__restrict__ cube, int ch_stride) {
+// Grouped-lane march of one 64-channel block: G adjacent lanes share one
+// pixel, lane h holding channels c0 + h CB ... c0 + h CB + CB - 1 (CB =
+// 64 / G) in registers.  Each lane shades one of every G consecutive samples
+// (lane h sample k + h) and the group passes the shadings (S, K, a, b)
+// around by DPP, so each sample is still shaded once for all 64 channels
+// while a lane carries 1/G of the state of a 64-channel lane (4 waves per
+// SIMD at G = 2, 5 at G = 4, against 3).  Lane h's velocities must be lane
+// 0's plus h `shift` (uniform channel spacing): the channel velocities stay
+// wave-uniform scalars, and lane h folds its offset into a, since
+// d_c = a - (v_c + h shift) b = (a - h shift b) - v_c b.
+template <int G, bool THIN, bool NEURAL>
+__global__ __launch_bounds__(256) void march_fwd_group(Geometry g, Shade s, Channels ch, float shift,
+                                                        float *__restrict__ cube, int ch_stride) {
     __shared__ float4 ztab[kZTableNodes - 1];
     stage_ztab(s, ztab);
-    constexpr int CB = 32, TW = 16, TH = 8;           // 128 pixels per workgroup
+    constexpr int CB = 64 / G, TW = G == 2 ? 16 : 8, TH = 256 / G / TW;
     const int tiles_x = (g.nx + TW - 1) / TW;
-    const int h = threadIdx.x & 1;
-    const int slot = threadIdx.x >> 1;
+    const int h = threadIdx.x % G;
+    const int slot = threadIdx.x / G;
     const int p = (blockIdx.x % tiles_x) * TW + slot % TW;
     const int q = (blockIdx.x / tiles_x) * TH + slot / TW;
-    const int c0 = blockIdx.y * 2 * CB;
+    const int c0 = blockIdx.y * 64;
     const bool inside = p < g.nx && q < g.ny;
     float I[CB], Tr[CB];
 #pragma unroll
     for (int c = 0; c < CB; ++c) { I[c] = 0.0f; Tr[c] = 1.0f; }
     const RaySetup r = ray_setup(g, inside ? p : 0, inside ? q : 0);
-    // both lanes of a pair take this branch together (same pixel)
+    // the lanes of a group take this branch together (same pixel)
     if (inside && r.live) {
         const float half = 0.5f * (float)g.nsamp;
-        const float vsh = h ? shift : 0.0f;
+        const float vsh = (float)h * shift;
         const int pix = q * g.nx + p;
-        for (int k = 0; k < g.nsamp; k += 2) {
+        auto vel = [&](int c) { return ch.v[c0 + c]; };
+        for (int k = 0; k < g.nsamp; k += G) {
             const int kk = min(k + h, g.nsamp - 1);
             const float t = ((float)kk + 0.5f - half) * r.ds;
             const SampleQ own = shade_sample<NEURAL>(s, ztab, r.px, fmaf(t, r.wy, r.pmy), fmaf(t, r.wz, r.pmz), r.ds,
                                                      o_index(s, kk, pix));
-            SampleQ oth;
-            oth.S = pair_swap(own.S);
-            oth.K = pair_swap(own.K);
-            oth.a = pair_swap(own.a);
-            oth.b = pair_swap(own.b);
-            SampleQ q0 = h ? oth : own, q1 = h ? own : oth;
-            q0.a = fmaf(-vsh, q0.b, q0.a);
-            q1.a = fmaf(-vsh, q1.b, q1.a);
-            march_sample<CB, THIN>(I, Tr, q0, [&](int c) { return ch.v[c0 + c]; });
-            if (k + 1 < g.nsamp) march_sample<CB, THIN>(I, Tr, q1, [&](int c) { return ch.v[c0 + c]; });
+            auto step = [&](auto jc) {
+                constexpr int J = decltype(jc)::value;
+                SampleQ sq;
+                sq.S = group_lane<G, J>(own.S);
+                sq.K = group_lane<G, J>(own.K);
+                sq.b = group_lane<G, J>(own.b);
+                sq.a = fmaf(-vsh, sq.b, group_lane<G, J>(own.a));
+                if (J == 0 || k + J < g.nsamp) march_sample<CB, THIN>(I, Tr, sq, vel);
+            };
+            step(std::integral_constant<int, 0>{});
+            step(std::integral_constant<int, 1>{});
+            if constexpr (G == 4) {
+                step(std::integral_constant<int, 2>{});
+                step(std::integral_constant<int, 3>{});
+            }
         }
     }
     if (!inside) return;
@@ -174,19 +185,30 @@ hipError_t launch_forward(const Geometry &g, const Shade &s, const Channels &ch,
     }
 }
 
-hipError_t launch_forward_pair(const Geometry &g, const Shade &s, const Channels &ch, float *cube, bool thin,
-                               float shift, hipStream_t st) {
-    const int tiles = ((g.nx + 15) / 16) * ((g.ny + 7) / 8);
+template <int G>
+static hipError_t launch_group_t(const Geometry &g, const Shade &s, const Channels &ch, float *cube, bool thin,
+                                 float shift, hipStream_t st) {
+    constexpr int TW = G == 2 ? 16 : 8, TH = 256 / G / TW;
+    const int tiles = ((g.nx + TW - 1) / TW) * ((g.ny + TH - 1) / TH);
     dim3 grid(tiles, (ch.n + 63) / 64);
     const int cs = g.nx * g.ny;
     if (s.mlp_o) {
-        if (thin) hipLaunchKernelGGL((march_fwd_pair<true, true>), grid, dim3(256), 0, st, g, s, ch, shift, cube, cs);
-        else hipLaunchKernelGGL((march_fwd_pair<false, true>), grid, dim3(256), 0, st, g, s, ch, shift, cube, cs);
+        if (thin) hipLaunchKernelGGL((march_fwd_group<G, true, true>), grid, dim3(256), 0, st, g, s, ch, shift, cube, cs);
+        else hipLaunchKernelGGL((march_fwd_group<G, false, true>), grid, dim3(256), 0, st, g, s, ch, shift, cube, cs);
     } else {
-        if (thin) hipLaunchKernelGGL((march_fwd_pair<true, false>), grid, dim3(256), 0, st, g, s, ch, shift, cube, cs);
-        else hipLaunchKernelGGL((march_fwd_pair<false, false>), grid, dim3(256), 0, st, g, s, ch, shift, cube, cs);
+        if (thin) hipLaunchKernelGGL((march_fwd_group<G, true, false>), grid, dim3(256), 0, st, g, s, ch, shift, cube, cs);
+        else hipLaunchKernelGGL((march_fwd_group<G, false, false>), grid, dim3(256), 0, st, g, s, ch, shift, cube, cs);
     }
     return hipGetLastError();
+}
+
+hipError_t launch_forward_group(const Geometry &g, const Shade &s, const Channels &ch, float *cube, bool thin,
+                                int lanes, float shift, hipStream_t st) {
+    switch (lanes) {
+    case 2: return launch_group_t<2>(g, s, ch, cube, thin, shift, st);
+    case 4: return launch_group_t<4>(g, s, ch, cube, thin, shift, st);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 } // namespace rt

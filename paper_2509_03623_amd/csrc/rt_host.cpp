@@ -52,7 +52,7 @@ static int64_t g_opt_accum = 0;
 static int64_t g_opt_adj_cap = 0;
 static int64_t g_opt_adj_cb = 0;
 static int64_t g_opt_adj_lanes = 0;
-static int64_t g_opt_pair = 1;
+static int64_t g_opt_group = 0;
 
 // Launch shape of the forward march: channels per lane (cb) and lanes per
 // ray (nsplit).  Measured on MI355X: one channel block per pixel is best
@@ -360,22 +360,30 @@ rt_status build_launch(const rt_problem *p, Geometry *g, Shade *s, const float4 
     return RT_OK;
 }
 
-// The paired-lane march needs, in every 64-channel block, the upper 32
-// velocities to be the lower 32 plus one shift (uniform spacing gives
-// 32 dv).  True, with the shift, if the n velocities v[] allow it (to 1e-9
-// of the velocity span: the float velocities the march uses round far
-// coarser).
-static bool pair_shift(const double *v, int n, double *shift) {
-    if (n <= 32) { *shift = 0.0; return true; }
-    const double sh = v[32] - v[0];
+// The grouped-lane march with G lanes per pixel needs, in every 64-channel
+// block, the velocities of lane m's channels (c + m 64/G) to be lane 0's plus
+// m shift (uniform spacing gives shift = 64/G dv).  True, with the shift, if
+// the n velocities v[] allow it (to 1e-9 of the velocity span: the float
+// velocities the march uses round far coarser).
+static bool group_shift(const double *v, int n, int G, double *shift) {
+    const int cb = 64 / G;
+    if (n <= cb) { *shift = 0.0; return true; }
+    const double sh = v[cb] - v[0];
     double span = 0.0;
     for (int c = 0; c < n; ++c) span = std::max(span, std::fabs(v[c] - v[0]));
+    const double tol = 1e-9 * std::max(span, 1e-12);
     for (int b = 0; b < n; b += 64)
-        for (int c = b; c < std::min(b + 32, n - 32); ++c)
-            if (std::fabs(v[c + 32] - v[c] - sh) > 1e-9 * std::max(span, 1e-12)) return false;
+        for (int m = 1; m < G; ++m)
+            for (int c = b; c < b + cb && c + m * cb < n; ++c)
+                if (std::fabs(v[c + m * cb] - v[c] - m * sh) > tol) return false;
     *shift = sh;
     return true;
 }
+
+// lanes per pixel of the forward march of 64-channel blocks.  Measured on
+// MI355X (512^2 x 64 x 512, disks 2000-2005): 2 lanes (104 VGPRs, 4 waves
+// per SIMD) 3-7 % and 4 lanes (67 VGPRs, 7 waves) 16-18 % faster than one.
+static int forward_group() { return g_opt_group ? (int)g_opt_group : 4; }
 
 // Forward march of the whole cube, one launch per chunk of channels.
 rt_status march_cube(const rt_problem *p, const Geometry &g, const Shade &s, float *cube, hipStream_t stream) {
@@ -390,8 +398,9 @@ rt_status march_cube(const rt_problem *p, const Geometry &g, const Shade &s, flo
         for (int c = 0; c < ch.n; ++c) ch.v[c] = (float)p->spec.v_kms[c0 + c];
         double shift = 0.0;
         hipError_t e;
-        if (cb == 64 && nsplit == 1 && g_opt_pair && pair_shift(p->spec.v_kms + c0, ch.n, &shift))
-            e = launch_forward_pair(g, s, ch, cube + (size_t)c0 * plane, thin_series(), (float)shift, stream);
+        const int G = forward_group();
+        if (cb == 64 && nsplit == 1 && G > 1 && group_shift(p->spec.v_kms + c0, ch.n, G, &shift))
+            e = launch_forward_group(g, s, ch, cube + (size_t)c0 * plane, thin_series(), G, (float)shift, stream);
         else
             e = launch_forward(g, s, ch, cube + (size_t)c0 * plane, cb, thin_series(), nsplit, stream);
         if (e != hipSuccess) return fail_hip(e, "forward launch");
@@ -450,9 +459,10 @@ rt_status rt_set_option(int32_t key, int64_t value) {
             return fail(RT_EINVAL, "ray split must be 0, 1, 2, 4 or 8");
         g_opt_split = value;
         return RT_OK;
-    case RT_OPT_FWD_PAIR:
-        if (value != 0 && value != 1) return fail(RT_EINVAL, "paired-lane forward must be 0 or 1");
-        g_opt_pair = value;
+    case RT_OPT_FWD_GROUP:
+        if (value != 0 && value != 1 && value != 2 && value != 4)
+            return fail(RT_EINVAL, "forward lanes per pixel must be 0, 1, 2 or 4");
+        g_opt_group = value;
         return RT_OK;
     default:
         return fail(RT_EINVAL, "unknown option %d", key);
@@ -469,7 +479,7 @@ int64_t rt_get_option(int32_t key) {
     case RT_OPT_ADJ_SCRATCH_CAP: return g_opt_adj_cap;
     case RT_OPT_ADJ_CHANNEL_BLOCK: return g_opt_adj_cb;
     case RT_OPT_ADJ_PIXEL_LANES: return g_opt_adj_lanes;
-    case RT_OPT_FWD_PAIR: return g_opt_pair;
+    case RT_OPT_FWD_GROUP: return g_opt_group;
     default: return -1;
     }
 }

@@ -6,9 +6,9 @@ namespace rt {
 
 hipError_t launch_forward(const Geometry &g, const Shade &s, const Channels &ch, float *cube, int cb, bool thin,
                           int nsplit, hipStream_t st);
-// paired-lane march of 64-channel blocks whose upper 32 velocities are the
-// lower 32 plus `shift`
-hipError_t launch_forward_pair(const Geometry &g, const Shade &s, const Channels &ch, float *cube, bool thin,
-                               float shift, hipStream_t st);
+// grouped-lane march of 64-channel blocks (lanes = 2 or 4 per pixel), lane
+// h's channel velocities being lane 0's plus h `shift`
+hipError_t launch_forward_group(const Geometry &g, const Shade &s, const Channels &ch, float *cube, bool thin,
+                                int lanes, float shift, hipStream_t st);
 
 } // namespace rt
