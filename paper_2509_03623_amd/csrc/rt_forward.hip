@@ -81,13 +81,14 @@ __device__ __forceinline__ float group_lane(float x) {
 // Grouped-lane march of one 64-channel block: G adjacent lanes share one
 // pixel, lane h holding channels c0 + h CB ... c0 + h CB + CB - 1 (CB =
 // 64 / G) in registers.  Each lane shades one of every G consecutive samples
-// (lane h sample k + h) and the group passes the shadings (S, K, a, b)
-// around by DPP, so each sample is still shaded once for all 64 channels
-// while a lane carries 1/G of the state of a 64-channel lane (4 waves per
-// SIMD at G = 2, 5 at G = 4, against 3).  Lane h's velocities must be lane
-// 0's plus h `shift` (uniform channel spacing): the channel velocities stay
-// wave-uniform scalars, and lane h folds its offset into a, since
-// d_c = a - (v_c + h shift) b = (a - h shift b) - v_c b.
+// (lane h sample k + h), and the group passes the shadings (S, log2 K, a, b
+// and the thin-sample decision) around by DPP.  Each sample is still shaded
+// once for all 64 channels, while a lane carries 1/G of the state of a
+// 64-channel lane: 4 waves per SIMD at G = 2 and 7 at G = 4, against 3.
+// Lane h's velocities must be lane 0's plus h `shift` (uniform channel
+// spacing): the channel velocities stay wave-uniform scalars, and lane h
+// folds its offset into a, since d_c = a - (v_c + h shift) b = (a - h shift b)
+// - v_c b.
 template <int G, bool THIN, bool NEURAL>
 __global__ __launch_bounds__(256) void march_fwd_group(Geometry g, Shade s, Channels ch, float shift,
                                                         float *__restrict__ cube, int ch_stride) {
@@ -116,14 +117,16 @@ __global__ __launch_bounds__(256) void march_fwd_group(Geometry g, Shade s, Chan
             const float t = ((float)kk + 0.5f - half) * r.ds;
             const SampleQ own = shade_sample<NEURAL>(s, ztab, r.px, fmaf(t, r.wy, r.pmy), fmaf(t, r.wz, r.pmz), r.ds,
                                                      o_index(s, kk, pix));
+            // the owner's log2 K and thin-sample decision travel with the shading
+            const float own_lk = flog2(own.K);
+            const float own_thin = own.K < kThinK ? 1.0f : 0.0f;
             auto step = [&](auto jc) {
                 constexpr int J = decltype(jc)::value;
-                SampleQ sq;
-                sq.S = group_lane<G, J>(own.S);
-                sq.K = group_lane<G, J>(own.K);
-                sq.b = group_lane<G, J>(own.b);
-                sq.a = fmaf(-vsh, sq.b, group_lane<G, J>(own.a));
-                if (J == 0 || k + J < g.nsamp) march_sample<CB, THIN>(I, Tr, sq, vel);
+                const float S = group_lane<G, J>(own.S), lK = group_lane<G, J>(own_lk);
+                const float b = group_lane<G, J>(own.b);
+                const float a = fmaf(-vsh, b, group_lane<G, J>(own.a));
+                const bool thin = group_lane<G, J>(own_thin) != 0.0f;
+                if (J == 0 || k + J < g.nsamp) march_lk<CB, THIN>(I, Tr, S, lK, a, b, thin, vel);
             };
             step(std::integral_constant<int, 0>{});
             step(std::integral_constant<int, 1>{});

@@ -365,33 +365,37 @@ __device__ __forceinline__ void stage_ztab(const Shade &s, float4 *lds_tab) {
 __device__ __forceinline__ float om_select(float x, float att) { return x < kThinK ? om_series3(x) : 1.0f - att; }
 
 // One sample of the forward channel loop over CB channels held in registers:
-// d = a - v_c b, x = K 2^-d^2 = 2^(log2 K - d^2), I_c += Tr_c (1 - 2^-x) S,
-// Tr_c *= 2^-x, with the series form on thin samples (THIN; branch per
-// lane).  vel(c) gives channel c's velocity.
+// d = a - v_c b, x = K 2^-d^2 = 2^(lK - d^2) with lK = log2 K (K = 0 gives
+// -inf, x = 0), I_c += Tr_c (1 - 2^-x) S, Tr_c *= 2^-x, with the series form
+// when `thin` (K below kThinK; THIN; a branch per lane).  vel(c) gives
+// channel c's velocity.
 template <int CB, bool THIN, class Vel>
-__device__ __forceinline__ void march_sample(float (&I)[CB], float (&Tr)[CB], const SampleQ &sq, Vel vel) {
-    // K 2^-d^2 = 2^(log2 K - d^2): the line-centre depth enters the exponent
-    // (K = 0 gives -inf, x = 0)
-    const float lK = flog2(sq.K);
-    if (THIN && sq.K < kThinK) {
+__device__ __forceinline__ void march_lk(float (&I)[CB], float (&Tr)[CB], float S, float lK, float a, float b,
+                                         bool thin, Vel vel) {
+    if (THIN && thin) {
 #pragma unroll
         for (int c = 0; c < CB; ++c) {
-            const float d = fmaf(-vel(c), sq.b, sq.a);
+            const float d = fmaf(-vel(c), b, a);
             const float x = fexp2(fmaf(-d, d, lK));
             const float t = Tr[c] * om_series3(x);
-            I[c] = fmaf(t, sq.S, I[c]);
+            I[c] = fmaf(t, S, I[c]);
             Tr[c] -= t;
         }
     } else {
 #pragma unroll
         for (int c = 0; c < CB; ++c) {
-            const float d = fmaf(-vel(c), sq.b, sq.a);
+            const float d = fmaf(-vel(c), b, a);
             const float x = fexp2(fmaf(-d, d, lK));
             const float att = fexp2(-x);
-            I[c] = fmaf(Tr[c] * (1.0f - att), sq.S, I[c]);
+            I[c] = fmaf(Tr[c] * (1.0f - att), S, I[c]);
             Tr[c] *= att;
         }
     }
+}
+
+template <int CB, bool THIN, class Vel>
+__device__ __forceinline__ void march_sample(float (&I)[CB], float (&Tr)[CB], const SampleQ &sq, Vel vel) {
+    march_lk<CB, THIN>(I, Tr, sq.S, flog2(sq.K), sq.a, sq.b, sq.K < kThinK, vel);
 }
 
 } // namespace rt
