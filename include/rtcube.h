@@ -460,7 +460,9 @@ int32_t rt_constants(double *out, int32_t n);
  * the adjoint's reverse march (8, 16, 24, 25 or 32; 0 = automatic; 24 and 25
  * only without checkpoints, 25 only with two lanes per pixel).  RT_OPT_ADJ_PIXEL_LANES: lanes sharing one pixel in the
  * checkpoint-free reverse march, each with its own channel block, their
- * per-sample sums added across the lanes (1 or 2; 0 = automatic).
+ * per-sample sums added across the lanes (1, 2 or 4; 0 = automatic, which
+ * takes 4 lanes of 16 or 12 channels in place of a pair of 32 or 24 when
+ * the channels are uniformly spaced in those groups; 2 keeps the pair).
  * RT_OPT_RAY_SPLIT: lanes sharing one ray in the forward
  * march, each taking a consecutive sub-chord (1, 2, 4 or 8; 0 = automatic).
  * RT_OPT_GRAD_ACCUM: 0 (default) accumulates the gradients of the adjoint

@@ -19,9 +19,11 @@ hipError_t copy_float_async(const float *src, float *dst, size_t n, hipStream_t 
 hipError_t launch_adj_tape(const Geometry &g, const Shade &s, float4 *tape, float4 *rays, hipStream_t st);
 // kseg 0: the checkpoint-free march with `lanes` (1 or 2) lanes per pixel;
 // kseg > 0: the checkpointed march (one lane per pixel)
+// reverse march; lanes = 4 needs the velocities uniformly spaced in groups of
+// cb (lane g's = lane 0's + g shift)
 hipError_t launch_adj_march(int cb, int kseg, int lanes, int nsamp, int npix, int plane, const Channels &ch,
-                            const float4 *tape, const float *dl, const float *target, float *ckpt, float4 *cot,
-                            float *cube_out, hipStream_t st);
+                            float shift, const float4 *tape, const float *dl, const float *target, float *ckpt,
+                            float4 *cot, float *cube_out, hipStream_t st);
 hipError_t launch_adj_chain(const Geometry &g, const Shade &s, const float4 *rays, const float4 *cot, int nblk,
                             const GradAcc &go, float4 *dO, hipStream_t st);
 bool chain_lds_fits(int nr, int nz);

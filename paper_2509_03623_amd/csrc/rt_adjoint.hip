@@ -170,36 +170,46 @@ __global__ __launch_bounds__(256) void adj_march(int nsamp, int npix, int plane,
 // operand, so after sample k the pair holds minus the prefix depth of k to
 // within one rounding of the prefix itself.
 
-// Work items: G adjacent lanes per pixel, each with CB channels (G = 2: the
-// pair's channel sums are added across the two lanes, so one cotangent slice
-// is written per G CB channels and the pair reads each tape entry once); the
-// channel blocks of one tile take workgroup ids 8 apart, so they run on one
-// XCD at about the same time and share the tile's tape through its L2.
+// Work items: G adjacent lanes per pixel, each with CB channels (G = 2 or 4:
+// the group's channel sums are added across its lanes, so one cotangent
+// slice is written per G CB channels and the group reads each tape entry
+// once); the channel blocks of one tile take workgroup ids 8 apart, so they
+// run on one XCD at about the same time and share the tile's tape through
+// its L2.  At G = 4 the channels are uniformly spaced in groups of CB (lane
+// g's velocities are lane 0's plus g shift): the velocities stay scalars and
+// each lane folds its offset into a.
 template <int CB, int G, bool CUBE>
 __global__ __launch_bounds__(256)
-__attribute__((amdgpu_waves_per_eu(CB * G <= 8 ? 6 : CB <= 16 && G == 1 ? 4 : CB <= 24 && G == 1 ? 3 : 2)))
-void adj_march_tau(int nsamp, int npix, int plane, int nblk, Channels ch, const float4 *__restrict__ tape,
-                   const float *__restrict__ dl_dcube, const float *__restrict__ target, float4 *__restrict__ cot,
-                   float *__restrict__ cube_out) {
-    static_assert(G == 1 || G == 2, "one or two lanes per pixel");
+__attribute__((amdgpu_waves_per_eu(CB * G <= 8 ? 6 : G == 4 ? 4 : CB <= 16 && G == 1 ? 4 : CB <= 24 && G == 1 ? 3 : 2)))
+void adj_march_tau(int nsamp, int npix, int plane, int nblk, Channels ch, float shift,
+                   const float4 *__restrict__ tape, const float *__restrict__ dl_dcube,
+                   const float *__restrict__ target, float4 *__restrict__ cot, float *__restrict__ cube_out) {
+    static_assert(G == 1 || G == 2 || G == 4, "one, two or four lanes per pixel");
     const int id = blockIdx.x, r8 = id >> 3;
     const int blk = r8 % nblk;
-    const int g = G == 1 ? 0 : (int)(threadIdx.x & 1);
+    const int g = G == 1 ? 0 : (int)(threadIdx.x % G);
     const int pix = ((r8 / nblk) * 8 + (id & 7)) * (256 / G) + (int)threadIdx.x / G;
-    if (pix >= npix) return;   // both lanes of a pixel leave together
+    if (pix >= npix) return;   // the lanes of a pixel leave together
     const int c0 = (blk * G + g) * CB;
-    // channel velocities: scalar registers with one lane per pixel, vector
-    // registers when the lanes of a pixel take different channels
-    float vv[G > 1 ? CB : 1];
-    if constexpr (G > 1) {
+    if constexpr (G == 4) {
+        auto vel = [&](int c) { return ch.v[blk * G * CB + c]; };
+        march_tau_pixel<CB, G, CUBE, true>(pix, blk, g, c0, ch.n, nsamp, npix, plane, vel, tape, dl_dcube, target,
+                                           cot, cube_out, (float)g * shift);
+    } else {
+        // channel velocities: scalar registers with one lane per pixel,
+        // vector registers when the lanes of a pixel take different channels
+        float vv[G > 1 ? CB : 1];
+        if constexpr (G > 1) {
 #pragma unroll
-        for (int c = 0; c < CB; ++c) vv[c] = g ? ch.v[blk * G * CB + CB + c] : ch.v[blk * G * CB + c];
+            for (int c = 0; c < CB; ++c) vv[c] = g ? ch.v[blk * G * CB + CB + c] : ch.v[blk * G * CB + c];
+        }
+        auto vel = [&](int c) -> float {
+            if constexpr (G > 1) return vv[c];
+            else return ch.v[c0 + c];
+        };
+        march_tau_pixel<CB, G, CUBE>(pix, blk, g, c0, ch.n, nsamp, npix, plane, vel, tape, dl_dcube, target, cot,
+                                     cube_out);
     }
-    auto vel = [&](int c) -> float {
-        if constexpr (G > 1) return vv[c];
-        else return ch.v[c0 + c];
-    };
-    march_tau_pixel<CB, G, CUBE>(pix, blk, g, c0, ch.n, nsamp, npix, plane, vel, tape, dl_dcube, target, cot, cube_out);
 }
 
 
@@ -499,27 +509,28 @@ static hipError_t launch_march_t(int nsamp, int npix, int plane, const Channels 
 }
 
 template <int CB, int G, bool CUBE>
-static hipError_t launch_tau_t(int nsamp, int npix, int plane, const Channels &ch, const float4 *tape, const float *dl,
-                               const float *target, float4 *cot, float *cube_out, hipStream_t st) {
+static hipError_t launch_tau_t(int nsamp, int npix, int plane, const Channels &ch, float shift, const float4 *tape,
+                               const float *dl, const float *target, float4 *cot, float *cube_out, hipStream_t st) {
     const int nblk = (ch.n + G * CB - 1) / (G * CB);
     const long tiles = (npix + 256 / G - 1) / (256 / G);
     const long ids = (tiles + 7) / 8 * 8 * nblk;
     hipLaunchKernelGGL((adj_march_tau<CB, G, CUBE>), dim3((unsigned)ids), dim3(256), 0, st, nsamp, npix, plane, nblk,
-                       ch, tape, dl, target, cot, cube_out);
+                       ch, shift, tape, dl, target, cot, cube_out);
     return hipGetLastError();
 }
 
 hipError_t launch_adj_march(int cb, int kseg, int lanes, int nsamp, int npix, int plane, const Channels &ch,
-                            const float4 *tape, const float *dl, const float *target, float *ckpt, float4 *cot,
-                            float *cube_out, hipStream_t st) {
+                            float shift, const float4 *tape, const float *dl, const float *target, float *ckpt,
+                            float4 *cot, float *cube_out, hipStream_t st) {
     if (kseg == 0) {
         const bool cube = target || cube_out;
-#define RT_TAU_CASE(C, G)                                                                                  \
-    if (cb == C && lanes == G)                                                                            \
-        return cube ? launch_tau_t<C, G, true>(nsamp, npix, plane, ch, tape, dl, target, cot, cube_out, st) \
-                    : launch_tau_t<C, G, false>(nsamp, npix, plane, ch, tape, dl, target, cot, cube_out, st);
+#define RT_TAU_CASE(C, G)                                                                                         \
+    if (cb == C && lanes == G)                                                                                   \
+        return cube ? launch_tau_t<C, G, true>(nsamp, npix, plane, ch, shift, tape, dl, target, cot, cube_out, st) \
+                    : launch_tau_t<C, G, false>(nsamp, npix, plane, ch, shift, tape, dl, target, cot, cube_out, st);
         RT_TAU_CASE(8, 1) RT_TAU_CASE(16, 1) RT_TAU_CASE(24, 1) RT_TAU_CASE(32, 1)
         RT_TAU_CASE(16, 2) RT_TAU_CASE(24, 2) RT_TAU_CASE(25, 2) RT_TAU_CASE(32, 2)
+        RT_TAU_CASE(12, 4) RT_TAU_CASE(16, 4)
 #undef RT_TAU_CASE
         return hipErrorInvalidValue;
     }

@@ -35,17 +35,25 @@ __device__ __forceinline__ float swap_pair(float x) {
     return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0xB1, 0xF, 0xF, false));
 }
 
+// value of the lane two places over in a quad (DPP quad permutation 2,3,0,1)
+__device__ __forceinline__ float swap_half_quad(float x) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0x4E, 0xF, 0xF, false));
+}
+
 // Pass B without checkpoints for one pixel and one block of CB channels per
-// lane (G lanes per pixel; this lane is g of the pair and its channels start
-// at c0; blk is the cotangent slice of the G CB channels).  vel(c) gives the
-// velocity of this lane's channel c.  With CUBE the march forms the
-// intensity, and with target != NULL dL/dI = 2 (I - D) from it; otherwise
-// dL/dI is read from dl_dcube.
-template <int CB, int G, bool CUBE, class Vel>
+// lane (G = 1, 2 or 4 lanes per pixel; this lane is g of its group and its
+// channels start at c0; blk is the cotangent slice of the G CB channels).
+// vel(c) gives the velocity of this lane's channel c, plus vsh when SHIFT:
+// the lane then folds vsh into a (d_c = (a - vsh b) - vel(c) b) and the
+// derivative in b takes -vsh times the one in a.  With CUBE the march forms
+// the intensity, and with target != NULL dL/dI = 2 (I - D) from it;
+// otherwise dL/dI is read from dl_dcube.
+template <int CB, int G, bool CUBE, bool SHIFT = false, class Vel>
 __device__ __forceinline__ void march_tau_pixel(int pix, int blk, int g, int c0, int nch, int nsamp, int npix,
                                                 int plane, Vel vel, const float4 *__restrict__ tape,
                                                 const float *__restrict__ dl_dcube, const float *__restrict__ target,
-                                                float4 *__restrict__ cot, float *__restrict__ cube_out) {
+                                                float4 *__restrict__ cot, float *__restrict__ cube_out,
+                                                float vsh = 0.0f) {
     float th[CB], tl[CB], w[CB];
     {
         // sweep 1, back to front: total depth and (CUBE) J, which reaches I
@@ -60,8 +68,9 @@ __device__ __forceinline__ void march_tau_pixel(int pix, int blk, int g, int c0,
         float4 qn = tape[(size_t)(nsamp - 1) * npix + pix];
 #pragma unroll 1
         for (int k = nsamp - 1; k >= 0; --k) {
-            const float4 q = qn;
+            float4 q = qn;
             qn = tape[(size_t)max(k - 1, 0) * npix + pix];
+            if constexpr (SHIFT) q.z = fmaf(-vsh, q.w, q.z);
             const float lK = flog2(q.y);
             // J_k-1 = S (1 - att) + att J_k: as S - att (S - J_k), or on a thin
             // sample as J_k + (1 - att)(S - J_k) with the series of 1 - att
@@ -112,7 +121,8 @@ __device__ __forceinline__ void march_tau_pixel(int pix, int blk, int g, int c0,
     for (int k = nsamp - 1; k >= 0; --k) {
         const float4 q = qn;
         qn = tape[(size_t)max(k - 1, 0) * npix + pix];
-        const float S = q.x, a = q.z, b = q.w;
+        const float S = q.x, b = q.w;
+        const float a = SHIFT ? fmaf(-vsh, q.w, q.z) : q.z;
         const float lK = flog2(q.y);
         // channel sums in two interleaved halves (shorter dependency chains)
         float cS[2] = {0.0f, 0.0f}, cX[2] = {0.0f, 0.0f}, ca[2] = {0.0f, 0.0f}, cb[2] = {0.0f, 0.0f};
@@ -152,11 +162,18 @@ __device__ __forceinline__ void march_tau_pixel(int pix, int blk, int g, int c0,
         else channels(std::false_type{});
         const float m = -2.0f * kLn2 * kLn2;
         float4 o = make_float4(cS[0] + cS[1], (cX[0] + cX[1]) * kLn2, (ca[0] + ca[1]) * m, (cb[0] + cb[1]) * m);
-        if constexpr (G == 2) {
+        if constexpr (SHIFT) o.w = fmaf(-vsh, o.z, o.w);
+        if constexpr (G >= 2) {
             o.x += swap_pair(o.x);
             o.y += swap_pair(o.y);
             o.z += swap_pair(o.z);
             o.w += swap_pair(o.w);
+        }
+        if constexpr (G == 4) {
+            o.x += swap_half_quad(o.x);
+            o.y += swap_half_quad(o.y);
+            o.z += swap_half_quad(o.z);
+            o.w += swap_half_quad(o.w);
         }
         if (g == 0) cot[((size_t)blk * nsamp + k) * npix + pix] = o;
     }

@@ -38,6 +38,7 @@ void adjoint_shape(int nch, long npix, bool cube, int *cb, int *lanes, int *kseg
     if (ocb == 8 || ocb == 16 || ocb == 24 || ocb == 25 || ocb == 32) *cb = ocb;
     const int olanes = adjoint_lanes_option();
     if (olanes == 1 || olanes == 2) *lanes = olanes;
+    if (olanes == 4) *lanes = 2;   // a pair, made four lanes at launch when the channels allow
     if (*cb == 25) *lanes = 2;   // 25 channels per lane only as a pair
     if (*lanes == 2 && *cb == 8) {
         // no 2 x 8 form: a pair asked for explicitly widens the block,
@@ -135,6 +136,15 @@ rt_status adjoint_core(const rt_problem *p, const float *dl, const rt_grads *g, 
         ch.n = std::min(kLaunchChannels, p->spec.nch - c0);
         for (int c = 0; c < ch.n; ++c) ch.v[c] = (float)p->spec.v_kms[c0 + c];
         const int nblk = (ch.n + lanes * cb - 1) / (lanes * cb);   // cotangent slices
+        // a pair of 32- or 24-channel lanes becomes four lanes of 16 or 12
+        // (same slices) when the channels are uniformly spaced in those groups
+        int cb_l = cb, lanes_l = lanes;
+        double shift = 0.0;
+        if (kseg == 0 && lanes == 2 && (cb == 32 || cb == 24) && adjoint_lanes_option() != 2 &&
+            group_shift(p->spec.v_kms + c0, ch.n, 4, cb / 2, &shift)) {
+            cb_l = cb / 2;
+            lanes_l = 4;
+        }
         for (int q0 = 0; q0 < ny; q0 += band) {
             const int rows = std::min(band, ny - q0);
             const int bpix = rows * nx;
@@ -157,8 +167,8 @@ rt_status adjoint_core(const rt_problem *p, const float *dl, const rt_grads *g, 
             float4 *cot = (float4 *)(base + tape_b + rays_b + ckpt_b);
             if ((e = launch_adj_tape(gb, sb, tape, rays, st)) != hipSuccess) return fail_hip(e, "adjoint tape");
             const size_t off = (size_t)c0 * plane + pix0;
-            if ((e = launch_adj_march(cb, kseg, lanes, ns, bpix, (int)plane, ch, tape, dl ? dl + off : nullptr,
-                                      target ? target + off : nullptr, ckpt, cot,
+            if ((e = launch_adj_march(cb_l, kseg, lanes_l, ns, bpix, (int)plane, ch, (float)shift, tape,
+                                      dl ? dl + off : nullptr, target ? target + off : nullptr, ckpt, cot,
                                       cube_opt ? cube_opt + off : nullptr, st)) != hipSuccess)
                 return fail_hip(e, "adjoint march");
             float4 *dOc = c0 == 0 ? dO : nullptr;

@@ -360,19 +360,18 @@ rt_status build_launch(const rt_problem *p, Geometry *g, Shade *s, const float4 
     return RT_OK;
 }
 
-// The grouped-lane march with G lanes per pixel needs, in every 64-channel
-// block, the velocities of lane m's channels (c + m 64/G) to be lane 0's plus
-// m shift (uniform spacing gives shift = 64/G dv).  True, with the shift, if
-// the n velocities v[] allow it (to 1e-9 of the velocity span: the float
-// velocities the march uses round far coarser).
-static bool group_shift(const double *v, int n, int G, double *shift) {
-    const int cb = 64 / G;
+// Marches with G lanes per pixel of cb channels each need, in every block
+// of G cb channels, the velocities of lane m's channels (c + m cb) to be lane
+// 0's plus m shift (uniform spacing gives shift = cb dv).  True, with the
+// shift, if the n velocities v[] allow it (to 1e-9 of the velocity span: the
+// float velocities the kernels use round far coarser).
+bool group_shift(const double *v, int n, int G, int cb, double *shift) {
     if (n <= cb) { *shift = 0.0; return true; }
     const double sh = v[cb] - v[0];
     double span = 0.0;
     for (int c = 0; c < n; ++c) span = std::max(span, std::fabs(v[c] - v[0]));
     const double tol = 1e-9 * std::max(span, 1e-12);
-    for (int b = 0; b < n; b += 64)
+    for (int b = 0; b < n; b += G * cb)
         for (int m = 1; m < G; ++m)
             for (int c = b; c < b + cb && c + m * cb < n; ++c)
                 if (std::fabs(v[c + m * cb] - v[c] - m * sh) > tol) return false;
@@ -399,7 +398,7 @@ rt_status march_cube(const rt_problem *p, const Geometry &g, const Shade &s, flo
         double shift = 0.0;
         hipError_t e;
         const int G = forward_group();
-        if (cb == 64 && nsplit == 1 && G > 1 && group_shift(p->spec.v_kms + c0, ch.n, G, &shift))
+        if (cb == 64 && nsplit == 1 && G > 1 && group_shift(p->spec.v_kms + c0, ch.n, G, 64 / G, &shift))
             e = launch_forward_group(g, s, ch, cube + (size_t)c0 * plane, thin_series(), G, (float)shift, stream);
         else
             e = launch_forward(g, s, ch, cube + (size_t)c0 * plane, cb, thin_series(), nsplit, stream);
@@ -450,8 +449,8 @@ rt_status rt_set_option(int32_t key, int64_t value) {
         g_opt_adj_cb = value;
         return RT_OK;
     case RT_OPT_ADJ_PIXEL_LANES:
-        if (value != 0 && value != 1 && value != 2)
-            return fail(RT_EINVAL, "adjoint lanes per pixel must be 0, 1 or 2");
+        if (value != 0 && value != 1 && value != 2 && value != 4)
+            return fail(RT_EINVAL, "adjoint lanes per pixel must be 0, 1, 2 or 4");
         g_opt_adj_lanes = value;
         return RT_OK;
     case RT_OPT_RAY_SPLIT:

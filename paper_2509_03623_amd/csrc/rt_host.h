@@ -25,6 +25,9 @@ void forward_shape(int nch, long npix, int nsamp, int *cb, int *nsplit);
 // none) of the reverse march; cube: the march also forms the intensity (fused
 // L2 loss or a requested cube)
 void adjoint_shape(int nch, long npix, bool cube, int *cb, int *lanes, int *kseg);
+// velocities v[n] uniformly spaced in groups of cb within blocks of G cb
+// channels (lane m's = lane 0's + m shift)
+bool group_shift(const double *v, int n, int G, int cb, double *shift);
 bool thin_series();
 int ckpt_segment_option();
 int ray_split_option();

@@ -289,13 +289,14 @@ def test_fused_l2_adjoint_equals_render_plus_adjoint(cap):
 
 
 @pytest.mark.parametrize("cb,lanes,kseg", [(8, 1, 0), (16, 1, 0), (24, 1, 0), (32, 1, 0), (16, 2, 0), (24, 2, 0),
-                                            (25, 2, 0), (32, 2, 0), (8, 1, 2), (8, 1, 16), (16, 1, 2), (16, 1, 8), (32, 1, 2),
-                                            (32, 1, 4)])
+                                            (25, 2, 0), (32, 2, 0), (24, 4, 0), (32, 4, 0), (8, 1, 2), (8, 1, 16),
+                                            (16, 1, 2), (16, 1, 8), (32, 1, 2), (32, 1, 4)])
 def test_reverse_march_shapes(cb, lanes, kseg):
     """Every instantiated (channels per lane, lanes per pixel, samples per
     checkpoint segment; 0 = the checkpoint-free march) of the reverse march
     against the oracle's gradient (37 channels: ragged blocks; 61 samples:
-    ragged segments)."""
+    ragged segments).  Lanes 4 with block 24 or 32 is the pair made four
+    lanes of 12 or 16 channels (uniformly spaced channels)."""
     rt = _rt()
     from paper_2509_03623_amd import _lib as L
     prob = kscale(synth.small_problem(nx=19, ny=17, nch=37, nsamp=61, nr=40, nz=20, seed=21, dv=0.1))
