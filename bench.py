@@ -59,10 +59,10 @@ SHADE3_SLOTS = 307 + 4 * 16
 # was taken on: the hash of those files is checked at run time.
 FWD_TRAFFIC = {"sources": ("paper_2509_03623_amd/csrc/rt_forward.hip", "paper_2509_03623_amd/csrc/rt_kernels.h",
                            "paper_2509_03623_amd/csrc/rt_launch.h"),
-               "sha256": "3e3f2980a20aa4d3cc8c705b42cbcf4e58c43f7ce82d05c4ae98c8305e34bb4d",
-               "fetch_scale": 1048576 / 524304.5, "write_scale": 1.0,
+               "sha256": "f3b9cbc5dae572afd12397a5e7b323944f13fe9b94cc9193eddf1e71e80161ae",
+               "fetch_scale": 1048576 / 524304.7, "write_scale": 1.0,
                # seed -> (FETCH_SIZE KiB, WRITE_SIZE KiB), mean of three launches each
-               "disks": {2000: (1053.4, 65536.0), 2001: (1164.4, 65536.0), 2002: (1018.8, 65536.0), 2003: (1008.5, 65536.0), 2004: (1068.1, 65536.0), 2005: (1084.2, 65536.0), 2006: (1123.4, 65536.0), 2007: (1145.3, 65536.0)}}
+               "disks": {2000: (1089.4, 65536.0), 2001: (1265.2, 65536.0), 2002: (1251.1, 65536.0), 2003: (1213.1, 65536.0), 2004: (1227.3, 65536.0), 2005: (1182.1, 65536.0), 2006: (1179.4, 65536.0), 2007: (1198.4, 65536.0)}}
 
 
 def measured_traffic(seed: int):
@@ -768,6 +768,10 @@ def bench_serving(rt, synth, dev, seconds, rate=200.0, seed=5, pool=16, saturate
         torch.cuda.synchronize()
 
     def served_run(order, arrivals):
+        # buffers the previous run left in torch's cache go back to the device,
+        # so the server's own allocations meet the memory its budget assumes
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
         with rt.Server(hbm_budget_bytes=96 << 30, max_slots=64, streams=4) as sv:
             sv.wait(submit(sv, order[0]))
             t0 = time.perf_counter()
@@ -779,6 +783,9 @@ def bench_serving(rt, synth, dev, seconds, rate=200.0, seed=5, pool=16, saturate
             infos = [sv.wait(t, timeout_s=300) for t in tickets]
             for t in tickets:
                 sv.release(t)
+        for t, x in zip(tickets, infos):
+            if x["state"] != "done":
+                log(f"request {t} ended {x['state']} (status {x['status']})")
         t_sub = np.array([x["t_submit_ns"] for x in infos], dtype=np.float64)
         t_done = np.array([x["t_done_ns"] for x in infos], dtype=np.float64)
         return (t_done - t_sub) * 1e-6, (t_done.max() - t_sub.min()) * 1e-9, sum(x["state"] != "done" for x in infos)

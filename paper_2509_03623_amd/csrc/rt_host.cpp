@@ -218,6 +218,9 @@ void *stream_workspace(hipStream_t st, int slot, size_t bytes, hipError_t *err) 
         b.bytes = 0;
     }
     if ((*err = hipMallocAsync(&b.p, want, st)) != hipSuccess) {
+        // the error goes back to the caller; it must not linger as this
+        // thread's last error and fail a later launch check
+        (void)hipGetLastError();
         b.p = nullptr;
         return nullptr;
     }

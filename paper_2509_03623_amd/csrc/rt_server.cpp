@@ -20,10 +20,14 @@
 // own request (each ray is marched by one lane with the same code whatever
 // else is in the batch); a gradient request's routing depends only on its
 // own shape, and its result on the rest of its batch only through the order
-// of the FP64 atomic additions.  Device memory: the budget covers the
-// footprints of admitted requests plus the library scratch that idle streams
-// keep for their next launch (reusing it saves a fresh mapping per launch);
-// when a request does not fit, the idle streams' scratch is released first.
+// of the accumulators' atomic additions.  Device memory: the budget covers
+// the footprints of admitted requests plus the library scratch that idle
+// streams keep for their next launch (reusing it saves a fresh mapping per
+// launch); when a request does not fit, the idle streams' scratch is released
+// first.  A launch whose scratch allocation fails while other launches run
+// (memory held outside the server's account) puts its batch back at the head
+// of the admitted queue and starts nothing until a running launch ends; the
+// idle streams then give their scratch back before the next start.
 #include <hip/hip_runtime.h>
 
 #include <chrono>
@@ -96,6 +100,8 @@ struct rt_server {
     std::deque<Req *> pending, admitted;
     uint64_t budget_used = 0;      // footprints of admitted requests, plus scratch held by running launches
     uint64_t retained_idle = 0;    // scratch held by idle streams
+    bool hold = false;             // a launch ran out of device memory: start nothing until a lane retires
+    bool squeeze = false;          // ... and then release the idle streams' scratch before the next start
     int slots_used = 0;
     std::vector<Lane> lanes;
 };
@@ -346,6 +352,7 @@ void scheduler(rt_server *sv) {
             lane_retired(sv, L);
             L.reqs.clear();
             L.busy = false;
+            sv->hold = false;
             progress = true;
         }
         // 2. admission in arrival order, by footprint and slots
@@ -372,8 +379,20 @@ void scheduler(rt_server *sv) {
             progress = true;
         }
         // 3. start admitted work on idle streams
+        if (sv->squeeze && !sv->hold) {
+            // (the frees complete before the next allocation, so the memory
+            // pool can hand their blocks to any stream)
+            for (Lane &L : sv->lanes) {
+                if (L.busy || L.retained == 0) continue;
+                release_stream_workspaces(L.st);
+                (void)hipStreamSynchronize(L.st);
+                sv->retained_idle -= L.retained;
+                L.retained = 0;
+            }
+            sv->squeeze = false;
+        }
         for (Lane &L : sv->lanes) {
-            if (L.busy || sv->admitted.empty()) continue;
+            if (L.busy || sv->admitted.empty() || sv->hold) continue;
             std::vector<Req *> batch;
             if (sv->admitted.front()->own_stream) {
                 batch.push_back(sv->admitted.front());
@@ -405,10 +424,22 @@ void scheduler(rt_server *sv) {
             if (rs == RT_OK) e = hipEventRecord(L.ev, L.st);
             lk.lock();
             if (rs != RT_OK || e != hipSuccess) {
-                // the stream may hold partial work: wait for it, then fail the requests
+                // the stream may hold partial work: wait for it and give its scratch back
                 (void)hipStreamSynchronize(L.st);
                 release_stream_workspaces(L.st);
-                for (Req *r : batch) finish(sv, r, rs != RT_OK ? rs : RT_EDEVICE);
+                bool running = false;
+                for (const Lane &O : sv->lanes) running = running || O.busy;
+                if (rs == RT_ENOMEM && running) {
+                    // device memory is short of what the budget assumed (memory
+                    // held outside the server): the batch goes back to the head
+                    // of the admitted queue, still charged, and waits for a
+                    // running launch to end and return its memory
+                    for (auto it = batch.rbegin(); it != batch.rend(); ++it) sv->admitted.push_front(*it);
+                    sv->hold = true;
+                    sv->squeeze = true;
+                } else {
+                    for (Req *r : batch) finish(sv, r, rs != RT_OK ? rs : RT_EDEVICE);
+                }
                 lane_retired(sv, L);
                 continue;
             }

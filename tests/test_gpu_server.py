@@ -390,6 +390,49 @@ def _alone_and_mixed(rt, sc, tgt):
     return alone, mixed, grads_a, grads_b, cube_a, cube_b
 
 
+def test_gradient_requests_wait_out_a_memory_squeeze():
+    """Device memory held outside the server (a tensor of the caller's)
+    leaves room for one full-size gradient request's scratch but not two:
+    the second request's launch fails to allocate while the first runs, goes
+    back to the admitted queue, and starts once the first has ended and the
+    idle stream's scratch has been released.  Both finish, with the direct
+    fused call's cube, loss and gradients (to the alone-vs-mix bars)."""
+    rt = _rt()
+    _, sc, tgt = grad_scene(512, 64, 512, 2300)
+    need = 16400 * 512 * 512          # tape, rays, cotangents of the fused adjoint per request
+    subs = []
+    outs = [(empty_cube(sc), {k: torch.full_like(getattr(sc, k), float("nan")) for k in GKEYS}) for _ in range(2)]
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    free, _ = torch.cuda.mem_get_info()
+    room = int(1.5 * need)
+    if free <= room + (1 << 30):
+        pytest.skip("device has too little free memory for the squeeze")
+    try:
+        blocker = torch.empty(free - room, dtype=torch.uint8, device="cuda")
+    except RuntimeError:
+        pytest.skip("could not hold the device memory for the squeeze")
+    print(f"[gpu] server under a memory squeeze: {room / 1e9:.1f} GB left", flush=True)
+    try:
+        with rt.Server(hbm_budget_bytes=64 << 30, max_slots=8, streams=2) as sv:
+            for cube, g in outs:
+                subs.append(sv.submit(sc, cube, target=tgt, grads=g))
+            infos = [sv.wait(t, timeout_s=120) for t in subs]
+        torch.cuda.synchronize()
+    finally:
+        del blocker
+        torch.cuda.empty_cache()
+    for info in infos:
+        assert info["state"] == "done", info
+    dc, dl, dg = rt.render_l2_adjoint(sc, tgt, want=GKEYS)
+    torch.cuda.synchronize()
+    for (cube, g), info in zip(outs, infos):
+        assert float((cube - dc).abs().max()) <= 1e-6 * float(dc.abs().max())
+        assert info["loss"] == pytest.approx(float(dl.item()), rel=1e-6)
+        for k in GKEYS:
+            assert float((g[k] - dg[k]).abs().max()) <= 1e-5 * float(dg[k].abs().max()), k
+
+
 def test_device_memory_stays_within_budget():
     """Gradient requests that each fill the device (their own streams),
     through four streams with a budget that admits two at a time: the device
