@@ -88,9 +88,11 @@ def with_options(opts, fn):
             rt.set_option(k, v)
 
 
-def test_512_samples_64_channels_thick_rays():
+@pytest.mark.parametrize("lanes", [2, 4])
+def test_512_samples_64_channels_thick_rays(lanes):
     """Small image of the full-size disk family: 64 channels, 512 samples,
-    (32 channels, 2 lanes) forced; fused L2 adjoint and explicit cotangent."""
+    32 channels on 2 lanes per pixel or 16 on 4 (the default at full size)
+    forced; fused L2 adjoint and explicit cotangent."""
     rt = _rt()
     from paper_2509_03623_amd import _lib as L
     prob = ta.kscale(synth.config2(2000, nx=24, ny=20, nch=64, nsamp=512, nr=96, nz=48))
@@ -105,10 +107,10 @@ def test_512_samples_64_channels_thick_rays():
     assert max(taus) >= 1e3
     target = ta.target_for(prob)
     _, oref = torch_ref.loss_and_grad(prob, target)
-    opts = {L.RT_OPT_ADJ_CHANNEL_BLOCK: 32, L.RT_OPT_ADJ_PIXEL_LANES: 2}
+    opts = {L.RT_OPT_ADJ_CHANNEL_BLOCK: 32, L.RT_OPT_ADJ_PIXEL_LANES: lanes}
     sc = rt.scene_from_problem(prob)
     tgt = torch.as_tensor(target, dtype=torch.float32, device="cuda")
-    print("[gpu] fused L2 adjoint 24x20x64 ns=512 as (32, 2)", flush=True)
+    print(f"[gpu] fused L2 adjoint 24x20x64 ns=512 on {lanes} lanes", flush=True)
     cube, loss, g = with_options(opts, lambda: rt.render_l2_adjoint(sc, tgt, want=GRID_BLOCKS))
     torch.cuda.synchronize()
     got_cube = cube.cpu().numpy().astype(np.float64)
@@ -126,9 +128,10 @@ def test_512_samples_64_channels_thick_rays():
 @pytest.mark.slow
 def test_full_size_adjoint_sampled_pixels():
     """512 x 512 x 64 x 512 on the 256 x 128 grid (disk 2000), the reverse
-    march in the benchmark's (32 channels, 2 lanes) form with the intensity
-    formed in the march: every gradient block against the oracle's autograd
-    over the 96 pixels carrying the cotangent, and 8 central differences."""
+    march in the benchmark's launch form (the library's default: four lanes
+    of 16 channels per pixel) with the intensity formed in the march: every
+    gradient block against the oracle's autograd over the 96 pixels carrying
+    the cotangent, and 8 central differences."""
     rt = _rt()
     from paper_2509_03623_amd import _lib as L
     prob = ta.kscale(synth.config2(2000))
@@ -142,9 +145,9 @@ def test_full_size_adjoint_sampled_pixels():
     dl[:, py, px] = w.T
     dl_t = torch.as_tensor(dl, device="cuda")
     cube2 = torch.empty_like(cube)
-    opts = {L.RT_OPT_ADJ_CHANNEL_BLOCK: 32, L.RT_OPT_ADJ_PIXEL_LANES: 2}
     print(f"[gpu] full-size adjoint, cotangent on {len(px)} pixels", flush=True)
-    g = with_options(opts, lambda: rt.render_adjoint(sc, dl_t, want=GRID_BLOCKS, cube_out=cube2))
+    assert rt.get_option(L.RT_OPT_ADJ_PIXEL_LANES) == 0 and rt.get_option(L.RT_OPT_ADJ_CHANNEL_BLOCK) == 0
+    g = rt.render_adjoint(sc, dl_t, want=GRID_BLOCKS, cube_out=cube2)
     torch.cuda.synchronize()
     assert float((cube2 - cube).abs().max()) <= 1e-6 * float(cube.abs().max())
     got = {k: v.cpu().numpy().astype(np.float64) for k, v in g.items()}
