@@ -386,7 +386,9 @@ __global__ __launch_bounds__(NT) void mlp_fwd_rr(Geometry g, Shade s, MlpDev w, 
 // mlp_bwd_rr: one workgroup of four waves per CU, each wave with the full
 // register file of its SIMD.  A wave takes 16 points per pass (the workgroup
 // 64): it recomputes the forward with the transposed product (weights read
-// as A operands from L2), keeping z' of every layer in registers as BF16;
+// as A operands from LDS, where the workgroup stages each layer's weights
+// from L2 just before the layer: one copy per pass for the four waves, its
+// loads all in flight at once), keeping z' of every layer as BF16;
 // walks back through the layers (dL/dh' of the layer below by the product
 // with the transposed weights, the SiLU derivative recomputed from z'); and
 // for the weight gradient, which sums over points, writes dL/dz' and h' of
@@ -477,6 +479,22 @@ __device__ __forceinline__ float br_rowsum(const __bf16 *X, int r, int half) {
     return sum + __shfl_xor(sum, 1);
 }
 
+// copy n bf16 elements (a multiple of 8) of one layer's prepared weights
+// from global memory into the workgroup's staging buffer (256 lanes): global
+// loads that write LDS directly (16 B per lane, lane i of a wave to the
+// wave's base + 16 i), so the copy holds no registers; every load is waited
+// for before the caller's barrier
+__device__ __forceinline__ void br_stage(__bf16 *dst, const gbf16 *src, int n, int tid) {
+    typedef __attribute__((address_space(3))) void lds_void;
+    typedef const __attribute__((address_space(1))) void g_void;
+    const int nchunk = n / 8, wv = tid >> 6, lane = tid & 63;
+    for (int c0 = 64 * wv; c0 < nchunk; c0 += 256) {
+        const int c = c0 + lane;
+        if (c < nchunk) __builtin_amdgcn_global_load_lds((g_void *)(src + 8 * c), (lds_void *)(dst + 8 * c0), 16, 0, 0);
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+}
+
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void mlp_bwd_rr(
     Geometry g, Shade s, MlpDev w, size_t M, const float4 *__restrict__ dO, float *__restrict__ dW) {
     typedef MM<__bf16> mm;
@@ -487,6 +505,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     // lane-private parking of z' (4 layers x 4 operand packs) and the two
     // feature packs between the forward and the backward of a pass
     __shared__ bf16x8 ZP[18][256];
+    // one layer's weights (forward) or transposed weights (backward)
+    __shared__ __attribute__((aligned(16))) __bf16 SW[kW * kRrRow];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int lg = lane >> 4, lc = lane & 15;
     for (int i = tid; i < 4 * kW; i += 256) sB[i] = kLog2E * w.b[i / kW][i % kW];
@@ -528,7 +548,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
         for (int l = 0; l < 4; ++l) {
             const int nk = l == 0 ? kF / 32 : kW / 32;
             const int row = l == 0 ? kRrRow0 : kRrRow;
-            const gbf16 *Wl = Wr + (l == 0 ? 0 : (size_t)kW * kRrRow0 + (size_t)(l - 1) * kW * kRrRow);
+            // (layer 0 follows the end-of-pass barrier, so SW is free)
+            if (l > 0) __syncthreads();
+            br_stage(SW, Wr + (l == 0 ? 0 : (size_t)kW * kRrRow0 + (size_t)(l - 1) * kW * kRrRow), kW * row, tid);
+            __syncthreads();
+            const __bf16 *Wl = SW;
             bf16x8 hout[4];
 #pragma unroll
             for (int cp = 0; cp < 4; ++cp) {
@@ -540,7 +564,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
                     if (c >= nk) break;
 #pragma unroll
                     for (int h = 0; h < 2; ++h) {
-                        const bf16x8 a = *(const gbf16x8 *)(Wl + (size_t)(32 * cp + 16 * h + lc) * row + 32 * c + 8 * lg);
+                        const bf16x8 a = *(const bf16x8 *)(Wl + (32 * cp + 16 * h + lc) * row + 32 * c + 8 * lg);
                         acc[h] = mm::mfma(a, hin[c], acc[h]);
                     }
                 }
@@ -554,6 +578,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
                         if (l < 3) hout[cp][4 * h + i] = (__bf16)(z * frcp(1.0f + fexp2(-z)));
                     }
                 ZP[4 * l + cp][tid] = zq;
+                // keep the next pair's weight reads after this pair's work
+                // (hoisting them all would spill)
+                __builtin_amdgcn_sched_barrier(0);
             }
             if (l < 3) {
 #pragma unroll
@@ -625,7 +652,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
             // dL/dh' of the layer below through the transposed weights, and
             // at once its h' and dL/dz'
             if (l >= 1) {
-                const gbf16 *WT = WrT + (size_t)(l - 1) * kW * kRrRow;
+                // (the barrier above follows every wave's last use of SW)
+                br_stage(SW, WrT + (size_t)(l - 1) * kW * kRrRow, kW * kRrRow, tid);
+                __syncthreads();
+                const __bf16 *WT = SW;
 #pragma unroll
                 for (int cp = 0; cp < 4; ++cp) {
                         floatx4 acc[2] = {floatx4{0.0f, 0.0f, 0.0f, 0.0f}, floatx4{0.0f, 0.0f, 0.0f, 0.0f}};
@@ -633,7 +663,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
                     for (int c = 0; c < 4; ++c)
 #pragma unroll
                         for (int h = 0; h < 2; ++h) {
-                            const bf16x8 a = *(const gbf16x8 *)(WT + (size_t)(32 * cp + 16 * h + lc) * kRrRow + 32 * c + 8 * lg);
+                            const bf16x8 a = *(const bf16x8 *)(WT + (32 * cp + 16 * h + lc) * kRrRow + 32 * c + 8 * lg);
                             acc[h] = mm::mfma(a, dzu[c], acc[h]);
                         }
                     const bf16x8 zq = ZP[4 * (l - 1) + cp][tid];
@@ -641,6 +671,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
                     for (int h = 0; h < 2; ++h)
 #pragma unroll
                         for (int i = 0; i < 4; ++i) br_act_grad(zq[4 * h + i], acc[h][i], hp[cp], dz[cp], 4 * h + i);
+                    __builtin_amdgcn_sched_barrier(0);
                 }
             }
         }
