@@ -166,6 +166,14 @@ constexpr double kZT0 = 0.1, kZT1 = 1.0e4;
 // The adjoint and network scratch (up to tens of GB) comes from the
 // device's default stream-ordered pool; keep freed blocks in the pool rather
 // than unmapping them at every synchronisation, so repeated calls reuse them.
+void trim_memory_pool() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return;
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) (void)hipMemPoolTrimTo(pool, 0);
+    (void)hipGetLastError();
+}
+
 static void keep_pool(int dev) {
     static std::mutex mu;
     static std::map<int, bool> done;

@@ -44,6 +44,8 @@ void *stream_workspace(hipStream_t st, int slot, size_t bytes, hipError_t *err);
 // bytes a workspace of `bytes` actually holds (the growth step rounds up)
 size_t workspace_round(size_t bytes);
 void release_stream_workspaces(hipStream_t st);
+// return the current device's memory-pool blocks that nothing holds to the device
+void trim_memory_pool();
 // bytes the stream's workspaces hold
 size_t stream_workspace_bytes(hipStream_t st);
 constexpr int kWsAdjoint = 0, kWsGradAcc = 1, kWsChain = 2, kWsNeuralT = 3, kWsBeam = 4, kWsBeamCube = 5,

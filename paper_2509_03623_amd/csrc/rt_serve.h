@@ -29,12 +29,16 @@ hipError_t launch_serve_fwd(const ServeDesc *descs, int nreq, uint32_t nitems, u
                             hipStream_t st);
 
 // Batched gradient requests (forward + L2 loss + adjoint of grid fields):
-// the reverse march runs kGradCB channels per lane, two lanes per pixel, so a
-// cotangent slice covers 2 kGradCB channels; tape items split each tile's
-// samples into kGradTapeChunks chunks; chain items are (field pass, chunk of
-// about kGradChainChunk pixel-samples) of one request, accumulated by a
-// 1024-lane workgroup in LDS and flushed once.
-constexpr int kGradCB = 16;
+// the reverse march runs kGradLanes lanes per pixel of kGradLaneCB channels
+// each, so a cotangent slice covers kGradSlice channels (the requests'
+// channels uniformly spaced in groups of kGradLaneCB: lane g's velocities are
+// lane 0's plus g vshift); tape items split each tile's samples into
+// kGradTapeChunks chunks; chain items are (field pass, chunk of about
+// kGradChainChunk pixel-samples) of one request, accumulated by a 1024-lane
+// workgroup in LDS and flushed once.
+constexpr int kGradSlice = 32;
+constexpr int kGradLanes = 4;
+constexpr int kGradLaneCB = kGradSlice / kGradLanes;
 constexpr int kGradTapeChunks = 4;
 constexpr int kGradChainThreads = 1024;
 constexpr long kGradChainChunk = 64L * kGradChainThreads;
@@ -42,7 +46,7 @@ constexpr long kGradChainChunk = 64L * kGradChainThreads;
 struct GradDesc {
     Geometry g;
     Shade s;
-    const float *vch;          // channel velocities, padded to a multiple of 2 kGradCB
+    const float *vch;          // channel velocities, padded to a multiple of kGradSlice
     const float *target;       // [nch][ny][nx]
     float *cube;               // [nch][ny][nx] (written by the reverse march)
     float4 *tape, *rays, *cot; // scratch: [nsamp][npix], [npix], [nblk][nsamp][npix]
@@ -50,7 +54,8 @@ struct GradDesc {
                                // double; float ones, the default, use the head of it)
     float *out[5];             // caller's gradient outputs in the same order (NULL: not requested)
     double *loss;              // L of this request
-    int32_t nch, nblk;         // channels, cotangent slices (of 2 kGradCB channels)
+    int32_t nch, nblk;         // channels, cotangent slices (of kGradSlice channels)
+    float vshift;              // velocity offset between adjacent lanes of a pixel (kGradLaneCB dv)
     uint32_t item0[3];         // first item of this request in the tape, march and chain passes
     int32_t nfp;               // chain field passes (>= 1; the first also takes the surfaces)
     int32_t fields[3];         // field of each pass: 0 ln n, 1 T, 2 v_phi, 3 none (surfaces only)

@@ -23,20 +23,20 @@
 
 namespace rt {
 
-static_assert(kGradCB == 16, "the batched reverse march is instantiated for 16 channels per lane");
+static_assert(kGradLanes == 4 && kGradLaneCB == 8, "the batched reverse march is instantiated for 4 x 8 channels");
 
 static size_t al256(size_t b) { return (b + 255) / 256 * 256; }
 
 size_t grad_batch_scratch_bytes(int nch, long npix, int nsamp, long nr, long nz) {
-    const size_t nblk = (size_t)(nch + 2 * kGradCB - 1) / (2 * kGradCB);
+    const size_t nblk = (size_t)(nch + kGradSlice - 1) / kGradSlice;
     return al256(sizeof(float4) * (size_t)nsamp * npix) + al256(sizeof(float4) * (size_t)npix) +
            al256(sizeof(float4) * nblk * nsamp * npix) + al256(sizeof(double) * (size_t)(3 * nr * nz + 2 * nr));
 }
 
 void grad_batch_items(int nch, long npix, int nsamp, int nfp, uint32_t items[3], uint32_t *chunks) {
-    const long nblk = (nch + 2 * kGradCB - 1) / (2 * kGradCB);
+    const long nblk = (nch + kGradSlice - 1) / kGradSlice;
     items[0] = (uint32_t)(((npix + 255) / 256) * kGradTapeChunks);
-    items[1] = (uint32_t)(((npix + 127) / 128) * nblk);
+    items[1] = (uint32_t)(((npix + 256 / kGradLanes - 1) / (256 / kGradLanes)) * nblk);
     *chunks = (uint32_t)std::max<size_t>(1, ((size_t)nsamp * npix + kGradChainChunk - 1) / kGradChainChunk);
     items[2] = (uint32_t)nfp * *chunks;
 }
@@ -122,7 +122,7 @@ __global__ __launch_bounds__(256) void grad_tape(const GradDesc *__restrict__ de
 
 // (two waves per SIMD: held to three, the item loop's state spills)
 __global__ __launch_bounds__(256) void grad_march(const GradDesc *__restrict__ descs, int nreq, uint32_t nitems, uint32_t *__restrict__ counter) {
-    constexpr int CB = kGradCB;
+    constexpr int CB = kGradLaneCB, G = kGradLanes, PX = 256 / kGradLanes;
     __shared__ uint32_t s_item;
     for (;;) {
         const uint32_t item = next_item(counter, &s_item);
@@ -134,17 +134,18 @@ __global__ __launch_bounds__(256) void grad_march(const GradDesc *__restrict__ d
         const int npix = __builtin_amdgcn_readfirstlane(D->g.nx * D->g.ny);
         const int nsamp = __builtin_amdgcn_readfirstlane(D->g.nsamp);
         const int nch = __builtin_amdgcn_readfirstlane(D->nch);
-        const int g = (int)(threadIdx.x & 1);
-        const int pix = tile * 128 + (int)threadIdx.x / 2;
-        const int c0 = (blk * 2 + g) * CB;
-        if (pix < npix) {   // both lanes of a pixel take the branch together
-            const float *vch = uniform_ptr(D->vch);
-            float vv[CB];
-#pragma unroll
-            for (int c = 0; c < CB; ++c) vv[c] = vch[c0 + c];
-            auto vel = [&](int c) -> float { return vv[c]; };
-            march_tau_pixel<CB, 2, true>(pix, blk, g, c0, nch, nsamp, npix, npix, vel, uniform_ptr(D->tape), nullptr,
-                                         uniform_ptr(D->target), uniform_ptr(D->cot), uniform_ptr(D->cube));
+        const float vshift = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(D->vshift)));
+        const int g = (int)(threadIdx.x % G);
+        const int pix = tile * PX + (int)threadIdx.x / G;
+        const int c0 = (blk * G + g) * CB;
+        if (pix < npix) {   // the lanes of a pixel take the branch together
+            // lane 0's velocities of the slice (wave-uniform), lane g's offset
+            // folded into a by the march
+            const float *vch = uniform_ptr(D->vch) + blk * kGradSlice;
+            auto vel = [&](int c) -> float { return vch[c]; };
+            march_tau_pixel<CB, G, true, true>(pix, blk, g, c0, nch, nsamp, npix, npix, vel, uniform_ptr(D->tape),
+                                               nullptr, uniform_ptr(D->target), uniform_ptr(D->cot),
+                                               uniform_ptr(D->cube), (float)g * vshift);
         }
     }
 }

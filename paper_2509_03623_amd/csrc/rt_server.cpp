@@ -27,7 +27,9 @@
 // first.  A launch whose scratch allocation fails while other launches run
 // (memory held outside the server's account) puts its batch back at the head
 // of the admitted queue and starts nothing until a running launch ends; the
-// idle streams then give their scratch back before the next start.
+// idle streams then give their scratch back before the next start.  With
+// nothing running, the memory pool is trimmed back to the device and the
+// batch tries once more before it fails.
 #include <hip/hip_runtime.h>
 
 #include <chrono>
@@ -66,6 +68,7 @@ struct Req {
     uint64_t footprint = 0, ray_samples = 0;
     bool own_stream = false;   // large or neural request
     bool grad_batch = false;   // small gradient request (batched launches)
+    bool trimmed = false;      // retried once after the memory pool was trimmed
 };
 
 struct Lane {
@@ -231,7 +234,7 @@ rt_status launch_batch(rt_server *sv, Lane &L, std::vector<Req *> &batch) {
 
 // one batched sequence of gradient launches over every request of the batch
 rt_status launch_grad(rt_server *sv, Lane &L, std::vector<Req *> &batch) {
-    constexpr int kPad = 2 * kGradCB;
+    constexpr int kPad = kGradSlice;
     size_t nv = 0, scratch = 0;
     for (Req *r : batch) {
         const rt_problem &p = r->rq.problem;
@@ -260,6 +263,9 @@ rt_status launch_grad(rt_server *sv, Lane &L, std::vector<Req *> &batch) {
         const size_t npix = (size_t)p.cam.nx * p.cam.ny, ns = p.nsamp;
         D.nch = nch;
         D.nblk = padded / kPad;
+        double shift = 0.0;
+        (void)group_shift(p.spec.v_kms, nch, kGradLanes, kGradLaneCB, &shift);   // checked at submission
+        D.vshift = (float)shift;
         D.target = q.target;
         D.cube = q.cube;
         D.tape = (float4 *)base;
@@ -427,8 +433,9 @@ void scheduler(rt_server *sv) {
                 // the stream may hold partial work: wait for it and give its scratch back
                 (void)hipStreamSynchronize(L.st);
                 release_stream_workspaces(L.st);
-                bool running = false;
+                bool running = false, trimmed = false;
                 for (const Lane &O : sv->lanes) running = running || O.busy;
+                for (const Req *r : batch) trimmed = trimmed || r->trimmed;
                 if (rs == RT_ENOMEM && running) {
                     // device memory is short of what the budget assumed (memory
                     // held outside the server): the batch goes back to the head
@@ -437,6 +444,21 @@ void scheduler(rt_server *sv) {
                     for (auto it = batch.rbegin(); it != batch.rend(); ++it) sv->admitted.push_front(*it);
                     sv->hold = true;
                     sv->squeeze = true;
+                } else if (rs == RT_ENOMEM && !trimmed) {
+                    // nothing left to wait for: the idle streams' scratch and
+                    // the memory pool's free blocks (which another stream may
+                    // not be allowed to reuse) go back to the device, and the
+                    // batch tries once more
+                    for (Lane &O : sv->lanes) {
+                        if (O.retained == 0) continue;
+                        release_stream_workspaces(O.st);
+                        (void)hipStreamSynchronize(O.st);
+                        sv->retained_idle -= O.retained;
+                        O.retained = 0;
+                    }
+                    trim_memory_pool();
+                    for (Req *r : batch) r->trimmed = true;
+                    for (auto it = batch.rbegin(); it != batch.rend(); ++it) sv->admitted.push_front(*it);
                 } else {
                     for (Req *r : batch) finish(sv, r, rs != RT_OK ? rs : RT_EDEVICE);
                 }
@@ -538,15 +560,20 @@ rt_status rt_submit(rt_server *sv, const rt_request *rq, uint64_t *ticket) {
     // 16-channel block) against the lanes the launch keeps resident
     const uint64_t device_lanes = (uint64_t)sv->ncu * kServeWorkgroupsPerCU * 256;
     const uint64_t serve_lanes = (uint64_t)p.cam.nx * p.cam.ny * ((p.spec.nch + 15) / 16) * kServeSplit;
-    // lanes of a gradient request in the batched reverse march: two per
-    // pixel and slice of 2 kGradCB channels.  Measured per request (eight of
-    // one shape, batched vs the fused single-request path, ms): 64^2 x 16 x
-    // 256 0.41 vs 0.54, 64^2 x 64 x 512 0.59 vs 1.03, 128^2 x 32 x 256 0.52 vs
-    // 0.67, but 128^2 x 128 x 384 1.53 vs 1.35 and 256^2 x 16 x 256 1.31 vs
-    // 1.00: requests under a quarter of the device's resident lanes batch.
-    const uint64_t grad_lanes = (uint64_t)p.cam.nx * p.cam.ny * ((p.spec.nch + 2 * kGradCB - 1) / (2 * kGradCB)) * 2;
+    // size of a gradient request in the batched reverse march, counted as two
+    // lanes per pixel and 32-channel slice.  Measured per request with the
+    // pair form of the march (eight of one shape, batched vs the fused
+    // single-request path, ms): 64^2 x 16 x 256 0.41 vs 0.54, 64^2 x 64 x 512
+    // 0.59 vs 1.03, 128^2 x 32 x 256 0.52 vs 0.67, but 128^2 x 128 x 384 1.53
+    // vs 1.35 and 256^2 x 16 x 256 1.31 vs 1.00: requests under a quarter of
+    // the device's resident lanes batch.  The batched march needs its
+    // channels uniformly spaced in groups of kGradLaneCB; other requests run
+    // on their own stream.
+    const uint64_t grad_lanes = (uint64_t)p.cam.nx * p.cam.ny * ((p.spec.nch + kGradSlice - 1) / kGradSlice) * 2;
+    double gshift = 0.0;
     if (rq->kind == RT_REQ_FWD_ADJ) {
-        r->grad_batch = p.mlp == nullptr && grad_lanes < device_lanes / 4 && grad_batch_grid_fits(p.grid.nr, p.grid.nz);
+        r->grad_batch = p.mlp == nullptr && grad_lanes < device_lanes / 4 && grad_batch_grid_fits(p.grid.nr, p.grid.nz) &&
+                        group_shift(p.spec.v_kms, p.spec.nch, kGradLanes, kGradLaneCB, &gshift);
         r->own_stream = !r->grad_batch;
     } else {
         r->own_stream = p.mlp != nullptr || serve_lanes >= device_lanes;

@@ -304,11 +304,17 @@ def submit_grad(sv, sc, target):
 
 def test_batched_gradient_requests_match_direct():
     """Small gradient requests of uneven sizes (pixels, channels, samples and
-    grids) submitted together share the batched launch sequence; each result
-    against the direct fused call on the same inputs (cube and loss to 1e-6,
-    every gradient block to 1e-5 of its largest entry: the same arithmetic, a
-    different order of the float accumulators' atomics), and one against the FP64 oracle's
-    autograd gradient."""
+    grids) submitted together share the batched launch sequence.  Every
+    result against the FP64 oracle's autograd gradient (L2 <= 1e-3 per
+    block, the gradient bar), and against the direct fused call on the same
+    inputs: the cube to 5e-6 of its peak (half the oracle bar: the batched
+    march's lanes fold their channel offset into a - g shift b, which rounds
+    differently from the direct call's one lane per pixel with its own
+    velocities, 1.3e-6 measured), the loss to what that cube difference
+    allows, and each gradient block to L2 <= 1e-4.  The gradients are linear
+    in the residual 2 (I - D), a few per cent of I, so the cubes' rounding
+    difference reaches them amplified (2.4e-5 of a block's largest entry
+    measured)."""
     rt = _rt()
     from oracle import torch_ref
     shapes = [(24, 12, 64, 48, 24), (40, 33, 96, 64, 32), (32, 20, 128, 40, 20), (56, 64, 80, 64, 32),
@@ -321,21 +327,58 @@ def test_batched_gradient_requests_match_direct():
         subs = [submit_grad(sv, sc, tgt) for _, sc, tgt in reqs]
         infos = [sv.wait(t) for t, _, _ in subs]
     torch.cuda.synchronize()
+
+    def l2rel(a, ref):
+        a, ref = a.ravel(), ref.ravel()
+        return float(np.linalg.norm(a - ref) / max(float(np.linalg.norm(ref)), 1e-300))
+
     for i, ((t, cube, grads), info, (dc, dl, dg)) in enumerate(zip(subs, infos, direct)):
         assert info["state"] == "done", i
         scale = float(dc.abs().max())
-        assert float((cube - dc).abs().max()) <= 1e-6 * scale, i
-        assert info["loss"] == pytest.approx(float(dl.item()), rel=1e-6), i
+        d_cube = float((cube - dc).abs().max())
+        assert d_cube <= 5e-6 * scale, i
+        # the two cubes differ by rounding, which moves L = sum (I - D)^2 by at
+        # most 2 sum |I - D| max|dI| + N max|dI|^2 (plus the FP64 sums' own error)
+        prob, _, tgt = reqs[i]
+        bound = 2.0 * float((dc - tgt).abs().double().sum()) * d_cube + dc.numel() * d_cube ** 2
+        assert abs(info["loss"] - float(dl.item())) <= bound + 1e-9 * float(dl.item()), i
+        _, oref = torch_ref.loss_and_grad(prob, tgt.cpu().numpy().astype(np.float64))
         for k in GKEYS:
-            s = float(dg[k].abs().max())
-            assert float((grads[k] - dg[k]).abs().max()) <= 1e-5 * s + 1e-30, (i, k)
-    prob, sc, tgt = reqs[1]
-    _, oref = torch_ref.loss_and_grad(prob, tgt.cpu().numpy().astype(np.float64))
+            g = grads[k].cpu().numpy().astype(np.float64)
+            vs_direct = l2rel(g, dg[k].cpu().numpy().astype(np.float64))
+            vs_oracle = l2rel(g, oref[k])
+            print(f"request {i} {k}: L2 rel vs direct {vs_direct:.2e}, vs oracle {vs_oracle:.2e}")
+            assert vs_direct <= 1e-4, (i, k)
+            assert vs_oracle <= 1e-3, (i, k)
+
+
+def test_gradient_request_with_uneven_channels():
+    """A small gradient request whose channel velocities are not uniformly
+    spaced cannot take the batched reverse march (its lanes hold channels
+    offset by one constant velocity) and runs the direct fused call on a
+    stream of its own, beside batched requests: cube, loss and gradients as
+    the direct call's."""
+    rt = _rt()
+    prob, sc, tgt = grad_scene(40, 24, 96, 2240)
+    v = sc.v_kms.copy()
+    v[13] += 0.037
+    sc = sc.replace(v_kms=v)
+    tgt = rt.render(sc.replace(z_up_au=sc.z_up_au * 1.05))
+    dc, dl, dg = rt.render_l2_adjoint(sc, tgt, want=GKEYS)
+    others = [grad_scene(32, 16, 64, 2241 + i) for i in range(2)]
+    torch.cuda.synchronize()
+    print("[gpu] server: uneven-channel gradient request beside batched ones", flush=True)
+    with rt.Server(max_slots=16, streams=2) as sv:
+        subs = [submit_grad(sv, s2, t2) for _, s2, t2 in others]
+        t, cube, grads = submit_grad(sv, sc, tgt)
+        info = sv.wait(t)
+        assert all(sv.wait(x[0])["state"] == "done" for x in subs)
+    torch.cuda.synchronize()
+    assert info["state"] == "done"
+    assert float((cube - dc).abs().max()) <= 1e-6 * float(dc.abs().max())
+    assert info["loss"] == pytest.approx(float(dl.item()), rel=1e-6)
     for k in GKEYS:
-        r, g = oref[k].ravel(), subs[1][2][k].cpu().numpy().astype(np.float64).ravel()
-        l2 = float(np.linalg.norm(g - r) / np.linalg.norm(r))
-        print(f"batched {k}: L2 rel vs oracle {l2:.2e}")
-        assert l2 <= 1e-3, k
+        assert float((grads[k] - dg[k]).abs().max()) <= 1e-5 * float(dg[k].abs().max()), k
 
 
 @pytest.mark.parametrize("accum", [0, 1])
@@ -422,6 +465,8 @@ def test_gradient_requests_wait_out_a_memory_squeeze():
     finally:
         del blocker
         torch.cuda.empty_cache()
+    print(f"free before the hold {free / 1e9:.2f} GB, left {room / 1e9:.2f} GB; tickets:",
+          [(x["state"], x["status"]) for x in infos], flush=True)
     for info in infos:
         assert info["state"] == "done", info
     dc, dl, dg = rt.render_l2_adjoint(sc, tgt, want=GKEYS)
