@@ -174,7 +174,7 @@ rt_status rt_render_cube_l2_adjoint(const rt_problem *p, const float *target, co
  * capture, tight serving loops, harnesses that forbid allocation): the same
  * as rt_render_cube_l2_adjoint for grid fields (no network), but it calls no
  * allocator.  The library's scratch for the call (partition-function table,
- * FP64 gradient accumulators, the sample tape and cotangents of one band of
+ * gradient accumulators, the sample tape and cotangents of one band of
  * image rows; the image is processed band by band) lives in one fixed device
  * array of rt_noalloc_scratch_bytes() bytes (256 MiB) per GPU, held until
  * the process ends.  Every call on a GPU shares that GPU's array: calls that

@@ -13,7 +13,8 @@
 //   giving dI/dS_k = Tr_k (1 - a_k) and dI/ddtau_k = Tr_{k+1} (S_k - J_k)
 //   without the cancellation of I minus a prefix sum.  Channel sums of the
 //   per-sample cotangents (S, ln K, a, b) are written per channel block.
-// Pass B without checkpoints (adj_march_tau<CB, CUBE>, the default): the
+// Pass B without checkpoints (adj_march_tau<CB, G, CUBE>, the default; G
+//   lanes per pixel): the
 //   optical depth is additive, so the transmission in front of sample k is
 //   2^-(tau_tot - tau_suf(k)) with tau_suf the depth behind it.  A first
 //   back-to-front sweep adds up tau_tot (and, when the intensity is wanted,
@@ -21,10 +22,11 @@
 //   tau_suf in the same order, so the only state kept per (ray, channel) is
 //   the total depth, in a register, and nothing is written but the
 //   cotangents.
-// Pass C (adj_chain): one lane per pixel-sample recomputes the shading with
-//   its local derivatives, chains the cotangents to the interpolated fields
-//   and scatters them to the grid nodes (float atomics; the surface vectors
-//   are accumulated in LDS first).
+// Pass C (adj_chain_lds, or adj_chain for grids too large for LDS): each
+//   pixel-sample's shading is recomputed with its local derivatives, the
+//   cotangents are chained to the interpolated fields and added to the grid
+//   nodes (one field per pass privatised in LDS and flushed once; adj_chain
+//   scatters with global atomics; the surface vectors in LDS either way).
 #include <type_traits>
 
 #include "rt_adjoint.h"

@@ -103,7 +103,7 @@ rt_status adjoint_core(const rt_problem *p, const float *dl, const rt_grads *g, 
     const int npix = p->cam.nx * p->cam.ny;
     const int ns = p->nsamp;
     const size_t nn = (size_t)p->grid.nr * p->grid.nz, nr = (size_t)p->grid.nr;
-    // gradients accumulate in double (float with RT_OPT_GRAD_ACCUM 0), then
+    // gradients accumulate in float (double with RT_OPT_GRAD_ACCUM 1), then
     // overwrite the caller's float outputs
     const size_t acc_n = 3 * nn + 2 * nr;
     double *ab = fx ? (double *)(fx->base + fixed_table_bytes())

@@ -8,8 +8,8 @@
 // kernel is point-symmetric and the padding is zeros, so the operator is its
 // own adjoint: the backward of the convolution is the same call.
 //
-// beam_weights (one workgroup) evaluates the (2R+1)^2 weights in double,
-// normalises them by their sum and stores them as float.  beam_conv: one
+// beam_weights (one workgroup) evaluates the (2R+1)^2 weights in float,
+// normalises them by their workgroup-reduced sum and stores them.  beam_conv: one
 // workgroup per 64 x 32 output tile of one channel; the tile plus its R-wide
 // halo is staged in LDS (zeros outside the image) with the weights; each lane
 // forms 8 consecutive outputs of one row, sliding a window of 8 staged values

@@ -7,14 +7,15 @@
 // item from a device counter:
 //   tape   -- (request, 256-pixel tile, chunk of samples): the shading of
 //             every sample to the request's tape;
-//   march  -- (request, 128-pixel tile, slice of 2 x 16 channels): the
+//   march  -- (request, 64-pixel tile, slice of 4 x 8 channels): the
 //             checkpoint-free reverse march with the intensity formed in the
 //             march, writing the cube and the per-sample cotangents;
 //   chain  -- (request, field pass, chunk of pixel-samples): the shading's
 //             local derivatives, accumulated in LDS by a 1024-lane workgroup
-//             and flushed once into the request's FP64 accumulators;
-// then one launch writes every request's gradients (FP64 -> FP32) and one its
-// loss.  A request's items are those of its own problem and its results go
+//             and flushed once into the request's accumulators (float, or
+//             double by option);
+// then one launch writes every request's gradients (as float) and one its
+// loss (summed in double).  A request's items are those of its own problem and its results go
 // to its own buffers, so what it gets does not depend on the rest of the
 // batch beyond the order of the atomic additions.
 #include "rt_adjoint_dev.h"
