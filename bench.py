@@ -773,16 +773,41 @@ def bench_serving(rt, synth, dev, seconds, rate=200.0, seed=5, pool=16, saturate
         torch.cuda.synchronize()
         torch.cuda.empty_cache()
         with rt.Server(hbm_budget_bytes=96 << 30, max_slots=64, streams=4) as sv:
-            sv.wait(submit(sv, order[0]))
+            first = submit(sv, order[0])
+            sv.wait(first)
+            sv.release(first)
             t0 = time.perf_counter()
-            tickets = []
+            tickets, done, live = [], {}, []
+            last = [t0]
+
+            def reap():
+                # finished requests hand their output cube back to torch's
+                # cache as the trace goes, so a long trace holds only the
+                # requests in flight
+                still = []
+                for t in live:
+                    x = sv.poll(t)
+                    if x["state"] in ("done", "canceled", "failed"):
+                        done[t] = x
+                        sv.release(t)
+                    else:
+                        still.append(t)
+                live[:] = still
+
             for i, ta in zip(order, arrivals):
                 while time.perf_counter() - t0 < ta:
                     time.sleep(2e-4)
-                tickets.append(submit(sv, i))
-            infos = [sv.wait(t, timeout_s=300) for t in tickets]
-            for t in tickets:
+                t = submit(sv, i)
+                tickets.append(t)
+                live.append(t)
+                now = time.perf_counter()
+                if now - last[0] > 2e-3:
+                    reap()
+                    last[0] = now
+            for t in live:
+                done[t] = sv.wait(t, timeout_s=300)
                 sv.release(t)
+        infos = [done[t] for t in tickets]
         for t, x in zip(tickets, infos):
             if x["state"] != "done":
                 log(f"request {t} ended {x['state']} (status {x['status']})")
