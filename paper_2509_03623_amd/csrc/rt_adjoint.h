@@ -22,7 +22,8 @@ hipError_t launch_adj_tape(const Geometry &g, const Shade &s, float4 *tape, floa
 // reverse march; lanes = 4 needs the velocities uniformly spaced in groups of
 // cb (lane g's = lane 0's + g shift)
 hipError_t launch_adj_march(int cb, int kseg, int lanes, int nsamp, int npix, int plane, const Channels &ch,
-                            float shift, const float4 *tape, const float *dl, const float *target, float *ckpt,
+                            float shift, const float4 *tape, const float4 *rays, const float *dl,
+                            const float *target, float *ckpt,
                             float4 *cot, float *cube_out, hipStream_t st);
 hipError_t launch_adj_chain(const Geometry &g, const Shade &s, const float4 *rays, const float4 *cot, int nblk,
                             const GradAcc &go, float4 *dO, hipStream_t st);

@@ -184,7 +184,7 @@ template <int CB, int G, bool CUBE>
 __global__ __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(CB * G <= 8 ? 6 : G == 4 ? 4 : CB <= 16 && G == 1 ? 4 : CB <= 24 && G == 1 ? 3 : 2)))
 void adj_march_tau(int nsamp, int npix, int plane, int nblk, Channels ch, float shift,
-                   const float4 *__restrict__ tape, const float *__restrict__ dl_dcube,
+                   const float4 *__restrict__ tape, const float4 *__restrict__ rays, const float *__restrict__ dl_dcube,
                    const float *__restrict__ target, float4 *__restrict__ cot, float *__restrict__ cube_out) {
     static_assert(G == 1 || G == 2 || G == 4, "one, two or four lanes per pixel");
     const int id = blockIdx.x, r8 = id >> 3;
@@ -193,10 +193,11 @@ void adj_march_tau(int nsamp, int npix, int plane, int nblk, Channels ch, float 
     const int pix = ((r8 / nblk) * 8 + (id & 7)) * (256 / G) + (int)threadIdx.x / G;
     if (pix >= npix) return;   // the lanes of a pixel leave together
     const int c0 = (blk * G + g) * CB;
+    const bool live = rays[pix].w > 0.0f;
     if constexpr (G == 4) {
         auto vel = [&](int c) { return ch.v[blk * G * CB + c]; };
-        march_tau_pixel<CB, G, CUBE, true>(pix, blk, g, c0, ch.n, nsamp, npix, plane, vel, tape, dl_dcube, target,
-                                           cot, cube_out, (float)g * shift);
+        march_tau_pixel<CB, G, CUBE, true>(pix, blk, g, c0, ch.n, nsamp, npix, plane, live, vel, tape, dl_dcube,
+                                           target, cot, cube_out, (float)g * shift);
     } else {
         // channel velocities: scalar registers with one lane per pixel,
         // vector registers when the lanes of a pixel take different channels
@@ -209,8 +210,8 @@ void adj_march_tau(int nsamp, int npix, int plane, int nblk, Channels ch, float 
             if constexpr (G > 1) return vv[c];
             else return ch.v[c0 + c];
         };
-        march_tau_pixel<CB, G, CUBE>(pix, blk, g, c0, ch.n, nsamp, npix, plane, vel, tape, dl_dcube, target, cot,
-                                     cube_out);
+        march_tau_pixel<CB, G, CUBE>(pix, blk, g, c0, ch.n, nsamp, npix, plane, live, vel, tape, dl_dcube, target,
+                                     cot, cube_out);
     }
 }
 
@@ -283,6 +284,9 @@ __global__ __launch_bounds__(256) void adj_chain(Geometry g, Shade s, const floa
 // lanes per workgroup of the privatised chain pass: one workgroup fills a CU's
 // LDS, so it brings sixteen waves to keep the CU busy
 constexpr int kChainThreads = 1024;
+// pixel rotation from one sample plane to the next in the chain pass (an odd
+// number of workgroup spans)
+constexpr int kChainTurn = 37 * kChainThreads;
 
 // Chain pass with the gradient of one field privatised in LDS.  Persistent
 // workgroups take runs of 1024 consecutive pixel-samples in grid-stride
@@ -308,10 +312,16 @@ __global__ __launch_bounds__(kChainThreads) void adj_chain_lds(Geometry g, Shade
     __syncthreads();
     const int npix = g.nx * g.ny;
     const size_t total = (size_t)g.nsamp * npix;
+    // sample plane k is visited with its pixels rotated by k kChainTurn: a
+    // lane's pixel moves across the image from one plane to the next, so no
+    // workgroup keeps the same rays (the disk's centre or the empty corners)
+    // for every sample when the grid stride is a multiple of the image
+    const int turn = (int)((size_t)kChainTurn % (size_t)npix);
     for (size_t idx = (size_t)blockIdx.x * kChainThreads + threadIdx.x; idx < total;
          idx += (size_t)gridDim.x * kChainThreads) {
         const int k = (int)(idx / npix);
-        const int pix = (int)(idx - (size_t)k * npix);
+        int pix = (int)(idx - (size_t)k * npix) + (int)(((long)k * turn) % npix);
+        if (pix >= npix) pix -= npix;
         const float4 r = rays[pix];
         // the first pass sums the channel-block slices and keeps the sum in slice 0
         float4 c = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
@@ -512,24 +522,26 @@ static hipError_t launch_march_t(int nsamp, int npix, int plane, const Channels 
 
 template <int CB, int G, bool CUBE>
 static hipError_t launch_tau_t(int nsamp, int npix, int plane, const Channels &ch, float shift, const float4 *tape,
-                               const float *dl, const float *target, float4 *cot, float *cube_out, hipStream_t st) {
+                               const float4 *rays, const float *dl, const float *target, float4 *cot, float *cube_out,
+                               hipStream_t st) {
     const int nblk = (ch.n + G * CB - 1) / (G * CB);
     const long tiles = (npix + 256 / G - 1) / (256 / G);
     const long ids = (tiles + 7) / 8 * 8 * nblk;
     hipLaunchKernelGGL((adj_march_tau<CB, G, CUBE>), dim3((unsigned)ids), dim3(256), 0, st, nsamp, npix, plane, nblk,
-                       ch, shift, tape, dl, target, cot, cube_out);
+                       ch, shift, tape, rays, dl, target, cot, cube_out);
     return hipGetLastError();
 }
 
 hipError_t launch_adj_march(int cb, int kseg, int lanes, int nsamp, int npix, int plane, const Channels &ch,
-                            float shift, const float4 *tape, const float *dl, const float *target, float *ckpt,
+                            float shift, const float4 *tape, const float4 *rays, const float *dl,
+                            const float *target, float *ckpt,
                             float4 *cot, float *cube_out, hipStream_t st) {
     if (kseg == 0) {
         const bool cube = target || cube_out;
 #define RT_TAU_CASE(C, G)                                                                                         \
     if (cb == C && lanes == G)                                                                                   \
-        return cube ? launch_tau_t<C, G, true>(nsamp, npix, plane, ch, shift, tape, dl, target, cot, cube_out, st) \
-                    : launch_tau_t<C, G, false>(nsamp, npix, plane, ch, shift, tape, dl, target, cot, cube_out, st);
+        return cube ? launch_tau_t<C, G, true>(nsamp, npix, plane, ch, shift, tape, rays, dl, target, cot, cube_out, st) \
+                    : launch_tau_t<C, G, false>(nsamp, npix, plane, ch, shift, tape, rays, dl, target, cot, cube_out, st);
         RT_TAU_CASE(8, 1) RT_TAU_CASE(16, 1) RT_TAU_CASE(24, 1) RT_TAU_CASE(32, 1)
         RT_TAU_CASE(16, 2) RT_TAU_CASE(24, 2) RT_TAU_CASE(25, 2) RT_TAU_CASE(32, 2)
         RT_TAU_CASE(12, 4) RT_TAU_CASE(16, 4)

@@ -47,14 +47,29 @@ __device__ __forceinline__ float swap_half_quad(float x) {
 // the lane then folds vsh into a (d_c = (a - vsh b) - vel(c) b) and the
 // derivative in b takes -vsh times the one in a.  With CUBE the march forms
 // the intensity, and with target != NULL dL/dI = 2 (I - D) from it;
-// otherwise dL/dI is read from dl_dcube.
+// otherwise dL/dI is read from dl_dcube.  A pixel whose ray misses the grid
+// (live false: its ray record has ds = 0) has zero intensity and no
+// samples: it only clears its channels of the cube, and its cotangents are
+// left unwritten, since every chain pass skips rays with ds = 0.
 template <int CB, int G, bool CUBE, bool SHIFT = false, class Vel>
 __device__ __forceinline__ void march_tau_pixel(int pix, int blk, int g, int c0, int nch, int nsamp, int npix,
-                                                int plane, Vel vel, const float4 *__restrict__ tape,
+                                                int plane, bool live, Vel vel, const float4 *__restrict__ tape,
                                                 const float *__restrict__ dl_dcube, const float *__restrict__ target,
                                                 float4 *__restrict__ cot, float *__restrict__ cube_out,
                                                 float vsh = 0.0f) {
+    if (!live) {
+        if (CUBE && cube_out) {
+#pragma unroll
+            for (int c = 0; c < CB; ++c)
+                if (c0 + c < nch) cube_out[(size_t)(c0 + c) * plane + pix] = 0.0f;
+        }
+        return;
+    }
     float th[CB], tl[CB], w[CB];
+    // the samples with K > 0 (one run along the ray): those outside [kf, kl]
+    // add nothing (their x is 0 in every channel), so sweep 2 leaves them out
+    // and their cotangents are zero
+    int kf = nsamp, kl = -1;
     {
         // sweep 1, back to front: total depth and (CUBE) J, which reaches I
         float J[CB];
@@ -70,6 +85,10 @@ __device__ __forceinline__ void march_tau_pixel(int pix, int blk, int g, int c0,
         for (int k = nsamp - 1; k >= 0; --k) {
             float4 q = qn;
             qn = tape[(size_t)max(k - 1, 0) * npix + pix];
+            if (q.y > 0.0f) {
+                kf = k;
+                kl = max(kl, k);
+            }
             if constexpr (SHIFT) q.z = fmaf(-vsh, q.w, q.z);
             const float lK = flog2(q.y);
             // J_k-1 = S (1 - att) + att J_k: as S - att (S - J_k), or on a thin
@@ -116,9 +135,15 @@ __device__ __forceinline__ void march_tau_pixel(int pix, int blk, int g, int c0,
         J[c] = 0.0f;
         u[c] = w[c] * fexp2(sh[c] + sl[c]);
     }
-    float4 qn = tape[(size_t)(nsamp - 1) * npix + pix];
+    if (g == 0) {
+        const float4 z = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        for (int k = nsamp - 1; k > kl; --k) cot[((size_t)blk * nsamp + k) * npix + pix] = z;
+        if (kl >= 0)
+            for (int k = kf - 1; k >= 0; --k) cot[((size_t)blk * nsamp + k) * npix + pix] = z;
+    }
+    float4 qn = tape[(size_t)max(kl, 0) * npix + pix];
 #pragma unroll 1
-    for (int k = nsamp - 1; k >= 0; --k) {
+    for (int k = kl; k >= kf; --k) {
         const float4 q = qn;
         qn = tape[(size_t)max(k - 1, 0) * npix + pix];
         const float S = q.x, b = q.w;

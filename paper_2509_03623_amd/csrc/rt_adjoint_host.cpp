@@ -167,7 +167,7 @@ rt_status adjoint_core(const rt_problem *p, const float *dl, const rt_grads *g, 
             float4 *cot = (float4 *)(base + tape_b + rays_b + ckpt_b);
             if ((e = launch_adj_tape(gb, sb, tape, rays, st)) != hipSuccess) return fail_hip(e, "adjoint tape");
             const size_t off = (size_t)c0 * plane + pix0;
-            if ((e = launch_adj_march(cb_l, kseg, lanes_l, ns, bpix, (int)plane, ch, (float)shift, tape,
+            if ((e = launch_adj_march(cb_l, kseg, lanes_l, ns, bpix, (int)plane, ch, (float)shift, tape, rays,
                                       dl ? dl + off : nullptr, target ? target + off : nullptr, ckpt, cot,
                                       cube_opt ? cube_opt + off : nullptr, st)) != hipSuccess)
                 return fail_hip(e, "adjoint march");

@@ -144,7 +144,8 @@ __global__ __launch_bounds__(256) void grad_march(const GradDesc *__restrict__ d
             // folded into a by the march
             const float *vch = uniform_ptr(D->vch) + blk * kGradSlice;
             auto vel = [&](int c) -> float { return vch[c]; };
-            march_tau_pixel<CB, G, true, true>(pix, blk, g, c0, nch, nsamp, npix, npix, vel, uniform_ptr(D->tape),
+            const bool live = uniform_ptr(D->rays)[pix].w > 0.0f;
+            march_tau_pixel<CB, G, true, true>(pix, blk, g, c0, nch, nsamp, npix, npix, live, vel, uniform_ptr(D->tape),
                                                nullptr, uniform_ptr(D->target), uniform_ptr(D->cot),
                                                uniform_ptr(D->cube), (float)g * vshift);
         }
