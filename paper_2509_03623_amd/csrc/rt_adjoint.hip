@@ -38,7 +38,7 @@ namespace rt {
 // blockIdx.y selects a chunk of the samples, so short images still give the
 // GPU enough lanes
 __global__ __launch_bounds__(256) void adj_tape(Geometry g, Shade s, float4 *__restrict__ tape,
-                                                float4 *__restrict__ rays) {
+                                                float4 *__restrict__ rays, int2 *__restrict__ span) {
     __shared__ float4 ztab[kZTableNodes - 1];
     stage_ztab(s, ztab);
     const int npix = g.nx * g.ny;
@@ -46,7 +46,7 @@ __global__ __launch_bounds__(256) void adj_tape(Geometry g, Shade s, float4 *__r
     if (pix >= npix) return;
     const int len = (g.nsamp + gridDim.y - 1) / gridDim.y;
     const int k0 = blockIdx.y * len, k1 = min(g.nsamp, k0 + len);
-    tape_pixel(g, s, ztab, pix, k0, k1, blockIdx.y == 0, tape, rays);
+    tape_pixel(g, s, ztab, pix, k0, k1, blockIdx.y == 0, tape, rays, span, gridDim.y > 1);
 }
 
 // dl_dcube: the cotangent dL/dI; or, with target != NULL, the cotangent of
@@ -184,7 +184,7 @@ template <int CB, int G, bool CUBE>
 __global__ __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(CB * G <= 8 ? 6 : G == 4 ? 4 : CB <= 16 && G == 1 ? 4 : CB <= 24 && G == 1 ? 3 : 2)))
 void adj_march_tau(int nsamp, int npix, int plane, int nblk, Channels ch, float shift,
-                   const float4 *__restrict__ tape, const float4 *__restrict__ rays, const float *__restrict__ dl_dcube,
+                   const float4 *__restrict__ tape, const int2 *__restrict__ span, const float *__restrict__ dl_dcube,
                    const float *__restrict__ target, float4 *__restrict__ cot, float *__restrict__ cube_out) {
     static_assert(G == 1 || G == 2 || G == 4, "one, two or four lanes per pixel");
     const int id = blockIdx.x, r8 = id >> 3;
@@ -193,11 +193,12 @@ void adj_march_tau(int nsamp, int npix, int plane, int nblk, Channels ch, float 
     const int pix = ((r8 / nblk) * 8 + (id & 7)) * (256 / G) + (int)threadIdx.x / G;
     if (pix >= npix) return;   // the lanes of a pixel leave together
     const int c0 = (blk * G + g) * CB;
-    const bool live = rays[pix].w > 0.0f;
+    const int2 ks = span_of(span[pix], nsamp);
+    const bool live = ks.y >= ks.x;
     if constexpr (G == 4) {
         auto vel = [&](int c) { return ch.v[blk * G * CB + c]; };
-        march_tau_pixel<CB, G, CUBE, true>(pix, blk, g, c0, ch.n, nsamp, npix, plane, live, vel, tape, dl_dcube,
-                                           target, cot, cube_out, (float)g * shift);
+        march_tau_pixel<CB, G, CUBE, true, true>(pix, blk, g, c0, ch.n, nsamp, npix, plane, live, vel, tape, dl_dcube,
+                                                 target, cot, cube_out, (float)g * shift, ks);
     } else {
         // channel velocities: scalar registers with one lane per pixel,
         // vector registers when the lanes of a pixel take different channels
@@ -210,8 +211,8 @@ void adj_march_tau(int nsamp, int npix, int plane, int nblk, Channels ch, float 
             if constexpr (G > 1) return vv[c];
             else return ch.v[c0 + c];
         };
-        march_tau_pixel<CB, G, CUBE>(pix, blk, g, c0, ch.n, nsamp, npix, plane, live, vel, tape, dl_dcube, target,
-                                     cot, cube_out);
+        march_tau_pixel<CB, G, CUBE, false, true>(pix, blk, g, c0, ch.n, nsamp, npix, plane, live, vel, tape, dl_dcube,
+                                                  target, cot, cube_out, 0.0f, ks);
     }
 }
 
@@ -228,8 +229,8 @@ __device__ __forceinline__ void scatter4(A *dst, int n00, int n10, float gv, flo
 
 template <typename A>
 __global__ __launch_bounds__(256) void adj_chain(Geometry g, Shade s, const float4 *__restrict__ rays,
-                                                 const float4 *__restrict__ cot, int nblk, GradAcc go,
-                                                 int lds_surfaces, float4 *__restrict__ dO) {
+                                                 const int2 *__restrict__ span, const float4 *__restrict__ cot,
+                                                 int nblk, GradAcc go, int lds_surfaces, float4 *__restrict__ dO) {
     extern __shared__ float lds[];   // [2][nr] surface gradients when lds_surfaces
     __shared__ float4 ztab[kZTableNodes - 1];
     stage_ztab(s, ztab);
@@ -245,11 +246,16 @@ __global__ __launch_bounds__(256) void adj_chain(Geometry g, Shade s, const floa
     if (idx < total) {
         const int k = (int)(idx / npix);
         const int pix = (int)(idx - (size_t)k * npix);
-        const float4 r = rays[pix];
+        // samples outside the ray's run of K > 0 have no cotangents
+        const int2 ks = span_of(span[pix], g.nsamp);
         float4 c = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        for (int b = 0; b < nblk; ++b) {
-            const float4 t = cot[((size_t)b * g.nsamp + k) * npix + pix];
-            c.x += t.x; c.y += t.y; c.z += t.z; c.w += t.w;
+        float4 r = c;
+        if (k >= ks.x && k <= ks.y) {
+            r = rays[pix];
+            for (int b = 0; b < nblk; ++b) {
+                const float4 t = cot[((size_t)b * g.nsamp + k) * npix + pix];
+                c.x += t.x; c.y += t.y; c.z += t.z; c.w += t.w;
+            }
         }
         float4 dout = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         if (r.w > 0.0f && (c.x != 0.0f || c.y != 0.0f || c.z != 0.0f || c.w != 0.0f)) {
@@ -299,8 +305,8 @@ constexpr int kChainTurn = 37 * kChainThreads;
 // writes dL/do.
 template <int FIELD, bool FIRST, typename A>
 __global__ __launch_bounds__(kChainThreads) void adj_chain_lds(Geometry g, Shade s, const float4 *__restrict__ rays,
-                                                     float4 *__restrict__ cot, int nblk, GradAcc go,
-                                                     float4 *__restrict__ dO) {
+                                                     const int2 *__restrict__ span, float4 *__restrict__ cot,
+                                                     int nblk, GradAcc go, float4 *__restrict__ dO) {
     extern __shared__ float dyn[];               // [2 nr] surfaces (FIRST), then [nr nz] field
     __shared__ float4 ztab[kZTableNodes - 1];
     const int nr = s.nr, nn = s.nr * s.nz;
@@ -322,15 +328,21 @@ __global__ __launch_bounds__(kChainThreads) void adj_chain_lds(Geometry g, Shade
         const int k = (int)(idx / npix);
         int pix = (int)(idx - (size_t)k * npix) + (int)(((long)k * turn) % npix);
         if (pix >= npix) pix -= npix;
-        const float4 r = rays[pix];
-        // the first pass sums the channel-block slices and keeps the sum in slice 0
+        // samples outside the ray's run of K > 0 have no cotangents (the
+        // march leaves them unwritten)
+        const int2 ks = span_of(span[pix], g.nsamp);
         float4 c = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        const int nb = FIRST ? nblk : 1;
-        for (int b = 0; b < nb; ++b) {
-            const float4 t = cot[((size_t)b * g.nsamp + k) * npix + pix];
-            c.x += t.x; c.y += t.y; c.z += t.z; c.w += t.w;
+        float4 r = c;
+        if (k >= ks.x && k <= ks.y) {
+            r = rays[pix];
+            // the first pass sums the channel-block slices and keeps the sum in slice 0
+            const int nb = FIRST ? nblk : 1;
+            for (int b = 0; b < nb; ++b) {
+                const float4 t = cot[((size_t)b * g.nsamp + k) * npix + pix];
+                c.x += t.x; c.y += t.y; c.z += t.z; c.w += t.w;
+            }
+            if (FIRST && nblk > 1) cot[(size_t)k * npix + pix] = c;
         }
-        if (FIRST && nblk > 1) cot[(size_t)k * npix + pix] = c;
         float4 dout = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         if (r.w > 0.0f && (c.x != 0.0f || c.y != 0.0f || c.z != 0.0f || c.w != 0.0f)) {
             const float ds = r.w;
@@ -398,13 +410,13 @@ __global__ __launch_bounds__(kChainThreads) void adj_chain_lds(Geometry g, Shade
 }
 
 template <int FIELD, bool FIRST, typename A>
-static hipError_t launch_chain_lds_t(const Geometry &g, const Shade &s, const float4 *rays, float4 *cot, int nblk,
-                                     const GradAcc &go, float4 *dO, int nwg, size_t shmem, hipStream_t st) {
+static hipError_t launch_chain_lds_t(const Geometry &g, const Shade &s, const float4 *rays, const int2 *span, float4 *cot,
+                                     int nblk, const GradAcc &go, float4 *dO, int nwg, size_t shmem, hipStream_t st) {
     hipError_t e = hipFuncSetAttribute((const void *)adj_chain_lds<FIELD, FIRST, A>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((adj_chain_lds<FIELD, FIRST, A>), dim3(nwg), dim3(kChainThreads), shmem, st, g, s, rays, cot,
-                       nblk, go, dO);
+    hipLaunchKernelGGL((adj_chain_lds<FIELD, FIRST, A>), dim3(nwg), dim3(kChainThreads), shmem, st, g, s, rays, span,
+                       cot, nblk, go, dO);
     return hipGetLastError();
 }
 
@@ -417,8 +429,8 @@ bool chain_lds_fits(int nr, int nz) {
 }
 
 template <typename A>
-static hipError_t chain_lds_passes(const Geometry &g, const Shade &s, const float4 *rays, float4 *cot, int nblk,
-                                   const GradAcc &go, float4 *dO, int nwg, hipStream_t st) {
+static hipError_t chain_lds_passes(const Geometry &g, const Shade &s, const float4 *rays, const int2 *span,
+                                   float4 *cot, int nblk, const GradAcc &go, float4 *dO, int nwg, hipStream_t st) {
     const size_t fb = (size_t)s.nr * s.nz * sizeof(float), sb = 2 * (size_t)s.nr * sizeof(float);
     const bool want[3] = {go.ln_n != nullptr, go.temp != nullptr, go.vphi != nullptr};
     bool first = true;
@@ -427,30 +439,30 @@ static hipError_t chain_lds_passes(const Geometry &g, const Shade &s, const floa
         if (!want[f]) continue;
         const size_t shmem = fb + (first ? sb : 0);
         if (first) {
-            e = f == 0 ? launch_chain_lds_t<0, true, A>(g, s, rays, cot, nblk, go, dO, nwg, shmem, st)
-              : f == 1 ? launch_chain_lds_t<1, true, A>(g, s, rays, cot, nblk, go, dO, nwg, shmem, st)
-                       : launch_chain_lds_t<2, true, A>(g, s, rays, cot, nblk, go, dO, nwg, shmem, st);
+            e = f == 0 ? launch_chain_lds_t<0, true, A>(g, s, rays, span, cot, nblk, go, dO, nwg, shmem, st)
+              : f == 1 ? launch_chain_lds_t<1, true, A>(g, s, rays, span, cot, nblk, go, dO, nwg, shmem, st)
+                       : launch_chain_lds_t<2, true, A>(g, s, rays, span, cot, nblk, go, dO, nwg, shmem, st);
         } else {
-            e = f == 1 ? launch_chain_lds_t<1, false, A>(g, s, rays, cot, nblk, go, dO, nwg, shmem, st)
-                       : launch_chain_lds_t<2, false, A>(g, s, rays, cot, nblk, go, dO, nwg, shmem, st);
+            e = f == 1 ? launch_chain_lds_t<1, false, A>(g, s, rays, span, cot, nblk, go, dO, nwg, shmem, st)
+                       : launch_chain_lds_t<2, false, A>(g, s, rays, span, cot, nblk, go, dO, nwg, shmem, st);
         }
         if (e != hipSuccess) return e;
         first = false;
     }
-    if (first) e = launch_chain_lds_t<3, true, A>(g, s, rays, cot, nblk, go, dO, nwg, sb, st);
+    if (first) e = launch_chain_lds_t<3, true, A>(g, s, rays, span, cot, nblk, go, dO, nwg, sb, st);
     return e;
 }
 
-hipError_t launch_adj_chain_lds(const Geometry &g, const Shade &s, const float4 *rays, float4 *cot, int nblk,
-                                const GradAcc &go, float4 *dO, hipStream_t st) {
+hipError_t launch_adj_chain_lds(const Geometry &g, const Shade &s, const float4 *rays, const int2 *span, float4 *cot,
+                                int nblk, const GradAcc &go, float4 *dO, hipStream_t st) {
     int dev = 0, ncu = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return e;
     const size_t total = (size_t)g.nsamp * g.nx * g.ny;
     const int nwg = (int)std::min<size_t>((size_t)ncu, (total + kChainThreads - 1) / kChainThreads);
-    return grad_accum_double() ? chain_lds_passes<double>(g, s, rays, cot, nblk, go, dO, nwg, st)
-                               : chain_lds_passes<float>(g, s, rays, cot, nblk, go, dO, nwg, st);
+    return grad_accum_double() ? chain_lds_passes<double>(g, s, rays, span, cot, nblk, go, dO, nwg, st)
+                               : chain_lds_passes<float>(g, s, rays, span, cot, nblk, go, dO, nwg, st);
 }
 
 __global__ void fill_zero_d(double *p, size_t n) {
@@ -500,13 +512,17 @@ hipError_t zero_async(float *p, size_t n, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_adj_tape(const Geometry &g, const Shade &s, float4 *tape, float4 *rays, hipStream_t st) {
+hipError_t launch_adj_tape(const Geometry &g, const Shade &s, float4 *tape, float4 *rays, int2 *span, hipStream_t st) {
     const int npix = g.nx * g.ny;
     const int tiles = (npix + 255) / 256;
     // sample chunks until about 16 waves per CU (of at least 32 samples each)
     int chunks = 1;
     while (chunks < 16 && (long)tiles * 4 * chunks < 16L * 256 && g.nsamp >= 64 * chunks) chunks *= 2;
-    hipLaunchKernelGGL(adj_tape, dim3(tiles, chunks), dim3(256), 0, st, g, s, tape, rays);
+    if (chunks > 1) {   // the chunks merge their spans into a cleared record
+        const hipError_t e = zero_async((float *)span, 2 * (size_t)npix, st);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(adj_tape, dim3(tiles, chunks), dim3(256), 0, st, g, s, tape, rays, span);
     return hipGetLastError();
 }
 
@@ -522,26 +538,26 @@ static hipError_t launch_march_t(int nsamp, int npix, int plane, const Channels 
 
 template <int CB, int G, bool CUBE>
 static hipError_t launch_tau_t(int nsamp, int npix, int plane, const Channels &ch, float shift, const float4 *tape,
-                               const float4 *rays, const float *dl, const float *target, float4 *cot, float *cube_out,
+                               const int2 *span, const float *dl, const float *target, float4 *cot, float *cube_out,
                                hipStream_t st) {
     const int nblk = (ch.n + G * CB - 1) / (G * CB);
     const long tiles = (npix + 256 / G - 1) / (256 / G);
     const long ids = (tiles + 7) / 8 * 8 * nblk;
     hipLaunchKernelGGL((adj_march_tau<CB, G, CUBE>), dim3((unsigned)ids), dim3(256), 0, st, nsamp, npix, plane, nblk,
-                       ch, shift, tape, rays, dl, target, cot, cube_out);
+                       ch, shift, tape, span, dl, target, cot, cube_out);
     return hipGetLastError();
 }
 
 hipError_t launch_adj_march(int cb, int kseg, int lanes, int nsamp, int npix, int plane, const Channels &ch,
-                            float shift, const float4 *tape, const float4 *rays, const float *dl,
+                            float shift, const float4 *tape, const int2 *span, const float *dl,
                             const float *target, float *ckpt,
                             float4 *cot, float *cube_out, hipStream_t st) {
     if (kseg == 0) {
         const bool cube = target || cube_out;
 #define RT_TAU_CASE(C, G)                                                                                         \
     if (cb == C && lanes == G)                                                                                   \
-        return cube ? launch_tau_t<C, G, true>(nsamp, npix, plane, ch, shift, tape, rays, dl, target, cot, cube_out, st) \
-                    : launch_tau_t<C, G, false>(nsamp, npix, plane, ch, shift, tape, rays, dl, target, cot, cube_out, st);
+        return cube ? launch_tau_t<C, G, true>(nsamp, npix, plane, ch, shift, tape, span, dl, target, cot, cube_out, st) \
+                    : launch_tau_t<C, G, false>(nsamp, npix, plane, ch, shift, tape, span, dl, target, cot, cube_out, st);
         RT_TAU_CASE(8, 1) RT_TAU_CASE(16, 1) RT_TAU_CASE(24, 1) RT_TAU_CASE(32, 1)
         RT_TAU_CASE(16, 2) RT_TAU_CASE(24, 2) RT_TAU_CASE(25, 2) RT_TAU_CASE(32, 2)
         RT_TAU_CASE(12, 4) RT_TAU_CASE(16, 4)
@@ -558,17 +574,17 @@ hipError_t launch_adj_march(int cb, int kseg, int lanes, int nsamp, int npix, in
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_adj_chain(const Geometry &g, const Shade &s, const float4 *rays, const float4 *cot, int nblk,
-                            const GradAcc &go, float4 *dO, hipStream_t st) {
+hipError_t launch_adj_chain(const Geometry &g, const Shade &s, const float4 *rays, const int2 *span, const float4 *cot,
+                            int nblk, const GradAcc &go, float4 *dO, hipStream_t st) {
     const size_t total = (size_t)g.nsamp * g.nx * g.ny;
     const int lds_surf = (s.nr <= 2048) ? 1 : 0;
     const size_t shmem = lds_surf ? sizeof(float) * 2 * s.nr : 0;
     if (grad_accum_double())
         hipLaunchKernelGGL(adj_chain<double>, dim3((unsigned)((total + 255) / 256)), dim3(256), shmem, st, g, s, rays,
-                           cot, nblk, go, lds_surf, dO);
+                           span, cot, nblk, go, lds_surf, dO);
     else
         hipLaunchKernelGGL(adj_chain<float>, dim3((unsigned)((total + 255) / 256)), dim3(256), shmem, st, g, s, rays,
-                           cot, nblk, go, lds_surf, dO);
+                           span, cot, nblk, go, lds_surf, dO);
     return hipGetLastError();
 }
 

@@ -9,13 +9,19 @@ namespace rt {
 // Pass A for one pixel: its ray set-up (to rays[pix] when write_ray) and the
 // channel-independent quantities (S, K, a, b) of samples [k0, k1) to the
 // sample-major tape [nsamp][npix].
+// span[pix] (when given) records the ray's samples with K > 0 as
+// (nsamp - first, last + 1), zero when there are none: written whole when one
+// chunk holds all the samples (shared = false), otherwise merged with atomic
+// maxima into a span cleared beforehand.
 __device__ __forceinline__ void tape_pixel(const Geometry &g, const Shade &s, const float4 *ztab, int pix, int k0,
                                            int k1, bool write_ray, float4 *__restrict__ tape,
-                                           float4 *__restrict__ rays) {
+                                           float4 *__restrict__ rays, int2 *__restrict__ span = nullptr,
+                                           bool shared = false) {
     const int npix = g.nx * g.ny;
     const RaySetup r = ray_setup(g, pix % g.nx, pix / g.nx);
     if (write_ray) rays[pix] = make_float4(r.px, r.pmy, r.pmz, r.live ? r.ds : 0.0f);
     const float half = 0.5f * (float)g.nsamp;
+    int kf = g.nsamp, kl = -1;
     for (int k = k0; k < k1; ++k) {
         float4 o = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         if (r.live) {
@@ -25,10 +31,38 @@ __device__ __forceinline__ void tape_pixel(const Geometry &g, const Shade &s, co
                                       : shade_sample<false>(s, ztab, r.px, fmaf(t, r.wy, r.pmy), fmaf(t, r.wz, r.pmz),
                                                             r.ds, 0);
             o = make_float4(q.S, q.K, q.a, q.b);
+            if (q.K > 0.0f) {
+                kf = min(kf, k);
+                kl = k;
+            }
         }
         tape[(size_t)k * npix + pix] = o;
     }
+    if (span) {
+        if (!shared) {
+            span[pix] = make_int2(g.nsamp - kf, kl + 1);
+        } else if (kl >= 0) {
+            atomicMax(&span[pix].x, g.nsamp - kf);
+            atomicMax(&span[pix].y, kl + 1);
+        }
+    }
 }
+
+// Largest v (0 <= v < 2^21) over the wave's active lanes, one bit at a time
+// from the top: a ballot counts only active lanes, so lanes that have left
+// (or never held a pixel) take no part.  Wave-uniform; needs one active lane.
+__device__ __forceinline__ int active_max(int v) {
+    int r = 0;
+#pragma unroll
+    for (int b = 20; b >= 0; --b) {
+        const int c = r | (1 << b);
+        if (__ballot(v >= c) != 0) r = c;
+    }
+    return r;
+}
+
+// (first, last) sample with K > 0 from a span record; first > last when none
+__device__ __forceinline__ int2 span_of(int2 sp, int nsamp) { return make_int2(nsamp - sp.x, sp.y - 1); }
 
 // value of the other lane of an adjacent pair (DPP quad permutation 1,0,3,2)
 __device__ __forceinline__ float swap_pair(float x) {
@@ -47,16 +81,21 @@ __device__ __forceinline__ float swap_half_quad(float x) {
 // the lane then folds vsh into a (d_c = (a - vsh b) - vel(c) b) and the
 // derivative in b takes -vsh times the one in a.  With CUBE the march forms
 // the intensity, and with target != NULL dL/dI = 2 (I - D) from it;
-// otherwise dL/dI is read from dl_dcube.  A pixel whose ray misses the grid
-// (live false: its ray record has ds = 0) has zero intensity and no
-// samples: it only clears its channels of the cube, and its cotangents are
-// left unwritten, since every chain pass skips rays with ds = 0.
-template <int CB, int G, bool CUBE, bool SHIFT = false, class Vel>
+// otherwise dL/dI is read from dl_dcube.  Only the samples with K > 0 (one
+// run along the ray) change anything: outside it x = 0 in every channel.
+// With SPAN the run comes from the tape's span record (kspan = (first,
+// last)): both sweeps cover it alone and the cotangents outside it are left
+// unwritten, since the chain passes read the same record; without, sweep 1
+// finds it and the cotangents outside are written as zeros.  A pixel whose
+// ray misses the grid (live false) has zero intensity: it only clears its
+// channels of the cube and leaves its cotangents unwritten (every chain pass
+// skips rays with ds = 0).
+template <int CB, int G, bool CUBE, bool SHIFT = false, bool SPAN = false, class Vel>
 __device__ __forceinline__ void march_tau_pixel(int pix, int blk, int g, int c0, int nch, int nsamp, int npix,
                                                 int plane, bool live, Vel vel, const float4 *__restrict__ tape,
                                                 const float *__restrict__ dl_dcube, const float *__restrict__ target,
                                                 float4 *__restrict__ cot, float *__restrict__ cube_out,
-                                                float vsh = 0.0f) {
+                                                float vsh = 0.0f, int2 kspan = make_int2(0, -1)) {
     if (!live) {
         if (CUBE && cube_out) {
 #pragma unroll
@@ -66,10 +105,15 @@ __device__ __forceinline__ void march_tau_pixel(int pix, int blk, int g, int c0,
         return;
     }
     float th[CB], tl[CB], w[CB];
-    // the samples with K > 0 (one run along the ray): those outside [kf, kl]
-    // add nothing (their x is 0 in every channel), so sweep 2 leaves them out
-    // and their cotangents are zero
     int kf = nsamp, kl = -1;
+    if constexpr (SPAN) {
+        // the union of the spans of the wave's live pixels (the lanes still
+        // active here): a wave-uniform range, so both sweeps are scalar
+        // loops; a lane's samples outside its own span in it have x = 0 and
+        // change nothing
+        kf = __builtin_amdgcn_readfirstlane(nsamp - active_max(nsamp - kspan.x));
+        kl = __builtin_amdgcn_readfirstlane(active_max(kspan.y + 1) - 1);
+    }
     {
         // sweep 1, back to front: total depth and (CUBE) J, which reaches I
         float J[CB];
@@ -79,13 +123,17 @@ __device__ __forceinline__ void march_tau_pixel(int pix, int blk, int g, int c0,
             tl[c] = 0.0f;
             J[c] = 0.0f;
         }
-        // the next sample's tape entry is loaded one iteration ahead
-        float4 qn = tape[(size_t)(nsamp - 1) * npix + pix];
+        // the next sample's tape entry is loaded one iteration ahead.  With
+        // SPAN the loop starts at kl and skips the samples in front of kf
+        // (a bound of kf itself makes the compiler spill)
+        const int k_hi = SPAN ? kl : nsamp - 1;
+        float4 qn = tape[(size_t)max(k_hi, 0) * npix + pix];
 #pragma unroll 1
-        for (int k = nsamp - 1; k >= 0; --k) {
+        for (int k = k_hi; k >= 0; --k) {
+            if (SPAN && k < kf) continue;
             float4 q = qn;
             qn = tape[(size_t)max(k - 1, 0) * npix + pix];
-            if (q.y > 0.0f) {
+            if (!SPAN && q.y > 0.0f) {
                 kf = k;
                 kl = max(kl, k);
             }
@@ -135,7 +183,7 @@ __device__ __forceinline__ void march_tau_pixel(int pix, int blk, int g, int c0,
         J[c] = 0.0f;
         u[c] = w[c] * fexp2(sh[c] + sl[c]);
     }
-    if (g == 0) {
+    if (!SPAN && g == 0) {
         const float4 z = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         for (int k = nsamp - 1; k > kl; --k) cot[((size_t)blk * nsamp + k) * npix + pix] = z;
         if (kl >= 0)

@@ -63,8 +63,8 @@ size_t adjoint_bytes_per_pixel(int nch, long npix, int nsamp, bool cube) {
     adjoint_shape(std::min(nch, kLaunchChannels), npix, cube, &cb, &lanes, &kseg);
     const size_t ch = std::min(nch, kLaunchChannels), nblk = (ch + lanes * cb - 1) / (lanes * cb);
     const size_t nseg = kseg ? ((size_t)nsamp + kseg - 1) / kseg : 0;
-    // tape, ray set-up, transmission checkpoints, per-block cotangents
-    return 16 * (size_t)nsamp + 16 + 4 * nseg * nblk * cb + 16 * nblk * (size_t)nsamp;
+    // tape, ray set-up, span, transmission checkpoints, per-block cotangents
+    return 16 * (size_t)nsamp + 16 + 8 + 4 * nseg * nblk * cb + 16 * nblk * (size_t)nsamp;
 }
 
 
@@ -156,24 +156,26 @@ rt_status adjoint_core(const rt_problem *p, const float *dl, const rt_grads *g, 
             sb.o_pix0 = (int64_t)pix0;
             const size_t tape_b = sizeof(float4) * (size_t)ns * bpix;
             const size_t rays_b = sizeof(float4) * (size_t)bpix;
+            const size_t span_b = sizeof(int2) * (size_t)bpix;
             const size_t ckpt_b = sizeof(float) * (size_t)nseg * nblk * cb * bpix;
             const size_t cot_b = sizeof(float4) * (size_t)nblk * ns * bpix;
             char *base = fx ? fx->base + fixed_table_bytes() + fixed_acc_bytes(p)
-                            : (char *)stream_workspace(st, kWsAdjoint, tape_b + rays_b + ckpt_b + cot_b, &e);
+                            : (char *)stream_workspace(st, kWsAdjoint, tape_b + rays_b + ckpt_b + cot_b + span_b, &e);
             if (!base) return fail_hip(e, "adjoint scratch");
             float4 *tape = (float4 *)base;
             float4 *rays = (float4 *)(base + tape_b);
             float *ckpt = (float *)(base + tape_b + rays_b);
             float4 *cot = (float4 *)(base + tape_b + rays_b + ckpt_b);
-            if ((e = launch_adj_tape(gb, sb, tape, rays, st)) != hipSuccess) return fail_hip(e, "adjoint tape");
+            int2 *span = (int2 *)(base + tape_b + rays_b + ckpt_b + cot_b);   // last: 8-byte records
+            if ((e = launch_adj_tape(gb, sb, tape, rays, span, st)) != hipSuccess) return fail_hip(e, "adjoint tape");
             const size_t off = (size_t)c0 * plane + pix0;
-            if ((e = launch_adj_march(cb_l, kseg, lanes_l, ns, bpix, (int)plane, ch, (float)shift, tape, rays,
+            if ((e = launch_adj_march(cb_l, kseg, lanes_l, ns, bpix, (int)plane, ch, (float)shift, tape, span,
                                       dl ? dl + off : nullptr, target ? target + off : nullptr, ckpt, cot,
                                       cube_opt ? cube_opt + off : nullptr, st)) != hipSuccess)
                 return fail_hip(e, "adjoint march");
             float4 *dOc = c0 == 0 ? dO : nullptr;
-            e = lds ? launch_adj_chain_lds(gb, sb, rays, cot, nblk, go, dOc, st)
-                    : launch_adj_chain(gb, sb, rays, cot, nblk, go, dOc, st);
+            e = lds ? launch_adj_chain_lds(gb, sb, rays, span, cot, nblk, go, dOc, st)
+                    : launch_adj_chain(gb, sb, rays, span, cot, nblk, go, dOc, st);
             if (e != hipSuccess) return fail_hip(e, "adjoint chain");
         }
     }
