@@ -85,11 +85,17 @@ def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def algorithmic(nch: int, cb: int, thin: float = 0.0):
-    """(FLOP per ray-sample, issue slots per ray-sample) of the dense march,
-    with a share `thin` of the pixel-samples on the series form."""
-    flop = (1.0 - thin) * LOOP_FLOP + thin * THIN_FLOP + SHADE_FLOP / cb
-    slots = ((1.0 - thin) * (LOOP_VALU + TRANS_SLOTS * LOOP_TRANS) + thin * (THIN_VALU + TRANS_SLOTS * THIN_TRANS) +
+def algorithmic(nch: int, cb: int, thin: float = 0.0, emit: float = 1.0):
+    """(FLOP per ray-sample, issue slots per ray-sample) of the march: the
+    shading of every pixel-sample (shared by the cb channels that use it)
+    and the channel loop on the share `emit` of the pixel-samples with any
+    opacity, `thin` of those on the series form.  A sample with K = 0
+    changes no channel: the march skips its channel loop wherever no ray of
+    the wave has opacity at that sample, so only the samples with opacity
+    are counted as loop work (a lower bound on what the lanes execute)."""
+    flop = emit * ((1.0 - thin) * LOOP_FLOP + thin * THIN_FLOP) + SHADE_FLOP / cb
+    slots = (emit * ((1.0 - thin) * (LOOP_VALU + TRANS_SLOTS * LOOP_TRANS) +
+                     thin * (THIN_VALU + TRANS_SLOTS * THIN_TRANS)) +
              (SHADE_VALU + TRANS_SLOTS * SHADE_TRANS) / cb)
     return flop, slots
 
@@ -287,13 +293,20 @@ def main():
         cen = sc_sd.census()
         wall_ms, kern_ms_sd = time_forward(rt, sc_sd, cube, args.steps, args.warmup)
         rs_sd = sc_sd.ray_samples
+        # samples with opacity; those without count as thin in the census
+        n_all, n_em = cen["pixel_samples"], cen["emitting_pixel_samples"]
+        n_thin_em = cen["thin_pixel_samples"] - (n_all - n_em)
         per_seed[sd] = dict(ray_samples_per_s=rs_sd / (wall_ms * 1e-3), ms_per_step=wall_ms, kernel_ms=kern_ms_sd,
                             ray_samples=rs_sd, live_fraction=cen["rays"] / (sc_sd.nx * sc_sd.ny),
-                            thin_fraction=cen["thin_pixel_samples"] / max(cen["pixel_samples"], 1),
+                            emitting_fraction=n_em / max(n_all, 1),
+                            emitting_ray_samples_per_s=n_em * sc_sd.nch / (wall_ms * 1e-3),
+                            thin_fraction=n_thin_em / max(n_em, 1),
                             incl_deg=prob_sd.camera.incl_deg)
         scenes[sd] = (prob_sd, sc_sd)
         log(f"disk {sd}: {wall_ms:.3f} ms/step (kernel {kern_ms_sd:.3f} ms), "
-            f"{per_seed[sd]['ray_samples_per_s']:.3e} ray-samples/s")
+            f"{per_seed[sd]['ray_samples_per_s']:.3e} ray-samples/s "
+            f"({per_seed[sd]['emitting_fraction']:.3f} of them with opacity: "
+            f"{per_seed[sd]['emitting_ray_samples_per_s']:.3e}/s)")
     rates = np.array([per_seed[sd]["ray_samples_per_s"] for sd in seeds])
     value = float(np.median(rates))
     # the disk at the median (the lower of the two middle ones) carries the roofline
@@ -303,6 +316,7 @@ def main():
     kern_ms = per_seed[med]["kernel_ms"]
     rs = per_seed[med]["ray_samples"]
     thin = per_seed[med]["thin_fraction"]
+    emit = per_seed[med]["emitting_fraction"]
     cb, split = auto_shape(sc.nch, sc.nx * sc.ny, sc.nsamp)
     cb = rt.get_option(L.RT_OPT_CHANNEL_BLOCK) or cb
     split = rt.get_option(L.RT_OPT_RAY_SPLIT) or split
@@ -310,7 +324,7 @@ def main():
     # pixel (uniform channels; 4 lanes unless set)
     group = rt.get_option(L.RT_OPT_FWD_GROUP) or 4
     kname = f"march_fwd_group<{group}>" if cb == 64 and split == 1 and group > 1 else "march_fwd"
-    flop, slots = algorithmic(sc.nch, cb, thin)
+    flop, slots = algorithmic(sc.nch, cb, thin, emit)
     achieved = flop * rs / (kern_ms * 1e-3) / 1e12
     peak = flop / slots * LANE_SLOTS_PER_S / 1e12
     out = {
@@ -334,7 +348,8 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": measured_traffic(med),
                      "kernel": kname, "kernel_ms": kern_ms, "disk": med,
-                     "thin_fraction": thin, "flop_per_ray_sample": flop, "issue_slots_per_ray_sample": slots,
+                     "emitting_fraction": emit, "thin_fraction_of_emitting": thin,
+                     "flop_per_ray_sample": flop, "issue_slots_per_ray_sample": slots,
                      "hbm_bytes_algorithmic": 4 * sc.nch * sc.nx * sc.ny + 4 * (3 * sc.nr * sc.nz + 2 * sc.nr)},
         "disks": {str(sd): v for sd, v in per_seed.items()},
     }
@@ -345,7 +360,8 @@ def main():
         # the march's measured mix: the channel loop at its measured rates
         # (thin share on the series form) plus the shading's issue slots
         sh = (SHADE_VALU + TRANS_SLOTS * SHADE_TRANS) / cb / LANE_SLOTS_PER_S
-        t_rs = (1.0 - thin) / mr["loop_thick_ray_samples_per_s"] + thin / mr["loop_thin_ray_samples_per_s"] + sh
+        t_rs = emit * ((1.0 - thin) / mr["loop_thick_ray_samples_per_s"] +
+                       thin / mr["loop_thin_ray_samples_per_s"]) + sh
         mr["mix_roof_ray_samples_per_s"] = 1.0 / t_rs
         out["roofline"]["frac_of_measured_mix"] = (rs / (kern_ms * 1e-3)) * t_rs
     out["micro"] = mr

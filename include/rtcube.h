@@ -193,9 +193,11 @@ uint64_t rt_noalloc_scratch_bytes(void);
  * counts[0] = rays that cross the cylinder (the others have no samples, zero
  * intensity and no work), counts[1] = their pixel-samples, counts[2] = those
  * pixel-samples whose line-centre depth is below the march's thin-sample
- * threshold (taken with the series form of 1 - e^-dtau), or -1 for a problem
- * with the network (its shading needs the network's outputs).  counts: [host]
- * int64[3].  mask (device, [ny][nx] bytes, may be NULL) receives 1 for each
+ * threshold (taken with the series form of 1 - e^-dtau), counts[3] = those
+ * with any opacity (K > 0; a sample with K = 0 changes no channel), the last
+ * two -1 for a problem with the network (its shading needs the network's
+ * outputs).  counts: [host] int64[4].  mask (device, [ny][nx] bytes, may be
+ * NULL) receives 1 for each
  * crossing ray, 0 otherwise.  The march's own ray set-up and shading are
  * used.  Synchronous: returns after the stream's work is done. */
 rt_status rt_render_census(const rt_problem *p, uint8_t *mask, int64_t *counts, void *stream);

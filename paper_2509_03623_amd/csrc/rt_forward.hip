@@ -7,7 +7,10 @@
 // fetch, density, CO mask, LTE populations, source function, line width,
 // projected velocity) and then runs the channel loop entirely in registers:
 // profile, optical depth, front-to-back accumulation of I and transmission.
-// Nothing is skipped: every (pixel, channel, sample) is evaluated.
+// Every sample of a ray is shaded; a sample with no opacity (K = 0: outside
+// the CO layer or the grid) changes no channel, so a wave skips the channel
+// loop of a sample where none of its rays has opacity there (a ballot over
+// the lanes marching).  The cube is the same either way.
 #include <type_traits>
 
 #include "rt_kernels.h"
@@ -47,6 +50,7 @@ __global__ __launch_bounds__(256) void march_fwd(Geometry g, Shade s, Channels c
             const float t = ((float)k + 0.5f - half) * r.ds;
             const SampleQ sq = shade_sample<NEURAL>(s, ztab, r.px, fmaf(t, r.wy, r.pmy), fmaf(t, r.wz, r.pmz), r.ds,
                                             o_index(s, k, q * g.nx + p));
+            if (__ballot(sq.K > 0.0f) == 0) continue;
             march_sample<CB, THIN>(I, Tr, sq, [&](int c) { return ch.v[c0 + c]; });
         }
     }
@@ -126,7 +130,10 @@ __global__ __launch_bounds__(256) void march_fwd_group(Geometry g, Shade s, Chan
                 const float b = group_lane<G, J>(own.b);
                 const float a = fmaf(-vsh, b, group_lane<G, J>(own.a));
                 const bool thin = group_lane<G, J>(own_thin) != 0.0f;
-                if (J == 0 || k + J < g.nsamp) march_lk<CB, THIN>(I, Tr, S, lK, a, b, thin, vel);
+                // the wave skips the step when none of its rays has opacity
+                // at it (a ballot counts only the lanes marching)
+                const bool any = __ballot(lK > -__builtin_huge_valf()) != 0;
+                if (any && (J == 0 || k + J < g.nsamp)) march_lk<CB, THIN>(I, Tr, S, lK, a, b, thin, vel);
             };
             step(std::integral_constant<int, 0>{});
             step(std::integral_constant<int, 1>{});

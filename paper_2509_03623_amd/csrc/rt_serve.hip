@@ -69,6 +69,8 @@ __global__ __launch_bounds__(256) void serve_fwd(const ServeDesc *__restrict__ d
                 const float t = ((float)k + 0.5f - half) * r.ds;
                 const SampleQ sq = shade_sample<false>(D.s, ztab, r.px, fmaf(t, r.wy, r.pmy),
                                                        fmaf(t, r.wz, r.pmz), r.ds, 0);
+                // no ray of the wave with opacity at this sample: no channel changes
+                if (__ballot(sq.K > 0.0f) == 0) continue;
                 march_sample<kServeCB, true>(I, Tr, sq, [&](int c) { return vc[c]; });
             }
         }

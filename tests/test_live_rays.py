@@ -54,8 +54,10 @@ def test_thin_sample_count_on_slabs(x_co):
     either 0 (outside the layer, or beyond the grid's top z/r row near the
     axis) or far from the threshold: the census's thin count equals the
     number of samples whose depth in the oracle's central channel (v_los = 0
-    face-on) is below 1/32 in natural units, and with a negligible abundance
-    every sample is thin."""
+    face-on) is below 1/32 in natural units, its count of samples with any
+    opacity the number whose depth there is not vanishing (the FP64 oracle
+    also keeps a few below 1e-45, which FP32 holds as 0), and with a
+    negligible abundance every sample is thin."""
     import paper_2509_03623_amd as rt
     prob = synth.slab_problem(nsamp=128, m=24, x_co=x_co, nx=8, ny=8, nch=3)
     sc = rt.scene_from_problem(prob)
@@ -64,13 +66,24 @@ def test_thin_sample_count_on_slabs(x_co):
     rays = int(got["mask"].sum())
     assert rays > 0 and got["pixel_samples"] == rays * prob.nsamp
     want = 0
+    depths = []
     for q in range(prob.camera.ny):
         for p in range(prob.camera.nx):
             _, _, dt, ch = oracle.ray_dump(prob, p, q)
             if ch[2] > 0.0:
                 want += int((dt[:, 1] < 1.0 / 32.0).sum())
-    print(f"thin pixel-samples: census {got['thin_pixel_samples']}, oracle {want} of {got['pixel_samples']}")
+                depths.append(dt[:, 1])
+    depths = np.concatenate(depths)
+    emit = int((depths > 1e-30 * depths.max()).sum())
+    print(f"thin pixel-samples: census {got['thin_pixel_samples']}, oracle {want} of {got['pixel_samples']}; "
+          f"with opacity: census {got['emitting_pixel_samples']}, oracle {emit}")
     assert got["thin_pixel_samples"] == want
+    # with opacity: the depths split into those the FP32 march holds (here
+    # above 1e-10 in natural units) and a handful of vanishing ones (below
+    # 1e-45, zero in FP32, some even in FP64), so the count above 1e-30 of
+    # the largest is the march's count of samples with K > 0
+    assert depths[(depths > 0.0) & (depths <= 1e-30 * depths.max())].max(initial=0.0) < 1e-40
+    assert got["emitting_pixel_samples"] == emit
     if x_co < 1e-10:
         assert want == got["pixel_samples"]
     else:
