@@ -54,15 +54,15 @@ SHADE3_SLOTS = 307 + 4 * 16
 # HBM traffic of one forward launch on the full-size render of each disk,
 # from two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch)
 # of `bench.py --copy-probe`, each scaled by what the same counter reads for
-# a 1 GiB device-to-device copy (FETCH_SIZE 524 305 KiB -> x2.0000,
+# a 1 GiB device-to-device copy (FETCH_SIZE 524 303 KiB -> x2.0000,
 # WRITE_SIZE 1 048 576 KiB -> x1.0000).  Valid only for the kernel sources it
 # was taken on: the hash of those files is checked at run time.
 FWD_TRAFFIC = {"sources": ("paper_2509_03623_amd/csrc/rt_forward.hip", "paper_2509_03623_amd/csrc/rt_kernels.h",
                            "paper_2509_03623_amd/csrc/rt_launch.h"),
-               "sha256": "f3b9cbc5dae572afd12397a5e7b323944f13fe9b94cc9193eddf1e71e80161ae",
-               "fetch_scale": 1048576 / 524304.7, "write_scale": 1.0,
+               "sha256": "39b6c0f087aac249e1b65d69be3d4fdd5662f034d1f873041a50ba375a21034d",
+               "fetch_scale": 1048576 / 524303.5, "write_scale": 1.0,
                # seed -> (FETCH_SIZE KiB, WRITE_SIZE KiB), mean of three launches each
-               "disks": {2000: (1089.4, 65536.0), 2001: (1265.2, 65536.0), 2002: (1251.1, 65536.0), 2003: (1213.1, 65536.0), 2004: (1227.3, 65536.0), 2005: (1182.1, 65536.0), 2006: (1179.4, 65536.0), 2007: (1198.4, 65536.0)}}
+               "disks": {2000: (1264.6, 65536.0), 2001: (1222.6, 65536.0), 2002: (1274.8, 65536.0), 2003: (1255.5, 65536.0), 2004: (1255.7, 65536.0), 2005: (1233.8, 65536.0), 2006: (1218.5, 65536.0), 2007: (1245.9, 65536.0)}}
 
 
 def measured_traffic(seed: int):
