@@ -35,6 +35,7 @@
 #include <algorithm>
 #include <cmath>
 
+#include "rt_adjoint.h"
 #include "rt_mlp.h"
 
 namespace rt {
@@ -495,8 +496,29 @@ __device__ __forceinline__ void br_stage(__bf16 *dst, const gbf16 *src, int n, i
     __builtin_amdgcn_s_waitcnt(0);
 }
 
+// The passes whose points have any dL/do != 0, for mlp_bwd_rr: one wave per
+// pass of kBrPts points votes by ballot and appends the pass's index to
+// list[1 ...], list[0] counting them (cleared beforehand).  dL/do = 0 at a
+// point (no opacity there) makes every layer's dL/dz' zero, so a pass whose
+// points all have it adds nothing to any gradient; the points of a pass are
+// adjacent pixels at one sample depth, so whole passes lie outside the CO
+// layer together.
+__global__ __launch_bounds__(256) void mlp_live_passes(const float4 *__restrict__ dO, size_t M,
+                                                       uint32_t *__restrict__ list) {
+    static_assert(kBrPts == 64, "one wave per pass");
+    const size_t pass = (size_t)blockIdx.x * 4 + threadIdx.x / 64;
+    const size_t m = pass * kBrPts + (threadIdx.x & 63);
+    bool nz = false;
+    if (m < M) {
+        const float4 d = dO[m];
+        nz = d.x != 0.0f || d.y != 0.0f || d.z != 0.0f;
+    }
+    if (__ballot(nz) != 0 && (threadIdx.x & 63) == 0) list[1 + atomicAdd(list, 1u)] = (uint32_t)pass;
+}
+
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void mlp_bwd_rr(
-    Geometry g, Shade s, MlpDev w, size_t M, const float4 *__restrict__ dO, float *__restrict__ dW) {
+    Geometry g, Shade s, MlpDev w, size_t M, const float4 *__restrict__ dO, const uint32_t *__restrict__ list,
+    float *__restrict__ dW) {
     typedef MM<__bf16> mm;
     __shared__ __attribute__((aligned(16))) __bf16 XD[kW * kBrStride];   // dL/dz' (or dL/do) rows x points
     __shared__ __attribute__((aligned(16))) __bf16 XH[kW * kBrStride];   // h' (or features) rows x points
@@ -524,7 +546,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     const int brow = 32 * wv + (lane >> 1), bhalf = lane & 1;     // bias row of this lane
     const int col = 16 * wv + lc;                                 // this lane's point within the pass
     __syncthreads();
-    for (size_t base = (size_t)blockIdx.x * kBrPts; base < M; base += (size_t)gridDim.x * kBrPts) {
+    const uint32_t npass = list[0];
+    for (uint32_t ip = blockIdx.x; ip < npass; ip += gridDim.x) {
+        const size_t base = (size_t)list[1 + ip] * kBrPts;
         // the weight operands are the same every pass: hide that from the
         // compiler, or it keeps all 208 fragments in registers across passes
         uint64_t wr_u = (uint64_t)w.Wr, wrt_u = (uint64_t)w.WrT;
@@ -913,16 +937,20 @@ hipError_t mlp_forward(const Geometry &g, const Shade &s, const MlpDev &w, int p
     return hipGetLastError();
 }
 
+size_t mlp_backward_list_bytes(size_t M) { return sizeof(uint32_t) * (1 + (M + kBrPts - 1) / kBrPts); }
+
 hipError_t mlp_backward(const Geometry &g, const Shade &s, const MlpDev &w, int precision, size_t M,
-                        const float4 *dO, float *dW, hipStream_t st) {
+                        const float4 *dO, uint32_t *list, float *dW, hipStream_t st) {
     int dev = 0, ncu = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return e;
     if (precision == RT_MLP_BF16) {
         const size_t passes = (M + kBrPts - 1) / kBrPts;
+        if ((e = zero_async((float *)list, 1, st)) != hipSuccess) return e;
+        hipLaunchKernelGGL(mlp_live_passes, dim3((unsigned)((passes + 3) / 4)), dim3(256), 0, st, dO, M, list);
         const unsigned grid = (unsigned)std::min<size_t>(passes, (size_t)ncu);
-        hipLaunchKernelGGL(mlp_bwd_rr, dim3(grid), dim3(256), 0, st, g, s, w, M, dO, dW);
+        hipLaunchKernelGGL(mlp_bwd_rr, dim3(grid), dim3(256), 0, st, g, s, w, M, dO, list, dW);
     } else {
         constexpr int P = 16;
         const size_t ntiles = (M + P - 1) / P;

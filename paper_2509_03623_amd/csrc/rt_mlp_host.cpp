@@ -26,8 +26,10 @@ static rt_status mlp_setup(const rt_problem *p, Geometry *geo, Shade *sh, MlpDev
     const size_t M = (size_t)p->cam.nx * p->cam.ny * p->nsamp;
     const size_t prep = (mlp_prep_bytes(prec) + 255) / 256 * 256;
     const size_t ob = sizeof(float4) * M;
+    // with the per-point extra (the backward's dL/do) comes the backward's pass list
+    const size_t list_b = extra ? mlp_backward_list_bytes(M) : 0;
     ws->st = st;
-    hipError_t e = hipMallocAsync(&ws->p, prep + ob + extra_point_bytes * M, st);
+    hipError_t e = hipMallocAsync(&ws->p, prep + ob + extra_point_bytes * M + list_b, st);
     if (e != hipSuccess) { ws->p = nullptr; return fail_hip(e, "network scratch"); }
     *out = (float4 *)((char *)ws->p + prep);
     if (extra) *extra = (char *)ws->p + prep + ob;
@@ -62,11 +64,12 @@ rt_status adjoint_mlp(const rt_problem *p, const float *dl, const rt_grads *g, f
     if (rs != RT_OK) return rs;
     rs = adjoint_core(p, dl, g, cube_opt, st, o, (float4 *)dO, target);
     if (rs != RT_OK) return rs;
+    const size_t M = (size_t)p->cam.nx * p->cam.ny * p->nsamp;
     if (g->d_mlp) {
         hipError_t e = zero_async(g->d_mlp, RT_MLP_PARAMS, st);
         if (e == hipSuccess)
-            e = mlp_backward(geo, sh, w, p->mlp->precision, (size_t)p->cam.nx * p->cam.ny * p->nsamp,
-                             (const float4 *)dO, g->d_mlp, st);
+            e = mlp_backward(geo, sh, w, p->mlp->precision, M, (const float4 *)dO,
+                             (uint32_t *)((float4 *)dO + M), g->d_mlp, st);
         if (e != hipSuccess) return fail_hip(e, "network backward");
     }
     return RT_OK;
