@@ -85,18 +85,20 @@ def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def algorithmic(nch: int, cb: int, thin: float = 0.0, emit: float = 1.0):
+def algorithmic(nch: int, cb: int, thin: float = 0.0, emit: float = 1.0, shaded: float = 1.0):
     """(FLOP per ray-sample, issue slots per ray-sample) of the march: the
-    shading of every pixel-sample (shared by the cb channels that use it)
-    and the channel loop on the share `emit` of the pixel-samples with any
-    opacity, `thin` of those on the series form.  A sample with K = 0
-    changes no channel: the march skips its channel loop wherever no ray of
-    the wave has opacity at that sample, so only the samples with opacity
-    are counted as loop work (a lower bound on what the lanes execute)."""
-    flop = emit * ((1.0 - thin) * LOOP_FLOP + thin * THIN_FLOP) + SHADE_FLOP / cb
+    shading of the share `shaded` of the pixel-samples inside the grid's
+    edge taper (shared by the cb channels that use it; the others stop
+    after locating the sample, not counted) and the channel loop on the
+    share `emit` with any opacity, `thin` of those on the series form.  A
+    sample with K = 0 changes no channel: the march skips its channel loop
+    wherever no ray of the wave has opacity at that sample, so only the
+    samples with opacity are counted as loop work (a lower bound on what the
+    lanes execute)."""
+    flop = emit * ((1.0 - thin) * LOOP_FLOP + thin * THIN_FLOP) + shaded * SHADE_FLOP / cb
     slots = (emit * ((1.0 - thin) * (LOOP_VALU + TRANS_SLOTS * LOOP_TRANS) +
                      thin * (THIN_VALU + TRANS_SLOTS * THIN_TRANS)) +
-             (SHADE_VALU + TRANS_SLOTS * SHADE_TRANS) / cb)
+             shaded * (SHADE_VALU + TRANS_SLOTS * SHADE_TRANS) / cb)
     return flop, slots
 
 
@@ -299,6 +301,7 @@ def main():
         per_seed[sd] = dict(ray_samples_per_s=rs_sd / (wall_ms * 1e-3), ms_per_step=wall_ms, kernel_ms=kern_ms_sd,
                             ray_samples=rs_sd, live_fraction=cen["rays"] / (sc_sd.nx * sc_sd.ny),
                             emitting_fraction=n_em / max(n_all, 1),
+                            shaded_fraction=cen["shaded_pixel_samples"] / max(n_all, 1),
                             emitting_ray_samples_per_s=n_em * sc_sd.nch / (wall_ms * 1e-3),
                             thin_fraction=n_thin_em / max(n_em, 1),
                             incl_deg=prob_sd.camera.incl_deg)
@@ -317,6 +320,7 @@ def main():
     rs = per_seed[med]["ray_samples"]
     thin = per_seed[med]["thin_fraction"]
     emit = per_seed[med]["emitting_fraction"]
+    shaded = per_seed[med]["shaded_fraction"]
     cb, split = auto_shape(sc.nch, sc.nx * sc.ny, sc.nsamp)
     cb = rt.get_option(L.RT_OPT_CHANNEL_BLOCK) or cb
     split = rt.get_option(L.RT_OPT_RAY_SPLIT) or split
@@ -324,7 +328,7 @@ def main():
     # pixel (uniform channels; 4 lanes unless set)
     group = rt.get_option(L.RT_OPT_FWD_GROUP) or 4
     kname = f"march_fwd_group<{group}>" if cb == 64 and split == 1 and group > 1 else "march_fwd"
-    flop, slots = algorithmic(sc.nch, cb, thin, emit)
+    flop, slots = algorithmic(sc.nch, cb, thin, emit, shaded)
     achieved = flop * rs / (kern_ms * 1e-3) / 1e12
     peak = flop / slots * LANE_SLOTS_PER_S / 1e12
     out = {
@@ -348,7 +352,7 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": measured_traffic(med),
                      "kernel": kname, "kernel_ms": kern_ms, "disk": med,
-                     "emitting_fraction": emit, "thin_fraction_of_emitting": thin,
+                     "emitting_fraction": emit, "thin_fraction_of_emitting": thin, "shaded_fraction": shaded,
                      "flop_per_ray_sample": flop, "issue_slots_per_ray_sample": slots,
                      "hbm_bytes_algorithmic": 4 * sc.nch * sc.nx * sc.ny + 4 * (3 * sc.nr * sc.nz + 2 * sc.nr)},
         "disks": {str(sd): v for sd, v in per_seed.items()},
@@ -359,7 +363,7 @@ def main():
     if "loop_thick_ray_samples_per_s" in mr and "loop_thin_ray_samples_per_s" in mr:
         # the march's measured mix: the channel loop at its measured rates
         # (thin share on the series form) plus the shading's issue slots
-        sh = (SHADE_VALU + TRANS_SLOTS * SHADE_TRANS) / cb / LANE_SLOTS_PER_S
+        sh = shaded * (SHADE_VALU + TRANS_SLOTS * SHADE_TRANS) / cb / LANE_SLOTS_PER_S
         t_rs = emit * ((1.0 - thin) / mr["loop_thick_ray_samples_per_s"] +
                        thin / mr["loop_thin_ray_samples_per_s"]) + sh
         mr["mix_roof_ray_samples_per_s"] = 1.0 / t_rs

@@ -194,9 +194,10 @@ uint64_t rt_noalloc_scratch_bytes(void);
  * intensity and no work), counts[1] = their pixel-samples, counts[2] = those
  * pixel-samples whose line-centre depth is below the march's thin-sample
  * threshold (taken with the series form of 1 - e^-dtau), counts[3] = those
- * with any opacity (K > 0; a sample with K = 0 changes no channel), the last
- * two -1 for a problem with the network (its shading needs the network's
- * outputs).  counts: [host] int64[4].  mask (device, [ny][nx] bytes, may be
+ * with any opacity (K > 0; a sample with K = 0 changes no channel), counts[4]
+ * = those inside the grid's edge taper (the march shades only these in
+ * full), the last three -1 for a problem with the network (its shading
+ * needs the network's outputs).  counts: [host] int64[5].  mask (device, [ny][nx] bytes, may be
  * NULL) receives 1 for each
  * crossing ray, 0 otherwise.  The march's own ray set-up and shading are
  * used.  Synchronous: returns after the stream's work is done. */

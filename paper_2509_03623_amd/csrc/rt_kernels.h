@@ -350,6 +350,14 @@ template <bool NEURAL>
 __device__ __forceinline__ SampleQ shade_sample(const Shade &s, const float4 *tab, float px, float py, float pz,
                                                 float ds, size_t m) {
     const Locus L = locate(s, px, py, pz);
+    // beyond the grid's edge taper (inside the bounding cylinder but above
+    // the top z/r row, inside the inner radius or outside the outer one) the
+    // density, and with it K, is exactly 0: no fetch, no physics
+    if (L.taper <= 0.0f) {
+        SampleQ z;
+        z.S = 0.0f; z.K = 0.0f; z.a = 0.0f; z.b = 0.0f;
+        return z;
+    }
     Fields F = fetch(s, L);
     if (NEURAL) apply_mlp(s, F, L, s.mlp_o[m]);
     return physics<false>(s, tab, L, F, px, ds, nullptr);

@@ -67,16 +67,17 @@ class Scene:
         the [ny, nx] bool mask of rays that cross the grid's bounding
         cylinder (the others have no samples: zero intensity, no work), their
         number, their pixel-samples, how many of those the march takes as
-        optically thin and how many have any opacity (the last two -1 with
-        the network)."""
+        optically thin, how many have any opacity and how many lie inside the
+        grid's edge taper (the last three -1 with the network)."""
         if self._live is None:
             mask = torch.empty(self.ny, self.nx, dtype=torch.uint8, device=self.ln_nh2.device)
-            counts = (C.c_int64 * 4)()
+            counts = (C.c_int64 * 5)()
             p, keep = problem_struct(self)
             L.check(L.lib().rt_render_census(C.byref(p), mask.data_ptr(), counts, C.c_void_p(_stream(stream))))
             object.__setattr__(self, "_live", dict(mask=mask.cpu().numpy().astype(bool), rays=int(counts[0]),
                                                    pixel_samples=int(counts[1]), thin_pixel_samples=int(counts[2]),
-                                                   emitting_pixel_samples=int(counts[3])))
+                                                   emitting_pixel_samples=int(counts[3]),
+                                                   shaded_pixel_samples=int(counts[4])))
         return self._live
 
     def live_mask(self) -> np.ndarray:

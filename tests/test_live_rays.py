@@ -84,6 +84,8 @@ def test_thin_sample_count_on_slabs(x_co):
     # the largest is the march's count of samples with K > 0
     assert depths[(depths > 0.0) & (depths <= 1e-30 * depths.max())].max(initial=0.0) < 1e-40
     assert got["emitting_pixel_samples"] == emit
+    # samples with opacity lie inside the grid's edge taper, which the march shades
+    assert emit <= got["shaded_pixel_samples"] <= got["pixel_samples"]
     if x_co < 1e-10:
         assert want == got["pixel_samples"]
     else:
