@@ -405,10 +405,11 @@ def bench_render3d(rt, dev, args):
     spherical grid of the paper's runtime benchmark, 512 samples per ray:
     256^2 pixels at 20, 64 and 128 channels, and 20 channels at 128^2, 256^2
     and 512^2 pixels.  The node packing (six planes -> interleaved records,
-    once per snapshot) is timed on its own.  Ray-samples count every pixel;
-    live_fraction is the share of rays that cross the bounding sphere (the
-    others do no work)."""
-    import math
+    once per snapshot) is timed on its own.  Ray-samples count the samples of
+    the rays that cross the bounding sphere (live_fraction of them; the
+    others do no work); alu_frac credits the full shading of the samples
+    inside the grid's fade and the channel loop of those with opacity only
+    (the march skips the rest), from the census."""
     import numpy as np
     import torch
     from synth import disk3d as S3
@@ -429,7 +430,6 @@ def bench_render3d(rt, dev, args):
     pack_ms = e0.elapsed_time(e1) / steps
     out = {"grid": "512x96x256", "nsamp": 512, "pack_ms": pack_ms,
            "pack_gb_per_s": (24 + 32) * nodes.numel() / 8 / (pack_ms * 1e-3) / 1e9}
-    rc = grid.r_max_au * math.exp(math.log(grid.r_max_au / grid.r_min_au) / (grid.nr - 1))
     legs = [("256x256x20ch", 256, 20), ("256x256x64ch", 256, 64), ("256x256x128ch", 256, 128),
             ("128x128x20ch", 128, 20), ("512x512x20ch", 512, 20)]
     for name, npx, nch in legs:
@@ -451,15 +451,23 @@ def bench_render3d(rt, dev, args):
         wall = (time.perf_counter() - t0) / steps
         gc.enable()
         kern = e0.elapsed_time(e1) / steps * 1e-3
-        d = sc.fov_au / npx
-        xy = (np.arange(npx) + 0.5 - npx / 2) * d
-        live = float(np.mean(xy[:, None] ** 2 + xy[None, :] ** 2 < rc * rc))
+        cen = sc.census()
+        n_all, n_em, n_in = cen["pixel_samples"], cen["emitting_pixel_samples"], cen["shaded_pixel_samples"]
+        live = cen["rays"] / (npx * npx)
+        # samples without opacity count as thin in the census
+        thin = (cen["thin_pixel_samples"] - (n_all - n_em)) / max(n_em, 1)
         cb, ns = auto_shape3(nch, npx * npx, 512)
         nchb = -(-nch // cb)
-        slots = live * npx * npx * 512 * nchb * (cb * (LOOP_VALU + TRANS_SLOTS * LOOP_TRANS) + SHADE3_SLOTS)
+        loop = ((1.0 - thin) * (LOOP_VALU + TRANS_SLOTS * LOOP_TRANS) +
+                thin * (THIN_VALU + TRANS_SLOTS * THIN_TRANS))
+        # the channel loop of the samples with opacity and the full shading of
+        # those inside the grid's fade, per channel block (the rest skipped)
+        slots = nchb * (n_em * cb * loop + n_in * SHADE3_SLOTS)
         hbm = 24 * grid.nr * grid.nt * grid.nphi + 4 * nch * npx * npx
         out[name] = {"ms": wall * 1e3, "kernel_ms": kern * 1e3, "ray_samples_per_s": sc.ray_samples / wall,
-                     "live_fraction": live, "channel_block": cb, "ray_split": ns,
+                     "live_fraction": live, "emitting_fraction": n_em / max(n_all, 1),
+                     "shaded_fraction": n_in / max(n_all, 1), "thin_fraction_of_emitting": thin,
+                     "channel_block": cb, "ray_split": ns,
                      "alu_frac": slots / LANE_SLOTS_PER_S / kern, "hbm_frac": hbm / kern / 8e12}
         log(f"3-D {name}: {wall * 1e3:.3f} ms, {sc.ray_samples / wall:.3e} ray-samples/s")
     if not args.no_cpu:

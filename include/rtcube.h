@@ -417,7 +417,11 @@ rt_status rt_pack_fields3d(const rt_grid3d *grid, const float *ln_nh2, const flo
 rt_status rt_render_cube_3d(const rt_problem3d *p, float *cube, void *stream);
 /* Work accounting of rt_render_cube_3d, as rt_render_census: counts[0] =
  * rays that cross the bounding sphere, counts[1] = their pixel-samples,
- * counts[2] = -1; mask (device, [ny][nx] bytes, may be NULL).  Synchronous. */
+ * counts[2] = those thin in the march's sense, counts[3] = those with any
+ * opacity, counts[4] = those inside the grid's fade (the march shades only
+ * these in full); counts[2..4] are -1 when p->nodes is NULL or misaligned.
+ * counts: [host] int64[5].  mask (device, [ny][nx] bytes, may be NULL).
+ * Synchronous. */
 rt_status rt_render_census_3d(const rt_problem3d *p, uint8_t *mask, int64_t *counts, void *stream);
 
 /* ---------------------------------------------------------------- beam convolution

@@ -111,6 +111,16 @@ __device__ __forceinline__ SampleQ shade3(const Shade3 &s, const float4 *tab, fl
     const float a1 = fmaf(rho, s.cth_c, -pz * s.sth_c);   // r sin(theta - theta_c)
     const float a2 = fmaf(pz, s.cth_c, rho * s.sth_c);    // r cos(theta - theta_c)
     const float w = fmaf(atan2f(a1, a2), s.inv_dth, s.half_nt1);
+    // fade one cell beyond the node ranges (radially from the cell and its
+    // fraction, exact near both ends); beyond the fade the density and the
+    // depth are exactly 0: no azimuth, no fetch, no physics
+    const float taper = clampf((float)i0 + fr + 1.0f, 0.0f, 1.0f) * clampf((s.fnr - (float)i0) - fr, 0.0f, 1.0f) *
+                        clampf(w + 1.0f, 0.0f, 1.0f) * clampf(s.fnt - w, 0.0f, 1.0f);
+    if (taper <= 0.0f) {
+        SampleQ z;
+        z.S = 0.0f; z.K = 0.0f; z.a = 0.0f; z.b = 0.0f;
+        return z;
+    }
     float sp = atan2f(py, px) * s.inv_dph;
     sp = sp < 0.0f ? sp + s.fnp : sp;
     const float fu = clampf(fr, 0.0f, 1.0f);
@@ -149,10 +159,6 @@ __device__ __forceinline__ SampleQ shade3(const Shade3 &s, const float4 *tab, fl
         vt = fmaf(wt[c], B[c].x, vt);
         vp = fmaf(wt[c], B[c].y, vp);
     }
-    // fade one cell beyond the node ranges (radially from the cell and its
-    // fraction, exact near both ends)
-    const float taper = clampf((float)i0 + fr + 1.0f, 0.0f, 1.0f) * clampf((s.fnr - (float)i0) - fr, 0.0f, 1.0f) *
-                        clampf(w + 1.0f, 0.0f, 1.0f) * clampf(s.fnt - w, 0.0f, 1.0f);
     const float nco = xco * fexp2(ln_n * kLog2E) * taper;
     // LTE populations and source function
     const float rT = frcp(T);
@@ -186,7 +192,7 @@ __device__ __forceinline__ SampleQ shade3(const Shade3 &s, const float4 *tab, fl
 // per SIMD, no spills): at 24 channels the unconstrained kernel takes ~137
 // and runs 3, and the extra resident waves are worth 14% at 512^2 pixels.
 template <int CB, int NSPLIT>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CB <= 24 ? 4 : 1))) void march3_fwd(Geometry3 g, Shade3 s, Channels ch, float *__restrict__ cube,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CB <= 16 ? 4 : 1))) void march3_fwd(Geometry3 g, Shade3 s, Channels ch, float *__restrict__ cube,
                                                    int ch_stride, int nchb, int nwork, int per_xcd) {
     const int L = blockIdx.x;
     const int work = (L % 8) * per_xcd + L / 8;
@@ -219,6 +225,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CB <= 24 ? 
         for (int k = k0; k < k1; ++k) {
             const float t = ((float)k + 0.5f - half) * ds;
             const SampleQ sq = shade3(s, ztab, pxr, fmaf(t, wy, pmy), fmaf(t, wz, pmz), ds);
+            // no ray of the wave with opacity at this sample: no channel changes
+            if (__ballot(sq.K > 0.0f) == 0) continue;
             march_sample<CB, true>(I, Tr, sq, [&](int c) { return ch.v[c0 + c]; });
         }
     }
@@ -369,25 +377,52 @@ static Geometry3 geometry3(const rt_problem3d *p) {
     return g;
 }
 
-// rays of a 3-D render that cross the bounding sphere (the march's own test)
-__global__ __launch_bounds__(256) void census3(Geometry3 g, uint8_t *__restrict__ mask,
-                                               unsigned long long *__restrict__ count) {
-    __shared__ unsigned long long part;
-    if (threadIdx.x == 0) part = 0ull;
+// Rays of a 3-D render that cross the bounding sphere (the march's own
+// test) and, with shade, their pixel-samples that are thin in the march's
+// sense, that have any opacity, and that lie inside the grid's fade (the
+// march's own shading).  blockIdx.y: a chunk of the samples of each ray.
+__global__ __launch_bounds__(256) void census3(Geometry3 g, Shade3 s, uint8_t *__restrict__ mask,
+                                               unsigned long long *__restrict__ counts, int shade) {
+    __shared__ float4 ztab[kZTableNodes - 1];
+    __shared__ unsigned long long part[4];
+    if (shade)
+        for (int i = threadIdx.x; i < kZTableNodes - 1; i += blockDim.x) ztab[i] = s.ztab[i];
+    if (threadIdx.x < 4) part[threadIdx.x] = 0ull;
     __syncthreads();
     const int pix = blockIdx.x * 256 + threadIdx.x;
     if (pix < g.nx * g.ny) {
         const int p = pix % g.nx, q = pix / g.nx;
-        const bool live = chord3(g, p, q).h2 > 0.0f;
-        if (mask) mask[pix] = live ? 1 : 0;
-        if (live) atomicAdd(&part, 1ull);
+        const Chord3 cr = chord3(g, p, q);
+        const bool live = cr.h2 > 0.0f;
+        if (blockIdx.y == 0) {
+            if (mask) mask[pix] = live ? 1 : 0;
+            if (live) atomicAdd(&part[0], 1ull);
+        }
+        if (live && shade) {
+            const float ds = 2.0f * sqrtf(cr.h2) / (float)g.nsamp;
+            const float pmy = cr.yp * g.ci, pmz = cr.yp * g.si, wy = g.si, wz = -g.ci;
+            const float half = 0.5f * (float)g.nsamp;
+            const int len = (g.nsamp + gridDim.y - 1) / gridDim.y;
+            const int k0 = blockIdx.y * len, k1 = min(g.nsamp, k0 + len);
+            unsigned thin = 0, emit = 0, inside = 0;
+            for (int k = k0; k < k1; ++k) {
+                const float t = ((float)k + 0.5f - half) * ds;
+                const SampleQ sq = shade3(s, ztab, cr.xp, fmaf(t, wy, pmy), fmaf(t, wz, pmz), ds);
+                thin += sq.K < kThinK ? 1u : 0u;
+                emit += sq.K > 0.0f ? 1u : 0u;
+                inside += sq.b > 0.0f ? 1u : 0u;   // b = 0 only for a sample beyond the fade
+            }
+            if (thin) atomicAdd(&part[1], (unsigned long long)thin);
+            if (emit) atomicAdd(&part[2], (unsigned long long)emit);
+            if (inside) atomicAdd(&part[3], (unsigned long long)inside);
+        }
     }
     __syncthreads();
-    if (threadIdx.x == 0 && part) atomicAdd(count, part);
+    if (threadIdx.x < 4 && part[threadIdx.x]) atomicAdd(counts + threadIdx.x, part[threadIdx.x]);
 }
 
 __global__ void census3_zero(unsigned long long *c) {
-    if (threadIdx.x == 0) *c = 0ull;
+    if (threadIdx.x < 4) c[threadIdx.x] = 0ull;
 }
 
 static rt_status validate_grid3(const rt_grid3d *g) {
@@ -400,6 +435,61 @@ static rt_status validate_grid3(const rt_grid3d *g) {
     if (!(std::isfinite(g->th_min) && std::isfinite(g->th_max) && g->th_min >= 0 && g->th_max > g->th_min &&
           g->th_max <= kPI3))
         return fail(RT_EINVAL, "need 0 <= th_min < th_max <= pi");
+    return RT_OK;
+}
+
+// Shading constants of a 3-D problem (grid, line, camera): shared by the
+// render and its census.  Needs the validated problem.
+static rt_status build_shade3(const rt_problem3d *p, Shade3 *s) {
+    rt_status st = RT_OK;
+    const rt_grid3d &gr = p->grid;
+    const rt_line &l = p->line;
+    const float4 *tab = nullptr;
+    st = partition_table(l, &tab);
+    if (st != RT_OK) return st;
+    constexpr double kH = 6.62607015e-27, kKB = 1.380649e-16, kC = 2.99792458e10, kAMU = 1.66053906660e-24,
+                     kAU = 1.495978707e13, kZT0 = 0.1, kZT1 = 1.0e4;
+    const double dln = std::log(gr.r_max_au / gr.r_min_au) / (gr.nr - 1);
+    const double dth = (gr.th_max - gr.th_min) / (gr.nt - 1);
+    const Geometry3 g = geometry3(p);
+    std::memset(s, 0, sizeof *s);
+    s->node = (const float4 *)p->nodes;
+    s->ztab = tab;
+    s->nr = gr.nr;
+    s->nt = gr.nt;
+    s->np = gr.np;
+    const float *inv_r2n = nullptr;
+    st = radius_table(gr, &inv_r2n);
+    if (st != RT_OK) return st;
+    s->inv_r2n = inv_r2n;
+    s->u_scale = (float)(std::log(2.0) / dln);
+    s->h_r = (float)(0.5 * std::log(2.0) / dln);
+    s->log2_rmin = (float)std::log2(gr.r_min_au);
+    const double thc = 0.5 * (gr.th_min + gr.th_max);
+    s->cth_c = (float)std::cos(thc);
+    s->sth_c = (float)std::sin(thc);
+    s->inv_dth = (float)(1.0 / dth);
+    s->half_nt1 = 0.5f * (float)(gr.nt - 1);
+    s->inv_dph = (float)(gr.np / (2.0 * kPI3));
+    s->fnp = (float)gr.np;
+    s->fnr = (float)gr.nr;
+    s->fnt = (float)gr.nt;
+    const double l0 = std::log2(kZT0), l1 = std::log2(kZT1), log2e = 1.0 / std::log(2.0);
+    s->zt_l2t0 = (float)l0;
+    s->zt_scale = (float)((kZTableNodes - 1) / (l1 - l0));
+    s->el_log2e = (float)(l.e_l_k * log2e);
+    const double nu = l.nu0_hz;
+    s->theta = (float)(kH * nu / kKB);
+    s->c_s = (float)(p->intensity_scale * 2.0 * kH * nu * nu * nu / (kC * kC));
+    const double bul = l.a_ul * kC * kC / (2.0 * kH * nu * nu * nu);
+    const double blu = l.g_u / l.g_l * bul;
+    s->c_k = (float)((kH * nu / (4.0 * kPI3)) * blu * l.g_l * (kC / nu) * kAU / (std::sqrt(kPI3) * 1e5) * log2e);
+    s->c_alpha = (float)((2.0 * kKB / (l.m_co_amu * kAMU) + p->v_turb * p->v_turb * 2.0 * kKB / (l.m_mol_amu * kAMU)) /
+                        1e10);
+    s->sqrt_log2e = (float)std::sqrt(log2e);
+    s->si = (float)g.si;
+    s->ci = (float)g.ci;
+    s->vsys = (float)p->spec.v_sys_kms;
     return RT_OK;
 }
 
@@ -432,20 +522,29 @@ rt_status rt_render_census_3d(const rt_problem3d *p, uint8_t *mask, int64_t *cou
     if (st != RT_OK) return st;
     if (!counts) return fail(RT_EINVAL, "counts is NULL");
     const Geometry3 g = geometry3(p);
+    // the shading counts need the node records
+    const int shade = p->nodes && ((uintptr_t)p->nodes & 15) == 0 ? 1 : 0;
+    Shade3 s;
+    std::memset(&s, 0, sizeof s);
+    if (shade && (st = build_shade3(p, &s)) != RT_OK) return st;
     hipStream_t hs = (hipStream_t)stream;
     hipError_t e;
-    unsigned long long *d = (unsigned long long *)stream_workspace(hs, kWsCensus, sizeof(unsigned long long), &e);
-    if (!d) return fail_hip(e, "census counter");
+    unsigned long long *d = (unsigned long long *)stream_workspace(hs, kWsCensus, 4 * sizeof(unsigned long long), &e);
+    if (!d) return fail_hip(e, "census counters");
     const int npix = p->cam.nx * p->cam.ny;
+    int chunks = 1;
+    while (shade && chunks < 64 && (long)((npix + 255) / 256) * chunks < 4096 && p->nsamp >= 16 * chunks) chunks *= 2;
     hipLaunchKernelGGL(census3_zero, dim3(1), dim3(64), 0, hs, d);
-    hipLaunchKernelGGL(census3, dim3((npix + 255) / 256), dim3(256), 0, hs, g, mask, d);
-    unsigned long long h = 0;
-    if ((e = hipGetLastError()) == hipSuccess) e = hipMemcpyAsync(&h, d, sizeof h, hipMemcpyDeviceToHost, hs);
+    hipLaunchKernelGGL(census3, dim3((npix + 255) / 256, chunks), dim3(256), 0, hs, g, s, mask, d, shade);
+    unsigned long long h[4] = {0, 0, 0, 0};
+    if ((e = hipGetLastError()) == hipSuccess) e = hipMemcpyAsync(h, d, sizeof h, hipMemcpyDeviceToHost, hs);
     if (e == hipSuccess) e = hipStreamSynchronize(hs);
     if (e != hipSuccess) return fail_hip(e, "3-D census");
-    counts[0] = (int64_t)h;
-    counts[1] = (int64_t)h * p->nsamp;
-    counts[2] = -1;
+    counts[0] = (int64_t)h[0];
+    counts[1] = (int64_t)h[0] * p->nsamp;
+    counts[2] = shade ? (int64_t)h[1] : -1;
+    counts[3] = shade ? (int64_t)h[2] : -1;
+    counts[4] = shade ? (int64_t)h[3] : -1;
     return RT_OK;
 }
 
@@ -459,55 +558,10 @@ rt_status rt_render_cube_3d(const rt_problem3d *p, float *cube, void *stream) {
     st = validate_view(p->line, p->cam, p->spec, p->nsamp, p->intensity_scale, 180.0);
     if (st != RT_OK) return st;
     if (!cube) return fail(RT_EINVAL, "cube is NULL");
-    const rt_grid3d &gr = p->grid;
-    const rt_line &l = p->line;
-    const float4 *tab = nullptr;
-    st = partition_table(l, &tab);
-    if (st != RT_OK) return st;
-    constexpr double kH = 6.62607015e-27, kKB = 1.380649e-16, kC = 2.99792458e10, kAMU = 1.66053906660e-24,
-                     kAU = 1.495978707e13, kZT0 = 0.1, kZT1 = 1.0e4;
-    const double dln = std::log(gr.r_max_au / gr.r_min_au) / (gr.nr - 1);
-    const double dth = (gr.th_max - gr.th_min) / (gr.nt - 1);
-    const Geometry3 g = geometry3(p);
     Shade3 s;
-    std::memset(&s, 0, sizeof s);
-    s.node = (const float4 *)p->nodes;
-    s.ztab = tab;
-    s.nr = gr.nr;
-    s.nt = gr.nt;
-    s.np = gr.np;
-    const float *inv_r2n = nullptr;
-    st = radius_table(gr, &inv_r2n);
+    st = build_shade3(p, &s);
     if (st != RT_OK) return st;
-    s.inv_r2n = inv_r2n;
-    s.u_scale = (float)(std::log(2.0) / dln);
-    s.h_r = (float)(0.5 * std::log(2.0) / dln);
-    s.log2_rmin = (float)std::log2(gr.r_min_au);
-    const double thc = 0.5 * (gr.th_min + gr.th_max);
-    s.cth_c = (float)std::cos(thc);
-    s.sth_c = (float)std::sin(thc);
-    s.inv_dth = (float)(1.0 / dth);
-    s.half_nt1 = 0.5f * (float)(gr.nt - 1);
-    s.inv_dph = (float)(gr.np / (2.0 * kPI3));
-    s.fnp = (float)gr.np;
-    s.fnr = (float)gr.nr;
-    s.fnt = (float)gr.nt;
-    const double l0 = std::log2(kZT0), l1 = std::log2(kZT1), log2e = 1.0 / std::log(2.0);
-    s.zt_l2t0 = (float)l0;
-    s.zt_scale = (float)((kZTableNodes - 1) / (l1 - l0));
-    s.el_log2e = (float)(l.e_l_k * log2e);
-    const double nu = l.nu0_hz;
-    s.theta = (float)(kH * nu / kKB);
-    s.c_s = (float)(p->intensity_scale * 2.0 * kH * nu * nu * nu / (kC * kC));
-    const double bul = l.a_ul * kC * kC / (2.0 * kH * nu * nu * nu);
-    const double blu = l.g_u / l.g_l * bul;
-    s.c_k = (float)((kH * nu / (4.0 * kPI3)) * blu * l.g_l * (kC / nu) * kAU / (std::sqrt(kPI3) * 1e5) * log2e);
-    s.c_alpha = (float)((2.0 * kKB / (l.m_co_amu * kAMU) + p->v_turb * p->v_turb * 2.0 * kKB / (l.m_mol_amu * kAMU)) /
-                        1e10);
-    s.sqrt_log2e = (float)std::sqrt(log2e);
-    s.si = (float)g.si;
-    s.ci = (float)g.ci;
-    s.vsys = (float)p->spec.v_sys_kms;
+    const Geometry3 g = geometry3(p);
     int cb, nsplit;
     forward_shape3(std::min(p->spec.nch, kLaunchChannels), (long)p->cam.nx * p->cam.ny, p->nsamp, &cb, &nsplit);
     if (channel_block_option()) cb = channel_block_option();

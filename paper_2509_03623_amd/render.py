@@ -414,12 +414,16 @@ class Scene3d:
     def census(self, stream=None) -> dict:
         """The library's work accounting of this 3-D render
         (rt_render_census_3d): the [ny, nx] bool mask of rays that cross the
-        bounding sphere r <= r_max e^dln, their number and pixel-samples."""
+        bounding sphere r <= r_max e^dln, their number and pixel-samples, and
+        how many of those the march takes as optically thin, have any
+        opacity, and lie inside the grid's fade."""
         mask = torch.empty(self.ny, self.nx, dtype=torch.uint8, device=self.nodes.device)
-        counts = (C.c_int64 * 3)()
+        counts = (C.c_int64 * 5)()
         p, keep = _problem3d(self)
         L.check(L.lib().rt_render_census_3d(C.byref(p), mask.data_ptr(), counts, C.c_void_p(_stream(stream))))
-        return dict(mask=mask.cpu().numpy().astype(bool), rays=int(counts[0]), pixel_samples=int(counts[1]))
+        return dict(mask=mask.cpu().numpy().astype(bool), rays=int(counts[0]), pixel_samples=int(counts[1]),
+                    thin_pixel_samples=int(counts[2]), emitting_pixel_samples=int(counts[3]),
+                    shaded_pixel_samples=int(counts[4]))
 
     def live_mask(self) -> np.ndarray:
         """[ny, nx] bool: pixels whose ray crosses the bounding sphere."""

@@ -46,6 +46,10 @@ def test_spherical_live_mask_matches_oracle_chords():
     assert 0 < want.sum() < want.size
     assert np.array_equal(got["mask"], want)
     assert sc.ray_samples == int(want.sum()) * sc.nch * sc.nsamp
+    # uniform fields: every sample inside the grid's fade has opacity, none beyond it
+    n = got["pixel_samples"]
+    assert 0 < got["emitting_pixel_samples"] == got["shaded_pixel_samples"] < n
+    assert got["thin_pixel_samples"] >= n - got["emitting_pixel_samples"]
 
 
 @pytest.mark.parametrize("x_co", [1e-2, 1e-12])
