@@ -50,6 +50,8 @@ struct GradDesc {
     const float *target;       // [nch][ny][nx]
     float *cube;               // [nch][ny][nx] (written by the reverse march)
     float4 *tape, *rays, *cot; // scratch: [nsamp][npix], [npix], [nblk][nsamp][npix]
+    int2 *span;                // scratch [npix]: each ray's run of samples with K > 0
+                               // as (nsamp - first, last + 1), (0, 0) for none
     double *acc;               // accumulators [3 nr nz + 2 nr]: ln n, T, v_phi, z_lo, z_up (sized for
                                // double; float ones, the default, use the head of it)
     float *out[5];             // caller's gradient outputs in the same order (NULL: not requested)
@@ -62,7 +64,7 @@ struct GradDesc {
     uint32_t chunks;           // chain chunks per field pass
 };
 
-// scratch bytes of one batched gradient request (tape, rays, cotangents, accumulators)
+// scratch bytes of one batched gradient request (tape, rays, cotangents, spans, accumulators)
 size_t grad_batch_scratch_bytes(int nch, long npix, int nsamp, long nr, long nz);
 // items of one request in the three passes (nfp chain field passes)
 void grad_batch_items(int nch, long npix, int nsamp, int nfp, uint32_t items[3], uint32_t *chunks);

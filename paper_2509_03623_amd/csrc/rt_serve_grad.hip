@@ -31,7 +31,8 @@ static size_t al256(size_t b) { return (b + 255) / 256 * 256; }
 size_t grad_batch_scratch_bytes(int nch, long npix, int nsamp, long nr, long nz) {
     const size_t nblk = (size_t)(nch + kGradSlice - 1) / kGradSlice;
     return al256(sizeof(float4) * (size_t)nsamp * npix) + al256(sizeof(float4) * (size_t)npix) +
-           al256(sizeof(float4) * nblk * nsamp * npix) + al256(sizeof(double) * (size_t)(3 * nr * nz + 2 * nr));
+           al256(sizeof(float4) * nblk * nsamp * npix) + al256(sizeof(int2) * (size_t)npix) +
+           al256(sizeof(double) * (size_t)(3 * nr * nz + 2 * nr));
 }
 
 void grad_batch_items(int nch, long npix, int nsamp, int nfp, uint32_t items[3], uint32_t *chunks) {
@@ -96,6 +97,10 @@ __global__ __launch_bounds__(256) void grad_zero(const GradDesc *__restrict__ de
     const size_t n = 3 * (size_t)D.s.nr * D.s.nz + 2 * (size_t)D.s.nr;
     A *acc = (A *)D.acc;
     for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) acc[i] = (A)0;
+    // the tape's chunks merge the rays' spans into a cleared record
+    const size_t np = (size_t)D.g.nx * D.g.ny;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < np; i += (size_t)gridDim.x * 256)
+        D.span[i] = make_int2(0, 0);
     if (blockIdx.x == 0 && threadIdx.x == 0) *D.loss = 0.0;
 }
 
@@ -116,12 +121,11 @@ __global__ __launch_bounds__(256) void grad_tape(const GradDesc *__restrict__ de
         if (pix < npix) {
             const int len = (D.g.nsamp + kGradTapeChunks - 1) / kGradTapeChunks;
             const int k0 = chunk * len, k1 = min(D.g.nsamp, k0 + len);
-            tape_pixel(D.g, D.s, ztab, pix, k0, k1, chunk == 0, D.tape, D.rays);
+            tape_pixel(D.g, D.s, ztab, pix, k0, k1, chunk == 0, D.tape, D.rays, D.span, true);
         }
     }
 }
 
-// (two waves per SIMD: held to three, the item loop's state spills)
 __global__ __launch_bounds__(256) void grad_march(const GradDesc *__restrict__ descs, int nreq, uint32_t nitems, uint32_t *__restrict__ counter) {
     constexpr int CB = kGradLaneCB, G = kGradLanes, PX = 256 / kGradLanes;
     __shared__ uint32_t s_item;
@@ -144,10 +148,10 @@ __global__ __launch_bounds__(256) void grad_march(const GradDesc *__restrict__ d
             // folded into a by the march
             const float *vch = uniform_ptr(D->vch) + blk * kGradSlice;
             auto vel = [&](int c) -> float { return vch[c]; };
-            const bool live = uniform_ptr(D->rays)[pix].w > 0.0f;
-            march_tau_pixel<CB, G, true, true>(pix, blk, g, c0, nch, nsamp, npix, npix, live, vel, uniform_ptr(D->tape),
-                                               nullptr, uniform_ptr(D->target), uniform_ptr(D->cot),
-                                               uniform_ptr(D->cube), (float)g * vshift);
+            const int2 ks = span_of(uniform_ptr(D->span)[pix], nsamp);
+            march_tau_pixel<CB, G, true, true, true>(pix, blk, g, c0, nch, nsamp, npix, npix, ks.y >= ks.x, vel,
+                                                     uniform_ptr(D->tape), nullptr, uniform_ptr(D->target),
+                                                     uniform_ptr(D->cot), uniform_ptr(D->cube), (float)g * vshift, ks);
         }
     }
 }
@@ -196,6 +200,9 @@ __global__ __launch_bounds__(kGradChainThreads) void grad_chain(const GradDesc *
         for (size_t idx = i0 + threadIdx.x; idx < i1; idx += kGradChainThreads) {
             const int k = (int)(idx / npix);
             const int pix = (int)(idx - (size_t)k * npix);
+            // samples outside the ray's run of K > 0 have no cotangents
+            const int2 ks = span_of(D.span[pix], nsamp);
+            if (k < ks.x || k > ks.y) continue;
             const float4 rr = D.rays[pix];
             float4 c = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
             for (int b = 0; b < D.nblk; ++b) {

@@ -274,6 +274,8 @@ rt_status launch_grad(rt_server *sv, Lane &L, std::vector<Req *> &batch) {
         base += al(sizeof(float4) * npix);
         D.cot = (float4 *)base;
         base += al(sizeof(float4) * D.nblk * ns * npix);
+        D.span = (int2 *)base;
+        base += al(sizeof(int2) * npix);
         D.acc = (double *)base;
         base += al(sizeof(double) * (3 * (size_t)p.grid.nr * p.grid.nz + 2 * (size_t)p.grid.nr));
         D.out[0] = q.grads.d_ln_nh2;
