@@ -17,8 +17,11 @@ hipError_t zero_async_d(double *p, size_t n, hipStream_t st);
 hipError_t to_float_async(const double *src, float *dst, size_t n, hipStream_t st);
 hipError_t copy_float_async(const float *src, float *dst, size_t n, hipStream_t st);
 // tape [nsamp][npix], ray records [npix], and each ray's run of samples with
-// K > 0 as span [npix] = (nsamp - first, last + 1), (0, 0) when it has none
-hipError_t launch_adj_tape(const Geometry &g, const Shade &s, float4 *tape, float4 *rays, int2 *span, hipStream_t st);
+// K > 0 as span [npix] = (nsamp - first, last + 1), (0, 0) when it has none;
+// span_only: the tape holds valid entries only inside each ray's run (when
+// one chunk covers a ray), which the checkpoint-free march is built for
+hipError_t launch_adj_tape(const Geometry &g, const Shade &s, float4 *tape, float4 *rays, int2 *span, bool span_only,
+                           hipStream_t st);
 // reverse march.  kseg 0: the checkpoint-free march with `lanes` (1, 2 or 4)
 // lanes per pixel over each ray's span alone (lanes = 4 needs the velocities
 // uniformly spaced in groups of cb: lane g's = lane 0's + g shift); kseg > 0:

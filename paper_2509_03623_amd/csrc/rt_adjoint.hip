@@ -38,7 +38,7 @@ namespace rt {
 // blockIdx.y selects a chunk of the samples, so short images still give the
 // GPU enough lanes
 __global__ __launch_bounds__(256) void adj_tape(Geometry g, Shade s, float4 *__restrict__ tape,
-                                                float4 *__restrict__ rays, int2 *__restrict__ span) {
+                                                float4 *__restrict__ rays, int2 *__restrict__ span, int span_only) {
     __shared__ float4 ztab[kZTableNodes - 1];
     stage_ztab(s, ztab);
     const int npix = g.nx * g.ny;
@@ -46,7 +46,8 @@ __global__ __launch_bounds__(256) void adj_tape(Geometry g, Shade s, float4 *__r
     if (pix >= npix) return;
     const int len = (g.nsamp + gridDim.y - 1) / gridDim.y;
     const int k0 = blockIdx.y * len, k1 = min(g.nsamp, k0 + len);
-    tape_pixel(g, s, ztab, pix, k0, k1, blockIdx.y == 0, tape, rays, span, gridDim.y > 1);
+    tape_pixel(g, s, ztab, pix, k0, k1, blockIdx.y == 0, tape, rays, span, gridDim.y > 1,
+               span_only && gridDim.y == 1);
 }
 
 // dl_dcube: the cotangent dL/dI; or, with target != NULL, the cotangent of
@@ -512,7 +513,8 @@ hipError_t zero_async(float *p, size_t n, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_adj_tape(const Geometry &g, const Shade &s, float4 *tape, float4 *rays, int2 *span, hipStream_t st) {
+hipError_t launch_adj_tape(const Geometry &g, const Shade &s, float4 *tape, float4 *rays, int2 *span, bool span_only,
+                           hipStream_t st) {
     const int npix = g.nx * g.ny;
     const int tiles = (npix + 255) / 256;
     // sample chunks until about 16 waves per CU (of at least 32 samples each)
@@ -522,7 +524,7 @@ hipError_t launch_adj_tape(const Geometry &g, const Shade &s, float4 *tape, floa
         const hipError_t e = zero_async((float *)span, 2 * (size_t)npix, st);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(adj_tape, dim3(tiles, chunks), dim3(256), 0, st, g, s, tape, rays, span);
+    hipLaunchKernelGGL(adj_tape, dim3(tiles, chunks), dim3(256), 0, st, g, s, tape, rays, span, span_only ? 1 : 0);
     return hipGetLastError();
 }
 

@@ -12,11 +12,14 @@ namespace rt {
 // span[pix] (when given) records the ray's samples with K > 0 as
 // (nsamp - first, last + 1), zero when there are none: written whole when one
 // chunk holds all the samples (shared = false), otherwise merged with atomic
-// maxima into a span cleared beforehand.
+// maxima into a span cleared beforehand.  With span_only (one chunk per ray)
+// only the tape entries of that run are written: a zero entry is held back
+// until a later sample with K > 0 shows it lies inside the run, so nothing
+// is written in front of it, behind it, or for a ray that misses the grid.
 __device__ __forceinline__ void tape_pixel(const Geometry &g, const Shade &s, const float4 *ztab, int pix, int k0,
                                            int k1, bool write_ray, float4 *__restrict__ tape,
                                            float4 *__restrict__ rays, int2 *__restrict__ span = nullptr,
-                                           bool shared = false) {
+                                           bool shared = false, bool span_only = false) {
     const int npix = g.nx * g.ny;
     const RaySetup r = ray_setup(g, pix % g.nx, pix / g.nx);
     if (write_ray) rays[pix] = make_float4(r.px, r.pmy, r.pmz, r.live ? r.ds : 0.0f);
@@ -31,12 +34,14 @@ __device__ __forceinline__ void tape_pixel(const Geometry &g, const Shade &s, co
                                       : shade_sample<false>(s, ztab, r.px, fmaf(t, r.wy, r.pmy), fmaf(t, r.wz, r.pmz),
                                                             r.ds, 0);
             o = make_float4(q.S, q.K, q.a, q.b);
-            if (q.K > 0.0f) {
-                kf = min(kf, k);
-                kl = k;
-            }
         }
-        tape[(size_t)k * npix + pix] = o;
+        if (o.y > 0.0f) {
+            if (span_only && kl >= 0)   // the zeros since the last sample with K > 0
+                for (int j = kl + 1; j < k; ++j) tape[(size_t)j * npix + pix] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            kf = min(kf, k);
+            kl = k;
+        }
+        if (!span_only || o.y > 0.0f) tape[(size_t)k * npix + pix] = o;
     }
     if (span) {
         if (!shared) {
@@ -84,9 +89,11 @@ __device__ __forceinline__ float swap_half_quad(float x) {
 // otherwise dL/dI is read from dl_dcube.  Only the samples with K > 0 (one
 // run along the ray) change anything: outside it x = 0 in every channel.
 // With SPAN the run comes from the tape's span record (kspan = (first,
-// last)): both sweeps cover it alone and the cotangents outside it are left
-// unwritten, since the chain passes read the same record; without, sweep 1
-// finds it and the cotangents outside are written as zeros.  A pixel whose
+// last)): both sweeps cover the union of the wave's runs, each lane taking
+// its tape entries outside its own run as zero (the tape may hold nothing
+// there), and the cotangents outside a run are left unwritten, since the
+// chain passes read the same record; without, sweep 1 finds the run and the
+// cotangents outside it are written as zeros.  A pixel whose
 // ray misses the grid (live false) has zero intensity: it only clears its
 // channels of the cube and leaves its cotangents unwritten (every chain pass
 // skips rays with ds = 0).
@@ -106,6 +113,8 @@ __device__ __forceinline__ void march_tau_pixel(int pix, int blk, int g, int c0,
     }
     float th[CB], tl[CB], w[CB];
     int kf = nsamp, kl = -1;
+    // this lane's own run: the tape may hold nothing valid outside it
+    const int own_f = kspan.x, own_l = kspan.y;
     if constexpr (SPAN) {
         // the union of the spans of the wave's live pixels (the lanes still
         // active here): a wave-uniform range, so both sweeps are scalar
@@ -133,6 +142,7 @@ __device__ __forceinline__ void march_tau_pixel(int pix, int blk, int g, int c0,
             if (SPAN && k < kf) continue;
             float4 q = qn;
             qn = tape[(size_t)max(k - 1, 0) * npix + pix];
+            if (SPAN && (k < own_f || k > own_l)) q = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
             if (!SPAN && q.y > 0.0f) {
                 kf = k;
                 kl = max(kl, k);
@@ -192,8 +202,9 @@ __device__ __forceinline__ void march_tau_pixel(int pix, int blk, int g, int c0,
     float4 qn = tape[(size_t)max(kl, 0) * npix + pix];
 #pragma unroll 1
     for (int k = kl; k >= kf; --k) {
-        const float4 q = qn;
+        float4 q = qn;
         qn = tape[(size_t)max(k - 1, 0) * npix + pix];
+        if (SPAN && (k < own_f || k > own_l)) q = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         const float S = q.x, b = q.w;
         const float a = SHIFT ? fmaf(-vsh, q.w, q.z) : q.z;
         const float lK = flog2(q.y);

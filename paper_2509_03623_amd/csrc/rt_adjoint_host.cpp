@@ -167,7 +167,9 @@ rt_status adjoint_core(const rt_problem *p, const float *dl, const rt_grads *g, 
             float *ckpt = (float *)(base + tape_b + rays_b);
             float4 *cot = (float4 *)(base + tape_b + rays_b + ckpt_b);
             int2 *span = (int2 *)(base + tape_b + rays_b + ckpt_b + cot_b);   // last: 8-byte records
-            if ((e = launch_adj_tape(gb, sb, tape, rays, span, st)) != hipSuccess) return fail_hip(e, "adjoint tape");
+            // the checkpointed march reads every tape entry
+            if ((e = launch_adj_tape(gb, sb, tape, rays, span, kseg == 0, st)) != hipSuccess)
+                return fail_hip(e, "adjoint tape");
             const size_t off = (size_t)c0 * plane + pix0;
             if ((e = launch_adj_march(cb_l, kseg, lanes_l, ns, bpix, (int)plane, ch, (float)shift, tape, span,
                                       dl ? dl + off : nullptr, target ? target + off : nullptr, ckpt, cot,
