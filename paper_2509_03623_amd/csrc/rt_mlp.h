@@ -30,7 +30,7 @@ hipError_t mlp_prepare(const float *flat, int precision, void *buf, MlpDev *w, h
 hipError_t mlp_forward(const Geometry &g, const Shade &s, const MlpDev &w, int precision, size_t M, float4 *out,
                        hipStream_t st);
 // list: device scratch of mlp_backward_list_bytes(M) (the BF16 backward's
-// list of the passes with any dL/do != 0)
+// list of the passes with any dL/do != 0, and their flags)
 size_t mlp_backward_list_bytes(size_t M);
 hipError_t mlp_backward(const Geometry &g, const Shade &s, const MlpDev &w, int precision, size_t M,
                         const float4 *dO, uint32_t *list, float *dW, hipStream_t st);

@@ -496,15 +496,16 @@ __device__ __forceinline__ void br_stage(__bf16 *dst, const gbf16 *src, int n, i
     __builtin_amdgcn_s_waitcnt(0);
 }
 
-// The passes whose points have any dL/do != 0, for mlp_bwd_rr: one wave per
-// pass of kBrPts points votes by ballot and appends the pass's index to
-// list[1 ...], list[0] counting them (cleared beforehand).  dL/do = 0 at a
+// Which passes of kBrPts points have any dL/do != 0, for mlp_bwd_rr: one
+// wave per pass votes by ballot and writes the pass's flag (no atomics:
+// appending through one shared counter serialised them, 2.1 ms at 16.8e6
+// points; mlp_list_passes compacts the flags).  dL/do = 0 at a
 // point (no opacity there) makes every layer's dL/dz' zero, so a pass whose
 // points all have it adds nothing to any gradient; the points of a pass are
 // adjacent pixels at one sample depth, so whole passes lie outside the CO
 // layer together.
-__global__ __launch_bounds__(256) void mlp_live_passes(const float4 *__restrict__ dO, size_t M,
-                                                       uint32_t *__restrict__ list) {
+__global__ __launch_bounds__(256) void mlp_live_passes(const float4 *__restrict__ dO, size_t M, size_t npass,
+                                                       uint32_t *__restrict__ live) {
     static_assert(kBrPts == 64, "one wave per pass");
     const size_t pass = (size_t)blockIdx.x * 4 + threadIdx.x / 64;
     const size_t m = pass * kBrPts + (threadIdx.x & 63);
@@ -513,7 +514,32 @@ __global__ __launch_bounds__(256) void mlp_live_passes(const float4 *__restrict_
         const float4 d = dO[m];
         nz = d.x != 0.0f || d.y != 0.0f || d.z != 0.0f;
     }
-    if (__ballot(nz) != 0 && (threadIdx.x & 63) == 0) list[1 + atomicAdd(list, 1u)] = (uint32_t)pass;
+    const bool any = __ballot(nz) != 0;
+    if ((threadIdx.x & 63) == 0 && pass < npass) live[pass] = any ? 1u : 0u;
+}
+
+// The flagged passes in order into list[1 ...], their number into list[0]:
+// one workgroup, each lane counting a contiguous run of flags, an exclusive
+// scan of the counts in LDS, then each lane writing its run's indices.
+__global__ __launch_bounds__(1024) void mlp_list_passes(const uint32_t *__restrict__ live, uint32_t npass,
+                                                        uint32_t *__restrict__ list) {
+    __shared__ uint32_t part[1024];
+    const uint32_t t = threadIdx.x, per = (npass + 1023) / 1024;
+    const uint32_t b = min(npass, t * per), e = min(npass, b + per);
+    uint32_t n = 0;
+    for (uint32_t i = b; i < e; ++i) n += live[i];
+    part[t] = n;
+    __syncthreads();
+    for (uint32_t off = 1; off < 1024; off <<= 1) {
+        const uint32_t v = t >= off ? part[t - off] : 0u;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    uint32_t o = part[t] - n;
+    for (uint32_t i = b; i < e; ++i)
+        if (live[i]) list[1 + o++] = i;
+    if (t == 1023) list[0] = part[1023];
 }
 
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void mlp_bwd_rr(
@@ -546,6 +572,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     const int brow = 32 * wv + (lane >> 1), bhalf = lane & 1;     // bias row of this lane
     const int col = 16 * wv + lc;                                 // this lane's point within the pass
     __syncthreads();
+    // the passes with any dL/do != 0, listed in order (list[0] of them)
     const uint32_t npass = list[0];
     for (uint32_t ip = blockIdx.x; ip < npass; ip += gridDim.x) {
         const size_t base = (size_t)list[1 + ip] * kBrPts;
@@ -937,7 +964,7 @@ hipError_t mlp_forward(const Geometry &g, const Shade &s, const MlpDev &w, int p
     return hipGetLastError();
 }
 
-size_t mlp_backward_list_bytes(size_t M) { return sizeof(uint32_t) * (1 + (M + kBrPts - 1) / kBrPts); }
+size_t mlp_backward_list_bytes(size_t M) { return sizeof(uint32_t) * (1 + 2 * ((M + kBrPts - 1) / kBrPts)); }
 
 hipError_t mlp_backward(const Geometry &g, const Shade &s, const MlpDev &w, int precision, size_t M,
                         const float4 *dO, uint32_t *list, float *dW, hipStream_t st) {
@@ -947,8 +974,9 @@ hipError_t mlp_backward(const Geometry &g, const Shade &s, const MlpDev &w, int 
     if (e != hipSuccess) return e;
     if (precision == RT_MLP_BF16) {
         const size_t passes = (M + kBrPts - 1) / kBrPts;
-        if ((e = zero_async((float *)list, 1, st)) != hipSuccess) return e;
-        hipLaunchKernelGGL(mlp_live_passes, dim3((unsigned)((passes + 3) / 4)), dim3(256), 0, st, dO, M, list);
+        uint32_t *flags = list + 1 + passes;   // [passes] after the list
+        hipLaunchKernelGGL(mlp_live_passes, dim3((unsigned)((passes + 3) / 4)), dim3(256), 0, st, dO, M, passes, flags);
+        hipLaunchKernelGGL(mlp_list_passes, dim3(1), dim3(1024), 0, st, flags, (uint32_t)passes, list);
         const unsigned grid = (unsigned)std::min<size_t>(passes, (size_t)ncu);
         hipLaunchKernelGGL(mlp_bwd_rr, dim3(grid), dim3(256), 0, st, g, s, w, M, dO, list, dW);
     } else {
