@@ -304,7 +304,13 @@ constexpr int kChainTurn = 37 * kChainThreads;
 // (float), and flush it once with atomics into the accumulators of type A;
 // the FIRST pass also accumulates the two surface vectors (LDS, float) and
 // writes dL/do.
-template <int FIELD, bool FIRST, typename A>
+// With STORE (the first pass, FIELD 0) each sample inside a ray's run also
+// leaves the temperature term of its chain in slice 0 of the cotangents,
+// which it has consumed: (dL/dT at the sample, the cell's first node as
+// integer bits, the two bilinear weights), zero where there is none; the
+// second pass (adj_chain_lds_stored) then adds those into the T gradient
+// without shading the sample again.
+template <int FIELD, bool FIRST, typename A, bool STORE = false>
 __global__ __launch_bounds__(kChainThreads) void adj_chain_lds(Geometry g, Shade s, const float4 *__restrict__ rays,
                                                      const int2 *__restrict__ span, float4 *__restrict__ cot,
                                                      int nblk, GradAcc go, float4 *__restrict__ dO) {
@@ -334,7 +340,8 @@ __global__ __launch_bounds__(kChainThreads) void adj_chain_lds(Geometry g, Shade
         const int2 ks = span_of(span[pix], g.nsamp);
         float4 c = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         float4 r = c;
-        if (k >= ks.x && k <= ks.y) {
+        const bool in_run = k >= ks.x && k <= ks.y;
+        if (in_run) {
             r = rays[pix];
             // the first pass sums the channel-block slices and keeps the sum in slice 0
             const int nb = FIRST ? nblk : 1;
@@ -342,9 +349,10 @@ __global__ __launch_bounds__(kChainThreads) void adj_chain_lds(Geometry g, Shade
                 const float4 t = cot[((size_t)b * g.nsamp + k) * npix + pix];
                 c.x += t.x; c.y += t.y; c.z += t.z; c.w += t.w;
             }
-            if (FIRST && nblk > 1) cot[(size_t)k * npix + pix] = c;
+            if (FIRST && !STORE && nblk > 1) cot[(size_t)k * npix + pix] = c;
         }
         float4 dout = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        float4 tterm = make_float4(0.0f, 0.0f, 0.0f, 0.0f);   // STORE: the sample's T term
         if (r.w > 0.0f && (c.x != 0.0f || c.y != 0.0f || c.z != 0.0f || c.w != 0.0f)) {
             const float ds = r.w;
             const float t = ((float)k + 0.5f - 0.5f * (float)g.nsamp) * ds;
@@ -371,6 +379,7 @@ __global__ __launch_bounds__(kChainThreads) void adj_chain_lds(Geometry g, Shade
                 const float dS_dT = q.S * (1.0f + tp.em1) / tp.em1 * tp.x * tp.rT;
                 const float gT = gS * dS_dT + gKK * dlnK_dT - 0.5f * tp.rT * (gb * q.b + ga * q.a);
                 if (FIELD == 1) gv = gT * tfac;
+                if (STORE) tterm = make_float4(gT * tfac, __int_as_float(L.i0 * s.nz + L.j0), L.fu, L.fv);
                 if (FIRST && s.mlp_o) {
                     const float s0 = sigmoidf_(o.x), s0c = sigmoidf_(-o.x);
                     const float s1 = sigmoidf_(o.y), s1c = sigmoidf_(-o.y);
@@ -397,6 +406,7 @@ __global__ __launch_bounds__(kChainThreads) void adj_chain_lds(Geometry g, Shade
             }
         }
         if (FIRST && dO) dO[o_index(s, k, pix)] = dout;
+        if (STORE && in_run) cot[(size_t)k * npix + pix] = tterm;
     }
     __syncthreads();
     A *dst = (A *)(FIELD == 0 ? go.ln_n : (FIELD == 1 ? go.temp : (FIELD == 2 ? go.vphi : nullptr)));
@@ -410,14 +420,51 @@ __global__ __launch_bounds__(kChainThreads) void adj_chain_lds(Geometry g, Shade
         }
 }
 
-template <int FIELD, bool FIRST, typename A>
+// The temperature pass from the terms a STORE first pass left in slice 0
+// of the cotangents: no shading, only the bilinear scatter into the grid in
+// LDS and one flush, in the first pass's order of the samples.
+template <typename A>
+__global__ __launch_bounds__(kChainThreads) void adj_chain_lds_stored(Geometry g, Shade s, const int2 *__restrict__ span,
+                                                             const float4 *__restrict__ cot, GradAcc go) {
+    extern __shared__ float field[];   // [nr nz]
+    const int nn = s.nr * s.nz;
+    for (int i = threadIdx.x; i < nn; i += kChainThreads) field[i] = 0.0f;
+    __syncthreads();
+    const int npix = g.nx * g.ny;
+    const size_t total = (size_t)g.nsamp * npix;
+    const int turn = (int)((size_t)kChainTurn % (size_t)npix);
+    for (size_t idx = (size_t)blockIdx.x * kChainThreads + threadIdx.x; idx < total;
+         idx += (size_t)gridDim.x * kChainThreads) {
+        const int k = (int)(idx / npix);
+        int pix = (int)(idx - (size_t)k * npix) + (int)(((long)k * turn) % npix);
+        if (pix >= npix) pix -= npix;
+        const int2 ks = span_of(span[pix], g.nsamp);
+        if (k < ks.x || k > ks.y) continue;
+        const float4 t = cot[(size_t)k * npix + pix];
+        const float gv = t.x;
+        if (gv != 0.0f) {
+            const int n00 = __float_as_int(t.y), n10 = n00 + s.nz;
+            const float fu = t.z, fv = t.w;
+            atomicAdd(field + n00, gv * (1.0f - fu) * (1.0f - fv));
+            atomicAdd(field + n00 + 1, gv * (1.0f - fu) * fv);
+            atomicAdd(field + n10, gv * fu * (1.0f - fv));
+            atomicAdd(field + n10 + 1, gv * fu * fv);
+        }
+    }
+    __syncthreads();
+    A *dst = (A *)go.temp;
+    for (int i = threadIdx.x; i < nn; i += kChainThreads)
+        if (field[i] != 0.0f) atomicAdd(dst + i, (A)field[i]);
+}
+
+template <int FIELD, bool FIRST, typename A, bool STORE = false>
 static hipError_t launch_chain_lds_t(const Geometry &g, const Shade &s, const float4 *rays, const int2 *span, float4 *cot,
                                      int nblk, const GradAcc &go, float4 *dO, int nwg, size_t shmem, hipStream_t st) {
-    hipError_t e = hipFuncSetAttribute((const void *)adj_chain_lds<FIELD, FIRST, A>,
+    hipError_t e = hipFuncSetAttribute((const void *)adj_chain_lds<FIELD, FIRST, A, STORE>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((adj_chain_lds<FIELD, FIRST, A>), dim3(nwg), dim3(kChainThreads), shmem, st, g, s, rays, span,
-                       cot, nblk, go, dO);
+    hipLaunchKernelGGL((adj_chain_lds<FIELD, FIRST, A, STORE>), dim3(nwg), dim3(kChainThreads), shmem, st, g, s, rays,
+                       span, cot, nblk, go, dO);
     return hipGetLastError();
 }
 
@@ -434,6 +481,16 @@ static hipError_t chain_lds_passes(const Geometry &g, const Shade &s, const floa
                                    float4 *cot, int nblk, const GradAcc &go, float4 *dO, int nwg, hipStream_t st) {
     const size_t fb = (size_t)s.nr * s.nz * sizeof(float), sb = 2 * (size_t)s.nr * sizeof(float);
     const bool want[3] = {go.ln_n != nullptr, go.temp != nullptr, go.vphi != nullptr};
+    if (want[0] && want[1] && !want[2]) {
+        // ln n and T: the first pass leaves the T terms for the second
+        hipError_t e = launch_chain_lds_t<0, true, A, true>(g, s, rays, span, cot, nblk, go, dO, nwg, fb + sb, st);
+        if (e != hipSuccess) return e;
+        e = hipFuncSetAttribute((const void *)adj_chain_lds_stored<A>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)fb);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(adj_chain_lds_stored<A>, dim3(nwg), dim3(kChainThreads), fb, st, g, s, span, cot, go);
+        return hipGetLastError();
+    }
     bool first = true;
     hipError_t e = hipSuccess;
     for (int f = 0; f < 3; ++f) {
