@@ -1,8 +1,10 @@
 // rt_adjoint.hip -- reverse-mode derivative of the ray march.
 //
 // Pass A (adj_tape): one lane per pixel walks its ray and writes the
-//   channel-independent sample quantities (S, K, a, b) of every sample to a
-//   sample-major tape, plus the ray's set-up.
+//   channel-independent sample quantities (S, K, a, b) to a sample-major
+//   tape, plus the ray's set-up and its span: the run of samples with K > 0,
+//   outside which a sample changes nothing and has no cotangents (with the
+//   checkpoint-free march and one chunk per ray only that run is written).
 // Pass B (adj_march<CB, KSEG>): one lane per pixel x channel block.  A
 //   forward sweep stores the transmission of each channel at the start of
 //   every KSEG-sample segment (the checkpoints); the reverse sweep visits the
@@ -21,12 +23,15 @@
 //   runs the J recurrence to the observer); the second sweep re-accumulates
 //   tau_suf in the same order, so the only state kept per (ray, channel) is
 //   the total depth, in a register, and nothing is written but the
-//   cotangents.
+//   cotangents.  Both sweeps cover only the union of the spans of the
+//   wave's rays; rays that miss the grid only clear their cube channels.
 // Pass C (adj_chain_lds, or adj_chain for grids too large for LDS): each
-//   pixel-sample's shading is recomputed with its local derivatives, the
-//   cotangents are chained to the interpolated fields and added to the grid
-//   nodes (one field per pass privatised in LDS and flushed once; adj_chain
-//   scatters with global atomics; the surface vectors in LDS either way).
+//   pixel-sample inside its ray's span that has a cotangent has its shading
+//   recomputed with its local derivatives, the cotangents chained to the
+//   interpolated fields and added to the grid nodes (one field per pass
+//   privatised in LDS and flushed once, the T pass from terms the first pass
+//   stored when ln n and T are asked for; adj_chain scatters with global
+//   atomics; the surface vectors in LDS either way).
 #include <type_traits>
 
 #include "rt_adjoint.h"

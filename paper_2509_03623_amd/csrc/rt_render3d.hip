@@ -17,8 +17,9 @@
 // source function as in the axisymmetric march, and the line-of-sight
 // velocity v . w from the three components and the local unit vectors.  The
 // channel loop, the lanes-per-ray split and its front-to-back composition
-// are those of the axisymmetric march.  Nothing is skipped: every
-// (pixel, channel, sample) of a ray crossing the bounding sphere is evaluated.
+// are those of the axisymmetric march.  A sample beyond the fade (density
+// and depth exactly 0) stops after its indices, and a wave skips the channel
+// loop of a sample where none of its rays has opacity; the cube is the same.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
