@@ -519,27 +519,30 @@ __global__ __launch_bounds__(256) void mlp_live_passes(const float4 *__restrict_
 }
 
 // The flagged passes in order into list[1 ...], their number into list[0]:
-// one workgroup, each lane counting a contiguous run of flags, an exclusive
-// scan of the counts in LDS, then each lane writing its run's indices.
+// one workgroup takes 1024 consecutive flags at a time (coalesced), each
+// lane's place from a ballot within its wave and the waves' counts in LDS.
 __global__ __launch_bounds__(1024) void mlp_list_passes(const uint32_t *__restrict__ live, uint32_t npass,
                                                         uint32_t *__restrict__ list) {
-    __shared__ uint32_t part[1024];
-    const uint32_t t = threadIdx.x, per = (npass + 1023) / 1024;
-    const uint32_t b = min(npass, t * per), e = min(npass, b + per);
-    uint32_t n = 0;
-    for (uint32_t i = b; i < e; ++i) n += live[i];
-    part[t] = n;
-    __syncthreads();
-    for (uint32_t off = 1; off < 1024; off <<= 1) {
-        const uint32_t v = t >= off ? part[t - off] : 0u;
+    __shared__ uint32_t wsum[16];
+    const uint32_t t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    uint32_t done = 0;   // passes listed so far (the same in every lane)
+    for (uint32_t c0 = 0; c0 < npass; c0 += 1024) {
+        const uint32_t i = c0 + t;
+        const bool f = i < npass && live[i] != 0u;
+        const uint64_t m = __ballot(f);
+        if (lane == 0) wsum[wv] = (uint32_t)__popcll(m);
         __syncthreads();
-        part[t] += v;
+        uint32_t off = done, tot = 0;
+        for (uint32_t j = 0; j < 16; ++j) {
+            const uint32_t n = wsum[j];
+            off += j < wv ? n : 0u;
+            tot += n;
+        }
+        if (f) list[1 + off + (uint32_t)__popcll(m & ((1ull << lane) - 1ull))] = i;
+        done += tot;
         __syncthreads();
     }
-    uint32_t o = part[t] - n;
-    for (uint32_t i = b; i < e; ++i)
-        if (live[i]) list[1 + o++] = i;
-    if (t == 1023) list[0] = part[1023];
+    if (t == 0) list[0] = done;
 }
 
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void mlp_bwd_rr(

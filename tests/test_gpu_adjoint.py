@@ -164,6 +164,24 @@ def test_end_to_end_l2_gradient():
         assert l2 <= 1e-3, (k, l2)
 
 
+def test_stored_temperature_terms_match_recomputed():
+    """Asking for ln n and T only makes the first chain pass store each
+    sample's T term and the T pass scatter those; asking for v_phi as well
+    runs a pass per field that shades again.  Same T and ln n gradients (the
+    terms are the same arithmetic; only the order of the LDS additions may
+    differ), and both against the oracle's autograd."""
+    prob = kscale(synth.small_problem(nx=24, ny=20, nch=12, nsamp=64, nr=48, nz=24, seed=5, dv=0.2, incl=45.0))
+    target = target_for(prob)
+    cot = 2.0 * (oracle.render(prob) - target)
+    stored, _, _ = gpu_grads(prob, target, want=("ln_nh2", "temp_k", "z_lo_au", "z_up_au"), cotangent=cot)
+    full, _, _ = gpu_grads(prob, target, want=tuple(BLOCKS), cotangent=cot)
+    _, ref = torch_ref.loss_and_grad(prob, target)
+    for k in ("ln_nh2", "temp_k", "z_lo_au", "z_up_au"):
+        a, b = stored[k], full[k]
+        assert np.linalg.norm(a - b) <= 1e-6 * np.linalg.norm(b), k
+        check_block(k, a, ref[k])
+
+
 def test_subset_of_gradients_and_determinism():
     prob = kscale(synth.small_problem(nx=20, ny=20, nch=10, nsamp=48, seed=3))
     target = target_for(prob)
