@@ -59,10 +59,10 @@ SHADE3_SLOTS = 307 + 4 * 16
 # was taken on: the hash of those files is checked at run time.
 FWD_TRAFFIC = {"sources": ("paper_2509_03623_amd/csrc/rt_forward.hip", "paper_2509_03623_amd/csrc/rt_kernels.h",
                            "paper_2509_03623_amd/csrc/rt_launch.h"),
-               "sha256": "39b6c0f087aac249e1b65d69be3d4fdd5662f034d1f873041a50ba375a21034d",
-               "fetch_scale": 1048576 / 524303.5, "write_scale": 1.0,
+               "sha256": "6ea039cd02742bf7d552e6ef90fd250c8277a33ca373562feed8ec088c478f49",
+               "fetch_scale": 1048576 / 524302.5, "write_scale": 1.0,
                # seed -> (FETCH_SIZE KiB, WRITE_SIZE KiB), mean of three launches each
-               "disks": {2000: (1264.6, 65536.0), 2001: (1222.6, 65536.0), 2002: (1274.8, 65536.0), 2003: (1255.5, 65536.0), 2004: (1255.7, 65536.0), 2005: (1233.8, 65536.0), 2006: (1218.5, 65536.0), 2007: (1245.9, 65536.0)}}
+               "disks": {2000: (1196.8, 65536.0), 2001: (1184.7, 65536.0), 2002: (1343.3, 65536.0), 2003: (1291.7, 65536.0), 2004: (1150.5, 65536.0), 2005: (1193.9, 65536.0), 2006: (1309.5, 65536.0), 2007: (1454.9, 65536.0)}}
 
 
 def measured_traffic(seed: int):
