@@ -155,7 +155,9 @@ rt_status rt_render_cube(const rt_problem *p, float *cube, void *stream);
  * ray's total optical depth (the single checkpoint per ray and channel) minus
  * the depth behind it, or, with RT_OPT_CKPT_SEGMENT, from transmission
  * checkpoints every few samples.  Gradients use atomics, so their last bits
- * may vary from run to run. */
+ * may vary from run to run.  With the network (p->mlp) a call takes at most
+ * 256 channels and fewer than 2^32 - 1 pixel-samples (nx ny nsamp);
+ * RT_EINVAL otherwise. */
 rt_status rt_render_cube_adjoint(const rt_problem *p, const float *dl_dcube, const rt_grads *g,
                                  float *cube_opt, void *stream);
 

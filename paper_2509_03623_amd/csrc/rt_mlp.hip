@@ -496,41 +496,75 @@ __device__ __forceinline__ void br_stage(__bf16 *dst, const gbf16 *src, int n, i
     __builtin_amdgcn_s_waitcnt(0);
 }
 
-// Which passes of kBrPts points have any dL/do != 0, for mlp_bwd_rr: one
-// wave per pass votes by ballot and writes the pass's flag (no atomics:
-// appending through one shared counter serialised them, 2.1 ms at 16.8e6
-// points; mlp_list_passes compacts the flags).  dL/do = 0 at a
-// point (no opacity there) makes every layer's dL/dz' zero, so a pass whose
-// points all have it adds nothing to any gradient; the points of a pass are
-// adjacent pixels at one sample depth, so whole passes lie outside the CO
-// layer together.
-__global__ __launch_bounds__(256) void mlp_live_passes(const float4 *__restrict__ dO, size_t M, size_t npass,
-                                                       uint32_t *__restrict__ live) {
-    static_assert(kBrPts == 64, "one wave per pass");
-    const size_t pass = (size_t)blockIdx.x * 4 + threadIdx.x / 64;
-    const size_t m = pass * kBrPts + (threadIdx.x & 63);
-    bool nz = false;
-    if (m < M) {
-        const float4 d = dO[m];
-        nz = d.x != 0.0f || d.y != 0.0f || d.z != 0.0f;
-    }
-    const bool any = __ballot(nz) != 0;
-    if ((threadIdx.x & 63) == 0 && pass < npass) live[pass] = any ? 1u : 0u;
+// The points with any dL/do != 0, in order, for mlp_bwd_rr.  dL/do = 0 at a
+// point (no opacity there) makes every layer's dL/dz' zero: the point adds
+// nothing to any gradient, so the backward takes the others only, packed 64
+// to a pass.  Three launches over kLiveChunks chunks of the points: the
+// count of each chunk, a scan of the counts, then each chunk writing its
+// points' indices (1024 consecutive points at a time, each lane's place from
+// a ballot within its wave and the waves' counts in LDS).  list: [0] the
+// number of points, [1 ...] their indices; then the chunks' counts and
+// offsets.
+constexpr int kLiveChunks = 4096;
+
+__device__ __forceinline__ bool live_point(const float4 *dO, size_t m) {
+    const float4 d = dO[m];
+    return d.x != 0.0f || d.y != 0.0f || d.z != 0.0f;
 }
 
-// The flagged passes in order into list[1 ...], their number into list[0]:
-// one workgroup takes 1024 consecutive flags at a time (coalesced), each
-// lane's place from a ballot within its wave and the waves' counts in LDS.
-__global__ __launch_bounds__(1024) void mlp_list_passes(const uint32_t *__restrict__ live, uint32_t npass,
-                                                        uint32_t *__restrict__ list) {
+__global__ __launch_bounds__(1024) void mlp_live_count(const float4 *__restrict__ dO, size_t M, size_t chunk,
+                                                       uint32_t *__restrict__ counts) {
+    __shared__ uint32_t tot;
+    if (threadIdx.x == 0) tot = 0u;
+    __syncthreads();
+    const size_t b0 = (size_t)blockIdx.x * chunk, b1 = min(M, b0 + chunk);
+    uint32_t n = 0;
+    for (size_t i = b0 + threadIdx.x; i < b1; i += 1024) n += live_point(dO, i) ? 1u : 0u;
+    if (n) atomicAdd(&tot, n);
+    __syncthreads();
+    if (threadIdx.x == 0) counts[blockIdx.x] = tot;
+}
+
+// exclusive offsets of nb <= 4 * 1024 counts (one workgroup) and their total into list[0]
+__global__ __launch_bounds__(1024) void mlp_live_scan(const uint32_t *__restrict__ counts, int nb,
+                                                      uint32_t *__restrict__ offsets, uint32_t *__restrict__ list) {
+    __shared__ uint32_t part[1024];
+    const int t = threadIdx.x;
+    uint32_t c[4], n = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        c[j] = 4 * t + j < nb ? counts[4 * t + j] : 0u;
+        n += c[j];
+    }
+    part[t] = n;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const uint32_t v = t >= off ? part[t - off] : 0u;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    uint32_t o = part[t] - n;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        if (4 * t + j < nb) offsets[4 * t + j] = o;
+        o += c[j];
+    }
+    if (t == 1023) list[0] = part[1023];
+}
+
+__global__ __launch_bounds__(1024) void mlp_live_write(const float4 *__restrict__ dO, size_t M, size_t chunk,
+                                                       const uint32_t *__restrict__ offsets,
+                                                       uint32_t *__restrict__ list) {
     __shared__ uint32_t wsum[16];
     const uint32_t t = threadIdx.x, lane = t & 63, wv = t >> 6;
-    uint32_t done = 0;   // passes listed so far (the same in every lane)
-    for (uint32_t c0 = 0; c0 < npass; c0 += 1024) {
-        const uint32_t i = c0 + t;
-        const bool f = i < npass && live[i] != 0u;
-        const uint64_t m = __ballot(f);
-        if (lane == 0) wsum[wv] = (uint32_t)__popcll(m);
+    const size_t b0 = (size_t)blockIdx.x * chunk, b1 = min(M, b0 + chunk);
+    uint32_t done = offsets[blockIdx.x];   // the same in every lane
+    for (size_t c0 = b0; c0 < b1; c0 += 1024) {
+        const size_t i = c0 + t;
+        const bool f = i < b1 && live_point(dO, i);
+        const uint64_t mk = __ballot(f);
+        if (lane == 0) wsum[wv] = (uint32_t)__popcll(mk);
         __syncthreads();
         uint32_t off = done, tot = 0;
         for (uint32_t j = 0; j < 16; ++j) {
@@ -538,11 +572,10 @@ __global__ __launch_bounds__(1024) void mlp_list_passes(const uint32_t *__restri
             off += j < wv ? n : 0u;
             tot += n;
         }
-        if (f) list[1 + off + (uint32_t)__popcll(m & ((1ull << lane) - 1ull))] = i;
+        if (f) list[1 + off + (uint32_t)__popcll(mk & ((1ull << lane) - 1ull))] = (uint32_t)i;
         done += tot;
         __syncthreads();
     }
-    if (t == 0) list[0] = done;
 }
 
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void mlp_bwd_rr(
@@ -575,17 +608,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     const int brow = 32 * wv + (lane >> 1), bhalf = lane & 1;     // bias row of this lane
     const int col = 16 * wv + lc;                                 // this lane's point within the pass
     __syncthreads();
-    // the passes with any dL/do != 0, listed in order (list[0] of them)
-    const uint32_t npass = list[0];
+    // the points with any dL/do != 0, listed in order (list[0] of them), 64
+    // to a pass
+    const uint32_t npts = list[0];
+    const uint32_t npass = (npts + kBrPts - 1) / kBrPts;
     for (uint32_t ip = blockIdx.x; ip < npass; ip += gridDim.x) {
-        const size_t base = (size_t)list[1 + ip] * kBrPts;
+        const uint32_t base = ip * kBrPts;
         // the weight operands are the same every pass: hide that from the
         // compiler, or it keeps all 208 fragments in registers across passes
         uint64_t wr_u = (uint64_t)w.Wr, wrt_u = (uint64_t)w.WrT;
         asm volatile("" : "+s"(wr_u), "+s"(wrt_u));
         const gbf16 *Wr = (const gbf16 *)wr_u;
         const gbf16 *WrT = (const gbf16 *)wrt_u;
-        const size_t m = base + col;
+        const size_t m = base + col < npts ? (size_t)list[1 + base + col] : M;   // M: no point
         float rh = 0.0f, zh = 0.0f;
         if (lane < 16 && m < M) point_coords(g, s, m, &rh, &zh);
         bf16x8 hin[4];
@@ -967,7 +1002,7 @@ hipError_t mlp_forward(const Geometry &g, const Shade &s, const MlpDev &w, int p
     return hipGetLastError();
 }
 
-size_t mlp_backward_list_bytes(size_t M) { return sizeof(uint32_t) * (1 + 2 * ((M + kBrPts - 1) / kBrPts)); }
+size_t mlp_backward_list_bytes(size_t M) { return sizeof(uint32_t) * (1 + M + 2 * (size_t)kLiveChunks); }
 
 hipError_t mlp_backward(const Geometry &g, const Shade &s, const MlpDev &w, int precision, size_t M,
                         const float4 *dO, uint32_t *list, float *dW, hipStream_t st) {
@@ -977,9 +1012,13 @@ hipError_t mlp_backward(const Geometry &g, const Shade &s, const MlpDev &w, int 
     if (e != hipSuccess) return e;
     if (precision == RT_MLP_BF16) {
         const size_t passes = (M + kBrPts - 1) / kBrPts;
-        uint32_t *flags = list + 1 + passes;   // [passes] after the list
-        hipLaunchKernelGGL(mlp_live_passes, dim3((unsigned)((passes + 3) / 4)), dim3(256), 0, st, dO, M, passes, flags);
-        hipLaunchKernelGGL(mlp_list_passes, dim3(1), dim3(1024), 0, st, flags, (uint32_t)passes, list);
+        // chunks of at least 1024 points, at most kLiveChunks of them
+        const size_t chunk = std::max<size_t>(1024, (M + kLiveChunks - 1) / kLiveChunks);
+        const int nb = (int)((M + chunk - 1) / chunk);
+        uint32_t *counts = list + 1 + M, *offsets = counts + kLiveChunks;
+        hipLaunchKernelGGL(mlp_live_count, dim3(nb), dim3(1024), 0, st, dO, M, chunk, counts);
+        hipLaunchKernelGGL(mlp_live_scan, dim3(1), dim3(1024), 0, st, counts, nb, offsets, list);
+        hipLaunchKernelGGL(mlp_live_write, dim3(nb), dim3(1024), 0, st, dO, M, chunk, offsets, list);
         const unsigned grid = (unsigned)std::min<size_t>(passes, (size_t)ncu);
         hipLaunchKernelGGL(mlp_bwd_rr, dim3(grid), dim3(256), 0, st, g, s, w, M, dO, list, dW);
     } else {

@@ -54,6 +54,9 @@ rt_status adjoint_mlp(const rt_problem *p, const float *dl, const rt_grads *g, f
                       const float *target) {
     if (p->spec.nch > kLaunchChannels)
         return fail(RT_EINVAL, "the neural CO layer adjoint takes at most %d channels per call", kLaunchChannels);
+    // the backward lists its points with 32-bit indices
+    if ((uint64_t)p->cam.nx * p->cam.ny * p->nsamp >= 0xFFFFFFFFull)
+        return fail(RT_EINVAL, "the neural CO layer adjoint takes fewer than 2^32 - 1 pixel-samples per call");
     Geometry geo;
     Shade sh;
     MlpDev w;
