@@ -730,9 +730,11 @@ def bench_mlp(rt, synth, dev, args):
         res = {}
         for leg in ("forward", "forward_adjoint"):
             def step():
-                rt.render(sc, out=cube)
-                if leg == "forward_adjoint":
-                    rt.render_adjoint(sc, dl, want=("temp_k", "mlp_w"))
+                if leg == "forward":
+                    rt.render(sc, out=cube)
+                else:
+                    # one pass: the adjoint's own forward writes the cube
+                    rt.render_adjoint(sc, dl, want=("temp_k", "mlp_w"), cube_out=cube)
             step()
             torch.cuda.synchronize()
             t0 = time.perf_counter()

@@ -149,3 +149,22 @@ def test_full_size_network_render_sampled_pixels(precision):
         assert err <= 1e-5
     else:
         assert l2 <= 1e-2
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_network_adjoint_returns_the_forward_cube(precision):
+    """The cube the network adjoint writes (cube_out) is the render's: one
+    call gives the forward and the gradients."""
+    rt = _rt()
+    prec = rt.RT_MLP_FP32 if precision == "fp32" else rt.RT_MLP_BF16
+    prob = mlp_problem(nx=22, ny=17, nch=11, nsamp=56)
+    print(f"[gpu] neural adjoint cube_out {precision}", flush=True)
+    sc = rt.scene_from_problem(prob, mlp_precision=prec)
+    cube = rt.render(sc)
+    cube2 = torch.full_like(cube, float("nan"))
+    rt.render_adjoint(sc, torch.ones_like(cube), want=("temp_k", "mlp_w"), cube_out=cube2)
+    torch.cuda.synchronize()
+    a, b = cube.cpu().numpy(), cube2.cpu().numpy()
+    assert np.isfinite(b).all()
+    assert a.max() > 1.0
+    assert np.abs(a - b).max() <= 1e-6 * np.abs(a).max()
