@@ -388,8 +388,12 @@ __global__ __launch_bounds__(NT) void mlp_fwd_rr(Geometry g, Shade s, MlpDev w, 
 // register file of its SIMD.  A wave takes 16 points per pass (the workgroup
 // 64): it recomputes the forward with the transposed product (weights read
 // as A operands from LDS, where the workgroup stages each layer's weights
-// from L2 just before the layer: one copy per pass for the four waves, its
-// loads all in flight at once), keeping z' of every layer as BF16;
+// from L2: one copy per pass for the four waves, written by loads that go
+// to LDS directly and are issued one stage ahead into a free buffer -- the
+// forward's layers alternate between the weight buffer and the point-major
+// rows, which the forward does not use; the backward's transposed weights
+// are issued before the weight-gradient products that precede them -- so
+// their latency overlaps the matrix work), keeping z' of every layer as BF16;
 // walks back through the layers (dL/dh' of the layer below by the product
 // with the transposed weights, the SiLU derivative recomputed from z'); and
 // for the weight gradient, which sums over points, writes dL/dz' and h' of
@@ -484,17 +488,22 @@ __device__ __forceinline__ float br_rowsum(const __bf16 *X, int r, int half) {
 // from global memory into the workgroup's staging buffer (256 lanes): global
 // loads that write LDS directly (16 B per lane, lane i of a wave to the
 // wave's base + 16 i), so the copy holds no registers; every load is waited
-// for before the caller's barrier
-__device__ __forceinline__ void br_stage(__bf16 *dst, const gbf16 *src, int n, int tid) {
+// for (br_wait) before the barrier that precedes the first read
+__device__ __forceinline__ void br_issue(__bf16 *dst, const gbf16 *src, int n, int tid) {
     typedef __attribute__((address_space(3))) void lds_void;
     typedef const __attribute__((address_space(1))) void g_void;
     const int nchunk = n / 8, wv = tid >> 6, lane = tid & 63;
+    // (kept apart from the surrounding matrix code: interleaved with it, the
+    // address arithmetic lengthens live ranges into spills)
+    __builtin_amdgcn_sched_barrier(0);
     for (int c0 = 64 * wv; c0 < nchunk; c0 += 256) {
         const int c = c0 + lane;
         if (c < nchunk) __builtin_amdgcn_global_load_lds((g_void *)(src + 8 * c), (lds_void *)(dst + 8 * c0), 16, 0, 0);
     }
-    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_sched_barrier(0);
 }
+
+__device__ __forceinline__ void br_wait() { __builtin_amdgcn_s_waitcnt(0); }
 
 // The points with any dL/do != 0, in order, for mlp_bwd_rr.  dL/do = 0 at a
 // point (no opacity there) makes every layer's dL/dz' zero: the point adds
@@ -582,8 +591,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     Geometry g, Shade s, MlpDev w, size_t M, const float4 *__restrict__ dO, const uint32_t *__restrict__ list,
     float *__restrict__ dW) {
     typedef MM<__bf16> mm;
-    __shared__ __attribute__((aligned(16))) __bf16 XD[kW * kBrStride];   // dL/dz' (or dL/do) rows x points
-    __shared__ __attribute__((aligned(16))) __bf16 XH[kW * kBrStride];   // h' (or features) rows x points
+    // point-major rows of the backward: dL/dz' (or dL/do) rows x points, then
+    // h' (or features) rows x points; in the forward, layers 1 and 3's weights
+    __shared__ __attribute__((aligned(16))) __bf16 XU[2 * kW * kBrStride];
+    static_assert(2 * kW * kBrStride >= kW * kRrRow, "a hidden layer's weights fit the row buffers");
+    __bf16 *const XD = XU;
+    __bf16 *const XH = XU + kW * kBrStride;
     __shared__ __attribute__((aligned(16))) float sB[4 * kW];
     __shared__ __attribute__((aligned(16))) float sW5[3 * kW];
     // lane-private parking of z' (4 layers x 4 operand packs) and the two
@@ -607,6 +620,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     float db0 = 0.0f, db1 = 0.0f, db2 = 0.0f, db3 = 0.0f, db5 = 0.0f;
     const int brow = 32 * wv + (lane >> 1), bhalf = lane & 1;     // bias row of this lane
     const int col = 16 * wv + lc;                                 // this lane's point within the pass
+    // layer 0's weights for the first pass (each pass stages the next's)
+    br_issue(SW, (const gbf16 *)(uint64_t)w.Wr, kW * kRrRow0, tid);
+    br_wait();
     __syncthreads();
     // the points with any dL/do != 0, listed in order (list[0] of them), 64
     // to a pass
@@ -637,11 +653,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
         for (int l = 0; l < 4; ++l) {
             const int nk = l == 0 ? kF / 32 : kW / 32;
             const int row = l == 0 ? kRrRow0 : kRrRow;
-            // (layer 0 follows the end-of-pass barrier, so SW is free)
-            if (l > 0) __syncthreads();
-            br_stage(SW, Wr + (l == 0 ? 0 : (size_t)kW * kRrRow0 + (size_t)(l - 1) * kW * kRrRow), kW * row, tid);
-            __syncthreads();
-            const __bf16 *Wl = SW;
+            // layer l's weights are in place; the next stage goes into the
+            // other buffer, free since the barrier that ended layer l - 1:
+            // layer l + 1's weights, or after layer 3 the transposed weights
+            // of the backward's first product
+            if (l < 3) br_issue(l & 1 ? SW : XU, Wr + (size_t)kW * kRrRow0 + (size_t)l * kW * kRrRow, kW * kRrRow, tid);
+            else br_issue(SW, WrT + (size_t)2 * kW * kRrRow, kW * kRrRow, tid);
+            const __bf16 *Wl = l & 1 ? XU : SW;
             bf16x8 hout[4];
 #pragma unroll
             for (int cp = 0; cp < 4; ++cp) {
@@ -675,6 +693,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
 #pragma unroll
                 for (int c = 0; c < 4; ++c) hin[c] = hout[c];
             }
+            br_wait();
+            __syncthreads();
         }
         // ---- output layer: dL/dh'_3 = W5'^T dL/do, then h'_3 and dL/dz'_3
         const float4 d = m < M ? dO[m] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
@@ -711,6 +731,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
                 br_write_rows(XD, dzu, lg, col);
             }
             __syncthreads();
+            // SW is free (every wave's product with it came before its rows):
+            // issue the transposed weights of the next product down, or after
+            // the last one the next pass's layer-0 weights
+            if (l == 2 || l == 1) br_issue(SW, WrT + (size_t)(l - 1) * kW * kRrRow, kW * kRrRow, tid);
+            else if (l == 0) br_issue(SW, Wr, kW * kRrRow0, tid);
             if (l == 3) {
 #pragma unroll
                 for (int kc = 0; kc < kBrPts / 32; ++kc) {
@@ -735,15 +760,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
                 br_dw<8>(g1, XD, XH, wv, lg, lc);
                 db1 += br_rowsum(XD, brow, bhalf);
             }
+            if (l != 0) br_wait();
             __syncthreads();
 #pragma unroll
             for (int c = 0; c < 4; ++c) dzu[c] = dz[c];
             // dL/dh' of the layer below through the transposed weights, and
             // at once its h' and dL/dz'
             if (l >= 1) {
-                // (the barrier above follows every wave's last use of SW)
-                br_stage(SW, WrT + (size_t)(l - 1) * kW * kRrRow, kW * kRrRow, tid);
-                __syncthreads();
+                // (the transposed weights are in SW, waited for before the
+                // barrier above)
                 const __bf16 *WT = SW;
 #pragma unroll
                 for (int cp = 0; cp < 4; ++cp) {
@@ -775,6 +800,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
         __syncthreads();
         br_dw<4>(g0, XD, XH, wv, lg, lc);
         db0 += br_rowsum(XD, brow, bhalf);
+        br_wait();   // the next pass's layer-0 weights
         __syncthreads();
     }
     // ---- flush: flat layout per layer W [out][in] then b [out]
