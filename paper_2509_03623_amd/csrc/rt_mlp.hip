@@ -201,7 +201,8 @@ constexpr int kRrRow0 = kF + 8;        // padded row of layer 0 (bf16 elements)
 constexpr int kRrRow = kW + 8;         // padded row of layers 1..3
 // 16-point column tiles per wave and lanes per workgroup (one workgroup per
 // CU, the weights filling most of its LDS); 4 x 512 measured fastest of
-// 2 x 1024, 2 x 768 and 4 x 512
+// 2 x 1024, 2 x 768 and 4 x 512, and the same as 3 x 512 (which spills no
+// registers where 4 x 512 spills 31: the spills cost nothing measurable)
 constexpr int kRrTiles = 4;
 constexpr int kRrThreads = 512;
 constexpr size_t kRrWeightElems = (size_t)kW * kRrRow0 + 3 * (size_t)kW * kRrRow;
