@@ -686,9 +686,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
                         if (l < 3) hout[cp][4 * h + i] = (__bf16)(z * frcp(1.0f + fexp2(-z)));
                     }
                 ZP[4 * l + cp][tid] = zq;
-                // keep the next pair's weight reads after this pair's work
-                // (hoisting them all would spill)
-                __builtin_amdgcn_sched_barrier(0);
             }
             if (l < 3) {
 #pragma unroll
@@ -786,7 +783,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
                     for (int h = 0; h < 2; ++h)
 #pragma unroll
                         for (int i = 0; i < 4; ++i) br_act_grad(zq[4 * h + i], acc[h][i], hp[cp], dz[cp], 4 * h + i);
-                    __builtin_amdgcn_sched_barrier(0);
                 }
             }
         }
