@@ -473,14 +473,20 @@ __device__ __forceinline__ void br_dw(floatx4 (&acc)[2][NI], const __bf16 *XD, c
     }
 }
 
-// sum over the 64 points of LDS row r (two lanes per row, 32 points each)
+// sum over the 64 points of LDS row r (two lanes per row, 32 points each);
+// two values per instruction, as a dot product with (1, 1)
 __device__ __forceinline__ float br_rowsum(const __bf16 *X, int r, int half) {
+    typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+    const bf16x2 one = {(__bf16)1.0f, (__bf16)1.0f};
     float sum = 0.0f;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const bf16x8 v = *(const bf16x8 *)(X + r * kBrStride + 32 * half + 8 * q);
 #pragma unroll
-        for (int j = 0; j < 8; ++j) sum += (float)v[j];
+        for (int j = 0; j < 4; ++j) {
+            const bf16x2 p = {v[2 * j], v[2 * j + 1]};
+            sum = __builtin_amdgcn_fdot2_f32_bf16(p, one, sum, false);
+        }
     }
     return sum + __shfl_xor(sum, 1);
 }
